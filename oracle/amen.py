@@ -1,0 +1,254 @@
+"""O2 -- a plain alternating minimal-energy (AMEn) sweep for A u = b (oracle).
+
+Alg. 2 of the paper solves A u = M f0 with the AMEn solver of Dolgov and
+Savostyanov (2014); the paper names the method and no parameters.  This module
+writes the method out step by step with numpy tensor contractions and LAPACK, in the order
+below, which the GPU library follows as well (the readings of every constant
+the paper leaves open are listed in the design doc):
+
+  * start: X = random rank-2 TT, Z = random rank-rho TT (SplitMix64 draws);
+    orthogonalise both from the right and build the right interfaces;
+  * half-sweep over the cores k = 0 .. K-1 (a "sweep" alternates direction;
+    the right-to-left half-sweep is the same step on the reversed chain):
+      g   = local right-hand side  (Phi_b,L  B_k  Phi_b,R)
+      B   = local operator          (Phi_A,L  A_k  Phi_A,R), symmetric
+      res = ||g - B x_k|| / ||g||
+      if res > tol/2: preconditioned CG from x_k (Jacobi: diag(B)) until
+            ||g - B x|| <= max(0.1 res, tol/2) ||g||
+      if k < K-1:
+        SVD of the (r_k n_k) x r_{k+1} unfolding, keep the smallest rank whose
+            discarded tail is <= tol/sqrt(K-1) of the norm, at most rank_cap;
+        z_k = projection of the residual b - A x~ on the Z interfaces, QR;
+        e   = residual b - A x~ projected on (left X, right Z) interfaces;
+        [U | e] -> QR -> new core X_k, carry Q^T x~ into X_{k+1}
+            (at most rank_cap columns in total);
+        update the four left interfaces.
+  * stop after a half-sweep with max_k res_k <= tol, or after max_sweeps.
+
+Parity: tests/test_oracle_amen.py pins it to the sparse direct solve of
+oracle.fem on small grids (unconstrained rank), to the load-scaling law
+u(sE) = u(E)/s and to superposition.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import rng
+
+
+# ----------------------------------------------------------------------------- local contractions
+# Shapes: left interface L[p, R, q]; MPO core A[R, n_out, n_in, R']; x[q, n, s];
+# right interface Rt[t, R', s]; result [p, n, t].
+
+def local_apply(L, A, x, Rt):
+    """y[p, j, t] = sum L[p, b, q] A[b, j, i, e] x[q, i, s] Rt[t, e, s], in three stages."""
+    T1 = np.tensordot(L, x, axes=([2], [0]))            # [p, b, i, s]
+    T2 = np.tensordot(T1, A, axes=([1, 2], [0, 2]))     # [p, s, j, e]
+    return np.tensordot(T2, Rt, axes=([3, 1], [1, 2]))  # [p, j, t]
+
+
+def local_rhs(Lb, B, Rb):
+    """g[p, j, u] = sum Lb[p, s] B[s, j, t] Rb[u, t]."""
+    return np.tensordot(np.tensordot(Lb, B, axes=([1], [0])), Rb, axes=([2], [1]))
+
+
+def local_diag(L, A, Rt):
+    """diag of the local operator: sum_{b,e} L[a, b, a] A[b, i, i, e] Rt[c, e, c]."""
+    Ld = np.einsum("aba->ab", L)
+    Ad = np.einsum("biie->bie", A)
+    Rd = np.einsum("cec->ce", Rt)
+    return np.tensordot(np.tensordot(Ld, Ad, axes=([1], [0])), Rd, axes=([2], [1]))
+
+
+def env_A(L, W, A, X):
+    """Next left interface: sum W[p, j, t] L[p, b, q] A[b, j, i, e] X[q, i, s] -> [t, e, s]."""
+    T1 = np.tensordot(L, X, axes=([2], [0]))             # [p, b, i, s]
+    T2 = np.tensordot(T1, A, axes=([1, 2], [0, 2]))      # [p, s, j, e]
+    return np.tensordot(W, T2, axes=([0, 1], [0, 2])).transpose(0, 2, 1)  # [t, e, s]
+
+
+def env_b(Lb, W, B):
+    """Next left load interface: sum W[p, j, t] Lb[p, s] B[s, j, u] -> [t, u]."""
+    T = np.tensordot(Lb, B, axes=([1], [0]))             # [p, j, u]
+    return np.tensordot(W, T, axes=([0, 1], [0, 1]))
+
+
+def pcg(apply, g, x, dinv, thr, maxit):
+    """Jacobi-preconditioned conjugate gradients from x until ||g - B x|| <= thr."""
+    r = g - apply(x)
+    z = r * dinv
+    p = z.copy()
+    rz = float(np.vdot(r, z))
+    it = 0
+    while it < maxit and np.linalg.norm(r) > thr:
+        q = apply(p)
+        pq = float(np.vdot(p, q))
+        if pq <= 0.0:
+            break
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        z = r * dinv
+        rz_new = float(np.vdot(r, z))
+        beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+        it += 1
+    return x, it
+
+
+def truncation_rank(s, tol_rel, cap):
+    """Smallest r with ||s[r:]|| <= tol_rel ||s||, clipped to [1, cap]."""
+    tot = float(np.sum(s ** 2))
+    tail = 0.0
+    r = len(s)
+    for j in range(len(s) - 1, -1, -1):  # tail sums from the smallest value up
+        if tail + s[j] ** 2 <= (tol_rel ** 2) * tot:
+            tail += s[j] ** 2
+            r = j
+        else:
+            break
+    return max(1, min(r, cap))
+
+
+# ----------------------------------------------------------------------------- state
+
+@dataclasses.dataclass
+class Options:
+    tol: float = 1e-8
+    rank_cap: int = 32
+    rho: int = 4
+    max_sweeps: int = 30
+    init_rank: int = 2
+    seed_x: int = 1
+    seed_z: int = 2
+    cg_maxit: int = 500
+
+
+@dataclasses.dataclass
+class Stats:
+    sweeps: int = 0
+    max_res: list = dataclasses.field(default_factory=list)
+    cg_iters: int = 0
+    applies: int = 0
+    ranks: list = dataclasses.field(default_factory=list)
+
+
+class _Chain:
+    """Cores of A, b, X, Z and the interfaces on every bond, in one orientation."""
+
+    def __init__(self, A, b, X, Z):
+        self.A = [C.copy() for C in A]
+        self.B = [C.copy() for C in b]
+        self.X = [C.copy() for C in X]
+        self.Z = [C.copy() for C in Z]
+        K = len(A)
+        one3 = np.ones((1, 1, 1))
+        one2 = np.ones((1, 1))
+        self.LA = [one3] + [None] * (K - 1) + [one3]
+        self.Lb = [one2] + [None] * (K - 1) + [one2]
+        self.LzA = [one3] + [None] * (K - 1) + [one3]
+        self.Lzb = [one2] + [None] * (K - 1) + [one2]
+        self.reversed = False
+
+    def reverse(self):
+        self.A = [C.transpose(3, 1, 2, 0) for C in self.A[::-1]]
+        self.B = [C.transpose(2, 1, 0) for C in self.B[::-1]]
+        self.X = [C.transpose(2, 1, 0) for C in self.X[::-1]]
+        self.Z = [C.transpose(2, 1, 0) for C in self.Z[::-1]]
+        self.LA, self.Lb = self.LA[::-1], self.Lb[::-1]
+        self.LzA, self.Lzb = self.LzA[::-1], self.Lzb[::-1]
+        self.reversed = not self.reversed
+
+    def update_envs(self, k):
+        A, B, X, Z = self.A[k], self.B[k], self.X[k], self.Z[k]
+        self.LA[k + 1] = env_A(self.LA[k], X, A, X)
+        self.Lb[k + 1] = env_b(self.Lb[k], X, B)
+        self.LzA[k + 1] = env_A(self.LzA[k], Z, A, X)
+        self.Lzb[k + 1] = env_b(self.Lzb[k], Z, B)
+
+    def qr_pass(self):
+        """Left-orthogonalise X and Z and build the left interfaces."""
+        K = len(self.A)
+        for k in range(K - 1):
+            for T in (self.X, self.Z):
+                r, n, r2 = T[k].shape
+                Q, R = np.linalg.qr(T[k].reshape(r * n, r2))
+                T[k] = Q.reshape(r, n, -1)
+                T[k + 1] = np.einsum("ab,bnc->anc", R, T[k + 1])
+            self.update_envs(k)
+
+
+def _half_sweep(ch: _Chain, opt: Options, st: Stats):
+    K = len(ch.A)
+    tol = opt.tol
+    tr_tol = tol / np.sqrt(max(K - 1, 1))
+    max_res = 0.0
+    for k in range(K):
+        L, A, Rt = ch.LA[k], ch.A[k], ch.LA[k + 1]
+        g = local_rhs(ch.Lb[k], ch.B[k], ch.Lb[k + 1])
+        x = ch.X[k]
+
+        def apply(v):
+            st.applies += 1
+            return local_apply(L, A, v, Rt)
+
+        gn = np.linalg.norm(g)
+        res0 = np.linalg.norm(g - apply(x))
+        res = res0 / gn if gn > 0 else (0.0 if res0 == 0 else 1.0)
+        max_res = max(max_res, res)
+        if res > 0.5 * tol:
+            dg = local_diag(L, A, Rt)
+            dinv = np.where(dg > 0, 1.0 / np.where(dg > 0, dg, 1.0), 1.0)
+            thr = max(0.1 * res, 0.5 * tol) * gn
+            x, it = pcg(apply, g, x, dinv, thr, opt.cg_maxit)
+            st.cg_iters += it
+        if k == K - 1:
+            ch.X[k] = x
+            break
+        r, n, r2 = x.shape
+        U, s, Vt = np.linalg.svd(x.reshape(r * n, r2), full_matrices=False)
+        rk = truncation_rank(s, tr_tol, opt.rank_cap)
+        xt = (U[:, :rk] * s[:rk]) @ Vt[:rk]
+        xt3 = xt.reshape(r, n, r2)
+        # residual projected on the Z interfaces -> new Z_k
+        zt = local_rhs(ch.Lzb[k], ch.B[k], ch.Lzb[k + 1]) - local_apply(ch.LzA[k], A, xt3, ch.LzA[k + 1])
+        rz, _, rz2 = zt.shape
+        Qz, _ = np.linalg.qr(zt.reshape(rz * n, rz2))
+        ch.Z[k] = Qz.reshape(rz, n, -1)
+        # enrichment: residual on (left X, right Z) interfaces
+        e = local_rhs(ch.Lb[k], ch.B[k], ch.Lzb[k + 1]) - local_apply(L, A, xt3, ch.LzA[k + 1])
+        rho_eff = max(0, min(e.shape[2], opt.rank_cap - rk, r * n - rk))
+        aug = np.concatenate([U[:, :rk], e.reshape(r * n, -1)[:, :rho_eff]], axis=1)
+        Q, _ = np.linalg.qr(aug)
+        ch.X[k] = Q.reshape(r, n, -1)
+        W = Q.T @ xt
+        ch.X[k + 1] = np.einsum("ab,bnc->anc", W, ch.X[k + 1])
+        ch.update_envs(k)
+    return max_res
+
+
+def amen_solve(A, b, opt: Options | None = None):
+    """Solve A u = b in TT format.  Returns (list of cores of u, Stats)."""
+    opt = opt or Options()
+    modes = [C.shape[1] for C in A]
+    X = rng.random_tt(modes, opt.init_rank, opt.seed_x)
+    Z = rng.random_tt(modes, opt.rho, opt.seed_z)
+    ch = _Chain(A, b, X, Z)
+    st = Stats()
+    ch.reverse()
+    ch.qr_pass()
+    ch.reverse()
+    for _ in range(opt.max_sweeps):
+        mr = _half_sweep(ch, opt, st)
+        st.sweeps += 1
+        st.max_res.append(mr)
+        ch.reverse()
+        if mr <= opt.tol:
+            break
+    if ch.reversed:
+        ch.reverse()
+    st.ranks = [C.shape[0] for C in ch.X] + [1]
+    return ch.X, st

@@ -1,0 +1,221 @@
+"""Pins of the sparse FEM oracle (O1) against facts fixed outside it."""
+import itertools
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import fem
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_lame_closed_form():
+    lam, mu = fem.lame(1.0, 0.3)
+    assert lam == pytest.approx(0.3 / (1.3 * 0.4), rel=1e-15)
+    assert mu == pytest.approx(1.0 / 2.6, rel=1e-15)
+    lps, mps = fem.lame(68e9, 0.33, plane_stress=True)
+    assert lps == pytest.approx(68e9 * 0.33 / (1 - 0.33 ** 2), rel=1e-14)
+    assert mps == pytest.approx(68e9 / 2.66, rel=1e-14)
+
+
+def _load_q4(nu, E):
+    coef, P = {}, []
+    for line in open(os.path.join(GOLD, "q4_plane_stress_element.txt")):
+        if line.startswith("coef"):
+            _, i, c0, c1 = line.split()
+            coef[int(i)] = float(Fraction(c0)) + float(Fraction(c1)) * nu
+        elif line.startswith("P"):
+            P.append([int(v) for v in line.split()[1:]])
+    return E / (1 - nu ** 2) * np.array([[coef[v] for v in row] for row in P])
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.33, 0.45])
+def test_element_matches_textbook_q4(nu):
+    """The quadrature element equals Sigmund's closed-form Q4 plane-stress matrix.
+
+    The textbook orders dofs node by node around the element; we search the
+    node orders (cyclic, either orientation, either start) and the two axis
+    reflections, and require an exact match for one of them.
+    """
+    E = 2.5
+    lam, mu = fem.lame(E, nu, plane_stress=True)
+    Ke, _ = fem.element_matrices(2, 0.7, lam, mu)  # square element; side does not matter in 2D
+    KE = _load_q4(nu, E)
+    bits = fem.corner_bits(2)  # our corners: (x bit, y bit), x most significant
+    best = np.inf
+    for perm in itertools.permutations(range(4)):
+        for sx, sy in itertools.product((1, -1), repeat=2):
+            idx, sgn = [], []
+            for node in perm:
+                idx += [0 * 4 + node, 1 * 4 + node]
+                sgn += [sx, sy]
+            T = np.array(sgn)[:, None] * Ke[np.ix_(idx, idx)] * np.array(sgn)[None, :]
+            best = min(best, np.abs(T - KE).max())
+    assert best < 1e-12 * np.abs(KE).max()
+    # the textbook matrix also fixes the eigenvalues (order free)
+    assert np.allclose(np.sort(np.linalg.eigvalsh(Ke)), np.sort(np.linalg.eigvalsh(KE)), atol=1e-12)
+    del bits
+
+
+def test_1d_element_closed_forms():
+    h = 0.37
+    lam, mu = 0.8, 0.6
+    Ke, Me = fem.element_matrices(1, h, lam, mu)
+    assert np.allclose(Ke, (lam + 2 * mu) / h * np.array([[1, -1], [-1, 1]]), rtol=1e-14)
+    assert np.allclose(Me, h / 6 * np.array([[2, 1], [1, 2]]), rtol=1e-14)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_element_equals_kronecker_form(D):
+    """Element stiffness = lambda D_ab + mu D_ba + mu delta_ab sum_c D_cc with 1D closed forms."""
+    h = np.array([0.3, 0.5, 0.7])[:D]
+    lam, mu = 1.3, 0.45
+    Ke, Me = fem.element_matrices(D, h, lam, mu)
+    S = [1 / h[a] * np.array([[1, -1], [-1, 1]]) for a in range(D)]
+    M = [h[a] / 6 * np.array([[2, 1], [1, 2]]) for a in range(D)]
+    G = [0.5 * np.array([[-1, -1], [1, 1]]) for a in range(D)]  # int phi_p' phi_q
+
+    def atom(a, b):
+        out = np.ones((1, 1))
+        for c in range(D):
+            if a == b:
+                F = S[c] if c == a else M[c]
+            else:
+                F = G[c] if c == a else (G[c].T if c == b else M[c])
+            out = np.kron(out, F)
+        return out
+
+    nc = 2 ** D
+    for a in range(D):
+        for b in range(D):
+            ref = lam * atom(a, b) + mu * atom(b, a)
+            if a == b:
+                ref = ref + mu * sum(atom(c, c) for c in range(D))
+            assert np.allclose(Ke[a * nc:(a + 1) * nc, b * nc:(b + 1) * nc], ref, rtol=1e-13, atol=1e-14)
+    Mref = np.ones((1, 1))
+    for c in range(D):
+        Mref = np.kron(Mref, M[c])
+    assert np.allclose(Me, Mref, rtol=1e-13)
+
+
+def _rigid_modes(grid):
+    x = grid.node_coords()
+    D, nn = grid.D, grid.n_nodes
+    modes = []
+    for a in range(D):
+        v = np.zeros((D, nn)); v[a] = 1.0
+        modes.append(v.reshape(-1))
+    for a, b in itertools.combinations(range(D), 2):
+        v = np.zeros((D, nn)); v[a] = -x[:, b]; v[b] = x[:, a]
+        modes.append(v.reshape(-1))
+    return modes
+
+
+@pytest.mark.parametrize("D,d", [(2, 3), (2, 4), (3, 2), (3, 3)])
+def test_stiffness_symmetric_and_rigid_null_space(D, d):
+    grid = fem.Grid(D, d, extent=[2.0, 1.0, 0.5][:D])
+    K, M = fem.assemble(grid, 0.7, 0.4)
+    nK = abs(K).max()
+    assert abs(K - K.T).max() <= 1e-15 * nK  # symmetric up to quadrature summation order
+    modes = _rigid_modes(grid)
+    assert len(modes) == (3 if D == 2 else 6)
+    for v in modes:
+        assert np.abs(K @ v).max() <= 1e-13 * nK * np.abs(v).max() * 10
+
+
+@pytest.mark.parametrize("D,d", [(2, 4), (3, 3)])
+def test_patch_test_linear_field(D, d):
+    """A linear displacement field has constant stress: interior nodal forces vanish."""
+    grid = fem.Grid(D, d)
+    K, _ = fem.assemble(grid, 1.1, 0.6)
+    x = grid.node_coords()
+    rng = np.random.default_rng(3)
+    Gm = rng.standard_normal((D, D))
+    c = rng.standard_normal(D)
+    u = (x @ Gm.T + c).T.reshape(-1)
+    f = (K @ u).reshape(D, -1)
+    coords = np.array(list(itertools.product(range(grid.n), repeat=D)))
+    interior = np.all((coords > 0) & (coords < grid.n - 1), axis=1)
+    assert np.abs(f[:, interior]).max() <= 1e-12 * np.abs(K).max() * np.abs(u).max()
+    assert np.abs(f[:, ~interior]).max() > 1e-3  # boundary tractions do not vanish
+
+
+@pytest.mark.parametrize("D,d", [(2, 3), (3, 2)])
+def test_load_totals(D, d):
+    ext = np.array([2.0, 1.5, 0.5])[:D]
+    grid = fem.Grid(D, d, extent=ext)
+    K, M = fem.assemble(grid, 1.0, 1.0)
+    f = np.array([0.3, -1.2, 2.0])[:D]
+    b = fem.body_load(grid, M, np.repeat(f[:, None], grid.n_nodes, axis=1))
+    tot = b.reshape(D, -1).sum(axis=1)
+    assert np.allclose(tot, f * np.prod(ext), rtol=1e-13)
+    t = np.array([1.0, -0.5, 0.25])[:D]
+    bt = fem.traction_load(grid, 0, 1, t)
+    area = np.prod(ext[1:])
+    assert np.allclose(bt.reshape(D, -1).sum(axis=1), t * area, rtol=1e-13)
+    # traction sits on the face x = L only
+    on = np.zeros(grid.n_nodes, bool); on[fem.face_nodes(grid, 0, 1)] = True
+    assert np.all(bt.reshape(D, -1)[:, ~on] == 0)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_manufactured_force_finite_difference(D):
+    """f = -div sigma(u*) checked by central differences of u* (independent of the closed form)."""
+    lam, mu = 0.9, 0.35
+    c = np.array([0.4, -1.1, 0.7])[:D]
+    rng = np.random.default_rng(7)
+    pts = rng.uniform(0.1, 0.9, size=(5, D))
+    hh = 1e-3
+
+    def sigma(x):
+        # gradient of u* by central differences
+        Gd = np.zeros((D, D))
+        for j in range(D):
+            e = np.zeros(D); e[j] = hh
+            Gd[:, j] = (fem.manufactured_u((x + e)[None], c)[:, 0] - fem.manufactured_u((x - e)[None], c)[:, 0]) / (2 * hh)
+        eps = 0.5 * (Gd + Gd.T)
+        return lam * np.trace(eps) * np.eye(D) + 2 * mu * eps
+
+    for x in pts:
+        div = np.zeros(D)
+        for j in range(D):
+            e = np.zeros(D); e[j] = hh
+            div += (sigma(x + e)[:, j] - sigma(x - e)[:, j]) / (2 * hh)
+        f = fem.manufactured_f(x[None], c, lam, mu)[:, 0]
+        assert np.allclose(f, -div, rtol=1e-4, atol=1e-4)
+
+
+def _manufactured_problem(D, d):
+    faces = [(a, s) for a in range(D) for s in (0, 1)]
+    return dict(dim=D, level=d, E=1.0, nu=0.3, clamp=faces, manufactured_c=[0.5, -1.0, 0.8][:D])
+
+
+@pytest.mark.parametrize("D,levels", [(2, [3, 4, 5, 6]), (3, [3, 4])])
+def test_manufactured_convergence_second_order(D, levels):
+    errs = []
+    for d in levels:
+        A, b, grid, info = fem.build_system(_manufactured_problem(D, d))
+        u = fem.direct_solve(A, b)
+        assert np.linalg.norm(A @ u - b) <= 1e-10 * np.linalg.norm(b)
+        ustar = fem.manufactured_u(grid.node_coords(), [0.5, -1.0, 0.8][:D]).reshape(-1)
+        errs.append(np.linalg.norm(u - ustar) / np.linalg.norm(ustar))
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(ratios > 3.0) and np.all(ratios < 5.0), (errs, ratios)
+
+
+def test_bc_system_is_spd_and_alpha_free():
+    prob = dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])])
+    A, b, grid, info = fem.build_system(prob)
+    Ad = A.toarray()
+    np.linalg.cholesky(Ad)  # SPD
+    u1 = fem.direct_solve(A, b)
+    A2, b2 = fem.apply_dirichlet(info["K"], info["b_raw"], info["mask"], 17.0 * info["alpha"])
+    u2 = fem.direct_solve(A2, b2)
+    assert np.allclose(u1, u2, rtol=1e-11, atol=1e-14)
+    assert np.all(u1[~info["mask"]] == 0.0)
+    # energy identity 1/2 u^T A u = 1/2 b^T u at the solution
+    assert u1 @ (A @ u1) == pytest.approx(b @ u1, rel=1e-12)
+    assert spla.norm(A - A.T) <= 1e-15 * spla.norm(A)
