@@ -1,0 +1,210 @@
+/*
+ * tnfem.h -- C ABI of the MI355X QTT finite-element elasticity solver.
+ *
+ * The library solves the Galerkin system A u = M f0 of isotropic linear
+ * elasticity discretised by Q1 (bilinear / trilinear) elements on a box with
+ * 2^d nodes per axis (Sec. 3 and Sec. 5 of Ali et al., "Quantum-Inspired Solver
+ * for Simulating Material Deformations", arXiv 2501.12151), entirely in
+ * quantics tensor-train (QTT) format, with the alternating minimal-energy
+ * (AMEn) sweep that the paper's Alg. 2 applies.  Every step of the sweep runs in
+ * the library's own HIP kernels for gfx950; the host only sequences them.
+ *
+ * Conventions
+ * -----------
+ * - All calls return an int status: TNFEM_OK (0) or a negative TNFEM_E* code;
+ *   tnfem_last_error() then returns a message for the calling thread.
+ * - Every *_create has a matching *_destroy.  Input arrays are caller owned and
+ *   copied; output TTs are library owned until destroyed.
+ * - Floating point is IEEE double unless stated otherwise.
+ * - TT layout (the same for the solution u and the load b): K = d + 1 cores.
+ *   Cores 0 .. d-1 are level cores with mode n = 2^D, most significant level
+ *   first (the binary index formula of Sec. 4), mode index
+ *   m = (ix_bit * 2 + iy_bit) [* 2 + iz_bit]; core d is the displacement
+ *   component core with mode D.  (Sec. 5.2 lists the component index first;
+ *   the library places it last, where the exact operator has lower TT rank:
+ *   25 instead of 51 in 2D, 125 instead of 342 in 3D.)  Core k is stored
+ *   row-major as [r_k][n_k][r_{k+1}], r_0 = r_K = 1.
+ *   Node (ix, iy[, iz]) sits at x = ix * extent[0] / (2^d - 1), etc.
+ * - Pointers documented as "device" are HIP device pointers on the context's
+ *   device (for instance torch tensor data pointers); "host" pointers are
+ *   ordinary memory.  A "stream" argument is a hipStream_t passed as void*;
+ *   NULL means the context's stream.
+ */
+#ifndef TNFEM_H
+#define TNFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TNFEM_OK = 0,
+  TNFEM_EINVAL = -1,   /* invalid argument or descriptor */
+  TNFEM_ENOMEM = -2,   /* host or device allocation failed */
+  TNFEM_EBUDGET = -3,  /* request does not fit the device-memory budget */
+  TNFEM_ENOTCONV = -4, /* sweep limit reached before the tolerance (result still returned) */
+  TNFEM_EDEVICE = -5,  /* a HIP call failed, or no device */
+  TNFEM_ENAN = -6,     /* a non-finite value appeared in the sweep */
+  TNFEM_EBUSY = -7     /* result not ready yet (serving queue) */
+};
+
+typedef struct tnfem_ctx tnfem_ctx;
+typedef struct tnfem_problem tnfem_problem;
+typedef struct tnfem_tt tnfem_tt;
+
+/* Face numbering: face = 2 * axis + side, side 0 at x_axis = 0, side 1 at x_axis = extent. */
+#define TNFEM_FACE(axis, side) (2 * (axis) + (side))
+
+/*
+ * Problem description (Alg. 1 inputs: grid exponent d, Young's modulus E,
+ * Poisson's ratio nu, domain, Dirichlet or Neumann data per side; Alg. 2 adds
+ * the load).  Material law of Sec. 2: lambda = E nu / ((1+nu)(1-2nu)),
+ * mu = E / (2(1+nu)); plane_stress (2D only) uses lambda = E nu / (1 - nu^2).
+ * Clamped faces fix every displacement component (u = 0) by symmetric
+ * elimination; other faces are traction free unless a traction is given.
+ * Loads: body force f (constant vector, enters as b = M f0 with f0 its nodal
+ * values, Sec. 5.3), uniform tractions t on faces (b += integral of t . v),
+ * and the manufactured force of u*_i = c_i prod_a sin(pi x_a) on the unit box.
+ * layer_E, if non-NULL, gives Young's modulus per element layer along
+ * layer_axis (2^d - 1 values), i.e. a piecewise constant E(x) at fixed nu;
+ * it replaces E in the element integrals (E still sets the diagonal given to
+ * clamped dofs).  Only 2^d - 1 == n_layer_E is accepted.
+ */
+typedef struct {
+  int dim;              /* D = 2 or 3 */
+  int level;            /* d >= 2: 2^d nodes per axis, boundary nodes included */
+  double extent[3];     /* box edge lengths (> 0) */
+  double E, nu;         /* Young's modulus (> 0), Poisson's ratio in (-1, 0.5) */
+  int plane_stress;     /* 2D only: 0 = plane strain, 1 = plane stress */
+  uint32_t clamp_mask;  /* bit TNFEM_FACE(axis, side) set = clamped face */
+  int n_tractions;      /* 0..6 */
+  int traction_face[6];
+  double traction[6][3];
+  int has_body_force;
+  double body_force[3];
+  int has_manufactured;
+  double manufactured_c[3];
+  int layer_axis;
+  int n_layer_E;
+  const double* layer_E; /* host, n_layer_E values, copied */
+} tnfem_problem_desc;
+
+/*
+ * Solve options (the AMEn constants; the paper names the solver only).
+ * precision: 0 = FP64 everywhere.  Other values are rejected with TNFEM_EINVAL
+ * by this version.
+ */
+typedef struct {
+  int rank_cap;      /* maximal TT rank of u, 1 .. 252 */
+  double tol;        /* stop when every local relative residual <= tol */
+  int max_sweeps;    /* half-sweeps (alternating direction) */
+  int rho;           /* rank of the residual-projection TT used for enrichment */
+  int init_rank;     /* rank of the random initial guess */
+  uint64_t seed_x;   /* SplitMix64 seed of the initial guess */
+  uint64_t seed_z;   /* SplitMix64 seed of the residual-projection TT */
+  int cg_maxit;      /* iteration limit of each local conjugate-gradient solve */
+  int precision;
+} tnfem_solve_opts;
+
+/* Fills opts with the defaults: cap 32, tol 1e-8, 30 sweeps, rho 4, init rank 2,
+ * seeds 1 and 2, 500 CG iterations, FP64. */
+void tnfem_default_opts(tnfem_solve_opts* opts);
+
+typedef struct {
+  int sweeps;             /* half-sweeps done */
+  int converged;          /* 1 if max local residual <= tol */
+  double final_max_res;   /* max local relative residual of the last half-sweep */
+  long long cg_iters;     /* local CG iterations, all cores */
+  long long local_applies;/* applications of a local operator */
+  double flops;           /* counted floating-point operations of the contractions */
+  double seconds;         /* wall time of the solve (device synchronised) */
+  int max_rank;           /* max TT rank of u */
+  double contraction_ms;  /* device time in the contraction kernels (events), or 0 */
+} tnfem_solve_stats;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`.  hip_stream may be NULL (the
+ * library creates its own default-priority stream).  Fails with TNFEM_EDEVICE
+ * if no device is present. */
+int tnfem_ctx_create(tnfem_ctx** out, int device, void* hip_stream);
+int tnfem_ctx_destroy(tnfem_ctx* ctx);
+
+/* Message of the last failing call in this thread (static storage). */
+const char* tnfem_last_error(void);
+
+/* ---------------------------------------------------------------- problems */
+
+/* Assembles the QTT operator A (with boundary conditions) and load b on the
+ * host (Alg. 1 on the Cartesian grid: exact Kronecker factors, no rounding of
+ * A) and uploads them to the context's device. */
+int tnfem_problem_create(tnfem_ctx* ctx, const tnfem_problem_desc* desc, tnfem_problem** out);
+int tnfem_problem_destroy(tnfem_problem* p);
+
+/* Shapes: ncores = d + 1; modes[ncores]; mpo_ranks[ncores + 1]; rhs_ranks[ncores + 1]. */
+int tnfem_problem_info(const tnfem_problem* p, int* ncores, int* modes, int* mpo_ranks, int* rhs_ranks);
+
+/* Blocking solve of A u = b (Alg. 2, line 2).  On TNFEM_OK or TNFEM_ENOTCONV
+ * *u_out receives the solution TT (caller destroys it) and *stats (if non-NULL)
+ * is filled. */
+int tnfem_solve(tnfem_problem* p, const tnfem_solve_opts* opts, tnfem_tt** u_out, tnfem_solve_stats* stats);
+
+/* ---------------------------------------------------------------- TT objects */
+
+/* Host TT from caller cores (concatenated row-major cores, doubles). */
+int tnfem_tt_create(int ncores, const int* modes, const int* ranks, const double* cores, tnfem_tt** out);
+/* ncores; modes[ncores]; ranks[ncores + 1] (any pointer may be NULL). */
+int tnfem_tt_shape(const tnfem_tt* t, int* ncores, int* modes, int* ranks);
+/* Number of doubles of all cores. */
+size_t tnfem_tt_size(const tnfem_tt* t);
+/* Copies all cores (concatenated) into dst (host, n >= tnfem_tt_size). */
+int tnfem_tt_copy_cores(const tnfem_tt* t, double* dst, size_t n);
+/* Entries at multi-indices idx[n][ncores] (host). */
+int tnfem_tt_eval(const tnfem_tt* t, const int64_t* idx, size_t n, double* out);
+int tnfem_tt_destroy(tnfem_tt* t);
+
+/* ---------------------------------------------------------------- host assembly export
+ * Host-only (no device needed).  Dense copies of the operator's cores, for
+ * checking the assembly: core k is [R_k][n][n][R_{k+1}] (output index first).
+ * ranks[ncores + 1]; dst receives all cores concatenated (n_doubles >= total). */
+int tnfem_export_operator(const tnfem_problem_desc* desc, int* ncores, int* modes, int* ranks,
+                          double* dst, size_t n_doubles, size_t* needed);
+/* Load TT b (same layout as u). */
+int tnfem_export_load(const tnfem_problem_desc* desc, int* ncores, int* modes, int* ranks,
+                      double* dst, size_t n_doubles, size_t* needed);
+
+/* ---------------------------------------------------------------- device primitives
+ * The sweep's building blocks on caller device buffers, for testing and for
+ * callers composing their own sweeps.  All run asynchronously on `stream`.
+ *
+ * Local operator apply (the hot contraction of every local solve):
+ *   y[p][j][t] = sum L[p][b][q] A_k[b][j][i][e] x[q][i][s] Rt[t][e][s]
+ * with A_k core k of the problem's operator (reversed = 1: core k of the
+ * reversed chain, whose bonds are swapped).  L: [p][R_l][q], x: [q][n][s],
+ * Rt: [t][R_r][s], y: [p][n][t], all device, row-major, FP64.
+ * Workspace is taken from the context. */
+int tnfem_prim_local_apply(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t,
+                           const double* L, const double* x, const double* Rt, double* y, void* stream);
+
+/* Interface update: Lnew[t][e][s] = sum W[p][j][t] L[p][b][q] A_k[b][j][i][e] X[q][i][s].
+ * W: [p][n][t], L: [p][R_l][q], X: [q][n][s], Lnew: [t][R_r][s], device. */
+int tnfem_prim_env_update(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t,
+                          const double* W, const double* L, const double* X, double* Lnew, void* stream);
+
+/* Thin Householder QR of the m x n row-major matrix A (device, m, n >= 1,
+ * n <= 256): Q (m x c, c = min(m, n)) and R (c x n), device, row-major. */
+int tnfem_prim_qr(tnfem_ctx* ctx, int m, int n, const double* A, double* Q, double* R, void* stream);
+
+/* Thin SVD of the m x n row-major matrix A (device, n <= 256, m >= 1):
+ * U (m x c), S (c), Vt (c x n), c = min(m, n), singular values descending.
+ * One-sided Jacobi on the R factor of a Householder QR. */
+int tnfem_prim_svd(tnfem_ctx* ctx, int m, int n, const double* A, double* U, double* S, double* Vt, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNFEM_H */

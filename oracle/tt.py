@@ -153,7 +153,8 @@ def tt_dot(x, y):
     """Euclidean inner product <x, y> of two TTs, by left-to-right contraction."""
     E = np.ones((1, 1))
     for a, b in zip(x, y):
-        E = np.einsum("ab,anc,bnd->cd", E, a, b)
+        T = np.tensordot(E, a, axes=([0], [0]))           # [b, n, c]
+        E = np.tensordot(T, b, axes=([0, 1], [0, 1]))     # [c, d]
     return float(E[0, 0])
 
 
@@ -167,7 +168,8 @@ def mpo_matvec(A, x):
     for C, X in zip(A, x):
         R, m, n, R2 = C.shape
         r, _, r2 = X.shape
-        Y = np.einsum("amnb,cnd->acmbd", C, X).reshape(R * r, m, R2 * r2)
+        Y = np.tensordot(C, X, axes=([2], [1]))            # [R, m, R2, r, r2]
+        Y = Y.transpose(0, 3, 1, 2, 4).reshape(R * r, m, R2 * r2)
         out.append(Y)
     return out
 

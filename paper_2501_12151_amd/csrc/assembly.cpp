@@ -1,0 +1,535 @@
+// Host assembly of the QTT stiffness operator and load vector.
+//
+// On a Cartesian box with constant Jacobians the element-by-element assembly of
+// eq. elassembly factorises over axes.  For test component a / trial component b
+//   K_ab = lambda D_ab + mu D_ba + mu delta_ab sum_c D_cc,
+// where D_ab is a Kronecker product of 1D Q1 integrals: S (phi' phi') on axis a
+// and M (phi phi) elsewhere when a == b; G (phi' phi) on a, G^T on b, M elsewhere
+// otherwise.  Every 1D factor on 2^d nodes is a combination of nine matrices:
+// I, the upper shift J, J^T and six corner units (E00, Ell, E01, E10, E_{l,l-1},
+// E_{l-1,l}).  In QTT format (levels most significant first, Sec. 4) all nine
+// are read by one five-state carry automaton per axis:
+//   EQ: row and column prefixes equal;  C: column prefix = row prefix + 1 with
+//   the carry still to be absorbed (for J);  B: the same for J^T;
+//   Z: both prefixes all zeros;  O: both prefixes all ones.
+// A level core of the D-dimensional operator is the Kronecker product of the
+// axes' automaton steps (5^D states), the last level core maps the final states
+// to the "atoms" D_ab (and the boundary-condition atoms), and the component core
+// combines atoms with the material constants.  The result is exact (no rounding)
+// and its middle cores are 0/1 matrices with one nonzero per (input state,
+// mode) pair -- the structure the device contraction kernels exploit.
+// Clamped faces: A_bc = P A P + alpha (I - P), alpha = (lambda + 2 mu) h_x^(D-2),
+// with P the Kronecker product of 1D masks (symmetric elimination).
+#include "assembly.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+
+#include "common.hpp"
+#include "hostla.hpp"
+
+namespace tnfem {
+
+std::vector<double> MpoCore::dense() const {
+  std::vector<double> out((size_t)Rl * n * n * Rr, 0.0);
+  for (size_t t = 0; t < v.size(); ++t)
+    out[(((size_t)b[t] * n + io[t]) * n + ii[t]) * Rr + e[t]] += v[t];
+  return out;
+}
+
+namespace {
+
+enum Basis { I_ = 0, J_, JT_, E00_, ELL_, E01_, E10_, ELLM_, ELML_, NBASIS };
+enum State { EQ = 0, C = 1, B = 2, Z = 3, O = 4, NSTATE = 5 };
+
+struct Factor {
+  std::array<double, NBASIS> f{};
+};
+
+Factor masked(Factor F, bool clamp0, bool clamp1) {
+  // P F P with P = I - [clamp0] E00 - [clamp1] Ell: zero the first/last row and column.
+  if (clamp0) {
+    F.f[E00_] = -F.f[I_];
+    F.f[E01_] = -F.f[J_];
+    F.f[E10_] = -F.f[JT_];
+  }
+  if (clamp1) {
+    F.f[ELL_] = -F.f[I_];
+    F.f[ELLM_] = -F.f[JT_];
+    F.f[ELML_] = -F.f[J_];
+  }
+  return F;
+}
+
+// Per-axis automaton entries: (state in, out bit, in bit, state out, value).
+struct Step {
+  int s, io, ii, t;
+  double v;
+};
+
+std::vector<Step> first_steps() {
+  return {{0, 0, 0, EQ, 1}, {0, 1, 1, EQ, 1}, {0, 0, 1, C, 1},
+          {0, 1, 0, B, 1},  {0, 0, 0, Z, 1},  {0, 1, 1, O, 1}};
+}
+
+std::vector<Step> middle_steps() {
+  return {{EQ, 0, 0, EQ, 1}, {EQ, 1, 1, EQ, 1}, {EQ, 0, 1, C, 1}, {EQ, 1, 0, B, 1},
+          {C, 1, 0, C, 1},   {B, 0, 1, B, 1},   {Z, 0, 0, Z, 1},  {O, 1, 1, O, 1}};
+}
+
+std::vector<Step> accept_steps(const Factor& F) {
+  const auto& f = F.f;
+  std::vector<Step> all = {{EQ, 0, 0, 0, f[I_]},    {EQ, 1, 1, 0, f[I_]},   {EQ, 0, 1, 0, f[J_]},
+                           {EQ, 1, 0, 0, f[JT_]},   {C, 1, 0, 0, f[J_]},    {B, 0, 1, 0, f[JT_]},
+                           {Z, 0, 0, 0, f[E00_]},   {Z, 0, 1, 0, f[E01_]},  {Z, 1, 0, 0, f[E10_]},
+                           {O, 1, 1, 0, f[ELL_]},   {O, 1, 0, 0, f[ELLM_]}, {O, 0, 1, 0, f[ELML_]}};
+  std::vector<Step> out;
+  for (const auto& s : all)
+    if (s.v != 0.0) out.push_back(s);
+  return out;
+}
+
+// Kronecker product over axes of per-axis step lists -> MPO nonzeros.
+// state index: axis 0 most significant (base nstate_in / nstate_out); mode bits likewise.
+void kron_steps(const std::vector<std::vector<Step>>& axes, int nin, int nout, MpoCore& core, int e_fixed) {
+  const int D = (int)axes.size();
+  std::vector<size_t> idx(D, 0);
+  while (true) {
+    int s = 0, t = 0, io = 0, ii = 0;
+    double v = 1.0;
+    for (int a = 0; a < D; ++a) {
+      const Step& st = axes[a][idx[a]];
+      s = s * nin + st.s;
+      t = t * nout + st.t;
+      io = io * 2 + st.io;
+      ii = ii * 2 + st.ii;
+      v *= st.v;
+    }
+    if (v != 0.0) core.add(s, io, ii, e_fixed >= 0 ? e_fixed : t, v);
+    int a = D - 1;
+    while (a >= 0 && ++idx[a] == axes[a].size()) idx[a--] = 0;
+    if (a < 0) break;
+  }
+}
+
+struct Atom {
+  std::vector<Factor> axis;  // one factor per axis
+  std::vector<double> comp;  // D x D component coefficients
+};
+
+// Dense TT-SVD of a vector of length 2^d into d QTT cores [r][2][r'].
+std::vector<TTCore> vector_qtt(const std::vector<double>& v, int d) {
+  std::vector<TTCore> cores;
+  std::vector<double> rest = v;  // r x cols, row-major
+  int r = 1;
+  size_t cols = v.size();
+  double nrm = 0;
+  for (double x : v) nrm += x * x;
+  nrm = std::sqrt(nrm);
+  const double delta = 1e-15 * nrm / std::sqrt(std::max(d - 1, 1));
+  for (int k = 0; k < d - 1; ++k) {
+    const int m = r * 2;
+    const size_t nc = cols / 2;
+    // rest as m x nc matrix (row-major), SVD
+    std::vector<double> U, S, Vt;
+    hostla::svd(m, (int)nc, rest.data(), U, S, Vt);
+    const int c = (int)S.size();
+    // truncation: drop tail <= delta (absolute)
+    double tail = 0;
+    int rk = c;
+    for (int j = c - 1; j >= 1; --j) {
+      if (tail + S[j] * S[j] <= delta * delta) {
+        tail += S[j] * S[j];
+        rk = j;
+      } else {
+        break;
+      }
+    }
+    TTCore core;
+    core.rl = r;
+    core.n = 2;
+    core.rr = rk;
+    core.data.resize((size_t)m * rk);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < rk; ++j) core.data[(size_t)i * rk + j] = U[(size_t)i * c + j];
+    cores.push_back(core);
+    std::vector<double> nr((size_t)rk * nc);
+    for (int i = 0; i < rk; ++i)
+      for (size_t j = 0; j < nc; ++j) nr[i * nc + j] = S[i] * Vt[(size_t)i * nc + j];
+    rest.swap(nr);
+    r = rk;
+    cols = nc;
+  }
+  TTCore last;
+  last.rl = r;
+  last.n = 2;
+  last.rr = 1;
+  last.data = rest;
+  cores.push_back(last);
+  return cores;
+}
+
+// Level cores of a Kronecker product of per-axis QTT vectors (axis 0 most significant).
+std::vector<TTCore> kron_vector_levels(const std::vector<std::vector<TTCore>>& axes) {
+  const int d = (int)axes[0].size();
+  std::vector<TTCore> out;
+  for (int l = 0; l < d; ++l) {
+    TTCore C = axes[0][l];
+    for (size_t a = 1; a < axes.size(); ++a) {
+      const TTCore& F = axes[a][l];
+      TTCore N;
+      N.rl = C.rl * F.rl;
+      N.n = C.n * F.n;
+      N.rr = C.rr * F.rr;
+      N.data.assign((size_t)N.rl * N.n * N.rr, 0.0);
+      for (int a1 = 0; a1 < C.rl; ++a1)
+        for (int a2 = 0; a2 < F.rl; ++a2)
+          for (int i1 = 0; i1 < C.n; ++i1)
+            for (int i2 = 0; i2 < F.n; ++i2)
+              for (int b1 = 0; b1 < C.rr; ++b1)
+                for (int b2 = 0; b2 < F.rr; ++b2) {
+                  const double x = C.data[((size_t)a1 * C.n + i1) * C.rr + b1] *
+                                   F.data[((size_t)a2 * F.n + i2) * F.rr + b2];
+                  N.data[(((size_t)(a1 * F.rl + a2)) * N.n + (i1 * F.n + i2)) * N.rr + (b1 * F.rr + b2)] = x;
+                }
+      C = N;
+    }
+    out.push_back(C);
+  }
+  return out;
+}
+
+// Direct sum of two TTs with equal modes (first core joined along the right bond,
+// last core along the left bond, middle cores block diagonal).
+std::vector<TTCore> tt_sum(const std::vector<TTCore>& x, const std::vector<TTCore>& y) {
+  const size_t K = x.size();
+  std::vector<TTCore> out(K);
+  for (size_t k = 0; k < K; ++k) {
+    const TTCore &a = x[k], &b = y[k];
+    TTCore c;
+    c.n = a.n;
+    c.rl = (k == 0) ? 1 : a.rl + b.rl;
+    c.rr = (k == K - 1) ? 1 : a.rr + b.rr;
+    c.data.assign((size_t)c.rl * c.n * c.rr, 0.0);
+    const int ol = (k == 0) ? 0 : a.rl, orr = (k == K - 1) ? 0 : a.rr;
+    for (int i = 0; i < a.rl; ++i)
+      for (int j = 0; j < a.n; ++j)
+        for (int l = 0; l < a.rr; ++l) c.data[((size_t)i * c.n + j) * c.rr + l] = a.data[((size_t)i * a.n + j) * a.rr + l];
+    for (int i = 0; i < b.rl; ++i)
+      for (int j = 0; j < b.n; ++j)
+        for (int l = 0; l < b.rr; ++l)
+          c.data[((size_t)(i + ol) * c.n + j) * c.rr + (l + orr)] += b.data[((size_t)i * b.n + j) * b.rr + l];
+    out[k] = c;
+  }
+  return out;
+}
+
+}  // namespace
+
+void tt_round_host(std::vector<TTCore>& cores, double tol, int rmax) {
+  const int K = (int)cores.size();
+  if (K == 1) return;
+  // right-to-left orthogonalisation: core k = L Q with Q row-orthonormal
+  for (int k = K - 1; k > 0; --k) {
+    TTCore& c = cores[k];
+    const int rows = c.rl, cols = c.n * c.rr;
+    std::vector<double> T((size_t)cols * rows);
+    for (int i = 0; i < rows; ++i)
+      for (int j = 0; j < cols; ++j) T[(size_t)j * rows + i] = c.data[(size_t)i * cols + j];
+    std::vector<double> Q, R;
+    hostla::qr(cols, rows, T.data(), Q, R);  // Q cols x q, R q x rows
+    const int q = std::min(cols, rows);
+    TTCore nc;
+    nc.rl = q;
+    nc.n = c.n;
+    nc.rr = c.rr;
+    nc.data.resize((size_t)q * cols);
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < cols; ++j) nc.data[(size_t)i * cols + j] = Q[(size_t)j * q + i];
+    // previous core times R^T
+    TTCore& p = cores[k - 1];
+    const int pr = p.rl * p.n;
+    std::vector<double> np((size_t)pr * q, 0.0);
+    for (int i = 0; i < pr; ++i)
+      for (int a = 0; a < rows; ++a) {
+        const double x = p.data[(size_t)i * rows + a];
+        if (x == 0.0) continue;
+        for (int j = 0; j < q; ++j) np[(size_t)i * q + j] += x * R[(size_t)j * rows + a];
+      }
+    p.rr = q;
+    p.data.swap(np);
+    c = nc;
+  }
+  double nrm = 0;
+  for (double x : cores[0].data) nrm += x * x;
+  nrm = std::sqrt(nrm);
+  const double delta_rel = tol / std::sqrt((double)std::max(K - 1, 1));
+  for (int k = 0; k < K - 1; ++k) {
+    TTCore& c = cores[k];
+    const int m = c.rl * c.n, n = c.rr;
+    std::vector<double> U, S, Vt;
+    hostla::svd(m, n, c.data.data(), U, S, Vt);
+    const int cc = (int)S.size();
+    // absolute threshold relative to the whole TT norm
+    double tail = 0;
+    int rk = cc;
+    for (int j = cc - 1; j >= 1; --j) {
+      if (tail + S[j] * S[j] <= delta_rel * delta_rel * nrm * nrm) {
+        tail += S[j] * S[j];
+        rk = j;
+      } else {
+        break;
+      }
+    }
+    rk = std::max(1, std::min(rk, rmax));
+    TTCore nc;
+    nc.rl = c.rl;
+    nc.n = c.n;
+    nc.rr = rk;
+    nc.data.resize((size_t)m * rk);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < rk; ++j) nc.data[(size_t)i * rk + j] = U[(size_t)i * cc + j];
+    TTCore& nx = cores[k + 1];
+    const int cols = nx.n * nx.rr;
+    std::vector<double> W((size_t)rk * n);
+    for (int i = 0; i < rk; ++i)
+      for (int j = 0; j < n; ++j) W[(size_t)i * n + j] = S[i] * Vt[(size_t)i * n + j];
+    std::vector<double> nd((size_t)rk * cols, 0.0);
+    hostla::gemm(rk, cols, n, W.data(), nx.data.data(), nd.data());
+    nx.rl = rk;
+    nx.data.swap(nd);
+    c = nc;
+  }
+}
+
+Assembled assemble(const tnfem_problem_desc& desc) {
+  const int D = desc.dim, d = desc.level;
+  TNFEM_REQUIRE(D == 2 || D == 3, "dim must be 2 or 3 (got %d)", D);
+  TNFEM_REQUIRE(d >= 2 && d <= 20, "level must be in [2, 20] (got %d)", d);
+  TNFEM_REQUIRE(desc.E > 0 && std::isfinite(desc.E), "E must be positive");
+  TNFEM_REQUIRE(desc.nu > -1.0 && desc.nu < 0.5, "nu must be in (-1, 0.5)");
+  for (int a = 0; a < D; ++a) TNFEM_REQUIRE(desc.extent[a] > 0, "extent[%d] must be positive", a);
+  TNFEM_REQUIRE(!(desc.plane_stress && D == 3), "plane_stress is a 2D option");
+  TNFEM_REQUIRE((desc.clamp_mask >> (2 * D)) == 0, "clamp_mask names a face beyond dim");
+  TNFEM_REQUIRE(desc.n_tractions >= 0 && desc.n_tractions <= 6, "n_tractions must be in [0, 6]");
+  TNFEM_REQUIRE(desc.layer_E == nullptr, "layered material is not supported by this version");
+  const int n = 1 << d;
+
+  Assembled out;
+  out.D = D;
+  out.d = d;
+  double lam = desc.E * desc.nu / ((1 + desc.nu) * (1 - 2 * desc.nu));
+  double mu = desc.E / (2 * (1 + desc.nu));
+  if (desc.plane_stress) lam = 2 * lam * mu / (lam + 2 * mu);
+  const double h0 = desc.extent[0] / (n - 1);
+  const double alpha = (lam + 2 * mu) * std::pow(h0, D - 2);
+  out.lam = lam;
+  out.mu = mu;
+  out.alpha = alpha;
+
+  bool c0[3] = {false, false, false}, c1[3] = {false, false, false};
+  bool any_clamp = false;
+  for (int a = 0; a < D; ++a) {
+    c0[a] = (desc.clamp_mask >> (2 * a)) & 1;
+    c1[a] = (desc.clamp_mask >> (2 * a + 1)) & 1;
+    any_clamp = any_clamp || c0[a] || c1[a];
+  }
+
+  // 1D factors per axis (closed forms of the element integrals, summed over elements)
+  std::vector<Factor> S(D), M(D), G(D), GT(D), Id(D), P(D);
+  for (int a = 0; a < D; ++a) {
+    const double h = desc.extent[a] / (n - 1);
+    Factor s, m, g, gt, id;
+    s.f[I_] = 2 / h; s.f[J_] = -1 / h; s.f[JT_] = -1 / h; s.f[E00_] = -1 / h; s.f[ELL_] = -1 / h;
+    m.f[I_] = 4 * h / 6; m.f[J_] = h / 6; m.f[JT_] = h / 6; m.f[E00_] = -2 * h / 6; m.f[ELL_] = -2 * h / 6;
+    g.f[J_] = -0.5; g.f[JT_] = 0.5; g.f[E00_] = -0.5; g.f[ELL_] = 0.5;
+    gt.f[J_] = 0.5; gt.f[JT_] = -0.5; gt.f[E00_] = -0.5; gt.f[ELL_] = 0.5;
+    id.f[I_] = 1;
+    S[a] = masked(s, c0[a], c1[a]);
+    M[a] = masked(m, c0[a], c1[a]);
+    G[a] = masked(g, c0[a], c1[a]);
+    GT[a] = masked(gt, c0[a], c1[a]);
+    Id[a] = id;
+    P[a] = masked(id, c0[a], c1[a]);
+  }
+
+  std::vector<Atom> atoms;
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) {
+      Atom at;
+      for (int c = 0; c < D; ++c) {
+        if (a == b) at.axis.push_back(c == a ? S[c] : M[c]);
+        else at.axis.push_back(c == a ? G[c] : (c == b ? GT[c] : M[c]));
+      }
+      at.comp.assign(D * D, 0.0);
+      at.comp[a * D + b] += lam;
+      at.comp[b * D + a] += mu;
+      if (a == b)
+        for (int c = 0; c < D; ++c) at.comp[c * D + c] += mu;
+      atoms.push_back(at);
+    }
+  if (any_clamp) {
+    Atom ia, pa;
+    ia.axis = Id;
+    pa.axis = P;
+    ia.comp.assign(D * D, 0.0);
+    pa.comp.assign(D * D, 0.0);
+    for (int c = 0; c < D; ++c) {
+      ia.comp[c * D + c] = alpha;
+      pa.comp[c * D + c] = -alpha;
+    }
+    atoms.push_back(ia);
+    atoms.push_back(pa);
+  }
+  const int nat = (int)atoms.size();
+  const int ns = (int)std::lround(std::pow(5.0, D));
+  const int nm = 1 << D;
+
+  // level cores
+  for (int l = 0; l < d; ++l) {
+    MpoCore core;
+    core.n = nm;
+    if (l == 0) {
+      core.Rl = 1;
+      core.Rr = ns;
+      kron_steps(std::vector<std::vector<Step>>(D, first_steps()), 1, NSTATE, core, -1);
+    } else if (l < d - 1) {
+      core.Rl = ns;
+      core.Rr = ns;
+      kron_steps(std::vector<std::vector<Step>>(D, middle_steps()), NSTATE, NSTATE, core, -1);
+    } else {
+      core.Rl = ns;
+      core.Rr = nat;
+      for (int t = 0; t < nat; ++t) {
+        std::vector<std::vector<Step>> axes;
+        for (int a = 0; a < D; ++a) axes.push_back(accept_steps(atoms[t].axis[a]));
+        kron_steps(axes, NSTATE, 1, core, t);
+      }
+    }
+    out.A.push_back(core);
+  }
+  // component core [nat][D][D][1]
+  {
+    MpoCore core;
+    core.Rl = nat;
+    core.Rr = 1;
+    core.n = D;
+    for (int t = 0; t < nat; ++t)
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b)
+          if (atoms[t].comp[a * D + b] != 0.0) core.add(t, a, b, 0, atoms[t].comp[a * D + b]);
+    out.A.push_back(core);
+  }
+
+  // ---- load: sum of (component vector) x (Kronecker product of 1D nodal vectors)
+  struct LoadTerm {
+    std::vector<double> comp;
+    std::vector<std::vector<double>> vec;
+  };
+  std::vector<LoadTerm> terms;
+  auto mass_times = [&](int a, const std::vector<double>& v) {
+    const double h = desc.extent[a] / (n - 1);
+    std::vector<double> r(n);
+    for (int i = 0; i < n; ++i) {
+      const double left = i > 0 ? v[i - 1] : 0.0, right = i < n - 1 ? v[i + 1] : 0.0;
+      const double diag = (i == 0 || i == n - 1) ? 2.0 : 4.0;
+      r[i] = h / 6.0 * (left + diag * v[i] + right);
+    }
+    return r;
+  };
+  auto mask_vec = [&](int a, std::vector<double> v) {
+    if (c0[a]) v[0] = 0.0;
+    if (c1[a]) v[n - 1] = 0.0;
+    return v;
+  };
+  const std::vector<double> ones(n, 1.0);
+  if (desc.has_body_force) {
+    LoadTerm t;
+    t.comp.assign(desc.body_force, desc.body_force + D);
+    for (int a = 0; a < D; ++a) t.vec.push_back(mask_vec(a, mass_times(a, ones)));
+    terms.push_back(t);
+  }
+  for (int q = 0; q < desc.n_tractions; ++q) {
+    const int face = desc.traction_face[q];
+    TNFEM_REQUIRE(face >= 0 && face < 2 * D, "traction face %d out of range", face);
+    const int ax = face / 2, side = face % 2;
+    LoadTerm t;
+    t.comp.assign(desc.traction[q], desc.traction[q] + D);
+    for (int a = 0; a < D; ++a) {
+      if (a == ax) {
+        std::vector<double> e(n, 0.0);
+        e[side ? n - 1 : 0] = 1.0;
+        t.vec.push_back(mask_vec(a, e));
+      } else {
+        t.vec.push_back(mask_vec(a, mass_times(a, ones)));
+      }
+    }
+    terms.push_back(t);
+  }
+  if (desc.has_manufactured) {
+    const double* c = desc.manufactured_c;
+    const double pi = 3.14159265358979323846;
+    std::vector<std::vector<double>> sv(D), kv(D);
+    for (int a = 0; a < D; ++a) {
+      std::vector<double> s(n), k(n);
+      for (int i = 0; i < n; ++i) {
+        const double x = i * desc.extent[a] / (n - 1);
+        s[i] = std::sin(pi * x);
+        k[i] = std::cos(pi * x);
+      }
+      sv[a] = mask_vec(a, mass_times(a, s));
+      kv[a] = mask_vec(a, mass_times(a, k));
+    }
+    // -div sigma(u*) with u*_i = c_i prod sin(pi x_a): separable terms
+    for (int i = 0; i < D; ++i) {
+      LoadTerm t;
+      t.comp.assign(D, 0.0);
+      t.comp[i] = pi * pi * (lam + (D + 1) * mu) * c[i];
+      for (int a = 0; a < D; ++a) t.vec.push_back(sv[a]);
+      terms.push_back(t);
+      for (int k = 0; k < D; ++k) {
+        if (k == i) continue;
+        LoadTerm u;
+        u.comp.assign(D, 0.0);
+        u.comp[i] = -pi * pi * (lam + mu) * c[k];
+        for (int a = 0; a < D; ++a) u.vec.push_back((a == i || a == k) ? kv[a] : sv[a]);
+        terms.push_back(u);
+      }
+    }
+  }
+  std::vector<TTCore> total;
+  for (const auto& t : terms) {
+    std::vector<std::vector<TTCore>> axes;
+    for (int a = 0; a < D; ++a) axes.push_back(vector_qtt(t.vec[a], d));
+    std::vector<TTCore> lev = kron_vector_levels(axes);
+    TTCore cc;
+    cc.rl = 1;
+    cc.n = D;
+    cc.rr = 1;
+    cc.data = t.comp;
+    lev.push_back(cc);
+    if (total.empty()) {
+      total = lev;
+    } else {
+      total = tt_sum(total, lev);
+      tt_round_host(total, 1e-14, 1 << 30);
+    }
+  }
+  if (total.empty()) {
+    for (int l = 0; l < d; ++l) {
+      TTCore z;
+      z.n = nm;
+      z.data.assign(nm, 0.0);
+      total.push_back(z);
+    }
+    TTCore z;
+    z.n = D;
+    z.data.assign(D, 0.0);
+    total.push_back(z);
+  }
+  out.b = total;
+  return out;
+}
+
+}  // namespace tnfem

@@ -1,0 +1,41 @@
+// Host assembly of the QTT operator and load (Alg. 1 on the Cartesian grid).
+#pragma once
+
+#include <vector>
+
+#include "../../include/tnfem.h"
+
+namespace tnfem {
+
+// One MPO core as a list of nonzeros A[b][io][ii][e] = v (io: output mode, ii: input mode).
+struct MpoCore {
+  int Rl = 1, Rr = 1, n = 1;
+  std::vector<int> b, io, ii, e;
+  std::vector<double> v;
+  void add(int b_, int io_, int ii_, int e_, double v_) {
+    b.push_back(b_); io.push_back(io_); ii.push_back(ii_); e.push_back(e_); v.push_back(v_);
+  }
+  size_t nnz() const { return v.size(); }
+  std::vector<double> dense() const;  // [Rl][n][n][Rr]
+};
+
+// One TT core, row-major [rl][n][rr].
+struct TTCore {
+  int rl = 1, n = 1, rr = 1;
+  std::vector<double> data;
+};
+
+struct Assembled {
+  int D = 2, d = 2;
+  double lam = 0, mu = 0, alpha = 0;
+  std::vector<MpoCore> A;  // d level cores, then the component core
+  std::vector<TTCore> b;   // load, same layout
+};
+
+// Validates desc (throws tnfem::Error) and assembles operator and load.
+Assembled assemble(const tnfem_problem_desc& desc);
+
+// TT rounding on the host (relative accuracy tol, at most rmax).
+void tt_round_host(std::vector<TTCore>& cores, double tol, int rmax);
+
+}  // namespace tnfem

@@ -1,0 +1,383 @@
+// C ABI entry points (declared in include/tnfem.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "assembly.hpp"
+#include "common.hpp"
+#include "engine.hpp"
+
+struct tnfem_ctx {
+  tnfem::Context c;
+};
+struct tnfem_problem {
+  std::unique_ptr<tnfem::Problem> p;
+  tnfem_ctx* ctx;
+};
+struct tnfem_tt {
+  tnfem::HostTT t;
+};
+
+namespace tnfem {
+static thread_local std::string g_last_error;
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+}  // namespace tnfem
+
+using tnfem::fail;
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const tnfem::Error& e) {
+    tnfem::set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    tnfem::set_last_error("host allocation failed");
+    return TNFEM_ENOMEM;
+  } catch (const std::exception& e) {
+    tnfem::set_last_error(e.what());
+    return TNFEM_EINVAL;
+  }
+}
+
+static hipStream_t pick_stream(tnfem_ctx* ctx, void* s) {
+  return s ? static_cast<hipStream_t>(s) : ctx->c.stream;
+}
+
+extern "C" {
+
+const char* tnfem_last_error(void) { return tnfem::g_last_error.c_str(); }
+
+void tnfem_default_opts(tnfem_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->rank_cap = 32;
+  o->tol = 1e-8;
+  o->max_sweeps = 30;
+  o->rho = 4;
+  o->init_rank = 2;
+  o->seed_x = 1;
+  o->seed_z = 2;
+  o->cg_maxit = 500;
+  o->precision = 0;
+}
+
+int tnfem_ctx_create(tnfem_ctx** out, int device, void* hip_stream) {
+  return guarded([&] {
+    if (!out) fail(TNFEM_EINVAL, "out is NULL");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) fail(TNFEM_EDEVICE, "no HIP device");
+    if (device < 0 || device >= count) fail(TNFEM_EINVAL, "device %d out of range (%d devices)", device, count);
+    auto c = std::make_unique<tnfem_ctx>();
+    c->c.device = device;
+    tnfem::hip_check(hipSetDevice(device), "hipSetDevice");
+    if (hip_stream) {
+      c->c.stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      tnfem::hip_check(hipStreamCreateWithFlags(&c->c.stream, hipStreamNonBlocking), "hipStreamCreate");
+      c->c.own_stream = true;
+    }
+    *out = c.release();
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_ctx_destroy(tnfem_ctx* ctx) {
+  return guarded([&] {
+    if (!ctx) return TNFEM_OK;
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.scratch) (void)hipFree(ctx->c.scratch);
+    if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
+    delete ctx;
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_problem_create(tnfem_ctx* ctx, const tnfem_problem_desc* desc, tnfem_problem** out) {
+  return guarded([&] {
+    if (!ctx || !desc || !out) fail(TNFEM_EINVAL, "NULL argument");
+    auto p = std::make_unique<tnfem_problem>();
+    p->ctx = ctx;
+    p->p = tnfem::make_problem(&ctx->c, *desc);
+    *out = p.release();
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_problem_destroy(tnfem_problem* p) {
+  return guarded([&] {
+    if (!p) return TNFEM_OK;
+    (void)hipSetDevice(p->ctx->c.device);
+    (void)hipStreamSynchronize(p->ctx->c.stream);
+    delete p;
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_problem_info(const tnfem_problem* p, int* ncores, int* modes, int* mpo_ranks, int* rhs_ranks) {
+  return guarded([&] {
+    if (!p) fail(TNFEM_EINVAL, "NULL problem");
+    const auto& P = *p->p;
+    if (ncores) *ncores = P.K;
+    for (int k = 0; k < P.K; ++k) {
+      if (modes) modes[k] = P.modes[k];
+    }
+    for (int k = 0; k <= P.K; ++k) {
+      if (mpo_ranks) mpo_ranks[k] = P.mrank[0][k];
+      if (rhs_ranks) rhs_ranks[k] = P.brank[0][k];
+    }
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_solve(tnfem_problem* p, const tnfem_solve_opts* opts, tnfem_tt** u_out, tnfem_solve_stats* stats) {
+  return guarded([&] {
+    if (!p || !u_out) fail(TNFEM_EINVAL, "NULL argument");
+    tnfem_solve_opts o;
+    if (opts) o = *opts;
+    else tnfem_default_opts(&o);
+    auto t = std::make_unique<tnfem_tt>();
+    tnfem_solve_stats st;
+    std::memset(&st, 0, sizeof st);
+    const int rc = tnfem::run_solve(*p->p, o, t->t, st);
+    if (stats) *stats = st;
+    if (rc == TNFEM_OK || rc == TNFEM_ENOTCONV) {
+      *u_out = t.release();
+    } else {
+      *u_out = nullptr;
+      tnfem::set_last_error("non-finite value in the sweep");
+    }
+    if (rc == TNFEM_ENOTCONV) tnfem::set_last_error("sweep limit reached before the tolerance");
+    return rc;
+  });
+}
+
+int tnfem_tt_create(int ncores, const int* modes, const int* ranks, const double* cores, tnfem_tt** out) {
+  return guarded([&] {
+    if (ncores < 1 || !modes || !ranks || !cores || !out) fail(TNFEM_EINVAL, "invalid TT description");
+    if (ranks[0] != 1 || ranks[ncores] != 1) fail(TNFEM_EINVAL, "boundary ranks must be 1");
+    auto t = std::make_unique<tnfem_tt>();
+    size_t off = 0;
+    for (int k = 0; k < ncores; ++k) {
+      if (modes[k] < 1 || ranks[k] < 1 || ranks[k + 1] < 1) fail(TNFEM_EINVAL, "nonpositive mode or rank");
+      const size_t cnt = (size_t)ranks[k] * modes[k] * ranks[k + 1];
+      t->t.cores.emplace_back(cores + off, cores + off + cnt);
+      off += cnt;
+    }
+    t->t.modes.assign(modes, modes + ncores);
+    t->t.ranks.assign(ranks, ranks + ncores + 1);
+    *out = t.release();
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_tt_shape(const tnfem_tt* t, int* ncores, int* modes, int* ranks) {
+  return guarded([&] {
+    if (!t) fail(TNFEM_EINVAL, "NULL TT");
+    const int K = (int)t->t.modes.size();
+    if (ncores) *ncores = K;
+    if (modes) std::copy(t->t.modes.begin(), t->t.modes.end(), modes);
+    if (ranks) std::copy(t->t.ranks.begin(), t->t.ranks.end(), ranks);
+    return TNFEM_OK;
+  });
+}
+
+size_t tnfem_tt_size(const tnfem_tt* t) {
+  if (!t) return 0;
+  size_t s = 0;
+  for (const auto& c : t->t.cores) s += c.size();
+  return s;
+}
+
+int tnfem_tt_copy_cores(const tnfem_tt* t, double* dst, size_t n) {
+  return guarded([&] {
+    if (!t || !dst) fail(TNFEM_EINVAL, "NULL argument");
+    if (n < tnfem_tt_size(t)) fail(TNFEM_EINVAL, "destination too small");
+    size_t off = 0;
+    for (const auto& c : t->t.cores) {
+      std::copy(c.begin(), c.end(), dst + off);
+      off += c.size();
+    }
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_tt_eval(const tnfem_tt* t, const int64_t* idx, size_t n, double* out) {
+  return guarded([&] {
+    if (!t || (n && (!idx || !out))) fail(TNFEM_EINVAL, "NULL argument");
+    const auto& T = t->t;
+    const int K = (int)T.modes.size();
+    std::vector<double> v, w;
+    for (size_t q = 0; q < n; ++q) {
+      v.assign(1, 1.0);
+      for (int k = 0; k < K; ++k) {
+        const int64_t i = idx[q * K + k];
+        if (i < 0 || i >= T.modes[k]) fail(TNFEM_EINVAL, "index out of range");
+        const int rl = T.ranks[k], rr = T.ranks[k + 1];
+        w.assign(rr, 0.0);
+        for (int a = 0; a < rl; ++a)
+          for (int b = 0; b < rr; ++b) w[b] += v[a] * T.cores[k][((size_t)a * T.modes[k] + i) * rr + b];
+        v.swap(w);
+      }
+      out[q] = v[0];
+    }
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_tt_destroy(tnfem_tt* t) {
+  delete t;
+  return TNFEM_OK;
+}
+
+int tnfem_export_operator(const tnfem_problem_desc* desc, int* ncores, int* modes, int* ranks, double* dst,
+                          size_t n_doubles, size_t* needed) {
+  return guarded([&] {
+    if (!desc) fail(TNFEM_EINVAL, "NULL descriptor");
+    tnfem::Assembled a = tnfem::assemble(*desc);
+    const int K = (int)a.A.size();
+    size_t tot = 0;
+    for (const auto& c : a.A) tot += (size_t)c.Rl * c.n * c.n * c.Rr;
+    if (needed) *needed = tot;
+    if (ncores) *ncores = K;
+    for (int k = 0; k < K; ++k) {
+      if (modes) modes[k] = a.A[k].n;
+      if (ranks) {
+        ranks[k] = a.A[k].Rl;
+        ranks[k + 1] = a.A[k].Rr;
+      }
+    }
+    if (dst) {
+      if (n_doubles < tot) fail(TNFEM_EINVAL, "destination too small (%zu < %zu)", n_doubles, tot);
+      size_t off = 0;
+      for (const auto& c : a.A) {
+        auto d = c.dense();
+        std::copy(d.begin(), d.end(), dst + off);
+        off += d.size();
+      }
+    }
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_export_load(const tnfem_problem_desc* desc, int* ncores, int* modes, int* ranks, double* dst,
+                      size_t n_doubles, size_t* needed) {
+  return guarded([&] {
+    if (!desc) fail(TNFEM_EINVAL, "NULL descriptor");
+    tnfem::Assembled a = tnfem::assemble(*desc);
+    const int K = (int)a.b.size();
+    size_t tot = 0;
+    for (const auto& c : a.b) tot += c.data.size();
+    if (needed) *needed = tot;
+    if (ncores) *ncores = K;
+    for (int k = 0; k < K; ++k) {
+      if (modes) modes[k] = a.b[k].n;
+      if (ranks) {
+        ranks[k] = a.b[k].rl;
+        ranks[k + 1] = a.b[k].rr;
+      }
+    }
+    if (dst) {
+      if (n_doubles < tot) fail(TNFEM_EINVAL, "destination too small");
+      size_t off = 0;
+      for (const auto& c : a.b) {
+        std::copy(c.data.begin(), c.data.end(), dst + off);
+        off += c.data.size();
+      }
+    }
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_prim_local_apply(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t, const double* L,
+                           const double* x, const double* Rt, double* y, void* stream) {
+  return guarded([&] {
+    if (!prob || !L || !x || !Rt || !y) fail(TNFEM_EINVAL, "NULL argument");
+    auto& P = *prob->p;
+    if (k < 0 || k >= P.K) fail(TNFEM_EINVAL, "core index %d out of range", k);
+    if (p < 1 || q < 1 || s < 1 || t < 1) fail(TNFEM_EINVAL, "ranks must be >= 1");
+    tnfem::hip_check(hipSetDevice(prob->ctx->c.device), "hipSetDevice");
+    const auto& pl = P.plans[reversed ? 1 : 0][k];
+    tnfem::dev_local_apply(P, pl, p, q, s, t, L, x, Rt, y, nullptr, pick_stream(prob->ctx, stream), nullptr);
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_prim_env_update(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t, const double* W,
+                          const double* L, const double* X, double* Lnew, void* stream) {
+  return guarded([&] {
+    if (!prob || !W || !L || !X || !Lnew) fail(TNFEM_EINVAL, "NULL argument");
+    auto& P = *prob->p;
+    if (k < 0 || k >= P.K) fail(TNFEM_EINVAL, "core index %d out of range", k);
+    if (p < 1 || q < 1 || s < 1 || t < 1) fail(TNFEM_EINVAL, "ranks must be >= 1");
+    tnfem::hip_check(hipSetDevice(prob->ctx->c.device), "hipSetDevice");
+    const auto& pl = P.plans[reversed ? 1 : 0][k];
+    tnfem::dev_env_update(P, pl, p, q, s, t, W, L, X, Lnew, pick_stream(prob->ctx, stream), nullptr);
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_prim_qr(tnfem_ctx* ctx, int m, int n, const double* A, double* Q, double* R, void* stream) {
+  return guarded([&] {
+    if (!ctx || !A || !Q || !R) fail(TNFEM_EINVAL, "NULL argument");
+    if (m < 1 || n < 1 || n > 256) fail(TNFEM_EINVAL, "need m >= 1, 1 <= n <= 256");
+    tnfem::hip_check(hipSetDevice(ctx->c.device), "hipSetDevice");
+    const int c = std::min(m, n);
+    double* ws = ctx->c.ensure_scratch((size_t)m * n + (size_t)m * c + 2 * c + 1);
+    tnfem::launch_qr(m, n, A, n, Q, c, R, n, ws, pick_stream(ctx, stream));
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_prim_svd(tnfem_ctx* ctx, int m, int n, const double* A, double* U, double* S, double* Vt, void* stream) {
+  return guarded([&] {
+    if (!ctx || !A || !U || !S || !Vt) fail(TNFEM_EINVAL, "NULL argument");
+    if (m < 1 || n < 1 || std::min(m, n) > 256) fail(TNFEM_EINVAL, "need min(m, n) <= 256");
+    tnfem::hip_check(hipSetDevice(ctx->c.device), "hipSetDevice");
+    hipStream_t st = pick_stream(ctx, stream);
+    const bool tall = m >= n;
+    const int mm = tall ? m : n, nn = tall ? n : m;  // work on the tall orientation
+    const size_t need = (size_t)mm * nn * 4 + (size_t)nn * nn * 6 + 4 * nn + 8;
+    double* ws = ctx->c.ensure_scratch(need);
+    double* At = ws;                       // mm x nn (transposed input when wide)
+    double* Q = At + (size_t)mm * nn;      // mm x nn
+    double* R = Q + (size_t)mm * nn;       // nn x nn
+    double* UR = R + (size_t)nn * nn;      // nn x nn
+    double* V = UR + (size_t)nn * nn;      // nn x nn
+    double* qws = V + (size_t)nn * nn;     // qr: 2 mm nn + 2 nn ; jacobi: 2 nn^2
+    const double* src = A;
+    if (!tall) {
+      tnfem::launch_core_transpose(m, 1, n, A, At, st);  // At = A^T (n x m)
+      src = At;
+    }
+    tnfem::launch_qr(mm, nn, src, nn, Q, nn, R, nn, qws, st);
+    tnfem::launch_jacobi_svd(nn, R, nn, UR, S, V, qws, st);
+    tnfem::GemmDesc g;
+    if (tall) {
+      // U = Q UR (m x n); Vt = V^T
+      g.A = Q; g.a_sm = nn; g.a_sk = 1;
+      g.B = UR; g.b_sk = nn; g.b_sn = 1;
+      g.C = U; g.c_sm = nn; g.c_sn = 1;
+      g.M = mm; g.N = nn; g.K = nn;
+      tnfem::launch_gemm(g, st);
+      tnfem::launch_core_transpose(nn, 1, nn, V, Vt, st);
+    } else {
+      // A^T = (Q UR) S V^T  =>  A = V S (Q UR)^T: U = V (m x m), Vt = (Q UR)^T (m x n)
+      tnfem::launch_copy2d(nn, nn, V, nn, U, nn, 1.0, 0.0, st);
+      g.A = UR; g.a_sm = 1; g.a_sk = nn;   // UR^T
+      g.B = Q; g.b_sk = 1; g.b_sn = nn;    // Q^T
+      g.C = Vt; g.c_sm = mm; g.c_sn = 1;
+      g.M = nn; g.N = mm; g.K = nn;
+      tnfem::launch_gemm(g, st);
+    }
+    return TNFEM_OK;
+  });
+}
+
+}  // extern "C"

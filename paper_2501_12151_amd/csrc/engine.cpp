@@ -1,0 +1,806 @@
+// The AMEn sweep on the device.
+//
+// Alg. 2 of the paper applies AMEn (Dolgov and Savostyanov) to A u = M f0.  The
+// sweep below follows the published method: alternating half-sweeps over the
+// cores; at each core the local system (interfaces x operator core x
+// interfaces) is solved by preconditioned conjugate gradients from the current
+// core, the solution is truncated by SVD, the basis is enriched with the
+// residual projected on a rank-rho residual TT Z, re-orthogonalised by QR, and
+// the interfaces are updated.  Every arithmetic step runs in the kernels of
+// kernels.hip; the host only sequences launches, reads back the CG status of a
+// core and the truncation rank (both needed to size later launches), and
+// decides when to stop.  A right-to-left half-sweep is the same code on the
+// reversed chain: cores are transposed on the device, operator plans for both
+// orientations are built at problem creation.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "common.hpp"
+
+namespace tnfem {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? TNFEM_ENOMEM : TNFEM_EDEVICE, "%s: %s", what,
+                            hipGetErrorString(e));
+}
+
+DevArena::~DevArena() { release_all(); }
+
+void DevArena::release_all() {
+  for (void* p : ptrs_) (void)hipFree(p);
+  ptrs_.clear();
+}
+
+void* DevArena::alloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  ptrs_.push_back(p);
+  return p;
+}
+
+template <class T>
+T* DevArena::upload(const std::vector<T>& v, hipStream_t s) {
+  T* d = static_cast<T*>(alloc(std::max<size_t>(v.size(), 1) * sizeof(T)));
+  // blocking copy: callers pass short-lived host vectors (setup only, never in the sweep)
+  (void)s;
+  if (!v.empty()) hip_check(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+  return d;
+}
+template int* DevArena::upload<int>(const std::vector<int>&, hipStream_t);
+template double* DevArena::upload<double>(const std::vector<double>&, hipStream_t);
+
+double* Context::ensure_scratch(size_t doubles) {
+  if (doubles > scratch_doubles) {
+    if (scratch) (void)hipFree(scratch);
+    scratch = nullptr;
+    hip_check(hipMalloc(&scratch, doubles * sizeof(double)), "hipMalloc scratch");
+    scratch_doubles = doubles;
+  }
+  return scratch;
+}
+
+// ----------------------------------------------------------------------------- plans
+
+static MpoCore reversed_core(const MpoCore& c) {
+  MpoCore r;
+  r.Rl = c.Rr;
+  r.Rr = c.Rl;
+  r.n = c.n;
+  r.b = c.e;
+  r.e = c.b;
+  r.io = c.io;
+  r.ii = c.ii;
+  r.v = c.v;
+  return r;
+}
+
+static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t* t1_slots, size_t* t2_slots) {
+  Plan P;
+  P.Rl = c.Rl;
+  P.Rr = c.Rr;
+  P.n = c.n;
+  const int n = c.n;
+  // distinct (b, ii) pairs in sorted order
+  std::map<std::pair<int, int>, int> slot_of;
+  for (size_t t = 0; t < c.nnz(); ++t) slot_of[{c.b[t], c.ii[t]}] = 0;
+  const double nnz = (double)c.nnz();
+  const double typical_rank = 32.0;
+  const double cost_sparse = nnz * typical_rank + (double)slot_of.size() * typical_rank;
+  const double cost_dense = (double)c.Rl * n * ((double)n * c.Rr) + (double)n * c.Rr * typical_rank +
+                            (double)c.Rl * n * typical_rank;
+  P.dense = cost_dense < cost_sparse;
+  std::vector<int> sb, si;
+  if (P.dense) {
+    for (int b = 0; b < c.Rl; ++b)
+      for (int i = 0; i < n; ++i) {
+        sb.push_back(b);
+        si.push_back(i);
+      }
+  } else {
+    int k = 0;
+    for (auto& kv : slot_of) {
+      kv.second = k++;
+      sb.push_back(kv.first.first);
+      si.push_back(kv.first.second);
+    }
+  }
+  P.nslot = (int)sb.size();
+  std::vector<int> beg(P.nslot + 1);
+  for (int i = 0; i <= P.nslot; ++i) beg[i] = i;
+  P.slot_beg = arena.upload(beg, s);
+  P.slot_b = arena.upload(sb, s);
+  P.slot_i = arena.upload(si, s);
+  *t1_slots = std::max(*t1_slots, (size_t)P.nslot);
+
+  std::vector<std::vector<int>> ap_a(n), ap_b(n), en_a(c.Rr), en_b(c.Rr);
+  std::vector<std::vector<double>> ap_v(n), en_v(c.Rr);
+  if (P.dense) {
+    std::vector<double> A2((size_t)P.nslot * n * c.Rr, 0.0);
+    for (size_t t = 0; t < c.nnz(); ++t)
+      A2[((size_t)c.b[t] * n + c.ii[t]) * ((size_t)n * c.Rr) + (size_t)c.io[t] * c.Rr + c.e[t]] += c.v[t];
+    P.A2 = arena.upload(A2, s);
+    *t2_slots = std::max(*t2_slots, (size_t)n * c.Rr);
+    for (int io = 0; io < n; ++io)
+      for (int e = 0; e < c.Rr; ++e) {
+        ap_a[io].push_back(io * c.Rr + e);
+        ap_b[io].push_back(e);
+        ap_v[io].push_back(1.0);
+        en_a[e].push_back(io);
+        en_b[e].push_back(io * c.Rr + e);
+        en_v[e].push_back(1.0);
+      }
+  } else {
+    for (size_t t = 0; t < c.nnz(); ++t) {
+      const int slot = slot_of[{c.b[t], c.ii[t]}];
+      ap_a[c.io[t]].push_back(slot);
+      ap_b[c.io[t]].push_back(c.e[t]);
+      ap_v[c.io[t]].push_back(c.v[t]);
+      en_a[c.e[t]].push_back(c.io[t]);
+      en_b[c.e[t]].push_back(slot);
+      en_v[c.e[t]].push_back(c.v[t]);
+    }
+  }
+  auto flatten = [&](const std::vector<std::vector<int>>& A, const std::vector<std::vector<int>>& B,
+                     const std::vector<std::vector<double>>& V, int** dbeg, int** da, int** db, double** dv) {
+    std::vector<int> b0, fa, fb;
+    std::vector<double> fv;
+    b0.push_back(0);
+    for (size_t g = 0; g < A.size(); ++g) {
+      fa.insert(fa.end(), A[g].begin(), A[g].end());
+      fb.insert(fb.end(), B[g].begin(), B[g].end());
+      fv.insert(fv.end(), V[g].begin(), V[g].end());
+      b0.push_back((int)fa.size());
+    }
+    *dbeg = arena.upload(b0, s);
+    *da = arena.upload(fa, s);
+    *db = arena.upload(fb, s);
+    *dv = arena.upload(fv, s);
+    return (int)fa.size();
+  };
+  P.n_ap = flatten(ap_a, ap_b, ap_v, &P.ap_beg, &P.ap_a, &P.ap_b, &P.ap_v);
+  P.n_en = flatten(en_a, en_b, en_v, &P.en_beg, &P.en_a, &P.en_b, &P.en_v);
+  // diagonal terms
+  std::vector<std::vector<int>> db(n), de(n);
+  std::vector<std::vector<double>> dv(n);
+  for (size_t t = 0; t < c.nnz(); ++t)
+    if (c.io[t] == c.ii[t]) {
+      db[c.ii[t]].push_back(c.b[t]);
+      de[c.ii[t]].push_back(c.e[t]);
+      dv[c.ii[t]].push_back(c.v[t]);
+    }
+  flatten(db, de, dv, &P.dg_beg, &P.dg_b, &P.dg_e, &P.dg_v);
+  return P;
+}
+
+std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& desc) {
+  auto P = std::make_unique<Problem>();
+  P->ctx = ctx;
+  P->host = assemble(desc);
+  const auto& A = P->host.A;
+  const auto& b = P->host.b;
+  P->K = (int)A.size();
+  hipStream_t s = ctx->stream;
+  hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+  for (int k = 0; k < P->K; ++k) {
+    P->modes.push_back(A[k].n);
+    P->maxn = std::max(P->maxn, A[k].n);
+  }
+  for (int o = 0; o < 2; ++o) {
+    P->mrank[o].assign(P->K + 1, 1);
+    P->brank[o].assign(P->K + 1, 1);
+    for (int j = 0; j < P->K; ++j) {
+      const int k = o ? P->K - 1 - j : j;
+      MpoCore c = o ? reversed_core(A[k]) : A[k];
+      P->plans[o].push_back(build_plan(c, P->arena, s, &P->t1max_slots, &P->t2max_slots));
+      P->mrank[o][j] = c.Rl;
+      P->mrank[o][j + 1] = c.Rr;
+      P->Rmax = std::max(P->Rmax, std::max(c.Rl, c.Rr));
+      const TTCore& bc = b[k];
+      std::vector<double> data = bc.data;
+      int rl = bc.rl, rr = bc.rr;
+      if (o) {
+        for (int x = 0; x < bc.rl; ++x)
+          for (int i = 0; i < bc.n; ++i)
+            for (int y = 0; y < bc.rr; ++y) data[((size_t)y * bc.n + i) * bc.rl + x] = bc.data[((size_t)x * bc.n + i) * bc.rr + y];
+        std::swap(rl, rr);
+      }
+      P->bcore[o].push_back(P->arena.upload(data, s));
+      P->brank[o][j] = rl;
+      P->brank[o][j + 1] = rr;
+      P->smax = std::max(P->smax, std::max(rl, rr));
+    }
+  }
+  hip_check(hipStreamSynchronize(s), "upload sync");
+  return P;
+}
+
+// ----------------------------------------------------------------------------- contractions
+
+static void count(Flops* f, double m, double n, double k, double terms) {
+  if (f) f->total += 2.0 * m * n * k * terms;
+}
+
+static void stage12(Problem& P, const Plan& pl, int p, int q, int s, const double* L, const double* x, const int* skip,
+                    hipStream_t st, Flops* f, double* T1, double* T2, const double** src) {
+  GemmDesc g1;
+  g1.A = L;
+  g1.a_slot = q;
+  g1.a_sm = (long)pl.Rl * q;
+  g1.a_sk = 1;
+  g1.B = x;
+  g1.b_slot = s;
+  g1.b_sk = (long)pl.n * s;
+  g1.b_sn = 1;
+  g1.C = T1;
+  g1.c_slot = (long)p * s;
+  g1.c_sm = s;
+  g1.c_sn = 1;
+  g1.M = p;
+  g1.N = s;
+  g1.K = q;
+  g1.ngroups = pl.nslot;
+  g1.grp_beg = pl.slot_beg;
+  g1.t_a = pl.slot_b;
+  g1.t_b = pl.slot_i;
+  g1.skip = skip;
+  launch_gemm(g1, st);
+  count(f, p, s, q, pl.nslot);
+  *src = T1;
+  if (pl.dense) {
+    GemmDesc g2;
+    g2.A = pl.A2;
+    g2.a_sm = 1;
+    g2.a_sk = (long)pl.n * pl.Rr;
+    g2.B = T1;
+    g2.b_sk = (long)p * s;
+    g2.b_sn = 1;
+    g2.C = T2;
+    g2.c_sm = (long)p * s;
+    g2.c_sn = 1;
+    g2.M = pl.n * pl.Rr;
+    g2.N = p * s;
+    g2.K = pl.nslot;
+    g2.ngroups = 1;
+    g2.skip = skip;
+    launch_gemm(g2, st);
+    count(f, g2.M, g2.N, g2.K, 1);
+    *src = T2;
+  }
+  (void)P;
+}
+
+static void local_apply_ws(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* L, const double* x,
+                           const double* Rt, double* y, const int* skip, hipStream_t st, Flops* f, double* T1,
+                           double* T2) {
+  const double* src = nullptr;
+  stage12(P, pl, p, q, s, L, x, skip, st, f, T1, T2, &src);
+  GemmDesc g3;
+  g3.A = src;
+  g3.a_slot = (long)p * s;
+  g3.a_sm = s;
+  g3.a_sk = 1;
+  g3.B = Rt;
+  g3.b_slot = s;
+  g3.b_sk = 1;
+  g3.b_sn = (long)pl.Rr * s;
+  g3.C = y;
+  g3.c_slot = t;
+  g3.c_sm = (long)pl.n * t;
+  g3.c_sn = 1;
+  g3.M = p;
+  g3.N = t;
+  g3.K = s;
+  g3.ngroups = pl.n;
+  g3.grp_beg = pl.ap_beg;
+  g3.t_a = pl.ap_a;
+  g3.t_b = pl.ap_b;
+  g3.t_v = pl.ap_v;
+  g3.skip = skip;
+  launch_gemm(g3, st);
+  count(f, p, t, s, pl.n_ap);
+}
+
+static void env_update_ws(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* W, const double* L,
+                          const double* X, double* Lnew, hipStream_t st, Flops* f, double* T1, double* T2) {
+  const double* src = nullptr;
+  stage12(P, pl, p, q, s, L, X, nullptr, st, f, T1, T2, &src);
+  GemmDesc g3;
+  g3.A = W;
+  g3.a_slot = t;
+  g3.a_sm = 1;
+  g3.a_sk = (long)pl.n * t;
+  g3.B = src;
+  g3.b_slot = (long)p * s;
+  g3.b_sk = s;
+  g3.b_sn = 1;
+  g3.C = Lnew;
+  g3.c_slot = s;
+  g3.c_sm = (long)pl.Rr * s;
+  g3.c_sn = 1;
+  g3.M = t;
+  g3.N = s;
+  g3.K = p;
+  g3.ngroups = pl.Rr;
+  g3.grp_beg = pl.en_beg;
+  g3.t_a = pl.en_a;
+  g3.t_b = pl.en_b;
+  g3.t_v = pl.en_v;
+  launch_gemm(g3, st);
+  count(f, t, s, p, pl.n_en);
+}
+
+void dev_local_apply(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* L, const double* x,
+                     const double* Rt, double* y, const int* skip, hipStream_t st, Flops* f) {
+  const size_t n1 = (size_t)pl.n_t1() * p * s, n2 = (size_t)pl.n_t2() * p * s;
+  double* T1 = P.ctx->ensure_scratch(n1 + n2 + 1);
+  local_apply_ws(P, pl, p, q, s, t, L, x, Rt, y, skip, st, f, T1, T1 + n1);
+}
+
+void dev_env_update(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* W, const double* L,
+                    const double* X, double* Lnew, hipStream_t st, Flops* f) {
+  const size_t n1 = (size_t)pl.n_t1() * p * s, n2 = (size_t)pl.n_t2() * p * s;
+  double* T1 = P.ctx->ensure_scratch(n1 + n2 + 1);
+  env_update_ws(P, pl, p, q, s, t, W, L, X, Lnew, st, f, T1, T1 + n1);
+}
+
+// g[p][n][u] = sum Lb[p][sb] B[sb][n][sb'] Rb[u][sb']
+static void local_rhs(int p, int n, int sb, int sb2, int u, const double* Lb, const double* B, const double* Rb,
+                      double* Tb, double* g, hipStream_t st, Flops* f) {
+  GemmDesc a;
+  a.A = Lb;
+  a.a_sm = sb;
+  a.a_sk = 1;
+  a.B = B;
+  a.b_sk = (long)n * sb2;
+  a.b_sn = 1;
+  a.C = Tb;
+  a.c_sm = (long)n * sb2;
+  a.c_sn = 1;
+  a.M = p;
+  a.N = n * sb2;
+  a.K = sb;
+  launch_gemm(a, st);
+  count(f, p, n * sb2, sb, 1);
+  GemmDesc b;
+  b.A = Tb;
+  b.a_slot = sb2;
+  b.a_sm = (long)n * sb2;
+  b.a_sk = 1;
+  b.B = Rb;
+  b.b_slot = 0;
+  b.b_sk = 1;
+  b.b_sn = sb2;
+  b.C = g;
+  b.c_slot = u;
+  b.c_sm = (long)n * u;
+  b.c_sn = 1;
+  b.M = p;
+  b.N = u;
+  b.K = sb2;
+  b.ngroups = n;
+  launch_gemm(b, st);
+  count(f, p, u, sb2, n);
+}
+
+// Lnew[t][sb'] = sum W[p][j][t] Lb[p][sb] B[sb][j][sb']
+static void env_b(int p, int n, int sb, int sb2, int t, const double* W, const double* Lb, const double* B, double* Tb,
+                  double* Lnew, hipStream_t st, Flops* f) {
+  GemmDesc a;
+  a.A = Lb;
+  a.a_sm = sb;
+  a.a_sk = 1;
+  a.B = B;
+  a.b_sk = (long)n * sb2;
+  a.b_sn = 1;
+  a.C = Tb;
+  a.c_sm = (long)n * sb2;
+  a.c_sn = 1;
+  a.M = p;
+  a.N = n * sb2;
+  a.K = sb;
+  launch_gemm(a, st);
+  count(f, p, n * sb2, sb, 1);
+  GemmDesc b;
+  b.A = W;
+  b.a_sm = 1;
+  b.a_sk = t;
+  b.B = Tb;
+  b.b_sk = sb2;
+  b.b_sn = 1;
+  b.C = Lnew;
+  b.c_sm = sb2;
+  b.c_sn = 1;
+  b.M = t;
+  b.N = sb2;
+  b.K = p * n;
+  launch_gemm(b, st);
+  count(f, t, sb2, p * n, 1);
+}
+
+// C (m x n) = A (m x k) B (k x n), plain row-major (lda/ldb/ldc given); transA reads A^T stored k x m.
+static void gemm_plain(int m, int n, int k, const double* A, long lda, bool transA, const double* B, long ldb,
+                       double* C, long ldc, hipStream_t st, Flops* f) {
+  GemmDesc g;
+  g.A = A;
+  if (transA) {
+    g.a_sm = 1;
+    g.a_sk = lda;
+  } else {
+    g.a_sm = lda;
+    g.a_sk = 1;
+  }
+  g.B = B;
+  g.b_sk = ldb;
+  g.b_sn = 1;
+  g.C = C;
+  g.c_sm = ldc;
+  g.c_sn = 1;
+  g.M = m;
+  g.N = n;
+  g.K = k;
+  launch_gemm(g, st);
+  count(f, m, n, k, 1);
+}
+
+// ----------------------------------------------------------------------------- workspace
+
+void Problem::ensure_workspace(int cap, int rho) {
+  if (ws && ws->cap >= cap && ws->rho >= rho) return;
+  ws.reset();
+  auto W = std::make_unique<Workspace>();
+  W->cap = cap;
+  W->rho = rho;
+  const size_t rc = (size_t)std::max(cap, rho);
+  const size_t core = rc * maxn * rc;
+  const size_t zcore = (size_t)rho * maxn * rho;
+  const size_t M = rc * maxn, Nw = rc + rho;
+  auto A = [&](size_t doubles) { return static_cast<double*>(W->arena.alloc(std::max<size_t>(doubles, 1) * 8)); };
+  for (int k = 0; k < K; ++k) {
+    W->X.push_back(A(core));
+    W->Z.push_back(A(std::max(zcore, core)));
+  }
+  W->Xspare = A(core);
+  W->Zspare = A(std::max(zcore, core));
+  for (int k = 0; k <= K; ++k) {
+    W->EA.push_back(A(rc * Rmax * rc));
+    W->Eb.push_back(A(rc * smax));
+    W->EzA.push_back(A((size_t)rho * Rmax * rc));
+    W->Ezb.push_back(A((size_t)rho * smax));
+  }
+  W->T1 = A(t1max_slots * rc * rc);
+  W->T2 = A(t2max_slots * rc * rc);
+  W->g = A(core);
+  W->r = A(core);
+  W->z = A(core);
+  W->p = A(core);
+  W->q = A(core);
+  W->dinv = A(core);
+  W->Tb = A(rc * maxn * smax);
+  W->gz = A(core);
+  W->yz = A(core);
+  W->ge = A(core);
+  W->ye = A(core);
+  W->Qx = A(M * Nw);
+  W->Rx = A(Nw * Nw);
+  W->UR = A(Nw * Nw);
+  W->S = A(Nw);
+  W->V = A(Nw * Nw);
+  W->Ur = A(M * Nw);
+  W->SVt = A(Nw * Nw);
+  W->xt = A(M * Nw);
+  W->aug = A(M * Nw);
+  W->Qa = A(M * Nw);
+  W->Ra = A(Nw * Nw);
+  W->Wm = A(Nw * Nw);
+  W->qrws = A(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw);
+  W->scal = A(CG_NSCAL);
+  W->part = A(3 * 512);
+  W->flag = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
+  W->drank = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
+  hip_check(hipMemset(W->flag, 0, sizeof(int) * 8), "memset flag");
+  hip_check(hipHostMalloc(&W->host_pinned, 4096, hipHostMallocDefault), "hipHostMalloc");
+  ws = std::move(W);
+}
+
+// ----------------------------------------------------------------------------- SplitMix64
+
+static inline uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static std::vector<std::vector<double>> random_tt_host(const std::vector<int>& modes, int rank, uint64_t seed,
+                                                       std::vector<int>& ranks) {
+  const int K = (int)modes.size();
+  ranks.assign(K + 1, 1);
+  for (int k = 1; k < K; ++k) {
+    double left = 1, right = 1;
+    for (int j = 0; j < k; ++j) left *= modes[j];
+    for (int j = k; j < K; ++j) right *= modes[j];
+    ranks[k] = (int)std::min<double>(rank, std::min(left, right));
+  }
+  std::vector<std::vector<double>> cores(K);
+  uint64_t off = 0;
+  for (int k = 0; k < K; ++k) {
+    const size_t cnt = (size_t)ranks[k] * modes[k] * ranks[k + 1];
+    cores[k].resize(cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+      const uint64_t z = splitmix64_at(seed, off + i);
+      cores[k][i] = 2.0 * (double)(z >> 11) * (1.0 / 9007199254740992.0) - 1.0;
+    }
+    off += cnt;
+  }
+  return cores;
+}
+
+// ----------------------------------------------------------------------------- the sweep
+
+namespace {
+
+struct Sweep {
+  Problem& P;
+  Workspace& W;
+  tnfem_solve_opts o;
+  hipStream_t st;
+  int K;
+  int orient = 0;  // 0: forward chain, 1: reversed
+  std::vector<double*> X, Z, EA, Eb, EzA, Ezb;
+  std::vector<int> xr, zr;  // K + 1 ranks (current orientation)
+  std::vector<int> n;       // modes (current orientation)
+  Flops fl;
+  long long cg_iters = 0, applies = 0;
+  double max_res = 0.0;
+  int nan_seen = 0;
+
+  Sweep(Problem& p, const tnfem_solve_opts& opts) : P(p), W(*p.ws), o(opts), st(p.ctx->stream), K(p.K) {}
+
+  volatile int* hint() { return static_cast<volatile int*>(W.host_pinned); }
+
+  void sync() { hip_check(hipStreamSynchronize(st), "hipStreamSynchronize"); }
+
+  void upload_initial() {
+    std::vector<int> rx, rz;
+    auto cx = random_tt_host(P.modes, o.init_rank, o.seed_x, rx);
+    auto cz = random_tt_host(P.modes, o.rho, o.seed_z, rz);
+    X = W.X;
+    Z = W.Z;
+    EA = W.EA;
+    Eb = W.Eb;
+    EzA = W.EzA;
+    Ezb = W.Ezb;
+    xr = rx;
+    zr = rz;
+    n = P.modes;
+    for (int k = 0; k < K; ++k) {
+      hip_check(hipMemcpyAsync(X[k], cx[k].data(), cx[k].size() * 8, hipMemcpyHostToDevice, st), "upload X0");
+      hip_check(hipMemcpyAsync(Z[k], cz[k].data(), cz[k].size() * 8, hipMemcpyHostToDevice, st), "upload Z0");
+    }
+    const double one = 1.0;
+    for (double* b : {EA[0], Eb[0], EzA[0], Ezb[0], EA[K], Eb[K], EzA[K], Ezb[K]})
+      hip_check(hipMemcpyAsync(b, &one, 8, hipMemcpyHostToDevice, st), "boundary interface");
+    sync();  // `one` is on the host stack
+  }
+
+  void reverse() {
+    for (int k = 0; k < K; ++k) {
+      launch_core_transpose(xr[k], n[k], xr[k + 1], X[k], W.Xspare, st);
+      std::swap(X[k], W.Xspare);
+      launch_core_transpose(zr[k], n[k], zr[k + 1], Z[k], W.Zspare, st);
+      std::swap(Z[k], W.Zspare);
+    }
+    std::reverse(X.begin(), X.end());
+    std::reverse(Z.begin(), Z.end());
+    std::reverse(xr.begin(), xr.end());
+    std::reverse(zr.begin(), zr.end());
+    std::reverse(n.begin(), n.end());
+    std::reverse(EA.begin(), EA.end());
+    std::reverse(Eb.begin(), Eb.end());
+    std::reverse(EzA.begin(), EzA.end());
+    std::reverse(Ezb.begin(), Ezb.end());
+    orient ^= 1;
+  }
+
+  const Plan& plan(int k) const { return P.plans[orient][k]; }
+  int R(int j) const { return P.mrank[orient][j]; }
+  int sb(int j) const { return P.brank[orient][j]; }
+  const double* B(int k) const { return P.bcore[orient][k]; }
+
+  void apply(int k, int p, int q, int s, int t, const double* L, const double* x, const double* Rt, double* y,
+             const int* skip) {
+    const Plan& pl = plan(k);
+    local_apply_ws(P, pl, p, q, s, t, L, x, Rt, y, skip, st, &fl, W.T1, W.T2);
+  }
+
+  void update_envs(int k) {
+    const int p = xr[k], s = xr[k + 1], pz = zr[k], tz = zr[k + 1];
+    env_update_ws(P, plan(k), p, p, s, s, X[k], EA[k], X[k], EA[k + 1], st, &fl, W.T1, W.T2);
+    env_b(p, n[k], sb(k), sb(k + 1), s, X[k], Eb[k], B(k), W.Tb, Eb[k + 1], st, &fl);
+    env_update_ws(P, plan(k), pz, p, s, tz, Z[k], EzA[k], X[k], EzA[k + 1], st, &fl, W.T1, W.T2);
+    env_b(pz, n[k], sb(k), sb(k + 1), tz, Z[k], Ezb[k], B(k), W.Tb, Ezb[k + 1], st, &fl);
+  }
+
+  // Left-orthogonalise core k of T (ranks tr) by QR and carry R into core k+1.
+  void qr_step(std::vector<double*>& T, std::vector<int>& tr, int k, double* spare) {
+    const int m = tr[k] * n[k], nc = tr[k + 1];
+    const int c = std::min(m, nc);
+    launch_qr(m, nc, T[k], nc, W.Qa, c, W.Ra, nc, W.qrws, st);
+    launch_copy2d(m, c, W.Qa, c, T[k], c, 1.0, 0.0, st);
+    const int cols = n[k + 1] * tr[k + 2];
+    gemm_plain(c, cols, nc, W.Ra, nc, false, T[k + 1], cols, spare, cols, st, &fl);
+    launch_copy2d(c, cols, spare, cols, T[k + 1], cols, 1.0, 0.0, st);
+    tr[k + 1] = c;
+  }
+
+  void qr_pass() {
+    for (int k = 0; k < K - 1; ++k) {
+      qr_step(X, xr, k, W.Xspare);
+      qr_step(Z, zr, k, W.Zspare);
+      update_envs(k);
+    }
+  }
+
+  // Returns the local residual res_k before the solve.
+  double solve_core(int k) {
+    const int p = xr[k], t = xr[k + 1];
+    const int N = p * n[k] * t;
+    local_rhs(p, n[k], sb(k), sb(k + 1), t, Eb[k], B(k), Eb[k + 1], W.Tb, W.g, st, &fl);
+    const Plan& pl = plan(k);
+    launch_local_diag(p, n[k], t, R(k), R(k + 1), EA[k], EA[k + 1], pl.dg_beg, pl.dg_b, pl.dg_e, pl.dg_v, W.dinv,
+                      st);
+    apply(k, p, p, t, t, EA[k], X[k], EA[k + 1], W.q, nullptr);
+    applies++;
+    launch_cg_init(N, W.g, W.q, W.dinv, W.r, W.z, W.p, W.scal, W.flag, W.part, o.tol, o.cg_maxit, st);
+    auto readback = [&]() {
+      hip_check(hipMemcpyAsync(W.host_pinned, W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flag readback");
+      hip_check(hipMemcpyAsync(static_cast<char*>(W.host_pinned) + 64, W.scal + CG_RES, sizeof(double),
+                               hipMemcpyDeviceToHost, st),
+                "res readback");
+      sync();
+    };
+    readback();
+    const double res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+    if (!std::isfinite(res)) nan_seen = 1;
+    int done = hint()[0];
+    const int chunk = 8;
+    int launched = 0;
+    while (!done && launched < o.cg_maxit) {
+      for (int c = 0; c < chunk && launched < o.cg_maxit; ++c, ++launched) {
+        apply(k, p, p, t, t, EA[k], W.p, EA[k + 1], W.q, W.flag + CG_DONE);
+        launch_cg_dot(N, W.p, W.q, W.scal, W.flag, W.part, st);
+        launch_cg_update(N, X[k], W.p, W.q, W.r, W.z, W.dinv, W.scal, W.flag, W.part, st);
+        launch_cg_pupdate(N, W.p, W.z, W.scal, W.flag, st);
+      }
+      readback();
+      done = hint()[0];
+    }
+    const int its = hint()[1];
+    cg_iters += its;
+    applies += its;
+    return res;
+  }
+
+  void truncate_enrich(int k) {
+    const int p = xr[k], nk = n[k], t = xr[k + 1];
+    const int M = p * nk, Nn = t;
+    if (M < Nn) fail(TNFEM_EINVAL, "internal: bond %d rank %d exceeds %d", k + 1, Nn, M);
+    // SVD of the unfolding: QR, Jacobi on R, U = Q U_R
+    launch_qr(M, Nn, X[k], Nn, W.Qx, Nn, W.Rx, Nn, W.qrws, st);
+    launch_jacobi_svd(Nn, W.Rx, Nn, W.UR, W.S, W.V, W.qrws, st);
+    const double trtol = o.tol / std::sqrt((double)std::max(K - 1, 1));
+    launch_trunc_rank(Nn, W.S, trtol, o.rank_cap, W.drank, st);
+    hip_check(hipMemcpyAsync(W.host_pinned, W.drank, sizeof(int), hipMemcpyDeviceToHost, st), "rank readback");
+    sync();
+    const int rk = hint()[0];
+    // Ur = Qx UR[:, :rk];  xt = Ur diag(S) V^T
+    gemm_plain(M, rk, Nn, W.Qx, Nn, false, W.UR, Nn, W.Ur, rk, st, &fl);
+    launch_scale_vt(rk, Nn, W.S, W.V, Nn, W.SVt, st);
+    gemm_plain(M, Nn, rk, W.Ur, rk, false, W.SVt, Nn, W.xt, Nn, st, &fl);
+    // residual projected on the Z interfaces -> new Z_k
+    const int pz = zr[k], tz = zr[k + 1];
+    local_rhs(pz, nk, sb(k), sb(k + 1), tz, Ezb[k], B(k), Ezb[k + 1], W.Tb, W.gz, st, &fl);
+    apply(k, pz, p, t, tz, EzA[k], W.xt, EzA[k + 1], W.yz, nullptr);
+    launch_sub((long)pz * nk * tz, W.gz, W.yz, W.gz, st);
+    const int mz = pz * nk, cz = std::min(mz, tz);
+    launch_qr(mz, tz, W.gz, tz, Z[k], cz, W.Ra, tz, W.qrws, st);
+    // enrichment: residual on (left X, right Z) interfaces
+    local_rhs(p, nk, sb(k), sb(k + 1), tz, Eb[k], B(k), Ezb[k + 1], W.Tb, W.ge, st, &fl);
+    apply(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ye, nullptr);
+    launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
+    const int rho_eff = std::max(0, std::min(tz, std::min(o.rank_cap - rk, M - rk)));
+    const int rnew = rk + rho_eff;
+    launch_copy2d(M, rk, W.Ur, rk, W.aug, rnew, 1.0, 0.0, st);
+    if (rho_eff > 0) launch_copy2d(M, rho_eff, W.ge, tz, W.aug + rk, rnew, 1.0, 0.0, st);
+    launch_qr(M, rnew, W.aug, rnew, X[k], rnew, W.Ra, rnew, W.qrws, st);
+    // W = Q^T xt (rnew x Nn); X_{k+1} <- W X_{k+1}
+    gemm_plain(rnew, Nn, M, X[k], rnew, true, W.xt, Nn, W.Wm, Nn, st, &fl);
+    const int cols = n[k + 1] * xr[k + 2];
+    gemm_plain(rnew, cols, Nn, W.Wm, Nn, false, X[k + 1], cols, W.Xspare, cols, st, &fl);
+    std::swap(X[k + 1], W.Xspare);
+    xr[k + 1] = rnew;
+    zr[k + 1] = cz;
+    update_envs(k);
+  }
+
+  double half_sweep() {
+    double mr = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double res = solve_core(k);
+      mr = std::max(mr, res);
+      if (nan_seen) return NAN;
+      if (k < K - 1) truncate_enrich(k);
+    }
+    return mr;
+  }
+};
+
+}  // namespace
+
+int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_stats& stats) {
+  TNFEM_REQUIRE(o.rank_cap >= 1 && o.rank_cap <= 252, "rank_cap must be in [1, 252]");
+  TNFEM_REQUIRE(o.rho >= 0 && o.rho <= 64, "rho must be in [0, 64]");
+  TNFEM_REQUIRE(o.init_rank >= 1 && o.init_rank <= o.rank_cap, "init_rank must be in [1, rank_cap]");
+  TNFEM_REQUIRE(o.tol > 0 && std::isfinite(o.tol), "tol must be positive");
+  TNFEM_REQUIRE(o.max_sweeps >= 1, "max_sweeps must be >= 1");
+  TNFEM_REQUIRE(o.cg_maxit >= 0, "cg_maxit must be >= 0");
+  TNFEM_REQUIRE(o.precision == 0, "only precision 0 (FP64) is available");
+  hip_check(hipSetDevice(P.ctx->device), "hipSetDevice");
+  const int rho = std::max(o.rho, 1);
+  P.ensure_workspace(o.rank_cap, rho);
+  if ((size_t)P.ws->cap * P.maxn * (P.ws->cap + rho) * 8 > (size_t)1 << 34)
+    fail(TNFEM_EBUDGET, "workspace too large");
+  const auto t0 = std::chrono::steady_clock::now();
+  tnfem_solve_opts oo = o;
+  oo.rho = rho;
+  Sweep sw(P, oo);
+  sw.upload_initial();
+  sw.reverse();
+  sw.qr_pass();
+  sw.reverse();
+  int sweeps = 0;
+  double last = INFINITY;
+  int converged = 0;
+  for (; sweeps < o.max_sweeps;) {
+    last = sw.half_sweep();
+    ++sweeps;
+    if (sw.nan_seen || !std::isfinite(last)) break;
+    sw.reverse();
+    if (last <= o.tol) {
+      converged = 1;
+      break;
+    }
+  }
+  if (sw.orient) sw.reverse();
+  sw.sync();
+  // download
+  out.modes = sw.n;
+  out.ranks = sw.xr;
+  out.cores.assign(P.K, {});
+  for (int k = 0; k < P.K; ++k) {
+    out.cores[k].resize((size_t)sw.xr[k] * sw.n[k] * sw.xr[k + 1]);
+    hip_check(hipMemcpyAsync(out.cores[k].data(), sw.X[k], out.cores[k].size() * 8, hipMemcpyDeviceToHost, sw.st),
+              "download");
+  }
+  sw.sync();
+  const auto t1 = std::chrono::steady_clock::now();
+  stats.sweeps = sweeps;
+  stats.converged = converged;
+  stats.final_max_res = last;
+  stats.cg_iters = sw.cg_iters;
+  stats.local_applies = sw.applies;
+  stats.flops = sw.fl.total;
+  stats.seconds = std::chrono::duration<double>(t1 - t0).count();
+  stats.max_rank = *std::max_element(sw.xr.begin(), sw.xr.end());
+  stats.contraction_ms = 0.0;
+  if (sw.nan_seen || !std::isfinite(last)) return TNFEM_ENAN;
+  return converged ? TNFEM_OK : TNFEM_ENOTCONV;
+}
+
+}  // namespace tnfem

@@ -1,0 +1,121 @@
+// Device-resident AMEn engine: problem state, contraction plans, the sweep.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <vector>
+
+#include "assembly.hpp"
+#include "kernels.hpp"
+
+namespace tnfem {
+
+void hip_check(hipError_t e, const char* what);
+
+// Owner of device allocations made for one object; freed on destruction.
+class DevArena {
+ public:
+  ~DevArena();
+  void* alloc(size_t bytes);
+  template <class T>
+  T* upload(const std::vector<T>& v, hipStream_t s);
+  void release_all();
+
+ private:
+  std::vector<void*> ptrs_;
+};
+
+// Contraction plan of one operator core in one chain orientation.
+// Stage 1: T1[slot] = L[:, b_slot, :] x[:, i_slot, :] for every used (b, i).
+// Stage 2 (dense plans only): T2[(io, e)] = sum_slot A2[slot][(io, e)] T1[slot].
+// Stage 3: apply terms (grouped by io): y[:, io, :] += v T[a] Rt[:, e = b, :]^T;
+//          interface terms (grouped by e): Lnew[:, e, :] += v W[:, io = a, :]^T T[b].
+struct Plan {
+  int Rl = 1, Rr = 1, n = 1;
+  int nslot = 0;
+  bool dense = false;
+  int *slot_beg = nullptr, *slot_b = nullptr, *slot_i = nullptr;
+  double* A2 = nullptr;
+  int *ap_beg = nullptr, *ap_a = nullptr, *ap_b = nullptr;
+  double* ap_v = nullptr;
+  int n_ap = 0;
+  int *en_beg = nullptr, *en_a = nullptr, *en_b = nullptr;
+  double* en_v = nullptr;
+  int n_en = 0;
+  int *dg_beg = nullptr, *dg_b = nullptr, *dg_e = nullptr;
+  double* dg_v = nullptr;
+  int n_t1() const { return nslot; }
+  int n_t2() const { return dense ? n * Rr : 0; }
+};
+
+struct Context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevArena arena;
+  double* scratch = nullptr;  // for primitives
+  size_t scratch_doubles = 0;
+  double* ensure_scratch(size_t doubles);
+};
+
+struct Problem;
+
+// Workspace of one problem for a given rank cap.
+struct Workspace {
+  int cap = 0, rho = 0;
+  DevArena arena;
+  std::vector<double*> X, Z;  // K core buffers each (+1 spare for swaps)
+  double *Xspare = nullptr, *Zspare = nullptr;
+  std::vector<double*> EA, Eb, EzA, Ezb;  // K + 1 bond buffers
+  double *T1 = nullptr, *T2 = nullptr;
+  double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+  double *Tb = nullptr, *gz = nullptr, *yz = nullptr, *ge = nullptr, *ye = nullptr;
+  double *Qx = nullptr, *Rx = nullptr, *UR = nullptr, *S = nullptr, *V = nullptr, *Ur = nullptr, *SVt = nullptr,
+         *xt = nullptr, *aug = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;
+  double *scal = nullptr, *part = nullptr;
+  int* flag = nullptr;
+  int* drank = nullptr;
+  void* host_pinned = nullptr;
+  size_t bytes = 0;
+  ~Workspace() {
+    if (host_pinned) (void)hipHostFree(host_pinned);
+  }
+};
+
+struct Problem {
+  Context* ctx = nullptr;
+  Assembled host;
+  int K = 0;
+  std::vector<int> modes;
+  std::vector<Plan> plans[2];
+  std::vector<double*> bcore[2];
+  std::vector<int> brank[2];  // K + 1
+  std::vector<int> mrank[2];  // K + 1
+  int Rmax = 1, smax = 1, maxn = 1;
+  size_t t1max_slots = 1, t2max_slots = 1;
+  DevArena arena;
+  std::unique_ptr<Workspace> ws;
+  void ensure_workspace(int cap, int rho);
+};
+
+// Host TT object.
+struct HostTT {
+  std::vector<int> modes, ranks;
+  std::vector<std::vector<double>> cores;
+};
+
+std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& desc);
+
+// Contractions on the problem's plans (device pointers, asynchronous on s).
+struct Flops {
+  double total = 0;
+};
+void dev_local_apply(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* L, const double* x,
+                     const double* Rt, double* y, const int* skip, hipStream_t st, Flops* f);
+void dev_env_update(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* W, const double* L,
+                    const double* X, double* Lnew, hipStream_t st, Flops* f);
+
+int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_stats& st);
+
+}  // namespace tnfem

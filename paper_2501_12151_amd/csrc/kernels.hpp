@@ -1,0 +1,84 @@
+// Device kernels of the QTT sweep (gfx950) and their host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tnfem {
+
+// Grouped, strided, coefficient-weighted FP64 GEMM on MFMA:
+//   C_g[m][n] = beta * C_g[m][n] + alpha * sum_{t in group g} v_t sum_k A_t[m][k] B_t[k][n]
+//   A_t[m][k] = A[a_idx(t) * a_slot + m * a_sm + k * a_sk]
+//   B_t[k][n] = B[b_idx(t) * b_slot + k * b_sk + n * b_sn]
+//   C_g[m][n] = C[c_idx(g) * c_slot + m * c_sm + n * c_sn]
+// grp_beg == nullptr: batched mode, group g has one term with a_idx = b_idx = g.
+// grp_c == nullptr: c_idx(g) = g.  t_v == nullptr: v_t = 1.
+// skip != nullptr and *skip != 0 at launch time on the device: the kernel does nothing.
+struct GemmDesc {
+  const double* A = nullptr;
+  long a_slot = 0, a_sm = 0, a_sk = 0;
+  const double* B = nullptr;
+  long b_slot = 0, b_sk = 0, b_sn = 0;
+  double* C = nullptr;
+  long c_slot = 0, c_sm = 0, c_sn = 0;
+  int M = 0, N = 0, K = 0;
+  int ngroups = 1;
+  const int* grp_beg = nullptr;
+  const int* grp_c = nullptr;
+  const int* t_a = nullptr;
+  const int* t_b = nullptr;
+  const double* t_v = nullptr;
+  double alpha = 1.0, beta = 0.0;
+  const int* skip = nullptr;
+};
+
+void launch_gemm(const GemmDesc& g, hipStream_t s);
+
+// Device scalars of a local CG solve.
+enum CgScal { CG_RZ = 0, CG_PQ, CG_RR, CG_GG, CG_THR2, CG_RES, CG_BETA, CG_NSCAL };
+enum CgFlag { CG_DONE = 0, CG_ITERS, CG_MAXIT, CG_COUNTER, CG_NFLAG };
+
+// r = g - q; z = dinv * r; p = z; scalars rz, rr, gg; res = ||r|| / ||g||;
+// thr = max(0.1 res, tol/2) ||g||; done = (res <= tol/2) or maxit == 0.
+void launch_cg_init(int n, const double* g, const double* q, const double* dinv, double* r, double* z, double* p,
+                    double* scal, int* flag, double* part, double tol, int maxit, hipStream_t s);
+// pq = p . q (skipped once done)
+void launch_cg_dot(int n, const double* p, const double* q, double* scal, int* flag, double* part, hipStream_t s);
+// x += a p, r -= a q, z = dinv r, beta, convergence flag (skipped once done)
+void launch_cg_update(int n, double* x, const double* p, const double* q, double* r, double* z, const double* dinv,
+                      double* scal, int* flag, double* part, hipStream_t s);
+// p = z + beta p (skipped once done)
+void launch_cg_pupdate(int n, double* p, const double* z, const double* scal, const int* flag, hipStream_t s);
+
+// Jacobi preconditioner: d[a][i][c] = sum over diagonal terms (b, e, v) of group i of
+// v * L[a][b][a] * Rt[c][e][c]; dinv = 1/d where d > 0 else 1.
+void launch_local_diag(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* dg_beg,
+                       const int* dg_b, const int* dg_e, const double* dg_v, double* dinv, hipStream_t s);
+
+// Householder QR of A (m x n, row-major, lda), single workgroup: Q (m x c), R (c x n), c = min(m, n).
+// ws: workspace of m * n + m * c + 2 * c doubles.
+void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws, hipStream_t s);
+
+// One-sided Jacobi SVD of the square n x n matrix G (row-major, ldg): G = U diag(S) V^T,
+// S descending.  U, V: n x n row-major.  ws: 2 n^2 doubles (used when n > 64).
+void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s);
+
+// out[0] = smallest r with sum_{j>=r} S_j^2 <= tol^2 sum S^2, clipped to [1, cap].
+void launch_trunc_rank(int c, const double* S, double tol, int cap, int* out, hipStream_t s);
+
+// dst[i][j] = alpha * src[i][j] (+ beta * dst) for i < rows, j < cols.
+void launch_copy2d(int rows, int cols, const double* src, long sld, double* dst, long dld, double alpha, double beta,
+                   hipStream_t s);
+
+// W[i][j] = S[i] * V[j][i] for i < r, j < n (V: n x ldv row-major).  Builds diag(S) V^T.
+void launch_scale_vt(int r, int n, const double* S, const double* V, int ldv, double* W, hipStream_t s);
+
+// Core transpose for chain reversal: out[b][i][a] = in[a][i][b], in: [ra][n][rb].
+void launch_core_transpose(int ra, int n, int rb, const double* in, double* out, hipStream_t s);
+
+// out = a - b (n entries)
+void launch_sub(long n, const double* a, const double* b, double* out, hipStream_t s);
+
+// flag[k] = 1 if any of the n values is not finite (OR accumulated).
+void launch_nan_check(long n, const double* x, int* flag, hipStream_t s);
+
+}  // namespace tnfem

@@ -1,0 +1,304 @@
+"""Python binding of libtnfem (ctypes; argument marshalling only).
+
+Every computation happens in the HIP library behind include/tnfem.h.  If the
+library has not been built (``python -m paper_2501_12151_amd.build`` or
+``__graft_entry__.build()``) importing this module raises ImportError; there is
+no fallback path.
+
+Problem descriptions are plain dicts with the keys
+    dim, level, E, nu, plane_stress (opt), extent (opt),
+    clamp: [(axis, side), ...], tractions: [(axis, side, t), ...],
+    body_force (opt), manufactured_c (opt)
+so that the same dict can describe a workload to any consumer.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtnfem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libtnfem.so is not built at {LIB_PATH}; run paper_2501_12151_amd/build.py")
+
+_lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EBUDGET, ENOTCONV, EDEVICE, ENAN, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("level", C.c_int), ("extent", C.c_double * 3),
+        ("E", C.c_double), ("nu", C.c_double), ("plane_stress", C.c_int),
+        ("clamp_mask", C.c_uint32), ("n_tractions", C.c_int), ("traction_face", C.c_int * 6),
+        ("traction", (C.c_double * 3) * 6), ("has_body_force", C.c_int), ("body_force", C.c_double * 3),
+        ("has_manufactured", C.c_int), ("manufactured_c", C.c_double * 3),
+        ("layer_axis", C.c_int), ("n_layer_E", C.c_int), ("layer_E", C.POINTER(C.c_double)),
+    ]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [
+        ("rank_cap", C.c_int), ("tol", C.c_double), ("max_sweeps", C.c_int), ("rho", C.c_int),
+        ("init_rank", C.c_int), ("seed_x", C.c_uint64), ("seed_z", C.c_uint64), ("cg_maxit", C.c_int),
+        ("precision", C.c_int),
+    ]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [
+        ("sweeps", C.c_int), ("converged", C.c_int), ("final_max_res", C.c_double),
+        ("cg_iters", C.c_longlong), ("local_applies", C.c_longlong), ("flops", C.c_double),
+        ("seconds", C.c_double), ("max_rank", C.c_int), ("contraction_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = C.c_void_p
+_ip = C.POINTER(C.c_int)
+_dp = C.POINTER(C.c_double)
+_sig = {
+    "tnfem_last_error": (C.c_char_p, []),
+    "tnfem_default_opts": (None, [C.POINTER(SolveOpts)]),
+    "tnfem_ctx_create": (C.c_int, [C.POINTER(_vp), C.c_int, _vp]),
+    "tnfem_ctx_destroy": (C.c_int, [_vp]),
+    "tnfem_problem_create": (C.c_int, [_vp, C.POINTER(ProblemDesc), C.POINTER(_vp)]),
+    "tnfem_problem_destroy": (C.c_int, [_vp]),
+    "tnfem_problem_info": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
+    "tnfem_solve": (C.c_int, [_vp, C.POINTER(SolveOpts), C.POINTER(_vp), C.POINTER(SolveStats)]),
+    "tnfem_tt_create": (C.c_int, [C.c_int, _ip, _ip, _dp, C.POINTER(_vp)]),
+    "tnfem_tt_shape": (C.c_int, [_vp, _ip, _ip, _ip]),
+    "tnfem_tt_size": (C.c_size_t, [_vp]),
+    "tnfem_tt_copy_cores": (C.c_int, [_vp, _dp, C.c_size_t]),
+    "tnfem_tt_eval": (C.c_int, [_vp, C.POINTER(C.c_int64), C.c_size_t, _dp]),
+    "tnfem_tt_destroy": (C.c_int, [_vp]),
+    "tnfem_export_operator": (C.c_int, [C.POINTER(ProblemDesc), _ip, _ip, _ip, _dp, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "tnfem_export_load": (C.c_int, [C.POINTER(ProblemDesc), _ip, _ip, _ip, _dp, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "tnfem_prim_local_apply": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "tnfem_prim_env_update": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "tnfem_prim_qr": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
+    "tnfem_prim_svd": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class TnfemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tnfem error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise TnfemError(rc, _lib.tnfem_last_error().decode())
+    return rc
+
+
+def make_desc(problem: dict) -> ProblemDesc:
+    d = ProblemDesc()
+    D = int(problem["dim"])
+    d.dim = D
+    d.level = int(problem["level"])
+    ext = problem.get("extent") or [1.0, 1.0, 1.0]
+    for a in range(3):
+        d.extent[a] = float(ext[a]) if a < len(ext) else 1.0
+    d.E = float(problem["E"])
+    d.nu = float(problem["nu"])
+    d.plane_stress = int(bool(problem.get("plane_stress", False)))
+    mask = 0
+    for axis, side in problem.get("clamp", []):
+        mask |= 1 << (2 * int(axis) + int(side))
+    d.clamp_mask = mask
+    trs = problem.get("tractions", [])
+    d.n_tractions = len(trs)
+    for q, (axis, side, t) in enumerate(trs):
+        d.traction_face[q] = 2 * int(axis) + int(side)
+        for a in range(min(3, len(t))):
+            d.traction[q][a] = float(t[a])
+    if problem.get("body_force") is not None:
+        d.has_body_force = 1
+        for a, v in enumerate(problem["body_force"][:3]):
+            d.body_force[a] = float(v)
+    if problem.get("manufactured_c") is not None:
+        d.has_manufactured = 1
+        for a, v in enumerate(problem["manufactured_c"][:3]):
+            d.manufactured_c[a] = float(v)
+    if problem.get("layered_E") is not None:
+        axis, vals = problem["layered_E"]
+        arr = np.ascontiguousarray(vals, dtype=np.float64)
+        d._layer_keep = arr
+        d.layer_axis = int(axis)
+        d.n_layer_E = arr.size
+        d.layer_E = arr.ctypes.data_as(_dp)
+    return d
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    _lib.tnfem_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _export(fn, problem):
+    desc = make_desc(problem)
+    nc = C.c_int()
+    modes = (C.c_int * 64)()
+    ranks = (C.c_int * 65)()
+    need = C.c_size_t()
+    _check(fn(C.byref(desc), C.byref(nc), modes, ranks, None, 0, C.byref(need)))
+    buf = np.zeros(need.value, dtype=np.float64)
+    _check(fn(C.byref(desc), C.byref(nc), modes, ranks, buf.ctypes.data_as(_dp), buf.size, C.byref(need)))
+    return nc.value, list(modes[: nc.value]), list(ranks[: nc.value + 1]), buf
+
+
+def export_operator(problem: dict):
+    """Dense copies of the library's operator cores, [R_k, n, n, R_k+1] each (host only)."""
+    K, modes, ranks, buf = _export(_lib.tnfem_export_operator, problem)
+    cores, off = [], 0
+    for k in range(K):
+        cnt = ranks[k] * modes[k] * modes[k] * ranks[k + 1]
+        cores.append(buf[off:off + cnt].reshape(ranks[k], modes[k], modes[k], ranks[k + 1]))
+        off += cnt
+    return cores
+
+
+def export_load(problem: dict):
+    """The library's load TT cores, [r_k, n, r_k+1] each (host only)."""
+    K, modes, ranks, buf = _export(_lib.tnfem_export_load, problem)
+    cores, off = [], 0
+    for k in range(K):
+        cnt = ranks[k] * modes[k] * ranks[k + 1]
+        cores.append(buf[off:off + cnt].reshape(ranks[k], modes[k], ranks[k + 1]))
+        off += cnt
+    return cores
+
+
+class TT:
+    """Library-owned TT (host memory); .cores gives numpy copies."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.tnfem_tt_destroy(self._h)
+            self._h = None
+
+    def shape(self):
+        nc = C.c_int()
+        modes = (C.c_int * 64)()
+        ranks = (C.c_int * 65)()
+        _check(_lib.tnfem_tt_shape(self._h, C.byref(nc), modes, ranks))
+        return list(modes[: nc.value]), list(ranks[: nc.value + 1])
+
+    @property
+    def cores(self):
+        modes, ranks = self.shape()
+        buf = np.zeros(_lib.tnfem_tt_size(self._h), dtype=np.float64)
+        _check(_lib.tnfem_tt_copy_cores(self._h, buf.ctypes.data_as(_dp), buf.size))
+        out, off = [], 0
+        for k, n in enumerate(modes):
+            cnt = ranks[k] * n * ranks[k + 1]
+            out.append(buf[off:off + cnt].reshape(ranks[k], n, ranks[k + 1]).copy())
+            off += cnt
+        return out
+
+    def eval(self, idx):
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.zeros(idx.shape[0])
+        _check(_lib.tnfem_tt_eval(self._h, idx.ctypes.data_as(C.POINTER(C.c_int64)), idx.shape[0],
+                                  out.ctypes.data_as(_dp)))
+        return out
+
+
+class Context:
+    """A device context; stream may be a torch.cuda.Stream or a raw hipStream_t int."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = _vp()
+        s = None
+        if stream is not None:
+            s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(_lib.tnfem_ctx_create(C.byref(h), int(device), s))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tnfem_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def qr(self, m, n, A, Q, R, stream=None):
+        """Device QR on raw pointers (ints) or torch tensors."""
+        _check(_lib.tnfem_prim_qr(self._h, m, n, _ptr(A), _ptr(Q), _ptr(R), _ptr(stream)))
+
+    def svd(self, m, n, A, U, S, Vt, stream=None):
+        _check(_lib.tnfem_prim_svd(self._h, m, n, _ptr(A), _ptr(U), _ptr(S), _ptr(Vt), _ptr(stream)))
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if hasattr(x, "cuda_stream"):
+        return x.cuda_stream
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return int(x)
+
+
+class Problem:
+    def __init__(self, ctx: Context, problem: dict):
+        self.ctx = ctx
+        self.desc = make_desc(problem)
+        h = _vp()
+        _check(_lib.tnfem_problem_create(ctx._h, C.byref(self.desc), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tnfem_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self):
+        nc = C.c_int()
+        modes = (C.c_int * 64)()
+        mr = (C.c_int * 65)()
+        br = (C.c_int * 65)()
+        _check(_lib.tnfem_problem_info(self._h, C.byref(nc), modes, mr, br))
+        K = nc.value
+        return dict(ncores=K, modes=list(modes[:K]), mpo_ranks=list(mr[:K + 1]), rhs_ranks=list(br[:K + 1]))
+
+    def solve(self, **opts):
+        """Blocking solve.  Returns (TT, stats dict, status code)."""
+        o = default_opts(**opts)
+        h = _vp()
+        st = SolveStats()
+        rc = _check(_lib.tnfem_solve(self._h, C.byref(o), C.byref(h), C.byref(st)), allow=(ENOTCONV,))
+        return TT(h), st.as_dict(), rc
+
+    def local_apply(self, k, reversed_, p, q, s, t, L, x, Rt, y, stream=None):
+        _check(_lib.tnfem_prim_local_apply(self._h, k, int(reversed_), p, q, s, t, _ptr(L), _ptr(x), _ptr(Rt),
+                                           _ptr(y), _ptr(stream)))
+
+    def env_update(self, k, reversed_, p, q, s, t, W, L, X, Lnew, stream=None):
+        _check(_lib.tnfem_prim_env_update(self._h, k, int(reversed_), p, q, s, t, _ptr(W), _ptr(L), _ptr(X),
+                                          _ptr(Lnew), _ptr(stream)))

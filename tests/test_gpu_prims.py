@@ -1,0 +1,125 @@
+"""GPU parity of the sweep's building blocks against the oracle / LAPACK."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import amen as oamen  # noqa: E402
+from paper_2501_12151_amd import tnfem, workloads  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tnfem.Context(0, stream=torch.cuda.current_stream())
+    yield c
+    c.close()
+
+
+QR_SHAPES = [(1, 1), (8, 8), (64, 16), (256, 36), (1024, 132), (37, 5), (5, 37), (300, 256)]
+
+
+@pytest.mark.parametrize("m,n", QR_SHAPES)
+def test_qr_matches_definition(ctx, m, n):
+    print(f"qr m={m} n={n}", flush=True)
+    rng = np.random.default_rng(m * 1000 + n)
+    A = rng.standard_normal((m, n))
+    c = min(m, n)
+    dA, dQ, dR = dev(A), torch.zeros((m, c), dtype=torch.float64, device="cuda"), torch.zeros((c, n), dtype=torch.float64, device="cuda")
+    ctx.qr(m, n, dA, dQ, dR, stream=torch.cuda.current_stream())
+    Q, R = host(dQ), host(dR)
+    assert np.linalg.norm(Q @ R - A) <= 1e-13 * np.linalg.norm(A) * max(1, np.sqrt(n))
+    assert np.abs(Q.T @ Q - np.eye(c)).max() <= 1e-13 * max(m, 1)
+    assert np.all(np.tril(R, -1) == 0)
+    Rl = np.linalg.qr(A)[1]
+    assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rl)), rtol=1e-10, atol=1e-12)
+
+
+SVD_CASES = [(1, 1, "rand"), (16, 8, "rand"), (256, 32, "rand"), (512, 68, "rand"), (40, 40, "graded"),
+             (128, 64, "lowrank"), (1024, 132, "rand"), (7, 30, "rand"), (64, 64, "zero")]
+
+
+@pytest.mark.parametrize("m,n,kind", SVD_CASES)
+def test_svd_matches_lapack(ctx, m, n, kind):
+    print(f"svd m={m} n={n} {kind}", flush=True)
+    rng = np.random.default_rng(7 + m + n)
+    if kind == "rand":
+        A = rng.standard_normal((m, n))
+    elif kind == "graded":
+        U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+        V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        A = (U * np.logspace(0, -12, n)) @ V.T
+    elif kind == "lowrank":
+        A = rng.standard_normal((m, 5)) @ rng.standard_normal((5, n))
+    else:
+        A = np.zeros((m, n))
+    c = min(m, n)
+    dU = torch.zeros((m, c), dtype=torch.float64, device="cuda")
+    dS = torch.zeros(c, dtype=torch.float64, device="cuda")
+    dV = torch.zeros((c, n), dtype=torch.float64, device="cuda")
+    ctx.svd(m, n, dev(A), dU, dS, dV, stream=torch.cuda.current_stream())
+    U, S, Vt = host(dU), host(dS), host(dV)
+    Sl = np.linalg.svd(A, compute_uv=False)
+    scale = max(Sl[0], 1e-300)
+    assert np.all(np.diff(S) <= 1e-14 * scale)  # descending
+    assert np.abs(S - Sl).max() <= 1e-13 * scale * max(1, np.sqrt(n))
+    if kind != "zero":
+        assert np.linalg.norm((U * S) @ Vt - A) <= 1e-13 * np.linalg.norm(A) * max(1, np.sqrt(n))
+        keep = S > 1e-10 * scale
+        assert np.abs(U[:, keep].T @ U[:, keep] - np.eye(keep.sum())).max() <= 1e-11
+    assert np.abs(Vt @ Vt.T - np.eye(c)).max() <= 1e-11
+
+
+def _core(Ac, k, rev):
+    K = len(Ac)
+    return Ac[K - 1 - k].transpose(3, 1, 2, 0) if rev else Ac[k]
+
+
+PROBS = {"2d": workloads.small_2d(), "3d": workloads.cube_body_force(4)}
+
+
+@pytest.fixture(scope="module")
+def problems(ctx):
+    out = {}
+    for name, prob in PROBS.items():
+        out[name] = (tnfem.Problem(ctx, prob), tnfem.export_operator(prob))
+    yield out
+    for P, _ in out.values():
+        P.close()
+
+
+APPLY_CASES = [(name, k, rev, ranks) for name, K in (("2d", 6), ("3d", 5)) for k in range(K) for rev in (0, 1)
+               for ranks in ((4, 4, 4, 4), (5, 7, 33, 17))]
+
+
+@pytest.mark.parametrize("name,k,rev,ranks", APPLY_CASES)
+def test_local_apply_and_interface_update_match_oracle(problems, name, k, rev, ranks):
+    print(f"apply {name} k={k} rev={rev} ranks={ranks}", flush=True)
+    P, Ac = problems[name]
+    A = _core(Ac, k, rev)
+    Rl, n, _, Rr = A.shape
+    p, q, s, t = ranks
+    rng = np.random.default_rng(hash((name, k, rev, ranks)) % 2 ** 32)
+    L = rng.standard_normal((p, Rl, q))
+    x = rng.standard_normal((q, n, s))
+    Rt = rng.standard_normal((t, Rr, s))
+    y = torch.zeros((p, n, t), dtype=torch.float64, device="cuda")
+    P.local_apply(k, rev, p, q, s, t, dev(L), dev(x), dev(Rt), y, stream=torch.cuda.current_stream())
+    ref = oamen.local_apply(L, A, x, Rt)
+    got = host(y)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref) + 1e-300
+    W = rng.standard_normal((p, n, t))
+    Ln = torch.zeros((t, Rr, s), dtype=torch.float64, device="cuda")
+    P.env_update(k, rev, p, q, s, t, dev(W), dev(L), dev(x), Ln, stream=torch.cuda.current_stream())
+    ref2 = oamen.env_A(L, W, A, x)
+    assert np.linalg.norm(host(Ln) - ref2) <= 1e-13 * np.linalg.norm(ref2)

@@ -1,0 +1,67 @@
+"""GPU AMEn solves against the oracle sweep and the sparse direct solve."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import amen as oamen, fem, qtt, tt  # noqa: E402
+from paper_2501_12151_amd import tnfem, workloads  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tnfem.Context(0)
+    yield c
+    c.close()
+
+
+SMALL = [
+    dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])]),
+    dict(dim=2, level=4, E=3.0, nu=0.2, clamp=[(0, 0)], body_force=[0.0, -1.0]),
+    dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, 0.0, -1.0]),
+    dict(dim=3, level=3, E=1.0, nu=0.45, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])]),
+    dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(a, s) for a in range(3) for s in (0, 1)], manufactured_c=[0.3, -1.0, 0.5]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SMALL)))
+def test_unconstrained_solve_equals_direct_and_oracle(ctx, case):
+    prob = SMALL[case]
+    print(f"solve small case {case}: {prob}", flush=True)
+    A, b, grid, _ = fem.build_system(prob)
+    u = qtt.to_qtt_order(fem.direct_solve(A, b), prob["dim"], prob["level"])
+    P = tnfem.Problem(ctx, prob)
+    opts = dict(rank_cap=256, tol=1e-10, max_sweeps=30)
+    U, st, rc = P.solve(**opts)
+    assert rc == tnfem.OK, st
+    ug = tt.tt_full(U.cores)
+    assert np.linalg.norm(ug - u) <= 1e-8 * np.linalg.norm(u)
+    X, ost = oamen.amen_solve(qtt.assemble_operator(prob), qtt.assemble_load(prob),
+                              oamen.Options(tol=1e-10, rank_cap=256, max_sweeps=30))
+    assert np.linalg.norm(ug - tt.tt_full(X)) <= 1e-8 * np.linalg.norm(u)
+    assert st["sweeps"] == ost.sweeps
+
+
+def test_small_2d_capped_matches_oracle(ctx):
+    """The 32 x 32 workload with rank cap 16: GPU sweep and oracle sweep agree."""
+    prob = workloads.small_2d()
+    P = tnfem.Problem(ctx, prob)
+    U, st, rc = P.solve(rank_cap=16, tol=1e-8, max_sweeps=20)
+    X, ost = oamen.amen_solve(qtt.assemble_operator(prob), qtt.assemble_load(prob),
+                              oamen.Options(tol=1e-8, rank_cap=16, max_sweeps=20))
+    ug, uo = tt.tt_full(U.cores), tt.tt_full(X)
+    rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    print(f"capped 2D: gpu sweeps={st['sweeps']} cg={st['cg_iters']} oracle cg={ost.cg_iters} rel.diff={rel:.2e}")
+    assert rel <= 1e-6
+    assert st["max_rank"] <= 16
+
+
+def test_solve_is_deterministic(ctx):
+    prob = SMALL[3]
+    P = tnfem.Problem(ctx, prob)
+    a = P.solve(rank_cap=32, tol=1e-9)[0].cores
+    b = P.solve(rank_cap=32, tol=1e-9)[0].cores
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

@@ -1,0 +1,111 @@
+"""Host-side checks of the C-ABI library (no GPU): exports, assembly parity, errors."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fem, qtt, tt
+from paper_2501_12151_amd import tnfem, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "tnfem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tnfem_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(tnfem.LIB_PATH)
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert set(names) == set(tnfem.EXPORTED)
+
+
+CASES = [
+    dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])]),
+    dict(dim=2, level=4, E=68.0, nu=0.33, plane_stress=True, clamp=[(0, 0)], body_force=[0.0, -1.0], extent=[20.0, 1.0]),
+    dict(dim=2, level=4, E=2.0, nu=0.25, clamp=[(0, 0), (0, 1), (1, 0), (1, 1)], manufactured_c=[0.7, -0.4]),
+    dict(dim=2, level=2, E=1.0, nu=0.2, clamp=[], tractions=[(1, 0, [0.5, 1.0]), (1, 1, [0.5, -1.0])]),
+    dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, 0.0, -1.0]),
+    dict(dim=3, level=3, E=0.5, nu=0.4, clamp=[(2, 0), (0, 1)], tractions=[(2, 1, [0, 0, -1.0]), (0, 1, [0.3, 0.2, 0.1])],
+         body_force=[0.1, 0.2, 0.3], extent=[2.0, 1.0, 0.5]),
+    dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(a, s) for a in range(3) for s in (0, 1)], manufactured_c=[0.5, 1.0, -0.3]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_library_assembly_equals_sparse_fem(case):
+    """The library's QTT operator and load, reconstructed densely, equal the sparse assembly."""
+    prob = CASES[case]
+    A, b, grid, info = fem.build_system(prob)
+    D, d = prob["dim"], prob["level"]
+    Ac = tnfem.export_operator(prob)
+    bc = tnfem.export_load(prob)
+    Ap = qtt.matrix_to_qtt_order(A, D, d).toarray()
+    assert np.abs(tt.mpo_full(Ac) - Ap).max() <= 1e-13 * np.abs(Ap).max()
+    bp = qtt.to_qtt_order(b, D, d)
+    assert np.abs(tt.tt_full(bc) - bp).max() <= 1e-13 * np.abs(bp).max()
+    # exact automaton ranks: 5^D joint carry states in the middle
+    assert max(C.shape[3] for C in Ac) <= 5 ** D
+
+
+@pytest.mark.parametrize("prob", [dict(workloads.small_2d(), level=8), workloads.cube_body_force(4)])
+def test_library_operator_matches_oracle_tt_at_larger_levels(prob):
+    """Beyond dense sizes: bilinear forms w^T A x agree for random TT vectors w, x."""
+    Ao = qtt.assemble_operator(prob)
+    Al = tnfem.export_operator(prob)
+    modes = [C.shape[1] for C in Ao]
+    rng = np.random.default_rng(0)
+    for trial in range(4):
+        x = [rng.standard_normal((1 if k == 0 else 2, n, 1 if k == len(modes) - 1 else 2)) for k, n in enumerate(modes)]
+        w = [rng.standard_normal((1 if k == 0 else 2, n, 1 if k == len(modes) - 1 else 2)) for k, n in enumerate(modes)]
+        vo = tt.tt_dot(w, tt.mpo_matvec(Ao, x))
+        vl = tt.tt_dot(w, tt.mpo_matvec(Al, x))
+        scale = np.sqrt(abs(tt.tt_dot(tt.mpo_matvec(Ao, x), tt.mpo_matvec(Ao, x)))) * tt.tt_norm(w)
+        assert abs(vo - vl) <= 1e-12 * scale
+    bo = qtt.assemble_load(prob)
+    bl = tnfem.export_load(prob)
+    assert tt.tt_rel_diff(bl, bo) <= 1e-12
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(dim=4), "dim"),
+    (dict(nu=0.5), "nu"),
+    (dict(level=1), "level"),
+    (dict(E=-1.0), "E"),
+    (dict(extent=[1.0, 0.0]), "extent"),
+])
+def test_invalid_descriptor_rejected(bad, msg):
+    prob = dict(workloads.small_2d(), **bad)
+    with pytest.raises(tnfem.TnfemError) as e:
+        tnfem.export_operator(prob)
+    assert e.value.code == tnfem.EINVAL
+    assert msg in str(e.value)
+
+
+def test_layered_material_reported_unsupported():
+    with pytest.raises(tnfem.TnfemError) as e:
+        tnfem.export_operator(workloads.layered_cube(3))
+    assert e.value.code == tnfem.EINVAL
+
+
+def test_no_device_is_a_clean_error():
+    import torch
+
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present")
+    with pytest.raises(tnfem.TnfemError) as e:
+        tnfem.Context(0)
+    assert e.value.code == tnfem.EDEVICE
+
+
+def test_default_options():
+    o = tnfem.default_opts()
+    assert (o.rank_cap, o.rho, o.init_rank, o.seed_x, o.seed_z, o.precision) == (32, 4, 2, 1, 2, 0)
+    assert o.tol == 1e-8
