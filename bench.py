@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the QTT AMEn elasticity solve on one MI355X.
+
+One step = one complete solve (initial orthogonalisation, half-sweeps of local
+CG solves, SVD truncation, residual enrichment, QR, interface updates) of the
+3D unit-cube workload: 128^3 nodes (QTT level 7, 6.3 M dofs), E = 1, nu = 0.3,
+face x = 0 clamped, uniform body force (0, 0, -1), FP64, TT rank cap 32.  The
+operator and load are assembled and resident on the device before timing.
+
+Prints one JSON line (see the repository documentation for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "solves/s + p50/p99 latency at 1e-6 rel. error; contraction TFLOP/s vs peak"
+PEAK_FP64_MFMA_TFLOPS = 78.6
+
+WORKLOADS = {
+    # name: (problem factory args, solve options, description)
+    "cube128": dict(level=7, opts=dict(rank_cap=32, tol=1e-6, max_sweeps=8),
+                    desc="3D unit cube 128^3 nodes (QTT level 7), body force (0,0,-1), x=0 clamped, E=1, nu=0.3, "
+                         "FP64, rank cap 32"),
+    "square32": dict(level=5, opts=dict(rank_cap=16, tol=1e-8, max_sweeps=20),
+                     desc="2D plane strain 32x32 nodes (QTT level 5), x-traction 1 on x=1, x=0 clamped, E=1, nu=0.3, "
+                          "FP64, rank cap 16"),
+}
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def problem_for(name):
+    from paper_2501_12151_amd import workloads
+
+    if name == "cube128":
+        return workloads.cube_body_force(WORKLOADS[name]["level"])
+    return workloads.small_2d()
+
+
+def cpu_baseline(name, gpu_sweeps):
+    """The oracle sweep timed on the host: one half-sweep, scaled by the GPU's sweep count."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import amen, qtt
+
+    prob = problem_for(name)
+    o = WORKLOADS[name]["opts"]
+    A = qtt.assemble_operator(prob)
+    b = qtt.assemble_load(prob)
+    opt = amen.Options(tol=o["tol"], rank_cap=o["rank_cap"], max_sweeps=1)
+    t0 = time.perf_counter()
+    _, st = amen.amen_solve(A, b, opt)
+    t1 = time.perf_counter()
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    per_solve = (t1 - t0) * max(gpu_sweeps, 1)
+    del np
+    return {
+        "value": 1.0 / per_solve,
+        "unit": "solves/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"initial orthogonalisation + 1 of {gpu_sweeps} half-sweeps of the same solve "
+                  f"({t1 - t0:.1f} s, {st.cg_iters} local CG iterations), time scaled by {gpu_sweeps}",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is not sharded across GPUs.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2501_12151_amd import tnfem
+
+    wl = WORKLOADS[args.workload]
+    prob = problem_for(args.workload)
+    opts = dict(wl["opts"])
+    ctx = tnfem.Context(0)
+    P = tnfem.Problem(ctx, prob)
+    info = P.info()
+    for i in range(args.warmup):
+        _, st, rc = P.solve(**opts)
+        print(f"warmup {i}: {st['seconds']:.3f} s sweeps={st['sweeps']} res={st['final_max_res']:.2e}",
+              file=sys.stderr, flush=True)
+    lat, stats = [], []
+    t_begin = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        u, st, rc = P.solve(**opts)
+        lat.append(time.perf_counter() - t0)
+        stats.append(st)
+        print(f"step {i}: {lat[-1]:.3f} s sweeps={st['sweeps']} cg={st['cg_iters']} res={st['final_max_res']:.2e}",
+              file=sys.stderr, flush=True)
+    total = time.perf_counter() - t_begin
+    st = stats[-1]
+    roof = None
+    if not args.no_profile:
+        _, pst, _ = P.solve(profile=1, **opts)
+        ms, fl, nl = pst["contraction_ms"], pst["contraction_flops"], pst["contraction_launches"]
+        achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        roof = {
+            "bound": "mfma",
+            "kernel": "gemm_grouped_kernel (all contraction launches of one solve)",
+            "achieved": achieved,
+            "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+            "traffic": None,
+            "launches": nl,
+            "avg_launch_us": 1e3 * ms / max(nl, 1),
+            "flops_per_launch": fl / max(nl, 1),
+            "contraction_ms_per_solve": ms,
+        }
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, st["sweeps"])
+    value = args.steps / total
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl["desc"],
+            "dofs": prob["dim"] * 2 ** (prob["dim"] * prob["level"]),
+            "mpo_ranks": info["mpo_ranks"],
+            "rank_cap": opts["rank_cap"],
+            "tol": opts["tol"],
+            "max_sweeps": opts["max_sweeps"],
+        },
+        "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
+        "solve": {
+            "sweeps": st["sweeps"], "converged": bool(st["converged"]), "final_max_local_residual": st["final_max_res"],
+            "cg_iters": st["cg_iters"], "max_rank": st["max_rank"], "counted_flops": st["flops"],
+            "median_latency_s": statistics.median(lat),
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -107,10 +107,12 @@ typedef struct {
   uint64_t seed_z;   /* SplitMix64 seed of the residual-projection TT */
   int cg_maxit;      /* iteration limit of each local conjugate-gradient solve */
   int precision;
+  int profile;       /* 1: time every contraction launch with HIP events (adds host work) */
 } tnfem_solve_opts;
 
 /* Fills opts with the defaults: cap 32, tol 1e-8, 30 sweeps, rho 4, init rank 2,
- * seeds 1 and 2, 500 CG iterations, FP64. */
+ * seeds 1 and 2, 500 CG iterations, FP64, no profiling.  Setting the environment
+ * variable TNFEM_VERBOSE=1 prints one line per half-sweep to stderr. */
 void tnfem_default_opts(tnfem_solve_opts* opts);
 
 typedef struct {
@@ -122,7 +124,9 @@ typedef struct {
   double flops;           /* counted floating-point operations of the contractions */
   double seconds;         /* wall time of the solve (device synchronised) */
   int max_rank;           /* max TT rank of u */
-  double contraction_ms;  /* device time in the contraction kernels (events), or 0 */
+  double contraction_ms;  /* profile = 1: summed device time of the contraction launches */
+  double contraction_flops; /* profile = 1: algorithmic flops of those launches */
+  long long contraction_launches; /* profile = 1: number of timed launches */
 } tnfem_solve_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -142,6 +146,7 @@ const char* tnfem_last_error(void);
  * host (Alg. 1 on the Cartesian grid: exact Kronecker factors, no rounding of
  * A) and uploads them to the context's device. */
 int tnfem_problem_create(tnfem_ctx* ctx, const tnfem_problem_desc* desc, tnfem_problem** out);
+/* Frees the problem's device memory.  Destroy every problem before its context. */
 int tnfem_problem_destroy(tnfem_problem* p);
 
 /* Shapes: ncores = d + 1; modes[ncores]; mpo_ranks[ncores + 1]; rhs_ranks[ncores + 1]. */

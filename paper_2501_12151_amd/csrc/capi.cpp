@@ -17,6 +17,7 @@ struct tnfem_ctx {
 struct tnfem_problem {
   std::unique_ptr<tnfem::Problem> p;
   tnfem_ctx* ctx;
+  int device;
 };
 struct tnfem_tt {
   tnfem::HostTT t;
@@ -104,6 +105,7 @@ int tnfem_problem_create(tnfem_ctx* ctx, const tnfem_problem_desc* desc, tnfem_p
     if (!ctx || !desc || !out) fail(TNFEM_EINVAL, "NULL argument");
     auto p = std::make_unique<tnfem_problem>();
     p->ctx = ctx;
+    p->device = ctx->c.device;
     p->p = tnfem::make_problem(&ctx->c, *desc);
     *out = p.release();
     return TNFEM_OK;
@@ -113,8 +115,9 @@ int tnfem_problem_create(tnfem_ctx* ctx, const tnfem_problem_desc* desc, tnfem_p
 int tnfem_problem_destroy(tnfem_problem* p) {
   return guarded([&] {
     if (!p) return TNFEM_OK;
-    (void)hipSetDevice(p->ctx->c.device);
-    (void)hipStreamSynchronize(p->ctx->c.stream);
+    // the context may already be gone only if the caller broke the documented order;
+    // touch nothing of it here (hipFree in the destructors waits for the device)
+    (void)hipSetDevice(p->device);
     delete p;
     return TNFEM_OK;
   });

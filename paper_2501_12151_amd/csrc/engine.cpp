@@ -17,8 +17,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <string>
 
 #include "common.hpp"
 
@@ -222,8 +225,10 @@ std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& de
 
 // ----------------------------------------------------------------------------- contractions
 
+static double flop_count(double m, double n, double k, double terms) { return 2.0 * m * n * k * terms; }
+
 static void count(Flops* f, double m, double n, double k, double terms) {
-  if (f) f->total += 2.0 * m * n * k * terms;
+  if (f) f->total += flop_count(m, n, k, terms);
 }
 
 static void stage12(Problem& P, const Plan& pl, int p, int q, int s, const double* L, const double* x, const int* skip,
@@ -249,6 +254,7 @@ static void stage12(Problem& P, const Plan& pl, int p, int q, int s, const doubl
   g1.t_a = pl.slot_b;
   g1.t_b = pl.slot_i;
   g1.skip = skip;
+  g1.flops = flop_count(p, s, q, pl.nslot);
   launch_gemm(g1, st);
   count(f, p, s, q, pl.nslot);
   *src = T1;
@@ -268,6 +274,7 @@ static void stage12(Problem& P, const Plan& pl, int p, int q, int s, const doubl
     g2.K = pl.nslot;
     g2.ngroups = 1;
     g2.skip = skip;
+    g2.flops = flop_count(g2.M, g2.N, g2.K, 1);
     launch_gemm(g2, st);
     count(f, g2.M, g2.N, g2.K, 1);
     *src = T2;
@@ -302,6 +309,7 @@ static void local_apply_ws(Problem& P, const Plan& pl, int p, int q, int s, int 
   g3.t_b = pl.ap_b;
   g3.t_v = pl.ap_v;
   g3.skip = skip;
+  g3.flops = flop_count(p, t, s, pl.n_ap);
   launch_gemm(g3, st);
   count(f, p, t, s, pl.n_ap);
 }
@@ -331,6 +339,7 @@ static void env_update_ws(Problem& P, const Plan& pl, int p, int q, int s, int t
   g3.t_a = pl.en_a;
   g3.t_b = pl.en_b;
   g3.t_v = pl.en_v;
+  g3.flops = flop_count(t, s, p, pl.n_en);
   launch_gemm(g3, st);
   count(f, t, s, p, pl.n_en);
 }
@@ -365,6 +374,7 @@ static void local_rhs(int p, int n, int sb, int sb2, int u, const double* Lb, co
   a.M = p;
   a.N = n * sb2;
   a.K = sb;
+  a.flops = flop_count(p, n * sb2, sb, 1);
   launch_gemm(a, st);
   count(f, p, n * sb2, sb, 1);
   GemmDesc b;
@@ -384,6 +394,7 @@ static void local_rhs(int p, int n, int sb, int sb2, int u, const double* Lb, co
   b.N = u;
   b.K = sb2;
   b.ngroups = n;
+  b.flops = flop_count(p, u, sb2, n);
   launch_gemm(b, st);
   count(f, p, u, sb2, n);
 }
@@ -404,6 +415,7 @@ static void env_b(int p, int n, int sb, int sb2, int t, const double* W, const d
   a.M = p;
   a.N = n * sb2;
   a.K = sb;
+  a.flops = flop_count(p, n * sb2, sb, 1);
   launch_gemm(a, st);
   count(f, p, n * sb2, sb, 1);
   GemmDesc b;
@@ -419,6 +431,7 @@ static void env_b(int p, int n, int sb, int sb2, int t, const double* W, const d
   b.M = t;
   b.N = sb2;
   b.K = p * n;
+  b.flops = flop_count(t, sb2, p * n, 1);
   launch_gemm(b, st);
   count(f, t, sb2, p * n, 1);
 }
@@ -444,6 +457,7 @@ static void gemm_plain(int m, int n, int k, const double* A, long lda, bool tran
   g.M = m;
   g.N = n;
   g.K = k;
+  g.flops = flop_count(m, n, k, 1);
   launch_gemm(g, st);
   count(f, m, n, k, 1);
 }
@@ -493,6 +507,8 @@ void Problem::ensure_workspace(int cap, int rho) {
   W->V = A(Nw * Nw);
   W->Ur = A(M * Nw);
   W->SVt = A(Nw * Nw);
+  W->Vt = A(Nw * Nw);
+  W->xT = A(M * Nw);
   W->xt = A(M * Nw);
   W->aug = A(M * Nw);
   W->Qa = A(M * Nw);
@@ -555,6 +571,7 @@ struct Sweep {
   std::vector<double*> X, Z, EA, Eb, EzA, Ezb;
   std::vector<int> xr, zr;  // K + 1 ranks (current orientation)
   std::vector<int> n;       // modes (current orientation)
+  double *xspare = nullptr, *zspare = nullptr;
   Flops fl;
   long long cg_iters = 0, applies = 0;
   double max_res = 0.0;
@@ -572,6 +589,8 @@ struct Sweep {
     auto cz = random_tt_host(P.modes, o.rho, o.seed_z, rz);
     X = W.X;
     Z = W.Z;
+    xspare = W.Xspare;
+    zspare = W.Zspare;
     EA = W.EA;
     Eb = W.Eb;
     EzA = W.EzA;
@@ -591,10 +610,10 @@ struct Sweep {
 
   void reverse() {
     for (int k = 0; k < K; ++k) {
-      launch_core_transpose(xr[k], n[k], xr[k + 1], X[k], W.Xspare, st);
-      std::swap(X[k], W.Xspare);
-      launch_core_transpose(zr[k], n[k], zr[k + 1], Z[k], W.Zspare, st);
-      std::swap(Z[k], W.Zspare);
+      launch_core_transpose(xr[k], n[k], xr[k + 1], X[k], xspare, st);
+      std::swap(X[k], xspare);
+      launch_core_transpose(zr[k], n[k], zr[k + 1], Z[k], zspare, st);
+      std::swap(Z[k], zspare);
     }
     std::reverse(X.begin(), X.end());
     std::reverse(Z.begin(), Z.end());
@@ -641,8 +660,8 @@ struct Sweep {
 
   void qr_pass() {
     for (int k = 0; k < K - 1; ++k) {
-      qr_step(X, xr, k, W.Xspare);
-      qr_step(Z, zr, k, W.Zspare);
+      qr_step(X, xr, k, xspare);
+      qr_step(Z, zr, k, zspare);
       update_envs(k);
     }
   }
@@ -690,18 +709,48 @@ struct Sweep {
   void truncate_enrich(int k) {
     const int p = xr[k], nk = n[k], t = xr[k + 1];
     const int M = p * nk, Nn = t;
-    if (M < Nn) fail(TNFEM_EINVAL, "internal: bond %d rank %d exceeds %d", k + 1, Nn, M);
-    // SVD of the unfolding: QR, Jacobi on R, U = Q U_R
-    launch_qr(M, Nn, X[k], Nn, W.Qx, Nn, W.Rx, Nn, W.qrws, st);
-    launch_jacobi_svd(Nn, W.Rx, Nn, W.UR, W.S, W.V, W.qrws, st);
+    const int c = std::min(M, Nn);
+    // thin SVD of the M x Nn unfolding: U (M x c) in W.Ur, V^T (c x Nn) in W.Vt
+    if (M >= Nn) {
+      launch_qr(M, Nn, X[k], Nn, W.Qx, Nn, W.Rx, Nn, W.qrws, st);
+      launch_jacobi_svd(Nn, W.Rx, Nn, W.UR, W.S, W.V, W.qrws, st);
+      gemm_plain(M, Nn, Nn, W.Qx, Nn, false, W.UR, Nn, W.Ur, c, st, &fl);
+      launch_core_transpose(Nn, 1, Nn, W.V, W.Vt, st);
+    } else {
+      // x^T = Q U_R S V^T  =>  x = V S (Q U_R)^T
+      launch_core_transpose(M, 1, Nn, X[k], W.xT, st);
+      launch_qr(Nn, M, W.xT, M, W.Qx, M, W.Rx, M, W.qrws, st);
+      launch_jacobi_svd(M, W.Rx, M, W.UR, W.S, W.V, W.qrws, st);
+      launch_copy2d(M, M, W.V, M, W.Ur, c, 1.0, 0.0, st);
+      // V^T = (Q U_R)^T = U_R^T Q^T, Q stored Nn x M row-major
+      GemmDesc g;
+      g.A = W.UR;
+      g.a_sm = 1;
+      g.a_sk = M;
+      g.B = W.Qx;
+      g.b_sk = 1;
+      g.b_sn = M;
+      g.C = W.Vt;
+      g.c_sm = Nn;
+      g.c_sn = 1;
+      g.M = M;
+      g.N = Nn;
+      g.K = M;
+      g.flops = flop_count(M, Nn, M, 1);
+      launch_gemm(g, st);
+      count(&fl, M, Nn, M, 1);
+    }
     const double trtol = o.tol / std::sqrt((double)std::max(K - 1, 1));
-    launch_trunc_rank(Nn, W.S, trtol, o.rank_cap, W.drank, st);
+    launch_trunc_rank(c, W.S, trtol, o.rank_cap, W.drank, st);
     hip_check(hipMemcpyAsync(W.host_pinned, W.drank, sizeof(int), hipMemcpyDeviceToHost, st), "rank readback");
     sync();
     const int rk = hint()[0];
-    // Ur = Qx UR[:, :rk];  xt = Ur diag(S) V^T
-    gemm_plain(M, rk, Nn, W.Qx, Nn, false, W.UR, Nn, W.Ur, rk, st, &fl);
-    launch_scale_vt(rk, Nn, W.S, W.V, Nn, W.SVt, st);
+    // keep U[:, :rk] (in place, leading dimension rk) and xt = U_rk diag(S) V^T_rk
+    if (rk < c) {
+      launch_copy2d(M, rk, W.Ur, c, W.aug, rk, 1.0, 0.0, st);
+      launch_copy2d(M, rk, W.aug, rk, W.Ur, rk, 1.0, 0.0, st);
+    }
+    launch_scale_rows(rk, Nn, W.S, W.Vt, Nn, W.SVt, st);
     gemm_plain(M, Nn, rk, W.Ur, rk, false, W.SVt, Nn, W.xt, Nn, st, &fl);
     // residual projected on the Z interfaces -> new Z_k
     const int pz = zr[k], tz = zr[k + 1];
@@ -722,8 +771,8 @@ struct Sweep {
     // W = Q^T xt (rnew x Nn); X_{k+1} <- W X_{k+1}
     gemm_plain(rnew, Nn, M, X[k], rnew, true, W.xt, Nn, W.Wm, Nn, st, &fl);
     const int cols = n[k + 1] * xr[k + 2];
-    gemm_plain(rnew, cols, Nn, W.Wm, Nn, false, X[k + 1], cols, W.Xspare, cols, st, &fl);
-    std::swap(X[k + 1], W.Xspare);
+    gemm_plain(rnew, cols, Nn, W.Wm, Nn, false, X[k + 1], cols, xspare, cols, st, &fl);
+    std::swap(X[k + 1], xspare);
     xr[k + 1] = rnew;
     zr[k + 1] = cz;
     update_envs(k);
@@ -759,6 +808,16 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   const auto t0 = std::chrono::steady_clock::now();
   tnfem_solve_opts oo = o;
   oo.rho = rho;
+  const char* verbose_env = std::getenv("TNFEM_VERBOSE");
+  const bool verbose = verbose_env && verbose_env[0] == '1';
+  if (o.profile) {
+    if (!P.ws->profile) P.ws->profile = std::make_unique<GemmProfile>();
+    P.ws->profile->reset();
+    set_gemm_profile(P.ws->profile.get());
+  }
+  struct Unset {
+    ~Unset() { set_gemm_profile(nullptr); }
+  } unset;
   Sweep sw(P, oo);
   sw.upload_initial();
   sw.reverse();
@@ -770,6 +829,13 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   for (; sweeps < o.max_sweeps;) {
     last = sw.half_sweep();
     ++sweeps;
+    if (verbose) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      std::string rk;
+      for (int r : sw.xr) rk += std::to_string(r) + " ";
+      fprintf(stderr, "[tnfem] half-sweep %d max_res %.3e cg %lld t %.3fs ranks %s\n", sweeps, last, sw.cg_iters, el,
+              rk.c_str());
+    }
     if (sw.nan_seen || !std::isfinite(last)) break;
     sw.reverse();
     if (last <= o.tol) {
@@ -779,6 +845,11 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   }
   if (sw.orient) sw.reverse();
   sw.sync();
+  // the buffers were permuted by the swaps: hand the permutation back to the workspace
+  P.ws->X = sw.X;
+  P.ws->Z = sw.Z;
+  P.ws->Xspare = sw.xspare;
+  P.ws->Zspare = sw.zspare;
   // download
   out.modes = sw.n;
   out.ranks = sw.xr;
@@ -799,6 +870,14 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   stats.seconds = std::chrono::duration<double>(t1 - t0).count();
   stats.max_rank = *std::max_element(sw.xr.begin(), sw.xr.end());
   stats.contraction_ms = 0.0;
+  stats.contraction_flops = 0.0;
+  stats.contraction_launches = 0;
+  if (o.profile && P.ws->profile) {
+    double fl = 0.0;
+    stats.contraction_ms = P.ws->profile->total_ms(&fl);
+    stats.contraction_flops = fl;
+    stats.contraction_launches = (long long)P.ws->profile->used;
+  }
   if (sw.nan_seen || !std::isfinite(last)) return TNFEM_ENAN;
   return converged ? TNFEM_OK : TNFEM_ENOTCONV;
 }

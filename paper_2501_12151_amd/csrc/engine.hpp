@@ -72,12 +72,13 @@ struct Workspace {
   double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
   double *Tb = nullptr, *gz = nullptr, *yz = nullptr, *ge = nullptr, *ye = nullptr;
   double *Qx = nullptr, *Rx = nullptr, *UR = nullptr, *S = nullptr, *V = nullptr, *Ur = nullptr, *SVt = nullptr,
-         *xt = nullptr, *aug = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;
+         *xt = nullptr, *aug = nullptr, *Vt = nullptr, *xT = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;
   double *scal = nullptr, *part = nullptr;
   int* flag = nullptr;
   int* drank = nullptr;
   void* host_pinned = nullptr;
   size_t bytes = 0;
+  std::unique_ptr<GemmProfile> profile;
   ~Workspace() {
     if (host_pinned) (void)hipHostFree(host_pinned);
   }

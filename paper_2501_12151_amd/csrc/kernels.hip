@@ -152,7 +152,8 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
     for (int j = 0; j < WNB; ++j) {
       const int col = n0 + wn * 16 * WNB + j * 16 + lrow;
       for (int q = 0; q < 4; ++q) {
-        const int row = m0 + wm * 16 * WMB + i * 16 + 4 * lk + q;
+        // v_mfma_f64_16x16x4f64 result: D[r][c] is in lane c + 16 (r % 4), register r / 4
+        const int row = m0 + wm * 16 * WMB + i * 16 + 4 * q + lk;
         if (row < g.M && col < g.N) {
           double* c = Cb + (long)row * g.c_sm + (long)col * g.c_sn;
           const double val = g.alpha * acc[i][j][q];
@@ -162,8 +163,48 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
     }
 }
 
+static thread_local GemmProfile* g_prof = nullptr;
+void set_gemm_profile(GemmProfile* p) { g_prof = p; }
+
+GemmProfile::~GemmProfile() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+double GemmProfile::total_ms(double* total_flops) {
+  double ms = 0.0, fl = 0.0;
+  if (used > 0) (void)hipEventSynchronize(ev[2 * used - 1]);
+  for (size_t i = 0; i < used; ++i) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) ms += t;
+    fl += flops[i];
+  }
+  if (total_flops) *total_flops = fl;
+  return ms;
+}
+
+static void launch_gemm_impl(const GemmDesc& d, hipStream_t s);
+
 void launch_gemm(const GemmDesc& d, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.ngroups <= 0) return;
+  GemmProfile* p = g_prof;
+  if (p && p->used < p->limit) {
+    while (p->ev.size() < 2 * (p->used + 1)) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) throw Error(TNFEM_EDEVICE, "hipEventCreate");
+      p->ev.push_back(e);
+    }
+    hipEvent_t a = p->ev[2 * p->used], b = p->ev[2 * p->used + 1];
+    (void)hipEventRecord(a, s);
+    launch_gemm_impl(d, s);
+    (void)hipEventRecord(b, s);
+    p->flops.push_back(d.flops);
+    p->used++;
+    return;
+  }
+  launch_gemm_impl(d, s);
+}
+
+static void launch_gemm_impl(const GemmDesc& d, hipStream_t s) {
   GemmArgs a{d.A, d.a_slot, d.a_sm, d.a_sk, d.B, d.b_slot, d.b_sk, d.b_sn, d.C, d.c_slot, d.c_sm, d.c_sn,
              d.M, d.N, d.K, d.grp_beg, d.grp_c, d.t_a, d.t_b, d.t_v, d.alpha, d.beta, d.skip, 0};
   if (d.M >= 64 && d.N >= 64) {
@@ -595,6 +636,19 @@ __global__ void scale_vt_kernel(int r, int n, const double* S, const double* V, 
 
 void launch_scale_vt(int r, int n, const double* S, const double* V, int ldv, double* W, hipStream_t s) {
   hipLaunchKernelGGL(scale_vt_kernel, dim3(blocks_for((long)r * n)), dim3(256), 0, s, r, n, S, V, ldv, W);
+  TN_CHECK_LAUNCH();
+}
+
+__global__ void scale_rows_kernel(int r, int n, const double* S, const double* Vt, int ldv, double* W) {
+  const long total = (long)r * n;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    W[idx] = S[i] * Vt[(long)i * ldv + j];
+  }
+}
+
+void launch_scale_rows(int r, int n, const double* S, const double* Vt, int ldv, double* W, hipStream_t s) {
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks_for((long)r * n)), dim3(256), 0, s, r, n, S, Vt, ldv, W);
   TN_CHECK_LAUNCH();
 }
 

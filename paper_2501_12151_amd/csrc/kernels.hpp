@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 namespace tnfem {
 
 // Grouped, strided, coefficient-weighted FP64 GEMM on MFMA:
@@ -29,9 +31,24 @@ struct GemmDesc {
   const double* t_v = nullptr;
   double alpha = 1.0, beta = 0.0;
   const int* skip = nullptr;
+  double flops = 0.0;  // algorithmic flops of this launch (2 M N K per term), for profiling
 };
 
 void launch_gemm(const GemmDesc& g, hipStream_t s);
+
+// Optional per-launch timing of launch_gemm on the calling thread: while a profile
+// is installed, every launch is bracketed by HIP events on its stream.
+struct GemmProfile {
+  std::vector<hipEvent_t> ev;
+  std::vector<double> flops;
+  size_t used = 0;
+  size_t limit = 200000;
+  ~GemmProfile();
+  void reset() { used = 0; flops.clear(); }
+  // Waits for the recorded events; returns total milliseconds and fills total flops.
+  double total_ms(double* total_flops);
+};
+void set_gemm_profile(GemmProfile* p);
 
 // Device scalars of a local CG solve.
 enum CgScal { CG_RZ = 0, CG_PQ, CG_RR, CG_GG, CG_THR2, CG_RES, CG_BETA, CG_NSCAL };
@@ -71,6 +88,9 @@ void launch_copy2d(int rows, int cols, const double* src, long sld, double* dst,
 
 // W[i][j] = S[i] * V[j][i] for i < r, j < n (V: n x ldv row-major).  Builds diag(S) V^T.
 void launch_scale_vt(int r, int n, const double* S, const double* V, int ldv, double* W, hipStream_t s);
+
+// W[i][j] = S[i] * Vt[i][j] for i < r, j < n (Vt row-major, leading dimension ldv).
+void launch_scale_rows(int r, int n, const double* S, const double* Vt, int ldv, double* W, hipStream_t s);
 
 // Core transpose for chain reversal: out[b][i][a] = in[a][i][b], in: [ra][n][rb].
 void launch_core_transpose(int ra, int n, int rb, const double* in, double* out, hipStream_t s);

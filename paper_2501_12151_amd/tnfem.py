@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -44,7 +45,7 @@ class SolveOpts(C.Structure):
     _fields_ = [
         ("rank_cap", C.c_int), ("tol", C.c_double), ("max_sweeps", C.c_int), ("rho", C.c_int),
         ("init_rank", C.c_int), ("seed_x", C.c_uint64), ("seed_z", C.c_uint64), ("cg_maxit", C.c_int),
-        ("precision", C.c_int),
+        ("precision", C.c_int), ("profile", C.c_int),
     ]
 
 
@@ -53,6 +54,7 @@ class SolveStats(C.Structure):
         ("sweeps", C.c_int), ("converged", C.c_int), ("final_max_res", C.c_double),
         ("cg_iters", C.c_longlong), ("local_applies", C.c_longlong), ("flops", C.c_double),
         ("seconds", C.c_double), ("max_rank", C.c_int), ("contraction_ms", C.c_double),
+        ("contraction_flops", C.c_double), ("contraction_launches", C.c_longlong),
     ]
 
     def as_dict(self):
@@ -235,9 +237,13 @@ class Context:
             s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         _check(_lib.tnfem_ctx_create(C.byref(h), int(device), s))
         self._h = h
+        self._problems = weakref.WeakSet()
 
     def close(self):
+        """Destroys the context after every problem created on it."""
         if getattr(self, "_h", None):
+            for p in list(self._problems):
+                p.close()
             _lib.tnfem_ctx_destroy(self._h)
             self._h = None
 
@@ -269,6 +275,7 @@ class Problem:
         h = _vp()
         _check(_lib.tnfem_problem_create(ctx._h, C.byref(self.desc), C.byref(h)))
         self._h = h
+        ctx._problems.add(self)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -33,13 +33,13 @@ def test_unconstrained_solve_equals_direct_and_oracle(ctx, case):
     A, b, grid, _ = fem.build_system(prob)
     u = qtt.to_qtt_order(fem.direct_solve(A, b), prob["dim"], prob["level"])
     P = tnfem.Problem(ctx, prob)
-    opts = dict(rank_cap=256, tol=1e-10, max_sweeps=30)
+    opts = dict(rank_cap=200, tol=1e-10, max_sweeps=30)
     U, st, rc = P.solve(**opts)
     assert rc == tnfem.OK, st
     ug = tt.tt_full(U.cores)
     assert np.linalg.norm(ug - u) <= 1e-8 * np.linalg.norm(u)
     X, ost = oamen.amen_solve(qtt.assemble_operator(prob), qtt.assemble_load(prob),
-                              oamen.Options(tol=1e-10, rank_cap=256, max_sweeps=30))
+                              oamen.Options(tol=1e-10, rank_cap=200, max_sweeps=30))
     assert np.linalg.norm(ug - tt.tt_full(X)) <= 1e-8 * np.linalg.norm(u)
     assert st["sweeps"] == ost.sweeps
 
