@@ -76,14 +76,23 @@ def env_b(Lb, W, B):
 
 
 def pcg(apply, g, x, dinv, thr, maxit):
-    """Jacobi-preconditioned conjugate gradients from x until ||g - B x|| <= thr."""
+    """Jacobi-preconditioned conjugate gradients from x until ||g - B x|| <= thr.
+
+    Each iteration applies B to the preconditioned residual z and carries
+    q = B p by the recurrence q = B z + beta q, which equals B p for
+    p = z + beta p by linearity (the textbook method, one product per step).
+    """
     r = g - apply(x)
     z = r * dinv
-    p = z.copy()
+    p = np.zeros_like(r)
+    q = np.zeros_like(r)
+    beta = 0.0
     rz = float(np.vdot(r, z))
     it = 0
     while it < maxit and np.linalg.norm(r) > thr:
-        q = apply(p)
+        w = apply(z)
+        p = z + beta * p
+        q = w + beta * q
         pq = float(np.vdot(p, q))
         if pq <= 0.0:
             break
@@ -94,7 +103,6 @@ def pcg(apply, g, x, dinv, thr, maxit):
         rz_new = float(np.vdot(r, z))
         beta = rz_new / rz
         rz = rz_new
-        p = z + beta * p
         it += 1
     return x, it
 
@@ -230,8 +238,12 @@ def _half_sweep(ch: _Chain, opt: Options, st: Stats):
     return max_res
 
 
-def amen_solve(A, b, opt: Options | None = None):
-    """Solve A u = b in TT format.  Returns (list of cores of u, Stats)."""
+def amen_solve(A, b, opt: Options | None = None, after_half_sweep=None):
+    """Solve A u = b in TT format.  Returns (list of cores of u, Stats).
+
+    after_half_sweep(stats), if given, is called after every half-sweep; a true
+    return value ends the sweep loop there (used to time bounded samples).
+    """
     opt = opt or Options()
     modes = [C.shape[1] for C in A]
     X = rng.random_tt(modes, opt.init_rank, opt.seed_x)
@@ -247,6 +259,8 @@ def amen_solve(A, b, opt: Options | None = None):
         st.max_res.append(mr)
         ch.reverse()
         if mr <= opt.tol:
+            break
+        if after_half_sweep is not None and after_half_sweep(st):
             break
     if ch.reversed:
         ch.reverse()

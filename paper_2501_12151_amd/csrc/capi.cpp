@@ -94,6 +94,7 @@ int tnfem_ctx_destroy(tnfem_ctx* ctx) {
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     if (ctx->c.scratch) (void)hipFree(ctx->c.scratch);
+    if (ctx->c.splitk) (void)hipFree(ctx->c.splitk);
     if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
     delete ctx;
     return TNFEM_OK;

@@ -58,6 +58,13 @@ T* DevArena::upload(const std::vector<T>& v, hipStream_t s) {
 template int* DevArena::upload<int>(const std::vector<int>&, hipStream_t);
 template double* DevArena::upload<double>(const std::vector<double>&, hipStream_t);
 
+void Context::ensure_splitk() {
+  if (!splitk) {
+    splitk_cap = (size_t)1 << 22;
+    hip_check(hipMalloc(&splitk, splitk_cap * sizeof(double)), "hipMalloc split-K buffer");
+  }
+}
+
 double* Context::ensure_scratch(size_t doubles) {
   if (doubles > scratch_doubles) {
     if (scratch) (void)hipFree(scratch);
@@ -150,8 +157,13 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
     }
   }
   auto flatten = [&](const std::vector<std::vector<int>>& A, const std::vector<std::vector<int>>& B,
-                     const std::vector<std::vector<double>>& V, int** dbeg, int** da, int** db, double** dv) {
+                     const std::vector<std::vector<double>>& V, int** dbeg, int** da, int** db, double** dv,
+                     int* gmax) {
     std::vector<int> b0, fa, fb;
+    if (gmax) {
+      *gmax = 1;
+      for (const auto& g : A) *gmax = std::max(*gmax, (int)g.size());
+    }
     std::vector<double> fv;
     b0.push_back(0);
     for (size_t g = 0; g < A.size(); ++g) {
@@ -166,8 +178,8 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
     *dv = arena.upload(fv, s);
     return (int)fa.size();
   };
-  P.n_ap = flatten(ap_a, ap_b, ap_v, &P.ap_beg, &P.ap_a, &P.ap_b, &P.ap_v);
-  P.n_en = flatten(en_a, en_b, en_v, &P.en_beg, &P.en_a, &P.en_b, &P.en_v);
+  P.n_ap = flatten(ap_a, ap_b, ap_v, &P.ap_beg, &P.ap_a, &P.ap_b, &P.ap_v, &P.ap_max);
+  P.n_en = flatten(en_a, en_b, en_v, &P.en_beg, &P.en_a, &P.en_b, &P.en_v, &P.en_max);
   // diagonal terms
   std::vector<std::vector<int>> db(n), de(n);
   std::vector<std::vector<double>> dv(n);
@@ -177,7 +189,7 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
       de[c.ii[t]].push_back(c.e[t]);
       dv[c.ii[t]].push_back(c.v[t]);
     }
-  flatten(db, de, dv, &P.dg_beg, &P.dg_b, &P.dg_e, &P.dg_v);
+  flatten(db, de, dv, &P.dg_beg, &P.dg_b, &P.dg_e, &P.dg_v, nullptr);
   return P;
 }
 
@@ -308,6 +320,7 @@ static void local_apply_ws(Problem& P, const Plan& pl, int p, int q, int s, int 
   g3.t_a = pl.ap_a;
   g3.t_b = pl.ap_b;
   g3.t_v = pl.ap_v;
+  g3.max_terms = pl.ap_max;
   g3.skip = skip;
   g3.flops = flop_count(p, t, s, pl.n_ap);
   launch_gemm(g3, st);
@@ -339,15 +352,23 @@ static void env_update_ws(Problem& P, const Plan& pl, int p, int q, int s, int t
   g3.t_a = pl.en_a;
   g3.t_b = pl.en_b;
   g3.t_v = pl.en_v;
+  g3.max_terms = pl.en_max;
   g3.flops = flop_count(t, s, p, pl.n_en);
   launch_gemm(g3, st);
   count(f, t, s, p, pl.n_en);
 }
 
+struct SplitkScope {
+  explicit SplitkScope(double* p, size_t cap) { set_gemm_splitk_buffer(p, cap); }
+  ~SplitkScope() { set_gemm_splitk_buffer(nullptr, 0); }
+};
+
 void dev_local_apply(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* L, const double* x,
                      const double* Rt, double* y, const int* skip, hipStream_t st, Flops* f) {
   const size_t n1 = (size_t)pl.n_t1() * p * s, n2 = (size_t)pl.n_t2() * p * s;
   double* T1 = P.ctx->ensure_scratch(n1 + n2 + 1);
+  P.ctx->ensure_splitk();
+  SplitkScope sk(P.ctx->splitk, P.ctx->splitk_cap);
   local_apply_ws(P, pl, p, q, s, t, L, x, Rt, y, skip, st, f, T1, T1 + n1);
 }
 
@@ -355,6 +376,8 @@ void dev_env_update(Problem& P, const Plan& pl, int p, int q, int s, int t, cons
                     const double* X, double* Lnew, hipStream_t st, Flops* f) {
   const size_t n1 = (size_t)pl.n_t1() * p * s, n2 = (size_t)pl.n_t2() * p * s;
   double* T1 = P.ctx->ensure_scratch(n1 + n2 + 1);
+  P.ctx->ensure_splitk();
+  SplitkScope sk(P.ctx->splitk, P.ctx->splitk_cap);
   env_update_ws(P, pl, p, q, s, t, W, L, X, Lnew, st, f, T1, T1 + n1);
 }
 
@@ -494,6 +517,7 @@ void Problem::ensure_workspace(int cap, int rho) {
   W->z = A(core);
   W->p = A(core);
   W->q = A(core);
+  W->w = A(core);
   W->dinv = A(core);
   W->Tb = A(rc * maxn * smax);
   W->gz = A(core);
@@ -516,6 +540,8 @@ void Problem::ensure_workspace(int cap, int rho) {
   W->Wm = A(Nw * Nw);
   W->qrws = A(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw);
   W->scal = A(CG_NSCAL);
+  W->splitk_cap = (size_t)1 << 22;
+  W->splitk = A(W->splitk_cap);
   W->part = A(3 * 512);
   W->flag = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
   W->drank = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
@@ -676,7 +702,7 @@ struct Sweep {
                       st);
     apply(k, p, p, t, t, EA[k], X[k], EA[k + 1], W.q, nullptr);
     applies++;
-    launch_cg_init(N, W.g, W.q, W.dinv, W.r, W.z, W.p, W.scal, W.flag, W.part, o.tol, o.cg_maxit, st);
+    launch_cg_init(N, W.g, W.q, W.dinv, W.r, W.z, W.p, W.w, W.scal, W.flag, W.part, o.tol, o.cg_maxit, st);
     auto readback = [&]() {
       hip_check(hipMemcpyAsync(W.host_pinned, W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flag readback");
       hip_check(hipMemcpyAsync(static_cast<char*>(W.host_pinned) + 64, W.scal + CG_RES, sizeof(double),
@@ -692,10 +718,9 @@ struct Sweep {
     int launched = 0;
     while (!done && launched < o.cg_maxit) {
       for (int c = 0; c < chunk && launched < o.cg_maxit; ++c, ++launched) {
-        apply(k, p, p, t, t, EA[k], W.p, EA[k + 1], W.q, W.flag + CG_DONE);
-        launch_cg_dot(N, W.p, W.q, W.scal, W.flag, W.part, st);
-        launch_cg_update(N, X[k], W.p, W.q, W.r, W.z, W.dinv, W.scal, W.flag, W.part, st);
-        launch_cg_pupdate(N, W.p, W.z, W.scal, W.flag, st);
+        apply(k, p, p, t, t, EA[k], W.z, EA[k + 1], W.q, W.flag + CG_DONE);
+        launch_cg_dir(N, W.z, W.q, W.p, W.w, W.scal, W.flag, W.part, st);
+        launch_cg_update(N, X[k], W.p, W.w, W.r, W.z, W.dinv, W.scal, W.flag, W.part, st);
       }
       readback();
       done = hint()[0];
@@ -816,8 +841,12 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
     set_gemm_profile(P.ws->profile.get());
   }
   struct Unset {
-    ~Unset() { set_gemm_profile(nullptr); }
+    ~Unset() {
+      set_gemm_profile(nullptr);
+      set_gemm_splitk_buffer(nullptr, 0);
+    }
   } unset;
+  set_gemm_splitk_buffer(P.ws->splitk, P.ws->splitk_cap);
   Sweep sw(P, oo);
   sw.upload_initial();
   sw.reverse();

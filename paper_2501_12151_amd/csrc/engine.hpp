@@ -39,10 +39,10 @@ struct Plan {
   double* A2 = nullptr;
   int *ap_beg = nullptr, *ap_a = nullptr, *ap_b = nullptr;
   double* ap_v = nullptr;
-  int n_ap = 0;
+  int n_ap = 0, ap_max = 1;
   int *en_beg = nullptr, *en_a = nullptr, *en_b = nullptr;
   double* en_v = nullptr;
-  int n_en = 0;
+  int n_en = 0, en_max = 1;
   int *dg_beg = nullptr, *dg_b = nullptr, *dg_e = nullptr;
   double* dg_v = nullptr;
   int n_t1() const { return nslot; }
@@ -56,7 +56,10 @@ struct Context {
   DevArena arena;
   double* scratch = nullptr;  // for primitives
   size_t scratch_doubles = 0;
+  double* splitk = nullptr;   // split-K partial tiles for primitives
+  size_t splitk_cap = 0;
   double* ensure_scratch(size_t doubles);
+  void ensure_splitk();
 };
 
 struct Problem;
@@ -69,11 +72,13 @@ struct Workspace {
   double *Xspare = nullptr, *Zspare = nullptr;
   std::vector<double*> EA, Eb, EzA, Ezb;  // K + 1 bond buffers
   double *T1 = nullptr, *T2 = nullptr;
-  double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+  double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *dinv = nullptr;
   double *Tb = nullptr, *gz = nullptr, *yz = nullptr, *ge = nullptr, *ye = nullptr;
   double *Qx = nullptr, *Rx = nullptr, *UR = nullptr, *S = nullptr, *V = nullptr, *Ur = nullptr, *SVt = nullptr,
          *xt = nullptr, *aug = nullptr, *Vt = nullptr, *xT = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;
   double *scal = nullptr, *part = nullptr;
+  double* splitk = nullptr;
+  size_t splitk_cap = 0;
   int* flag = nullptr;
   int* drank = nullptr;
   void* host_pinned = nullptr;

@@ -12,6 +12,7 @@
 //   matrices are at most (r n) x (r + rho) and (r + rho)^2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -75,12 +76,15 @@ struct GemmArgs {
   const double* t_v;
   double alpha, beta;
   const int* skip;
-  int tiles_n;
+  int tiles_n, ntiles, ngroups, ksplit;
+  double* partial;
 };
 
-constexpr int BK = 16;
+constexpr int BK = 32;
 
 // 4 waves in a 2 x 2 arrangement; each wave owns WMB x WNB blocks of 16 x 16.
+// blockIdx.x: output tile, blockIdx.y: group, blockIdx.z: split of the group's
+// (term, k-step) iterations.
 template <int WMB, int WNB>
 __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
   constexpr int TM = 32 * WMB, TN = 32 * WNB;
@@ -89,6 +93,7 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
   if (g.skip && *g.skip) return;
   const int grp = blockIdx.y;
   const int tile = blockIdx.x;
+  const int z = blockIdx.z;
   const int m0 = (tile / g.tiles_n) * TM, n0 = (tile % g.tiles_n) * TN;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
@@ -102,49 +107,67 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
     tb = grp;
     te = grp + 1;
   }
+  const int nks = (g.K + BK - 1) / BK;
+  const long iters = (long)(te - tb) * nks;
+  const long chunk = (iters + g.ksplit - 1) / g.ksplit;
+  const long it0 = (long)z * chunk;
+  const long it1 = it0 + chunk < iters ? it0 + chunk : iters;
+
   d4_t acc[WMB][WNB];
   for (int i = 0; i < WMB; ++i)
     for (int j = 0; j < WNB; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
   const bool a_kfast = (g.a_sk == 1);
   const bool b_nfast = (g.b_sn == 1);
-  for (int t = tb; t < te; ++t) {
+  for (long it = it0; it < it1; ++it) {
+    const int t = tb + (int)(it / nks);
+    const int k0 = (int)(it % nks) * BK;
     const int ai = g.grp_beg ? g.t_a[t] : t;
     const int bi = g.grp_beg ? g.t_b[t] : t;
     const double v = g.t_v ? g.t_v[t] : 1.0;
     const double* Ab = g.A + (long)ai * g.a_slot;
     const double* Bb = g.B + (long)bi * g.b_slot;
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-      // stage A tile (TM x BK) k-major
-      for (int idx = tid; idx < TM * BK; idx += 256) {
-        int mm, kk;
-        if (a_kfast) { mm = idx / BK; kk = idx % BK; }
-        else { mm = idx % TM; kk = idx / TM; }
-        const int gm = m0 + mm, gk = k0 + kk;
-        sA[kk][mm] = (gm < g.M && gk < g.K) ? v * Ab[(long)gm * g.a_sm + (long)gk * g.a_sk] : 0.0;
-      }
-      for (int idx = tid; idx < TN * BK; idx += 256) {
-        int nn, kk;
-        if (b_nfast) { nn = idx % TN; kk = idx / TN; }
-        else { nn = idx / BK; kk = idx % BK; }
-        const int gn = n0 + nn, gk = k0 + kk;
-        sB[kk][nn] = (gn < g.N && gk < g.K) ? Bb[(long)gk * g.b_sk + (long)gn * g.b_sn] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        double af[WMB], bf[WNB];
-#pragma unroll
-        for (int i = 0; i < WMB; ++i) af[i] = sA[kk + lk][wm * 16 * WMB + i * 16 + lrow];
-#pragma unroll
-        for (int j = 0; j < WNB; ++j) bf[j] = sB[kk + lk][wn * 16 * WNB + j * 16 + lrow];
-#pragma unroll
-        for (int i = 0; i < WMB; ++i)
-#pragma unroll
-          for (int j = 0; j < WNB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-      }
-      __syncthreads();
+    for (int idx = tid; idx < TM * BK; idx += 256) {
+      int mm, kk;
+      if (a_kfast) { mm = idx / BK; kk = idx % BK; }
+      else { mm = idx % TM; kk = idx / TM; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      sA[kk][mm] = (gm < g.M && gk < g.K) ? v * Ab[(long)gm * g.a_sm + (long)gk * g.a_sk] : 0.0;
     }
+    for (int idx = tid; idx < TN * BK; idx += 256) {
+      int nn, kk;
+      if (b_nfast) { nn = idx % TN; kk = idx / TN; }
+      else { nn = idx / BK; kk = idx % BK; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      sB[kk][nn] = (gn < g.N && gk < g.K) ? Bb[(long)gk * g.b_sk + (long)gn * g.b_sn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double af[WMB], bf[WNB];
+#pragma unroll
+      for (int i = 0; i < WMB; ++i) af[i] = sA[kk + lk][wm * 16 * WMB + i * 16 + lrow];
+#pragma unroll
+      for (int j = 0; j < WNB; ++j) bf[j] = sB[kk + lk][wn * 16 * WNB + j * 16 + lrow];
+#pragma unroll
+      for (int i = 0; i < WMB; ++i)
+#pragma unroll
+        for (int j = 0; j < WNB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (g.ksplit > 1) {
+    // full (padded) partial tile, row-major TM x TN
+    double* Pt = g.partial + (((long)z * g.ngroups + grp) * g.ntiles + tile) * (long)(TM * TN);
+    for (int i = 0; i < WMB; ++i)
+      for (int j = 0; j < WNB; ++j) {
+        const int col = wn * 16 * WNB + j * 16 + lrow;
+        for (int q = 0; q < 4; ++q) {
+          const int row = wm * 16 * WMB + i * 16 + 4 * q + lk;
+          Pt[row * TN + col] = acc[i][j][q];
+        }
+      }
+    return;
   }
   const int ci = g.grp_c ? g.grp_c[grp] : grp;
   double* Cb = g.C + (long)ci * g.c_slot;
@@ -163,8 +186,44 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
     }
 }
 
+// Sums the split partial tiles in split order and writes C (alpha, beta as above).
+// One thread per tile element; blockIdx.z covers the tile's elements.
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
+  if (g.skip && *g.skip) return;
+  const int grp = blockIdx.y, tile = blockIdx.x;
+  const int e = blockIdx.z * 256 + threadIdx.x;
+  if (e >= TM * TN) return;
+  const int m0 = (tile / g.tiles_n) * TM, n0 = (tile % g.tiles_n) * TN;
+  const int row = m0 + e / TN, col = n0 + e % TN;
+  if (row >= g.M || col >= g.N) return;
+  const long stride = (long)g.ngroups * g.ntiles * (TM * TN);
+  const double* src = g.partial + ((long)grp * g.ntiles + tile) * (long)(TM * TN) + e;
+  double s = 0.0;
+  int z = 0;
+  for (; z + 4 <= g.ksplit; z += 4) {
+    const double a0 = src[(long)z * stride], a1 = src[(long)(z + 1) * stride];
+    const double a2 = src[(long)(z + 2) * stride], a3 = src[(long)(z + 3) * stride];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; z < g.ksplit; ++z) s += src[(long)z * stride];
+  const int ci = g.grp_c ? g.grp_c[grp] : grp;
+  double* c = g.C + (long)ci * g.c_slot + (long)row * g.c_sm + (long)col * g.c_sn;
+  const double val = g.alpha * s;
+  *c = (g.beta == 0.0) ? val : val + g.beta * *c;
+}
+
 static thread_local GemmProfile* g_prof = nullptr;
 void set_gemm_profile(GemmProfile* p) { g_prof = p; }
+static thread_local double* g_splitk = nullptr;
+static thread_local size_t g_splitk_cap = 0;
+void set_gemm_splitk_buffer(double* p, size_t cap) {
+  g_splitk = p;
+  g_splitk_cap = p ? cap : 0;
+}
 
 GemmProfile::~GemmProfile() {
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -186,57 +245,98 @@ static void launch_gemm_impl(const GemmDesc& d, hipStream_t s);
 
 void launch_gemm(const GemmDesc& d, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.ngroups <= 0) return;
-  GemmProfile* p = g_prof;
-  if (p && p->used < p->limit) {
-    while (p->ev.size() < 2 * (p->used + 1)) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) throw Error(TNFEM_EDEVICE, "hipEventCreate");
-      p->ev.push_back(e);
-    }
-    hipEvent_t a = p->ev[2 * p->used], b = p->ev[2 * p->used + 1];
-    (void)hipEventRecord(a, s);
-    launch_gemm_impl(d, s);
-    (void)hipEventRecord(b, s);
-    p->flops.push_back(d.flops);
-    p->used++;
-    return;
-  }
   launch_gemm_impl(d, s);
+}
+
+// Event pair around the contraction kernel itself (not its split-K reduction).
+static hipEvent_t* prof_begin(hipStream_t s) {
+  GemmProfile* p = g_prof;
+  if (!p || p->used >= p->limit) return nullptr;
+  while (p->ev.size() < 2 * (p->used + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) throw Error(TNFEM_EDEVICE, "hipEventCreate");
+    p->ev.push_back(e);
+  }
+  hipEvent_t* pair = &p->ev[2 * p->used];
+  (void)hipEventRecord(pair[0], s);
+  return pair;
+}
+
+static void prof_end(hipEvent_t* pair, double flops, hipStream_t s) {
+  if (!pair) return;
+  (void)hipEventRecord(pair[1], s);
+  g_prof->flops.push_back(flops);
+  g_prof->used++;
+}
+
+// Workgroups wanted per launch before splitting is considered (256 CUs).
+constexpr long SPLIT_TARGET_WG = 512;
+constexpr int SPLIT_MIN_ITERS = 2;  // (term, k-step) iterations per split at least
+
+template <int WMB, int WNB>
+static void launch_tiled(GemmArgs a, const GemmDesc& d, hipStream_t s) {
+  constexpr int TM = 32 * WMB, TN = 32 * WNB;
+  a.tiles_n = (d.N + TN - 1) / TN;
+  a.ntiles = ((d.M + TM - 1) / TM) * a.tiles_n;
+  a.ngroups = d.ngroups;
+  a.ksplit = 1;
+  const long natural = (long)a.ntiles * d.ngroups;
+  const long iters = (long)std::max(d.max_terms, 1) * ((d.K + BK - 1) / BK);
+  double* pbuf = d.partial ? d.partial : g_splitk;
+  const size_t pcap = d.partial ? d.partial_cap : g_splitk_cap;
+  if (pbuf && natural < SPLIT_TARGET_WG && iters >= 2 * SPLIT_MIN_ITERS) {
+    long ks = (SPLIT_TARGET_WG + natural - 1) / natural;
+    ks = std::min(ks, iters / SPLIT_MIN_ITERS);
+    const long per = natural * (long)(TM * TN);
+    ks = std::min(ks, (long)(pcap / std::max(per, 1L)));
+    ks = std::min(ks, 64L);
+    if (ks >= 2) a.ksplit = (int)ks;
+  }
+  a.partial = d.partial ? d.partial : g_splitk;
+  dim3 grid(a.ntiles, d.ngroups, a.ksplit);
+  hipEvent_t* ev = prof_begin(s);
+  hipLaunchKernelGGL((gemm_grouped_kernel<WMB, WNB>), grid, dim3(256), 0, s, a);
+  prof_end(ev, d.flops, s);
+  TN_CHECK_LAUNCH();
+  if (a.ksplit > 1) {
+    hipLaunchKernelGGL((splitk_reduce_kernel<TM, TN>), dim3(a.ntiles, d.ngroups, (TM * TN + 255) / 256), dim3(256), 0,
+                       s, a);
+    TN_CHECK_LAUNCH();
+  }
 }
 
 static void launch_gemm_impl(const GemmDesc& d, hipStream_t s) {
   GemmArgs a{d.A, d.a_slot, d.a_sm, d.a_sk, d.B, d.b_slot, d.b_sk, d.b_sn, d.C, d.c_slot, d.c_sm, d.c_sn,
-             d.M, d.N, d.K, d.grp_beg, d.grp_c, d.t_a, d.t_b, d.t_v, d.alpha, d.beta, d.skip, 0};
-  if (d.M >= 64 && d.N >= 64) {
-    a.tiles_n = (d.N + 63) / 64;
-    dim3 grid(((d.M + 63) / 64) * a.tiles_n, d.ngroups);
-    hipLaunchKernelGGL((gemm_grouped_kernel<2, 2>), grid, dim3(256), 0, s, a);
-  } else {
-    a.tiles_n = (d.N + 31) / 32;
-    dim3 grid(((d.M + 31) / 32) * a.tiles_n, d.ngroups);
-    hipLaunchKernelGGL((gemm_grouped_kernel<1, 1>), grid, dim3(256), 0, s, a);
-  }
-  TN_CHECK_LAUNCH();
+             d.M, d.N, d.K, d.grp_beg, d.grp_c, d.t_a, d.t_b, d.t_v, d.alpha, d.beta, d.skip, 0, 0, 0, 1, nullptr};
+  if (d.M >= 64 && d.N >= 64) launch_tiled<2, 2>(a, d, s);
+  else launch_tiled<1, 1>(a, d, s);
 }
 
 // ----------------------------------------------------------------------------- CG
 
 constexpr int CG_NT = 256;
+constexpr int CG_NT1 = 1024;          // single-workgroup variant
 constexpr int CG_MAXB = 512;
+constexpr int CG_SINGLE_MAX = 32768;  // vectors up to this length use one workgroup
 
 static int cg_blocks(int n) {
   int b = (n + CG_NT * 4 - 1) / (CG_NT * 4);
   return b < 1 ? 1 : (b > CG_MAXB ? CG_MAXB : b);
 }
 
-// Last-block reduction of NV partial sums per block.  Returns true in the last block,
-// with out[] holding the totals (valid in every thread of that block).
-template <int NV>
+// Reduction of NV partial sums over the grid.  With one workgroup the block sum
+// is final; otherwise per-block partials are written and the last block to
+// finish sums them in block order.  Returns true in the block holding the totals.
+template <int NT, int NV>
 __device__ bool last_block_reduce(const double (&mine)[NV], double* part, int* counter, double* out) {
-  __shared__ double red[CG_NT / 64];
+  __shared__ double red[NT / 64];
   __shared__ bool am_last;
   double tot[NV];
-  for (int v = 0; v < NV; ++v) tot[v] = block_sum<CG_NT>(mine[v], red);
+  for (int v = 0; v < NV; ++v) tot[v] = block_sum<NT>(mine[v], red);
+  if (gridDim.x == 1) {
+    for (int v = 0; v < NV; ++v) out[v] = tot[v];
+    return true;
+  }
   if (threadIdx.x == 0) {
     for (int v = 0; v < NV; ++v) part[v * CG_MAXB + blockIdx.x] = tot[v];
     __threadfence();
@@ -248,29 +348,31 @@ __device__ bool last_block_reduce(const double (&mine)[NV], double* part, int* c
   __threadfence();
   for (int v = 0; v < NV; ++v) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += CG_NT) s += __builtin_nontemporal_load(&part[v * CG_MAXB + b]);
-    out[v] = block_sum<CG_NT>(s, red);
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += NT) s += part[v * CG_MAXB + b];
+    out[v] = block_sum<NT>(s, red);
   }
   return true;
 }
 
-__global__ __launch_bounds__(CG_NT) void cg_init_kernel(int n, const double* g, const double* q, const double* dinv,
-                                                        double* r, double* z, double* p, double* scal, int* flag,
-                                                        double* part, double tol, int maxit) {
+template <int NT>
+__global__ __launch_bounds__(NT) void cg_init_kernel(int n, const double* g, const double* q, const double* dinv,
+                                                        double* r, double* z, double* p, double* qr, double* scal,
+                                                        int* flag, double* part, double tol, int maxit) {
   double loc[3] = {0.0, 0.0, 0.0};  // rz, rr, gg
-  for (int i = blockIdx.x * CG_NT + threadIdx.x; i < n; i += gridDim.x * CG_NT) {
+  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
     const double gi = g[i];
     const double ri = gi - q[i];
     const double zi = ri * dinv[i];
     r[i] = ri;
     z[i] = zi;
-    p[i] = zi;
+    p[i] = 0.0;
+    qr[i] = 0.0;
     loc[0] += ri * zi;
     loc[1] += ri * ri;
     loc[2] += gi * gi;
   }
   double tot[3];
-  if (last_block_reduce<3>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
+  if (last_block_reduce<NT, 3>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
     const double rr = tot[1], gg = tot[2];
     const double gn = sqrt(gg);
     const double res = gg > 0.0 ? sqrt(rr) / gn : (rr == 0.0 ? 0.0 : 1.0);
@@ -280,6 +382,7 @@ __global__ __launch_bounds__(CG_NT) void cg_init_kernel(int n, const double* g, 
     scal[CG_GG] = gg;
     scal[CG_RES] = res;
     scal[CG_THR2] = thr * thr;
+    scal[CG_BETA] = 0.0;
     flag[CG_ITERS] = 0;
     flag[CG_MAXIT] = maxit;
     flag[CG_DONE] = (res <= 0.5 * tol || maxit <= 0) ? 1 : 0;
@@ -287,30 +390,37 @@ __global__ __launch_bounds__(CG_NT) void cg_init_kernel(int n, const double* g, 
   }
 }
 
-__global__ __launch_bounds__(CG_NT) void cg_dot_kernel(int n, const double* p, const double* q, double* scal,
-                                                       int* flag, double* part) {
+// p = z + beta p; q = w + beta q (q = B p by linearity); pq = p . q
+template <int NT>
+__global__ __launch_bounds__(NT) void cg_dir_kernel(int n, const double* z, const double* w, double* p, double* q,
+                                                       double* scal, int* flag, double* part) {
   if (flag[CG_DONE]) return;
+  const double beta = scal[CG_BETA];
   double loc[1] = {0.0};
-  for (int i = blockIdx.x * CG_NT + threadIdx.x; i < n; i += gridDim.x * CG_NT) loc[0] += p[i] * q[i];
+  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    const double pi = z[i] + beta * p[i];
+    const double qi = w[i] + beta * q[i];
+    p[i] = pi;
+    q[i] = qi;
+    loc[0] += pi * qi;
+  }
   double tot[1];
-  if (last_block_reduce<1>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
+  if (last_block_reduce<NT, 1>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
     scal[CG_PQ] = tot[0];
+    if (!(tot[0] > 0.0)) flag[CG_DONE] = 2;  // breakdown: stop before updating
     flag[CG_COUNTER] = 0;
   }
 }
 
-__global__ __launch_bounds__(CG_NT) void cg_update_kernel(int n, double* x, const double* p, const double* q, double* r,
+// x += alpha p; r -= alpha q; z = dinv r; beta = (r.z)_new / (r.z)_old; convergence flag
+template <int NT>
+__global__ __launch_bounds__(NT) void cg_update_kernel(int n, double* x, const double* p, const double* q, double* r,
                                                           double* z, const double* dinv, double* scal, int* flag,
                                                           double* part) {
   if (flag[CG_DONE]) return;
-  const double pq = scal[CG_PQ];
-  if (!(pq > 0.0)) {  // breakdown: stop without updating (every block takes this branch)
-    if (blockIdx.x == 0 && threadIdx.x == 0) flag[CG_DONE] = 2;
-    return;
-  }
-  const double alpha = scal[CG_RZ] / pq;
+  const double alpha = scal[CG_RZ] / scal[CG_PQ];
   double loc[2] = {0.0, 0.0};  // rz, rr
-  for (int i = blockIdx.x * CG_NT + threadIdx.x; i < n; i += gridDim.x * CG_NT) {
+  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     const double zi = ri * dinv[i];
@@ -320,7 +430,7 @@ __global__ __launch_bounds__(CG_NT) void cg_update_kernel(int n, double* x, cons
     loc[1] += ri * ri;
   }
   double tot[2];
-  if (last_block_reduce<2>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
+  if (last_block_reduce<NT, 2>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
     scal[CG_BETA] = tot[0] / scal[CG_RZ];
     scal[CG_RZ] = tot[0];
     scal[CG_RR] = tot[1];
@@ -331,31 +441,32 @@ __global__ __launch_bounds__(CG_NT) void cg_update_kernel(int n, double* x, cons
   }
 }
 
-__global__ __launch_bounds__(CG_NT) void cg_pupdate_kernel(int n, double* p, const double* z, const double* scal,
-                                                           const int* flag) {
-  if (flag[CG_DONE]) return;
-  const double beta = scal[CG_BETA];
-  for (int i = blockIdx.x * CG_NT + threadIdx.x; i < n; i += gridDim.x * CG_NT) p[i] = z[i] + beta * p[i];
-}
-
 void launch_cg_init(int n, const double* g, const double* q, const double* dinv, double* r, double* z, double* p,
-                    double* scal, int* flag, double* part, double tol, int maxit, hipStream_t s) {
-  hipLaunchKernelGGL(cg_init_kernel, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, g, q, dinv, r, z, p, scal, flag, part,
-                     tol, maxit);
+                    double* qr, double* scal, int* flag, double* part, double tol, int maxit, hipStream_t s) {
+  if (n <= CG_SINGLE_MAX)
+    hipLaunchKernelGGL(cg_init_kernel<CG_NT1>, dim3(1), dim3(CG_NT1), 0, s, n, g, q, dinv, r, z, p, qr, scal, flag,
+                       part, tol, maxit);
+  else
+    hipLaunchKernelGGL(cg_init_kernel<CG_NT>, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, g, q, dinv, r, z, p, qr, scal,
+                       flag, part, tol, maxit);
   TN_CHECK_LAUNCH();
 }
-void launch_cg_dot(int n, const double* p, const double* q, double* scal, int* flag, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(cg_dot_kernel, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, p, q, scal, flag, part);
+void launch_cg_dir(int n, const double* z, const double* w, double* p, double* q, double* scal, int* flag,
+                   double* part, hipStream_t s) {
+  if (n <= CG_SINGLE_MAX)
+    hipLaunchKernelGGL(cg_dir_kernel<CG_NT1>, dim3(1), dim3(CG_NT1), 0, s, n, z, w, p, q, scal, flag, part);
+  else
+    hipLaunchKernelGGL(cg_dir_kernel<CG_NT>, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, z, w, p, q, scal, flag, part);
   TN_CHECK_LAUNCH();
 }
 void launch_cg_update(int n, double* x, const double* p, const double* q, double* r, double* z, const double* dinv,
                       double* scal, int* flag, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(cg_update_kernel, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, x, p, q, r, z, dinv, scal, flag,
-                     part);
-  TN_CHECK_LAUNCH();
-}
-void launch_cg_pupdate(int n, double* p, const double* z, const double* scal, const int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(cg_pupdate_kernel, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, p, z, scal, flag);
+  if (n <= CG_SINGLE_MAX)
+    hipLaunchKernelGGL(cg_update_kernel<CG_NT1>, dim3(1), dim3(CG_NT1), 0, s, n, x, p, q, r, z, dinv, scal, flag,
+                       part);
+  else
+    hipLaunchKernelGGL(cg_update_kernel<CG_NT>, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, x, p, q, r, z, dinv, scal,
+                       flag, part);
   TN_CHECK_LAUNCH();
 }
 
@@ -391,17 +502,22 @@ void launch_local_diag(int p, int n, int t, int Rl, int Rr, const double* L, con
 
 // ----------------------------------------------------------------------------- QR
 
-constexpr int QR_NT = 256;
+constexpr int QR_NT = 1024;
+constexpr size_t QR_LDS_BYTES = 160 * 1024 - 2048;  // gfx950: 160 KB of LDS per workgroup
 
+// LDS = true: the Householder vectors and the Q accumulation live in dynamic LDS.
+template <bool LDS>
 __global__ __launch_bounds__(QR_NT) void qr_kernel(int m, int n, const double* A, int lda, double* Q, int ldq,
                                                    double* R, int ldr, double* ws) {
+  extern __shared__ double dyn[];
   __shared__ double red[QR_NT / 64];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int c = m < n ? m : n;
-  double* W = ws;                  // m x n, column-major
-  double* Qc = ws + (long)m * n;   // m x c, column-major
-  double* tau = Qc + (long)m * c;  // c
-  double* diag = tau + c;          // c
+  double* base = LDS ? dyn : ws;
+  double* W = base;                  // m x n, column-major
+  double* Qc = base + (long)m * n;   // m x c, column-major
+  double* tau = Qc + (long)m * c;    // c
+  double* diag = tau + c;            // c
   for (long idx = tid; idx < (long)m * n; idx += QR_NT) {
     const int i = idx / n, j = idx % n;
     W[(long)j * m + i] = A[(long)i * lda + j];
@@ -469,7 +585,19 @@ __global__ __launch_bounds__(QR_NT) void qr_kernel(int m, int n, const double* A
 
 void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws,
                hipStream_t s) {
-  hipLaunchKernelGGL(qr_kernel, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+  const int c = m < n ? m : n;
+  const size_t bytes = ((size_t)m * n + (size_t)m * c + 2 * (size_t)c) * sizeof(double);
+  if (bytes <= QR_LDS_BYTES) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_BYTES);
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(qr_kernel<true>, dim3(1), dim3(QR_NT), bytes, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+  } else {
+    hipLaunchKernelGGL(qr_kernel<false>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+  }
   TN_CHECK_LAUNCH();
 }
 

@@ -32,6 +32,12 @@ struct GemmDesc {
   double alpha = 1.0, beta = 0.0;
   const int* skip = nullptr;
   double flops = 0.0;  // algorithmic flops of this launch (2 M N K per term), for profiling
+  // Split-K: with a partial buffer, groups with few output tiles split their
+  // (term, k) iteration space over several workgroups; partial tiles are summed
+  // in a fixed order by a second kernel, so results do not depend on timing.
+  int max_terms = 1;           // upper bound of terms per group (host knowledge)
+  double* partial = nullptr;   // device buffer for partial tiles
+  size_t partial_cap = 0;      // its size in doubles
 };
 
 void launch_gemm(const GemmDesc& g, hipStream_t s);
@@ -49,22 +55,27 @@ struct GemmProfile {
   double total_ms(double* total_flops);
 };
 void set_gemm_profile(GemmProfile* p);
+// Default split-K partial buffer for launches of the calling thread whose
+// descriptor names none (nullptr: no splitting).
+void set_gemm_splitk_buffer(double* p, size_t cap_doubles);
 
 // Device scalars of a local CG solve.
 enum CgScal { CG_RZ = 0, CG_PQ, CG_RR, CG_GG, CG_THR2, CG_RES, CG_BETA, CG_NSCAL };
 enum CgFlag { CG_DONE = 0, CG_ITERS, CG_MAXIT, CG_COUNTER, CG_NFLAG };
 
-// r = g - q; z = dinv * r; p = z; scalars rz, rr, gg; res = ||r|| / ||g||;
-// thr = max(0.1 res, tol/2) ||g||; done = (res <= tol/2) or maxit == 0.
+// Local preconditioned CG, one iteration = (w = B z), cg_dir, cg_update:
+//   init:   r = g - q (q = B x), z = dinv r, p = q_rec = 0, beta = 0; scalars rz, rr, gg;
+//           res = ||r|| / ||g||; thr = max(0.1 res, tol/2) ||g||; done = (res <= tol/2) or maxit == 0.
+//   dir:    p = z + beta p; q_rec = w + beta q_rec (= B p); pq = p . q_rec.
+//   update: x += a p; r -= a q_rec; z = dinv r (a = rz / pq); beta = rz_new / rz;
+//           done when ||r||^2 <= thr^2 or the iteration limit is reached.
+// Every kernel returns at once when done is set.
 void launch_cg_init(int n, const double* g, const double* q, const double* dinv, double* r, double* z, double* p,
-                    double* scal, int* flag, double* part, double tol, int maxit, hipStream_t s);
-// pq = p . q (skipped once done)
-void launch_cg_dot(int n, const double* p, const double* q, double* scal, int* flag, double* part, hipStream_t s);
-// x += a p, r -= a q, z = dinv r, beta, convergence flag (skipped once done)
+                    double* qr, double* scal, int* flag, double* part, double tol, int maxit, hipStream_t s);
+void launch_cg_dir(int n, const double* z, const double* w, double* p, double* q, double* scal, int* flag,
+                   double* part, hipStream_t s);
 void launch_cg_update(int n, double* x, const double* p, const double* q, double* r, double* z, const double* dinv,
                       double* scal, int* flag, double* part, hipStream_t s);
-// p = z + beta p (skipped once done)
-void launch_cg_pupdate(int n, double* p, const double* z, const double* scal, const int* flag, hipStream_t s);
 
 // Jacobi preconditioner: d[a][i][c] = sum over diagonal terms (b, e, v) of group i of
 // v * L[a][b][a] * Rt[c][e][c]; dinv = 1/d where d > 0 else 1.
