@@ -180,6 +180,37 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
   };
   P.n_ap = flatten(ap_a, ap_b, ap_v, &P.ap_beg, &P.ap_a, &P.ap_b, &P.ap_v, &P.ap_max);
   P.n_en = flatten(en_a, en_b, en_v, &P.en_beg, &P.en_a, &P.en_b, &P.en_v, &P.en_max);
+  // nonzero term lists (identical to the main lists for sparse plans)
+  if (!P.dense) {
+    P.sp_nslot = P.nslot;
+    P.sp_slot_b = P.slot_b;
+    P.sp_slot_i = P.slot_i;
+    P.sp_ap_beg = P.ap_beg;
+    P.sp_ap_a = P.ap_a;
+    P.sp_ap_b = P.ap_b;
+    P.sp_ap_v = P.ap_v;
+    P.sp_n_ap = P.n_ap;
+    P.sp_ap_max = P.ap_max;
+  } else {
+    std::vector<int> ssb, ssi;
+    int k2 = 0;
+    for (auto& kv : slot_of) {
+      kv.second = k2++;
+      ssb.push_back(kv.first.first);
+      ssi.push_back(kv.first.second);
+    }
+    P.sp_nslot = (int)ssb.size();
+    P.sp_slot_b = arena.upload(ssb, s);
+    P.sp_slot_i = arena.upload(ssi, s);
+    std::vector<std::vector<int>> sa(n), sbb(n);
+    std::vector<std::vector<double>> sv(n);
+    for (size_t t = 0; t < c.nnz(); ++t) {
+      sa[c.io[t]].push_back(slot_of[{c.b[t], c.ii[t]}]);
+      sbb[c.io[t]].push_back(c.e[t]);
+      sv[c.io[t]].push_back(c.v[t]);
+    }
+    P.sp_n_ap = flatten(sa, sbb, sv, &P.sp_ap_beg, &P.sp_ap_a, &P.sp_ap_b, &P.sp_ap_v, &P.sp_ap_max);
+  }
   // diagonal terms
   std::vector<std::vector<int>> db(n), de(n);
   std::vector<std::vector<double>> dv(n);
@@ -539,10 +570,12 @@ void Problem::ensure_workspace(int cap, int rho) {
   W->Ra = A(Nw * Nw);
   W->Wm = A(Nw * Nw);
   W->qrws = A(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw);
-  W->scal = A(CG_NSCAL);
+  W->scal = A(16);
+  W->fpart_cap = (size_t)1 << 22;
+  W->fpart = A(W->fpart_cap);
   W->splitk_cap = (size_t)1 << 22;
   W->splitk = A(W->splitk_cap);
-  W->part = A(3 * 512);
+  W->part = A(6 * 512);
   W->flag = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
   W->drank = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
   hip_check(hipMemset(W->flag, 0, sizeof(int) * 8), "memset flag");
@@ -702,7 +735,23 @@ struct Sweep {
                       st);
     apply(k, p, p, t, t, EA[k], X[k], EA[k + 1], W.q, nullptr);
     applies++;
-    launch_cg_init(N, W.g, W.q, W.dinv, W.r, W.z, W.p, W.w, W.scal, W.flag, W.part, o.tol, o.cg_maxit, st);
+    CgIterArgs a;
+    a.N = N;
+    a.x = X[k];
+    a.r = W.r;
+    a.z = W.z;
+    a.p = W.p;
+    a.q = W.w;
+    a.dinv = W.dinv;
+    a.scal = W.scal;
+    a.flag = W.flag;
+    a.parts = W.part;
+    a.maxit = o.cg_maxit;
+    a.n = n[k];
+    a.t = t;
+    a.nb_upd = cg_dir_blocks(N);
+    a.nb_dir = cg_dir_blocks(N);
+    launch_cg_init2(a, W.g, W.q, o.tol, st);
     auto readback = [&]() {
       hip_check(hipMemcpyAsync(W.host_pinned, W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flag readback");
       hip_check(hipMemcpyAsync(static_cast<char*>(W.host_pinned) + 64, W.scal + CG_RES, sizeof(double),
@@ -714,13 +763,53 @@ struct Sweep {
     const double res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
     if (!std::isfinite(res)) nan_seen = 1;
     int done = hint()[0];
+    FusedArgs f;
+    // fused evaluation from the nonzero lists: always for sparse plans; for dense
+    // plans when the per-apply work of the term lists stays small
+    const double sp_flops = 2.0 * pl.sp_n_ap * ((double)p * p * t + (double)p * t * t);
+    (void)sp_flops;
+    const bool fused = !pl.dense;
+    if (fused) {
+      f.L = EA[k];
+      f.x = W.z;
+      f.Rt = EA[k + 1];
+      f.partial = W.fpart;
+      f.p = p;
+      f.q = p;
+      f.s = t;
+      f.t = t;
+      f.Rl = R(k);
+      f.Rr = R(k + 1);
+      f.n = n[k];
+      f.slot_b = pl.sp_slot_b;
+      f.slot_i = pl.sp_slot_i;
+      f.beg = pl.sp_ap_beg;
+      f.ta = pl.sp_ap_a;
+      f.tb = pl.sp_ap_b;
+      f.tv = pl.sp_ap_v;
+      f.ksplit = fused_apply_splits(n[k], p, t, pl.sp_ap_max, W.fpart_cap);
+      f.skip = W.flag + CG_DONE;
+      a.ksplit = f.ksplit;
+      a.partial = W.fpart;
+      a.tiles_n = (t + 31) / 32;
+      a.ntiles = ((p + 31) / 32) * a.tiles_n;
+    } else {
+      a.ksplit = 0;
+      a.w = W.q;
+    }
+    const double apply_flops = 2.0 * p * p * t * pl.sp_nslot + 2.0 * p * t * t * pl.sp_n_ap;
     const int chunk = 8;
-    int launched = 0;
-    while (!done && launched < o.cg_maxit) {
-      for (int c = 0; c < chunk && launched < o.cg_maxit; ++c, ++launched) {
-        apply(k, p, p, t, t, EA[k], W.z, EA[k + 1], W.q, W.flag + CG_DONE);
-        launch_cg_dir(N, W.z, W.q, W.p, W.w, W.scal, W.flag, W.part, st);
-        launch_cg_update(N, X[k], W.p, W.w, W.r, W.z, W.dinv, W.scal, W.flag, W.part, st);
+    int kit = 0;
+    while (!done && kit <= o.cg_maxit) {
+      for (int c = 0; c < chunk && kit <= o.cg_maxit; ++c, ++kit) {
+        if (fused) {
+          launch_fused_apply(f, apply_flops, st);
+          fl.total += apply_flops;
+        } else {
+          apply(k, p, p, t, t, EA[k], W.z, EA[k + 1], W.q, W.flag + CG_DONE);
+        }
+        launch_cg_reduce_dir(a, kit, st);
+        launch_cg_update2(a, kit, st);
       }
       readback();
       done = hint()[0];

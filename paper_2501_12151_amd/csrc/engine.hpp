@@ -45,6 +45,11 @@ struct Plan {
   int n_en = 0, en_max = 1;
   int *dg_beg = nullptr, *dg_b = nullptr, *dg_e = nullptr;
   double* dg_v = nullptr;
+  // Term lists of the nonzeros (for dense plans: the alternative evaluation by
+  // the fused kernel, cheaper when the ranks next to this core are small).
+  int sp_nslot = 0, sp_n_ap = 0, sp_ap_max = 1;
+  int *sp_slot_b = nullptr, *sp_slot_i = nullptr, *sp_ap_beg = nullptr, *sp_ap_a = nullptr, *sp_ap_b = nullptr;
+  double* sp_ap_v = nullptr;
   int n_t1() const { return nslot; }
   int n_t2() const { return dense ? n * Rr : 0; }
 };
@@ -79,6 +84,8 @@ struct Workspace {
   double *scal = nullptr, *part = nullptr;
   double* splitk = nullptr;
   size_t splitk_cap = 0;
+  double* fpart = nullptr;  // fused-apply partial tiles
+  size_t fpart_cap = 0;
   int* flag = nullptr;
   int* drank = nullptr;
   void* host_pinned = nullptr;

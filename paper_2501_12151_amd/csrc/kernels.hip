@@ -470,6 +470,337 @@ void launch_cg_update(int n, double* x, const double* p, const double* q, double
   TN_CHECK_LAUNCH();
 }
 
+// ----------------------------------------------------------------------------- fused local apply
+
+// y partial tiles for a sparse operator core (every term a product of small blocks):
+//   part[z][i'][tile][32 x 32] = sum_{terms (slot, e, v) of group i' in split z}
+//                                v (L[rows, b, :] x[:, i, :]) Rt[cols, e, :]^T
+// The stage-1 product (rows of T1 = L_b x_i for this tile) is formed in LDS per
+// term and consumed at once.  Padded rows/cols are written as zeros.
+__global__ __launch_bounds__(256) void fused_apply_kernel(FusedArgs f) {
+  __shared__ double sA[32][33];
+  __shared__ double sB[32][33];
+  __shared__ double sT[32][33];
+  __shared__ double sR[32][33];
+  if (f.skip && *f.skip) return;
+  const int grp = blockIdx.y, tile = blockIdx.x, z = blockIdx.z;
+  const int m0 = (tile / f.tiles_n) * 32, n0 = (tile % f.tiles_n) * 32;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int lrow = lane % 16, lk = lane / 16;
+  const int tb0 = f.beg[grp], te0 = f.beg[grp + 1];
+  const int cnt = te0 - tb0;
+  const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
+  const int tb = tb0 + z * chunk;
+  const int te = tb + chunk < te0 ? tb + chunk : te0;
+  const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
+  d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int t = tb; t < te; ++t) {
+    const int slot = f.ta[t], e = f.tb[t];
+    const double v = f.tv[t];
+    const int b = f.slot_b[slot], i = f.slot_i[slot];
+    const double* Lb = f.L + (long)b * f.q;
+    const double* Xi = f.x + (long)i * f.s;
+    const double* Re = f.Rt + (long)e * f.s;
+    for (int s0 = 0; s0 < f.s; s0 += 32) {
+      d4_t tacc = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int q0 = 0; q0 < f.q; q0 += 32) {
+        for (int idx = tid; idx < 32 * 32; idx += 256) {
+          const int r = idx / 32, c = idx % 32;  // c fastest: contiguous in memory
+          const int gm = m0 + r, gk = q0 + c;
+          sA[c][r] = (gm < f.p && gk < f.q) ? Lb[gm * Lrow + gk] : 0.0;
+          const int gk2 = q0 + r, gn = s0 + c;
+          sB[r][c] = (gk2 < f.q && gn < f.s) ? Xi[gk2 * Xrow + gn] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 4) {
+          const double af = sA[kk + lk][wm * 16 + lrow];
+          const double bf = sB[kk + lk][wn * 16 + lrow];
+          tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, tacc, 0, 0, 0);
+        }
+        __syncthreads();
+      }
+      // T1 chunk (32 rows x 32 cols of s) -> sT[s][row], scaled by v; Rt chunk -> sR[s][col]
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) sT[wn * 16 + lrow][wm * 16 + 4 * qq + lk] = v * tacc[qq];
+      for (int idx = tid; idx < 32 * 32; idx += 256) {
+        const int r = idx / 32, c = idx % 32;  // r: output col (t), c: s index (contiguous)
+        const int gn = n0 + r, gk = s0 + c;
+        sR[c][r] = (gn < f.t && gk < f.s) ? Re[gn * Rrow + gk] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 32; kk += 4) {
+        const double af = sT[kk + lk][wm * 16 + lrow];
+        const double bf = sR[kk + lk][wn * 16 + lrow];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  double* Pt = f.partial + (((long)z * f.n + grp) * f.ntiles + tile) * 1024;
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + 4 * qq + lk) * 32 + wn * 16 + lrow] = acc[qq];
+}
+
+// Fast path of fused_apply_kernel for p, q, s, t <= 32 (one tile, one chunk of
+// each contracted index): the next term's operand tiles are loaded into
+// registers while the current term's two MFMA products run.
+__global__ __launch_bounds__(256) void fused_apply32_kernel(FusedArgs f) {
+  __shared__ double sA[32][33];
+  __shared__ double sB[32][33];
+  __shared__ double sT[32][33];
+  __shared__ double sR[32][33];
+  if (f.skip && *f.skip) return;
+  const int grp = blockIdx.y, z = blockIdx.z;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int lrow = lane % 16, lk = lane / 16;
+  const int tb0 = f.beg[grp], te0 = f.beg[grp + 1];
+  const int cnt = te0 - tb0;
+  const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
+  const int tb = tb0 + z * chunk;
+  const int te = tb + chunk < te0 ? tb + chunk : te0;
+  const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
+  // thread -> 4 elements of each 32 x 32 tile: r = idx / 32, c = idx % 32, idx = tid + 256 j
+  double la[4], xb[4], rb[4], vcur = 0.0;
+  auto load = [&](int t, double (&l)[4], double (&x)[4], double (&rr)[4], double& v) {
+    const int slot = f.ta[t], e = f.tb[t];
+    v = f.tv[t];
+    const double* Lb = f.L + (long)f.slot_b[slot] * f.q;
+    const double* Xi = f.x + (long)f.slot_i[slot] * f.s;
+    const double* Re = f.Rt + (long)e * f.s;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = tid + 256 * j, r = idx / 32, c = idx % 32;
+      l[j] = (r < f.p && c < f.q) ? Lb[r * Lrow + c] : 0.0;
+      x[j] = (r < f.q && c < f.s) ? Xi[r * Xrow + c] : 0.0;
+      rr[j] = (r < f.t && c < f.s) ? Re[r * Rrow + c] : 0.0;
+    }
+  };
+  if (tb < te) load(tb, la, xb, rb, vcur);
+  d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int t = tb; t < te; ++t) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = tid + 256 * j, r = idx / 32, c = idx % 32;
+      sA[c][r] = la[j];  // A = L rows (m = r) x q (k = c)
+      sB[r][c] = xb[j];  // B = x (k = r) x s (n = c)
+      sR[c][r] = rb[j];  // B' = Rt^T: k = s (c), n = t (r)
+    }
+    const double v = vcur;
+    if (t + 1 < te) load(t + 1, la, xb, rb, vcur);
+    __syncthreads();
+    d4_t tacc = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4)
+      tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[kk + lk][wm * 16 + lrow], sB[kk + lk][wn * 16 + lrow], tacc, 0,
+                                                  0, 0);
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) sT[wn * 16 + lrow][wm * 16 + 4 * qq + lk] = v * tacc[qq];
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[kk + lk][wm * 16 + lrow], sR[kk + lk][wn * 16 + lrow], acc, 0, 0,
+                                                 0);
+    __syncthreads();
+  }
+  double* Pt = f.partial + ((long)z * f.n + grp) * 1024;
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + 4 * qq + lk) * 32 + wn * 16 + lrow] = acc[qq];
+}
+
+int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles) {
+  const int ntiles = ((p + 31) / 32) * ((t + 31) / 32);
+  long ks = (128 + (long)n * ntiles - 1) / ((long)n * ntiles);
+  ks = std::min<long>(ks, std::max(1, max_terms / 2));
+  const long fit = (long)(cap_doubles / ((size_t)n * ntiles * 1024));
+  if (fit < 1) throw Error(TNFEM_EINVAL, "fused apply: partial buffer too small");
+  ks = std::min<long>(ks, fit);
+  return (int)std::max<long>(ks, 1);
+}
+
+static hipEvent_t* prof_begin(hipStream_t s);
+static void prof_end(hipEvent_t* pair, double flops, hipStream_t s);
+
+void launch_fused_apply(FusedArgs f, double flops, hipStream_t s) {
+  f.tiles_n = (f.t + 31) / 32;
+  f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
+  hipEvent_t* ev = prof_begin(s);
+  if (f.p <= 32 && f.q <= 32 && f.s <= 32 && f.t <= 32)
+    hipLaunchKernelGGL(fused_apply32_kernel, dim3(1, f.n, f.ksplit), dim3(256), 0, s, f);
+  else
+    hipLaunchKernelGGL(fused_apply_kernel, dim3(f.ntiles, f.n, f.ksplit), dim3(256), 0, s, f);
+  prof_end(ev, flops, s);
+  TN_CHECK_LAUNCH();
+}
+
+// ----------------------------------------------------------------------------- CG iteration kernels
+// Block partials: parts[PART_RZ + (k % 2) * CG_MAXB + blk] etc.; scalars scal[CG_RZ0 + k % 2].
+
+constexpr int PART_RZ = 0, PART_RR = 2 * CG_MAXB, PART_PQ = 4 * CG_MAXB;
+
+__device__ inline double sum_parts(const double* a, int nb) {
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += a[b];
+  return s;
+}
+
+// w = sum of split partials (or w given directly); p = z + beta p; q = w + beta q; block partials of p.q.
+// First checks convergence of iteration k from the update's partials.
+__global__ __launch_bounds__(256) void cg_reduce_dir_kernel(CgIterArgs a, int k) {
+  __shared__ double red[4];
+  if (a.flag[CG_DONE]) return;
+  const int nb = a.nb_upd;
+  const int par = k & 1;
+  const double rr = sum_parts(a.parts + PART_RR + par * CG_MAXB, nb);
+  if (rr <= a.scal[CG_THR2] || k >= a.maxit) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.flag[CG_DONE] = 1;
+      a.flag[CG_ITERS] = k;
+    }
+    return;
+  }
+  const double rz = sum_parts(a.parts + PART_RZ + par * CG_MAXB, nb);
+  const double beta = (k == 0) ? 0.0 : rz / a.scal[CG_RZ0 + (par ^ 1)];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[CG_RZ0 + par] = rz;
+    a.flag[CG_ITERS] = k;
+  }
+  double loc = 0.0;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < a.N; e += gridDim.x * 256) {
+    double w;
+    if (a.ksplit > 0) {
+      // e = (row * n + grp) * t + col
+      const int col = e % a.t, grp = (e / a.t) % a.n, row = e / (a.t * a.n);
+      const int tile = (row / 32) * a.tiles_n + col / 32;
+      const long stride = (long)a.n * a.ntiles * 1024;
+      const double* src = a.partial + ((long)grp * a.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
+      w = 0.0;
+      int zz = 0;
+      for (; zz + 4 <= a.ksplit; zz += 4) {
+        const double w0 = src[zz * stride], w1 = src[(zz + 1) * stride];
+        const double w2 = src[(zz + 2) * stride], w3 = src[(zz + 3) * stride];
+        w += w0;
+        w += w1;
+        w += w2;
+        w += w3;
+      }
+      for (; zz < a.ksplit; ++zz) w += src[zz * stride];
+    } else {
+      w = a.w[e];
+    }
+    const double pi = a.z[e] + beta * a.p[e];
+    const double qi = w + beta * a.q[e];
+    a.p[e] = pi;
+    a.q[e] = qi;
+    loc += pi * qi;
+  }
+  const double tot = block_sum<256>(loc, red);
+  if (threadIdx.x == 0) a.parts[PART_PQ + blockIdx.x] = tot;
+}
+
+// x += alpha p; r -= alpha q; z = dinv r; block partials of r.z and r.r for iteration k + 1.
+__global__ __launch_bounds__(256) void cg_update2_kernel(CgIterArgs a, int k) {
+  __shared__ double red[4];
+  if (a.flag[CG_DONE]) return;
+  const int nb = gridDim.x;
+  const double pq = sum_parts(a.parts + PART_PQ, a.nb_dir);
+  if (!(pq > 0.0)) {  // breakdown: stop without updating
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.flag[CG_DONE] = 2;
+      a.flag[CG_ITERS] = k;
+    }
+    return;
+  }
+  const double alpha = a.scal[CG_RZ0 + (k & 1)] / pq;
+  double lrz = 0.0, lrr = 0.0;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < a.N; e += nb * 256) {
+    a.x[e] += alpha * a.p[e];
+    const double ri = a.r[e] - alpha * a.q[e];
+    const double zi = ri * a.dinv[e];
+    a.r[e] = ri;
+    a.z[e] = zi;
+    lrz += ri * zi;
+    lrr += ri * ri;
+  }
+  const double trz = block_sum<256>(lrz, red);
+  const double trr = block_sum<256>(lrr, red);
+  const int par = (k + 1) & 1;
+  if (threadIdx.x == 0) {
+    a.parts[PART_RZ + par * CG_MAXB + blockIdx.x] = trz;
+    a.parts[PART_RR + par * CG_MAXB + blockIdx.x] = trr;
+  }
+}
+
+// r = g - Bx; z = dinv r; p = q = 0; block partials of r.z, r.r (parity 0);
+// the last block also derives res, thr and the skip decision for the host.
+__global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const double* g, const double* bx, double tol) {
+  __shared__ double red[4];
+  __shared__ bool am_last;
+  double lrz = 0.0, lrr = 0.0, lgg = 0.0;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < a.N; e += gridDim.x * 256) {
+    const double gi = g[e];
+    const double ri = gi - bx[e];
+    const double zi = ri * a.dinv[e];
+    a.r[e] = ri;
+    a.z[e] = zi;
+    a.p[e] = 0.0;
+    a.q[e] = 0.0;
+    lrz += ri * zi;
+    lrr += ri * ri;
+    lgg += gi * gi;
+  }
+  const double trz = block_sum<256>(lrz, red);
+  const double trr = block_sum<256>(lrr, red);
+  const double tgg = block_sum<256>(lgg, red);
+  if (threadIdx.x == 0) {
+    a.parts[PART_RZ + blockIdx.x] = trz;
+    a.parts[PART_RR + blockIdx.x] = trr;
+    a.parts[PART_PQ + blockIdx.x] = tgg;  // scratch for the gg total
+    __threadfence();
+    am_last = atomicAdd(&a.flag[CG_COUNTER], 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!am_last || threadIdx.x != 0) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  const double rr = sum_parts(a.parts + PART_RR, nb), gg = sum_parts(a.parts + PART_PQ, nb);
+  const double gn = sqrt(gg);
+  const double res = gg > 0.0 ? sqrt(rr) / gn : (rr == 0.0 ? 0.0 : 1.0);
+  const double thr = fmax(0.1 * res, 0.5 * tol) * gn;
+  a.scal[CG_GG] = gg;
+  a.scal[CG_RES] = res;
+  a.scal[CG_THR2] = thr * thr;
+  a.flag[CG_ITERS] = 0;
+  a.flag[CG_DONE] = (res <= 0.5 * tol || a.maxit <= 0) ? 1 : 0;
+  a.flag[CG_COUNTER] = 0;
+}
+
+int cg_vec_blocks(int n) {
+  int b = (n + 256 * 8 - 1) / (256 * 8);
+  return b < 1 ? 1 : (b > CG_MAXB ? CG_MAXB : b);
+}
+
+int cg_dir_blocks(int n) {
+  int b = (n + 255) / 256;
+  return b < 1 ? 1 : (b > CG_MAXB ? CG_MAXB : b);
+}
+
+void launch_cg_init2(const CgIterArgs& a, const double* g, const double* bx, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(cg_init2_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, g, bx, tol);
+  TN_CHECK_LAUNCH();
+}
+void launch_cg_reduce_dir(const CgIterArgs& a, int k, hipStream_t s) {
+  hipLaunchKernelGGL(cg_reduce_dir_kernel, dim3(a.nb_dir), dim3(256), 0, s, a, k);
+  TN_CHECK_LAUNCH();
+}
+void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s) {
+  hipLaunchKernelGGL(cg_update2_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, k);
+  TN_CHECK_LAUNCH();
+}
+
 // ----------------------------------------------------------------------------- local diagonal
 
 __global__ void local_diag_kernel(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt,

@@ -77,6 +77,49 @@ void launch_cg_dir(int n, const double* z, const double* w, double* p, double* q
 void launch_cg_update(int n, double* x, const double* p, const double* q, double* r, double* z, const double* dinv,
                       double* scal, int* flag, double* part, hipStream_t s);
 
+// Fused local apply for operator cores given as term lists: writes split partial
+// tiles part[z][i'][tile][32 x 32] of y = (L x A_k x Rt) x (see kernels.hip).
+struct FusedArgs {
+  const double* L = nullptr;
+  const double* x = nullptr;
+  const double* Rt = nullptr;
+  double* partial = nullptr;
+  int p = 0, q = 0, s = 0, t = 0, Rl = 0, Rr = 0, n = 0;
+  const int* slot_b = nullptr;
+  const int* slot_i = nullptr;
+  const int* beg = nullptr;
+  const int* ta = nullptr;
+  const int* tb = nullptr;
+  const double* tv = nullptr;
+  int ksplit = 1, tiles_n = 1, ntiles = 1;
+  const int* skip = nullptr;
+};
+int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles);
+void launch_fused_apply(FusedArgs f, double flops, hipStream_t s);
+
+// Local PCG with per-block partial sums (no atomics inside the iteration):
+// iteration k = apply (w = B z) -> reduce_dir(k) -> update2(k).
+enum { CG_RZ0 = 8 };  // scal[CG_RZ0 + k % 2] = r.z of iteration k
+struct CgIterArgs {
+  int N = 0;
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  const double* dinv = nullptr;
+  const double* w = nullptr;        // apply output when ksplit == 0
+  const double* partial = nullptr;  // fused-apply partial tiles when ksplit > 0
+  int ksplit = 0, n = 0, t = 0, tiles_n = 1, ntiles = 1;
+  double* scal = nullptr;
+  int* flag = nullptr;
+  double* parts = nullptr;  // 5 * 512 doubles
+  int maxit = 0;
+  int nb_upd = 1;  // blocks of init / update (partials of r.z, r.r)
+  int nb_dir = 1;  // blocks of reduce_dir (partials of p.q)
+};
+int cg_vec_blocks(int n);
+int cg_dir_blocks(int n);
+void launch_cg_init2(const CgIterArgs& a, const double* g, const double* bx, double tol, hipStream_t s);
+void launch_cg_reduce_dir(const CgIterArgs& a, int k, hipStream_t s);
+void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s);
+
 // Jacobi preconditioner: d[a][i][c] = sum over diagonal terms (b, e, v) of group i of
 // v * L[a][b][a] * Rt[c][e][c]; dinv = 1/d where d > 0 else 1.
 void launch_local_diag(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* dg_beg,
