@@ -91,9 +91,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
+    ap.add_argument("--slots", type=int, default=8, help="serving: worker slots")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is not sharded across GPUs.",
@@ -102,6 +104,9 @@ def main():
 
     from paper_2501_12151_amd import tnfem
 
+    if args.workload == "serving":
+        serving(args)
+        return
     wl = WORKLOADS[args.workload]
     prob = problem_for(args.workload)
     opts = dict(wl["opts"])
@@ -174,6 +179,61 @@ def main():
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serving(args):
+    """Serving stream: Poisson arrivals of mixed 2D/3D requests; throughput and p50/p99 latency."""
+    from paper_2501_12151_amd import tnfem, workloads
+
+    def opts_for(cap):
+        return dict(rank_cap=cap, tol=1e-6, max_sweeps=12)
+
+    # closed loop: all requests at once -> saturation throughput
+    sat_reqs = workloads.serving_stream(min(64, args.requests), seed=1, rate=1.0)
+    srv = tnfem.Server(0, slots=args.slots)
+    t0 = time.perf_counter()
+    ts = [srv.submit(p, **opts_for(c)) for _, p, c in sat_reqs]
+    for t in ts:
+        srv.poll(t)
+    sat = len(ts) / (time.perf_counter() - t0)
+    srv.close()
+    print(f"closed loop: {len(ts)} requests, {sat:.2f} solves/s", file=sys.stderr, flush=True)
+    rate = 0.8 * sat
+    reqs = workloads.serving_stream(args.requests, seed=0, rate=rate)
+    srv = tnfem.Server(0, slots=args.slots)
+    lat, tickets = [], []
+    t0 = time.perf_counter()
+    for arrival, p, c in reqs:
+        now = time.perf_counter() - t0
+        if arrival > now:
+            time.sleep(arrival - now)
+        tickets.append(srv.submit(p, **opts_for(c)))
+    for t in tickets:
+        _, st, rc, l = srv.poll(t)
+        lat.append(l)
+    elapsed = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    out = {
+        "metric": METRIC,
+        "value": len(tickets) / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(tickets),
+        "warmup": 0,
+        "ms_per_step": 1e3 * elapsed / len(tickets),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream: {len(tickets)} requests, Poisson arrivals at 0.8 x closed-loop "
+                               f"rate ({rate:.2f}/s), 2D/3D, levels 6..10, caps 32..64, {args.slots} slots",
+                   "closed_loop_solves_per_s": sat},
+        "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
+        "server": info,
     }
     print(json.dumps(out), flush=True)
 

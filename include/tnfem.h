@@ -157,6 +157,37 @@ int tnfem_problem_info(const tnfem_problem* p, int* ncores, int* modes, int* mpo
  * is filled. */
 int tnfem_solve(tnfem_problem* p, const tnfem_solve_opts* opts, tnfem_tt** u_out, tnfem_solve_stats* stats);
 
+/* ---------------------------------------------------------------- serving
+ * A server runs many solves on one device at once.  Requests are queued at
+ * submission; each of `slots` worker slots (its own HIP stream) takes the oldest
+ * queued request, assembles and uploads its problem, and starts the solve as soon
+ * as the request's device bytes (problem + workspace) fit in the HBM budget next
+ * to the running requests, so requests arriving while others run are admitted as
+ * slots and memory free up and their work overlaps on the device.  Requests share
+ * no device data: a result is the same alone and in a mix.  Latency is measured
+ * from submission to completion.  hbm_budget_bytes = 0 means 80% of the free
+ * device memory at creation.  A request larger than the whole budget fails with
+ * TNFEM_EBUDGET.  Calls are thread safe. */
+typedef struct tnfem_server tnfem_server;
+typedef struct {
+  int queued, running, peak_running;
+  long long completed;
+  size_t bytes_in_use, peak_bytes, budget_bytes;
+} tnfem_server_state;
+
+int tnfem_server_create(int device, int slots, size_t hbm_budget_bytes, tnfem_server** out);
+/* Copies desc and opts (NULL opts: defaults); *ticket identifies the request. */
+int tnfem_server_submit(tnfem_server* s, const tnfem_problem_desc* desc, const tnfem_solve_opts* opts,
+                        long long* ticket);
+/* Result of a request: TNFEM_EBUSY while it is not finished (wait = 0), else the
+ * solve's status; on TNFEM_OK / TNFEM_ENOTCONV *u_out receives the solution (caller
+ * destroys it).  latency_s = completion - submission.  A ticket is returned once. */
+int tnfem_server_poll(tnfem_server* s, long long ticket, int wait, tnfem_tt** u_out, tnfem_solve_stats* stats,
+                      double* latency_s);
+int tnfem_server_info(tnfem_server* s, tnfem_server_state* info);
+/* Stops the workers after their running requests; queued requests are dropped. */
+int tnfem_server_destroy(tnfem_server* s);
+
 /* ---------------------------------------------------------------- TT objects */
 
 /* Host TT from caller cores (concatenated row-major cores, doubles). */

@@ -19,9 +19,6 @@ struct tnfem_problem {
   tnfem_ctx* ctx;
   int device;
 };
-struct tnfem_tt {
-  tnfem::HostTT t;
-};
 
 namespace tnfem {
 static thread_local std::string g_last_error;

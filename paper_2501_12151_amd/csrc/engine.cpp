@@ -37,6 +37,7 @@ DevArena::~DevArena() { release_all(); }
 void DevArena::release_all() {
   for (void* p : ptrs_) (void)hipFree(p);
   ptrs_.clear();
+  bytes_ = 0;
 }
 
 void* DevArena::alloc(size_t bytes) {
@@ -44,6 +45,7 @@ void* DevArena::alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
   hip_check(hipMalloc(&p, bytes), "hipMalloc");
   ptrs_.push_back(p);
+  bytes_ += bytes;
   return p;
 }
 
@@ -518,64 +520,89 @@ static void gemm_plain(int m, int n, int k, const double* A, long lda, bool tran
 
 // ----------------------------------------------------------------------------- workspace
 
+// Lays out the workspace of a problem for (cap, rho); `A` returns a buffer of the
+// given number of doubles (or counts them when only the size is wanted).
+template <class Alloc>
+static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, Alloc A) {
+  const int K = P.K;
+  const size_t maxn = (size_t)P.maxn, Rmax = (size_t)P.Rmax, smax = (size_t)P.smax;
+  const size_t rc = (size_t)std::max(cap, rho);
+  const size_t core = rc * maxn * rc;
+  const size_t zcore = (size_t)rho * maxn * rho;
+  const size_t M = rc * maxn, Nw = rc + rho;
+  W.X.clear();
+  W.Z.clear();
+  W.EA.clear();
+  W.Eb.clear();
+  W.EzA.clear();
+  W.Ezb.clear();
+  for (int k = 0; k < K; ++k) {
+    W.X.push_back(A(core));
+    W.Z.push_back(A(std::max(zcore, core)));
+  }
+  W.Xspare = A(core);
+  W.Zspare = A(std::max(zcore, core));
+  for (int k = 0; k <= K; ++k) {
+    W.EA.push_back(A(rc * Rmax * rc));
+    W.Eb.push_back(A(rc * smax));
+    W.EzA.push_back(A((size_t)rho * Rmax * rc));
+    W.Ezb.push_back(A((size_t)rho * smax));
+  }
+  W.T1 = A(P.t1max_slots * rc * rc);
+  W.T2 = A(P.t2max_slots * rc * rc);
+  W.g = A(core);
+  W.r = A(core);
+  W.z = A(core);
+  W.p = A(core);
+  W.q = A(core);
+  W.w = A(core);
+  W.dinv = A(core);
+  W.Tb = A(rc * maxn * smax);
+  W.gz = A(core);
+  W.yz = A(core);
+  W.ge = A(core);
+  W.ye = A(core);
+  W.Qx = A(M * Nw);
+  W.Rx = A(Nw * Nw);
+  W.UR = A(Nw * Nw);
+  W.S = A(Nw);
+  W.V = A(Nw * Nw);
+  W.Ur = A(M * Nw);
+  W.SVt = A(Nw * Nw);
+  W.Vt = A(Nw * Nw);
+  W.xT = A(M * Nw);
+  W.xt = A(M * Nw);
+  W.aug = A(M * Nw);
+  W.Qa = A(M * Nw);
+  W.Ra = A(Nw * Nw);
+  W.Wm = A(Nw * Nw);
+  W.qrws = A(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw);
+  W.scal = A(16);
+  W.fpart_cap = (size_t)1 << 22;
+  W.fpart = A(W.fpart_cap);
+  W.splitk_cap = (size_t)1 << 22;
+  W.splitk = A(W.splitk_cap);
+  W.part = A(6 * 512);
+}
+
+size_t Problem::workspace_bytes(int cap, int rho) const {
+  Workspace W;
+  size_t total = 0;
+  layout_workspace(*this, W, cap, rho, [&](size_t d) {
+    total += std::max<size_t>(d, 1) * 8;
+    return static_cast<double*>(nullptr);
+  });
+  return total + 64 + 4096;
+}
+
 void Problem::ensure_workspace(int cap, int rho) {
   if (ws && ws->cap >= cap && ws->rho >= rho) return;
   ws.reset();
   auto W = std::make_unique<Workspace>();
   W->cap = cap;
   W->rho = rho;
-  const size_t rc = (size_t)std::max(cap, rho);
-  const size_t core = rc * maxn * rc;
-  const size_t zcore = (size_t)rho * maxn * rho;
-  const size_t M = rc * maxn, Nw = rc + rho;
-  auto A = [&](size_t doubles) { return static_cast<double*>(W->arena.alloc(std::max<size_t>(doubles, 1) * 8)); };
-  for (int k = 0; k < K; ++k) {
-    W->X.push_back(A(core));
-    W->Z.push_back(A(std::max(zcore, core)));
-  }
-  W->Xspare = A(core);
-  W->Zspare = A(std::max(zcore, core));
-  for (int k = 0; k <= K; ++k) {
-    W->EA.push_back(A(rc * Rmax * rc));
-    W->Eb.push_back(A(rc * smax));
-    W->EzA.push_back(A((size_t)rho * Rmax * rc));
-    W->Ezb.push_back(A((size_t)rho * smax));
-  }
-  W->T1 = A(t1max_slots * rc * rc);
-  W->T2 = A(t2max_slots * rc * rc);
-  W->g = A(core);
-  W->r = A(core);
-  W->z = A(core);
-  W->p = A(core);
-  W->q = A(core);
-  W->w = A(core);
-  W->dinv = A(core);
-  W->Tb = A(rc * maxn * smax);
-  W->gz = A(core);
-  W->yz = A(core);
-  W->ge = A(core);
-  W->ye = A(core);
-  W->Qx = A(M * Nw);
-  W->Rx = A(Nw * Nw);
-  W->UR = A(Nw * Nw);
-  W->S = A(Nw);
-  W->V = A(Nw * Nw);
-  W->Ur = A(M * Nw);
-  W->SVt = A(Nw * Nw);
-  W->Vt = A(Nw * Nw);
-  W->xT = A(M * Nw);
-  W->xt = A(M * Nw);
-  W->aug = A(M * Nw);
-  W->Qa = A(M * Nw);
-  W->Ra = A(Nw * Nw);
-  W->Wm = A(Nw * Nw);
-  W->qrws = A(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw);
-  W->scal = A(16);
-  W->fpart_cap = (size_t)1 << 22;
-  W->fpart = A(W->fpart_cap);
-  W->splitk_cap = (size_t)1 << 22;
-  W->splitk = A(W->splitk_cap);
-  W->part = A(6 * 512);
+  layout_workspace(*this, *W, cap, rho,
+                   [&](size_t d) { return static_cast<double*>(W->arena.alloc(std::max<size_t>(d, 1) * 8)); });
   W->flag = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
   W->drank = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
   hip_check(hipMemset(W->flag, 0, sizeof(int) * 8), "memset flag");

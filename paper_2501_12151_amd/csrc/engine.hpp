@@ -21,9 +21,11 @@ class DevArena {
   template <class T>
   T* upload(const std::vector<T>& v, hipStream_t s);
   void release_all();
+  size_t bytes() const { return bytes_; }
 
  private:
   std::vector<void*> ptrs_;
+  size_t bytes_ = 0;
 };
 
 // Contraction plan of one operator core in one chain orientation.
@@ -110,6 +112,7 @@ struct Problem {
   DevArena arena;
   std::unique_ptr<Workspace> ws;
   void ensure_workspace(int cap, int rho);
+  size_t workspace_bytes(int cap, int rho) const;  // device bytes ensure_workspace would allocate
 };
 
 // Host TT object.
@@ -132,3 +135,8 @@ void dev_env_update(Problem& P, const Plan& pl, int p, int q, int s, int t, cons
 int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_stats& st);
 
 }  // namespace tnfem
+
+// Host TT handed out through the C ABI.
+struct tnfem_tt {
+  tnfem::HostTT t;
+};

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <mutex>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -919,12 +920,11 @@ void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, doubl
   const int c = m < n ? m : n;
   const size_t bytes = ((size_t)m * n + (size_t)m * c + 2 * (size_t)c) * sizeof(double);
   if (bytes <= QR_LDS_BYTES) {
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_kernel<true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_BYTES);
-      attr_set = true;
-    }
+    });
     hipLaunchKernelGGL(qr_kernel<true>, dim3(1), dim3(QR_NT), bytes, s, m, n, A, lda, Q, ldq, R, ldr, ws);
   } else {
     hipLaunchKernelGGL(qr_kernel<false>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);

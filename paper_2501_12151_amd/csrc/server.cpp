@@ -1,0 +1,281 @@
+// Continuous-batching request server: elasticity solves of different sizes,
+// materials and loads share one GPU.
+//
+// A request is queued at submission.  Each worker slot owns a HIP stream (one
+// context); a free slot takes the oldest queued request, assembles and uploads
+// its problem, computes the device bytes its solve will hold (problem +
+// workspace) and is admitted as soon as that fits in the HBM budget next to the
+// requests already running.  Running requests' kernels are on different
+// streams, so their work overlaps on the device; nothing is shared between
+// requests, so a result does not depend on what else runs.  Latency is measured
+// from submission to completion.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "common.hpp"
+#include "engine.hpp"
+
+namespace tnfem {
+
+struct Request {
+  long long id = 0;
+  tnfem_problem_desc desc{};
+  std::vector<double> layer;
+  tnfem_solve_opts opts{};
+  std::chrono::steady_clock::time_point t_submit, t_done;
+  int state = 0;  // 0 queued, 1 running, 2 done
+  int rc = TNFEM_OK;
+  std::string error;
+  HostTT result;
+  tnfem_solve_stats stats{};
+  size_t bytes = 0;
+};
+
+class Server {
+ public:
+  Server(int device, int slots, size_t budget) : device_(device), budget_(budget) {
+    for (int i = 0; i < slots; ++i) workers_.emplace_back([this] { worker(); });
+  }
+
+  ~Server() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_work_.notify_all();
+    cv_budget_.notify_all();
+    for (auto& t : workers_) t.join();
+  }
+
+  long long submit(const tnfem_problem_desc& d, const tnfem_solve_opts& o) {
+    auto r = std::make_unique<Request>();
+    r->desc = d;
+    if (d.layer_E && d.n_layer_E > 0) {
+      r->layer.assign(d.layer_E, d.layer_E + d.n_layer_E);
+      r->desc.layer_E = r->layer.data();
+    }
+    r->opts = o;
+    r->t_submit = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lk(mu_);
+    r->id = ++next_id_;
+    const long long id = r->id;
+    queue_.push_back(r.get());
+    all_[id] = std::move(r);
+    cv_work_.notify_one();
+    return id;
+  }
+
+  // Returns nullptr if unknown; blocks until done when wait is set.
+  std::unique_ptr<Request> take(long long id, bool wait, bool* busy) {
+    std::unique_lock<std::mutex> lk(mu_);
+    *busy = false;
+    auto it = all_.find(id);
+    if (it == all_.end()) return nullptr;
+    if (it->second->state != 2) {
+      if (!wait) {
+        *busy = true;
+        return nullptr;
+      }
+      cv_done_.wait(lk, [&] { return it->second->state == 2; });
+    }
+    std::unique_ptr<Request> r = std::move(it->second);
+    all_.erase(it);
+    return r;
+  }
+
+  void info(tnfem_server_state* out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    out->queued = (int)queue_.size();
+    out->running = running_;
+    out->peak_running = peak_running_;
+    out->completed = completed_;
+    out->bytes_in_use = in_use_;
+    out->peak_bytes = peak_bytes_;
+    out->budget_bytes = budget_;
+  }
+
+ private:
+  void worker() {
+    Context ctx;
+    ctx.device = device_;
+    if (hipSetDevice(device_) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx.stream, hipStreamNonBlocking) != hipSuccess) {
+      return;
+    }
+    ctx.own_stream = true;
+    for (;;) {
+      Request* r = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_work_.wait(lk, [&] { return stop_ || !queue_.empty(); });
+        if (stop_) break;
+        r = queue_.front();
+        queue_.pop_front();
+        r->state = 1;
+      }
+      run(ctx, r);
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        r->state = 2;
+        r->t_done = std::chrono::steady_clock::now();
+        ++completed_;
+      }
+      cv_done_.notify_all();
+    }
+    (void)hipStreamSynchronize(ctx.stream);
+    if (ctx.scratch) (void)hipFree(ctx.scratch);
+    if (ctx.splitk) (void)hipFree(ctx.splitk);
+    (void)hipStreamDestroy(ctx.stream);
+  }
+
+  void run(Context& ctx, Request* r) {
+    std::unique_ptr<Problem> P;
+    size_t bytes = 0;
+    bool admitted = false;
+    try {
+      P = make_problem(&ctx, r->desc);
+      const int rho = std::max(r->opts.rho, 1);
+      bytes = P->arena.bytes() + P->workspace_bytes(r->opts.rank_cap, rho);
+      if (bytes > budget_) fail(TNFEM_EBUDGET, "request needs %zu device bytes, budget is %zu", bytes, budget_);
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_budget_.wait(lk, [&] { return stop_ || in_use_ + bytes <= budget_; });
+        if (stop_) fail(TNFEM_EBUSY, "server stopped");
+        in_use_ += bytes;
+        peak_bytes_ = std::max(peak_bytes_, in_use_);
+        ++running_;
+        peak_running_ = std::max(peak_running_, running_);
+        admitted = true;
+      }
+      r->bytes = bytes;
+      r->rc = run_solve(*P, r->opts, r->result, r->stats);
+    } catch (const Error& e) {
+      r->rc = e.code;
+      r->error = e.what();
+    } catch (const std::exception& e) {
+      r->rc = TNFEM_EINVAL;
+      r->error = e.what();
+    }
+    P.reset();  // frees the request's device memory before releasing its budget
+    if (admitted) {
+      std::lock_guard<std::mutex> lk(mu_);
+      in_use_ -= bytes;
+      --running_;
+    }
+    cv_budget_.notify_all();
+  }
+
+  int device_;
+  size_t budget_;
+  std::mutex mu_;
+  std::condition_variable cv_work_, cv_done_, cv_budget_;
+  std::deque<Request*> queue_;
+  std::map<long long, std::unique_ptr<Request>> all_;
+  std::vector<std::thread> workers_;
+  long long next_id_ = 0;
+  bool stop_ = false;
+  size_t in_use_ = 0, peak_bytes_ = 0;
+  int running_ = 0, peak_running_ = 0;
+  long long completed_ = 0;
+};
+
+}  // namespace tnfem
+
+struct tnfem_server {
+  std::unique_ptr<tnfem::Server> s;
+};
+
+template <class F>
+static int guarded_s(F&& f) {
+  try {
+    return f();
+  } catch (const tnfem::Error& e) {
+    tnfem::set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    tnfem::set_last_error(e.what());
+    return TNFEM_EINVAL;
+  }
+}
+
+extern "C" {
+
+int tnfem_server_create(int device, int slots, size_t hbm_budget_bytes, tnfem_server** out) {
+  return guarded_s([&]() -> int {
+    if (!out) tnfem::fail(TNFEM_EINVAL, "out is NULL");
+    if (slots < 1 || slots > 64) tnfem::fail(TNFEM_EINVAL, "slots must be in [1, 64]");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) tnfem::fail(TNFEM_EDEVICE, "no HIP device");
+    if (device < 0 || device >= count) tnfem::fail(TNFEM_EINVAL, "device out of range");
+    size_t budget = hbm_budget_bytes;
+    if (budget == 0) {
+      size_t free_b = 0, total_b = 0;
+      tnfem::hip_check(hipSetDevice(device), "hipSetDevice");
+      tnfem::hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      budget = (size_t)(0.8 * (double)free_b);
+    }
+    auto s = std::make_unique<tnfem_server>();
+    s->s = std::make_unique<tnfem::Server>(device, slots, budget);
+    *out = s.release();
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_server_submit(tnfem_server* s, const tnfem_problem_desc* desc, const tnfem_solve_opts* opts,
+                        long long* ticket) {
+  return guarded_s([&]() -> int {
+    if (!s || !desc || !ticket) tnfem::fail(TNFEM_EINVAL, "NULL argument");
+    tnfem_solve_opts o;
+    if (opts) o = *opts;
+    else tnfem_default_opts(&o);
+    *ticket = s->s->submit(*desc, o);
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_server_poll(tnfem_server* s, long long ticket, int wait, tnfem_tt** u_out, tnfem_solve_stats* stats,
+                      double* latency_s) {
+  return guarded_s([&]() -> int {
+    if (!s) tnfem::fail(TNFEM_EINVAL, "NULL server");
+    bool busy = false;
+    auto r = s->s->take(ticket, wait != 0, &busy);
+    if (busy) return TNFEM_EBUSY;
+    if (!r) tnfem::fail(TNFEM_EINVAL, "unknown ticket %lld", ticket);
+    if (stats) *stats = r->stats;
+    if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    if (u_out) *u_out = nullptr;
+    if (r->rc == TNFEM_OK || r->rc == TNFEM_ENOTCONV) {
+      if (u_out) {
+        auto t = new tnfem_tt;
+        t->t = std::move(r->result);
+        *u_out = t;
+      }
+    } else {
+      tnfem::set_last_error(r->error.c_str());
+    }
+    return r->rc;
+  });
+}
+
+int tnfem_server_info(tnfem_server* s, tnfem_server_state* info) {
+  return guarded_s([&]() -> int {
+    if (!s || !info) tnfem::fail(TNFEM_EINVAL, "NULL argument");
+    s->s->info(info);
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_server_destroy(tnfem_server* s) {
+  delete s;
+  return TNFEM_OK;
+}
+
+}  // extern "C"

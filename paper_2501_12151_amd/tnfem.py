@@ -61,6 +61,16 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerInfo(C.Structure):
+    _fields_ = [
+        ("queued", C.c_int), ("running", C.c_int), ("peak_running", C.c_int), ("completed", C.c_longlong),
+        ("bytes_in_use", C.c_size_t), ("peak_bytes", C.c_size_t), ("budget_bytes", C.c_size_t),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp = C.c_void_p
 _ip = C.POINTER(C.c_int)
 _dp = C.POINTER(C.c_double)
@@ -85,6 +95,12 @@ _sig = {
     "tnfem_prim_env_update": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "tnfem_prim_qr": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "tnfem_prim_svd": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "tnfem_server_create": (C.c_int, [C.c_int, C.c_int, C.c_size_t, C.POINTER(_vp)]),
+    "tnfem_server_submit": (C.c_int, [_vp, C.POINTER(ProblemDesc), C.POINTER(SolveOpts), C.POINTER(C.c_longlong)]),
+    "tnfem_server_poll": (C.c_int, [_vp, C.c_longlong, C.c_int, C.POINTER(_vp), C.POINTER(SolveStats),
+                                    C.POINTER(C.c_double)]),
+    "tnfem_server_info": (C.c_int, [_vp, C.POINTER(ServerInfo)]),
+    "tnfem_server_destroy": (C.c_int, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -309,3 +325,45 @@ class Problem:
     def env_update(self, k, reversed_, p, q, s, t, W, L, X, Lnew, stream=None):
         _check(_lib.tnfem_prim_env_update(self._h, k, int(reversed_), p, q, s, t, _ptr(W), _ptr(L), _ptr(X),
                                           _ptr(Lnew), _ptr(stream)))
+
+
+class Server:
+    """Request server on one device (see tnfem_server_* in include/tnfem.h)."""
+
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget_bytes: int = 0):
+        h = _vp()
+        _check(_lib.tnfem_server_create(int(device), int(slots), int(hbm_budget_bytes), C.byref(h)))
+        self._h = h
+        self._descs = {}
+
+    def submit(self, problem: dict, **opts) -> int:
+        desc = make_desc(problem)
+        o = default_opts(**opts)
+        t = C.c_longlong()
+        _check(_lib.tnfem_server_submit(self._h, C.byref(desc), C.byref(o), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """None while running (wait=False); else (TT or None, stats, status, latency_s)."""
+        h = _vp()
+        st = SolveStats()
+        lat = C.c_double()
+        rc = _lib.tnfem_server_poll(self._h, int(ticket), int(bool(wait)), C.byref(h), C.byref(st), C.byref(lat))
+        if rc == EBUSY:
+            return None
+        if rc not in (OK, ENOTCONV):
+            raise TnfemError(rc, _lib.tnfem_last_error().decode())
+        return TT(h), st.as_dict(), rc, lat.value
+
+    def info(self):
+        i = ServerInfo()
+        _check(_lib.tnfem_server_info(self._h, C.byref(i)))
+        return i.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tnfem_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

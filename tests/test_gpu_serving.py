@@ -1,0 +1,77 @@
+"""Serving: results alone equal results in a mix; admission by HBM budget."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import tt  # noqa: E402
+from paper_2501_12151_amd import tnfem, workloads  # noqa: E402
+
+MIX = [
+    (workloads.small_2d(), dict(rank_cap=16, tol=1e-8, max_sweeps=12)),
+    (dict(dim=3, level=4, E=2.0, nu=0.25, clamp=[(0, 0)], tractions=[(0, 1, [0.3, -1.0, 0.5])]),
+     dict(rank_cap=32, tol=1e-6, max_sweeps=8)),
+    (dict(dim=2, level=6, E=0.5, nu=0.4, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.2])]),
+     dict(rank_cap=32, tol=1e-6, max_sweeps=10)),
+    (workloads.cube_body_force(5), dict(rank_cap=32, tol=1e-6, max_sweeps=6)),
+]
+
+
+def _cores(res):
+    return [c.copy() for c in res[0].cores]
+
+
+def test_alone_equals_in_mix():
+    alone = []
+    srv = tnfem.Server(0, slots=1)
+    for prob, opt in MIX:
+        print(f"alone: {prob}", flush=True)
+        alone.append(_cores(srv.poll(srv.submit(prob, **opt))))
+    srv.close()
+    srv = tnfem.Server(0, slots=4)
+    tickets = []
+    for rep in range(3):
+        for j, (prob, opt) in enumerate(MIX):
+            tickets.append((j, srv.submit(prob, **opt)))
+    info_seen = srv.info()
+    results = [(j, srv.poll(t)) for j, t in tickets]
+    info = srv.info()
+    srv.close()
+    print("server info", info_seen, info, flush=True)
+    assert info["completed"] == len(tickets)
+    assert info["peak_running"] >= 2  # requests overlapped on the device
+    for j, res in results:
+        got = _cores(res)
+        assert len(got) == len(alone[j])
+        for a, b in zip(got, alone[j]):
+            assert np.array_equal(a, b)  # bitwise: no cross-request interaction
+        assert res[3] > 0  # latency measured
+
+
+def test_budget_rejects_and_serialises():
+    srv = tnfem.Server(0, slots=2, hbm_budget_bytes=1 << 20)
+    t = srv.submit(MIX[0][0], **MIX[0][1])
+    with pytest.raises(tnfem.TnfemError) as e:
+        srv.poll(t)
+    assert e.value.code == tnfem.EBUDGET
+    srv.close()
+    # measure one request's device footprint, then allow 1.5 of them: one at a time
+    srv = tnfem.Server(0, slots=1)
+    srv.poll(srv.submit(MIX[0][0], **MIX[0][1]))
+    one = srv.info()["peak_bytes"]
+    srv.close()
+    budget = int(1.5 * one)
+    srv = tnfem.Server(0, slots=4, hbm_budget_bytes=budget)
+    ts = [srv.submit(MIX[0][0], **MIX[0][1]) for _ in range(4)]
+    outs = [srv.poll(t) for t in ts]
+    info = srv.info()
+    srv.close()
+    print("small budget info", info, flush=True)
+    assert info["peak_bytes"] <= budget
+    assert info["peak_running"] == 1
+    ref = _cores(outs[0])
+    for o in outs[1:]:
+        for a, b in zip(_cores(o), ref):
+            assert np.array_equal(a, b)
