@@ -94,8 +94,16 @@ typedef struct {
 
 /*
  * Solve options (the AMEn constants; the paper names the solver only).
- * precision: 0 = FP64 everywhere.  Other values are rejected with TNFEM_EINVAL
- * by this version.
+ * precision: 0 = FP64 everywhere.  1 / 2 = the local CG iterations apply the
+ * local operator with FP32 / BF16 operands and FP32 accumulation (MFMA), while
+ * interfaces, QR, SVD truncation, enrichment, CG vectors and scalars stay FP64;
+ * every local solve is refined: after the low-precision CG stops, the residual is
+ * recomputed with the FP64 operator and CG restarts on it until that FP64
+ * residual meets the same target as precision 0.  A restart whose FP64
+ * residual is not below 0.9 x the best one so far returns to the best iterate
+ * and finishes that local solve in FP64 (counted in precision_fallbacks); a
+ * low-precision pass stops after 100 iterations.  Operator cores with dense
+ * plans (next to the component core) always use FP64.
  */
 typedef struct {
   int rank_cap;      /* maximal TT rank of u, 1 .. 252 */
@@ -124,6 +132,10 @@ typedef struct {
   double flops;           /* counted floating-point operations of the contractions */
   double seconds;         /* wall time of the solve (device synchronised) */
   int max_rank;           /* max TT rank of u */
+  long long refinements;  /* precision > 0: FP64 residual restarts of local solves */
+  double low_precision_flops; /* counted flops done with FP32/BF16 operands */
+  long long precision_fallbacks; /* precision > 0: local solves finished in FP64 after a restart
+                                    that did not lower the FP64 residual */
   double contraction_ms;  /* profile = 1: summed device time of the contraction launches */
   double contraction_flops; /* profile = 1: algorithmic flops of those launches */
   long long contraction_launches; /* profile = 1: number of timed launches */
@@ -224,6 +236,12 @@ int tnfem_export_load(const tnfem_problem_desc* desc, int* ncores, int* modes, i
  * Workspace is taken from the context. */
 int tnfem_prim_local_apply(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t,
                            const double* L, const double* x, const double* Rt, double* y, void* stream);
+
+/* The same apply by the fused kernel of the sweep's local CG, with operand
+ * precision 0 (FP64), 1 (FP32, FP32 accumulate) or 2 (BF16, FP32 accumulate).
+ * Only for cores with a sparse plan (TNFEM_EINVAL otherwise). */
+int tnfem_prim_local_apply_ex(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t, const double* L,
+                              const double* x, const double* Rt, double* y, int precision, void* stream);
 
 /* Interface update: Lnew[t][e][s] = sum W[p][j][t] L[p][b][q] A_k[b][j][i][e] X[q][i][s].
  * W: [p][n][t], L: [p][R_l][q], X: [q][n][s], Lnew: [t][R_r][s], device. */

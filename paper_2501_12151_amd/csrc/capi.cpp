@@ -310,6 +310,21 @@ int tnfem_prim_local_apply(tnfem_problem* prob, int k, int reversed, int p, int 
   });
 }
 
+int tnfem_prim_local_apply_ex(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t, const double* L,
+                              const double* x, const double* Rt, double* y, int precision, void* stream) {
+  return guarded([&] {
+    if (!prob || !L || !x || !Rt || !y) fail(TNFEM_EINVAL, "NULL argument");
+    auto& P = *prob->p;
+    if (k < 0 || k >= P.K) fail(TNFEM_EINVAL, "core index %d out of range", k);
+    if (p < 1 || q < 1 || s < 1 || t < 1) fail(TNFEM_EINVAL, "ranks must be >= 1");
+    if (precision < 0 || precision > 2) fail(TNFEM_EINVAL, "precision must be 0, 1 or 2");
+    tnfem::hip_check(hipSetDevice(prob->ctx->c.device), "hipSetDevice");
+    const auto& pl = P.plans[reversed ? 1 : 0][k];
+    tnfem::dev_local_apply_fused(P, pl, p, q, s, t, L, x, Rt, y, precision, pick_stream(prob->ctx, stream));
+    return TNFEM_OK;
+  });
+}
+
 int tnfem_prim_env_update(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t, const double* W,
                           const double* L, const double* X, double* Lnew, void* stream) {
   return guarded([&] {

@@ -405,6 +405,33 @@ void dev_local_apply(Problem& P, const Plan& pl, int p, int q, int s, int t, con
   local_apply_ws(P, pl, p, q, s, t, L, x, Rt, y, skip, st, f, T1, T1 + n1);
 }
 
+void dev_local_apply_fused(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* L, const double* x,
+                           const double* Rt, double* y, int precision, hipStream_t st) {
+  if (pl.dense) fail(TNFEM_EINVAL, "this operator core has a dense plan; the fused apply is for sparse plans");
+  P.ctx->ensure_splitk();
+  FusedArgs f;
+  f.L = L;
+  f.x = x;
+  f.Rt = Rt;
+  f.partial = P.ctx->splitk;
+  f.p = p;
+  f.q = q;
+  f.s = s;
+  f.t = t;
+  f.Rl = pl.Rl;
+  f.Rr = pl.Rr;
+  f.n = pl.n;
+  f.slot_b = pl.sp_slot_b;
+  f.slot_i = pl.sp_slot_i;
+  f.beg = pl.sp_ap_beg;
+  f.ta = pl.sp_ap_a;
+  f.tb = pl.sp_ap_b;
+  f.tv = pl.sp_ap_v;
+  f.ksplit = fused_apply_splits(pl.n, p, t, pl.sp_ap_max, P.ctx->splitk_cap);
+  launch_fused_apply(f, 0.0, st, precision);
+  launch_fused_sum(f, y, st);
+}
+
 void dev_env_update(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* W, const double* L,
                     const double* X, double* Lnew, hipStream_t st, Flops* f) {
   const size_t n1 = (size_t)pl.n_t1() * p * s, n2 = (size_t)pl.n_t2() * p * s;
@@ -659,7 +686,8 @@ struct Sweep {
   std::vector<int> n;       // modes (current orientation)
   double *xspare = nullptr, *zspare = nullptr;
   Flops fl;
-  long long cg_iters = 0, applies = 0;
+  double fl_low = 0.0;
+  long long cg_iters = 0, applies = 0, refinements = 0, fallbacks = 0;
   double max_res = 0.0;
   int nan_seen = 0;
 
@@ -825,25 +853,69 @@ struct Sweep {
       a.w = W.q;
     }
     const double apply_flops = 2.0 * p * p * t * pl.sp_nslot + 2.0 * p * t * t * pl.sp_n_ap;
+    // precision > 0: inner CG with low-precision applies, restarted on the residual
+    // recomputed in FP64 until that residual meets the target (local refinement).
+    // The best FP64-checked iterate is kept; a restart that does not lower the FP64
+    // residual (the low-precision operator is too far from the FP64 one for this
+    // local system) returns to that iterate and finishes the solve in FP64.
+    int prec = fused ? o.precision : 0;
+    const int lp_pass_cap = 100;
     const int chunk = 8;
-    int kit = 0;
-    while (!done && kit <= o.cg_maxit) {
-      for (int c = 0; c < chunk && kit <= o.cg_maxit; ++c, ++kit) {
-        if (fused) {
-          launch_fused_apply(f, apply_flops, st);
-          fl.total += apply_flops;
-        } else {
-          apply(k, p, p, t, t, EA[k], W.z, EA[k + 1], W.q, W.flag + CG_DONE);
-        }
-        launch_cg_reduce_dir(a, kit, st);
-        launch_cg_update2(a, kit, st);
-      }
+    int total_its = 0;
+    const bool converged_at_entry = done;
+    double res_best = res;
+    double* xbest = W.ye;
+    if (prec && !converged_at_entry) launch_copy2d(1, N, X[k], N, xbest, N, 1.0, 0.0, st);
+    auto fp64_restart = [&]() {
+      apply(k, p, p, t, t, EA[k], X[k], EA[k + 1], W.q, nullptr);
+      applies++;
+      a.keep_thr = 1;
+      a.maxit = o.cg_maxit - total_its;
+      launch_cg_init2(a, W.g, W.q, o.tol, st);
+      a.keep_thr = 0;
       readback();
       done = hint()[0];
+      return *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+    };
+    for (int refine = 0;; ++refine) {
+      int kit = 0;
+      const int budget = prec ? std::min(o.cg_maxit - total_its, lp_pass_cap) : o.cg_maxit - total_its;
+      a.maxit = budget;
+      while (!done && kit <= budget) {
+        for (int c = 0; c < chunk && kit <= budget; ++c, ++kit) {
+          if (fused) {
+            launch_fused_apply(f, apply_flops, st, prec);
+            fl.total += apply_flops;
+            if (prec) fl_low += apply_flops;
+          } else {
+            apply(k, p, p, t, t, EA[k], W.z, EA[k + 1], W.q, W.flag + CG_DONE);
+          }
+          launch_cg_reduce_dir(a, kit, st);
+          launch_cg_update2(a, kit, st);
+        }
+        readback();
+        done = hint()[0];
+      }
+      total_its += hint()[1];
+      if (prec == 0 || converged_at_entry || total_its >= o.cg_maxit) break;
+      const double res_now = fp64_restart();
+      refinements++;
+      if (done) break;
+      if (std::isfinite(res_now) && res_now < 0.9 * res_best && refine < 30) {
+        res_best = res_now;
+        launch_copy2d(1, N, X[k], N, xbest, N, 1.0, 0.0, st);
+        continue;
+      }
+      if (!(std::isfinite(res_now) && res_now < res_best)) {
+        launch_copy2d(1, N, xbest, N, X[k], N, 1.0, 0.0, st);
+        fp64_restart();
+        if (done) break;
+      }
+      prec = 0;
+      fallbacks++;
     }
-    const int its = hint()[1];
-    cg_iters += its;
-    applies += its;
+    cg_iters += total_its;
+    applies += total_its;
     return res;
   }
 
@@ -940,7 +1012,7 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   TNFEM_REQUIRE(o.tol > 0 && std::isfinite(o.tol), "tol must be positive");
   TNFEM_REQUIRE(o.max_sweeps >= 1, "max_sweeps must be >= 1");
   TNFEM_REQUIRE(o.cg_maxit >= 0, "cg_maxit must be >= 0");
-  TNFEM_REQUIRE(o.precision == 0, "only precision 0 (FP64) is available");
+  TNFEM_REQUIRE(o.precision >= 0 && o.precision <= 2, "precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
   hip_check(hipSetDevice(P.ctx->device), "hipSetDevice");
   const int rho = std::max(o.rho, 1);
   P.ensure_workspace(o.rank_cap, rho);
@@ -1014,6 +1086,9 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   stats.flops = sw.fl.total;
   stats.seconds = std::chrono::duration<double>(t1 - t0).count();
   stats.max_rank = *std::max_element(sw.xr.begin(), sw.xr.end());
+  stats.refinements = sw.refinements;
+  stats.low_precision_flops = sw.fl_low;
+  stats.precision_fallbacks = sw.fallbacks;
   stats.contraction_ms = 0.0;
   stats.contraction_flops = 0.0;
   stats.contraction_launches = 0;

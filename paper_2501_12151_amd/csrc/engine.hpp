@@ -129,6 +129,8 @@ struct Flops {
 };
 void dev_local_apply(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* L, const double* x,
                      const double* Rt, double* y, const int* skip, hipStream_t st, Flops* f);
+void dev_local_apply_fused(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* L, const double* x,
+                           const double* Rt, double* y, int precision, hipStream_t st);
 void dev_env_update(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* W, const double* L,
                     const double* X, double* Lnew, hipStream_t st, Flops* f);
 

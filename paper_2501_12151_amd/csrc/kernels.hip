@@ -478,81 +478,73 @@ void launch_cg_update(int n, double* x, const double* p, const double* q, double
 //                                v (L[rows, b, :] x[:, i, :]) Rt[cols, e, :]^T
 // The stage-1 product (rows of T1 = L_b x_i for this tile) is formed in LDS per
 // term and consumed at once.  Padded rows/cols are written as zeros.
-__global__ __launch_bounds__(256) void fused_apply_kernel(FusedArgs f) {
-  __shared__ double sA[32][33];
-  __shared__ double sB[32][33];
-  __shared__ double sT[32][33];
-  __shared__ double sR[32][33];
-  if (f.skip && *f.skip) return;
-  const int grp = blockIdx.y, tile = blockIdx.x, z = blockIdx.z;
-  const int m0 = (tile / f.tiles_n) * 32, n0 = (tile % f.tiles_n) * 32;
-  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int wm = wave / 2, wn = wave % 2;
-  const int lrow = lane % 16, lk = lane / 16;
-  const int tb0 = f.beg[grp], te0 = f.beg[grp + 1];
-  const int cnt = te0 - tb0;
-  const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
-  const int tb = tb0 + z * chunk;
-  const int te = tb + chunk < te0 ? tb + chunk : te0;
-  const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
-  d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
-  for (int t = tb; t < te; ++t) {
-    const int slot = f.ta[t], e = f.tb[t];
-    const double v = f.tv[t];
-    const int b = f.slot_b[slot], i = f.slot_i[slot];
-    const double* Lb = f.L + (long)b * f.q;
-    const double* Xi = f.x + (long)i * f.s;
-    const double* Re = f.Rt + (long)e * f.s;
-    for (int s0 = 0; s0 < f.s; s0 += 32) {
-      d4_t tacc = d4_t{0.0, 0.0, 0.0, 0.0};
-      for (int q0 = 0; q0 < f.q; q0 += 32) {
-        for (int idx = tid; idx < 32 * 32; idx += 256) {
-          const int r = idx / 32, c = idx % 32;  // c fastest: contiguous in memory
-          const int gm = m0 + r, gk = q0 + c;
-          sA[c][r] = (gm < f.p && gk < f.q) ? Lb[gm * Lrow + gk] : 0.0;
-          const int gk2 = q0 + r, gn = s0 + c;
-          sB[r][c] = (gk2 < f.q && gn < f.s) ? Xi[gk2 * Xrow + gn] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 32; kk += 4) {
-          const double af = sA[kk + lk][wm * 16 + lrow];
-          const double bf = sB[kk + lk][wn * 16 + lrow];
-          tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, tacc, 0, 0, 0);
-        }
-        __syncthreads();
-      }
-      // T1 chunk (32 rows x 32 cols of s) -> sT[s][row], scaled by v; Rt chunk -> sR[s][col]
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) sT[wn * 16 + lrow][wm * 16 + 4 * qq + lk] = v * tacc[qq];
-      for (int idx = tid; idx < 32 * 32; idx += 256) {
-        const int r = idx / 32, c = idx % 32;  // r: output col (t), c: s index (contiguous)
-        const int gn = n0 + r, gk = s0 + c;
-        sR[c][r] = (gn < f.t && gk < f.s) ? Re[gn * Rrow + gk] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < 32; kk += 4) {
-        const double af = sT[kk + lk][wm * 16 + lrow];
-        const double bf = sR[kk + lk][wn * 16 + lrow];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc, 0, 0, 0);
-      }
-      __syncthreads();
-    }
-  }
-  double* Pt = f.partial + (((long)z * f.n + grp) * f.ntiles + tile) * 1024;
-#pragma unroll
-  for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + 4 * qq + lk) * 32 + wn * 16 + lrow] = acc[qq];
+// Operand precision of the fused apply: 0 = FP64 operands and accumulation
+// (v_mfma_f64_16x16x4f64), 1 = FP32 operands, FP32 accumulation
+// (v_mfma_f32_16x16x4f32), 2 = BF16 operands, FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16).  Inputs are FP64 in memory and rounded when staged;
+// the stage-1 product is rounded to the operand type before stage 3; partial
+// tiles are written as FP64.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+template <int P>
+struct Prec;
+template <>
+struct Prec<0> {
+  using T = double;
+  using Acc = d4_t;
+};
+template <>
+struct Prec<1> {
+  using T = float;
+  using Acc = f4_t;
+};
+template <>
+struct Prec<2> {
+  using T = __bf16;
+  using Acc = f4_t;
+};
+
+// Row (within a 16 x 16 block) held by accumulator entry q of lane (lk = lane / 16).
+template <int P>
+__device__ inline int acc_row(int q, int lk) {
+  return P == 0 ? 4 * q + lk : 4 * lk + q;
 }
 
-// Fast path of fused_apply_kernel for p, q, s, t <= 32 (one tile, one chunk of
-// each contracted index): the next term's operand tiles are loaded into
-// registers while the current term's two MFMA products run.
+// acc += A[arow + 0..15][0..31] * B[0..31][bcol + 0..15], A stored sA[k][m], B stored sB[k][n].
+template <int P>
+__device__ inline void mfma_k32(const typename Prec<P>::T (*sA)[33], const typename Prec<P>::T (*sB)[33], int arow,
+                                int bcol, int lk, int lrow, typename Prec<P>::Acc& acc) {
+  if constexpr (P == 0) {
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[kk + lk][arow + lrow], sB[kk + lk][bcol + lrow], acc, 0, 0, 0);
+  } else if constexpr (P == 1) {
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[kk + lk][arow + lrow], sB[kk + lk][bcol + lrow], acc, 0, 0, 0);
+  } else {
+    bf8_t a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a[j] = sA[8 * lk + j][arow + lrow];
+      b[j] = sB[8 * lk + j][bcol + lrow];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+}
+
+// Fast path of the fused apply for p, q, s, t <= 32 (one tile, one chunk of each
+// contracted index): the next term's operand tiles are loaded into registers
+// while the current term's two MFMA products run.
+template <int P>
 __global__ __launch_bounds__(256) void fused_apply32_kernel(FusedArgs f) {
-  __shared__ double sA[32][33];
-  __shared__ double sB[32][33];
-  __shared__ double sT[32][33];
-  __shared__ double sR[32][33];
+  using T = typename Prec<P>::T;
+  using Acc = typename Prec<P>::Acc;
+  __shared__ T sA[32][33];
+  __shared__ T sB[32][33];
+  __shared__ T sT[32][33];
+  __shared__ T sR[32][33];
   if (f.skip && *f.skip) return;
   const int grp = blockIdx.y, z = blockIdx.z;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
@@ -581,35 +573,89 @@ __global__ __launch_bounds__(256) void fused_apply32_kernel(FusedArgs f) {
     }
   };
   if (tb < te) load(tb, la, xb, rb, vcur);
-  d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+  Acc acc = {0, 0, 0, 0};
   for (int t = tb; t < te; ++t) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int idx = tid + 256 * j, r = idx / 32, c = idx % 32;
-      sA[c][r] = la[j];  // A = L rows (m = r) x q (k = c)
-      sB[r][c] = xb[j];  // B = x (k = r) x s (n = c)
-      sR[c][r] = rb[j];  // B' = Rt^T: k = s (c), n = t (r)
+      sA[c][r] = (T)la[j];  // A = L rows (m = r) x q (k = c)
+      sB[r][c] = (T)xb[j];  // B = x (k = r) x s (n = c)
+      sR[c][r] = (T)rb[j];  // B' = Rt^T: k = s (c), n = t (r)
     }
     const double v = vcur;
     if (t + 1 < te) load(t + 1, la, xb, rb, vcur);
     __syncthreads();
-    d4_t tacc = d4_t{0.0, 0.0, 0.0, 0.0};
+    Acc tacc = {0, 0, 0, 0};
+    mfma_k32<P>(sA, sB, wm * 16, wn * 16, lk, lrow, tacc);
 #pragma unroll
-    for (int kk = 0; kk < 32; kk += 4)
-      tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[kk + lk][wm * 16 + lrow], sB[kk + lk][wn * 16 + lrow], tacc, 0,
-                                                  0, 0);
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) sT[wn * 16 + lrow][wm * 16 + 4 * qq + lk] = v * tacc[qq];
+    for (int qq = 0; qq < 4; ++qq) sT[wn * 16 + lrow][wm * 16 + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[qq]);
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 32; kk += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[kk + lk][wm * 16 + lrow], sR[kk + lk][wn * 16 + lrow], acc, 0, 0,
-                                                 0);
+    mfma_k32<P>(sT, sR, wm * 16, wn * 16, lk, lrow, acc);
     __syncthreads();
   }
   double* Pt = f.partial + ((long)z * f.n + grp) * 1024;
 #pragma unroll
-  for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + 4 * qq + lk) * 32 + wn * 16 + lrow] = acc[qq];
+  for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + acc_row<P>(qq, lk)) * 32 + wn * 16 + lrow] = (double)acc[qq];
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void fused_apply_kernel(FusedArgs f) {
+  using T = typename Prec<P>::T;
+  using Acc = typename Prec<P>::Acc;
+  __shared__ T sA[32][33];
+  __shared__ T sB[32][33];
+  __shared__ T sT[32][33];
+  __shared__ T sR[32][33];
+  if (f.skip && *f.skip) return;
+  const int grp = blockIdx.y, tile = blockIdx.x, z = blockIdx.z;
+  const int m0 = (tile / f.tiles_n) * 32, n0 = (tile % f.tiles_n) * 32;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int lrow = lane % 16, lk = lane / 16;
+  const int tb0 = f.beg[grp], te0 = f.beg[grp + 1];
+  const int cnt = te0 - tb0;
+  const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
+  const int tb = tb0 + z * chunk;
+  const int te = tb + chunk < te0 ? tb + chunk : te0;
+  const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
+  Acc acc = {0, 0, 0, 0};
+  for (int t = tb; t < te; ++t) {
+    const int slot = f.ta[t], e = f.tb[t];
+    const double v = f.tv[t];
+    const int b = f.slot_b[slot], i = f.slot_i[slot];
+    const double* Lb = f.L + (long)b * f.q;
+    const double* Xi = f.x + (long)i * f.s;
+    const double* Re = f.Rt + (long)e * f.s;
+    for (int s0 = 0; s0 < f.s; s0 += 32) {
+      Acc tacc = {0, 0, 0, 0};
+      for (int q0 = 0; q0 < f.q; q0 += 32) {
+        for (int idx = tid; idx < 32 * 32; idx += 256) {
+          const int r = idx / 32, c = idx % 32;  // c fastest: contiguous in memory
+          const int gm = m0 + r, gk = q0 + c;
+          sA[c][r] = (T)((gm < f.p && gk < f.q) ? Lb[gm * Lrow + gk] : 0.0);
+          const int gk2 = q0 + r, gn = s0 + c;
+          sB[r][c] = (T)((gk2 < f.q && gn < f.s) ? Xi[gk2 * Xrow + gn] : 0.0);
+        }
+        __syncthreads();
+        mfma_k32<P>(sA, sB, wm * 16, wn * 16, lk, lrow, tacc);
+        __syncthreads();
+      }
+      // T1 chunk (32 rows x 32 cols of s) -> sT[s][row], scaled by v; Rt chunk -> sR[s][col]
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) sT[wn * 16 + lrow][wm * 16 + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[qq]);
+      for (int idx = tid; idx < 32 * 32; idx += 256) {
+        const int r = idx / 32, c = idx % 32;  // r: output col (t), c: s index (contiguous)
+        const int gn = n0 + r, gk = s0 + c;
+        sR[c][r] = (T)((gn < f.t && gk < f.s) ? Re[gn * Rrow + gk] : 0.0);
+      }
+      __syncthreads();
+      mfma_k32<P>(sT, sR, wm * 16, wn * 16, lk, lrow, acc);
+      __syncthreads();
+    }
+  }
+  double* Pt = f.partial + (((long)z * f.n + grp) * f.ntiles + tile) * 1024;
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + acc_row<P>(qq, lk)) * 32 + wn * 16 + lrow] = (double)acc[qq];
 }
 
 int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles) {
@@ -625,15 +671,47 @@ int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles) {
 static hipEvent_t* prof_begin(hipStream_t s);
 static void prof_end(hipEvent_t* pair, double flops, hipStream_t s);
 
-void launch_fused_apply(FusedArgs f, double flops, hipStream_t s) {
+void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision) {
   f.tiles_n = (f.t + 31) / 32;
   f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
   hipEvent_t* ev = prof_begin(s);
-  if (f.p <= 32 && f.q <= 32 && f.s <= 32 && f.t <= 32)
-    hipLaunchKernelGGL(fused_apply32_kernel, dim3(1, f.n, f.ksplit), dim3(256), 0, s, f);
-  else
-    hipLaunchKernelGGL(fused_apply_kernel, dim3(f.ntiles, f.n, f.ksplit), dim3(256), 0, s, f);
+  const bool small = f.p <= 32 && f.q <= 32 && f.s <= 32 && f.t <= 32;
+  const dim3 g32(1, f.n, f.ksplit), g(f.ntiles, f.n, f.ksplit);
+  if (precision == 1) {
+    if (small) hipLaunchKernelGGL(fused_apply32_kernel<1>, g32, dim3(256), 0, s, f);
+    else hipLaunchKernelGGL(fused_apply_kernel<1>, g, dim3(256), 0, s, f);
+  } else if (precision == 2) {
+    if (small) hipLaunchKernelGGL(fused_apply32_kernel<2>, g32, dim3(256), 0, s, f);
+    else hipLaunchKernelGGL(fused_apply_kernel<2>, g, dim3(256), 0, s, f);
+  } else {
+    if (small) hipLaunchKernelGGL(fused_apply32_kernel<0>, g32, dim3(256), 0, s, f);
+    else hipLaunchKernelGGL(fused_apply_kernel<0>, g, dim3(256), 0, s, f);
+  }
   prof_end(ev, flops, s);
+  TN_CHECK_LAUNCH();
+}
+
+static int blocks_for(long total);
+
+// y[row][grp][col] = sum over splits of the fused partial tiles (split order).
+__global__ void fused_sum_kernel(FusedArgs f, double* y) {
+  const long N = (long)f.p * f.n * f.t;
+  const long stride = (long)f.n * f.ntiles * 1024;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
+    const int col = e % f.t, grp = (e / f.t) % f.n, row = e / ((long)f.t * f.n);
+    const int tile = (row / 32) * f.tiles_n + col / 32;
+    const double* src = f.partial + ((long)grp * f.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
+    double w = 0.0;
+    for (int z = 0; z < f.ksplit; ++z) w += src[z * stride];
+    y[e] = w;
+  }
+}
+
+void launch_fused_sum(FusedArgs f, double* y, hipStream_t s) {
+  f.tiles_n = (f.t + 31) / 32;
+  f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
+  const long N = (long)f.p * f.n * f.t;
+  hipLaunchKernelGGL(fused_sum_kernel, dim3(blocks_for(N)), dim3(256), 0, s, f, y);
   TN_CHECK_LAUNCH();
 }
 
@@ -770,12 +848,16 @@ __global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const doubl
   const double rr = sum_parts(a.parts + PART_RR, nb), gg = sum_parts(a.parts + PART_PQ, nb);
   const double gn = sqrt(gg);
   const double res = gg > 0.0 ? sqrt(rr) / gn : (rr == 0.0 ? 0.0 : 1.0);
-  const double thr = fmax(0.1 * res, 0.5 * tol) * gn;
   a.scal[CG_GG] = gg;
   a.scal[CG_RES] = res;
-  a.scal[CG_THR2] = thr * thr;
   a.flag[CG_ITERS] = 0;
-  a.flag[CG_DONE] = (res <= 0.5 * tol || a.maxit <= 0) ? 1 : 0;
+  if (a.keep_thr) {
+    a.flag[CG_DONE] = (rr <= a.scal[CG_THR2] || a.maxit <= 0) ? 1 : 0;
+  } else {
+    const double thr = fmax(0.1 * res, 0.5 * tol) * gn;
+    a.scal[CG_THR2] = thr * thr;
+    a.flag[CG_DONE] = (res <= 0.5 * tol || a.maxit <= 0) ? 1 : 0;
+  }
   a.flag[CG_COUNTER] = 0;
 }
 

@@ -95,7 +95,10 @@ struct FusedArgs {
   const int* skip = nullptr;
 };
 int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles);
-void launch_fused_apply(FusedArgs f, double flops, hipStream_t s);
+// precision: 0 FP64, 1 FP32 operands (FP32 accumulate), 2 BF16 operands (FP32 accumulate)
+void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision = 0);
+// y = sum of the partial tiles written by launch_fused_apply with the same f.
+void launch_fused_sum(FusedArgs f, double* y, hipStream_t s);
 
 // Local PCG with per-block partial sums (no atomics inside the iteration):
 // iteration k = apply (w = B z) -> reduce_dir(k) -> update2(k).
@@ -113,6 +116,7 @@ struct CgIterArgs {
   int maxit = 0;
   int nb_upd = 1;  // blocks of init / update (partials of r.z, r.r)
   int nb_dir = 1;  // blocks of reduce_dir (partials of p.q)
+  int keep_thr = 0;  // init: keep the stored threshold (refinement restart) instead of deriving it
 };
 int cg_vec_blocks(int n);
 int cg_dir_blocks(int n);

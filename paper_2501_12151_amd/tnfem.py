@@ -53,7 +53,9 @@ class SolveStats(C.Structure):
     _fields_ = [
         ("sweeps", C.c_int), ("converged", C.c_int), ("final_max_res", C.c_double),
         ("cg_iters", C.c_longlong), ("local_applies", C.c_longlong), ("flops", C.c_double),
-        ("seconds", C.c_double), ("max_rank", C.c_int), ("contraction_ms", C.c_double),
+        ("seconds", C.c_double), ("max_rank", C.c_int), ("refinements", C.c_longlong),
+        ("low_precision_flops", C.c_double), ("precision_fallbacks", C.c_longlong),
+        ("contraction_ms", C.c_double),
         ("contraction_flops", C.c_double), ("contraction_launches", C.c_longlong),
     ]
 
@@ -92,6 +94,8 @@ _sig = {
     "tnfem_export_operator": (C.c_int, [C.POINTER(ProblemDesc), _ip, _ip, _ip, _dp, C.c_size_t, C.POINTER(C.c_size_t)]),
     "tnfem_export_load": (C.c_int, [C.POINTER(ProblemDesc), _ip, _ip, _ip, _dp, C.c_size_t, C.POINTER(C.c_size_t)]),
     "tnfem_prim_local_apply": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "tnfem_prim_local_apply_ex": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp,
+                                             _vp, C.c_int, _vp]),
     "tnfem_prim_env_update": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "tnfem_prim_qr": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "tnfem_prim_svd": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
@@ -321,6 +325,10 @@ class Problem:
     def local_apply(self, k, reversed_, p, q, s, t, L, x, Rt, y, stream=None):
         _check(_lib.tnfem_prim_local_apply(self._h, k, int(reversed_), p, q, s, t, _ptr(L), _ptr(x), _ptr(Rt),
                                            _ptr(y), _ptr(stream)))
+
+    def local_apply_ex(self, k, reversed_, p, q, s, t, L, x, Rt, y, precision=0, stream=None):
+        _check(_lib.tnfem_prim_local_apply_ex(self._h, k, int(reversed_), p, q, s, t, _ptr(L), _ptr(x), _ptr(Rt),
+                                              _ptr(y), int(precision), _ptr(stream)))
 
     def env_update(self, k, reversed_, p, q, s, t, W, L, X, Lnew, stream=None):
         _check(_lib.tnfem_prim_env_update(self._h, k, int(reversed_), p, q, s, t, _ptr(W), _ptr(L), _ptr(X),

@@ -1,0 +1,93 @@
+"""Mixed precision: FP32 / BF16 local applies (FP32 accumulation) and FP64-refined solves."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import amen as oamen, fem, qtt, tt  # noqa: E402
+from paper_2501_12151_amd import tnfem, workloads  # noqa: E402
+
+U32 = 2.0 ** -24
+UBF = 2.0 ** -8
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tnfem.Context(0, stream=torch.cuda.current_stream())
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("ranks", [(32, 32, 32, 32), (5, 7, 33, 17)])
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_fused_apply_precision_bound(ctx, dim, ranks, precision):
+    prob = workloads.small_2d() if dim == 2 else workloads.cube_body_force(4)
+    P = tnfem.Problem(ctx, prob)
+    Ac = tnfem.export_operator(prob)
+    k = 1  # a middle level core (sparse plan)
+    A = Ac[k]
+    Rl, n, _, Rr = A.shape
+    p, q, s, t = ranks
+    rng = np.random.default_rng(100 * dim + precision)
+    L = rng.standard_normal((p, Rl, q))
+    x = rng.standard_normal((q, n, s))
+    Rt = rng.standard_normal((t, Rr, s))
+    y = torch.zeros((p, n, t), dtype=torch.float64, device="cuda")
+    print(f"fused apply dim={dim} ranks={ranks} precision={precision}", flush=True)
+    P.local_apply_ex(k, 0, p, q, s, t, dev(L), dev(x), dev(Rt), y, precision=precision,
+                     stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    ref = oamen.local_apply(L, A, x, Rt)
+    yabs = oamen.local_apply(np.abs(L), np.abs(A), np.abs(x), np.abs(Rt))
+    err = np.abs(got - ref)
+    nterms = max(int(np.count_nonzero(A[:, j, :, :])) for j in range(n))
+    K = q + s * nterms
+    if precision == 0:
+        assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+    elif precision == 1:
+        assert np.all(err <= (6 * U32 + K * U32) * yabs + 1e-300)
+    else:
+        assert np.all(err <= (6 * UBF + K * U32) * yabs + 1e-300)
+    if precision > 0:
+        print(f"  max err / yabs = {np.max(err / np.maximum(yabs, 1e-300)):.2e}", flush=True)
+    P.close()
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_refined_small_2d_matches_fp64_oracle(precision):
+    prob = workloads.small_2d()
+    ctx = tnfem.Context(0)
+    P = tnfem.Problem(ctx, prob)
+    U, st, rc = P.solve(rank_cap=16, tol=1e-8, max_sweeps=20, precision=precision)
+    X, ost = oamen.amen_solve(qtt.assemble_operator(prob), qtt.assemble_load(prob),
+                              oamen.Options(tol=1e-8, rank_cap=16, max_sweeps=20))
+    ug, uo = tt.tt_full(U.cores), tt.tt_full(X)
+    rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    print(f"precision {precision}: rel.diff vs FP64 oracle {rel:.2e}, refinements {st['refinements']}, "
+          f"low-precision flops {st['low_precision_flops']:.3e} of {st['flops']:.3e}, "
+          f"FP64 fallbacks {st['precision_fallbacks']}", flush=True)
+    assert st["low_precision_flops"] > 0  # low-precision applies were used
+    assert rel <= 1e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_refined_unconstrained_3d_equals_direct(precision):
+    prob = dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, 0.0, -1.0])
+    A, b, grid, _ = fem.build_system(prob)
+    u = qtt.to_qtt_order(fem.direct_solve(A, b), 3, 3)
+    ctx = tnfem.Context(0)
+    P = tnfem.Problem(ctx, prob)
+    U, st, rc = P.solve(rank_cap=200, tol=1e-10, max_sweeps=30, precision=precision)
+    rel = np.linalg.norm(tt.tt_full(U.cores) - u) / np.linalg.norm(u)
+    print(f"precision {precision}: 3D level 3 rel.err vs direct {rel:.2e}, refinements {st['refinements']}", flush=True)
+    assert rel <= 1e-8
+    ctx.close()
