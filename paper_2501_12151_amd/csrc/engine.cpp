@@ -549,6 +549,10 @@ static void gemm_plain(int m, int n, int k, const double* A, long lda, bool tran
 
 // Lays out the workspace of a problem for (cap, rho); `A` returns a buffer of the
 // given number of doubles (or counts them when only the size is wanted).
+// Local systems of dense-plan cores with at most this many unknowns are solved with
+// the explicit local matrix (formed once per local solve) instead of the contraction chain.
+constexpr size_t kExplicitMaxN = 2048;
+
 template <class Alloc>
 static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, Alloc A) {
   const int K = P.K;
@@ -610,6 +614,10 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   W.splitk_cap = (size_t)1 << 22;
   W.splitk = A(W.splitk_cap);
   W.part = A(6 * 512);
+  W.bloc_n = std::min<size_t>(kExplicitMaxN, rc * maxn * rc);
+  W.Bloc = A(W.bloc_n * W.bloc_n);
+  W.mloc_cap = W.bloc_n * W.bloc_n;
+  W.Mloc = A(W.mloc_cap);
 }
 
 size_t Problem::workspace_bytes(int cap, int rho) const {
@@ -690,8 +698,12 @@ struct Sweep {
   long long cg_iters = 0, applies = 0, refinements = 0, fallbacks = 0;
   double max_res = 0.0;
   int nan_seen = 0;
+  int verbose = 0;  // 2: one line per local solve on stderr
 
-  Sweep(Problem& p, const tnfem_solve_opts& opts) : P(p), W(*p.ws), o(opts), st(p.ctx->stream), K(p.K) {}
+  Sweep(Problem& p, const tnfem_solve_opts& opts) : P(p), W(*p.ws), o(opts), st(p.ctx->stream), K(p.K) {
+    const char* v = std::getenv("TNFEM_VERBOSE");
+    verbose = v ? std::atoi(v) : 0;
+  }
 
   volatile int* hint() { return static_cast<volatile int*>(W.host_pinned); }
 
@@ -824,6 +836,12 @@ struct Sweep {
     const double sp_flops = 2.0 * pl.sp_n_ap * ((double)p * p * t + (double)p * t * t);
     (void)sp_flops;
     const bool fused = !pl.dense;
+    const size_t m_need = (size_t)pl.Rl * n[k] * n[k] * (size_t)t * t;
+    const bool explicit_mat = pl.dense && !done && (size_t)N <= W.bloc_n && m_need <= W.mloc_cap;
+    if (explicit_mat) {
+      launch_local_matrix(p, n[k], t, pl.Rl, pl.Rr, EA[k], pl.A2, EA[k + 1], W.Mloc, W.Bloc, st);
+      fl.total += 2.0 * m_need * pl.Rr + 2.0 * (double)N * N * pl.Rl;
+    }
     if (fused) {
       f.L = EA[k];
       f.x = W.z;
@@ -887,6 +905,9 @@ struct Sweep {
             launch_fused_apply(f, apply_flops, st, prec);
             fl.total += apply_flops;
             if (prec) fl_low += apply_flops;
+          } else if (explicit_mat) {
+            launch_dense_matvec(N, W.Bloc, W.z, W.q, W.flag + CG_DONE, st);
+            fl.total += 2.0 * (double)N * N;
           } else {
             apply(k, p, p, t, t, EA[k], W.z, EA[k + 1], W.q, W.flag + CG_DONE);
           }
@@ -916,6 +937,9 @@ struct Sweep {
     }
     cg_iters += total_its;
     applies += total_its;
+    if (verbose >= 2)
+      fprintf(stderr, "[tnfem]   core %d (orient %d) p %d n %d t %d N %d %s R %d/%d res %.3e cg %d\n", k, orient, p,
+              n[k], t, N, pl.dense ? "dense" : "sparse", R(k), R(k + 1), res, total_its);
     return res;
   }
 
@@ -1022,7 +1046,7 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   tnfem_solve_opts oo = o;
   oo.rho = rho;
   const char* verbose_env = std::getenv("TNFEM_VERBOSE");
-  const bool verbose = verbose_env && verbose_env[0] == '1';
+  const bool verbose = verbose_env && std::atoi(verbose_env) >= 1;
   if (o.profile) {
     if (!P.ws->profile) P.ws->profile = std::make_unique<GemmProfile>();
     P.ws->profile->reset();

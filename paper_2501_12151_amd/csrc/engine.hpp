@@ -88,6 +88,8 @@ struct Workspace {
   size_t splitk_cap = 0;
   double* fpart = nullptr;  // fused-apply partial tiles
   size_t fpart_cap = 0;
+  double *Bloc = nullptr, *Mloc = nullptr;  // explicit local matrix (dense plans, small local systems)
+  size_t bloc_n = 0, mloc_cap = 0;
   int* flag = nullptr;
   int* drank = nullptr;
   void* host_pinned = nullptr;

@@ -914,6 +914,75 @@ void launch_local_diag(int p, int n, int t, int Rl, int Rr, const double* L, con
   TN_CHECK_LAUNCH();
 }
 
+// ----------------------------------------------------------------------------- explicit local matrix
+
+// Stage 1: M[b][j][i][c][c'] = sum_e A2[(b n + i) n + j][e] Rt[c][e][c']  (A2: dense operator core,
+// rows (b, in-index i), columns (out-index j, e)).
+__global__ void local_matrix_r_kernel(int Rl, int n, int Rr, int t, const double* A2, const double* Rt, double* M) {
+  const long tt = (long)t * t;
+  const long total = (long)Rl * n * n * tt;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int c2 = idx % t;
+    const int c = (idx / t) % t;
+    const long bji = idx / tt;
+    const int i = bji % n;
+    const int j = (bji / n) % n;
+    const int b = bji / ((long)n * n);
+    const double* a = A2 + (((long)b * n + i) * n + j) * Rr;
+    const double* r = Rt + (long)c * Rr * t + c2;
+    double s = 0.0;
+    for (int e = 0; e < Rr; ++e) s += a[e] * r[(long)e * t];
+    M[idx] = s;
+  }
+}
+
+// Stage 2: Bm[(a n + j) t + c][(a' n + i) t + c'] = sum_b L[a][b][a'] M[b][j][i][c][c'].
+__global__ void local_matrix_l_kernel(int p, int n, int t, int Rl, const double* L, const double* M, double* Bm) {
+  const long N = (long)p * n * t;
+  const long total = N * N;
+  const long tt = (long)t * t, slab = (long)n * n * tt;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const long row = idx / N, col = idx % N;
+    const int c = row % t, j = (row / t) % n, a = row / ((long)t * n);
+    const int c2 = col % t, i = (col / t) % n, a2 = col / ((long)t * n);
+    const double* m = M + ((long)j * n + i) * tt + (long)c * t + c2;
+    const double* l = L + (long)a * Rl * p + a2;
+    double s = 0.0;
+    for (int b = 0; b < Rl; ++b) s += l[(long)b * p] * m[b * slab];
+    Bm[idx] = s;
+  }
+}
+
+void launch_local_matrix(int p, int n, int t, int Rl, int Rr, const double* L, const double* A2, const double* Rt,
+                         double* M, double* Bm, hipStream_t s) {
+  const long m_total = (long)Rl * n * n * t * t;
+  const long b_total = (long)p * n * t * (long)p * n * t;
+  hipLaunchKernelGGL(local_matrix_r_kernel, dim3(blocks_for(m_total)), dim3(256), 0, s, Rl, n, Rr, t, A2, Rt, M);
+  TN_CHECK_LAUNCH();
+  hipLaunchKernelGGL(local_matrix_l_kernel, dim3(blocks_for(b_total)), dim3(256), 0, s, p, n, t, Rl, L, M, Bm);
+  TN_CHECK_LAUNCH();
+}
+
+// y = Bm z, Bm N x N row-major; one wavefront per row, fixed reduction order.
+__global__ __launch_bounds__(256) void dense_matvec_kernel(int N, const double* Bm, const double* z, double* y,
+                                                           const int* skip) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x % 64;
+  const long row = (long)blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= N) return;
+  const double* b = Bm + row * N;
+  double s = 0.0;
+  for (int c = lane; c < N; c += 64) s += b[c] * z[c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) y[row] = s;
+}
+
+void launch_dense_matvec(int N, const double* Bm, const double* z, double* y, const int* skip, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(dense_matvec_kernel, dim3((N + 3) / 4), dim3(256), 0, s, N, Bm, z, y, skip);
+  TN_CHECK_LAUNCH();
+}
+
 // ----------------------------------------------------------------------------- QR
 
 constexpr int QR_NT = 1024;

@@ -129,6 +129,14 @@ void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s);
 void launch_local_diag(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* dg_beg,
                        const int* dg_b, const int* dg_e, const double* dg_v, double* dinv, hipStream_t s);
 
+// Explicit local matrix of a dense operator core A2 (rows (b, in-index), columns (out-index, e)):
+//   Bm[(a n + j) t + c][(a' n + i) t + c'] = sum_{b,e} L[a][b][a'] A[b][j][i][e] Rt[c][e][c'],
+// through M[b][j][i][c][c'] = sum_e A[b][j][i][e] Rt[c][e][c'] (Rl n^2 t^2 doubles).
+void launch_local_matrix(int p, int n, int t, int Rl, int Rr, const double* L, const double* A2, const double* Rt,
+                         double* M, double* Bm, hipStream_t s);
+// y = Bm z (N x N row-major); does nothing when skip != nullptr and *skip != 0 on the device.
+void launch_dense_matvec(int N, const double* Bm, const double* z, double* y, const int* skip, hipStream_t s);
+
 // Householder QR of A (m x n, row-major, lda), single workgroup: Q (m x c), R (c x n), c = min(m, n).
 // ws: workspace of m * n + m * c + 2 * c doubles.
 void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws, hipStream_t s);
