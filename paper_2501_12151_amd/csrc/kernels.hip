@@ -37,14 +37,52 @@ namespace tnfem {
 
 // ----------------------------------------------------------------------------- reductions
 
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Lane exchanges within rows of 16 lanes through DPP (no LDS round trip).  The
+// patterns are symmetric, so after each step every lane of a group holds the
+// same value, summed in the same order.  All lanes of a group must be active.
+enum : int {
+  DPP_XOR1 = 0xB1,         // quad_perm [1, 0, 3, 2]
+  DPP_XOR2 = 0x4E,         // quad_perm [2, 3, 0, 1]
+  DPP_HALF_MIRROR = 0x141, // lane l <- 7 - l within each 8 lanes
+  DPP_MIRROR = 0x140,      // lane l <- 15 - l within each 16 lanes
+};
+
+template <int CTRL>
+__device__ inline double dpp_get(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double lane_get(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of each row.
+__device__ inline double row_sum(double v) {
+  v += dpp_get<DPP_XOR1>(v);
+  v += dpp_get<DPP_XOR2>(v);
+  v += dpp_get<DPP_HALF_MIRROR>(v);
+  v += dpp_get<DPP_MIRROR>(v);
   return v;
 }
 
-// Sum over a group of `width` consecutive lanes (width a power of two <= 64).
+// Sum over the wavefront; every lane receives the same value.
+__device__ inline double wave_sum(double v) {
+  v = row_sum(v);
+  return (lane_get(v, 0) + lane_get(v, 16)) + (lane_get(v, 32) + lane_get(v, 48));
+}
+
+// Sum over a group of `width` consecutive lanes (width a power of two <= 64, groups aligned).
 __device__ inline double group_sum(double v, int width) {
-  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (width >= 2) v += dpp_get<DPP_XOR1>(v);
+  if (width >= 4) v += dpp_get<DPP_XOR2>(v);
+  if (width >= 8) v += dpp_get<DPP_HALF_MIRROR>(v);
+  if (width >= 16) v += dpp_get<DPP_MIRROR>(v);
+  if (width >= 32) v += __shfl_xor(v, 16, 64);
+  if (width >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -1066,6 +1104,100 @@ __global__ __launch_bounds__(QR_NT) void qr_kernel(int m, int n, const double* A
   }
 }
 
+// Householder QR with columns owned by wavefronts (column col belongs to wave
+// col % waves) and rows by lanes (row i to lane i % 64) in every phase, so no
+// lane reads another lane's writes without a barrier in between.  The owner of
+// column j + 1 applies reflector j to it first and forms reflector j + 1 at
+// once, so each column costs one barrier; Q is accumulated by every wave for its
+// own columns over all reflectors without barriers.
+template <bool LDS>
+__global__ __launch_bounds__(QR_NT) void qr_owner_kernel(int m, int n, const double* A, int lda, double* Q, int ldq,
+                                                         double* R, int ldr, double* ws) {
+  extern __shared__ double dyn[];
+  constexpr int NW = QR_NT / 64;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int c = m < n ? m : n;
+  double* base = LDS ? dyn : ws;
+  double* W = base;                  // m x n, column-major
+  double* Qc = base + (long)m * n;   // m x c, column-major
+  double* tau = Qc + (long)m * c;    // c
+  double* diag = tau + c;            // c
+  for (long idx = tid; idx < (long)m * n; idx += QR_NT) {
+    const int i = idx / n, j = idx % n;
+    W[(long)j * m + i] = A[(long)i * lda + j];
+  }
+  __syncthreads();
+  // reflector of column j (rows j..m-1), formed by the wave that owns column j
+  auto reflector = [&](int j) {
+    double* v = W + (long)j * m;
+    double loc = 0.0, xj = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      if (i >= j) {
+        const double x = v[i];
+        loc += x * x;
+        if (i == j) xj = x;
+      }
+    }
+    const double s2 = wave_sum(loc);
+    const double x0 = __shfl(xj, j % 64, 64);
+    const double nrm = sqrt(s2);
+    double tj = 0.0, alpha = 0.0, v0 = x0;
+    if (nrm > 0.0) {
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      v0 = x0 - alpha;
+      tj = 2.0 / (s2 - x0 * x0 + v0 * v0);
+    }
+    if (lane == j % 64) {
+      v[j] = v0;
+      tau[j] = tj;
+      diag[j] = alpha;
+    }
+  };
+  // w <- (I - tau v v^T) w over rows j..m-1
+  auto apply = [&](const double* v, double tj, double* w, int j) {
+    double part = 0.0;
+    for (int i = lane; i < m; i += 64)
+      if (i >= j) part += v[i] * w[i];
+    const double f = tj * wave_sum(part);
+    for (int i = lane; i < m; i += 64)
+      if (i >= j) w[i] -= f * v[i];
+  };
+  if (c > 0 && wave == 0) reflector(0);
+  __syncthreads();
+  for (int j = 0; j < c; ++j) {
+    const double tj = tau[j];
+    const double* v = W + (long)j * m;
+    const int nxt = j + 1;
+    if (nxt < n && wave == nxt % NW) {
+      if (tj != 0.0) apply(v, tj, W + (long)nxt * m, j);
+      if (nxt < c) reflector(nxt);
+    }
+    if (tj != 0.0) {
+      for (int col = nxt + 1; col < n; ++col)
+        if (col % NW == wave) apply(v, tj, W + (long)col * m, j);
+    }
+    __syncthreads();
+  }
+  for (long idx = tid; idx < (long)c * n; idx += QR_NT) {
+    const int i = idx / n, jj = idx % n;
+    R[(long)i * ldr + jj] = jj < i ? 0.0 : (jj == i ? diag[i] : W[(long)jj * m + i]);
+  }
+  // Q = H_0 ... H_{c-1} E: column col of E is changed only by reflectors j <= col
+  for (int col = wave; col < c; col += NW) {
+    double* q = Qc + (long)col * m;
+    for (int i = lane; i < m; i += 64) q[i] = (i == col) ? 1.0 : 0.0;
+    for (int j = col; j >= 0; --j) {
+      const double tj = tau[j];
+      if (tj != 0.0) apply(W + (long)j * m, tj, q, j);
+    }
+  }
+  __syncthreads();
+  for (long idx = tid; idx < (long)m * c; idx += QR_NT) {
+    const int i = idx / c, jj = idx % c;
+    Q[(long)i * ldq + jj] = Qc[(long)jj * m + i];
+  }
+}
+
 void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws,
                hipStream_t s) {
   const int c = m < n ? m : n;
@@ -1073,12 +1205,12 @@ void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, doubl
   if (bytes <= QR_LDS_BYTES) {
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_kernel<true>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_owner_kernel<true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_BYTES);
     });
-    hipLaunchKernelGGL(qr_kernel<true>, dim3(1), dim3(QR_NT), bytes, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+    hipLaunchKernelGGL(qr_owner_kernel<true>, dim3(1), dim3(QR_NT), bytes, s, m, n, A, lda, Q, ldq, R, ldr, ws);
   } else {
-    hipLaunchKernelGGL(qr_kernel<false>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+    hipLaunchKernelGGL(qr_owner_kernel<false>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
   }
   TN_CHECK_LAUNCH();
 }
@@ -1113,7 +1245,9 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
   while (pw * 2 <= tpp) pw *= 2;
   tpp = pw;
   const int pair = tid / tpp, sub = tid % tpp;
-  const double eps = 1e-15;
+  // rotation threshold at the rounding level of an n-term dot product: smaller
+  // off-diagonal values are rounding noise, and rotating them never terminates
+  const double eps = (n > 4 ? n : 4) * 2.220446049250313e-16;
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -1179,8 +1313,106 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
   for (int j = tid; j < n; j += SV_NT) S[pos[j]] = sv[j];
 }
 
+// The same one-sided Jacobi iteration for n <= 64 on a single wavefront: each
+// column pair of a step is owned by a group of 64 / (n / 2) lanes that reduce
+// their dot products with cross-lane shuffles; a step ends with a barrier of the
+// one-wave workgroup.
+constexpr int SVW_MAXN = 64;
+
+__global__ __launch_bounds__(64) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, double* U, double* S,
+                                                            double* V) {
+  // column-major n x n with a padded column stride: the columns handled at one
+  // step start in different LDS banks
+  __shared__ double Gc[SVW_MAXN * (SVW_MAXN + 1)];
+  __shared__ double Vc[SVW_MAXN * (SVW_MAXN + 1)];
+  __shared__ double sv[SVW_MAXN];
+  __shared__ int pos[SVW_MAXN];
+  const int lane = threadIdx.x;
+  const int ld = n + 1;
+  for (int idx = lane; idx < n * n; idx += 64) {
+    const int i = idx % n, j = idx / n;
+    Gc[j * ld + i] = G[(long)i * ldg + j];
+    Vc[j * ld + i] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int npad = n + (n & 1);
+  const int npairs = npad / 2 > 0 ? npad / 2 : 1;
+  int tpp = 1;
+  while (tpp * 2 * npairs <= 64) tpp *= 2;
+  const int pair = lane / tpp, sub = lane % tpp;
+  const int rpl = (n + tpp - 1) / tpp;  // rows per lane, contiguous
+  const int i0 = sub * rpl, i1 = min(n, i0 + rpl);
+  // rotation threshold at the rounding level of an n-term dot product: smaller
+  // off-diagonal values are rounding noise, and rotating them never terminates
+  const double eps = (n > 4 ? n : 4) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+    int rot = 0;
+    for (int step = 0; step < npad - 1; ++step) {
+      if (pair < npairs) {
+        const int ia = pair, ib = npad - 1 - pair;
+        const int pa = ia == 0 ? 0 : 1 + (ia - 1 + step) % (npad - 1);
+        const int pb = ib == 0 ? 0 : 1 + (ib - 1 + step) % (npad - 1);
+        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+        double a = 0.0, b = 0.0, cc = 0.0;
+        if (q < n) {
+          for (int i = i0; i < i1; ++i) {
+            const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
+            a += gp * gp;
+            b += gq * gq;
+            cc += gp * gq;
+          }
+        }
+        a = group_sum(a, tpp);
+        b = group_sum(b, tpp);
+        cc = group_sum(cc, tpp);
+        if (q < n && cc != 0.0 && fabs(cc) > eps * sqrt(a * b)) {
+          const double zeta = (b - a) / (2.0 * cc);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int i = i0; i < i1; ++i) {
+            const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
+            Gc[p * ld + i] = cs * gp - sn * gq;
+            Gc[q * ld + i] = sn * gp + cs * gq;
+            const double vp = Vc[p * ld + i], vq = Vc[q * ld + i];
+            Vc[p * ld + i] = cs * vp - sn * vq;
+            Vc[q * ld + i] = sn * vp + cs * vq;
+          }
+          rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (__ballot(rot) == 0) break;
+  }
+  for (int j = lane; j < n; j += 64) {
+    double s2 = 0.0;
+    for (int i = 0; i < n; ++i) s2 += Gc[j * ld + i] * Gc[j * ld + i];
+    sv[j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = lane; j < n; j += 64) {
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += (sv[i] > sv[j]) || (sv[i] == sv[j] && i < j);
+    pos[j] = r;
+  }
+  __syncthreads();
+  for (int idx = lane; idx < n * n; idx += 64) {
+    const int j = idx / n, i = idx % n;
+    const int pj = pos[j];
+    const double sj = sv[j];
+    U[(long)i * n + pj] = sj > 0.0 ? Gc[j * ld + i] / sj : (i == pj ? 1.0 : 0.0);
+    V[(long)i * n + pj] = Vc[j * ld + i];
+  }
+  for (int j = lane; j < n; j += 64) S[pos[j]] = sv[j];
+}
+
 void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s) {
   if (n > SV_MAXN) throw Error(TNFEM_EINVAL, "Jacobi SVD limited to n <= 256");
+  if (n <= SVW_MAXN) {
+    hipLaunchKernelGGL(jacobi_svd_wave_kernel, dim3(1), dim3(64), 0, s, n, G, ldg, U, S, V);
+    TN_CHECK_LAUNCH();
+    return;
+  }
   hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(SV_NT), 0, s, n, G, ldg, U, S, V, ws);
   TN_CHECK_LAUNCH();
 }

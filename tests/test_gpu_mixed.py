@@ -61,8 +61,39 @@ def test_fused_apply_precision_bound(ctx, dim, ranks, precision):
     P.close()
 
 
+def _stats_line(st):
+    return (f"refinements {st['refinements']}, low-precision flops {st['low_precision_flops']:.3e} of "
+            f"{st['flops']:.3e}, FP64 fallbacks {st['precision_fallbacks']}")
+
+
 @pytest.mark.parametrize("precision", [1, 2])
-def test_refined_small_2d_matches_fp64_oracle(precision):
+def test_refined_converged_2d_matches_fp64_oracle_and_direct(precision):
+    """Rank cap 64 does not bind: the FP64 sweep converges to the discrete solution, and the
+    refined low-precision solve must reach it to the 1e-6 target as well."""
+    prob = workloads.small_2d()
+    A, b, grid, _ = fem.build_system(prob)
+    u = qtt.to_qtt_order(fem.direct_solve(A, b), 2, 5)
+    ctx = tnfem.Context(0)
+    P = tnfem.Problem(ctx, prob)
+    U, st, rc = P.solve(rank_cap=64, tol=1e-10, max_sweeps=30, precision=precision)
+    X, ost = oamen.amen_solve(qtt.assemble_operator(prob), qtt.assemble_load(prob),
+                              oamen.Options(tol=1e-10, rank_cap=64, max_sweeps=30))
+    ug, uo = tt.tt_full(U.cores), tt.tt_full(X)
+    rel_o = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    rel_d = np.linalg.norm(ug.reshape(-1) - u) / np.linalg.norm(u)
+    print(f"precision {precision}: rel.diff vs FP64 oracle {rel_o:.2e}, vs direct {rel_d:.2e}, {_stats_line(st)}",
+          flush=True)
+    assert st["converged"] == 1
+    assert st["low_precision_flops"] > 0
+    assert rel_o <= 1e-6 and rel_d <= 1e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,bound", [(1, 1e-6), (2, 1e-5)])
+def test_refined_capped_2d_near_fp64_oracle(precision, bound):
+    """Rank cap 16 binds (the FP64 sweep is still 7e-6 from the discrete solution after 20
+    half-sweeps), so the iterate depends on the rounding path; FP32 tracks the FP64 path to the
+    target, BF16 (fallbacks change the path) is held to a looser bound and its error is printed."""
     prob = workloads.small_2d()
     ctx = tnfem.Context(0)
     P = tnfem.Problem(ctx, prob)
@@ -71,11 +102,9 @@ def test_refined_small_2d_matches_fp64_oracle(precision):
                               oamen.Options(tol=1e-8, rank_cap=16, max_sweeps=20))
     ug, uo = tt.tt_full(U.cores), tt.tt_full(X)
     rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
-    print(f"precision {precision}: rel.diff vs FP64 oracle {rel:.2e}, refinements {st['refinements']}, "
-          f"low-precision flops {st['low_precision_flops']:.3e} of {st['flops']:.3e}, "
-          f"FP64 fallbacks {st['precision_fallbacks']}", flush=True)
-    assert st["low_precision_flops"] > 0  # low-precision applies were used
-    assert rel <= 1e-6
+    print(f"precision {precision} (cap 16): rel.diff vs FP64 oracle {rel:.2e}, {_stats_line(st)}", flush=True)
+    assert st["low_precision_flops"] > 0
+    assert rel <= bound
     ctx.close()
 
 

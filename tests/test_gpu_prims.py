@@ -46,7 +46,8 @@ def test_qr_matches_definition(ctx, m, n):
 
 
 SVD_CASES = [(1, 1, "rand"), (16, 8, "rand"), (256, 32, "rand"), (512, 68, "rand"), (40, 40, "graded"),
-             (128, 64, "lowrank"), (1024, 132, "rand"), (7, 30, "rand"), (64, 64, "zero")]
+             (128, 64, "lowrank"), (1024, 132, "rand"), (7, 30, "rand"), (64, 64, "zero"), (100, 63, "rand"),
+             (70, 17, "graded")]
 
 
 @pytest.mark.parametrize("m,n,kind", SVD_CASES)
@@ -56,9 +57,10 @@ def test_svd_matches_lapack(ctx, m, n, kind):
     if kind == "rand":
         A = rng.standard_normal((m, n))
     elif kind == "graded":
-        U, _ = np.linalg.qr(rng.standard_normal((m, m)))
-        V, _ = np.linalg.qr(rng.standard_normal((n, n)))
-        A = (U * np.logspace(0, -12, n)) @ V.T
+        c = min(m, n)
+        U, _ = np.linalg.qr(rng.standard_normal((m, c)))
+        V, _ = np.linalg.qr(rng.standard_normal((n, c)))
+        A = (U * np.logspace(0, -12, c)) @ V.T
     elif kind == "lowrank":
         A = rng.standard_normal((m, 5)) @ rng.standard_normal((5, n))
     else:
