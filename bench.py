@@ -24,6 +24,10 @@ if ROOT not in sys.path:
 
 METRIC = "solves/s + p50/p99 latency at 1e-6 rel. error; contraction TFLOP/s vs peak"
 PEAK_FP64_MFMA_TFLOPS = 78.6
+# HBM bytes per launch of fused_apply32_kernel<0> on the cube128 workload: FETCH_SIZE and
+# WRITE_SIZE per dispatch, each scaled by what the counter reads for a 256 MiB copy
+# (profiles/fused_apply_cube128_f64_cap32.md).  Valid while that kernel is unchanged.
+FUSED_APPLY_TRAFFIC_BYTES = 4264407.6
 
 WORKLOADS = {
     # name: (problem factory args, solve options, description)
@@ -94,6 +98,9 @@ def main():
     ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the high-rank reference solves")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 10 device-to-device copies of MIB MiB (to calibrate HBM byte counters)")
     ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=8, help="serving: worker slots")
     args = ap.parse_args()
@@ -101,6 +108,18 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is not sharded across GPUs.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": {"read": 8 * n, "write": 8 * n}, "copies": 10}))
+        return
 
     from paper_2501_12151_amd import tnfem
 
@@ -130,22 +149,10 @@ def main():
     st = stats[-1]
     roof = None
     if not args.no_profile:
-        _, pst, _ = P.solve(profile=1, **opts)
-        ms, fl, nl = pst["contraction_ms"], pst["contraction_flops"], pst["contraction_launches"]
-        achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-        roof = {
-            "bound": "mfma",
-            "kernel": "gemm_grouped_kernel (all contraction launches of one solve)",
-            "achieved": achieved,
-            "peak": PEAK_FP64_MFMA_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
-            "traffic": None,
-            "launches": nl,
-            "avg_launch_us": 1e3 * ms / max(nl, 1),
-            "flops_per_launch": fl / max(nl, 1),
-            "contraction_ms_per_solve": ms,
-        }
+        roof = roofline(P, opts)
+    accuracy = None
+    if not args.no_accuracy:
+        accuracy = accuracy_vs_reference(P, u, opts)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, st["local_applies"])
@@ -177,10 +184,66 @@ def main():
             "cg_iters": st["cg_iters"], "max_rank": st["max_rank"], "counted_flops": st["flops"],
             "median_latency_s": statistics.median(lat),
         },
+        "accuracy": accuracy,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def roofline(P, opts):
+    """Live roofline of the dominant contraction kernel, the fused local apply (row a2):
+    one more solve with per-launch HIP events on the library stream around every
+    contraction launch.  achieved = algorithmic flops of the launches that did work
+    (sparse-operator term counts at the actual ranks) / summed event time of all its
+    launches; the all-contraction rate (grouped GEMMs included) is reported beside it."""
+    _, pst, _ = P.solve(profile=1, **opts)
+    ms, fl, nl = pst["apply_kernel_ms"], pst["apply_kernel_flops"], pst["apply_kernel_launches"]
+    achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    cms, cfl, cnl = pst["contraction_ms"], pst["contraction_flops"], pst["contraction_launches"]
+    return {
+        "bound": "mfma",
+        "kernel": "fused_apply32_kernel<0> (fused local operator apply, FP64 MFMA, ranks <= 32)",
+        "achieved": achieved,
+        "peak": PEAK_FP64_MFMA_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+        "traffic": FUSED_APPLY_TRAFFIC_BYTES if opts.get("precision", 0) == 0 else None,
+        "traffic_unit": "bytes per launch (PMC, copy-calibrated)",
+        "launches_per_solve": nl,
+        "avg_launch_us": 1e3 * ms / max(nl, 1),
+        "flops_per_launch": fl / max(nl, 1),
+        "all_contractions": {
+            "kernels": "fused_apply32_kernel<0> + gemm_grouped_kernel<*>",
+            "launches_per_solve": cnl, "ms_per_solve": cms,
+            "tflops": cfl / (cms * 1e-3) / 1e12 if cms > 0 else 0.0,
+        },
+    }
+
+
+def accuracy_vs_reference(P, u, opts, ref_caps=(64, 96), ref_sweeps=30):
+    """Relative displacement error of the timed solve against high-rank FP64 solves of the
+    same problem, computed by the library in TT format (no densification).  The two
+    references differ only in their rank cap; their mutual difference bounds how far the
+    larger one is from converged."""
+    refs = {}
+    for cap in ref_caps:
+        r, rst, _ = P.solve(rank_cap=cap, tol=1e-9, max_sweeps=ref_sweeps)
+        refs[cap] = (r, rst)
+        print(f"reference cap {cap}: {rst['seconds']:.2f} s, max local residual {rst['final_max_res']:.2e}",
+              file=sys.stderr, flush=True)
+    top = refs[ref_caps[-1]][0]
+    err = u.rel_diff(top)
+    ref_gap = refs[ref_caps[0]][0].rel_diff(top)
+    return {
+        "rel_error_vs_reference": err,
+        "reference": f"same problem, FP64, rank cap {ref_caps[-1]}, tol 1e-9, {ref_sweeps} half-sweeps "
+                     f"(max local residual {refs[ref_caps[-1]][1]['final_max_res']:.2e})",
+        "reference_cap_gap": {"caps": list(ref_caps), "rel_diff": ref_gap},
+        "target": 1e-6,
+        "meets_target": bool(err <= 1e-6),
+        "rank_cap_of_timed_solve": opts["rank_cap"],
+    }
 
 
 def serving(args):

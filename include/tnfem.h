@@ -136,9 +136,15 @@ typedef struct {
   double low_precision_flops; /* counted flops done with FP32/BF16 operands */
   long long precision_fallbacks; /* precision > 0: local solves finished in FP64 after a restart
                                     that did not lower the FP64 residual */
-  double contraction_ms;  /* profile = 1: summed device time of the contraction launches */
-  double contraction_flops; /* profile = 1: algorithmic flops of those launches */
+  double contraction_ms;  /* profile = 1: summed device time of the contraction launches (grouped
+                             GEMM and fused local apply, HIP events around each kernel) */
+  double contraction_flops; /* profile = 1: algorithmic flops of the launches that did work (CG
+                               launches queued after convergence return at once: time, no flops) */
   long long contraction_launches; /* profile = 1: number of timed launches */
+  double apply_kernel_ms; /* profile = 1: the same for the fused local-apply kernel alone (the
+                             precision of the solve) */
+  double apply_kernel_flops;
+  long long apply_kernel_launches;
 } tnfem_solve_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -213,6 +219,12 @@ int tnfem_tt_copy_cores(const tnfem_tt* t, double* dst, size_t n);
 /* Entries at multi-indices idx[n][ncores] (host). */
 int tnfem_tt_eval(const tnfem_tt* t, const int64_t* idx, size_t n, double* out);
 int tnfem_tt_destroy(tnfem_tt* t);
+/* Frobenius norm of the TT (host FP64: QR of each unfolding, R carried forward). */
+int tnfem_tt_norm(const tnfem_tt* t, double* out);
+/* ||a - b|| / ||b|| (||a - b|| if b = 0) for TTs of equal mode sizes, in TT format: the
+ * difference is the block TT of ranks r_a + r_b, whose norm is taken as above, so nearly
+ * equal TTs do not cancel.  Host FP64; cost O(sum_k n_k (r_a + r_b)^3). */
+int tnfem_tt_rel_diff(const tnfem_tt* a, const tnfem_tt* b, double* out);
 
 /* ---------------------------------------------------------------- host assembly export
  * Host-only (no device needed).  Dense copies of the operator's cores, for

@@ -10,6 +10,7 @@
 #include "assembly.hpp"
 #include "common.hpp"
 #include "engine.hpp"
+#include "hostla.hpp"
 
 struct tnfem_ctx {
   tnfem::Context c;
@@ -228,6 +229,80 @@ int tnfem_tt_eval(const tnfem_tt* t, const int64_t* idx, size_t n, double* out) 
       }
       out[q] = v[0];
     }
+    return TNFEM_OK;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Frobenius norm of a TT by left-orthogonalisation: QR of each unfolding, the R
+// factor carried into the next core; the norm is that of the last carried core.
+double tt_norm_host(std::vector<int> modes, std::vector<int> ranks, std::vector<std::vector<double>> cores) {
+  const int K = (int)modes.size();
+  for (int k = 0; k + 1 < K; ++k) {
+    const int m = ranks[k] * modes[k], nc = ranks[k + 1];
+    std::vector<double> Q, R;
+    tnfem::hostla::qr(m, nc, cores[k].data(), Q, R);
+    const int c = std::min(m, nc);
+    const int cols = modes[k + 1] * ranks[k + 2];
+    std::vector<double> next((size_t)c * cols);
+    tnfem::hostla::gemm(c, cols, nc, R.data(), cores[k + 1].data(), next.data());
+    cores[k + 1].swap(next);
+    ranks[k + 1] = c;
+  }
+  double s = 0.0;
+  for (double v : cores[K - 1]) s += v * v;
+  return std::sqrt(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tnfem_tt_norm(const tnfem_tt* t, double* out) {
+  return guarded([&] {
+    if (!t || !out) fail(TNFEM_EINVAL, "NULL argument");
+    *out = tt_norm_host(t->t.modes, t->t.ranks, t->t.cores);
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_tt_rel_diff(const tnfem_tt* a, const tnfem_tt* b, double* out) {
+  return guarded([&] {
+    if (!a || !b || !out) fail(TNFEM_EINVAL, "NULL argument");
+    const auto& A = a->t;
+    const auto& B = b->t;
+    const int K = (int)A.modes.size();
+    if (K < 1 || B.modes != A.modes) fail(TNFEM_EINVAL, "TTs have different mode sizes");
+    // a - b as a TT of ranks ra + rb: first core [A_0, -B_0], middle block diagonal, last [A; B]
+    std::vector<int> ranks(K + 1);
+    std::vector<std::vector<double>> cores(K);
+    ranks[0] = 1;
+    ranks[K] = 1;
+    for (int k = 1; k < K; ++k) ranks[k] = A.ranks[k] + B.ranks[k];
+    for (int k = 0; k < K; ++k) {
+      const int n = A.modes[k];
+      const int ral = A.ranks[k], rar = A.ranks[k + 1], rbl = B.ranks[k], rbr = B.ranks[k + 1];
+      const int rl = ranks[k], rr = ranks[k + 1];
+      cores[k].assign((size_t)rl * n * rr, 0.0);
+      const int bl_off = k == 0 ? 0 : ral;       // row offset of B's block
+      const int br_off = k == K - 1 ? 0 : rar;   // column offset of B's block
+      const double bsign = k == 0 ? -1.0 : 1.0;
+      for (int x = 0; x < ral; ++x)
+        for (int i = 0; i < n; ++i)
+          for (int y = 0; y < rar; ++y)
+            cores[k][((size_t)x * n + i) * rr + y] = A.cores[k][((size_t)x * n + i) * rar + y];
+      for (int x = 0; x < rbl; ++x)
+        for (int i = 0; i < n; ++i)
+          for (int y = 0; y < rbr; ++y)
+            cores[k][((size_t)(x + bl_off) * n + i) * rr + y + br_off] +=
+                bsign * B.cores[k][((size_t)x * n + i) * rbr + y];
+    }
+    const double nd = tt_norm_host(A.modes, ranks, std::move(cores));
+    const double nb = tt_norm_host(B.modes, B.ranks, B.cores);
+    *out = nb > 0.0 ? nd / nb : nd;
     return TNFEM_OK;
   });
 }

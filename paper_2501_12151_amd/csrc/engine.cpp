@@ -899,8 +899,11 @@ struct Sweep {
       int kit = 0;
       const int budget = prec ? std::min(o.cg_maxit - total_its, lp_pass_cap) : o.cg_maxit - total_its;
       a.maxit = budget;
+      const size_t pmark = profile_mark();
+      const double fl0 = fl.total, fll0 = fl_low;
       while (!done && kit <= budget) {
         for (int c = 0; c < chunk && kit <= budget; ++c, ++kit) {
+          set_profile_tag(kit);
           if (fused) {
             launch_fused_apply(f, apply_flops, st, prec);
             fl.total += apply_flops;
@@ -917,7 +920,20 @@ struct Sweep {
         readback();
         done = hint()[0];
       }
-      total_its += hint()[1];
+      set_profile_tag(-1);
+      // the apply of launch index k runs before iteration k's convergence test, so a
+      // pass that stopped after `its` iterations ran its + 1 applies; later launches
+      // of the last chunk returned at once and are not counted
+      const int its = hint()[1];
+      const int ran = std::min(kit, its + 1);
+      profile_drop_from(pmark, ran);
+      if (kit > 0) {
+        const double frac = (double)ran / kit;
+        fl.total = fl0 + (fl.total - fl0) * frac;
+        fl_low = fll0 + (fl_low - fll0) * frac;
+      }
+      applies += ran;
+      total_its += its;
       if (prec == 0 || converged_at_entry || total_its >= o.cg_maxit) break;
       const double res_now = fp64_restart();
       refinements++;
@@ -936,7 +952,6 @@ struct Sweep {
       fallbacks++;
     }
     cg_iters += total_its;
-    applies += total_its;
     if (verbose >= 2)
       fprintf(stderr, "[tnfem]   core %d (orient %d) p %d n %d t %d N %d %s R %d/%d res %.3e cg %d\n", k, orient, p,
               n[k], t, N, pl.dense ? "dense" : "sparse", R(k), R(k + 1), res, total_its);
@@ -1116,11 +1131,19 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   stats.contraction_ms = 0.0;
   stats.contraction_flops = 0.0;
   stats.contraction_launches = 0;
+  stats.apply_kernel_ms = 0.0;
+  stats.apply_kernel_flops = 0.0;
+  stats.apply_kernel_launches = 0;
   if (o.profile && P.ws->profile) {
     double fl = 0.0;
-    stats.contraction_ms = P.ws->profile->total_ms(&fl);
+    long cnt = 0;
+    stats.contraction_ms = P.ws->profile->total_ms(&fl, -1, &cnt);
     stats.contraction_flops = fl;
-    stats.contraction_launches = (long long)P.ws->profile->used;
+    stats.contraction_launches = cnt;
+    const int kind = o.precision ? PROF_FUSED_LOW : PROF_FUSED;
+    stats.apply_kernel_ms = P.ws->profile->total_ms(&fl, kind, &cnt);
+    stats.apply_kernel_flops = fl;
+    stats.apply_kernel_launches = cnt;
   }
   if (sw.nan_seen || !std::isfinite(last)) return TNFEM_ENAN;
   return converged ? TNFEM_OK : TNFEM_ENOTCONV;

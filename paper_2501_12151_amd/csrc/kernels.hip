@@ -10,6 +10,7 @@
 //   fixed order, so results do not depend on timing).
 // * Householder QR and one-sided Jacobi SVD run in one workgroup each; the
 //   matrices are at most (r n) x (r + rho) and (r + rho)^2.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -256,7 +257,16 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
 }
 
 static thread_local GemmProfile* g_prof = nullptr;
+static thread_local int g_prof_tag = -1;
 void set_gemm_profile(GemmProfile* p) { g_prof = p; }
+void set_profile_tag(int tag) { g_prof_tag = tag; }
+size_t profile_mark() { return g_prof ? g_prof->used : 0; }
+void profile_drop_from(size_t mark, int min_tag) {
+  GemmProfile* p = g_prof;
+  if (!p) return;
+  for (size_t i = mark; i < p->used; ++i)
+    if (p->tag[i] >= min_tag) p->valid[i] = 0;
+}
 static thread_local double* g_splitk = nullptr;
 static thread_local size_t g_splitk_cap = 0;
 void set_gemm_splitk_buffer(double* p, size_t cap) {
@@ -268,15 +278,19 @@ GemmProfile::~GemmProfile() {
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 
-double GemmProfile::total_ms(double* total_flops) {
+double GemmProfile::total_ms(double* total_flops, int want, long* launches) {
   double ms = 0.0, fl = 0.0;
+  long cnt = 0;
   if (used > 0) (void)hipEventSynchronize(ev[2 * used - 1]);
   for (size_t i = 0; i < used; ++i) {
+    if (want >= 0 && kind[i] != want) continue;
     float t = 0.0f;
     if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) ms += t;
-    fl += flops[i];
+    if (valid[i]) fl += flops[i];
+    ++cnt;
   }
   if (total_flops) *total_flops = fl;
+  if (launches) *launches = cnt;
   return ms;
 }
 
@@ -296,15 +310,26 @@ static hipEvent_t* prof_begin(hipStream_t s) {
     if (hipEventCreate(&e) != hipSuccess) throw Error(TNFEM_EDEVICE, "hipEventCreate");
     p->ev.push_back(e);
   }
-  hipEvent_t* pair = &p->ev[2 * p->used];
-  (void)hipEventRecord(pair[0], s);
-  return pair;
+  return &p->ev[2 * p->used];
 }
 
-static void prof_end(hipEvent_t* pair, double flops, hipStream_t s) {
+// Launch; with a profile pair, the dispatch itself stamps the pair with the kernel's
+// start and end (the same timestamps a kernel trace reports).
+#define TN_LAUNCH(ev, kernel, grid, block, shm, s, ...)                                      \
+  do {                                                                                   \
+    if (ev)                                                                              \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, s, (ev)[0], (ev)[1], 0, __VA_ARGS__); \
+    else                                                                                 \
+      hipLaunchKernelGGL(kernel, grid, block, shm, s, __VA_ARGS__);                      \
+  } while (0)
+
+static void prof_end(hipEvent_t* pair, double flops, hipStream_t s, int kind) {
+  (void)s;
   if (!pair) return;
-  (void)hipEventRecord(pair[1], s);
   g_prof->flops.push_back(flops);
+  g_prof->kind.push_back(kind);
+  g_prof->tag.push_back(g_prof_tag);
+  g_prof->valid.push_back(1);
   g_prof->used++;
 }
 
@@ -334,8 +359,8 @@ static void launch_tiled(GemmArgs a, const GemmDesc& d, hipStream_t s) {
   a.partial = d.partial ? d.partial : g_splitk;
   dim3 grid(a.ntiles, d.ngroups, a.ksplit);
   hipEvent_t* ev = prof_begin(s);
-  hipLaunchKernelGGL((gemm_grouped_kernel<WMB, WNB>), grid, dim3(256), 0, s, a);
-  prof_end(ev, d.flops, s);
+  TN_LAUNCH(ev, (gemm_grouped_kernel<WMB, WNB>), grid, dim3(256), 0, s, a);
+  prof_end(ev, d.flops, s, PROF_GEMM);
   TN_CHECK_LAUNCH();
   if (a.ksplit > 1) {
     hipLaunchKernelGGL((splitk_reduce_kernel<TM, TN>), dim3(a.ntiles, d.ngroups, (TM * TN + 255) / 256), dim3(256), 0,
@@ -707,7 +732,7 @@ int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles) {
 }
 
 static hipEvent_t* prof_begin(hipStream_t s);
-static void prof_end(hipEvent_t* pair, double flops, hipStream_t s);
+static void prof_end(hipEvent_t* pair, double flops, hipStream_t s, int kind);
 
 void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision) {
   f.tiles_n = (f.t + 31) / 32;
@@ -716,16 +741,16 @@ void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision)
   const bool small = f.p <= 32 && f.q <= 32 && f.s <= 32 && f.t <= 32;
   const dim3 g32(1, f.n, f.ksplit), g(f.ntiles, f.n, f.ksplit);
   if (precision == 1) {
-    if (small) hipLaunchKernelGGL(fused_apply32_kernel<1>, g32, dim3(256), 0, s, f);
-    else hipLaunchKernelGGL(fused_apply_kernel<1>, g, dim3(256), 0, s, f);
+    if (small) TN_LAUNCH(ev, fused_apply32_kernel<1>, g32, dim3(256), 0, s, f);
+    else TN_LAUNCH(ev, fused_apply_kernel<1>, g, dim3(256), 0, s, f);
   } else if (precision == 2) {
-    if (small) hipLaunchKernelGGL(fused_apply32_kernel<2>, g32, dim3(256), 0, s, f);
-    else hipLaunchKernelGGL(fused_apply_kernel<2>, g, dim3(256), 0, s, f);
+    if (small) TN_LAUNCH(ev, fused_apply32_kernel<2>, g32, dim3(256), 0, s, f);
+    else TN_LAUNCH(ev, fused_apply_kernel<2>, g, dim3(256), 0, s, f);
   } else {
-    if (small) hipLaunchKernelGGL(fused_apply32_kernel<0>, g32, dim3(256), 0, s, f);
-    else hipLaunchKernelGGL(fused_apply_kernel<0>, g, dim3(256), 0, s, f);
+    if (small) TN_LAUNCH(ev, fused_apply32_kernel<0>, g32, dim3(256), 0, s, f);
+    else TN_LAUNCH(ev, fused_apply_kernel<0>, g, dim3(256), 0, s, f);
   }
-  prof_end(ev, flops, s);
+  prof_end(ev, flops, s, precision ? PROF_FUSED_LOW : PROF_FUSED);
   TN_CHECK_LAUNCH();
 }
 

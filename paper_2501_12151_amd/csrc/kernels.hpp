@@ -42,19 +42,37 @@ struct GemmDesc {
 
 void launch_gemm(const GemmDesc& g, hipStream_t s);
 
-// Optional per-launch timing of launch_gemm on the calling thread: while a profile
-// is installed, every launch is bracketed by HIP events on its stream.
+// Optional per-launch timing of the contraction kernels (launch_gemm and
+// launch_fused_apply) on the calling thread: while a profile is installed, every
+// launch is bracketed by HIP events on its stream and tagged with its kind and
+// the current tag (the CG iteration it belongs to, -1 outside CG loops).
+enum ProfKind { PROF_GEMM = 0, PROF_FUSED = 1, PROF_FUSED_LOW = 2 };
 struct GemmProfile {
   std::vector<hipEvent_t> ev;
   std::vector<double> flops;
+  std::vector<int> kind, tag;
+  std::vector<char> valid;
   size_t used = 0;
   size_t limit = 200000;
   ~GemmProfile();
-  void reset() { used = 0; flops.clear(); }
-  // Waits for the recorded events; returns total milliseconds and fills total flops.
-  double total_ms(double* total_flops);
+  void reset() {
+    used = 0;
+    flops.clear();
+    kind.clear();
+    tag.clear();
+    valid.clear();
+  }
+  // Waits for the recorded events; total milliseconds and number of the launches of
+  // the given kind (-1: all kinds), and the flops of those that did work.
+  double total_ms(double* total_flops, int kind = -1, long* launches = nullptr);
 };
 void set_gemm_profile(GemmProfile* p);
+void set_profile_tag(int tag);
+size_t profile_mark();
+// Marks the launches recorded since `mark` whose tag is >= min_tag as having done
+// no work (CG launches queued after convergence, which return at once): their time
+// still counts, their flops do not.
+void profile_drop_from(size_t mark, int min_tag);
 // Default split-K partial buffer for launches of the calling thread whose
 // descriptor names none (nullptr: no splitting).
 void set_gemm_splitk_buffer(double* p, size_t cap_doubles);

@@ -57,6 +57,8 @@ class SolveStats(C.Structure):
         ("low_precision_flops", C.c_double), ("precision_fallbacks", C.c_longlong),
         ("contraction_ms", C.c_double),
         ("contraction_flops", C.c_double), ("contraction_launches", C.c_longlong),
+        ("apply_kernel_ms", C.c_double), ("apply_kernel_flops", C.c_double),
+        ("apply_kernel_launches", C.c_longlong),
     ]
 
     def as_dict(self):
@@ -91,6 +93,8 @@ _sig = {
     "tnfem_tt_copy_cores": (C.c_int, [_vp, _dp, C.c_size_t]),
     "tnfem_tt_eval": (C.c_int, [_vp, C.POINTER(C.c_int64), C.c_size_t, _dp]),
     "tnfem_tt_destroy": (C.c_int, [_vp]),
+    "tnfem_tt_norm": (C.c_int, [_vp, _dp]),
+    "tnfem_tt_rel_diff": (C.c_int, [_vp, _vp, _dp]),
     "tnfem_export_operator": (C.c_int, [C.POINTER(ProblemDesc), _ip, _ip, _ip, _dp, C.c_size_t, C.POINTER(C.c_size_t)]),
     "tnfem_export_load": (C.c_int, [C.POINTER(ProblemDesc), _ip, _ip, _ip, _dp, C.c_size_t, C.POINTER(C.c_size_t)]),
     "tnfem_prim_local_apply": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
@@ -220,6 +224,16 @@ class TT:
             _lib.tnfem_tt_destroy(self._h)
             self._h = None
 
+    @classmethod
+    def from_cores(cls, cores):
+        """Library TT holding copies of the given cores ([r_k, n_k, r_{k+1}] arrays)."""
+        modes = (C.c_int * len(cores))(*[int(c.shape[1]) for c in cores])
+        ranks = (C.c_int * (len(cores) + 1))(*([int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]))
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for c in cores]))
+        h = _vp()
+        _check(_lib.tnfem_tt_create(len(cores), modes, ranks, flat.ctypes.data_as(_dp), C.byref(h)))
+        return cls(h)
+
     def shape(self):
         nc = C.c_int()
         modes = (C.c_int * 64)()
@@ -238,6 +252,17 @@ class TT:
             out.append(buf[off:off + cnt].reshape(ranks[k], n, ranks[k + 1]).copy())
             off += cnt
         return out
+
+    def norm(self):
+        out = C.c_double()
+        _check(_lib.tnfem_tt_norm(self._h, C.byref(out)))
+        return out.value
+
+    def rel_diff(self, ref):
+        """||self - ref|| / ||ref||, computed by the library in TT format."""
+        out = C.c_double()
+        _check(_lib.tnfem_tt_rel_diff(self._h, ref._h, C.byref(out)))
+        return out.value
 
     def eval(self, idx):
         idx = np.ascontiguousarray(idx, dtype=np.int64)

@@ -109,3 +109,35 @@ def test_default_options():
     o = tnfem.default_opts()
     assert (o.rank_cap, o.rho, o.init_rank, o.seed_x, o.seed_z, o.precision) == (32, 4, 2, 1, 2, 0)
     assert o.tol == 1e-8
+
+
+def _random_tt(rng, modes, ranks):
+    return [rng.standard_normal((ranks[k], n, ranks[k + 1])) for k, n in enumerate(modes)]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tt_norm_and_rel_diff_match_dense(seed):
+    rng = np.random.default_rng(seed)
+    modes = [3, 4, 2, 5]
+    a = _random_tt(rng, modes, [1, 3, 5, 4, 1])
+    b = _random_tt(rng, modes, [1, 2, 6, 3, 1])
+    A, B = tnfem.TT.from_cores(a), tnfem.TT.from_cores(b)
+    fa, fb = tt.tt_full(a), tt.tt_full(b)
+    assert abs(A.norm() - np.linalg.norm(fa)) <= 1e-13 * np.linalg.norm(fa)
+    ref = np.linalg.norm(fa - fb) / np.linalg.norm(fb)
+    assert abs(A.rel_diff(B) - ref) <= 1e-13 * ref
+    assert A.rel_diff(A) <= 1e-15
+
+
+def test_tt_rel_diff_resolves_small_differences():
+    # b = a + 1e-9 * c: the relative difference must come out to a few digits, where
+    # ||a||^2 + ||b||^2 - 2 <a, b> would lose it to cancellation
+    rng = np.random.default_rng(5)
+    modes = [4] * 6
+    a = _random_tt(rng, modes, [1, 4, 6, 6, 6, 4, 1])
+    c = _random_tt(rng, modes, [1, 2, 2, 2, 2, 2, 1])
+    b = tt.tt_add(a, c, 1.0, 1e-9)
+    A, B = tnfem.TT.from_cores(a), tnfem.TT.from_cores(b)
+    fa, fb = tt.tt_full(a), tt.tt_full(b)
+    ref = np.linalg.norm(fa - fb) / np.linalg.norm(fb)
+    assert abs(A.rel_diff(B) - ref) <= 1e-6 * ref
