@@ -23,20 +23,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "solves/s + p50/p99 latency at 1e-6 rel. error; contraction TFLOP/s vs peak"
-PEAK_FP64_MFMA_TFLOPS = 78.6
 # HBM bytes per launch of fused_apply32_kernel<0> on the cube128 workload: FETCH_SIZE and
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a 256 MiB copy
 # (profiles/fused_apply_cube128_f64_cap32.md).  Valid while that kernel is unchanged.
 FUSED_APPLY_TRAFFIC_BYTES = 4264407.6
 
+PEAKS = {0: 78.6, 1: 157.3, 2: 2500.0}  # dense MFMA TFLOP/s: FP64, FP32, BF16
+DTYPES = {0: "f64", 1: "f32 (FP32 MFMA local applies, FP64 refinement)",
+          2: "bf16 (BF16 MFMA local applies, FP32 accumulate, FP64 refinement)"}
+
 WORKLOADS = {
-    # name: (problem factory args, solve options, description)
+    # refs: (rank cap, tol, half-sweeps) of the FP64 reference solves for the accuracy block
     "cube128": dict(level=7, opts=dict(rank_cap=32, tol=1e-6, max_sweeps=16),
+                    refs=[(64, 1e-9, 30), (96, 1e-9, 30)],
                     desc="3D unit cube 128^3 nodes (QTT level 7), body force (0,0,-1), x=0 clamped, E=1, nu=0.3, "
-                         "FP64, rank cap 32"),
+                         "rank cap 32"),
+    "cube1024": dict(level=10, opts=dict(rank_cap=64, tol=1e-6, max_sweeps=24),
+                     refs=[(64, 1e-8, 40), (96, 1e-9, 40)],
+                     desc="3D unit cube 1024^3 nodes (QTT level 10), all faces clamped, load of the manufactured field "
+                          "u_i = c_i sin(pi x) sin(pi y) sin(pi z), c ~ N(0,1) (seed 0), E=1, nu=0.3, rank cap 64"),
     "square32": dict(level=5, opts=dict(rank_cap=16, tol=1e-8, max_sweeps=20),
+                     refs=[(64, 1e-10, 30)],
                      desc="2D plane strain 32x32 nodes (QTT level 5), x-traction 1 on x=1, x=0 clamped, E=1, nu=0.3, "
-                          "FP64, rank cap 16"),
+                          "rank cap 16"),
 }
 
 
@@ -54,7 +63,34 @@ def problem_for(name):
 
     if name == "cube128":
         return workloads.cube_body_force(WORKLOADS[name]["level"])
+    if name == "cube1024":
+        return workloads.cube_manufactured(WORKLOADS[name]["level"])
     return workloads.small_2d()
+
+
+def manufactured_field_cores(level, c):
+    """QTT of the nodal field u_i = c_i sin(pi x) sin(pi y) sin(pi z), x = ix / (2^level - 1),
+    levels most significant bit first, mode (bx 2 + by) 2 + bz, component core last: each axis
+    carries the state [cos phi, sin phi] of its partial angle and a bit b of weight w rotates
+    it by b w, so every level core is a Kronecker product of three 2 x 2 rotations (rank 8)."""
+    import numpy as np
+
+    h = 1.0 / (2 ** level - 1)
+    cores = []
+    for k in range(level):
+        w = np.pi * h * 2 ** (level - 1 - k)
+        rot = [np.array([[np.cos(b * w), np.sin(b * w)], [-np.sin(b * w), np.cos(b * w)]]) for b in (0, 1)]
+        core = np.zeros((8, 8, 8))
+        for m in range(8):
+            bx, by, bz = (m >> 2) & 1, (m >> 1) & 1, m & 1
+            core[:, m, :] = np.kron(np.kron(rot[bx], rot[by]), rot[bz])
+        if k == 0:
+            core = core[:1]  # start state (cos 0, sin 0) on every axis: row index 0
+        cores.append(core)
+    comp = np.zeros((8, 3, 1))
+    comp[7, :, 0] = c  # sin component on all three axes
+    cores.append(comp)
+    return cores
 
 
 def cpu_baseline(name, gpu_applies, budget_s=20.0):
@@ -96,6 +132,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1, 2),
+                    help="0 FP64; 1 FP32 local applies; 2 BF16 local applies (both refined in FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the high-rank reference solves")
@@ -128,7 +166,7 @@ def main():
         return
     wl = WORKLOADS[args.workload]
     prob = problem_for(args.workload)
-    opts = dict(wl["opts"])
+    opts = dict(wl["opts"], precision=args.precision)
     ctx = tnfem.Context(0)
     P = tnfem.Problem(ctx, prob)
     info = P.info()
@@ -152,7 +190,7 @@ def main():
         roof = roofline(P, opts)
     accuracy = None
     if not args.no_accuracy:
-        accuracy = accuracy_vs_reference(P, u, opts)
+        accuracy = accuracy_vs_reference(P, u, opts, args.workload, prob)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, st["local_applies"])
@@ -168,10 +206,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": wl["desc"],
+            "workload": wl["desc"] + ", " + DTYPES[args.precision],
             "dofs": prob["dim"] * 2 ** (prob["dim"] * prob["level"]),
             "mpo_ranks": info["mpo_ranks"],
             "rank_cap": opts["rank_cap"],
@@ -193,57 +231,76 @@ def main():
 
 def roofline(P, opts):
     """Live roofline of the dominant contraction kernel, the fused local apply (row a2):
-    one more solve with per-launch HIP events on the library stream around every
-    contraction launch.  achieved = algorithmic flops of the launches that did work
-    (sparse-operator term counts at the actual ranks) / summed event time of all its
-    launches; the all-contraction rate (grouped GEMMs included) is reported beside it."""
+    one more solve with start/stop events stamped by every contraction dispatch.
+    achieved = algorithmic flops of the launches that did work (nonzero-term counts at the
+    actual ranks) / summed duration of all its launches; the all-contraction rate
+    (grouped GEMMs included) is reported beside it."""
+    prec = opts.get("precision", 0)
     _, pst, _ = P.solve(profile=1, **opts)
     ms, fl, nl = pst["apply_kernel_ms"], pst["apply_kernel_flops"], pst["apply_kernel_launches"]
     achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     cms, cfl, cnl = pst["contraction_ms"], pst["contraction_flops"], pst["contraction_launches"]
+    small = opts["rank_cap"] <= 32
+    kname = f"fused_apply32_kernel<{prec}>" if small else \
+        f"fused_apply_kernel<{prec}> / fused_apply32_kernel<{prec}> (by the ranks of each core step)"
+    what = {0: "FP64 MFMA", 1: "FP32 MFMA", 2: "BF16 MFMA, FP32 accumulate"}[prec]
     return {
         "bound": "mfma",
-        "kernel": "fused_apply32_kernel<0> (fused local operator apply, FP64 MFMA, ranks <= 32)",
+        "kernel": f"{kname} (fused local operator apply, {what})",
         "achieved": achieved,
-        "peak": PEAK_FP64_MFMA_TFLOPS,
+        "peak": PEAKS[prec],
         "unit": "TFLOP/s",
-        "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
-        "traffic": FUSED_APPLY_TRAFFIC_BYTES if opts.get("precision", 0) == 0 else None,
+        "frac": achieved / PEAKS[prec],
+        "traffic": FUSED_APPLY_TRAFFIC_BYTES if (prec == 0 and small and P.info()["ncores"] == 8) else None,
         "traffic_unit": "bytes per launch (PMC, copy-calibrated)",
         "launches_per_solve": nl,
         "avg_launch_us": 1e3 * ms / max(nl, 1),
         "flops_per_launch": fl / max(nl, 1),
         "all_contractions": {
-            "kernels": "fused_apply32_kernel<0> + gemm_grouped_kernel<*>",
+            "kernels": f"{kname} + gemm_grouped_kernel<*>",
             "launches_per_solve": cnl, "ms_per_solve": cms,
             "tflops": cfl / (cms * 1e-3) / 1e12 if cms > 0 else 0.0,
         },
     }
 
 
-def accuracy_vs_reference(P, u, opts, ref_caps=(64, 96), ref_sweeps=30):
-    """Relative displacement error of the timed solve against high-rank FP64 solves of the
-    same problem, computed by the library in TT format (no densification).  The two
-    references differ only in their rank cap; their mutual difference bounds how far the
-    larger one is from converged."""
-    refs = {}
-    for cap in ref_caps:
-        r, rst, _ = P.solve(rank_cap=cap, tol=1e-9, max_sweeps=ref_sweeps)
-        refs[cap] = (r, rst)
-        print(f"reference cap {cap}: {rst['seconds']:.2f} s, max local residual {rst['final_max_res']:.2e}",
+def accuracy_vs_reference(P, u, opts, name, prob):
+    """Relative displacement error of the timed solve, computed by the library in TT format
+    (no densification), against FP64 reference solves of the same problem with larger rank
+    caps / tighter tolerances (their mutual difference bounds how far the last one is from
+    converged); for low precision also against the FP64 solve with the same options; for
+    the manufactured load also against the closed-form field (which adds the O(h^2)
+    discretisation error)."""
+    from paper_2501_12151_amd import tnfem
+
+    refs = []
+    for cap, tol, sw in WORKLOADS[name]["refs"]:
+        r, rst, _ = P.solve(rank_cap=cap, tol=tol, max_sweeps=sw)
+        refs.append((r, rst, cap, tol, sw))
+        print(f"reference cap {cap} tol {tol:g}: {rst['seconds']:.2f} s, max local residual {rst['final_max_res']:.2e}",
               file=sys.stderr, flush=True)
-    top = refs[ref_caps[-1]][0]
+    top, tst, cap, tol, sw = refs[-1]
     err = u.rel_diff(top)
-    ref_gap = refs[ref_caps[0]][0].rel_diff(top)
-    return {
+    out = {
         "rel_error_vs_reference": err,
-        "reference": f"same problem, FP64, rank cap {ref_caps[-1]}, tol 1e-9, {ref_sweeps} half-sweeps "
-                     f"(max local residual {refs[ref_caps[-1]][1]['final_max_res']:.2e})",
-        "reference_cap_gap": {"caps": list(ref_caps), "rel_diff": ref_gap},
+        "reference": f"same problem, FP64, rank cap {cap}, tol {tol:g}, {sw} half-sweeps "
+                     f"(max local residual {tst['final_max_res']:.2e}, max rank {tst['max_rank']})",
         "target": 1e-6,
         "meets_target": bool(err <= 1e-6),
         "rank_cap_of_timed_solve": opts["rank_cap"],
     }
+    if len(refs) > 1:
+        out["reference_gap"] = {"between": [f"cap {c} tol {t:g}" for _, _, c, t, _ in refs],
+                                "rel_diff": refs[0][0].rel_diff(top)}
+    if opts.get("precision", 0):
+        o64 = dict(opts, precision=0)
+        u64, _, _ = P.solve(**o64)
+        out["rel_diff_vs_fp64_same_options"] = u.rel_diff(u64)
+    if "manufactured_c" in prob:
+        exact = tnfem.TT.from_cores(manufactured_field_cores(prob["level"], prob["manufactured_c"]))
+        out["rel_error_vs_closed_form"] = u.rel_diff(exact)
+        out["reference_vs_closed_form"] = top.rel_diff(exact)
+    return out
 
 
 def serving(args):
