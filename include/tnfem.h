@@ -175,22 +175,41 @@ int tnfem_problem_info(const tnfem_problem* p, int* ncores, int* modes, int* mpo
  * is filled. */
 int tnfem_solve(tnfem_problem* p, const tnfem_solve_opts* opts, tnfem_tt** u_out, tnfem_solve_stats* stats);
 
+/* Lockstep solve of n problems (1 <= n <= 16) of the same dimension and level,
+ * created in the same context, FP64 (opts->precision 0, no profile): every problem
+ * takes exactly the steps of tnfem_solve and gets the same result bit for bit,
+ * while the local CG iterations of all problems still iterating are issued as
+ * shared launches (one fused local apply, one direction update and one vector
+ * update per iteration for the whole batch).  Serving batches of requests of one
+ * shape bucket (the request server groups queued requests this way).
+ * problems[n] (caller-owned); u_out[n] receives a TT per problem whose status[n]
+ * is TNFEM_OK or TNFEM_ENOTCONV (NULL otherwise); stats[n] may be NULL.  Returns
+ * TNFEM_OK when the batch ran (per-problem outcomes in status), else the error. */
+int tnfem_solve_batch(tnfem_problem* const* problems, int n, const tnfem_solve_opts* opts, tnfem_tt** u_out,
+                      tnfem_solve_stats* stats, int* status);
+
 /* ---------------------------------------------------------------- serving
  * A server runs many solves on one device at once.  Requests are queued at
  * submission; each of `slots` worker slots (its own HIP stream) takes the oldest
- * queued request, assembles and uploads its problem, and starts the solve as soon
- * as the request's device bytes (problem + workspace) fit in the HBM budget next
- * to the running requests, so requests arriving while others run are admitted as
- * slots and memory free up and their work overlaps on the device.  Requests share
- * no device data: a result is the same alone and in a mix.  Latency is measured
- * from submission to completion.  hbm_budget_bytes = 0 means 80% of the free
- * device memory at creation.  A request larger than the whole budget fails with
- * TNFEM_EBUDGET.  Calls are thread safe. */
+ * queued request together with the other queued requests of its shape bucket
+ * (same dimension, level and solve options, FP64; at most max_batch, default 8),
+ * assembles and uploads their problems, and starts them as soon as their device
+ * bytes (problems + workspaces) fit in the HBM budget next to the running
+ * requests, so requests arriving while others run are admitted as slots and
+ * memory free up, and the work of different slots overlaps on the device.  A
+ * bucket of several requests runs as one lockstep batch (tnfem_solve_batch:
+ * shared launches of the local CG iterations).  Requests share no arithmetic: a
+ * result is bit for bit the same alone and in a mix.  Latency is measured from
+ * submission to the request's completion.  hbm_budget_bytes = 0 means 80% of
+ * the free device memory at creation.  A request larger than the whole budget
+ * fails with TNFEM_EBUDGET.  Calls are thread safe. */
 typedef struct tnfem_server tnfem_server;
 typedef struct {
   int queued, running, peak_running;
   long long completed;
   size_t bytes_in_use, peak_bytes, budget_bytes;
+  int peak_batch;              /* largest lockstep batch run so far */
+  long long batched_requests;  /* requests that ran in a batch of two or more */
 } tnfem_server_state;
 
 int tnfem_server_create(int device, int slots, size_t hbm_budget_bytes, tnfem_server** out);
@@ -203,6 +222,8 @@ int tnfem_server_submit(tnfem_server* s, const tnfem_problem_desc* desc, const t
 int tnfem_server_poll(tnfem_server* s, long long ticket, int wait, tnfem_tt** u_out, tnfem_solve_stats* stats,
                       double* latency_s);
 int tnfem_server_info(tnfem_server* s, tnfem_server_state* info);
+/* Largest lockstep batch a slot forms (1 .. 16; 1 turns batching off). */
+int tnfem_server_set_max_batch(tnfem_server* s, int max_batch);
 /* Stops the workers after their running requests; queued requests are dropped. */
 int tnfem_server_destroy(tnfem_server* s);
 

@@ -160,6 +160,36 @@ int tnfem_solve(tnfem_problem* p, const tnfem_solve_opts* opts, tnfem_tt** u_out
   });
 }
 
+int tnfem_solve_batch(tnfem_problem* const* problems, int n, const tnfem_solve_opts* opts, tnfem_tt** u_out,
+                      tnfem_solve_stats* stats, int* status) {
+  return guarded([&] {
+    if (!problems || !u_out || !status || n < 1) fail(TNFEM_EINVAL, "NULL argument or empty batch");
+    tnfem_solve_opts o;
+    if (opts) o = *opts;
+    else tnfem_default_opts(&o);
+    std::vector<tnfem::Problem*> ps;
+    for (int i = 0; i < n; ++i) {
+      if (!problems[i]) fail(TNFEM_EINVAL, "NULL problem %d", i);
+      ps.push_back(problems[i]->p.get());
+    }
+    std::vector<tnfem::HostTT> outs;
+    std::vector<tnfem_solve_stats> st;
+    std::vector<int> rcs;
+    tnfem::run_solve_batch(ps, o, outs, st, rcs);
+    for (int i = 0; i < n; ++i) {
+      status[i] = rcs[i];
+      if (stats) stats[i] = st[i];
+      u_out[i] = nullptr;
+      if (rcs[i] == TNFEM_OK || rcs[i] == TNFEM_ENOTCONV) {
+        auto t = std::make_unique<tnfem_tt>();
+        t->t = std::move(outs[i]);
+        u_out[i] = t.release();
+      }
+    }
+    return TNFEM_OK;
+  });
+}
+
 int tnfem_tt_create(int ncores, const int* modes, const int* ranks, const double* cores, tnfem_tt** out) {
   return guarded([&] {
     if (ncores < 1 || !modes || !ranks || !cores || !out) fail(TNFEM_EINVAL, "invalid TT description");

@@ -1044,7 +1044,228 @@ struct Sweep {
 
 }  // namespace
 
-int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_stats& stats) {
+// ----------------------------------------------------------------------------- lockstep batches
+
+namespace {
+
+// Device + pinned host copies of the per-request argument arrays of the shared launches.
+struct BatchArgs {
+  FusedArgs* d_f = nullptr;
+  CgIterArgs* d_a = nullptr;
+  FusedArgs* h_f = nullptr;
+  CgIterArgs* h_a = nullptr;
+  explicit BatchArgs(int n) {
+    hip_check(hipMalloc(&d_f, sizeof(FusedArgs) * n), "hipMalloc batch args");
+    hip_check(hipMalloc(&d_a, sizeof(CgIterArgs) * n), "hipMalloc batch args");
+    hip_check(hipHostMalloc(reinterpret_cast<void**>(&h_f), sizeof(FusedArgs) * n, hipHostMallocDefault),
+              "hipHostMalloc batch args");
+    hip_check(hipHostMalloc(reinterpret_cast<void**>(&h_a), sizeof(CgIterArgs) * n, hipHostMallocDefault),
+              "hipHostMalloc batch args");
+  }
+  ~BatchArgs() {
+    if (d_f) (void)hipFree(d_f);
+    if (d_a) (void)hipFree(d_a);
+    if (h_f) (void)hipHostFree(h_f);
+    if (h_a) (void)hipHostFree(h_a);
+  }
+};
+
+// The local solves of core k of several sweeps (same chain, same orientation, FP64):
+// per request exactly the steps of Sweep::solve_core, with the CG iterations of all
+// requests issued as shared launches (one fused apply, one direction update, one
+// vector update per iteration).  Returns each request's local residual.
+std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& args, hipStream_t st) {
+  const int nb = (int)S.size();
+  struct Loc {
+    int p = 0, t = 0, N = 0;
+    const Plan* pl = nullptr;
+    CgIterArgs a;
+    FusedArgs f;
+    bool fused = false, explicit_mat = false, done = false;
+    double res = 0.0, apply_flops = 0.0, fl0 = 0.0;
+  };
+  std::vector<Loc> L(nb);
+  for (int r = 0; r < nb; ++r) {
+    Sweep& w = *S[r];
+    Workspace& W = w.W;
+    Loc& c = L[r];
+    set_gemm_splitk_buffer(W.splitk, W.splitk_cap);
+    c.p = w.xr[k];
+    c.t = w.xr[k + 1];
+    c.N = c.p * w.n[k] * c.t;
+    c.pl = &w.plan(k);
+    local_rhs(c.p, w.n[k], w.sb(k), w.sb(k + 1), c.t, w.Eb[k], w.B(k), w.Eb[k + 1], W.Tb, W.g, st, &w.fl);
+    launch_local_diag(c.p, w.n[k], c.t, w.R(k), w.R(k + 1), w.EA[k], w.EA[k + 1], c.pl->dg_beg, c.pl->dg_b,
+                      c.pl->dg_e, c.pl->dg_v, W.dinv, st);
+    w.apply(k, c.p, c.p, c.t, c.t, w.EA[k], w.X[k], w.EA[k + 1], W.q, nullptr);
+    w.applies++;
+    CgIterArgs& a = c.a;
+    a.N = c.N;
+    a.x = w.X[k];
+    a.r = W.r;
+    a.z = W.z;
+    a.p = W.p;
+    a.q = W.w;
+    a.dinv = W.dinv;
+    a.scal = W.scal;
+    a.flag = W.flag;
+    a.parts = W.part;
+    a.maxit = w.o.cg_maxit;
+    a.n = w.n[k];
+    a.t = c.t;
+    a.nb_upd = cg_dir_blocks(c.N);
+    a.nb_dir = cg_dir_blocks(c.N);
+    launch_cg_init2(a, W.g, W.q, w.o.tol, st);
+    hip_check(hipMemcpyAsync(W.host_pinned, W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flag readback");
+    hip_check(hipMemcpyAsync(static_cast<char*>(W.host_pinned) + 64, W.scal + CG_RES, sizeof(double),
+                             hipMemcpyDeviceToHost, st),
+              "res readback");
+  }
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  int max_n = 0;
+  for (int r = 0; r < nb; ++r) {
+    Sweep& w = *S[r];
+    Workspace& W = w.W;
+    Loc& c = L[r];
+    const Plan& pl = *c.pl;
+    c.res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+    if (!std::isfinite(c.res)) w.nan_seen = 1;
+    c.done = w.hint()[0] != 0;
+    c.fused = !pl.dense;
+    const size_t m_need = (size_t)pl.Rl * w.n[k] * w.n[k] * (size_t)c.t * c.t;
+    c.explicit_mat = pl.dense && !c.done && (size_t)c.N <= W.bloc_n && m_need <= W.mloc_cap;
+    if (c.explicit_mat) {
+      launch_local_matrix(c.p, w.n[k], c.t, pl.Rl, pl.Rr, w.EA[k], pl.A2, w.EA[k + 1], W.Mloc, W.Bloc, st);
+      w.fl.total += 2.0 * m_need * pl.Rr + 2.0 * (double)c.N * c.N * pl.Rl;
+    }
+    FusedArgs& f = c.f;
+    if (c.fused) {
+      f.L = w.EA[k];
+      f.x = W.z;
+      f.Rt = w.EA[k + 1];
+      f.partial = W.fpart;
+      f.p = c.p;
+      f.q = c.p;
+      f.s = c.t;
+      f.t = c.t;
+      f.Rl = w.R(k);
+      f.Rr = w.R(k + 1);
+      f.n = w.n[k];
+      f.slot_b = pl.sp_slot_b;
+      f.slot_i = pl.sp_slot_i;
+      f.beg = pl.sp_ap_beg;
+      f.ta = pl.sp_ap_a;
+      f.tb = pl.sp_ap_b;
+      f.tv = pl.sp_ap_v;
+      f.ksplit = fused_apply_splits(w.n[k], c.p, c.t, pl.sp_ap_max, W.fpart_cap);
+      f.skip = W.flag + CG_DONE;
+      fused_prepare(f);
+      c.a.ksplit = f.ksplit;
+      c.a.partial = W.fpart;
+      c.a.tiles_n = (c.t + 31) / 32;
+      c.a.ntiles = ((c.p + 31) / 32) * c.a.tiles_n;
+    } else {
+      c.a.ksplit = 0;
+      c.a.w = W.q;
+    }
+    c.apply_flops = 2.0 * c.p * c.p * c.t * pl.sp_nslot + 2.0 * c.p * c.t * c.t * pl.sp_n_ap;
+    c.fl0 = w.fl.total;
+    max_n = std::max(max_n, w.n[k]);
+  }
+  // requests still iterating, split by apply kind; argument arrays to the device once
+  std::vector<int> cg, small, large, other;
+  for (int r = 0; r < nb; ++r) {
+    if (L[r].done) continue;
+    cg.push_back(r);
+    if (!L[r].fused) other.push_back(r);
+    else if (fused_is_small(L[r].f)) small.push_back(r);
+    else large.push_back(r);
+  }
+  int kit = 0;
+  if (!cg.empty()) {
+    FusedBatch fb_small, fb_large;
+    int large_tiles = 1;
+    int nf = 0;
+    auto fill = [&](const std::vector<int>& ids, FusedBatch& fb) {
+      fb.args = args.d_f + nf;
+      fb.nreq = (int)ids.size();
+      fb.zoff[0] = 0;
+      for (int i = 0; i < fb.nreq; ++i) {
+        const FusedArgs& f = L[ids[i]].f;
+        args.h_f[nf + i] = f;
+        fb.zoff[i + 1] = fb.zoff[i] + f.ksplit;
+        large_tiles = std::max(large_tiles, f.ntiles);
+      }
+      nf += fb.nreq;
+    };
+    fill(small, fb_small);
+    fill(large, fb_large);
+    CgBatch dir, upd;
+    dir.args = upd.args = args.d_a;
+    dir.nreq = upd.nreq = (int)cg.size();
+    for (size_t i = 0; i < cg.size(); ++i) {
+      args.h_a[i] = L[cg[i]].a;
+      dir.boff[i + 1] = dir.boff[i] + L[cg[i]].a.nb_dir;
+      upd.boff[i + 1] = upd.boff[i] + L[cg[i]].a.nb_upd;
+    }
+    if (nf)
+      hip_check(hipMemcpyAsync(args.d_f, args.h_f, sizeof(FusedArgs) * nf, hipMemcpyHostToDevice, st),
+                "batch args upload");
+    hip_check(hipMemcpyAsync(args.d_a, args.h_a, sizeof(CgIterArgs) * cg.size(), hipMemcpyHostToDevice, st),
+              "batch args upload");
+    const int budget = S[0]->o.cg_maxit;
+    const int chunk = 8;
+    bool any = true;
+    while (any && kit <= budget) {
+      for (int c = 0; c < chunk && kit <= budget; ++c, ++kit) {
+        if (fb_small.nreq) launch_fused_apply_batch(fb_small, max_n, 1, true, st, 0);
+        if (fb_large.nreq) launch_fused_apply_batch(fb_large, max_n, large_tiles, false, st, 0);
+        for (int r : small) S[r]->fl.total += L[r].apply_flops;
+        for (int r : large) S[r]->fl.total += L[r].apply_flops;
+        for (int r : other) {
+          Sweep& w = *S[r];
+          if (L[r].explicit_mat) {
+            launch_dense_matvec(L[r].N, w.W.Bloc, w.W.z, w.W.q, w.W.flag + CG_DONE, st);
+            w.fl.total += 2.0 * (double)L[r].N * L[r].N;
+          } else {
+            set_gemm_splitk_buffer(w.W.splitk, w.W.splitk_cap);
+            w.apply(k, L[r].p, L[r].p, L[r].t, L[r].t, w.EA[k], w.W.z, w.EA[k + 1], w.W.q, w.W.flag + CG_DONE);
+          }
+        }
+        launch_cg_reduce_dir_batch(dir, kit, st);
+        launch_cg_update2_batch(upd, kit, st);
+      }
+      for (int r : cg)
+        hip_check(hipMemcpyAsync(S[r]->W.host_pinned, S[r]->W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st),
+                  "flag readback");
+      hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+      any = false;
+      for (int r : cg) any = any || S[r]->hint()[0] == 0;
+    }
+  }
+  std::vector<double> res(nb);
+  for (int r = 0; r < nb; ++r) {
+    Sweep& w = *S[r];
+    Loc& c = L[r];
+    int its = 0, ran = 0;
+    if (!c.done) {
+      its = w.hint()[1];
+      ran = std::min(kit, its + 1);
+      if (kit > 0) w.fl.total = c.fl0 + (w.fl.total - c.fl0) * ((double)ran / kit);
+    }
+    w.applies += ran;
+    w.cg_iters += its;
+    if (w.verbose >= 2)
+      fprintf(stderr, "[tnfem]   core %d (orient %d, batch of %d) p %d n %d t %d N %d %s res %.3e cg %d\n", k,
+              w.orient, nb, c.p, w.n[k], c.t, c.N, c.pl->dense ? "dense" : "sparse", c.res, its);
+    res[r] = c.res;
+  }
+  return res;
+}
+
+}  // namespace
+
+static void check_opts(const tnfem_solve_opts& o) {
   TNFEM_REQUIRE(o.rank_cap >= 1 && o.rank_cap <= 252, "rank_cap must be in [1, 252]");
   TNFEM_REQUIRE(o.rho >= 0 && o.rho <= 64, "rho must be in [0, 64]");
   TNFEM_REQUIRE(o.init_rank >= 1 && o.init_rank <= o.rank_cap, "init_rank must be in [1, rank_cap]");
@@ -1052,11 +1273,56 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   TNFEM_REQUIRE(o.max_sweeps >= 1, "max_sweeps must be >= 1");
   TNFEM_REQUIRE(o.cg_maxit >= 0, "cg_maxit must be >= 0");
   TNFEM_REQUIRE(o.precision >= 0 && o.precision <= 2, "precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
-  hip_check(hipSetDevice(P.ctx->device), "hipSetDevice");
+}
+
+static void prepare_workspace(Problem& P, const tnfem_solve_opts& o) {
   const int rho = std::max(o.rho, 1);
   P.ensure_workspace(o.rank_cap, rho);
   if ((size_t)P.ws->cap * P.maxn * (P.ws->cap + rho) * 8 > (size_t)1 << 34)
     fail(TNFEM_EBUDGET, "workspace too large");
+}
+
+// Back to the forward orientation, hand the buffer permutation back to the
+// workspace and download the solution cores.
+static void finish_sweep(Problem& P, Sweep& sw, HostTT& out) {
+  if (sw.orient) sw.reverse();
+  sw.sync();
+  P.ws->X = sw.X;
+  P.ws->Z = sw.Z;
+  P.ws->Xspare = sw.xspare;
+  P.ws->Zspare = sw.zspare;
+  out.modes = sw.n;
+  out.ranks = sw.xr;
+  out.cores.assign(P.K, {});
+  for (int k = 0; k < P.K; ++k) {
+    out.cores[k].resize((size_t)sw.xr[k] * sw.n[k] * sw.xr[k + 1]);
+    hip_check(hipMemcpyAsync(out.cores[k].data(), sw.X[k], out.cores[k].size() * 8, hipMemcpyDeviceToHost, sw.st),
+              "download");
+  }
+  sw.sync();
+}
+
+static void fill_stats(const Sweep& sw, int sweeps, int converged, double last, double seconds,
+                       tnfem_solve_stats& stats) {
+  stats = tnfem_solve_stats{};
+  stats.sweeps = sweeps;
+  stats.converged = converged;
+  stats.final_max_res = last;
+  stats.cg_iters = sw.cg_iters;
+  stats.local_applies = sw.applies;
+  stats.flops = sw.fl.total;
+  stats.seconds = seconds;
+  stats.max_rank = *std::max_element(sw.xr.begin(), sw.xr.end());
+  stats.refinements = sw.refinements;
+  stats.low_precision_flops = sw.fl_low;
+  stats.precision_fallbacks = sw.fallbacks;
+}
+
+int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_stats& stats) {
+  check_opts(o);
+  hip_check(hipSetDevice(P.ctx->device), "hipSetDevice");
+  const int rho = std::max(o.rho, 1);
+  prepare_workspace(P, o);
   const auto t0 = std::chrono::steady_clock::now();
   tnfem_solve_opts oo = o;
   oo.rho = rho;
@@ -1099,41 +1365,9 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
       break;
     }
   }
-  if (sw.orient) sw.reverse();
-  sw.sync();
-  // the buffers were permuted by the swaps: hand the permutation back to the workspace
-  P.ws->X = sw.X;
-  P.ws->Z = sw.Z;
-  P.ws->Xspare = sw.xspare;
-  P.ws->Zspare = sw.zspare;
-  // download
-  out.modes = sw.n;
-  out.ranks = sw.xr;
-  out.cores.assign(P.K, {});
-  for (int k = 0; k < P.K; ++k) {
-    out.cores[k].resize((size_t)sw.xr[k] * sw.n[k] * sw.xr[k + 1]);
-    hip_check(hipMemcpyAsync(out.cores[k].data(), sw.X[k], out.cores[k].size() * 8, hipMemcpyDeviceToHost, sw.st),
-              "download");
-  }
-  sw.sync();
+  finish_sweep(P, sw, out);
   const auto t1 = std::chrono::steady_clock::now();
-  stats.sweeps = sweeps;
-  stats.converged = converged;
-  stats.final_max_res = last;
-  stats.cg_iters = sw.cg_iters;
-  stats.local_applies = sw.applies;
-  stats.flops = sw.fl.total;
-  stats.seconds = std::chrono::duration<double>(t1 - t0).count();
-  stats.max_rank = *std::max_element(sw.xr.begin(), sw.xr.end());
-  stats.refinements = sw.refinements;
-  stats.low_precision_flops = sw.fl_low;
-  stats.precision_fallbacks = sw.fallbacks;
-  stats.contraction_ms = 0.0;
-  stats.contraction_flops = 0.0;
-  stats.contraction_launches = 0;
-  stats.apply_kernel_ms = 0.0;
-  stats.apply_kernel_flops = 0.0;
-  stats.apply_kernel_launches = 0;
+  fill_stats(sw, sweeps, converged, last, std::chrono::duration<double>(t1 - t0).count(), stats);
   if (o.profile && P.ws->profile) {
     double fl = 0.0;
     long cnt = 0;
@@ -1147,6 +1381,99 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   }
   if (sw.nan_seen || !std::isfinite(last)) return TNFEM_ENAN;
   return converged ? TNFEM_OK : TNFEM_ENOTCONV;
+}
+
+int run_solve_batch(std::vector<Problem*>& Ps, const tnfem_solve_opts& o, std::vector<HostTT>& outs,
+                    std::vector<tnfem_solve_stats>& stats, std::vector<int>& rcs) {
+  check_opts(o);
+  const int nb = (int)Ps.size();
+  TNFEM_REQUIRE(nb >= 1 && nb <= FB_MAX, "a batch holds 1 .. %d problems", FB_MAX);
+  TNFEM_REQUIRE(o.precision == 0, "batched solves run in FP64 (precision 0)");
+  TNFEM_REQUIRE(!o.profile, "batched solves do not record per-launch profiles");
+  Context* ctx = Ps[0]->ctx;
+  for (Problem* P : Ps) {
+    TNFEM_REQUIRE(P->ctx == ctx, "all problems of a batch must share one context");
+    TNFEM_REQUIRE(P->K == Ps[0]->K && P->modes == Ps[0]->modes,
+                  "all problems of a batch must have the same dimension and level");
+  }
+  hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+  const auto t0 = std::chrono::steady_clock::now();
+  tnfem_solve_opts oo = o;
+  oo.rho = std::max(o.rho, 1);
+  struct Unset {
+    ~Unset() { set_gemm_splitk_buffer(nullptr, 0); }
+  } unset;
+  std::vector<std::unique_ptr<Sweep>> sweeps;
+  for (Problem* P : Ps) {
+    prepare_workspace(*P, o);
+    set_gemm_splitk_buffer(P->ws->splitk, P->ws->splitk_cap);
+    auto sw = std::make_unique<Sweep>(*P, oo);
+    sw->upload_initial();
+    sw->reverse();
+    sw->qr_pass();
+    sw->reverse();
+    sweeps.push_back(std::move(sw));
+  }
+  BatchArgs args(nb);
+  outs.assign(nb, HostTT{});
+  stats.assign(nb, tnfem_solve_stats{});
+  rcs.assign(nb, TNFEM_ENOTCONV);
+  std::vector<int> nsw(nb, 0), conv(nb, 0);
+  std::vector<double> last(nb, INFINITY);
+  std::vector<int> active(nb);
+  for (int r = 0; r < nb; ++r) active[r] = r;
+  const int K = Ps[0]->K;
+  auto finish = [&](int r) {
+    finish_sweep(*Ps[r], *sweeps[r], outs[r]);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(*sweeps[r], nsw[r], conv[r], last[r], secs, stats[r]);
+    rcs[r] = (sweeps[r]->nan_seen || !std::isfinite(last[r])) ? TNFEM_ENAN : (conv[r] ? TNFEM_OK : TNFEM_ENOTCONV);
+  };
+  for (int it = 0; it < o.max_sweeps && !active.empty(); ++it) {
+    std::vector<double> mr(nb, 0.0);
+    std::vector<int> live = active;
+    for (int k = 0; k < K && !live.empty(); ++k) {
+      std::vector<Sweep*> S;
+      for (int r : live) S.push_back(sweeps[r].get());
+      const std::vector<double> res = batch_solve_core(S, k, args, ctx->stream);
+      std::vector<int> keep;
+      for (size_t i = 0; i < live.size(); ++i) {
+        const int r = live[i];
+        mr[r] = std::max(mr[r], res[i]);
+        if (sweeps[r]->nan_seen) {
+          mr[r] = NAN;
+          continue;
+        }
+        keep.push_back(r);
+      }
+      live.swap(keep);
+      if (k < K - 1)
+        for (int r : live) {
+          set_gemm_splitk_buffer(Ps[r]->ws->splitk, Ps[r]->ws->splitk_cap);
+          sweeps[r]->truncate_enrich(k);
+        }
+    }
+    std::vector<int> still;
+    for (int r : active) {
+      ++nsw[r];
+      last[r] = mr[r];
+      Sweep& w = *sweeps[r];
+      if (w.nan_seen || !std::isfinite(last[r])) {
+        finish(r);
+        continue;
+      }
+      w.reverse();
+      if (last[r] <= o.tol) {
+        conv[r] = 1;
+        finish(r);
+        continue;
+      }
+      still.push_back(r);
+    }
+    active.swap(still);
+  }
+  for (int r : active) finish(r);
+  return TNFEM_OK;
 }
 
 }  // namespace tnfem

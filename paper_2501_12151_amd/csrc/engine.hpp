@@ -137,6 +137,11 @@ void dev_env_update(Problem& P, const Plan& pl, int p, int q, int s, int t, cons
                     const double* X, double* Lnew, hipStream_t st, Flops* f);
 
 int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_stats& st);
+// Lockstep solve of several problems of the same dimension and level in one context
+// (FP64): per problem the same steps and results as run_solve, with the CG iterations
+// of all problems issued as shared launches.  Per-problem status in rcs.
+int run_solve_batch(std::vector<Problem*>& Ps, const tnfem_solve_opts& o, std::vector<HostTT>& outs,
+                    std::vector<tnfem_solve_stats>& stats, std::vector<int>& rcs);
 
 }  // namespace tnfem
 

@@ -601,15 +601,13 @@ __device__ inline void mfma_k32(const typename Prec<P>::T (*sA)[33], const typen
 // contracted index): the next term's operand tiles are loaded into registers
 // while the current term's two MFMA products run.
 template <int P>
-__global__ __launch_bounds__(256) void fused_apply32_kernel(FusedArgs f) {
+__device__ __forceinline__ void fused_apply32_body(const FusedArgs& f, const int grp, const int z) {
   using T = typename Prec<P>::T;
   using Acc = typename Prec<P>::Acc;
   __shared__ T sA[32][33];
   __shared__ T sB[32][33];
   __shared__ T sT[32][33];
   __shared__ T sR[32][33];
-  if (f.skip && *f.skip) return;
-  const int grp = blockIdx.y, z = blockIdx.z;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
   const int lrow = lane % 16, lk = lane / 16;
@@ -662,15 +660,19 @@ __global__ __launch_bounds__(256) void fused_apply32_kernel(FusedArgs f) {
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void fused_apply_kernel(FusedArgs f) {
+__global__ __launch_bounds__(256) void fused_apply32_kernel(FusedArgs f) {
+  if (f.skip && *f.skip) return;
+  fused_apply32_body<P>(f, blockIdx.y, blockIdx.z);
+}
+
+template <int P>
+__device__ __forceinline__ void fused_apply_body(const FusedArgs& f, const int grp, const int tile, const int z) {
   using T = typename Prec<P>::T;
   using Acc = typename Prec<P>::Acc;
   __shared__ T sA[32][33];
   __shared__ T sB[32][33];
   __shared__ T sT[32][33];
   __shared__ T sR[32][33];
-  if (f.skip && *f.skip) return;
-  const int grp = blockIdx.y, tile = blockIdx.x, z = blockIdx.z;
   const int m0 = (tile / f.tiles_n) * 32, n0 = (tile % f.tiles_n) * 32;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
@@ -721,6 +723,36 @@ __global__ __launch_bounds__(256) void fused_apply_kernel(FusedArgs f) {
   for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + acc_row<P>(qq, lk)) * 32 + wn * 16 + lrow] = (double)acc[qq];
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void fused_apply_kernel(FusedArgs f) {
+  if (f.skip && *f.skip) return;
+  fused_apply_body<P>(f, blockIdx.y, blockIdx.x, blockIdx.z);
+}
+
+// Shared launch of the fused apply of several requests (same mode count n): grid z
+// runs over the requests' split ranges zoff[r] .. zoff[r + 1]; every block does
+// exactly what the single-request launch does for its (request, mode, tile, split).
+template <int P>
+__global__ __launch_bounds__(256) void fused_apply32_batch_kernel(FusedBatch b) {
+  const int z = blockIdx.z;
+  int r = 0;
+  while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
+  const FusedArgs f = b.args[r];
+  if (f.skip && *f.skip) return;
+  fused_apply32_body<P>(f, blockIdx.y, z - b.zoff[r]);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void fused_apply_batch_kernel(FusedBatch b) {
+  const int z = blockIdx.z;
+  int r = 0;
+  while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
+  const FusedArgs f = b.args[r];
+  if (f.skip && *f.skip) return;
+  if ((int)blockIdx.x >= f.ntiles) return;
+  fused_apply_body<P>(f, blockIdx.y, blockIdx.x, z - b.zoff[r]);
+}
+
 int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles) {
   const int ntiles = ((p + 31) / 32) * ((t + 31) / 32);
   long ks = (128 + (long)n * ntiles - 1) / ((long)n * ntiles);
@@ -751,6 +783,31 @@ void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision)
     else TN_LAUNCH(ev, fused_apply_kernel<0>, g, dim3(256), 0, s, f);
   }
   prof_end(ev, flops, s, precision ? PROF_FUSED_LOW : PROF_FUSED);
+  TN_CHECK_LAUNCH();
+}
+
+void fused_prepare(FusedArgs& f) {
+  f.tiles_n = (f.t + 31) / 32;
+  f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
+}
+
+bool fused_is_small(const FusedArgs& f) { return f.p <= 32 && f.q <= 32 && f.s <= 32 && f.t <= 32; }
+
+void launch_fused_apply_batch(const FusedBatch& b, int n, int max_ntiles, bool small, hipStream_t s, int precision) {
+  if (b.nreq <= 0) return;
+  if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "fused apply batch: too many requests");
+  const int zt = b.zoff[b.nreq];
+  const dim3 g32(1, n, zt), g(max_ntiles, n, zt);
+  if (precision == 1) {
+    if (small) hipLaunchKernelGGL(fused_apply32_batch_kernel<1>, g32, dim3(256), 0, s, b);
+    else hipLaunchKernelGGL(fused_apply_batch_kernel<1>, g, dim3(256), 0, s, b);
+  } else if (precision == 2) {
+    if (small) hipLaunchKernelGGL(fused_apply32_batch_kernel<2>, g32, dim3(256), 0, s, b);
+    else hipLaunchKernelGGL(fused_apply_batch_kernel<2>, g, dim3(256), 0, s, b);
+  } else {
+    if (small) hipLaunchKernelGGL(fused_apply32_batch_kernel<0>, g32, dim3(256), 0, s, b);
+    else hipLaunchKernelGGL(fused_apply_batch_kernel<0>, g, dim3(256), 0, s, b);
+  }
   TN_CHECK_LAUNCH();
 }
 
@@ -791,14 +848,14 @@ __device__ inline double sum_parts(const double* a, int nb) {
 
 // w = sum of split partials (or w given directly); p = z + beta p; q = w + beta q; block partials of p.q.
 // First checks convergence of iteration k from the update's partials.
-__global__ __launch_bounds__(256) void cg_reduce_dir_kernel(CgIterArgs a, int k) {
+__device__ __forceinline__ void cg_reduce_dir_body(const CgIterArgs& a, const int k, const int bid) {
   __shared__ double red[4];
   if (a.flag[CG_DONE]) return;
   const int nb = a.nb_upd;
   const int par = k & 1;
   const double rr = sum_parts(a.parts + PART_RR + par * CG_MAXB, nb);
   if (rr <= a.scal[CG_THR2] || k >= a.maxit) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
       a.flag[CG_DONE] = 1;
       a.flag[CG_ITERS] = k;
     }
@@ -806,12 +863,12 @@ __global__ __launch_bounds__(256) void cg_reduce_dir_kernel(CgIterArgs a, int k)
   }
   const double rz = sum_parts(a.parts + PART_RZ + par * CG_MAXB, nb);
   const double beta = (k == 0) ? 0.0 : rz / a.scal[CG_RZ0 + (par ^ 1)];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bid == 0 && threadIdx.x == 0) {
     a.scal[CG_RZ0 + par] = rz;
     a.flag[CG_ITERS] = k;
   }
   double loc = 0.0;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < a.N; e += gridDim.x * 256) {
+  for (int e = bid * 256 + threadIdx.x; e < a.N; e += a.nb_dir * 256) {
     double w;
     if (a.ksplit > 0) {
       // e = (row * n + grp) * t + col
@@ -840,17 +897,20 @@ __global__ __launch_bounds__(256) void cg_reduce_dir_kernel(CgIterArgs a, int k)
     loc += pi * qi;
   }
   const double tot = block_sum<256>(loc, red);
-  if (threadIdx.x == 0) a.parts[PART_PQ + blockIdx.x] = tot;
+  if (threadIdx.x == 0) a.parts[PART_PQ + bid] = tot;
 }
 
+__global__ __launch_bounds__(256) void cg_reduce_dir_kernel(CgIterArgs a, int k) { cg_reduce_dir_body(a, k, blockIdx.x); }
+
+
 // x += alpha p; r -= alpha q; z = dinv r; block partials of r.z and r.r for iteration k + 1.
-__global__ __launch_bounds__(256) void cg_update2_kernel(CgIterArgs a, int k) {
+__device__ __forceinline__ void cg_update2_body(const CgIterArgs& a, const int k, const int bid) {
   __shared__ double red[4];
   if (a.flag[CG_DONE]) return;
-  const int nb = gridDim.x;
+  const int nb = a.nb_upd;
   const double pq = sum_parts(a.parts + PART_PQ, a.nb_dir);
   if (!(pq > 0.0)) {  // breakdown: stop without updating
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
       a.flag[CG_DONE] = 2;
       a.flag[CG_ITERS] = k;
     }
@@ -858,7 +918,7 @@ __global__ __launch_bounds__(256) void cg_update2_kernel(CgIterArgs a, int k) {
   }
   const double alpha = a.scal[CG_RZ0 + (k & 1)] / pq;
   double lrz = 0.0, lrr = 0.0;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < a.N; e += nb * 256) {
+  for (int e = bid * 256 + threadIdx.x; e < a.N; e += nb * 256) {
     a.x[e] += alpha * a.p[e];
     const double ri = a.r[e] - alpha * a.q[e];
     const double zi = ri * a.dinv[e];
@@ -871,10 +931,12 @@ __global__ __launch_bounds__(256) void cg_update2_kernel(CgIterArgs a, int k) {
   const double trr = block_sum<256>(lrr, red);
   const int par = (k + 1) & 1;
   if (threadIdx.x == 0) {
-    a.parts[PART_RZ + par * CG_MAXB + blockIdx.x] = trz;
-    a.parts[PART_RR + par * CG_MAXB + blockIdx.x] = trr;
+    a.parts[PART_RZ + par * CG_MAXB + bid] = trz;
+    a.parts[PART_RR + par * CG_MAXB + bid] = trr;
   }
 }
+
+__global__ __launch_bounds__(256) void cg_update2_kernel(CgIterArgs a, int k) { cg_update2_body(a, k, blockIdx.x); }
 
 // r = g - Bx; z = dinv r; p = q = 0; block partials of r.z, r.r (parity 0);
 // the last block also derives res, thr and the skip decision for the host.
@@ -944,6 +1006,40 @@ void launch_cg_reduce_dir(const CgIterArgs& a, int k, hipStream_t s) {
 }
 void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s) {
   hipLaunchKernelGGL(cg_update2_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, k);
+  TN_CHECK_LAUNCH();
+}
+
+// Shared launches of the CG iteration kernels of several requests: grid x runs over
+// the requests' block ranges boff[r] .. boff[r + 1] (nb_dir or nb_upd blocks each).
+__device__ inline int cg_batch_request(const CgBatch& b, int x) {
+  int r = 0;
+  while (r + 1 < b.nreq && x >= b.boff[r + 1]) ++r;
+  return r;
+}
+
+__global__ __launch_bounds__(256) void cg_reduce_dir_batch_kernel(CgBatch b, int k) {
+  const int r = cg_batch_request(b, blockIdx.x);
+  const CgIterArgs a = b.args[r];
+  cg_reduce_dir_body(a, k, blockIdx.x - b.boff[r]);
+}
+
+__global__ __launch_bounds__(256) void cg_update2_batch_kernel(CgBatch b, int k) {
+  const int r = cg_batch_request(b, blockIdx.x);
+  const CgIterArgs a = b.args[r];
+  cg_update2_body(a, k, blockIdx.x - b.boff[r]);
+}
+
+void launch_cg_reduce_dir_batch(const CgBatch& b, int k, hipStream_t s) {
+  if (b.nreq <= 0) return;
+  if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "CG batch: too many requests");
+  hipLaunchKernelGGL(cg_reduce_dir_batch_kernel, dim3(b.boff[b.nreq]), dim3(256), 0, s, b, k);
+  TN_CHECK_LAUNCH();
+}
+
+void launch_cg_update2_batch(const CgBatch& b, int k, hipStream_t s) {
+  if (b.nreq <= 0) return;
+  if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "CG batch: too many requests");
+  hipLaunchKernelGGL(cg_update2_batch_kernel, dim3(b.boff[b.nreq]), dim3(256), 0, s, b, k);
   TN_CHECK_LAUNCH();
 }
 

@@ -113,6 +113,22 @@ struct FusedArgs {
   const int* skip = nullptr;
 };
 int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles);
+// Sets the tile counts of f from its ranks (launch_fused_apply does this itself).
+void fused_prepare(FusedArgs& f);
+bool fused_is_small(const FusedArgs& f);  // all ranks <= 32: the one-tile kernel
+
+// Shared launches across requests (at most FB_MAX per launch).  The argument
+// arrays live in device memory; zoff / boff are prefix sums of each request's
+// split count (fused apply) or block count (CG kernels).
+constexpr int FB_MAX = 16;
+struct FusedBatch {
+  const FusedArgs* args = nullptr;  // device array of nreq prepared FusedArgs
+  int nreq = 0;
+  int zoff[FB_MAX + 1] = {};
+};
+// All requests must have the same mode count n and all be small (or all not).
+void launch_fused_apply_batch(const FusedBatch& b, int n, int max_ntiles, bool small, hipStream_t s,
+                              int precision = 0);
 // precision: 0 FP64, 1 FP32 operands (FP32 accumulate), 2 BF16 operands (FP32 accumulate)
 void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision = 0);
 // y = sum of the partial tiles written by launch_fused_apply with the same f.
@@ -141,6 +157,13 @@ int cg_dir_blocks(int n);
 void launch_cg_init2(const CgIterArgs& a, const double* g, const double* bx, double tol, hipStream_t s);
 void launch_cg_reduce_dir(const CgIterArgs& a, int k, hipStream_t s);
 void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s);
+struct CgBatch {
+  const CgIterArgs* args = nullptr;  // device array
+  int nreq = 0;
+  int boff[FB_MAX + 1] = {};
+};
+void launch_cg_reduce_dir_batch(const CgBatch& b, int k, hipStream_t s);  // boff over nb_dir
+void launch_cg_update2_batch(const CgBatch& b, int k, hipStream_t s);     // boff over nb_upd
 
 // Jacobi preconditioner: d[a][i][c] = sum over diagonal terms (b, e, v) of group i of
 // v * L[a][b][a] * Rt[c][e][c]; dinv = 1/d where d > 0 else 1.

@@ -2,16 +2,22 @@
 // materials and loads share one GPU.
 //
 // A request is queued at submission.  Each worker slot owns a HIP stream (one
-// context); a free slot takes the oldest queued request, assembles and uploads
-// its problem, computes the device bytes its solve will hold (problem +
-// workspace) and is admitted as soon as that fits in the HBM budget next to the
-// requests already running.  Running requests' kernels are on different
-// streams, so their work overlaps on the device; nothing is shared between
-// requests, so a result does not depend on what else runs.  Latency is measured
-// from submission to completion.
+// context); a free slot takes the oldest queued request together with the
+// queued requests of the same shape bucket (same dimension, level and solve
+// options, FP64; up to max_batch of them), assembles and uploads their problems,
+// computes the device bytes their solves will hold (problem + workspace) and is
+// admitted as soon as that fits in the HBM budget next to the requests already
+// running.  A bucket of several requests is solved in lockstep with shared
+// launches of the local CG iterations (run_solve_batch); different slots run
+// on different streams, so their work overlaps on the device.  A request's
+// arithmetic does not depend on what else runs (per-request kernels and
+// reductions), so every result equals the request solved alone.  Latency is
+// measured from submission to the request's own completion.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -32,6 +38,7 @@ struct Request {
   tnfem_solve_opts opts{};
   std::chrono::steady_clock::time_point t_submit, t_done;
   int state = 0;  // 0 queued, 1 running, 2 done
+  int batch = 1;  // size of the lockstep batch it ran in
   int rc = TNFEM_OK;
   std::string error;
   HostTT result;
@@ -100,6 +107,8 @@ class Server {
     out->bytes_in_use = in_use_;
     out->peak_bytes = peak_bytes_;
     out->budget_bytes = budget_;
+    out->peak_batch = peak_batch_;
+    out->batched_requests = batched_;
   }
 
  private:
@@ -112,21 +121,34 @@ class Server {
     }
     ctx.own_stream = true;
     for (;;) {
-      Request* r = nullptr;
+      std::vector<Request*> group;
       {
         std::unique_lock<std::mutex> lk(mu_);
         cv_work_.wait(lk, [&] { return stop_ || !queue_.empty(); });
         if (stop_) break;
-        r = queue_.front();
+        Request* r = queue_.front();
         queue_.pop_front();
-        r->state = 1;
+        group.push_back(r);
+        if (batchable(r))
+          for (auto it = queue_.begin(); it != queue_.end() && (int)group.size() < max_batch_;) {
+            if (same_bucket(r, *it)) {
+              group.push_back(*it);
+              it = queue_.erase(it);
+            } else {
+              ++it;
+            }
+          }
+        for (Request* q : group) q->state = 1;
       }
-      run(ctx, r);
+      if (group.size() == 1) run(ctx, group[0]);
+      else run_group(ctx, group);
       {
         std::lock_guard<std::mutex> lk(mu_);
-        r->state = 2;
-        r->t_done = std::chrono::steady_clock::now();
-        ++completed_;
+        for (Request* q : group) {
+          q->state = 2;
+          if (q->batch == 1) q->t_done = std::chrono::steady_clock::now();
+          ++completed_;
+        }
       }
       cv_done_.notify_all();
     }
@@ -173,8 +195,116 @@ class Server {
     cv_budget_.notify_all();
   }
 
+  static bool batchable(const Request* r) {
+    return r->opts.precision == 0 && r->opts.profile == 0 && r->layer.empty();
+  }
+
+  static bool same_bucket(const Request* a, const Request* b) {
+    return batchable(b) && a->desc.dim == b->desc.dim && a->desc.level == b->desc.level &&
+           std::memcmp(&a->opts, &b->opts, sizeof(tnfem_solve_opts)) == 0;
+  }
+
+  // Admits the group's device bytes as one unit (waiting for room in the budget).
+  bool admit(size_t bytes) {
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_budget_.wait(lk, [&] { return stop_ || in_use_ + bytes <= budget_; });
+    if (stop_) return false;
+    in_use_ += bytes;
+    peak_bytes_ = std::max(peak_bytes_, in_use_);
+    return true;
+  }
+
+  void run_group(Context& ctx, std::vector<Request*>& group) {
+    std::vector<std::unique_ptr<Problem>> probs;
+    std::vector<Request*> members;
+    size_t bytes = 0;
+    for (Request* r : group) {
+      try {
+        auto P = make_problem(&ctx, r->desc);
+        const size_t b = P->arena.bytes() + P->workspace_bytes(r->opts.rank_cap, std::max(r->opts.rho, 1));
+        if (b > budget_) fail(TNFEM_EBUDGET, "request needs %zu device bytes, budget is %zu", b, budget_);
+        if (bytes + b > budget_) {  // the rest waits for another slot
+          std::lock_guard<std::mutex> lk(mu_);
+          r->state = 0;
+          queue_.push_front(r);
+          cv_work_.notify_one();
+          continue;
+        }
+        bytes += b;
+        r->bytes = b;
+        probs.push_back(std::move(P));
+        members.push_back(r);
+      } catch (const Error& e) {
+        r->rc = e.code;
+        r->error = e.what();
+        r->t_done = std::chrono::steady_clock::now();
+      }
+    }
+    group.erase(std::remove_if(group.begin(), group.end(), [](Request* r) { return r->state == 0; }), group.end());
+    if (members.empty()) return;
+    if (!admit(bytes)) {
+      for (Request* r : members) {
+        r->rc = TNFEM_EBUSY;
+        r->error = "server stopped";
+      }
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      running_ += (int)members.size();
+      peak_running_ = std::max(peak_running_, running_);
+      peak_batch_ = std::max(peak_batch_, (int)members.size());
+      if (members.size() > 1) batched_ += (long long)members.size();
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    try {
+      std::vector<Problem*> ps;
+      for (auto& P : probs) ps.push_back(P.get());
+      std::vector<HostTT> outs;
+      std::vector<tnfem_solve_stats> st;
+      std::vector<int> rcs;
+      run_solve_batch(ps, members[0]->opts, outs, st, rcs);
+      for (size_t i = 0; i < members.size(); ++i) {
+        Request* r = members[i];
+        r->rc = rcs[i];
+        r->stats = st[i];
+        r->result = std::move(outs[i]);
+        r->batch = (int)members.size();
+        r->t_done = t0 + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                             std::chrono::duration<double>(st[i].seconds));
+      }
+    } catch (const Error& e) {
+      for (Request* r : members) {
+        r->rc = e.code;
+        r->error = e.what();
+      }
+    } catch (const std::exception& e) {
+      for (Request* r : members) {
+        r->rc = TNFEM_EINVAL;
+        r->error = e.what();
+      }
+    }
+    probs.clear();  // frees the group's device memory before releasing its budget
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      in_use_ -= bytes;
+      running_ -= (int)members.size();
+    }
+    cv_budget_.notify_all();
+  }
+
+ public:
+  void set_max_batch(int b) {
+    std::lock_guard<std::mutex> lk(mu_);
+    max_batch_ = b;
+  }
+
+ private:
   int device_;
   size_t budget_;
+  int max_batch_ = 8;
+  int peak_batch_ = 1;
+  long long batched_ = 0;
   std::mutex mu_;
   std::condition_variable cv_work_, cv_done_, cv_budget_;
   std::deque<Request*> queue_;
@@ -269,6 +399,15 @@ int tnfem_server_info(tnfem_server* s, tnfem_server_state* info) {
   return guarded_s([&]() -> int {
     if (!s || !info) tnfem::fail(TNFEM_EINVAL, "NULL argument");
     s->s->info(info);
+    return TNFEM_OK;
+  });
+}
+
+int tnfem_server_set_max_batch(tnfem_server* s, int max_batch) {
+  return guarded_s([&]() -> int {
+    if (!s) tnfem::fail(TNFEM_EINVAL, "NULL server");
+    if (max_batch < 1 || max_batch > tnfem::FB_MAX) tnfem::fail(TNFEM_EINVAL, "max_batch must be in [1, 16]");
+    s->s->set_max_batch(max_batch);
     return TNFEM_OK;
   });
 }

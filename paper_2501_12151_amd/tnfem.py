@@ -10,6 +10,12 @@ Problem descriptions are plain dicts with the keys
     clamp: [(axis, side), ...], tractions: [(axis, side, t), ...],
     body_force (opt), manufactured_c (opt)
 so that the same dict can describe a workload to any consumer.
+
+torch ships its own HIP runtime under the same library names (libamdhip64.so.7,
+libhsa-runtime64.so.1) as the ROCm runtime the library links, and a process holds
+whichever copy it loads first.  torch does not initialise on a runtime other than
+its own, so this module imports torch (when it is installed) before loading the
+library: the process then has one runtime, torch's, for both.
 """
 from __future__ import annotations
 
@@ -25,6 +31,10 @@ LIB_PATH = os.path.join(_HERE, "libtnfem.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libtnfem.so is not built at {LIB_PATH}; run paper_2501_12151_amd/build.py")
 
+try:  # load torch's HIP runtime first (see the module docstring)
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EBUDGET, ENOTCONV, EDEVICE, ENAN, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
@@ -69,6 +79,7 @@ class ServerInfo(C.Structure):
     _fields_ = [
         ("queued", C.c_int), ("running", C.c_int), ("peak_running", C.c_int), ("completed", C.c_longlong),
         ("bytes_in_use", C.c_size_t), ("peak_bytes", C.c_size_t), ("budget_bytes", C.c_size_t),
+        ("peak_batch", C.c_int), ("batched_requests", C.c_longlong),
     ]
 
     def as_dict(self):
@@ -87,6 +98,8 @@ _sig = {
     "tnfem_problem_destroy": (C.c_int, [_vp]),
     "tnfem_problem_info": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     "tnfem_solve": (C.c_int, [_vp, C.POINTER(SolveOpts), C.POINTER(_vp), C.POINTER(SolveStats)]),
+    "tnfem_solve_batch": (C.c_int, [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp), _vp, _ip]),
+    "tnfem_server_set_max_batch": (C.c_int, [_vp, C.c_int]),
     "tnfem_tt_create": (C.c_int, [C.c_int, _ip, _ip, _dp, C.POINTER(_vp)]),
     "tnfem_tt_shape": (C.c_int, [_vp, _ip, _ip, _ip]),
     "tnfem_tt_size": (C.c_size_t, [_vp]),
@@ -313,6 +326,23 @@ def _ptr(x):
     return int(x)
 
 
+def solve_batch(problems, **opts):
+    """Lockstep solve of several problems of one dimension and level in one context (FP64,
+    shared launches of the CG iterations).  Returns [(TT or None, stats dict, status)]."""
+    n = len(problems)
+    o = default_opts(**opts)
+    hs = (_vp * n)(*[p._h for p in problems])
+    outs = (_vp * n)()
+    sts = (SolveStats * n)()
+    status = (C.c_int * n)()
+    _check(_lib.tnfem_solve_batch(hs, n, C.byref(o), outs, C.cast(sts, _vp), status))
+    res = []
+    for i in range(n):
+        tt = TT(outs[i]) if outs[i] else None
+        res.append((tt, sts[i].as_dict(), status[i]))
+    return res
+
+
 class Problem:
     def __init__(self, ctx: Context, problem: dict):
         self.ctx = ctx
@@ -387,6 +417,9 @@ class Server:
         if rc not in (OK, ENOTCONV):
             raise TnfemError(rc, _lib.tnfem_last_error().decode())
         return TT(h), st.as_dict(), rc, lat.value
+
+    def set_max_batch(self, n: int):
+        _check(_lib.tnfem_server_set_max_batch(self._h, int(n)))
 
     def info(self):
         i = ServerInfo()

@@ -10,3 +10,18 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _torch_device_first():
+    """torch ships its own HIP runtime next to the library's; in a process that uses
+    both, torch's must initialise the device first (the tests hand torch buffers and
+    streams to the library), whatever order the test files run in."""
+    try:
+        import torch
+    except ImportError:
+        yield
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+    yield

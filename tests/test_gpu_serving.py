@@ -75,3 +75,43 @@ def test_budget_rejects_and_serialises():
     for o in outs[1:]:
         for a, b in zip(_cores(o), ref):
             assert np.array_equal(a, b)
+
+
+def _bucket_requests():
+    rng = np.random.default_rng(3)
+    out = []
+    for _ in range(6):
+        out.append(dict(dim=3, level=5, E=float(10 ** rng.uniform(-1, 1)), nu=float(rng.uniform(0.2, 0.45)),
+                        clamp=[(0, 0)], tractions=[(0, 1, [float(v) for v in rng.standard_normal(3)])]))
+    return out
+
+
+def test_server_batches_one_bucket_and_results_equal_alone():
+    opts = dict(rank_cap=32, tol=1e-6, max_sweeps=6)
+    reqs = _bucket_requests()
+    ctx = tnfem.Context(0)
+    alone = []
+    for d in reqs:
+        P = tnfem.Problem(ctx, d)
+        alone.append([c.copy() for c in P.solve(**opts)[0].cores])
+        P.close()
+    ctx.close()
+    blocker = (workloads.cube_body_force(6), dict(rank_cap=32, tol=1e-6, max_sweeps=6))
+    for max_batch, expect in [(8, 6), (1, 1)]:
+        srv = tnfem.Server(0, slots=1)
+        srv.set_max_batch(max_batch)
+        tb = srv.submit(blocker[0], **blocker[1])  # keeps the one slot busy while the bucket queues
+        ts = [srv.submit(d, **opts) for d in reqs]
+        outs = [srv.poll(t) for t in ts]
+        srv.poll(tb)
+        info = srv.info()
+        srv.close()
+        print(f"max_batch {max_batch}: {info}", flush=True)
+        assert info["peak_batch"] == expect
+        assert info["batched_requests"] == (6 if expect > 1 else 0)
+        for o, a in zip(outs, alone):
+            got = [c.copy() for c in o[0].cores]
+            assert len(got) == len(a)
+            for x, y in zip(got, a):
+                assert np.array_equal(x, y)
+            assert o[3] > 0
