@@ -40,8 +40,11 @@ std::vector<double> MpoCore::dense() const {
 
 namespace {
 
-enum Basis { I_ = 0, J_, JT_, E00_, ELL_, E01_, E10_, ELLM_, ELML_, NBASIS };
-enum State { EQ = 0, C = 1, B = 2, Z = 3, O = 4, NSTATE = 5 };
+enum Basis { I_ = 0, J_, JT_, E00_, ELL_, E01_, E10_, ELLM_, ELML_, LZ_, U_, NBASIS };
+// Layered axis only: LZ, the equal-prefix path whose bits below the layer level
+// are all zero; U, an unweighted copy of the equal-prefix path (for the
+// boundary atoms, which are not element sums).
+enum State { EQ = 0, C = 1, B = 2, Z = 3, O = 4, NSTATE = 5, LZ = 5, U = 6 };
 
 struct Factor {
   std::array<double, NBASIS> f{};
@@ -91,17 +94,20 @@ std::vector<Step> accept_steps(const Factor& F) {
 }
 
 // Kronecker product over axes of per-axis step lists -> MPO nonzeros.
-// state index: axis 0 most significant (base nstate_in / nstate_out); mode bits likewise.
-void kron_steps(const std::vector<std::vector<Step>>& axes, int nin, int nout, MpoCore& core, int e_fixed) {
+// state index: axis 0 most significant (radix nin[a] / nout[a] per axis); mode bits likewise.
+void kron_steps(const std::vector<std::vector<Step>>& axes, const std::vector<int>& nin,
+                const std::vector<int>& nout, MpoCore& core, int e_fixed) {
   const int D = (int)axes.size();
   std::vector<size_t> idx(D, 0);
+  for (const auto& ax : axes)
+    if (ax.empty()) return;
   while (true) {
     int s = 0, t = 0, io = 0, ii = 0;
     double v = 1.0;
     for (int a = 0; a < D; ++a) {
       const Step& st = axes[a][idx[a]];
-      s = s * nin + st.s;
-      t = t * nout + st.t;
+      s = s * nin[a] + st.s;
+      t = t * nout[a] + st.t;
       io = io * 2 + st.io;
       ii = ii * 2 + st.ii;
       v *= st.v;
@@ -111,6 +117,101 @@ void kron_steps(const std::vector<std::vector<Step>>& axes, int nin, int nout, M
     while (a >= 0 && ++idx[a] == axes[a].size()) idx[a--] = 0;
     if (a < 0) break;
   }
+}
+
+// Young's modulus varying along one axis by one bit of the element index:
+// element e (between nodes e and e + 1) has weight w[bit], bit = the level-L bit
+// of e (levels most significant first).  The element-summed 1D factors of that
+// axis then carry the weight on the steps of level L: the equal-prefix and J
+// paths read it from the row bit, the J^T path from the column bit; the
+// contribution of the element below a node (diagonal term d w(i - 1)) differs
+// from w(i) only when the bits of i below level L are all zero, which the extra
+// state LZ tracks with weight w(1 - bit) - w(bit).  The corner paths (Z, O) are
+// not weighted; their coefficients are solved for the exact corner entries.
+// The boundary atoms use the unweighted copy U of the equal-prefix path.
+struct Layer {
+  int axis = -1, L = 0;
+  double w[2] = {1.0, 1.0};
+};
+
+std::vector<Step> level_steps(int l, const Layer* ly) {
+  std::vector<Step> st = (l == 0) ? first_steps() : middle_steps();
+  if (!ly) return st;
+  const int src = (l == 0) ? 0 : EQ;
+  if (l == ly->L) {
+    for (auto& x : st) {
+      if (x.t == EQ || x.t == C) x.v *= ly->w[x.io];
+      else if (x.t == B) x.v *= ly->w[x.ii];
+    }
+    for (int b = 0; b < 2; ++b) st.push_back({src, b, b, LZ, ly->w[1 - b] - ly->w[b]});
+  } else if (l > ly->L) {
+    st.push_back({LZ, 0, 0, LZ, 1.0});
+  }
+  for (int b = 0; b < 2; ++b) st.push_back({l == 0 ? 0 : U, b, b, U, 1.0});
+  return st;
+}
+
+std::vector<Step> accept_level_steps(const Factor& F, int d, const Layer* ly) {
+  if (!ly) return accept_steps(F);
+  const auto& f = F.f;
+  std::vector<Step> all;
+  if (ly->L < d - 1) {
+    all = accept_steps(F);
+    all.push_back({LZ, 0, 0, 0, f[LZ_]});
+  } else {  // the weighted level is the last one
+    const double* w = ly->w;
+    all = {{EQ, 0, 0, 0, f[I_] * w[0] + f[LZ_] * (w[1] - w[0])},
+           {EQ, 1, 1, 0, f[I_] * w[1] + f[LZ_] * (w[0] - w[1])},
+           {EQ, 0, 1, 0, f[J_] * w[0]},
+           {EQ, 1, 0, 0, f[JT_] * w[0]},
+           {C, 1, 0, 0, f[J_] * w[1]},
+           {B, 0, 1, 0, f[JT_] * w[1]},
+           {Z, 0, 0, 0, f[E00_]},
+           {Z, 0, 1, 0, f[E01_]},
+           {Z, 1, 0, 0, f[E10_]},
+           {O, 1, 1, 0, f[ELL_]},
+           {O, 1, 0, 0, f[ELLM_]},
+           {O, 0, 1, 0, f[ELML_]}};
+  }
+  all.push_back({U, 0, 0, 0, f[U_]});
+  all.push_back({U, 1, 1, 0, f[U_]});
+  std::vector<Step> out;
+  for (const auto& x : all)
+    if (x.v != 0.0) out.push_back(x);
+  return out;
+}
+
+// Element-summed factor with element matrix [[a, b], [c, dd]] on a layered axis,
+// masked at clamped ends (P F P): the coefficients of the weighted paths, and the
+// corner coefficients that make the corner entries exact.
+Factor layered_factor(double a, double b, double c, double dd, bool cl0, bool cl1, const Layer& ly, int d) {
+  Factor F;
+  F.f[I_] = a + dd;
+  F.f[J_] = b;
+  F.f[JT_] = c;
+  F.f[LZ_] = dd;
+  const double w0 = ly.w[0], w1 = ly.w[1];
+  const double wN2 = ly.w[ly.L < d - 1 ? 1 : 0];  // weight of element N - 2
+  // (0, 0): the low bits of node 0 are zero, so the LZ path reaches it
+  F.f[E00_] = (cl0 ? 0.0 : a * w0) - ((a + dd) * w0 + dd * (w1 - w0));
+  F.f[E01_] = cl0 ? -b * w0 : 0.0;
+  F.f[E10_] = cl0 ? -c * w0 : 0.0;
+  // (N-1, N-1): the bits of N - 1 below level L are all ones unless L is the last level
+  const double pathLL = (a + dd) * w1 + (ly.L == d - 1 ? dd * (w0 - w1) : 0.0);
+  F.f[ELL_] = (cl1 ? 0.0 : dd * wN2) - pathLL;
+  F.f[ELLM_] = cl1 ? -c * wN2 : 0.0;
+  F.f[ELML_] = cl1 ? -b * wN2 : 0.0;
+  return F;
+}
+
+// Identity (and its masked form) on a layered axis: the unweighted path U, so the
+// boundary atoms alpha (I - P) are the same as on a homogeneous axis.
+Factor layered_identity(bool cl0, bool cl1) {
+  Factor F;
+  F.f[U_] = 1.0;
+  if (cl0) F.f[E00_] = -1.0;
+  if (cl1) F.f[ELL_] = -1.0;
+  return F;
 }
 
 struct Atom {
@@ -313,8 +414,38 @@ Assembled assemble(const tnfem_problem_desc& desc) {
   TNFEM_REQUIRE(!(desc.plane_stress && D == 3), "plane_stress is a 2D option");
   TNFEM_REQUIRE((desc.clamp_mask >> (2 * D)) == 0, "clamp_mask names a face beyond dim");
   TNFEM_REQUIRE(desc.n_tractions >= 0 && desc.n_tractions <= 6, "n_tractions must be in [0, 6]");
-  TNFEM_REQUIRE(desc.layer_E == nullptr, "layered material is not supported by this version");
   const int n = 1 << d;
+  Layer ly;
+  const bool layered = desc.layer_E != nullptr;
+  if (layered) {
+    TNFEM_REQUIRE(desc.layer_axis >= 0 && desc.layer_axis < D, "layer_axis must be in [0, dim)");
+    TNFEM_REQUIRE(desc.n_layer_E == n - 1, "layer_E must hold one value per element layer (%d)", n - 1);
+    std::vector<double> w(n - 1);
+    for (int e = 0; e < n - 1; ++e) {
+      w[e] = desc.layer_E[e] / desc.E;
+      TNFEM_REQUIRE(w[e] > 0 && std::isfinite(w[e]), "layer_E must be positive");
+    }
+    bool found = false;
+    for (int L = 0; L < d && !found; ++L) {
+      double v[2] = {NAN, NAN};
+      bool ok = true;
+      for (int e = 0; e < n - 1 && ok; ++e) {
+        const int bit = (e >> (d - 1 - L)) & 1;
+        if (std::isnan(v[bit])) v[bit] = w[e];
+        else ok = v[bit] == w[e];
+      }
+      if (ok) {
+        found = true;
+        ly.axis = desc.layer_axis;
+        ly.L = L;
+        ly.w[0] = v[0];
+        ly.w[1] = v[1];
+      }
+    }
+    TNFEM_REQUIRE(found,
+                  "layer_E must be a function of one bit of the element index along layer_axis "
+                  "(slabs alternating every 2^k element layers)");
+  }
 
   Assembled out;
   out.D = D;
@@ -352,6 +483,14 @@ Assembled assemble(const tnfem_problem_desc& desc) {
     GT[a] = masked(gt, c0[a], c1[a]);
     Id[a] = id;
     P[a] = masked(id, c0[a], c1[a]);
+    if (layered && a == ly.axis) {  // element matrices [[a, b], [c, d]] of S, M, G, G^T
+      S[a] = layered_factor(1 / h, -1 / h, -1 / h, 1 / h, c0[a], c1[a], ly, d);
+      M[a] = layered_factor(2 * h / 6, h / 6, h / 6, 2 * h / 6, c0[a], c1[a], ly, d);
+      G[a] = layered_factor(-0.5, -0.5, 0.5, 0.5, c0[a], c1[a], ly, d);
+      GT[a] = layered_factor(-0.5, 0.5, -0.5, 0.5, c0[a], c1[a], ly, d);
+      Id[a] = layered_identity(false, false);
+      P[a] = layered_identity(c0[a], c1[a]);
+    }
   }
 
   std::vector<Atom> atoms;
@@ -383,28 +522,35 @@ Assembled assemble(const tnfem_problem_desc& desc) {
     atoms.push_back(pa);
   }
   const int nat = (int)atoms.size();
-  const int ns = (int)std::lround(std::pow(5.0, D));
+  std::vector<int> nsa(D, NSTATE);  // automaton states per axis
+  if (layered) nsa[ly.axis] = NSTATE + 2;
+  int ns = 1;
+  for (int a = 0; a < D; ++a) ns *= nsa[a];
   const int nm = 1 << D;
+  auto layer_of = [&](int a) { return (layered && a == ly.axis) ? &ly : nullptr; };
 
   // level cores
   for (int l = 0; l < d; ++l) {
     MpoCore core;
     core.n = nm;
-    if (l == 0) {
-      core.Rl = 1;
+    if (l < d - 1) {
+      core.Rl = l == 0 ? 1 : ns;
       core.Rr = ns;
-      kron_steps(std::vector<std::vector<Step>>(D, first_steps()), 1, NSTATE, core, -1);
-    } else if (l < d - 1) {
-      core.Rl = ns;
-      core.Rr = ns;
-      kron_steps(std::vector<std::vector<Step>>(D, middle_steps()), NSTATE, NSTATE, core, -1);
+      std::vector<std::vector<Step>> axes;
+      std::vector<int> rin, rout;
+      for (int a = 0; a < D; ++a) {
+        axes.push_back(level_steps(l, layer_of(a)));
+        rin.push_back(l == 0 ? 1 : nsa[a]);
+        rout.push_back(nsa[a]);
+      }
+      kron_steps(axes, rin, rout, core, -1);
     } else {
       core.Rl = ns;
       core.Rr = nat;
       for (int t = 0; t < nat; ++t) {
         std::vector<std::vector<Step>> axes;
-        for (int a = 0; a < D; ++a) axes.push_back(accept_steps(atoms[t].axis[a]));
-        kron_steps(axes, NSTATE, 1, core, t);
+        for (int a = 0; a < D; ++a) axes.push_back(accept_level_steps(atoms[t].axis[a], d, layer_of(a)));
+        kron_steps(axes, nsa, std::vector<int>(D, 1), core, t);
       }
     }
     out.A.push_back(core);

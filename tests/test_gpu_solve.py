@@ -65,3 +65,23 @@ def test_solve_is_deterministic(ctx):
     b = P.solve(rank_cap=32, tol=1e-9)[0].cores
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+
+@pytest.mark.parametrize("prob", [
+    dict(workloads.layered_cube(3), clamp=[(2, 0), (0, 0)]),
+    dict(dim=2, level=5, E=1.0, nu=0.3, clamp=[(1, 0)], tractions=[(1, 1, [0.0, -1.0])],
+         layered_E=(1, np.where((np.arange(31) >> 2) & 1, 10.0, 1.0).tolist())),
+])
+def test_layered_material_solve_equals_direct(prob):
+    """Slab-wise Young's modulus: the GPU sweep with an unbinding rank cap reaches the direct solve."""
+    A, b, grid, _ = fem.build_system(prob)
+    u = qtt.to_qtt_order(fem.direct_solve(A, b), prob["dim"], prob["level"])
+    ctx = tnfem.Context(0)
+    P = tnfem.Problem(ctx, prob)
+    U, st, rc = P.solve(rank_cap=200, tol=1e-10, max_sweeps=40)
+    rel = np.linalg.norm(tt.tt_full(U.cores).reshape(-1) - u) / np.linalg.norm(u)
+    print(f"layered {prob['dim']}D level {prob['level']}: rel.err vs direct {rel:.2e}, sweeps {st['sweeps']}", flush=True)
+    assert rel <= 1e-8
+    P.close()
+    ctx.close()

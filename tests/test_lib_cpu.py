@@ -55,7 +55,8 @@ def test_library_assembly_equals_sparse_fem(case):
     assert max(C.shape[3] for C in Ac) <= 5 ** D
 
 
-@pytest.mark.parametrize("prob", [dict(workloads.small_2d(), level=8), workloads.cube_body_force(4)])
+@pytest.mark.parametrize("prob", [dict(workloads.small_2d(), level=8), workloads.cube_body_force(4),
+                                  workloads.layered_cube(5)])
 def test_library_operator_matches_oracle_tt_at_larger_levels(prob):
     """Beyond dense sizes: bilinear forms w^T A x agree for random TT vectors w, x."""
     Ao = qtt.assemble_operator(prob)
@@ -89,10 +90,49 @@ def test_invalid_descriptor_rejected(bad, msg):
     assert msg in str(e.value)
 
 
-def test_layered_material_reported_unsupported():
+def _layers(level, L, v0, v1):
+    """Per-element weights of one bit (level L, most significant first) of the element index."""
+    e = np.arange(2 ** level - 1)
+    return np.where((e >> (level - 1 - L)) & 1, v1, v0).tolist()
+
+
+LAYERED = [
+    workloads.layered_cube(3),  # the slab pattern (bit 2 of 3: the last level)
+    workloads.layered_cube(4),  # the slab pattern at a middle level
+    dict(dim=3, level=3, E=2.0, nu=0.3, clamp=[(2, 0), (2, 1)], body_force=[0.0, 0.0, -1.0],
+         layered_E=(2, _layers(3, 0, 2.0, 20.0))),  # first level; both ends of the layered axis clamped
+    dict(dim=3, level=3, E=1.0, nu=0.25, clamp=[(0, 0)], tractions=[(0, 1, [0.2, 0.4, -1.0])],
+         layered_E=(1, _layers(3, 1, 3.0, 0.5))),  # layered across y, clamp on another axis
+    dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(1, 0)], tractions=[(1, 1, [0.0, -1.0])],
+         layered_E=(1, _layers(4, 2, 1.0, 10.0))),
+    dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(0, 0), (1, 1)], tractions=[(0, 1, [1.0, 0.0])],
+         layered_E=(0, _layers(4, 3, 4.0, 1.5))),  # the last level, clamped at both ends of two axes
+    dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])],
+         layered_E=(0, [2.5] * 7)),  # constant: a rescaled material
+]
+
+
+@pytest.mark.parametrize("case", range(len(LAYERED)))
+def test_layered_assembly_equals_sparse_fem(case):
+    """Young's modulus varying by one bit of the element index along an axis: the library's
+    weighted automaton operator equals the sparse FEM assembly with per-element E."""
+    prob = LAYERED[case]
+    A, b, grid, info = fem.build_system(prob)
+    D, d = prob["dim"], prob["level"]
+    Ac = tnfem.export_operator(prob)
+    Ap = qtt.matrix_to_qtt_order(A, D, d).toarray()
+    assert np.abs(tt.mpo_full(Ac) - Ap).max() <= 1e-13 * np.abs(Ap).max()
+    bp = qtt.to_qtt_order(b, D, d)
+    assert np.abs(tt.tt_full(tnfem.export_load(prob)) - bp).max() <= 1e-13 * np.abs(bp).max()
+    assert max(C.shape[3] for C in Ac) <= 7 * 5 ** (D - 1)  # two extra states on the layered axis
+
+
+def test_unsupported_layering_rejected():
+    prob = dict(workloads.layered_cube(3), layered_E=(2, [1.0, 2.0, 3.0, 1.0, 2.0, 3.0, 1.0]))
     with pytest.raises(tnfem.TnfemError) as e:
-        tnfem.export_operator(workloads.layered_cube(3))
+        tnfem.export_operator(prob)
     assert e.value.code == tnfem.EINVAL
+    assert "one bit" in str(e.value)
 
 
 def test_no_device_is_a_clean_error():
