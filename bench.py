@@ -42,6 +42,10 @@ WORKLOADS = {
                      refs=[(64, 1e-8, 40), (96, 1e-9, 40)],
                      desc="3D unit cube 1024^3 nodes (QTT level 10), all faces clamped, load of the manufactured field "
                           "u_i = c_i sin(pi x) sin(pi y) sin(pi z), c ~ N(0,1) (seed 0), E=1, nu=0.3, rank cap 64"),
+    "layered512": dict(level=9, opts=dict(rank_cap=128, tol=1e-6, max_sweeps=12),
+                       refs=[(128, 1e-8, 24)],
+                       desc="3D unit cube 512^3 nodes (QTT level 9), 8 slabs along z alternating E=1 and E=10, "
+                            "nu=0.3, base z=0 clamped, top pressure 1.0, rank cap 128"),
     "square32": dict(level=5, opts=dict(rank_cap=16, tol=1e-8, max_sweeps=20),
                      refs=[(64, 1e-10, 30)],
                      desc="2D plane strain 32x32 nodes (QTT level 5), x-traction 1 on x=1, x=0 clamped, E=1, nu=0.3, "
@@ -65,6 +69,8 @@ def problem_for(name):
         return workloads.cube_body_force(WORKLOADS[name]["level"])
     if name == "cube1024":
         return workloads.cube_manufactured(WORKLOADS[name]["level"])
+    if name == "layered512":
+        return workloads.layered_cube(WORKLOADS[name]["level"])
     return workloads.small_2d()
 
 

@@ -608,6 +608,8 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   W.Ra = A(Nw * Nw);
   W.Wm = A(Nw * Nw);
   W.qrws = A(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw);
+  W.Rz = A((size_t)rho * maxn * rho + 1);
+  W.qrwsz = A(2 * (size_t)rho * maxn * rho + 4 * (size_t)rho);
   W.scal = A(16);
   W.fpart_cap = (size_t)1 << 22;
   W.fpart = A(W.fpart_cap);
@@ -958,21 +960,47 @@ struct Sweep {
     return res;
   }
 
-  void truncate_enrich(int k) {
-    const int p = xr[k], nk = n[k], t = xr[k + 1];
-    const int M = p * nk, Nn = t;
-    const int c = std::min(M, Nn);
-    // thin SVD of the M x Nn unfolding: U (M x c) in W.Ur, V^T (c x Nn) in W.Vt
-    if (M >= Nn) {
-      launch_qr(M, Nn, X[k], Nn, W.Qx, Nn, W.Rx, Nn, W.qrws, st);
-      launch_jacobi_svd(Nn, W.Rx, Nn, W.UR, W.S, W.V, W.qrws, st);
-      gemm_plain(M, Nn, Nn, W.Qx, Nn, false, W.UR, Nn, W.Ur, c, st, &fl);
-      launch_core_transpose(Nn, 1, Nn, W.V, W.Vt, st);
+  // Truncation and enrichment of core k, in four phases so that a lockstep batch can
+  // issue the QR / SVD of all its requests as shared launches between them:
+  //   trunc_begin  -> QR job of the unfolding, SVD job of its R factor
+  //   trunc_rank   -> U, V^T, truncation rank (read back; the caller synchronises)
+  //   enrich_begin -> truncated core, residual projections; QR jobs of the new Z
+  //                   core and of the enriched basis [U | residual]
+  //   enrich_end   -> carry Q^T x into core k + 1, ranks, interface updates
+  struct TruncState {
+    int p = 0, nk = 0, t = 0, M = 0, Nn = 0, c = 0, rk = 0, rnew = 0, cz = 0;
+    bool tall = true;
+    QrJob qr, zqr, aqr;
+    SvdJob svd;
+  };
+
+  void trunc_begin(int k, TruncState& s) {
+    s.p = xr[k];
+    s.nk = n[k];
+    s.t = xr[k + 1];
+    s.M = s.p * s.nk;
+    s.Nn = s.t;
+    s.c = std::min(s.M, s.Nn);
+    s.tall = s.M >= s.Nn;
+    const int M = s.M, Nn = s.Nn;
+    if (s.tall) {
+      s.qr = QrJob{M, Nn, Nn, Nn, Nn, X[k], W.Qx, W.Rx, W.qrws};
+      s.svd = SvdJob{Nn, Nn, W.Rx, W.UR, W.S, W.V, W.qrws};
     } else {
       // x^T = Q U_R S V^T  =>  x = V S (Q U_R)^T
       launch_core_transpose(M, 1, Nn, X[k], W.xT, st);
-      launch_qr(Nn, M, W.xT, M, W.Qx, M, W.Rx, M, W.qrws, st);
-      launch_jacobi_svd(M, W.Rx, M, W.UR, W.S, W.V, W.qrws, st);
+      s.qr = QrJob{Nn, M, M, M, M, W.xT, W.Qx, W.Rx, W.qrws};
+      s.svd = SvdJob{M, M, W.Rx, W.UR, W.S, W.V, W.qrws};
+    }
+  }
+
+  void trunc_rank(int k, TruncState& s) {
+    (void)k;
+    const int M = s.M, Nn = s.Nn, c = s.c;
+    if (s.tall) {
+      gemm_plain(M, Nn, Nn, W.Qx, Nn, false, W.UR, Nn, W.Ur, c, st, &fl);
+      launch_core_transpose(Nn, 1, Nn, W.V, W.Vt, st);
+    } else {
       launch_copy2d(M, M, W.V, M, W.Ur, c, 1.0, 0.0, st);
       // V^T = (Q U_R)^T = U_R^T Q^T, Q stored Nn x M row-major
       GemmDesc g;
@@ -995,8 +1023,12 @@ struct Sweep {
     const double trtol = o.tol / std::sqrt((double)std::max(K - 1, 1));
     launch_trunc_rank(c, W.S, trtol, o.rank_cap, W.drank, st);
     hip_check(hipMemcpyAsync(W.host_pinned, W.drank, sizeof(int), hipMemcpyDeviceToHost, st), "rank readback");
-    sync();
+  }
+
+  void enrich_begin(int k, TruncState& s) {
+    const int p = s.p, nk = s.nk, t = s.t, M = s.M, Nn = s.Nn, c = s.c;
     const int rk = hint()[0];
+    s.rk = rk;
     // keep U[:, :rk] (in place, leading dimension rk) and xt = U_rk diag(S) V^T_rk
     if (rk < c) {
       launch_copy2d(M, rk, W.Ur, c, W.aug, rk, 1.0, 0.0, st);
@@ -1004,30 +1036,48 @@ struct Sweep {
     }
     launch_scale_rows(rk, Nn, W.S, W.Vt, Nn, W.SVt, st);
     gemm_plain(M, Nn, rk, W.Ur, rk, false, W.SVt, Nn, W.xt, Nn, st, &fl);
-    // residual projected on the Z interfaces -> new Z_k
+    // residual projected on the Z interfaces -> new Z_k (QR job)
     const int pz = zr[k], tz = zr[k + 1];
     local_rhs(pz, nk, sb(k), sb(k + 1), tz, Ezb[k], B(k), Ezb[k + 1], W.Tb, W.gz, st, &fl);
     apply(k, pz, p, t, tz, EzA[k], W.xt, EzA[k + 1], W.yz, nullptr);
     launch_sub((long)pz * nk * tz, W.gz, W.yz, W.gz, st);
-    const int mz = pz * nk, cz = std::min(mz, tz);
-    launch_qr(mz, tz, W.gz, tz, Z[k], cz, W.Ra, tz, W.qrws, st);
+    const int mz = pz * nk;
+    s.cz = std::min(mz, tz);
+    s.zqr = QrJob{mz, tz, tz, s.cz, tz, W.gz, Z[k], W.Rz, W.qrwsz};
     // enrichment: residual on (left X, right Z) interfaces
     local_rhs(p, nk, sb(k), sb(k + 1), tz, Eb[k], B(k), Ezb[k + 1], W.Tb, W.ge, st, &fl);
     apply(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ye, nullptr);
     launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
     const int rho_eff = std::max(0, std::min(tz, std::min(o.rank_cap - rk, M - rk)));
     const int rnew = rk + rho_eff;
+    s.rnew = rnew;
     launch_copy2d(M, rk, W.Ur, rk, W.aug, rnew, 1.0, 0.0, st);
     if (rho_eff > 0) launch_copy2d(M, rho_eff, W.ge, tz, W.aug + rk, rnew, 1.0, 0.0, st);
-    launch_qr(M, rnew, W.aug, rnew, X[k], rnew, W.Ra, rnew, W.qrws, st);
+    s.aqr = QrJob{M, rnew, rnew, rnew, rnew, W.aug, X[k], W.Ra, W.qrws};
+  }
+
+  void enrich_end(int k, TruncState& s) {
+    const int M = s.M, Nn = s.Nn, rnew = s.rnew;
     // W = Q^T xt (rnew x Nn); X_{k+1} <- W X_{k+1}
     gemm_plain(rnew, Nn, M, X[k], rnew, true, W.xt, Nn, W.Wm, Nn, st, &fl);
     const int cols = n[k + 1] * xr[k + 2];
     gemm_plain(rnew, cols, Nn, W.Wm, Nn, false, X[k + 1], cols, xspare, cols, st, &fl);
     std::swap(X[k + 1], xspare);
     xr[k + 1] = rnew;
-    zr[k + 1] = cz;
+    zr[k + 1] = s.cz;
     update_envs(k);
+  }
+
+  void truncate_enrich(int k) {
+    TruncState s;
+    trunc_begin(k, s);
+    launch_qr(s.qr.m, s.qr.n, s.qr.A, s.qr.lda, s.qr.Q, s.qr.ldq, s.qr.R, s.qr.ldr, s.qr.ws, st);
+    launch_jacobi_svd(s.svd.n, s.svd.G, s.svd.ldg, s.svd.U, s.svd.S, s.svd.V, s.svd.ws, st);
+    trunc_rank(k, s);
+    sync();
+    enrich_begin(k, s);
+    launch_qr_batch({s.zqr, s.aqr}, st);  // independent: one launch, two workgroups
+    enrich_end(k, s);
   }
 
   double half_sweep() {
@@ -1447,11 +1497,40 @@ int run_solve_batch(std::vector<Problem*>& Ps, const tnfem_solve_opts& o, std::v
         keep.push_back(r);
       }
       live.swap(keep);
-      if (k < K - 1)
-        for (int r : live) {
+      if (k < K - 1 && !live.empty()) {
+        // truncation and enrichment with shared QR / SVD launches over the requests
+        std::vector<Sweep::TruncState> ts(live.size());
+        std::vector<QrJob> qj, qj2;
+        std::vector<SvdJob> sj;
+        for (size_t i = 0; i < live.size(); ++i) {
+          const int r = live[i];
           set_gemm_splitk_buffer(Ps[r]->ws->splitk, Ps[r]->ws->splitk_cap);
-          sweeps[r]->truncate_enrich(k);
+          sweeps[r]->trunc_begin(k, ts[i]);
+          qj.push_back(ts[i].qr);
+          sj.push_back(ts[i].svd);
         }
+        launch_qr_batch(qj, ctx->stream);
+        launch_jacobi_svd_batch(sj, ctx->stream);
+        for (size_t i = 0; i < live.size(); ++i) {
+          const int r = live[i];
+          set_gemm_splitk_buffer(Ps[r]->ws->splitk, Ps[r]->ws->splitk_cap);
+          sweeps[r]->trunc_rank(k, ts[i]);
+        }
+        hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        for (size_t i = 0; i < live.size(); ++i) {
+          const int r = live[i];
+          set_gemm_splitk_buffer(Ps[r]->ws->splitk, Ps[r]->ws->splitk_cap);
+          sweeps[r]->enrich_begin(k, ts[i]);
+          qj2.push_back(ts[i].zqr);
+          qj2.push_back(ts[i].aqr);
+        }
+        launch_qr_batch(qj2, ctx->stream);
+        for (size_t i = 0; i < live.size(); ++i) {
+          const int r = live[i];
+          set_gemm_splitk_buffer(Ps[r]->ws->splitk, Ps[r]->ws->splitk_cap);
+          sweeps[r]->enrich_end(k, ts[i]);
+        }
+      }
     }
     std::vector<int> still;
     for (int r : active) {

@@ -83,6 +83,7 @@ struct Workspace {
   double *Tb = nullptr, *gz = nullptr, *yz = nullptr, *ge = nullptr, *ye = nullptr;
   double *Qx = nullptr, *Rx = nullptr, *UR = nullptr, *S = nullptr, *V = nullptr, *Ur = nullptr, *SVt = nullptr,
          *xt = nullptr, *aug = nullptr, *Vt = nullptr, *xT = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;
+  double *Rz = nullptr, *qrwsz = nullptr;  // R and scratch of the residual-TT QR
   double *scal = nullptr, *part = nullptr;
   double* splitk = nullptr;
   size_t splitk_cap = 0;

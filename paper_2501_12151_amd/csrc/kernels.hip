@@ -1232,9 +1232,8 @@ __global__ __launch_bounds__(QR_NT) void qr_kernel(int m, int n, const double* A
 // once, so each column costs one barrier; Q is accumulated by every wave for its
 // own columns over all reflectors without barriers.
 template <bool LDS>
-__global__ __launch_bounds__(QR_NT) void qr_owner_kernel(int m, int n, const double* A, int lda, double* Q, int ldq,
-                                                         double* R, int ldr, double* ws) {
-  extern __shared__ double dyn[];
+__device__ __forceinline__ void qr_owner_body(int m, int n, const double* A, int lda, double* Q, int ldq, double* R,
+                                              int ldr, double* ws, double* dyn) {
   constexpr int NW = QR_NT / 64;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int c = m < n ? m : n;
@@ -1316,6 +1315,54 @@ __global__ __launch_bounds__(QR_NT) void qr_owner_kernel(int m, int n, const dou
   for (long idx = tid; idx < (long)m * c; idx += QR_NT) {
     const int i = idx / c, jj = idx % c;
     Q[(long)i * ldq + jj] = Qc[(long)jj * m + i];
+  }
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(QR_NT) void qr_owner_kernel(int m, int n, const double* A, int lda, double* Q, int ldq,
+                                                         double* R, int ldr, double* ws) {
+  extern __shared__ double dyn[];
+  qr_owner_body<LDS>(m, n, A, lda, Q, ldq, R, ldr, ws, dyn);
+}
+
+// One workgroup per job: the same QR as qr_owner_kernel for each job of the batch.
+template <bool LDS>
+__global__ __launch_bounds__(QR_NT) void qr_owner_batch_kernel(QrBatch b) {
+  extern __shared__ double dyn[];
+  const QrJob j = b.job[blockIdx.x];
+  qr_owner_body<LDS>(j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R, j.ldr, j.ws, dyn);
+}
+
+static size_t qr_lds_bytes(int m, int n) {
+  const int c = m < n ? m : n;
+  return ((size_t)m * n + (size_t)m * c + 2 * (size_t)c) * sizeof(double);
+}
+
+void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s) {
+  if (jobs.size() > (size_t)QR_BATCH_MAX) throw Error(TNFEM_EINVAL, "QR batch: too many jobs");
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_owner_batch_kernel<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_BYTES);
+  });
+  QrBatch in_lds, in_ws;
+  size_t lds_max = 0;
+  for (const QrJob& j : jobs) {
+    const size_t b = qr_lds_bytes(j.m, j.n);
+    if (b <= QR_LDS_BYTES) {
+      in_lds.job[in_lds.njob++] = j;
+      lds_max = std::max(lds_max, b);
+    } else {
+      in_ws.job[in_ws.njob++] = j;
+    }
+  }
+  if (in_lds.njob) {
+    hipLaunchKernelGGL(qr_owner_batch_kernel<true>, dim3(in_lds.njob), dim3(QR_NT), lds_max, s, in_lds);
+    TN_CHECK_LAUNCH();
+  }
+  if (in_ws.njob) {
+    hipLaunchKernelGGL(qr_owner_batch_kernel<false>, dim3(in_ws.njob), dim3(QR_NT), 0, s, in_ws);
+    TN_CHECK_LAUNCH();
   }
 }
 
@@ -1440,8 +1487,8 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
 // one-wave workgroup.
 constexpr int SVW_MAXN = 64;
 
-__global__ __launch_bounds__(64) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, double* U, double* S,
-                                                            double* V) {
+__device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int ldg, double* U, double* S,
+                                                     double* V) {
   // column-major n x n with a padded column stride: the columns handled at one
   // step start in different LDS banks
   __shared__ double Gc[SVW_MAXN * (SVW_MAXN + 1)];
@@ -1527,10 +1574,180 @@ __global__ __launch_bounds__(64) void jacobi_svd_wave_kernel(int n, const double
   for (int j = lane; j < n; j += 64) S[pos[j]] = sv[j];
 }
 
+// The same iteration for 64 < n <= 137 on 1024 threads: G in dynamic LDS with a
+// padded column stride (n + 1), V in LDS as well when both fit, else in ws; each
+// column pair of a step is owned by an aligned group of lanes (DPP sums).
+constexpr int SVB_NT = 1024;
+constexpr size_t SVB_LDS_BYTES = 156 * 1024;
+
+template <bool V_LDS>
+__device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int ldg, double* U, double* S, double* V,
+                                                    double* ws, double* dyn) {
+  __shared__ double sv[SV_MAXN];
+  __shared__ int pos[SV_MAXN];
+  const int tid = threadIdx.x;
+  const int ld = n + 1;
+  double* Gc = dyn;
+  double* Vc = V_LDS ? dyn + (long)n * ld : ws;
+  for (int idx = tid; idx < n * n; idx += SVB_NT) {
+    const int i = idx % n, j = idx / n;
+    Gc[j * ld + i] = G[(long)i * ldg + j];
+    Vc[j * ld + i] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int npad = n + (n & 1);
+  const int npairs = npad / 2;
+  int tpp = 1;
+  while (tpp * 2 * npairs <= SVB_NT && tpp < 64) tpp *= 2;
+  const int pair = tid / tpp, sub = tid % tpp;
+  const int rpl = (n + tpp - 1) / tpp;
+  const int i0 = sub * rpl, i1 = min(n, i0 + rpl);
+  const double eps = n * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    int rot = 0;
+    for (int step = 0; step < npad - 1; ++step) {
+      if (pair < npairs) {
+        const int ia = pair, ib = npad - 1 - pair;
+        const int pa = ia == 0 ? 0 : 1 + (ia - 1 + step) % (npad - 1);
+        const int pb = ib == 0 ? 0 : 1 + (ib - 1 + step) % (npad - 1);
+        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+        double a = 0.0, b = 0.0, cc = 0.0;
+        if (q < n) {
+          for (int i = i0; i < i1; ++i) {
+            const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
+            a += gp * gp;
+            b += gq * gq;
+            cc += gp * gq;
+          }
+        }
+        a = group_sum(a, tpp);
+        b = group_sum(b, tpp);
+        cc = group_sum(cc, tpp);
+        if (q < n && cc != 0.0 && fabs(cc) > eps * sqrt(a * b)) {
+          const double zeta = (b - a) / (2.0 * cc);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int i = i0; i < i1; ++i) {
+            const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
+            Gc[p * ld + i] = cs * gp - sn * gq;
+            Gc[q * ld + i] = sn * gp + cs * gq;
+            const double vp = Vc[p * ld + i], vq = Vc[q * ld + i];
+            Vc[p * ld + i] = cs * vp - sn * vq;
+            Vc[q * ld + i] = sn * vp + cs * vq;
+          }
+          rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rot)) break;
+  }
+  for (int j = tid; j < n; j += SVB_NT) {
+    double s2 = 0.0;
+    for (int i = 0; i < n; ++i) s2 += Gc[j * ld + i] * Gc[j * ld + i];
+    sv[j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += SVB_NT) {
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += (sv[i] > sv[j]) || (sv[i] == sv[j] && i < j);
+    pos[j] = r;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += SVB_NT) {
+    const int j = idx / n, i = idx % n;
+    const int pj = pos[j];
+    const double sj = sv[j];
+    U[(long)i * n + pj] = sj > 0.0 ? Gc[j * ld + i] / sj : (i == pj ? 1.0 : 0.0);
+    V[(long)i * n + pj] = Vc[j * ld + i];
+  }
+  for (int j = tid; j < n; j += SVB_NT) S[pos[j]] = sv[j];
+}
+
+__global__ __launch_bounds__(64) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, double* U, double* S,
+                                                            double* V) {
+  jacobi_svd_wave_body(n, G, ldg, U, S, V);
+}
+
+template <bool V_LDS>
+__global__ __launch_bounds__(SVB_NT) void jacobi_svd_big_kernel(int n, const double* G, int ldg, double* U, double* S,
+                                                               double* V, double* ws) {
+  extern __shared__ double dyn[];
+  jacobi_svd_big_body<V_LDS>(n, G, ldg, U, S, V, ws, dyn);
+}
+
+// One workgroup per job: the same one-sided Jacobi as the single launches.
+__global__ __launch_bounds__(64) void jacobi_svd_wave_batch_kernel(SvdBatch b) {
+  const SvdJob j = b.job[blockIdx.x];
+  jacobi_svd_wave_body(j.n, j.G, j.ldg, j.U, j.S, j.V);
+}
+
+template <bool V_LDS>
+__global__ __launch_bounds__(SVB_NT) void jacobi_svd_big_batch_kernel(SvdBatch b) {
+  extern __shared__ double dyn[];
+  const SvdJob j = b.job[blockIdx.x];
+  jacobi_svd_big_body<V_LDS>(j.n, j.G, j.ldg, j.U, j.S, j.V, j.ws, dyn);
+}
+
+void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
+  if (jobs.size() > (size_t)SVD_BATCH_MAX) throw Error(TNFEM_EINVAL, "SVD batch: too many jobs");
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_big_batch_kernel<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)SVB_LDS_BYTES);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_big_batch_kernel<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)SVB_LDS_BYTES);
+  });
+  SvdBatch wave, big2, big1;
+  size_t m2 = 0, m1 = 0;
+  for (const SvdJob& j : jobs) {
+    const size_t g = (size_t)j.n * (j.n + 1) * sizeof(double);
+    if (j.n <= SVW_MAXN) {
+      wave.job[wave.njob++] = j;
+    } else if (2 * g <= SVB_LDS_BYTES) {
+      big2.job[big2.njob++] = j;
+      m2 = std::max(m2, 2 * g);
+    } else if (g <= SVB_LDS_BYTES) {
+      big1.job[big1.njob++] = j;
+      m1 = std::max(m1, g);
+    } else {
+      launch_jacobi_svd(j.n, j.G, j.ldg, j.U, j.S, j.V, j.ws, s);
+    }
+  }
+  if (wave.njob) {
+    hipLaunchKernelGGL(jacobi_svd_wave_batch_kernel, dim3(wave.njob), dim3(64), 0, s, wave);
+    TN_CHECK_LAUNCH();
+  }
+  if (big2.njob) {
+    hipLaunchKernelGGL(jacobi_svd_big_batch_kernel<true>, dim3(big2.njob), dim3(SVB_NT), m2, s, big2);
+    TN_CHECK_LAUNCH();
+  }
+  if (big1.njob) {
+    hipLaunchKernelGGL(jacobi_svd_big_batch_kernel<false>, dim3(big1.njob), dim3(SVB_NT), m1, s, big1);
+    TN_CHECK_LAUNCH();
+  }
+}
+
 void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s) {
   if (n > SV_MAXN) throw Error(TNFEM_EINVAL, "Jacobi SVD limited to n <= 256");
   if (n <= SVW_MAXN) {
     hipLaunchKernelGGL(jacobi_svd_wave_kernel, dim3(1), dim3(64), 0, s, n, G, ldg, U, S, V);
+    TN_CHECK_LAUNCH();
+    return;
+  }
+  const size_t gbytes = (size_t)n * (n + 1) * sizeof(double);
+  if (gbytes <= SVB_LDS_BYTES) {
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_big_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)SVB_LDS_BYTES);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_big_kernel<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)SVB_LDS_BYTES);
+    });
+    if (2 * gbytes <= SVB_LDS_BYTES)
+      hipLaunchKernelGGL(jacobi_svd_big_kernel<true>, dim3(1), dim3(SVB_NT), 2 * gbytes, s, n, G, ldg, U, S, V, ws);
+    else
+      hipLaunchKernelGGL(jacobi_svd_big_kernel<false>, dim3(1), dim3(SVB_NT), gbytes, s, n, G, ldg, U, S, V, ws);
     TN_CHECK_LAUNCH();
     return;
   }

@@ -182,9 +182,35 @@ void launch_dense_matvec(int N, const double* Bm, const double* z, double* y, co
 // ws: workspace of m * n + m * c + 2 * c doubles.
 void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws, hipStream_t s);
 
+// Batched QR: one workgroup per job, each the same computation as launch_qr.
+struct QrJob {
+  int m = 0, n = 0, lda = 0, ldq = 0, ldr = 0;
+  const double* A = nullptr;
+  double *Q = nullptr, *R = nullptr, *ws = nullptr;
+};
+constexpr int QR_BATCH_MAX = 32;
+struct QrBatch {
+  int njob = 0;
+  QrJob job[QR_BATCH_MAX];
+};
+void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s);
+
 // One-sided Jacobi SVD of the square n x n matrix G (row-major, ldg): G = U diag(S) V^T,
 // S descending.  U, V: n x n row-major.  ws: 2 n^2 doubles (used when n > 64).
 void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s);
+
+// Batched Jacobi SVD: one workgroup per job, each the same computation as launch_jacobi_svd.
+struct SvdJob {
+  int n = 0, ldg = 0;
+  const double* G = nullptr;
+  double *U = nullptr, *S = nullptr, *V = nullptr, *ws = nullptr;
+};
+constexpr int SVD_BATCH_MAX = 16;
+struct SvdBatch {
+  int njob = 0;
+  SvdJob job[SVD_BATCH_MAX];
+};
+void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s);
 
 // out[0] = smallest r with sum_{j>=r} S_j^2 <= tol^2 sum S^2, clipped to [1, cap].
 void launch_trunc_rank(int c, const double* S, double tol, int cap, int* out, hipStream_t s);

@@ -232,10 +232,16 @@ class TT:
     def __init__(self, handle):
         self._h = handle
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "_h", None):
             _lib.tnfem_tt_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except (AttributeError, TypeError):  # interpreter shutdown: the library is already gone
+            pass
 
     @classmethod
     def from_cores(cls, cores):
@@ -306,7 +312,10 @@ class Context:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except (AttributeError, TypeError):  # interpreter shutdown: the library is already gone
+            pass
 
     def qr(self, m, n, A, Q, R, stream=None):
         """Device QR on raw pointers (ints) or torch tensors."""
@@ -358,7 +367,10 @@ class Problem:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except (AttributeError, TypeError):  # interpreter shutdown: the library is already gone
+            pass
 
     def info(self):
         nc = C.c_int()
@@ -432,4 +444,7 @@ class Server:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except (AttributeError, TypeError):  # interpreter shutdown: the library is already gone
+            pass
