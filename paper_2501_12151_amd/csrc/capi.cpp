@@ -478,7 +478,7 @@ int tnfem_prim_svd(tnfem_ctx* ctx, int m, int n, const double* A, double* U, dou
       src = At;
     }
     tnfem::launch_qr(mm, nn, src, nn, Q, nn, R, nn, qws, st);
-    tnfem::launch_jacobi_svd(nn, R, nn, UR, S, V, qws, st);
+    tnfem::launch_jacobi_svd(nn, R, nn, V, S, UR, qws, st, 1);  // on R^T: outputs swapped
     tnfem::GemmDesc g;
     if (tall) {
       // U = Q UR (m x n); Vt = V^T

@@ -985,12 +985,13 @@ struct Sweep {
     const int M = s.M, Nn = s.Nn;
     if (s.tall) {
       s.qr = QrJob{M, Nn, Nn, Nn, Nn, X[k], W.Qx, W.Rx, W.qrws};
-      s.svd = SvdJob{Nn, Nn, W.Rx, W.UR, W.S, W.V, W.qrws};
+      // Jacobi on R^T: its normalised columns are R's right, its rotations R's left vectors
+      s.svd = SvdJob{Nn, Nn, W.Rx, W.V, W.S, W.UR, W.qrws, 1};
     } else {
       // x^T = Q U_R S V^T  =>  x = V S (Q U_R)^T
       launch_core_transpose(M, 1, Nn, X[k], W.xT, st);
       s.qr = QrJob{Nn, M, M, M, M, W.xT, W.Qx, W.Rx, W.qrws};
-      s.svd = SvdJob{M, M, W.Rx, W.UR, W.S, W.V, W.qrws};
+      s.svd = SvdJob{M, M, W.Rx, W.V, W.S, W.UR, W.qrws, 1};
     }
   }
 
@@ -1072,7 +1073,7 @@ struct Sweep {
     TruncState s;
     trunc_begin(k, s);
     launch_qr(s.qr.m, s.qr.n, s.qr.A, s.qr.lda, s.qr.Q, s.qr.ldq, s.qr.R, s.qr.ldr, s.qr.ws, st);
-    launch_jacobi_svd(s.svd.n, s.svd.G, s.svd.ldg, s.svd.U, s.svd.S, s.svd.V, s.svd.ws, st);
+    launch_jacobi_svd(s.svd.n, s.svd.G, s.svd.ldg, s.svd.U, s.svd.S, s.svd.V, s.svd.ws, st, s.svd.trans);
     trunc_rank(k, s);
     sync();
     enrich_begin(k, s);

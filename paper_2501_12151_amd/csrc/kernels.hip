@@ -1389,7 +1389,7 @@ constexpr int SV_NT = 256;
 constexpr int SV_LDS_MAXN = 64;
 constexpr int SV_MAXN = 256;
 
-__global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* G, int ldg, double* U, double* S,
+__global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* G, int ldg, int trans, double* U, double* S,
                                                            double* V, double* ws) {
   __shared__ double lds[2 * SV_LDS_MAXN * SV_LDS_MAXN];
   __shared__ double sv[SV_MAXN];
@@ -1401,7 +1401,7 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
   double* Vc = use_lds ? lds + n * n : ws + (long)n * n;
   for (int idx = tid; idx < n * n; idx += SV_NT) {
     const int i = idx % n, j = idx / n;
-    Gc[idx] = G[(long)i * ldg + j];
+    Gc[idx] = trans ? G[(long)j * ldg + i] : G[(long)i * ldg + j];
     Vc[idx] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -1487,7 +1487,7 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
 // one-wave workgroup.
 constexpr int SVW_MAXN = 64;
 
-__device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int ldg, double* U, double* S,
+__device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int ldg, int trans, double* U, double* S,
                                                      double* V) {
   // column-major n x n with a padded column stride: the columns handled at one
   // step start in different LDS banks
@@ -1499,7 +1499,7 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
   const int ld = n + 1;
   for (int idx = lane; idx < n * n; idx += 64) {
     const int i = idx % n, j = idx / n;
-    Gc[j * ld + i] = G[(long)i * ldg + j];
+    Gc[j * ld + i] = trans ? G[(long)j * ldg + i] : G[(long)i * ldg + j];
     Vc[j * ld + i] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -1581,7 +1581,7 @@ constexpr int SVB_NT = 1024;
 constexpr size_t SVB_LDS_BYTES = 156 * 1024;
 
 template <bool V_LDS>
-__device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int ldg, double* U, double* S, double* V,
+__device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int ldg, int trans, double* U, double* S, double* V,
                                                     double* ws, double* dyn) {
   __shared__ double sv[SV_MAXN];
   __shared__ int pos[SV_MAXN];
@@ -1591,7 +1591,7 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
   double* Vc = V_LDS ? dyn + (long)n * ld : ws;
   for (int idx = tid; idx < n * n; idx += SVB_NT) {
     const int i = idx % n, j = idx / n;
-    Gc[j * ld + i] = G[(long)i * ldg + j];
+    Gc[j * ld + i] = trans ? G[(long)j * ldg + i] : G[(long)i * ldg + j];
     Vc[j * ld + i] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -1664,29 +1664,29 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
   for (int j = tid; j < n; j += SVB_NT) S[pos[j]] = sv[j];
 }
 
-__global__ __launch_bounds__(64) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, double* U, double* S,
-                                                            double* V) {
-  jacobi_svd_wave_body(n, G, ldg, U, S, V);
+__global__ __launch_bounds__(64) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, int trans, double* U,
+                                                            double* S, double* V) {
+  jacobi_svd_wave_body(n, G, ldg, trans, U, S, V);
 }
 
 template <bool V_LDS>
-__global__ __launch_bounds__(SVB_NT) void jacobi_svd_big_kernel(int n, const double* G, int ldg, double* U, double* S,
-                                                               double* V, double* ws) {
+__global__ __launch_bounds__(SVB_NT) void jacobi_svd_big_kernel(int n, const double* G, int ldg, int trans, double* U,
+                                                               double* S, double* V, double* ws) {
   extern __shared__ double dyn[];
-  jacobi_svd_big_body<V_LDS>(n, G, ldg, U, S, V, ws, dyn);
+  jacobi_svd_big_body<V_LDS>(n, G, ldg, trans, U, S, V, ws, dyn);
 }
 
 // One workgroup per job: the same one-sided Jacobi as the single launches.
 __global__ __launch_bounds__(64) void jacobi_svd_wave_batch_kernel(SvdBatch b) {
   const SvdJob j = b.job[blockIdx.x];
-  jacobi_svd_wave_body(j.n, j.G, j.ldg, j.U, j.S, j.V);
+  jacobi_svd_wave_body(j.n, j.G, j.ldg, j.trans, j.U, j.S, j.V);
 }
 
 template <bool V_LDS>
 __global__ __launch_bounds__(SVB_NT) void jacobi_svd_big_batch_kernel(SvdBatch b) {
   extern __shared__ double dyn[];
   const SvdJob j = b.job[blockIdx.x];
-  jacobi_svd_big_body<V_LDS>(j.n, j.G, j.ldg, j.U, j.S, j.V, j.ws, dyn);
+  jacobi_svd_big_body<V_LDS>(j.n, j.G, j.ldg, j.trans, j.U, j.S, j.V, j.ws, dyn);
 }
 
 void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
@@ -1711,7 +1711,7 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
       big1.job[big1.njob++] = j;
       m1 = std::max(m1, g);
     } else {
-      launch_jacobi_svd(j.n, j.G, j.ldg, j.U, j.S, j.V, j.ws, s);
+      launch_jacobi_svd(j.n, j.G, j.ldg, j.U, j.S, j.V, j.ws, s, j.trans);
     }
   }
   if (wave.njob) {
@@ -1728,10 +1728,11 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
   }
 }
 
-void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s) {
+void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s,
+                       int trans) {
   if (n > SV_MAXN) throw Error(TNFEM_EINVAL, "Jacobi SVD limited to n <= 256");
   if (n <= SVW_MAXN) {
-    hipLaunchKernelGGL(jacobi_svd_wave_kernel, dim3(1), dim3(64), 0, s, n, G, ldg, U, S, V);
+    hipLaunchKernelGGL(jacobi_svd_wave_kernel, dim3(1), dim3(64), 0, s, n, G, ldg, trans, U, S, V);
     TN_CHECK_LAUNCH();
     return;
   }
@@ -1745,13 +1746,15 @@ void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, do
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)SVB_LDS_BYTES);
     });
     if (2 * gbytes <= SVB_LDS_BYTES)
-      hipLaunchKernelGGL(jacobi_svd_big_kernel<true>, dim3(1), dim3(SVB_NT), 2 * gbytes, s, n, G, ldg, U, S, V, ws);
+      hipLaunchKernelGGL(jacobi_svd_big_kernel<true>, dim3(1), dim3(SVB_NT), 2 * gbytes, s, n, G, ldg, trans, U, S, V,
+                         ws);
     else
-      hipLaunchKernelGGL(jacobi_svd_big_kernel<false>, dim3(1), dim3(SVB_NT), gbytes, s, n, G, ldg, U, S, V, ws);
+      hipLaunchKernelGGL(jacobi_svd_big_kernel<false>, dim3(1), dim3(SVB_NT), gbytes, s, n, G, ldg, trans, U, S, V,
+                         ws);
     TN_CHECK_LAUNCH();
     return;
   }
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(SV_NT), 0, s, n, G, ldg, U, S, V, ws);
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(SV_NT), 0, s, n, G, ldg, trans, U, S, V, ws);
   TN_CHECK_LAUNCH();
 }
 

@@ -197,13 +197,18 @@ void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s);
 
 // One-sided Jacobi SVD of the square n x n matrix G (row-major, ldg): G = U diag(S) V^T,
 // S descending.  U, V: n x n row-major.  ws: 2 n^2 doubles (used when n > 64).
-void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s);
+// trans != 0: works on G^T (element (i, j) read from G[j * ldg + i]).  Jacobi on R^T
+// (R from a QR) converges in fewer sweeps than on R; the caller then passes the
+// destinations swapped: U receives R's right and V its left singular vectors.
+void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s,
+                       int trans = 0);
 
 // Batched Jacobi SVD: one workgroup per job, each the same computation as launch_jacobi_svd.
 struct SvdJob {
   int n = 0, ldg = 0;
   const double* G = nullptr;
   double *U = nullptr, *S = nullptr, *V = nullptr, *ws = nullptr;
+  int trans = 0;
 };
 constexpr int SVD_BATCH_MAX = 16;
 struct SvdBatch {
