@@ -13,8 +13,11 @@ the paper leaves open are listed in the design doc):
       g   = local right-hand side  (Phi_b,L  B_k  Phi_b,R)
       B   = local operator          (Phi_A,L  A_k  Phi_A,R), symmetric
       res = ||g - B x_k|| / ||g||
-      if res > tol/2: preconditioned CG from x_k (Jacobi: diag(B)) until
-            ||g - B x|| <= max(0.1 res, tol/2) ||g||
+      if res > tol/2: preconditioned CG from x_k until
+            ||g - B x|| <= max(0.1 res, tol/2) ||g||; the preconditioner is
+            block Jacobi over the mode index: for every pair (a, c) of left and
+            right interface indices the n x n diagonal block B[(a,:,c),(a,:,c)]
+            is inverted
       if k < K-1:
         SVD of the (r_k n_k) x r_{k+1} unfolding, keep the smallest rank whose
             discarded tail is <= tol/sqrt(K-1) of the norm, at most rank_cap;
@@ -75,15 +78,32 @@ def env_b(Lb, W, B):
     return np.tensordot(W, T, axes=([0, 1], [0, 1]))
 
 
-def pcg(apply, g, x, dinv, thr, maxit):
-    """Jacobi-preconditioned conjugate gradients from x until ||g - B x|| <= thr.
+def local_block(L, A, Rt):
+    """Diagonal blocks of the local operator over the mode index:
+    blk[a, c, j, i] = sum_{b,e} L[a, b, a] A[b, j, i, e] Rt[c, e, c]."""
+    La = np.einsum("aba->ab", L)
+    Rc = np.einsum("cec->ce", Rt)
+    return np.einsum("ab,bjie,ce->acji", La, A, Rc)
 
-    Each iteration applies B to the preconditioned residual z and carries
-    q = B p by the recurrence q = B z + beta q, which equals B p for
-    p = z + beta p by linearity (the textbook method, one product per step).
+
+def block_preconditioner(blk):
+    """r -> z with z[a, :, c] = blk[a, c]^{-1} r[a, :, c] (blocks of an SPD operator are SPD)."""
+    def apply(r):
+        rr = r.transpose(0, 2, 1)[..., None]                # [p, t, n, 1]
+        return np.linalg.solve(blk, rr)[..., 0].transpose(0, 2, 1)
+    return apply
+
+
+def pcg(apply, g, x, precond, thr, maxit):
+    """Preconditioned conjugate gradients from x until ||g - B x|| <= thr.
+
+    precond(r) returns the preconditioned residual z.  Each iteration applies B
+    to z and carries q = B p by the recurrence q = B z + beta q, which equals
+    B p for p = z + beta p by linearity (the textbook method, one product per
+    step).
     """
     r = g - apply(x)
-    z = r * dinv
+    z = precond(r)
     p = np.zeros_like(r)
     q = np.zeros_like(r)
     beta = 0.0
@@ -99,7 +119,7 @@ def pcg(apply, g, x, dinv, thr, maxit):
         alpha = rz / pq
         x = x + alpha * p
         r = r - alpha * q
-        z = r * dinv
+        z = precond(r)
         rz_new = float(np.vdot(r, z))
         beta = rz_new / rz
         rz = rz_new
@@ -208,10 +228,9 @@ def _half_sweep(ch: _Chain, opt: Options, st: Stats):
         res = res0 / gn if gn > 0 else (0.0 if res0 == 0 else 1.0)
         max_res = max(max_res, res)
         if res > 0.5 * tol:
-            dg = local_diag(L, A, Rt)
-            dinv = np.where(dg > 0, 1.0 / np.where(dg > 0, dg, 1.0), 1.0)
+            precond = block_preconditioner(local_block(L, A, Rt))
             thr = max(0.1 * res, 0.5 * tol) * gn
-            x, it = pcg(apply, g, x, dinv, thr, opt.cg_maxit)
+            x, it = pcg(apply, g, x, precond, thr, opt.cg_maxit)
             st.cg_iters += it
         if k == K - 1:
             ch.X[k] = x

@@ -588,6 +588,7 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   W.q = A(core);
   W.w = A(core);
   W.dinv = A(core);
+  W.binv = A(rc * rc * maxn * maxn);
   W.Tb = A(rc * maxn * smax);
   W.gz = A(core);
   W.yz = A(core);
@@ -683,6 +684,16 @@ static std::vector<std::vector<double>> random_tt_host(const std::vector<int>& m
 // ----------------------------------------------------------------------------- the sweep
 
 namespace {
+
+// Block-Jacobi preconditioner over the mode index: blocks of n unknowns (a, :, c).
+static void set_block_precond(CgIterArgs& a, int n, int t, const double* binv) {
+  int np2 = 1;
+  while (np2 < n) np2 *= 2;
+  a.bn = n;
+  a.bnp = np2;
+  a.bt = t;
+  a.binv = binv;
+}
 
 struct Sweep {
   Problem& P;
@@ -800,8 +811,8 @@ struct Sweep {
     const int N = p * n[k] * t;
     local_rhs(p, n[k], sb(k), sb(k + 1), t, Eb[k], B(k), Eb[k + 1], W.Tb, W.g, st, &fl);
     const Plan& pl = plan(k);
-    launch_local_diag(p, n[k], t, R(k), R(k + 1), EA[k], EA[k + 1], pl.dg_beg, pl.dg_b, pl.dg_e, pl.dg_v, W.dinv,
-                      st);
+    launch_local_block_inv(p, n[k], t, R(k), R(k + 1), EA[k], EA[k + 1], pl.sp_ap_beg, pl.sp_ap_a, pl.sp_ap_b,
+                           pl.sp_ap_v, pl.sp_slot_b, pl.sp_slot_i, W.binv, st);
     apply(k, p, p, t, t, EA[k], X[k], EA[k + 1], W.q, nullptr);
     applies++;
     CgIterArgs a;
@@ -820,6 +831,7 @@ struct Sweep {
     a.t = t;
     a.nb_upd = cg_dir_blocks(N);
     a.nb_dir = cg_dir_blocks(N);
+    set_block_precond(a, n[k], t, W.binv);
     launch_cg_init2(a, W.g, W.q, o.tol, st);
     auto readback = [&]() {
       hip_check(hipMemcpyAsync(W.host_pinned, W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flag readback");
@@ -1146,8 +1158,8 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     c.N = c.p * w.n[k] * c.t;
     c.pl = &w.plan(k);
     local_rhs(c.p, w.n[k], w.sb(k), w.sb(k + 1), c.t, w.Eb[k], w.B(k), w.Eb[k + 1], W.Tb, W.g, st, &w.fl);
-    launch_local_diag(c.p, w.n[k], c.t, w.R(k), w.R(k + 1), w.EA[k], w.EA[k + 1], c.pl->dg_beg, c.pl->dg_b,
-                      c.pl->dg_e, c.pl->dg_v, W.dinv, st);
+    launch_local_block_inv(c.p, w.n[k], c.t, w.R(k), w.R(k + 1), w.EA[k], w.EA[k + 1], c.pl->sp_ap_beg,
+                           c.pl->sp_ap_a, c.pl->sp_ap_b, c.pl->sp_ap_v, c.pl->sp_slot_b, c.pl->sp_slot_i, W.binv, st);
     w.apply(k, c.p, c.p, c.t, c.t, w.EA[k], w.X[k], w.EA[k + 1], W.q, nullptr);
     w.applies++;
     CgIterArgs& a = c.a;
@@ -1166,6 +1178,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     a.t = c.t;
     a.nb_upd = cg_dir_blocks(c.N);
     a.nb_dir = cg_dir_blocks(c.N);
+    set_block_precond(a, w.n[k], c.t, W.binv);
     launch_cg_init2(a, W.g, W.q, w.o.tol, st);
     hip_check(hipMemcpyAsync(W.host_pinned, W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flag readback");
     hip_check(hipMemcpyAsync(static_cast<char*>(W.host_pinned) + 64, W.scal + CG_RES, sizeof(double),

@@ -80,6 +80,7 @@ struct Workspace {
   std::vector<double*> EA, Eb, EzA, Ezb;  // K + 1 bond buffers
   double *T1 = nullptr, *T2 = nullptr;
   double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *dinv = nullptr;
+  double* binv = nullptr;  // inverses of the diagonal mode blocks of the local operator
   double *Tb = nullptr, *gz = nullptr, *yz = nullptr, *ge = nullptr, *ye = nullptr;
   double *Qx = nullptr, *Rx = nullptr, *UR = nullptr, *S = nullptr, *V = nullptr, *Ur = nullptr, *SVt = nullptr,
          *xt = nullptr, *aug = nullptr, *Vt = nullptr, *xT = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;

@@ -840,6 +840,17 @@ void launch_fused_sum(FusedArgs f, double* y, hipStream_t s) {
 
 constexpr int PART_RZ = 0, PART_RR = 2 * CG_MAXB, PART_PQ = 4 * CG_MAXB;
 
+// z_j = sum_i brow[i] r_i over the bn lanes of a block (aligned groups of bnp lanes);
+// every lane of the group takes part in the exchanges.
+__device__ inline double block_apply(const double* brow, double ri, int bn, int gbase, bool act) {
+  double zi = 0.0;
+  for (int i = 0; i < bn; ++i) {
+    const double rv = __shfl(ri, gbase + i, 64);
+    if (act) zi += brow[i] * rv;
+  }
+  return zi;
+}
+
 __device__ inline double sum_parts(const double* a, int nb) {
   double s = 0.0;
   for (int b = 0; b < nb; ++b) s += a[b];
@@ -918,14 +929,38 @@ __device__ __forceinline__ void cg_update2_body(const CgIterArgs& a, const int k
   }
   const double alpha = a.scal[CG_RZ0 + (k & 1)] / pq;
   double lrz = 0.0, lrr = 0.0;
-  for (int e = bid * 256 + threadIdx.x; e < a.N; e += nb * 256) {
-    a.x[e] += alpha * a.p[e];
-    const double ri = a.r[e] - alpha * a.q[e];
-    const double zi = ri * a.dinv[e];
-    a.r[e] = ri;
-    a.z[e] = zi;
-    lrz += ri * zi;
-    lrr += ri * ri;
+  if (a.bn > 0) {
+    const int bn = a.bn, bnp = a.bnp, t = a.bt;
+    const long total = (long)(a.N / bn) * bnp;
+    const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
+    for (long idx = bid * 256 + threadIdx.x; idx < total; idx += (long)nb * 256) {
+      const int j = (int)(idx % bnp);
+      const long blk = idx / bnp;
+      const bool act = j < bn;
+      const long e = ((blk / t) * bn + j) * t + blk % t;
+      double ri = 0.0;
+      if (act) {
+        a.x[e] += alpha * a.p[e];
+        ri = a.r[e] - alpha * a.q[e];
+        a.r[e] = ri;
+      }
+      const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
+      if (act) {
+        a.z[e] = zi;
+        lrz += ri * zi;
+        lrr += ri * ri;
+      }
+    }
+  } else {
+    for (int e = bid * 256 + threadIdx.x; e < a.N; e += nb * 256) {
+      a.x[e] += alpha * a.p[e];
+      const double ri = a.r[e] - alpha * a.q[e];
+      const double zi = ri * a.dinv[e];
+      a.r[e] = ri;
+      a.z[e] = zi;
+      lrz += ri * zi;
+      lrr += ri * ri;
+    }
   }
   const double trz = block_sum<256>(lrz, red);
   const double trr = block_sum<256>(lrr, red);
@@ -944,17 +979,44 @@ __global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const doubl
   __shared__ double red[4];
   __shared__ bool am_last;
   double lrz = 0.0, lrr = 0.0, lgg = 0.0;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < a.N; e += gridDim.x * 256) {
-    const double gi = g[e];
-    const double ri = gi - bx[e];
-    const double zi = ri * a.dinv[e];
-    a.r[e] = ri;
-    a.z[e] = zi;
-    a.p[e] = 0.0;
-    a.q[e] = 0.0;
-    lrz += ri * zi;
-    lrr += ri * ri;
-    lgg += gi * gi;
+  if (a.bn > 0) {
+    const int bn = a.bn, bnp = a.bnp, t = a.bt;
+    const long total = (long)(a.N / bn) * bnp;
+    const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
+    for (long idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long)gridDim.x * 256) {
+      const int j = (int)(idx % bnp);
+      const long blk = idx / bnp;
+      const bool act = j < bn;
+      const long e = ((blk / t) * bn + j) * t + blk % t;
+      double gi = 0.0, ri = 0.0;
+      if (act) {
+        gi = g[e];
+        ri = gi - bx[e];
+        a.r[e] = ri;
+        a.p[e] = 0.0;
+        a.q[e] = 0.0;
+      }
+      const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
+      if (act) {
+        a.z[e] = zi;
+        lrz += ri * zi;
+        lrr += ri * ri;
+        lgg += gi * gi;
+      }
+    }
+  } else {
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < a.N; e += gridDim.x * 256) {
+      const double gi = g[e];
+      const double ri = gi - bx[e];
+      const double zi = ri * a.dinv[e];
+      a.r[e] = ri;
+      a.z[e] = zi;
+      a.p[e] = 0.0;
+      a.q[e] = 0.0;
+      lrz += ri * zi;
+      lrr += ri * ri;
+      lgg += gi * gi;
+    }
   }
   const double trz = block_sum<256>(lrz, red);
   const double trr = block_sum<256>(lrr, red);
@@ -1139,6 +1201,63 @@ __global__ __launch_bounds__(256) void dense_matvec_kernel(int N, const double* 
 void launch_dense_matvec(int N, const double* Bm, const double* z, double* y, const int* skip, hipStream_t s) {
   if (N <= 0) return;
   hipLaunchKernelGGL(dense_matvec_kernel, dim3((N + 3) / 4), dim3(256), 0, s, N, Bm, z, y, skip);
+  TN_CHECK_LAUNCH();
+}
+
+// ----------------------------------------------------------------------------- block-Jacobi preconditioner
+
+constexpr int BLK_MAXN = 8;
+
+// One wavefront per block (a, c); lane = 8 j + i holds entry (j, i) of [m | m^{-1}]
+// (modes n < 8 padded with the identity).  The blocks are principal submatrices of
+// the SPD local operator, so Gauss-Jordan needs no pivoting; the pivot row and
+// column entries are exchanged between lanes at each step.
+__global__ __launch_bounds__(256) void local_block_inv_kernel(int p, int n, int t, int Rl, int Rr, const double* L,
+                                                             const double* Rt, const int* beg, const int* ta,
+                                                             const int* tb, const double* tv, const int* slot_b,
+                                                             const int* slot_i, double* binv) {
+  const int lane = threadIdx.x % 64;
+  const long nblk = (long)p * t;
+  const int j = lane / BLK_MAXN, i = lane % BLK_MAXN;
+  const bool act = j < n && i < n;
+  for (long blk = (long)blockIdx.x * 4 + threadIdx.x / 64; blk < nblk; blk += (long)gridDim.x * 4) {
+    const int a = (int)(blk / t), c = (int)(blk % t);
+    double m = (j == i) ? 1.0 : 0.0;
+    if (act) {
+      m = 0.0;
+      for (int k = beg[j]; k < beg[j + 1]; ++k) {
+        const int slot = ta[k];
+        if (slot_i[slot] != i) continue;
+        m += tv[k] * L[((long)a * Rl + slot_b[slot]) * p + a] * Rt[((long)c * Rr + tb[k]) * t + c];
+      }
+    }
+    double v = (j == i) ? 1.0 : 0.0;
+    for (int col = 0; col < n; ++col) {
+      const double piv = __shfl(m, col * BLK_MAXN + col, 64);
+      const double mrow = __shfl(m, col * BLK_MAXN + i, 64);
+      const double vrow = __shfl(v, col * BLK_MAXN + i, 64);
+      const double f = __shfl(m, j * BLK_MAXN + col, 64);
+      if (j == col) {
+        m = mrow / piv;
+        v = vrow / piv;
+      } else {
+        m -= f * (mrow / piv);
+        v -= f * (vrow / piv);
+      }
+    }
+    if (act) binv[blk * n * n + (long)j * n + i] = v;
+  }
+}
+
+void launch_local_block_inv(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* beg,
+                            const int* ta, const int* tb, const double* tv, const int* slot_b, const int* slot_i,
+                            double* binv, hipStream_t s) {
+  if (n < 1 || n > BLK_MAXN) throw Error(TNFEM_EINVAL, "block preconditioner: mode size out of range");
+  const long nblk = (long)p * t;
+  if (nblk <= 0) return;
+  const unsigned grid = (unsigned)std::min<long>((nblk + 3) / 4, 2048);
+  hipLaunchKernelGGL(local_block_inv_kernel, dim3(grid), dim3(256), 0, s, p, n, t, Rl, Rr, L, Rt, beg, ta, tb, tv,
+                     slot_b, slot_i, binv);
   TN_CHECK_LAUNCH();
 }
 

@@ -151,6 +151,10 @@ struct CgIterArgs {
   int nb_upd = 1;  // blocks of init / update (partials of r.z, r.r)
   int nb_dir = 1;  // blocks of reduce_dir (partials of p.q)
   int keep_thr = 0;  // init: keep the stored threshold (refinement restart) instead of deriving it
+  // block-Jacobi preconditioner over the mode index (bn > 0): z[a, :, c] = binv[a, c] r[a, :, c],
+  // binv [p][t][bn][bn]; bnp = bn rounded up to a power of two (lanes per block); bt = t
+  int bn = 0, bnp = 1, bt = 1;
+  const double* binv = nullptr;
 };
 int cg_vec_blocks(int n);
 int cg_dir_blocks(int n);
@@ -177,6 +181,14 @@ void launch_local_matrix(int p, int n, int t, int Rl, int Rr, const double* L, c
                          double* M, double* Bm, hipStream_t s);
 // y = Bm z (N x N row-major); does nothing when skip != nullptr and *skip != 0 on the device.
 void launch_dense_matvec(int N, const double* Bm, const double* z, double* y, const int* skip, hipStream_t s);
+
+// Inverses of the diagonal mode blocks of the local operator, for the block-Jacobi
+// preconditioner: blk[a, c][j][i] = sum over the operator's nonzero terms (b, j, i, e, v)
+// of v L[a][b][a] Rt[c][e][c]; binv[(a t + c) n n + j n + i] = blk[a, c]^{-1} (Gauss-Jordan,
+// partial pivoting).  Term lists grouped by output mode j (beg[n + 1]); slot -> (b, i).
+void launch_local_block_inv(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* beg,
+                            const int* ta, const int* tb, const double* tv, const int* slot_b, const int* slot_i,
+                            double* binv, hipStream_t s);
 
 // Householder QR of A (m x n, row-major, lda), single workgroup: Q (m x c), R (c x n), c = min(m, n).
 // ws: workspace of m * n + m * c + 2 * c doubles.
