@@ -223,6 +223,16 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
       dv[c.ii[t]].push_back(c.v[t]);
     }
   flatten(db, de, dv, &P.dg_beg, &P.dg_b, &P.dg_e, &P.dg_v, nullptr);
+  // all terms grouped by (out, in) mode pair: entries of the diagonal mode blocks
+  std::vector<std::vector<int>> kb(n * n), ke(n * n);
+  std::vector<std::vector<double>> kv(n * n);
+  for (size_t t = 0; t < c.nnz(); ++t) {
+    const int pr = c.io[t] * n + c.ii[t];
+    kb[pr].push_back(c.b[t]);
+    ke[pr].push_back(c.e[t]);
+    kv[pr].push_back(c.v[t]);
+  }
+  flatten(kb, ke, kv, &P.bk_beg, &P.bk_b, &P.bk_e, &P.bk_v, nullptr);
   return P;
 }
 
@@ -811,8 +821,8 @@ struct Sweep {
     const int N = p * n[k] * t;
     local_rhs(p, n[k], sb(k), sb(k + 1), t, Eb[k], B(k), Eb[k + 1], W.Tb, W.g, st, &fl);
     const Plan& pl = plan(k);
-    launch_local_block_inv(p, n[k], t, R(k), R(k + 1), EA[k], EA[k + 1], pl.sp_ap_beg, pl.sp_ap_a, pl.sp_ap_b,
-                           pl.sp_ap_v, pl.sp_slot_b, pl.sp_slot_i, W.binv, st);
+    launch_local_block_inv(p, n[k], t, R(k), R(k + 1), EA[k], EA[k + 1], pl.bk_beg, pl.bk_b, pl.bk_e, pl.bk_v,
+                           W.binv, st);
     apply(k, p, p, t, t, EA[k], X[k], EA[k + 1], W.q, nullptr);
     applies++;
     CgIterArgs a;
@@ -1158,8 +1168,8 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     c.N = c.p * w.n[k] * c.t;
     c.pl = &w.plan(k);
     local_rhs(c.p, w.n[k], w.sb(k), w.sb(k + 1), c.t, w.Eb[k], w.B(k), w.Eb[k + 1], W.Tb, W.g, st, &w.fl);
-    launch_local_block_inv(c.p, w.n[k], c.t, w.R(k), w.R(k + 1), w.EA[k], w.EA[k + 1], c.pl->sp_ap_beg,
-                           c.pl->sp_ap_a, c.pl->sp_ap_b, c.pl->sp_ap_v, c.pl->sp_slot_b, c.pl->sp_slot_i, W.binv, st);
+    launch_local_block_inv(c.p, w.n[k], c.t, w.R(k), w.R(k + 1), w.EA[k], w.EA[k + 1], c.pl->bk_beg, c.pl->bk_b,
+                           c.pl->bk_e, c.pl->bk_v, W.binv, st);
     w.apply(k, c.p, c.p, c.t, c.t, w.EA[k], w.X[k], w.EA[k + 1], W.q, nullptr);
     w.applies++;
     CgIterArgs& a = c.a;

@@ -47,6 +47,9 @@ struct Plan {
   int n_en = 0, en_max = 1;
   int *dg_beg = nullptr, *dg_b = nullptr, *dg_e = nullptr;
   double* dg_v = nullptr;
+  // all nonzero terms grouped by (out, in) mode pair (j n + i): (b, e, v)
+  int *bk_beg = nullptr, *bk_b = nullptr, *bk_e = nullptr;
+  double* bk_v = nullptr;
   // Term lists of the nonzeros (for dense plans: the alternative evaluation by
   // the fused kernel, cheaper when the ranks next to this core are small).
   int sp_nslot = 0, sp_n_ap = 0, sp_ap_max = 1;

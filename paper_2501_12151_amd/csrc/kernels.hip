@@ -1213,9 +1213,8 @@ constexpr int BLK_MAXN = 8;
 // the SPD local operator, so Gauss-Jordan needs no pivoting; the pivot row and
 // column entries are exchanged between lanes at each step.
 __global__ __launch_bounds__(256) void local_block_inv_kernel(int p, int n, int t, int Rl, int Rr, const double* L,
-                                                             const double* Rt, const int* beg, const int* ta,
-                                                             const int* tb, const double* tv, const int* slot_b,
-                                                             const int* slot_i, double* binv) {
+                                                             const double* Rt, const int* beg, const int* kb,
+                                                             const int* ke, const double* kv, double* binv) {
   const int lane = threadIdx.x % 64;
   const long nblk = (long)p * t;
   const int j = lane / BLK_MAXN, i = lane % BLK_MAXN;
@@ -1225,11 +1224,9 @@ __global__ __launch_bounds__(256) void local_block_inv_kernel(int p, int n, int 
     double m = (j == i) ? 1.0 : 0.0;
     if (act) {
       m = 0.0;
-      for (int k = beg[j]; k < beg[j + 1]; ++k) {
-        const int slot = ta[k];
-        if (slot_i[slot] != i) continue;
-        m += tv[k] * L[((long)a * Rl + slot_b[slot]) * p + a] * Rt[((long)c * Rr + tb[k]) * t + c];
-      }
+      const int pr = j * n + i;
+      for (int k = beg[pr]; k < beg[pr + 1]; ++k)
+        m += kv[k] * L[((long)a * Rl + kb[k]) * p + a] * Rt[((long)c * Rr + ke[k]) * t + c];
     }
     double v = (j == i) ? 1.0 : 0.0;
     for (int col = 0; col < n; ++col) {
@@ -1250,14 +1247,13 @@ __global__ __launch_bounds__(256) void local_block_inv_kernel(int p, int n, int 
 }
 
 void launch_local_block_inv(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* beg,
-                            const int* ta, const int* tb, const double* tv, const int* slot_b, const int* slot_i,
-                            double* binv, hipStream_t s) {
+                            const int* kb, const int* ke, const double* kv, double* binv, hipStream_t s) {
   if (n < 1 || n > BLK_MAXN) throw Error(TNFEM_EINVAL, "block preconditioner: mode size out of range");
   const long nblk = (long)p * t;
   if (nblk <= 0) return;
   const unsigned grid = (unsigned)std::min<long>((nblk + 3) / 4, 2048);
-  hipLaunchKernelGGL(local_block_inv_kernel, dim3(grid), dim3(256), 0, s, p, n, t, Rl, Rr, L, Rt, beg, ta, tb, tv,
-                     slot_b, slot_i, binv);
+  hipLaunchKernelGGL(local_block_inv_kernel, dim3(grid), dim3(256), 0, s, p, n, t, Rl, Rr, L, Rt, beg, kb, ke, kv,
+                     binv);
   TN_CHECK_LAUNCH();
 }
 

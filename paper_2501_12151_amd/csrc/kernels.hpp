@@ -184,11 +184,10 @@ void launch_dense_matvec(int N, const double* Bm, const double* z, double* y, co
 
 // Inverses of the diagonal mode blocks of the local operator, for the block-Jacobi
 // preconditioner: blk[a, c][j][i] = sum over the operator's nonzero terms (b, j, i, e, v)
-// of v L[a][b][a] Rt[c][e][c]; binv[(a t + c) n n + j n + i] = blk[a, c]^{-1} (Gauss-Jordan,
-// partial pivoting).  Term lists grouped by output mode j (beg[n + 1]); slot -> (b, i).
+// of v L[a][b][a] Rt[c][e][c]; binv[(a t + c) n n + j n + i] = blk[a, c]^{-1}.  Terms grouped
+// by mode pair j n + i (beg[n n + 1]; kb = b, ke = e, kv = v).
 void launch_local_block_inv(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* beg,
-                            const int* ta, const int* tb, const double* tv, const int* slot_b, const int* slot_i,
-                            double* binv, hipStream_t s);
+                            const int* kb, const int* ke, const double* kv, double* binv, hipStream_t s);
 
 // Householder QR of A (m x n, row-major, lda), single workgroup: Q (m x c), R (c x n), c = min(m, n).
 // ws: workspace of m * n + m * c + 2 * c doubles.
