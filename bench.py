@@ -246,9 +246,12 @@ def roofline(P, opts):
     ms, fl, nl = pst["apply_kernel_ms"], pst["apply_kernel_flops"], pst["apply_kernel_launches"]
     achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     cms, cfl, cnl = pst["contraction_ms"], pst["contraction_flops"], pst["contraction_launches"]
-    small = opts["rank_cap"] <= 32
-    kname = f"fused_apply32_kernel<{prec}>" if small else \
-        f"fused_apply_kernel<{prec}> / fused_apply32_kernel<{prec}> (by the ranks of each core step)"
+    cap = opts["rank_cap"]
+    kinds = ["fused_apply32_kernel"] + (["fused_apply64_kernel"] if cap > 32 else []) + \
+        (["fused_apply_kernel"] if cap > 64 else [])
+    kname = " / ".join(f"{k}<{prec}>" for k in kinds)
+    if len(kinds) > 1:
+        kname += " (by the ranks of each core step)"
     what = {0: "FP64 MFMA", 1: "FP32 MFMA", 2: "BF16 MFMA, FP32 accumulate"}[prec]
     return {
         "bound": "mfma",

@@ -437,7 +437,7 @@ void dev_local_apply_fused(Problem& P, const Plan& pl, int p, int q, int s, int 
   f.ta = pl.sp_ap_a;
   f.tb = pl.sp_ap_b;
   f.tv = pl.sp_ap_v;
-  f.ksplit = fused_apply_splits(pl.n, p, t, pl.sp_ap_max, P.ctx->splitk_cap);
+  f.ksplit = fused_apply_splits(f, pl.sp_ap_max, P.ctx->splitk_cap);
   launch_fused_apply(f, 0.0, st, precision);
   launch_fused_sum(f, y, st);
 }
@@ -884,7 +884,7 @@ struct Sweep {
       f.ta = pl.sp_ap_a;
       f.tb = pl.sp_ap_b;
       f.tv = pl.sp_ap_v;
-      f.ksplit = fused_apply_splits(n[k], p, t, pl.sp_ap_max, W.fpart_cap);
+      f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
       f.skip = W.flag + CG_DONE;
       a.ksplit = f.ksplit;
       a.partial = W.fpart;
@@ -1231,7 +1231,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
       f.ta = pl.sp_ap_a;
       f.tb = pl.sp_ap_b;
       f.tv = pl.sp_ap_v;
-      f.ksplit = fused_apply_splits(w.n[k], c.p, c.t, pl.sp_ap_max, W.fpart_cap);
+      f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
       f.skip = W.flag + CG_DONE;
       fused_prepare(f);
       c.a.ksplit = f.ksplit;
@@ -1247,17 +1247,16 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     max_n = std::max(max_n, w.n[k]);
   }
   // requests still iterating, split by apply kind; argument arrays to the device once
-  std::vector<int> cg, small, large, other;
+  std::vector<int> cg, other, bykind[3];
   for (int r = 0; r < nb; ++r) {
     if (L[r].done) continue;
     cg.push_back(r);
     if (!L[r].fused) other.push_back(r);
-    else if (fused_is_small(L[r].f)) small.push_back(r);
-    else large.push_back(r);
+    else bykind[fused_kind(L[r].f)].push_back(r);
   }
   int kit = 0;
   if (!cg.empty()) {
-    FusedBatch fb_small, fb_large;
+    FusedBatch fb[3];
     int large_tiles = 1;
     int nf = 0;
     auto fill = [&](const std::vector<int>& ids, FusedBatch& fb) {
@@ -1272,8 +1271,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
       }
       nf += fb.nreq;
     };
-    fill(small, fb_small);
-    fill(large, fb_large);
+    for (int kd = 0; kd < 3; ++kd) fill(bykind[kd], fb[kd]);
     CgBatch dir, upd;
     dir.args = upd.args = args.d_a;
     dir.nreq = upd.nreq = (int)cg.size();
@@ -1292,10 +1290,10 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     bool any = true;
     while (any && kit <= budget) {
       for (int c = 0; c < chunk && kit <= budget; ++c, ++kit) {
-        if (fb_small.nreq) launch_fused_apply_batch(fb_small, max_n, 1, true, st, 0);
-        if (fb_large.nreq) launch_fused_apply_batch(fb_large, max_n, large_tiles, false, st, 0);
-        for (int r : small) S[r]->fl.total += L[r].apply_flops;
-        for (int r : large) S[r]->fl.total += L[r].apply_flops;
+        for (int kd = 0; kd < 3; ++kd) {
+          if (fb[kd].nreq) launch_fused_apply_batch(fb[kd], max_n, large_tiles, kd, st, 0);
+          for (int r : bykind[kd]) S[r]->fl.total += L[r].apply_flops;
+        }
         for (int r : other) {
           Sweep& w = *S[r];
           if (L[r].explicit_mat) {

@@ -597,6 +597,127 @@ __device__ inline void mfma_k32(const typename Prec<P>::T (*sA)[33], const typen
   }
 }
 
+// The same on LDS tiles of row length LD, over k = k0 .. k0 + 31.
+template <int P, int LD>
+__device__ inline void mfma_k32o(const typename Prec<P>::T (*sA)[LD], const typename Prec<P>::T (*sB)[LD], int k0,
+                                 int arow, int bcol, int lk, int lrow, typename Prec<P>::Acc& acc) {
+  if constexpr (P == 0) {
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[k0 + kk + lk][arow + lrow], sB[k0 + kk + lk][bcol + lrow], acc, 0,
+                                                 0, 0);
+  } else if constexpr (P == 1) {
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[k0 + kk + lk][arow + lrow], sB[k0 + kk + lk][bcol + lrow], acc, 0,
+                                                 0, 0);
+  } else {
+    bf8_t a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a[j] = sA[k0 + 8 * lk + j][arow + lrow];
+      b[j] = sB[k0 + 8 * lk + j][bcol + lrow];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+}
+
+// The fused apply for 32 < max(p, q, s, t) <= 64: one workgroup computes the whole
+// p x t output of its mode (each wave one 32 x 32 quadrant), so the stage-1 product
+// L_b x_i (p x s, K = q) is formed once per term; the next term's operands are
+// loaded into registers while the current term's products run.  Partial tiles are
+// written in the 32 x 32 tile layout of the general kernel.
+template <int P>
+__device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int grp, const int z) {
+  using T = typename Prec<P>::T;
+  using Acc = typename Prec<P>::Acc;
+  __shared__ T sA[64][65];
+  __shared__ T sB[64][65];
+  __shared__ T sT[64][65];
+  __shared__ T sR[64][65];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int lrow = lane % 16, lk = lane / 16;
+  const int tb0 = f.beg[grp], te0 = f.beg[grp + 1];
+  const int cnt = te0 - tb0;
+  const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
+  const int tb = tb0 + z * chunk;
+  const int te = tb + chunk < te0 ? tb + chunk : te0;
+  const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
+  // thread -> 16 elements of each 64 x 64 tile: r = idx / 64, c = idx % 64, idx = tid + 256 j
+  double la[16], xb[16], rb[16], vcur = 0.0;
+  auto load = [&](int t, double (&l)[16], double (&x)[16], double (&rr)[16], double& v) {
+    const int slot = f.ta[t], e = f.tb[t];
+    v = f.tv[t];
+    const double* Lb = f.L + (long)f.slot_b[slot] * f.q;
+    const double* Xi = f.x + (long)f.slot_i[slot] * f.s;
+    const double* Re = f.Rt + (long)e * f.s;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
+      l[j] = (r < f.p && c < f.q) ? Lb[r * Lrow + c] : 0.0;
+      x[j] = (r < f.q && c < f.s) ? Xi[r * Xrow + c] : 0.0;
+      rr[j] = (r < f.t && c < f.s) ? Re[r * Rrow + c] : 0.0;
+    }
+  };
+  if (tb < te) load(tb, la, xb, rb, vcur);
+  Acc acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+  for (int t = tb; t < te; ++t) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
+      sA[c][r] = (T)la[j];  // A = L rows (m = r) x q (k = c)
+      sB[r][c] = (T)xb[j];  // B = x (k = r) x s (n = c)
+      sR[c][r] = (T)rb[j];  // B' = Rt^T: k = s (c), n = t (r)
+    }
+    const double v = vcur;
+    if (t + 1 < te) load(t + 1, la, xb, rb, vcur);
+    __syncthreads();
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        Acc tacc = {0, 0, 0, 0};
+        mfma_k32o<P, 65>(sA, sB, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, tacc);
+        mfma_k32o<P, 65>(sA, sB, 32, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, tacc);
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          sT[wn * 32 + ni * 16 + lrow][wm * 32 + mi * 16 + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[qq]);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        mfma_k32o<P, 65>(sT, sR, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, acc[mi][ni]);
+        mfma_k32o<P, 65>(sT, sR, 32, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, acc[mi][ni]);
+      }
+    __syncthreads();
+  }
+  // quadrant (wm, wn) is the 32 x 32 tile (wm, wn) of the general layout, when it exists
+  if (wm * 32 < f.p && wn * 32 < f.t) {
+    const int tile = wm * f.tiles_n + wn;
+    double* Pt = f.partial + (((long)z * f.n + grp) * f.ntiles + tile) * 1024;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          Pt[(mi * 16 + acc_row<P>(qq, lk)) * 32 + ni * 16 + lrow] = (double)acc[mi][ni][qq];
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void fused_apply64_kernel(FusedArgs f) {
+  if (f.skip && *f.skip) return;
+  fused_apply64_body<P>(f, blockIdx.y, blockIdx.z);
+}
+
 // Fast path of the fused apply for p, q, s, t <= 32 (one tile, one chunk of each
 // contracted index): the next term's operand tiles are loaded into registers
 // while the current term's two MFMA products run.
@@ -743,6 +864,16 @@ __global__ __launch_bounds__(256) void fused_apply32_batch_kernel(FusedBatch b) 
 }
 
 template <int P>
+__global__ __launch_bounds__(256) void fused_apply64_batch_kernel(FusedBatch b) {
+  const int z = blockIdx.z;
+  int r = 0;
+  while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
+  const FusedArgs f = b.args[r];
+  if (f.skip && *f.skip) return;
+  fused_apply64_body<P>(f, blockIdx.y, z - b.zoff[r]);
+}
+
+template <int P>
 __global__ __launch_bounds__(256) void fused_apply_batch_kernel(FusedBatch b) {
   const int z = blockIdx.z;
   int r = 0;
@@ -753,9 +884,17 @@ __global__ __launch_bounds__(256) void fused_apply_batch_kernel(FusedBatch b) {
   fused_apply_body<P>(f, blockIdx.y, blockIdx.x, z - b.zoff[r]);
 }
 
-int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles) {
-  const int ntiles = ((p + 31) / 32) * ((t + 31) / 32);
-  long ks = (128 + (long)n * ntiles - 1) / ((long)n * ntiles);
+int fused_kind(const FusedArgs& f) {
+  const int m = std::max(std::max(f.p, f.q), std::max(f.s, f.t));
+  return m <= 32 ? FUSED_32 : (m <= 64 ? FUSED_64 : FUSED_TILED);
+}
+
+int fused_apply_splits(const FusedArgs& f, int max_terms, size_t cap_doubles) {
+  const int n = f.n;
+  const int ntiles = ((f.p + 31) / 32) * ((f.t + 31) / 32);
+  // workgroups per split: the 32 / 64 kernels cover all output tiles of a mode in one
+  const long per_split = fused_kind(f) == FUSED_TILED ? (long)n * ntiles : n;
+  long ks = (128 + per_split - 1) / per_split;
   ks = std::min<long>(ks, std::max(1, max_terms / 2));
   const long fit = (long)(cap_doubles / ((size_t)n * ntiles * 1024));
   if (fit < 1) throw Error(TNFEM_EINVAL, "fused apply: partial buffer too small");
@@ -766,22 +905,21 @@ int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles) {
 static hipEvent_t* prof_begin(hipStream_t s);
 static void prof_end(hipEvent_t* pair, double flops, hipStream_t s, int kind);
 
+template <int P>
+static void launch_fused_kind(const FusedArgs& f, int kind, hipEvent_t* ev, hipStream_t s) {
+  const dim3 g1(1, f.n, f.ksplit), g(f.ntiles, f.n, f.ksplit);
+  if (kind == FUSED_32) TN_LAUNCH(ev, fused_apply32_kernel<P>, g1, dim3(256), 0, s, f);
+  else if (kind == FUSED_64) TN_LAUNCH(ev, fused_apply64_kernel<P>, g1, dim3(256), 0, s, f);
+  else TN_LAUNCH(ev, fused_apply_kernel<P>, g, dim3(256), 0, s, f);
+}
+
 void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision) {
-  f.tiles_n = (f.t + 31) / 32;
-  f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
+  fused_prepare(f);
   hipEvent_t* ev = prof_begin(s);
-  const bool small = f.p <= 32 && f.q <= 32 && f.s <= 32 && f.t <= 32;
-  const dim3 g32(1, f.n, f.ksplit), g(f.ntiles, f.n, f.ksplit);
-  if (precision == 1) {
-    if (small) TN_LAUNCH(ev, fused_apply32_kernel<1>, g32, dim3(256), 0, s, f);
-    else TN_LAUNCH(ev, fused_apply_kernel<1>, g, dim3(256), 0, s, f);
-  } else if (precision == 2) {
-    if (small) TN_LAUNCH(ev, fused_apply32_kernel<2>, g32, dim3(256), 0, s, f);
-    else TN_LAUNCH(ev, fused_apply_kernel<2>, g, dim3(256), 0, s, f);
-  } else {
-    if (small) TN_LAUNCH(ev, fused_apply32_kernel<0>, g32, dim3(256), 0, s, f);
-    else TN_LAUNCH(ev, fused_apply_kernel<0>, g, dim3(256), 0, s, f);
-  }
+  const int kind = fused_kind(f);
+  if (precision == 1) launch_fused_kind<1>(f, kind, ev, s);
+  else if (precision == 2) launch_fused_kind<2>(f, kind, ev, s);
+  else launch_fused_kind<0>(f, kind, ev, s);
   prof_end(ev, flops, s, precision ? PROF_FUSED_LOW : PROF_FUSED);
   TN_CHECK_LAUNCH();
 }
@@ -791,23 +929,21 @@ void fused_prepare(FusedArgs& f) {
   f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
 }
 
-bool fused_is_small(const FusedArgs& f) { return f.p <= 32 && f.q <= 32 && f.s <= 32 && f.t <= 32; }
+template <int P>
+static void launch_fused_batch_kind(const FusedBatch& b, int n, int max_ntiles, int kind, hipStream_t s) {
+  const int zt = b.zoff[b.nreq];
+  const dim3 g1(1, n, zt), g(max_ntiles, n, zt);
+  if (kind == FUSED_32) hipLaunchKernelGGL(fused_apply32_batch_kernel<P>, g1, dim3(256), 0, s, b);
+  else if (kind == FUSED_64) hipLaunchKernelGGL(fused_apply64_batch_kernel<P>, g1, dim3(256), 0, s, b);
+  else hipLaunchKernelGGL(fused_apply_batch_kernel<P>, g, dim3(256), 0, s, b);
+}
 
-void launch_fused_apply_batch(const FusedBatch& b, int n, int max_ntiles, bool small, hipStream_t s, int precision) {
+void launch_fused_apply_batch(const FusedBatch& b, int n, int max_ntiles, int kind, hipStream_t s, int precision) {
   if (b.nreq <= 0) return;
   if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "fused apply batch: too many requests");
-  const int zt = b.zoff[b.nreq];
-  const dim3 g32(1, n, zt), g(max_ntiles, n, zt);
-  if (precision == 1) {
-    if (small) hipLaunchKernelGGL(fused_apply32_batch_kernel<1>, g32, dim3(256), 0, s, b);
-    else hipLaunchKernelGGL(fused_apply_batch_kernel<1>, g, dim3(256), 0, s, b);
-  } else if (precision == 2) {
-    if (small) hipLaunchKernelGGL(fused_apply32_batch_kernel<2>, g32, dim3(256), 0, s, b);
-    else hipLaunchKernelGGL(fused_apply_batch_kernel<2>, g, dim3(256), 0, s, b);
-  } else {
-    if (small) hipLaunchKernelGGL(fused_apply32_batch_kernel<0>, g32, dim3(256), 0, s, b);
-    else hipLaunchKernelGGL(fused_apply_batch_kernel<0>, g, dim3(256), 0, s, b);
-  }
+  if (precision == 1) launch_fused_batch_kind<1>(b, n, max_ntiles, kind, s);
+  else if (precision == 2) launch_fused_batch_kind<2>(b, n, max_ntiles, kind, s);
+  else launch_fused_batch_kind<0>(b, n, max_ntiles, kind, s);
   TN_CHECK_LAUNCH();
 }
 

@@ -112,10 +112,13 @@ struct FusedArgs {
   int ksplit = 1, tiles_n = 1, ntiles = 1;
   const int* skip = nullptr;
 };
-int fused_apply_splits(int n, int p, int t, int max_terms, size_t cap_doubles);
+int fused_apply_splits(const FusedArgs& f, int max_terms, size_t cap_doubles);  // needs n, p, q, s, t
 // Sets the tile counts of f from its ranks (launch_fused_apply does this itself).
 void fused_prepare(FusedArgs& f);
-bool fused_is_small(const FusedArgs& f);  // all ranks <= 32: the one-tile kernel
+// kernel for a fused apply: all ranks <= 32 (one 32 x 32 tile), <= 64 (one 64 x 64 block
+// per workgroup), else 32 x 32 output tiles per workgroup
+enum FusedKind { FUSED_32 = 0, FUSED_64 = 1, FUSED_TILED = 2 };
+int fused_kind(const FusedArgs& f);
 
 // Shared launches across requests (at most FB_MAX per launch).  The argument
 // arrays live in device memory; zoff / boff are prefix sums of each request's
@@ -126,8 +129,8 @@ struct FusedBatch {
   int nreq = 0;
   int zoff[FB_MAX + 1] = {};
 };
-// All requests must have the same mode count n and all be small (or all not).
-void launch_fused_apply_batch(const FusedBatch& b, int n, int max_ntiles, bool small, hipStream_t s,
+// All requests must have the same mode count n and the same fused_kind.
+void launch_fused_apply_batch(const FusedBatch& b, int n, int max_ntiles, int kind, hipStream_t s,
                               int precision = 0);
 // precision: 0 FP64, 1 FP32 operands (FP32 accumulate), 2 BF16 operands (FP32 accumulate)
 void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision = 0);
