@@ -256,6 +256,7 @@ std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& de
       const int k = o ? P->K - 1 - j : j;
       MpoCore c = o ? reversed_core(A[k]) : A[k];
       P->plans[o].push_back(build_plan(c, P->arena, s, &P->t1max_slots, &P->t2max_slots));
+      if (!P->plans[o].back().dense) P->sp_slots_max = std::max(P->sp_slots_max, (size_t)P->plans[o].back().sp_nslot);
       P->mrank[o][j] = c.Rl;
       P->mrank[o][j + 1] = c.Rr;
       P->Rmax = std::max(P->Rmax, std::max(c.Rl, c.Rr));
@@ -437,6 +438,12 @@ void dev_local_apply_fused(Problem& P, const Plan& pl, int p, int q, int s, int 
   f.ta = pl.sp_ap_a;
   f.tb = pl.sp_ap_b;
   f.tv = pl.sp_ap_v;
+  f.nslot = pl.sp_nslot;
+  if (fused_kind(f) == FUSED_TILED) {
+    const size_t elems = fused_stage_elems(f);
+    f.stage = P.ctx->ensure_scratch(elems);
+    f.stage_bytes = elems * sizeof(double);
+  }
   f.ksplit = fused_apply_splits(f, pl.sp_ap_max, P.ctx->splitk_cap);
   launch_fused_apply(f, 0.0, st, precision);
   launch_fused_sum(f, y, st);
@@ -624,6 +631,14 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   W.scal = A(16);
   W.fpart_cap = (size_t)1 << 22;
   W.fpart = A(W.fpart_cap);
+  if (rc > 64) {  // the two-stage fused apply holds one padded p x s product per slot
+    const size_t rc64 = (rc + 63) / 64 * 64;
+    W.stage_bytes = P.sp_slots_max * rc64 * rc64 * sizeof(double);
+    W.stage = A(P.sp_slots_max * rc64 * rc64);
+  } else {
+    W.stage_bytes = 0;
+    W.stage = nullptr;
+  }
   W.splitk_cap = (size_t)1 << 22;
   W.splitk = A(W.splitk_cap);
   W.part = A(6 * 512);
@@ -884,6 +899,9 @@ struct Sweep {
       f.ta = pl.sp_ap_a;
       f.tb = pl.sp_ap_b;
       f.tv = pl.sp_ap_v;
+      f.nslot = pl.sp_nslot;
+      f.stage = W.stage;
+      f.stage_bytes = W.stage_bytes;
       f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
       f.skip = W.flag + CG_DONE;
       a.ksplit = f.ksplit;
@@ -1231,6 +1249,9 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
       f.ta = pl.sp_ap_a;
       f.tb = pl.sp_ap_b;
       f.tv = pl.sp_ap_v;
+      f.nslot = pl.sp_nslot;
+      f.stage = W.stage;
+      f.stage_bytes = W.stage_bytes;
       f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
       f.skip = W.flag + CG_DONE;
       fused_prepare(f);
@@ -1256,8 +1277,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
   }
   int kit = 0;
   if (!cg.empty()) {
-    FusedBatch fb[3];
-    int large_tiles = 1;
+    FusedBatch fb[2];  // shared launches of the one-pass kernels; ranks above 64 per request
     int nf = 0;
     auto fill = [&](const std::vector<int>& ids, FusedBatch& fb) {
       fb.args = args.d_f + nf;
@@ -1267,11 +1287,10 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
         const FusedArgs& f = L[ids[i]].f;
         args.h_f[nf + i] = f;
         fb.zoff[i + 1] = fb.zoff[i] + f.ksplit;
-        large_tiles = std::max(large_tiles, f.ntiles);
       }
       nf += fb.nreq;
     };
-    for (int kd = 0; kd < 3; ++kd) fill(bykind[kd], fb[kd]);
+    for (int kd = 0; kd < 2; ++kd) fill(bykind[kd], fb[kd]);
     CgBatch dir, upd;
     dir.args = upd.args = args.d_a;
     dir.nreq = upd.nreq = (int)cg.size();
@@ -1290,10 +1309,11 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     bool any = true;
     while (any && kit <= budget) {
       for (int c = 0; c < chunk && kit <= budget; ++c, ++kit) {
-        for (int kd = 0; kd < 3; ++kd) {
-          if (fb[kd].nreq) launch_fused_apply_batch(fb[kd], max_n, large_tiles, kd, st, 0);
+        for (int kd = 0; kd < 2; ++kd)
+          if (fb[kd].nreq) launch_fused_apply_batch(fb[kd], max_n, kd, st, 0);
+        for (int r : bykind[FUSED_TILED]) launch_fused_apply(L[r].f, 0.0, st, 0);
+        for (int kd = 0; kd < 3; ++kd)
           for (int r : bykind[kd]) S[r]->fl.total += L[r].apply_flops;
-        }
         for (int r : other) {
           Sweep& w = *S[r];
           if (L[r].explicit_mat) {

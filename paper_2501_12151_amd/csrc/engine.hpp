@@ -93,6 +93,8 @@ struct Workspace {
   size_t splitk_cap = 0;
   double* fpart = nullptr;  // fused-apply partial tiles
   size_t fpart_cap = 0;
+  double* stage = nullptr;  // slot products of the fused apply at ranks above 64
+  size_t stage_bytes = 0;
   double *Bloc = nullptr, *Mloc = nullptr;  // explicit local matrix (dense plans, small local systems)
   size_t bloc_n = 0, mloc_cap = 0;
   int* flag = nullptr;
@@ -116,6 +118,7 @@ struct Problem {
   std::vector<int> mrank[2];  // K + 1
   int Rmax = 1, smax = 1, maxn = 1;
   size_t t1max_slots = 1, t2max_slots = 1;
+  size_t sp_slots_max = 1;  // most slots of a sparse plan (stage of the two-stage fused apply)
   DevArena arena;
   std::unique_ptr<Workspace> ws;
   void ensure_workspace(int cap, int rho);

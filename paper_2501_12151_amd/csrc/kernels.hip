@@ -786,15 +786,95 @@ __global__ __launch_bounds__(256) void fused_apply32_kernel(FusedArgs f) {
   fused_apply32_body<P>(f, blockIdx.y, blockIdx.z);
 }
 
+// Ranks above 64: the apply in two stages.
+// Stage 1 (slot_product_kernel): S[slot] = L_b x_i for every slot (b, i) of the core,
+// p x s, stored in the operand type with rows and columns padded to multiples of 64
+// (the padding is written as zeros).  Each product is formed once, where the one-pass
+// kernels form it once per term that uses the slot.
+// Stage 2 (slot_apply_kernel): per output mode i', 64 x 64 output tiles,
+//   part[z][i'][tile32][32 x 32] = sum over the split's terms (slot, e, v) of
+//                                  v S[slot] Rt_e^T,
+// each term's product accumulated on MFMA (in the accumulate type) and added with its
+// coefficient into FP64 accumulators.  The partial tiles have the layout of the
+// one-pass kernels (32 x 32 tiles), so the CG reduction sums them unchanged.
+constexpr int kStageTile = 64;
+
+inline int pad64(int x) { return (x + kStageTile - 1) / kStageTile * kStageTile; }
+
 template <int P>
-__device__ __forceinline__ void fused_apply_body(const FusedArgs& f, const int grp, const int tile, const int z) {
+__global__ __launch_bounds__(256) void slot_product_kernel(FusedArgs f) {
   using T = typename Prec<P>::T;
   using Acc = typename Prec<P>::Acc;
-  __shared__ T sA[32][33];
-  __shared__ T sB[32][33];
-  __shared__ T sT[32][33];
-  __shared__ T sR[32][33];
-  const int m0 = (tile / f.tiles_n) * 32, n0 = (tile % f.tiles_n) * 32;
+  if (f.skip && *f.skip) return;
+  __shared__ T sA[32][65];
+  __shared__ T sB[32][65];
+  const int slot = blockIdx.y;
+  const int p64 = (f.p + 63) / 64 * 64, s64 = (f.s + 63) / 64 * 64;
+  const int tn = s64 / 64;
+  const int m0 = (blockIdx.x / tn) * 64, n0 = (blockIdx.x % tn) * 64;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int lrow = lane % 16, lk = lane / 16;
+  const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s;
+  const double* Lb = f.L + (long)f.slot_b[slot] * f.q;
+  const double* Xi = f.x + (long)f.slot_i[slot] * f.s;
+  // A: 64 rows x 32 k (k contiguous in memory); B: 32 k x 64 columns (columns contiguous)
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int idx = tid + 256 * j;
+      const int r = idx / 32, k = idx % 32;
+      ra[j] = (m0 + r < f.p && k0 + k < f.q) ? Lb[(m0 + r) * Lrow + k0 + k] : 0.0;
+      const int kb = idx / 64, c = idx % 64;
+      rb[j] = (k0 + kb < f.q && n0 + c < f.s) ? Xi[(k0 + kb) * Xrow + n0 + c] : 0.0;
+    }
+  };
+  Acc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+  const int nks = (f.q + 31) / 32;
+  load(0);
+  for (int ks = 0; ks < nks; ++ks) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int idx = tid + 256 * j;
+      sA[idx % 32][idx / 32] = (T)ra[j];
+      sB[idx / 64][idx % 64] = (T)rb[j];
+    }
+    if (ks + 1 < nks) load((ks + 1) * 32);
+    __syncthreads();
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+        mfma_k32o<P, 65>(sA, sB, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, acc[mi][ni]);
+    __syncthreads();
+  }
+  T* S = static_cast<T*>(f.stage) + ((long)slot * p64 + m0) * s64 + n0;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq)
+        S[(long)(wm * 32 + mi * 16 + acc_row<P>(qq, lk)) * s64 + wn * 32 + ni * 16 + lrow] = (T)acc[mi][ni][qq];
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void slot_apply_kernel(FusedArgs f) {
+  using T = typename Prec<P>::T;
+  using Acc = typename Prec<P>::Acc;
+  if (f.skip && *f.skip) return;
+  __shared__ T sA[32][65];
+  __shared__ T sB[32][65];
+  const int grp = blockIdx.y, z = blockIdx.z;
+  const int p64 = (f.p + 63) / 64 * 64, s64 = (f.s + 63) / 64 * 64;
+  const int tn = (f.t + 63) / 64;
+  const int bm = blockIdx.x / tn, bn = blockIdx.x % tn;
+  const int m0 = bm * 64, n0 = bn * 64;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
   const int lrow = lane % 16, lk = lane / 16;
@@ -803,52 +883,78 @@ __device__ __forceinline__ void fused_apply_body(const FusedArgs& f, const int g
   const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
   const int tb = tb0 + z * chunk;
   const int te = tb + chunk < te0 ? tb + chunk : te0;
-  const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
-  Acc acc = {0, 0, 0, 0};
-  for (int t = tb; t < te; ++t) {
-    const int slot = f.ta[t], e = f.tb[t];
-    const double v = f.tv[t];
-    const int b = f.slot_b[slot], i = f.slot_i[slot];
-    const double* Lb = f.L + (long)b * f.q;
-    const double* Xi = f.x + (long)i * f.s;
-    const double* Re = f.Rt + (long)e * f.s;
-    for (int s0 = 0; s0 < f.s; s0 += 32) {
-      Acc tacc = {0, 0, 0, 0};
-      for (int q0 = 0; q0 < f.q; q0 += 32) {
-        for (int idx = tid; idx < 32 * 32; idx += 256) {
-          const int r = idx / 32, c = idx % 32;  // c fastest: contiguous in memory
-          const int gm = m0 + r, gk = q0 + c;
-          sA[c][r] = (T)((gm < f.p && gk < f.q) ? Lb[gm * Lrow + gk] : 0.0);
-          const int gk2 = q0 + r, gn = s0 + c;
-          sB[r][c] = (T)((gk2 < f.q && gn < f.s) ? Xi[gk2 * Xrow + gn] : 0.0);
-        }
-        __syncthreads();
-        mfma_k32<P>(sA, sB, wm * 16, wn * 16, lk, lrow, tacc);
-        __syncthreads();
-      }
-      // T1 chunk (32 rows x 32 cols of s) -> sT[s][row], scaled by v; Rt chunk -> sR[s][col]
+  const long Rrow = (long)f.Rr * f.s;
+  const T* S = static_cast<const T*>(f.stage);
+  const int nks = (f.s + 31) / 32;
+  // item = (term, k step); A = S[slot] rows m0.., k (in bounds: padded); B = Rt_e^T
+  T ra[8];
+  double rb[8];
+  auto load = [&](int t, int k0) {
+    const T* Sa = S + ((long)f.ta[t] * p64 + m0) * s64 + k0;
+    const double* Re = f.Rt + (long)f.tb[t] * f.s + k0;
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) sT[wn * 16 + lrow][wm * 16 + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[qq]);
-      for (int idx = tid; idx < 32 * 32; idx += 256) {
-        const int r = idx / 32, c = idx % 32;  // r: output col (t), c: s index (contiguous)
-        const int gn = n0 + r, gk = s0 + c;
-        sR[c][r] = (T)((gn < f.t && gk < f.s) ? Re[gn * Rrow + gk] : 0.0);
-      }
-      __syncthreads();
-      mfma_k32<P>(sT, sR, wm * 16, wn * 16, lk, lrow, acc);
-      __syncthreads();
+    for (int j = 0; j < 8; ++j) {
+      const int idx = tid + 256 * j;
+      const int r = idx / 32, k = idx % 32;
+      ra[j] = Sa[(long)r * s64 + k];
+      rb[j] = (n0 + r < f.t && k0 + k < f.s) ? Re[(n0 + r) * Rrow + k] : 0.0;
+    }
+  };
+  double acc[2][2][4];
+  Acc tacc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      tacc[i][j] = Acc{0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.0;
+    }
+  const long items = (long)(te > tb ? te - tb : 0) * nks;
+  if (items > 0) load(tb, 0);
+  for (long it = 0; it < items; ++it) {
+    const int t = tb + (int)(it / nks), ks = (int)(it % nks);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int idx = tid + 256 * j;
+      sA[idx % 32][idx / 32] = ra[j];
+      sB[idx % 32][idx / 32] = (T)rb[j];
+    }
+    if (it + 1 < items) load(tb + (int)((it + 1) / nks), (int)((it + 1) % nks) * 32);
+    __syncthreads();
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+        mfma_k32o<P, 65>(sA, sB, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, tacc[mi][ni]);
+    __syncthreads();
+    if (ks == nks - 1) {
+      const double v = f.tv[t];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[mi][ni][q] += v * (double)tacc[mi][ni][q];
+          tacc[mi][ni] = Acc{0, 0, 0, 0};
+        }
     }
   }
-  double* Pt = f.partial + (((long)z * f.n + grp) * f.ntiles + tile) * 1024;
+  // the wave's 32 x 32 quadrant is 32-tile (2 bm + wm, 2 bn + wn), when it exists
+  const int rt = 2 * bm + wm, ct = 2 * bn + wn;
+  if (rt * 32 < f.p && ct * 32 < f.t) {
+    double* Pt = f.partial + (((long)z * f.n + grp) * f.ntiles + rt * f.tiles_n + ct) * 1024;
 #pragma unroll
-  for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + acc_row<P>(qq, lk)) * 32 + wn * 16 + lrow] = (double)acc[qq];
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          Pt[(mi * 16 + acc_row<P>(qq, lk)) * 32 + ni * 16 + lrow] = acc[mi][ni][qq];
+  }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void fused_apply_kernel(FusedArgs f) {
-  if (f.skip && *f.skip) return;
-  fused_apply_body<P>(f, blockIdx.y, blockIdx.x, blockIdx.z);
-}
+size_t fused_stage_elems(const FusedArgs& f) { return (size_t)f.nslot * pad64(f.p) * pad64(f.s); }
 
 // Shared launch of the fused apply of several requests (same mode count n): grid z
 // runs over the requests' split ranges zoff[r] .. zoff[r + 1]; every block does
@@ -873,17 +979,6 @@ __global__ __launch_bounds__(256) void fused_apply64_batch_kernel(FusedBatch b) 
   fused_apply64_body<P>(f, blockIdx.y, z - b.zoff[r]);
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void fused_apply_batch_kernel(FusedBatch b) {
-  const int z = blockIdx.z;
-  int r = 0;
-  while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
-  const FusedArgs f = b.args[r];
-  if (f.skip && *f.skip) return;
-  if ((int)blockIdx.x >= f.ntiles) return;
-  fused_apply_body<P>(f, blockIdx.y, blockIdx.x, z - b.zoff[r]);
-}
-
 int fused_kind(const FusedArgs& f) {
   const int m = std::max(std::max(f.p, f.q), std::max(f.s, f.t));
   return m <= 32 ? FUSED_32 : (m <= 64 ? FUSED_64 : FUSED_TILED);
@@ -892,9 +987,13 @@ int fused_kind(const FusedArgs& f) {
 int fused_apply_splits(const FusedArgs& f, int max_terms, size_t cap_doubles) {
   const int n = f.n;
   const int ntiles = ((f.p + 31) / 32) * ((f.t + 31) / 32);
-  // workgroups per split: the 32 / 64 kernels cover all output tiles of a mode in one
-  const long per_split = fused_kind(f) == FUSED_TILED ? (long)n * ntiles : n;
-  long ks = (128 + per_split - 1) / per_split;
+  // workgroups per split: the 32 / 64 kernels cover all output tiles of a mode in one;
+  // the two-stage kernel has 64 x 64 output tiles and far more work per term, so it is
+  // split further (about two workgroups per compute unit)
+  const bool staged = fused_kind(f) == FUSED_TILED;
+  const long per_split = staged ? (long)n * ((f.p + 63) / 64) * ((f.t + 63) / 64) : n;
+  const long target = staged ? 512 : 128;
+  long ks = (target + per_split - 1) / per_split;
   ks = std::min<long>(ks, std::max(1, max_terms / 2));
   const long fit = (long)(cap_doubles / ((size_t)n * ntiles * 1024));
   if (fit < 1) throw Error(TNFEM_EINVAL, "fused apply: partial buffer too small");
@@ -907,10 +1006,25 @@ static void prof_end(hipEvent_t* pair, double flops, hipStream_t s, int kind);
 
 template <int P>
 static void launch_fused_kind(const FusedArgs& f, int kind, hipEvent_t* ev, hipStream_t s) {
-  const dim3 g1(1, f.n, f.ksplit), g(f.ntiles, f.n, f.ksplit);
-  if (kind == FUSED_32) TN_LAUNCH(ev, fused_apply32_kernel<P>, g1, dim3(256), 0, s, f);
-  else if (kind == FUSED_64) TN_LAUNCH(ev, fused_apply64_kernel<P>, g1, dim3(256), 0, s, f);
-  else TN_LAUNCH(ev, fused_apply_kernel<P>, g, dim3(256), 0, s, f);
+  const dim3 g1(1, f.n, f.ksplit);
+  if (kind == FUSED_32) {
+    TN_LAUNCH(ev, fused_apply32_kernel<P>, g1, dim3(256), 0, s, f);
+  } else if (kind == FUSED_64) {
+    TN_LAUNCH(ev, fused_apply64_kernel<P>, g1, dim3(256), 0, s, f);
+  } else {
+    if (!f.stage || f.nslot <= 0 || fused_stage_elems(f) * sizeof(double) > f.stage_bytes)
+      throw Error(TNFEM_EINVAL, "fused apply: stage buffer missing or too small for ranks above 64");
+    const dim3 g_prod((pad64(f.p) / 64) * (pad64(f.s) / 64), f.nslot);
+    const dim3 g_app(((f.p + 63) / 64) * ((f.t + 63) / 64), f.n, f.ksplit);
+    // the profile pair brackets both stages: start at the first dispatch, end at the second
+    if (ev) {
+      hipExtLaunchKernelGGL(slot_product_kernel<P>, g_prod, dim3(256), 0, s, ev[0], nullptr, 0, f);
+      hipExtLaunchKernelGGL(slot_apply_kernel<P>, g_app, dim3(256), 0, s, nullptr, ev[1], 0, f);
+    } else {
+      hipLaunchKernelGGL(slot_product_kernel<P>, g_prod, dim3(256), 0, s, f);
+      hipLaunchKernelGGL(slot_apply_kernel<P>, g_app, dim3(256), 0, s, f);
+    }
+  }
 }
 
 void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision) {
@@ -930,20 +1044,20 @@ void fused_prepare(FusedArgs& f) {
 }
 
 template <int P>
-static void launch_fused_batch_kind(const FusedBatch& b, int n, int max_ntiles, int kind, hipStream_t s) {
+static void launch_fused_batch_kind(const FusedBatch& b, int n, int kind, hipStream_t s) {
   const int zt = b.zoff[b.nreq];
-  const dim3 g1(1, n, zt), g(max_ntiles, n, zt);
+  const dim3 g1(1, n, zt);
   if (kind == FUSED_32) hipLaunchKernelGGL(fused_apply32_batch_kernel<P>, g1, dim3(256), 0, s, b);
   else if (kind == FUSED_64) hipLaunchKernelGGL(fused_apply64_batch_kernel<P>, g1, dim3(256), 0, s, b);
-  else hipLaunchKernelGGL(fused_apply_batch_kernel<P>, g, dim3(256), 0, s, b);
+  else throw Error(TNFEM_EINVAL, "fused apply batch: ranks above 64 are launched per request");
 }
 
-void launch_fused_apply_batch(const FusedBatch& b, int n, int max_ntiles, int kind, hipStream_t s, int precision) {
+void launch_fused_apply_batch(const FusedBatch& b, int n, int kind, hipStream_t s, int precision) {
   if (b.nreq <= 0) return;
   if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "fused apply batch: too many requests");
-  if (precision == 1) launch_fused_batch_kind<1>(b, n, max_ntiles, kind, s);
-  else if (precision == 2) launch_fused_batch_kind<2>(b, n, max_ntiles, kind, s);
-  else launch_fused_batch_kind<0>(b, n, max_ntiles, kind, s);
+  if (precision == 1) launch_fused_batch_kind<1>(b, n, kind, s);
+  else if (precision == 2) launch_fused_batch_kind<2>(b, n, kind, s);
+  else launch_fused_batch_kind<0>(b, n, kind, s);
   TN_CHECK_LAUNCH();
 }
 
@@ -1398,84 +1512,6 @@ void launch_local_block_inv(int p, int n, int t, int Rl, int Rr, const double* L
 constexpr int QR_NT = 1024;
 constexpr size_t QR_LDS_BYTES = 160 * 1024 - 2048;  // gfx950: 160 KB of LDS per workgroup
 
-// LDS = true: the Householder vectors and the Q accumulation live in dynamic LDS.
-template <bool LDS>
-__global__ __launch_bounds__(QR_NT) void qr_kernel(int m, int n, const double* A, int lda, double* Q, int ldq,
-                                                   double* R, int ldr, double* ws) {
-  extern __shared__ double dyn[];
-  __shared__ double red[QR_NT / 64];
-  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int c = m < n ? m : n;
-  double* base = LDS ? dyn : ws;
-  double* W = base;                  // m x n, column-major
-  double* Qc = base + (long)m * n;   // m x c, column-major
-  double* tau = Qc + (long)m * c;    // c
-  double* diag = tau + c;            // c
-  for (long idx = tid; idx < (long)m * n; idx += QR_NT) {
-    const int i = idx / n, j = idx % n;
-    W[(long)j * m + i] = A[(long)i * lda + j];
-  }
-  __syncthreads();
-  for (int j = 0; j < c; ++j) {
-    double* v = W + (long)j * m;
-    double loc = 0.0;
-    for (int i = j + tid; i < m; i += QR_NT) loc += v[i] * v[i];
-    const double s = block_sum<QR_NT>(loc, red);
-    const double x0 = v[j];
-    const double nrm = sqrt(s);
-    double tj = 0.0, alpha = 0.0, v0 = x0;
-    if (nrm > 0.0) {
-      alpha = x0 >= 0.0 ? -nrm : nrm;
-      v0 = x0 - alpha;
-      tj = 2.0 / (s - x0 * x0 + v0 * v0);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      v[j] = v0;
-      tau[j] = tj;
-      diag[j] = alpha;
-    }
-    __syncthreads();
-    if (tj != 0.0) {
-      for (int col = j + 1 + wave; col < n; col += QR_NT / 64) {
-        double* w = W + (long)col * m;
-        double part = 0.0;
-        for (int i = j + lane; i < m; i += 64) part += v[i] * w[i];
-        const double f = tj * wave_sum(part);
-        for (int i = j + lane; i < m; i += 64) w[i] -= f * v[i];
-      }
-    }
-    __syncthreads();
-  }
-  for (long idx = tid; idx < (long)c * n; idx += QR_NT) {
-    const int i = idx / n, jj = idx % n;
-    R[(long)i * ldr + jj] = jj < i ? 0.0 : (jj == i ? diag[i] : W[(long)jj * m + i]);
-  }
-  for (long idx = tid; idx < (long)m * c; idx += QR_NT) {
-    const int jj = idx / m, i = idx % m;
-    Qc[idx] = (i == jj) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int j = c - 1; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj != 0.0) {
-      const double* v = W + (long)j * m;
-      for (int col = j + wave; col < c; col += QR_NT / 64) {
-        double* q = Qc + (long)col * m;
-        double part = 0.0;
-        for (int i = j + lane; i < m; i += 64) part += v[i] * q[i];
-        const double f = tj * wave_sum(part);
-        for (int i = j + lane; i < m; i += 64) q[i] -= f * v[i];
-      }
-    }
-    __syncthreads();
-  }
-  for (long idx = tid; idx < (long)m * c; idx += QR_NT) {
-    const int i = idx / c, jj = idx % c;
-    Q[(long)i * ldq + jj] = Qc[(long)jj * m + i];
-  }
-}
-
 // Householder QR with columns owned by wavefronts (column col belongs to wave
 // col % waves) and rows by lanes (row i to lane i % 64) in every phase, so no
 // lane reads another lane's writes without a barrier in between.  The owner of
@@ -1584,6 +1620,186 @@ __global__ __launch_bounds__(QR_NT) void qr_owner_batch_kernel(QrBatch b) {
   qr_owner_body<LDS>(j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R, j.ldr, j.ws, dyn);
 }
 
+// The same factorisation for matrices that do not fit in LDS (m <= 64 KR): W and the
+// Q accumulation stay in global memory, with the same column ownership.  A column
+// update loads the lane's KR rows of the column into registers at once (one memory
+// latency per column rather than one per row block), takes the reflector from an LDS
+// double buffer, and writes the column back once.  Column accesses are buffer
+// loads / stores whose range is the column's m rows, so rows past m read as zero and
+// are not written, with no branches (branches around each store make the compiler
+// wait for every earlier store).  Reflector j is held in LDS with zeros outside rows
+// j..m-1, so a column update needs no row masks: rows above j are left as they are.
+// The owner of column j + 1 forms reflector j + 1 from its registers and publishes it
+// in the other LDS buffer, so each column still costs one barrier.
+// Q = H_0 ... H_{c-1} E is accumulated backwards: at step j every wave applies H_j to
+// its columns col >= j (a column of E is untouched by the reflectors after it; rows
+// above j are still zero), the reflector staged in LDS one step ahead by its owner.
+typedef long long i64x1_t __attribute__((ext_vector_type(1)));
+
+__device__ inline __amdgpu_buffer_rsrc_t column_rsrc(double* col, int m) {
+  // raw buffer, 32-bit data format (the gfx9 descriptor word for untyped access)
+  return __builtin_amdgcn_make_buffer_rsrc(col, (short)0, m * 8, 0x00020000);
+}
+
+template <int KR, int NT>
+__device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int lda, double* Q, int ldq, double* R,
+                                            int ldr, double* ws) {
+  constexpr int NW = NT / 64;
+  __shared__ double sv[2][64 * KR];
+  __shared__ double stau[2];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int c = m < n ? m : n;
+  double* W = ws;                   // m x n, column-major
+  double* Qc = ws + (long)m * n;    // m x c, column-major
+  double* tau = Qc + (long)m * c;   // c
+  double* diag = tau + c;           // c
+  for (long idx = tid; idx < (long)m * n; idx += NT) {
+    const int i = idx / n, j = idx % n;
+    W[(long)j * m + i] = A[(long)i * lda + j];
+  }
+  for (int i = tid; i < 2 * 64 * KR; i += NT) (&sv[0][0])[i] = 0.0;
+  __syncthreads();
+  double wr[KR];
+  // all m rows of a column, rows below lo replaced by zero
+  auto load_col = [&](double* w, int lo) {
+    const __amdgpu_buffer_rsrc_t rs = column_rsrc(w, m);
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = lane + 64 * k;
+      const double x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, 512 * k, 0));
+      wr[k] = i >= lo ? x : 0.0;
+    }
+  };
+  auto store_col = [&](double* w) {
+    const __amdgpu_buffer_rsrc_t rs = column_rsrc(w, m);
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i64x1_t, wr[k]), rs, lane * 8, 512 * k, 0);
+  };
+  // wr <- (I - tj v v^T) wr; v is zero outside the reflector's rows
+  auto apply_reg = [&](const double* v, double tj) {
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) part += v[lane + 64 * k] * wr[k];
+    const double f = tj * wave_sum(part);
+    // read v again rather than holding it in KR more registers
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < KR; ++k) wr[k] -= f * v[lane + 64 * k];
+  };
+  // reflector of column j from wr (rows >= j, zero elsewhere): v to W column j and sv[buf]
+  auto reflect = [&](int j, int buf) {
+    double loc = 0.0, xj = 0.0;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      loc += wr[k] * wr[k];
+      xj = lane + 64 * k == j ? wr[k] : xj;
+    }
+    const double s2 = wave_sum(loc);
+    const double x0 = __shfl(xj, j % 64, 64);
+    const double nrm = sqrt(s2);
+    double tj = 0.0, alpha = 0.0, v0 = x0;
+    if (nrm > 0.0) {
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      v0 = x0 - alpha;
+      tj = 2.0 / (s2 - x0 * x0 + v0 * v0);
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) sv[buf][lane + 64 * k] = lane + 64 * k == j ? v0 : wr[k];
+    if (lane == j % 64) {
+      W[(long)j * m + j] = v0;
+      tau[j] = tj;
+      diag[j] = alpha;
+      stau[buf] = tj;
+    }
+  };
+  if (c > 0 && wave == 0) {
+    load_col(W, 0);
+    reflect(0, 0);
+  }
+  __syncthreads();
+  for (int j = 0; j < c; ++j) {
+    const double* v = sv[j & 1];
+    const double tj = stau[j & 1];
+    const int nxt = j + 1;
+    if (nxt < n && wave == nxt % NW) {
+      double* w = W + (long)nxt * m;
+      load_col(w, 0);
+      if (tj != 0.0) apply_reg(v, tj);
+      store_col(w);
+      if (nxt < c) {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) wr[k] = lane + 64 * k >= nxt ? wr[k] : 0.0;
+        reflect(nxt, nxt & 1);
+      }
+    }
+    if (tj != 0.0) {
+      for (int col = nxt + 1; col < n; ++col) {
+        if (col % NW != wave) continue;
+        double* w = W + (long)col * m;
+        load_col(w, 0);
+        apply_reg(v, tj);
+        store_col(w);
+      }
+    }
+    __syncthreads();
+  }
+  for (long idx = tid; idx < (long)c * n; idx += NT) {
+    const int i = idx / n, jj = idx % n;
+    R[(long)i * ldr + jj] = jj < i ? 0.0 : (jj == i ? diag[i] : W[(long)jj * m + i]);
+  }
+  // Q, backwards over the reflectors; v_j staged into sv[j & 1] one step ahead
+  auto stage = [&](int j) {
+    load_col(W + (long)j * m, j);
+#pragma unroll
+    for (int k = 0; k < KR; ++k) sv[j & 1][lane + 64 * k] = wr[k];
+  };
+  if (c > 0 && wave == (c - 1) % NW) stage(c - 1);
+  __syncthreads();
+  for (int j = c - 1; j >= 0; --j) {
+    const double* v = sv[j & 1];
+    const double tj = tau[j];
+    for (int col = j; col < c; ++col) {
+      if (col % NW != wave) continue;
+      double* q = Qc + (long)col * m;
+      if (col == j) {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) wr[k] = lane + 64 * k == j ? 1.0 : 0.0;
+      } else {
+        load_col(q, j + 1);  // rows up to j are still zero in this column
+      }
+      if (tj != 0.0) apply_reg(v, tj);
+      store_col(q);
+    }
+    if (j > 0 && wave == (j - 1) % NW) stage(j - 1);
+    __syncthreads();
+  }
+  for (long idx = tid; idx < (long)m * c; idx += NT) {
+    const int i = idx / c, jj = idx % c;
+    Q[(long)i * ldq + jj] = Qc[(long)jj * m + i];
+  }
+}
+
+// threads of the register variant: 32 rows per lane need the register file of 2 waves per SIMD
+template <int KR>
+constexpr int qr_reg_threads() { return KR >= 32 ? 512 : QR_NT; }
+
+template <int KR>
+__global__ __launch_bounds__(qr_reg_threads<KR>()) void qr_reg_kernel(int m, int n, const double* A, int lda,
+                                                                     double* Q, int ldq, double* R, int ldr,
+                                                                     double* ws) {
+  qr_reg_body<KR, qr_reg_threads<KR>()>(m, n, A, lda, Q, ldq, R, ldr, ws);
+}
+
+template <int KR>
+__global__ __launch_bounds__(qr_reg_threads<KR>()) void qr_reg_batch_kernel(QrBatch b) {
+  const QrJob j = b.job[blockIdx.x];
+  qr_reg_body<KR, qr_reg_threads<KR>()>(j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R, j.ldr, j.ws);
+}
+
+// rows per lane of the register variant for m rows (0: too tall, use the plain global variant)
+static int qr_reg_rows(int m) { return m <= 512 ? 8 : (m <= 1024 ? 16 : (m <= 2048 ? 32 : 0)); }
+
 static size_t qr_lds_bytes(int m, int n) {
   const int c = m < n ? m : n;
   return ((size_t)m * n + (size_t)m * c + 2 * (size_t)c) * sizeof(double);
@@ -1612,7 +1828,15 @@ void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s) {
     TN_CHECK_LAUNCH();
   }
   if (in_ws.njob) {
-    hipLaunchKernelGGL(qr_owner_batch_kernel<false>, dim3(in_ws.njob), dim3(QR_NT), 0, s, in_ws);
+    int kr = 8;
+    for (int i = 0; i < in_ws.njob; ++i) {
+      const int r = qr_reg_rows(in_ws.job[i].m);
+      kr = r == 0 ? 0 : (kr == 0 ? 0 : std::max(kr, r));
+    }
+    if (kr == 8) hipLaunchKernelGGL(qr_reg_batch_kernel<8>, dim3(in_ws.njob), dim3(QR_NT), 0, s, in_ws);
+    else if (kr == 16) hipLaunchKernelGGL(qr_reg_batch_kernel<16>, dim3(in_ws.njob), dim3(QR_NT), 0, s, in_ws);
+    else if (kr == 32) hipLaunchKernelGGL(qr_reg_batch_kernel<32>, dim3(in_ws.njob), dim3(qr_reg_threads<32>()), 0, s, in_ws);
+    else hipLaunchKernelGGL(qr_owner_batch_kernel<false>, dim3(in_ws.njob), dim3(QR_NT), 0, s, in_ws);
     TN_CHECK_LAUNCH();
   }
 }
@@ -1629,7 +1853,12 @@ void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, doubl
     });
     hipLaunchKernelGGL(qr_owner_kernel<true>, dim3(1), dim3(QR_NT), bytes, s, m, n, A, lda, Q, ldq, R, ldr, ws);
   } else {
-    hipLaunchKernelGGL(qr_owner_kernel<false>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+    const int kr = qr_reg_rows(m);
+    if (kr == 8) hipLaunchKernelGGL(qr_reg_kernel<8>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+    else if (kr == 16) hipLaunchKernelGGL(qr_reg_kernel<16>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+    else if (kr == 32)
+      hipLaunchKernelGGL(qr_reg_kernel<32>, dim3(1), dim3(qr_reg_threads<32>()), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+    else hipLaunchKernelGGL(qr_owner_kernel<false>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
   }
   TN_CHECK_LAUNCH();
 }

@@ -111,12 +111,18 @@ struct FusedArgs {
   const double* tv = nullptr;
   int ksplit = 1, tiles_n = 1, ntiles = 1;
   const int* skip = nullptr;
+  // ranks above 64 (two-stage apply): the slot products S[slot] = L_b x_i, nslot slots,
+  // fused_stage_elems(f) elements of the operand type in a buffer of stage_bytes bytes
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  int nslot = 0;
 };
+size_t fused_stage_elems(const FusedArgs& f);
 int fused_apply_splits(const FusedArgs& f, int max_terms, size_t cap_doubles);  // needs n, p, q, s, t
 // Sets the tile counts of f from its ranks (launch_fused_apply does this itself).
 void fused_prepare(FusedArgs& f);
 // kernel for a fused apply: all ranks <= 32 (one 32 x 32 tile), <= 64 (one 64 x 64 block
-// per workgroup), else 32 x 32 output tiles per workgroup
+// per workgroup), else the two-stage apply (slot products, then 64 x 64 output tiles)
 enum FusedKind { FUSED_32 = 0, FUSED_64 = 1, FUSED_TILED = 2 };
 int fused_kind(const FusedArgs& f);
 
@@ -129,9 +135,9 @@ struct FusedBatch {
   int nreq = 0;
   int zoff[FB_MAX + 1] = {};
 };
-// All requests must have the same mode count n and the same fused_kind.
-void launch_fused_apply_batch(const FusedBatch& b, int n, int max_ntiles, int kind, hipStream_t s,
-                              int precision = 0);
+// All requests must have the same mode count n and the same fused_kind, FUSED_32 or
+// FUSED_64 (the two-stage apply of higher ranks is launched per request).
+void launch_fused_apply_batch(const FusedBatch& b, int n, int kind, hipStream_t s, int precision = 0);
 // precision: 0 FP64, 1 FP32 operands (FP32 accumulate), 2 BF16 operands (FP32 accumulate)
 void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision = 0);
 // y = sum of the partial tiles written by launch_fused_apply with the same f.

@@ -25,7 +25,7 @@ def ctx():
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("ranks", [(32, 32, 32, 32), (5, 7, 33, 17)])
+@pytest.mark.parametrize("ranks", [(32, 32, 32, 32), (5, 7, 33, 17), (70, 65, 100, 66), (129, 40, 33, 72)])
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_fused_apply_precision_bound(ctx, dim, ranks, precision):
     prob = workloads.small_2d() if dim == 2 else workloads.cube_body_force(4)

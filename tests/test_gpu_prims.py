@@ -26,7 +26,10 @@ def ctx():
     c.close()
 
 
-QR_SHAPES = [(1, 1), (8, 8), (64, 16), (256, 36), (1024, 132), (37, 5), (5, 37), (300, 256)]
+# beyond LDS: 8 / 16 / 32 rows per lane in registers (m <= 512 / 1024 / 2048), wide (m < n),
+# and taller than 2048 rows (the plain global-memory variant)
+QR_SHAPES = [(1, 1), (8, 8), (64, 16), (256, 36), (1024, 132), (37, 5), (5, 37), (300, 256), (1600, 200),
+             (100, 250), (2100, 40), (513, 65)]
 
 
 @pytest.mark.parametrize("m,n", QR_SHAPES)
@@ -43,6 +46,24 @@ def test_qr_matches_definition(ctx, m, n):
     assert np.all(np.tril(R, -1) == 0)
     Rl = np.linalg.qr(A)[1]
     assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rl)), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("m,n", [(700, 60), (40, 12)])
+def test_qr_rank_deficient(ctx, m, n):
+    """Zero and repeated columns (zero reflectors): Q R = A and Q orthonormal still hold."""
+    print(f"qr deficient m={m} n={n}", flush=True)
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n))
+    A[:, 3] = 0.0
+    A[:, 7] = A[:, 1]
+    A[:, n - 1] = 2.0 * A[:, 0]
+    c = min(m, n)
+    dA, dQ, dR = dev(A), torch.zeros((m, c), dtype=torch.float64, device="cuda"), torch.zeros((c, n), dtype=torch.float64, device="cuda")
+    ctx.qr(m, n, dA, dQ, dR, stream=torch.cuda.current_stream())
+    Q, R = host(dQ), host(dR)
+    assert np.linalg.norm(Q @ R - A) <= 1e-13 * np.linalg.norm(A) * np.sqrt(n)
+    assert np.abs(Q.T @ Q - np.eye(c)).max() <= 1e-13 * m
+    assert np.all(np.tril(R, -1) == 0)
 
 
 SVD_CASES = [(1, 1, "rand"), (16, 8, "rand"), (256, 32, "rand"), (512, 68, "rand"), (40, 40, "graded"),
