@@ -796,10 +796,42 @@ struct Sweep {
   int sb(int j) const { return P.brank[orient][j]; }
   const double* B(int k) const { return P.bcore[orient][k]; }
 
+  // y = local operator applied to x between interfaces L and Rt: the fused kernel plus
+  // the ordered sum of its partial tiles for sparse plans, the GEMM chain for dense ones
   void apply(int k, int p, int q, int s, int t, const double* L, const double* x, const double* Rt, double* y,
              const int* skip) {
     const Plan& pl = plan(k);
-    local_apply_ws(P, pl, p, q, s, t, L, x, Rt, y, skip, st, &fl, W.T1, W.T2);
+    if (pl.dense) {
+      local_apply_ws(P, pl, p, q, s, t, L, x, Rt, y, skip, st, &fl, W.T1, W.T2);
+      return;
+    }
+    FusedArgs f;
+    f.L = L;
+    f.x = x;
+    f.Rt = Rt;
+    f.partial = W.fpart;
+    f.p = p;
+    f.q = q;
+    f.s = s;
+    f.t = t;
+    f.Rl = pl.Rl;
+    f.Rr = pl.Rr;
+    f.n = pl.n;
+    f.slot_b = pl.sp_slot_b;
+    f.slot_i = pl.sp_slot_i;
+    f.beg = pl.sp_ap_beg;
+    f.ta = pl.sp_ap_a;
+    f.tb = pl.sp_ap_b;
+    f.tv = pl.sp_ap_v;
+    f.nslot = pl.sp_nslot;
+    f.stage = W.stage;
+    f.stage_bytes = W.stage_bytes;
+    f.skip = skip;
+    f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
+    const double flops = 2.0 * p * q * s * pl.sp_nslot + 2.0 * p * s * t * pl.sp_n_ap;
+    launch_fused_apply(f, flops, st, 0);
+    launch_fused_sum(f, y, st);
+    fl.total += flops;
   }
 
   void update_envs(int k) {
@@ -872,8 +904,6 @@ struct Sweep {
     FusedArgs f;
     // fused evaluation from the nonzero lists: always for sparse plans; for dense
     // plans when the per-apply work of the term lists stays small
-    const double sp_flops = 2.0 * pl.sp_n_ap * ((double)p * p * t + (double)p * t * t);
-    (void)sp_flops;
     const bool fused = !pl.dense;
     const size_t m_need = (size_t)pl.Rl * n[k] * n[k] * (size_t)t * t;
     const bool explicit_mat = pl.dense && !done && (size_t)N <= W.bloc_n && m_need <= W.mloc_cap;

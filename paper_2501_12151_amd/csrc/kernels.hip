@@ -1065,6 +1065,7 @@ static int blocks_for(long total);
 
 // y[row][grp][col] = sum over splits of the fused partial tiles (split order).
 __global__ void fused_sum_kernel(FusedArgs f, double* y) {
+  if (f.skip && *f.skip) return;
   const long N = (long)f.p * f.n * f.t;
   const long stride = (long)f.n * f.ntiles * 1024;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
