@@ -1866,6 +1866,42 @@ void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, doubl
 
 // ----------------------------------------------------------------------------- Jacobi SVD
 
+// Jacobi rotation of a column pair with squared norms a, b and inner product c:
+// tan(theta) = t, the root of smaller magnitude of t^2 + 2 zeta t - 1 = 0 with
+// zeta = (b - a) / (2c), cs = 1 / sqrt(1 + t^2), sn = cs t.  The reciprocals and
+// square roots are the hardware approximations refined by two Newton steps each
+// (quadratic convergence from their ~26 correct bits), a shorter dependency chain
+// than IEEE division and square root; the rotation only needs a few ulps.
+__device__ inline double rcp_refined(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ inline double rsq_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+// c != 0 and a, b >= 0
+__device__ inline void jacobi_rotation(double a, double b, double c, double& cs, double& sn) {
+  const double zeta = (b - a) * rcp_refined(2.0 * c);
+  const double az = fabs(zeta);
+  double t;
+  if (az < 1e150) {
+    const double x = fma(zeta, zeta, 1.0);
+    t = rcp_refined(az + x * rsq_refined(x));
+  } else {
+    t = 0.5 / az;
+  }
+  t = zeta >= 0.0 ? t : -t;
+  cs = rsq_refined(fma(t, t, 1.0));
+  sn = cs * t;
+}
+// whether the pair is off the rounding level: |c| > eps sqrt(a b)
+__device__ inline bool jacobi_rotate(double a, double b, double c, double eps) {
+  return c != 0.0 && c * c > eps * eps * (a * b);
+}
+
 constexpr int SV_NT = 256;
 constexpr int SV_LDS_MAXN = 64;
 constexpr int SV_MAXN = 256;
@@ -1919,10 +1955,9 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
         a = group_sum(a, tpp);
         b = group_sum(b, tpp);
         cc = group_sum(cc, tpp);
-        if (q < n && cc != 0.0 && fabs(cc) > eps * sqrt(a * b)) {
-          const double zeta = (b - a) / (2.0 * cc);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        if (q < n && jacobi_rotate(a, b, cc, eps)) {
+          double cs, sn;
+          jacobi_rotation(a, b, cc, cs, sn);
           for (int i = sub; i < n; i += tpp) {
             const double gp = Gc[p * n + i], gq = Gc[q * n + i];
             Gc[p * n + i] = cs * gp - sn * gq;
@@ -1962,11 +1997,11 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
   for (int j = tid; j < n; j += SV_NT) S[pos[j]] = sv[j];
 }
 
-// The same one-sided Jacobi iteration for n <= 64 on a single wavefront: each
-// column pair of a step is owned by a group of 64 / (n / 2) lanes that reduce
-// their dot products with cross-lane shuffles; a step ends with a barrier of the
-// one-wave workgroup.
+// The same one-sided Jacobi iteration for n <= 64 on four wavefronts: each column
+// pair of a step is owned by an aligned group of lanes (within one wavefront) that
+// reduce their dot products with DPP sums; a step ends with a workgroup barrier.
 constexpr int SVW_MAXN = 64;
+constexpr int SVW_NT = 256;
 
 __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int ldg, int trans, double* U, double* S,
                                                      double* V) {
@@ -1976,9 +2011,9 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
   __shared__ double Vc[SVW_MAXN * (SVW_MAXN + 1)];
   __shared__ double sv[SVW_MAXN];
   __shared__ int pos[SVW_MAXN];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   const int ld = n + 1;
-  for (int idx = lane; idx < n * n; idx += 64) {
+  for (int idx = tid; idx < n * n; idx += SVW_NT) {
     const int i = idx % n, j = idx / n;
     Gc[j * ld + i] = trans ? G[(long)j * ldg + i] : G[(long)i * ldg + j];
     Vc[j * ld + i] = (i == j) ? 1.0 : 0.0;
@@ -1987,8 +2022,8 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
   const int npad = n + (n & 1);
   const int npairs = npad / 2 > 0 ? npad / 2 : 1;
   int tpp = 1;
-  while (tpp * 2 * npairs <= 64) tpp *= 2;
-  const int pair = lane / tpp, sub = lane % tpp;
+  while (tpp * 2 * npairs <= SVW_NT && tpp < 64) tpp *= 2;
+  const int pair = tid / tpp, sub = tid % tpp;
   const int rpl = (n + tpp - 1) / tpp;  // rows per lane, contiguous
   const int i0 = sub * rpl, i1 = min(n, i0 + rpl);
   // rotation threshold at the rounding level of an n-term dot product: smaller
@@ -2014,10 +2049,9 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
         a = group_sum(a, tpp);
         b = group_sum(b, tpp);
         cc = group_sum(cc, tpp);
-        if (q < n && cc != 0.0 && fabs(cc) > eps * sqrt(a * b)) {
-          const double zeta = (b - a) / (2.0 * cc);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        if (q < n && jacobi_rotate(a, b, cc, eps)) {
+          double cs, sn;
+          jacobi_rotation(a, b, cc, cs, sn);
           for (int i = i0; i < i1; ++i) {
             const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
             Gc[p * ld + i] = cs * gp - sn * gq;
@@ -2031,28 +2065,28 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
       }
       __syncthreads();
     }
-    if (__ballot(rot) == 0) break;
+    if (!__syncthreads_or(rot)) break;
   }
-  for (int j = lane; j < n; j += 64) {
+  for (int j = tid; j < n; j += SVW_NT) {
     double s2 = 0.0;
     for (int i = 0; i < n; ++i) s2 += Gc[j * ld + i] * Gc[j * ld + i];
     sv[j] = sqrt(s2);
   }
   __syncthreads();
-  for (int j = lane; j < n; j += 64) {
+  for (int j = tid; j < n; j += SVW_NT) {
     int r = 0;
     for (int i = 0; i < n; ++i) r += (sv[i] > sv[j]) || (sv[i] == sv[j] && i < j);
     pos[j] = r;
   }
   __syncthreads();
-  for (int idx = lane; idx < n * n; idx += 64) {
+  for (int idx = tid; idx < n * n; idx += SVW_NT) {
     const int j = idx / n, i = idx % n;
     const int pj = pos[j];
     const double sj = sv[j];
     U[(long)i * n + pj] = sj > 0.0 ? Gc[j * ld + i] / sj : (i == pj ? 1.0 : 0.0);
     V[(long)i * n + pj] = Vc[j * ld + i];
   }
-  for (int j = lane; j < n; j += 64) S[pos[j]] = sv[j];
+  for (int j = tid; j < n; j += SVW_NT) S[pos[j]] = sv[j];
 }
 
 // The same iteration for 64 < n <= 137 on 1024 threads: G in dynamic LDS with a
@@ -2104,10 +2138,9 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
         a = group_sum(a, tpp);
         b = group_sum(b, tpp);
         cc = group_sum(cc, tpp);
-        if (q < n && cc != 0.0 && fabs(cc) > eps * sqrt(a * b)) {
-          const double zeta = (b - a) / (2.0 * cc);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        if (q < n && jacobi_rotate(a, b, cc, eps)) {
+          double cs, sn;
+          jacobi_rotation(a, b, cc, cs, sn);
           for (int i = i0; i < i1; ++i) {
             const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
             Gc[p * ld + i] = cs * gp - sn * gq;
@@ -2145,7 +2178,7 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
   for (int j = tid; j < n; j += SVB_NT) S[pos[j]] = sv[j];
 }
 
-__global__ __launch_bounds__(64) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, int trans, double* U,
+__global__ __launch_bounds__(SVW_NT) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, int trans, double* U,
                                                             double* S, double* V) {
   jacobi_svd_wave_body(n, G, ldg, trans, U, S, V);
 }
@@ -2158,7 +2191,7 @@ __global__ __launch_bounds__(SVB_NT) void jacobi_svd_big_kernel(int n, const dou
 }
 
 // One workgroup per job: the same one-sided Jacobi as the single launches.
-__global__ __launch_bounds__(64) void jacobi_svd_wave_batch_kernel(SvdBatch b) {
+__global__ __launch_bounds__(SVW_NT) void jacobi_svd_wave_batch_kernel(SvdBatch b) {
   const SvdJob j = b.job[blockIdx.x];
   jacobi_svd_wave_body(j.n, j.G, j.ldg, j.trans, j.U, j.S, j.V);
 }
@@ -2196,7 +2229,7 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
     }
   }
   if (wave.njob) {
-    hipLaunchKernelGGL(jacobi_svd_wave_batch_kernel, dim3(wave.njob), dim3(64), 0, s, wave);
+    hipLaunchKernelGGL(jacobi_svd_wave_batch_kernel, dim3(wave.njob), dim3(SVW_NT), 0, s, wave);
     TN_CHECK_LAUNCH();
   }
   if (big2.njob) {
@@ -2213,7 +2246,7 @@ void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, do
                        int trans) {
   if (n > SV_MAXN) throw Error(TNFEM_EINVAL, "Jacobi SVD limited to n <= 256");
   if (n <= SVW_MAXN) {
-    hipLaunchKernelGGL(jacobi_svd_wave_kernel, dim3(1), dim3(64), 0, s, n, G, ldg, trans, U, S, V);
+    hipLaunchKernelGGL(jacobi_svd_wave_kernel, dim3(1), dim3(SVW_NT), 0, s, n, G, ldg, trans, U, S, V);
     TN_CHECK_LAUNCH();
     return;
   }
