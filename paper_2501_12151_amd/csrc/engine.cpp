@@ -938,6 +938,12 @@ struct Sweep {
       a.partial = W.fpart;
       a.tiles_n = (t + 31) / 32;
       a.ntiles = ((p + 31) / 32) * a.tiles_n;
+      // the apply also forms the partials of (z, B z): one CG kernel per iteration
+      const int nd = fused_dot_count(f);
+      if (nd <= CG_DOT_MAX) {
+        f.dots = W.part + CG_DOT_OFFSET;
+        a.ndots = nd;
+      }
     } else {
       a.ksplit = 0;
       a.w = W.q;
@@ -986,8 +992,12 @@ struct Sweep {
           } else {
             apply(k, p, p, t, t, EA[k], W.z, EA[k + 1], W.q, W.flag + CG_DONE);
           }
-          launch_cg_reduce_dir(a, kit, st);
-          launch_cg_update2(a, kit, st);
+          if (a.ndots > 0) {
+            launch_cg_step(a, kit, st);
+          } else {
+            launch_cg_reduce_dir(a, kit, st);
+            launch_cg_update2(a, kit, st);
+          }
         }
         readback();
         done = hint()[0];
@@ -1289,6 +1299,11 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
       c.a.partial = W.fpart;
       c.a.tiles_n = (c.t + 31) / 32;
       c.a.ntiles = ((c.p + 31) / 32) * c.a.tiles_n;
+      const int nd = fused_dot_count(f);
+      if (nd <= CG_DOT_MAX) {
+        f.dots = W.part + CG_DOT_OFFSET;
+        c.a.ndots = nd;
+      }
     } else {
       c.a.ksplit = 0;
       c.a.w = W.q;
@@ -1321,13 +1336,25 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
       nf += fb.nreq;
     };
     for (int kd = 0; kd < 2; ++kd) fill(bykind[kd], fb[kd]);
-    CgBatch dir, upd;
-    dir.args = upd.args = args.d_a;
-    dir.nreq = upd.nreq = (int)cg.size();
-    for (size_t i = 0; i < cg.size(); ++i) {
-      args.h_a[i] = L[cg[i]].a;
-      dir.boff[i + 1] = dir.boff[i] + L[cg[i]].a.nb_dir;
-      upd.boff[i + 1] = upd.boff[i] + L[cg[i]].a.nb_upd;
+    // requests whose apply forms (z, B z) take one step kernel per iteration, the others
+    // the direction and update kernels; the argument array holds the step group first
+    std::vector<int> order;
+    for (int r : cg)
+      if (L[r].a.ndots > 0) order.push_back(r);
+    const int nstep = (int)order.size();
+    for (int r : cg)
+      if (L[r].a.ndots == 0) order.push_back(r);
+    CgBatch step, dir, upd;
+    step.args = args.d_a;
+    step.nreq = nstep;
+    dir.args = upd.args = args.d_a + nstep;
+    dir.nreq = upd.nreq = (int)cg.size() - nstep;
+    for (int i = 0; i < (int)order.size(); ++i) args.h_a[i] = L[order[i]].a;
+    for (int i = 0; i < nstep; ++i) step.boff[i + 1] = step.boff[i] + L[order[i]].a.nb_upd;
+    for (int i = 0; i < dir.nreq; ++i) {
+      const CgIterArgs& a = L[order[nstep + i]].a;
+      dir.boff[i + 1] = dir.boff[i] + a.nb_dir;
+      upd.boff[i + 1] = upd.boff[i] + a.nb_upd;
     }
     if (nf)
       hip_check(hipMemcpyAsync(args.d_f, args.h_f, sizeof(FusedArgs) * nf, hipMemcpyHostToDevice, st),
@@ -1354,6 +1381,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
             w.apply(k, L[r].p, L[r].p, L[r].t, L[r].t, w.EA[k], w.W.z, w.EA[k + 1], w.W.q, w.W.flag + CG_DONE);
           }
         }
+        launch_cg_step_batch(step, kit, st);
         launch_cg_reduce_dir_batch(dir, kit, st);
         launch_cg_update2_batch(upd, kit, st);
       }

@@ -550,6 +550,16 @@ void launch_cg_update(int n, double* x, const double* p, const double* q, double
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
+// Sum of one value per thread over a 256-thread workgroup in a fixed order, stored by
+// thread 0 (every thread of the workgroup must call it).
+__device__ inline void store_block_dot(double d, double* dst) {
+  __shared__ double red[4];
+  d = wave_sum(d);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) *dst = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 template <int P>
 struct Prec;
 template <>
@@ -710,6 +720,19 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
         for (int qq = 0; qq < 4; ++qq)
           Pt[(mi * 16 + acc_row<P>(qq, lk)) * 32 + ni * 16 + lrow] = (double)acc[mi][ni][qq];
   }
+  if (f.dots) {
+    double d = 0.0;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int row = wm * 32 + mi * 16 + acc_row<P>(qq, lk), col = wn * 32 + ni * 16 + lrow;
+          if (row < f.p && col < f.t) d += (double)acc[mi][ni][qq] * f.x[((long)row * f.n + grp) * f.s + col];
+        }
+    store_block_dot(d, f.dots + (long)z * f.n + grp);
+  }
 }
 
 template <int P>
@@ -778,6 +801,15 @@ __device__ __forceinline__ void fused_apply32_body(const FusedArgs& f, const int
   double* Pt = f.partial + ((long)z * f.n + grp) * 1024;
 #pragma unroll
   for (int qq = 0; qq < 4; ++qq) Pt[(wm * 16 + acc_row<P>(qq, lk)) * 32 + wn * 16 + lrow] = (double)acc[qq];
+  if (f.dots) {
+    double d = 0.0;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int row = wm * 16 + acc_row<P>(qq, lk), col = wn * 16 + lrow;
+      if (row < f.p && col < f.t) d += (double)acc[qq] * f.x[((long)row * f.n + grp) * f.s + col];
+    }
+    store_block_dot(d, f.dots + (long)z * f.n + grp);
+  }
 }
 
 template <int P>
@@ -952,6 +984,19 @@ __global__ __launch_bounds__(256) void slot_apply_kernel(FusedArgs f) {
         for (int qq = 0; qq < 4; ++qq)
           Pt[(mi * 16 + acc_row<P>(qq, lk)) * 32 + ni * 16 + lrow] = acc[mi][ni][qq];
   }
+  if (f.dots) {
+    double d = 0.0;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int row = m0 + wm * 32 + mi * 16 + acc_row<P>(qq, lk), col = n0 + wn * 32 + ni * 16 + lrow;
+          if (row < f.p && col < f.t) d += acc[mi][ni][qq] * f.x[((long)row * f.n + grp) * f.s + col];
+        }
+    store_block_dot(d, f.dots + ((long)z * f.n + grp) * (((f.p + 63) / 64) * tn) + blockIdx.x);
+  }
 }
 
 size_t fused_stage_elems(const FusedArgs& f) { return (size_t)f.nslot * pad64(f.p) * pad64(f.s); }
@@ -982,6 +1027,11 @@ __global__ __launch_bounds__(256) void fused_apply64_batch_kernel(FusedBatch b) 
 int fused_kind(const FusedArgs& f) {
   const int m = std::max(std::max(f.p, f.q), std::max(f.s, f.t));
   return m <= 32 ? FUSED_32 : (m <= 64 ? FUSED_64 : FUSED_TILED);
+}
+
+int fused_dot_count(const FusedArgs& f) {
+  const int per = fused_kind(f) == FUSED_TILED ? ((f.p + 63) / 64) * ((f.t + 63) / 64) : 1;
+  return f.ksplit * f.n * per;
 }
 
 int fused_apply_splits(const FusedArgs& f, int max_terms, size_t cap_doubles) {
@@ -1090,6 +1140,8 @@ void launch_fused_sum(FusedArgs f, double* y, hipStream_t s) {
 // Block partials: parts[PART_RZ + (k % 2) * CG_MAXB + blk] etc.; scalars scal[CG_RZ0 + k % 2].
 
 constexpr int PART_RZ = 0, PART_RR = 2 * CG_MAXB, PART_PQ = 4 * CG_MAXB;
+// cg_step reuses the p.q region (and the one after it) for the apply's (z, B z) partials
+static_assert(CG_DOT_OFFSET == PART_PQ && CG_DOT_MAX == 2 * CG_MAXB, "dot partial region");
 
 // z_j = sum_i brow[i] r_i over the bn lanes of a block (aligned groups of bnp lanes);
 // every lane of the group takes part in the exchanges.
@@ -1224,6 +1276,141 @@ __device__ __forceinline__ void cg_update2_body(const CgIterArgs& a, const int k
 
 __global__ __launch_bounds__(256) void cg_update2_kernel(CgIterArgs a, int k) { cg_update2_body(a, k, blockIdx.x); }
 
+// One iteration of the same preconditioned CG in the Chronopoulos-Gear arrangement,
+// after the fused apply of z_k that also wrote the partials of delta = (z_k, B z_k):
+//   gamma = (r_k, z_k); beta = gamma / gamma_{k-1}; (p_k, B p_k) = delta - beta gamma / alpha_{k-1}
+//   (delta alone at k = 0, beta = 0); alpha = gamma / (p_k, B p_k);
+//   p = z + beta p; q = w + beta q (q = B p); x += alpha p; r -= alpha q; z = M^-1 r;
+//   block partials of (r, z), (r, r) for iteration k + 1.
+// Convergence of iteration k is tested first, from the previous step's partials.
+__device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, const int bid) {
+  __shared__ double red[4];
+  __shared__ double tot[3];
+  if (a.flag[CG_DONE]) return;
+  const int nb = a.nb_upd;
+  const int par = k & 1;
+  // the three partial sums by the first wavefront (lane-strided, then a fixed-order
+  // wavefront sum), the same in every block
+  if (threadIdx.x < 64) {
+    const double* prr = a.parts + PART_RR + par * CG_MAXB;
+    const double* prz = a.parts + PART_RZ + par * CG_MAXB;
+    const double* pd = a.parts + CG_DOT_OFFSET;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 64) {
+      s0 += prr[i];
+      s1 += prz[i];
+    }
+    for (int i = threadIdx.x; i < a.ndots; i += 64) s2 += pd[i];
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (threadIdx.x == 0) {
+      tot[0] = s0;
+      tot[1] = s1;
+      tot[2] = s2;
+    }
+  }
+  __syncthreads();
+  const double rr = tot[0];
+  if (rr <= a.scal[CG_THR2] || k >= a.maxit) {
+    if (bid == 0 && threadIdx.x == 0) {
+      a.flag[CG_DONE] = 1;
+      a.flag[CG_ITERS] = k;
+    }
+    return;
+  }
+  const double gamma = tot[1];
+  const double delta = tot[2];
+  double beta = 0.0, pq = delta;
+  if (k > 0) {
+    beta = gamma / a.scal[CG_RZ0 + (par ^ 1)];
+    pq = delta - beta * gamma / a.scal[CG_ALPHA0 + (par ^ 1)];
+  }
+  if (!(pq > 0.0)) {  // breakdown: stop without updating
+    if (bid == 0 && threadIdx.x == 0) {
+      a.flag[CG_DONE] = 2;
+      a.flag[CG_ITERS] = k;
+    }
+    return;
+  }
+  const double alpha = gamma / pq;
+  if (bid == 0 && threadIdx.x == 0) {
+    a.scal[CG_RZ0 + par] = gamma;
+    a.scal[CG_ALPHA0 + par] = alpha;
+    a.flag[CG_ITERS] = k;
+  }
+  const long stride = (long)a.n * a.ntiles * 1024;
+  // B z at element e: the ordered sum of the split partial tiles
+  auto bz = [&](long e) {
+    const int col = (int)(e % a.t), grp = (int)((e / a.t) % a.n), row = (int)(e / ((long)a.t * a.n));
+    const int tile = (row / 32) * a.tiles_n + col / 32;
+    const double* src = a.partial + ((long)grp * a.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
+    double w = 0.0;
+    int zz = 0;
+    for (; zz + 4 <= a.ksplit; zz += 4) {
+      const double w0 = src[zz * stride], w1 = src[(zz + 1) * stride];
+      const double w2 = src[(zz + 2) * stride], w3 = src[(zz + 3) * stride];
+      w += w0;
+      w += w1;
+      w += w2;
+      w += w3;
+    }
+    for (; zz < a.ksplit; ++zz) w += src[zz * stride];
+    return w;
+  };
+  double lrz = 0.0, lrr = 0.0;
+  if (a.bn > 0) {
+    const int bn = a.bn, bnp = a.bnp, t = a.bt;
+    const long total = (long)(a.N / bn) * bnp;
+    const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
+    for (long idx = bid * 256 + threadIdx.x; idx < total; idx += (long)nb * 256) {
+      const int j = (int)(idx % bnp);
+      const long blk = idx / bnp;
+      const bool act = j < bn;
+      const long e = ((blk / t) * bn + j) * t + blk % t;
+      double ri = 0.0;
+      if (act) {
+        const double pi = a.z[e] + beta * a.p[e];
+        const double qi = bz(e) + beta * a.q[e];
+        a.p[e] = pi;
+        a.q[e] = qi;
+        a.x[e] += alpha * pi;
+        ri = a.r[e] - alpha * qi;
+        a.r[e] = ri;
+      }
+      const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
+      if (act) {
+        a.z[e] = zi;
+        lrz += ri * zi;
+        lrr += ri * ri;
+      }
+    }
+  } else {
+    for (long e = bid * 256 + threadIdx.x; e < a.N; e += (long)nb * 256) {
+      const double pi = a.z[e] + beta * a.p[e];
+      const double qi = bz(e) + beta * a.q[e];
+      a.p[e] = pi;
+      a.q[e] = qi;
+      a.x[e] += alpha * pi;
+      const double ri = a.r[e] - alpha * qi;
+      const double zi = ri * a.dinv[e];
+      a.r[e] = ri;
+      a.z[e] = zi;
+      lrz += ri * zi;
+      lrr += ri * ri;
+    }
+  }
+  const double trz = block_sum<256>(lrz, red);
+  const double trr = block_sum<256>(lrr, red);
+  const int npar = (k + 1) & 1;
+  if (threadIdx.x == 0) {
+    a.parts[PART_RZ + npar * CG_MAXB + bid] = trz;
+    a.parts[PART_RR + npar * CG_MAXB + bid] = trr;
+  }
+}
+
+__global__ __launch_bounds__(256) void cg_step_kernel(CgIterArgs a, int k) { cg_step_body(a, k, blockIdx.x); }
+
 // r = g - Bx; z = dinv r; p = q = 0; block partials of r.z, r.r (parity 0);
 // the last block also derives res, thr and the skip decision for the host.
 __global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const double* g, const double* bx, double tol) {
@@ -1321,6 +1508,11 @@ void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s) {
   hipLaunchKernelGGL(cg_update2_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, k);
   TN_CHECK_LAUNCH();
 }
+void launch_cg_step(const CgIterArgs& a, int k, hipStream_t s) {
+  if (a.ndots <= 0 || a.ndots > CG_DOT_MAX || a.ksplit <= 0) throw Error(TNFEM_EINVAL, "cg_step: needs fused partials");
+  hipLaunchKernelGGL(cg_step_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, k);
+  TN_CHECK_LAUNCH();
+}
 
 // Shared launches of the CG iteration kernels of several requests: grid x runs over
 // the requests' block ranges boff[r] .. boff[r + 1] (nb_dir or nb_upd blocks each).
@@ -1342,6 +1534,12 @@ __global__ __launch_bounds__(256) void cg_update2_batch_kernel(CgBatch b, int k)
   cg_update2_body(a, k, blockIdx.x - b.boff[r]);
 }
 
+__global__ __launch_bounds__(256) void cg_step_batch_kernel(CgBatch b, int k) {
+  const int r = cg_batch_request(b, blockIdx.x);
+  const CgIterArgs a = b.args[r];
+  cg_step_body(a, k, blockIdx.x - b.boff[r]);
+}
+
 void launch_cg_reduce_dir_batch(const CgBatch& b, int k, hipStream_t s) {
   if (b.nreq <= 0) return;
   if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "CG batch: too many requests");
@@ -1353,6 +1551,13 @@ void launch_cg_update2_batch(const CgBatch& b, int k, hipStream_t s) {
   if (b.nreq <= 0) return;
   if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "CG batch: too many requests");
   hipLaunchKernelGGL(cg_update2_batch_kernel, dim3(b.boff[b.nreq]), dim3(256), 0, s, b, k);
+  TN_CHECK_LAUNCH();
+}
+
+void launch_cg_step_batch(const CgBatch& b, int k, hipStream_t s) {
+  if (b.nreq <= 0) return;
+  if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "CG batch: too many requests");
+  hipLaunchKernelGGL(cg_step_batch_kernel, dim3(b.boff[b.nreq]), dim3(256), 0, s, b, k);
   TN_CHECK_LAUNCH();
 }
 

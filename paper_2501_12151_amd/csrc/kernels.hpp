@@ -116,7 +116,12 @@ struct FusedArgs {
   void* stage = nullptr;
   size_t stage_bytes = 0;
   int nslot = 0;
+  // optional (CG, p == q and s == t): each workgroup writes the inner product of x with
+  // its partial output tile(s) to dots[fused_dot_index]; their sum is (x, A x)
+  double* dots = nullptr;
 };
+// number of inner-product partials a fused apply with dots writes
+int fused_dot_count(const FusedArgs& f);
 size_t fused_stage_elems(const FusedArgs& f);
 int fused_apply_splits(const FusedArgs& f, int max_terms, size_t cap_doubles);  // needs n, p, q, s, t
 // Sets the tile counts of f from its ranks (launch_fused_apply does this itself).
@@ -145,7 +150,9 @@ void launch_fused_sum(FusedArgs f, double* y, hipStream_t s);
 
 // Local PCG with per-block partial sums (no atomics inside the iteration):
 // iteration k = apply (w = B z) -> reduce_dir(k) -> update2(k).
-enum { CG_RZ0 = 8 };  // scal[CG_RZ0 + k % 2] = r.z of iteration k
+enum { CG_RZ0 = 8, CG_ALPHA0 = 10 };  // scal[CG_RZ0 + k % 2] = r.z, scal[CG_ALPHA0 + k % 2] = alpha of iteration k
+// the inner-product partials of the fused apply (cg_step) live at parts + CG_DOT_OFFSET
+constexpr int CG_DOT_OFFSET = 4 * 512, CG_DOT_MAX = 1024;
 struct CgIterArgs {
   int N = 0;
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
@@ -164,12 +171,17 @@ struct CgIterArgs {
   // binv [p][t][bn][bn]; bnp = bn rounded up to a power of two (lanes per block); bt = t
   int bn = 0, bnp = 1, bt = 1;
   const double* binv = nullptr;
+  // > 0: the apply wrote ndots partials of (z, B z) at parts + CG_DOT_OFFSET (cg_step)
+  int ndots = 0;
 };
 int cg_vec_blocks(int n);
 int cg_dir_blocks(int n);
 void launch_cg_init2(const CgIterArgs& a, const double* g, const double* bx, double tol, hipStream_t s);
 void launch_cg_reduce_dir(const CgIterArgs& a, int k, hipStream_t s);
 void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s);
+// One kernel per iteration after a fused apply that wrote its (z, B z) partials
+// (Chronopoulos-Gear form of the same PCG): replaces reduce_dir + update2.
+void launch_cg_step(const CgIterArgs& a, int k, hipStream_t s);
 struct CgBatch {
   const CgIterArgs* args = nullptr;  // device array
   int nreq = 0;
@@ -177,6 +189,7 @@ struct CgBatch {
 };
 void launch_cg_reduce_dir_batch(const CgBatch& b, int k, hipStream_t s);  // boff over nb_dir
 void launch_cg_update2_batch(const CgBatch& b, int k, hipStream_t s);     // boff over nb_upd
+void launch_cg_step_batch(const CgBatch& b, int k, hipStream_t s);        // boff over nb_upd
 
 // Jacobi preconditioner: d[a][i][c] = sum over diagonal terms (b, e, v) of group i of
 // v * L[a][b][a] * Rt[c][e][c]; dinv = 1/d where d > 0 else 1.
