@@ -1847,40 +1847,65 @@ __device__ inline __amdgpu_buffer_rsrc_t column_rsrc(double* col, int m) {
   return __builtin_amdgcn_make_buffer_rsrc(col, (short)0, m * 8, 0x00020000);
 }
 
-template <int KR, int NT>
+// PAD = true: W and Q live in dynamic LDS (dyn) with the column stride padded to 64 KR
+// rows of zeros, so column accesses are plain LDS reads and writes with no range
+// checks; the padding rows stay zero (every reflector is zero there).
+template <int KR, int NT, bool PAD>
 __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int lda, double* Q, int ldq, double* R,
-                                            int ldr, double* ws) {
+                                            int ldr, double* ws, double* dyn) {
   constexpr int NW = NT / 64;
   __shared__ double sv[2][64 * KR];
   __shared__ double stau[2];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int c = m < n ? m : n;
-  double* W = ws;                   // m x n, column-major
-  double* Qc = ws + (long)m * n;    // m x c, column-major
-  double* tau = Qc + (long)m * c;   // c
-  double* diag = tau + c;           // c
-  for (long idx = tid; idx < (long)m * n; idx += NT) {
-    const int i = idx / n, j = idx % n;
-    W[(long)j * m + i] = A[(long)i * lda + j];
+  const int ld = PAD ? 64 * KR : m;  // column stride of W and Q
+  double* W = PAD ? dyn : ws;         // ld x n, column-major
+  double* Qc = W + (long)ld * n;      // ld x c, column-major
+  double* tau = Qc + (long)ld * c;    // c
+  double* diag = tau + c;             // c
+  if constexpr (PAD) {
+    for (long idx = tid; idx < (long)ld * n; idx += NT) {
+      const int i = idx % ld, j = idx / ld;
+      W[(long)j * ld + i] = i < m ? A[(long)i * lda + j] : 0.0;
+    }
+  } else {
+    for (long idx = tid; idx < (long)m * n; idx += NT) {
+      const int i = idx / n, j = idx % n;
+      W[(long)j * ld + i] = A[(long)i * lda + j];
+    }
   }
   for (int i = tid; i < 2 * 64 * KR; i += NT) (&sv[0][0])[i] = 0.0;
   __syncthreads();
   double wr[KR];
   // all m rows of a column, rows below lo replaced by zero
   auto load_col = [&](double* w, int lo) {
-    const __amdgpu_buffer_rsrc_t rs = column_rsrc(w, m);
+    if constexpr (PAD) {
 #pragma unroll
-    for (int k = 0; k < KR; ++k) {
-      const int i = lane + 64 * k;
-      const double x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, 512 * k, 0));
-      wr[k] = i >= lo ? x : 0.0;
+      for (int k = 0; k < KR; ++k) {
+        const int i = lane + 64 * k;
+        const double x = w[i];
+        wr[k] = i >= lo ? x : 0.0;
+      }
+    } else {
+      const __amdgpu_buffer_rsrc_t rs = column_rsrc(w, m);
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = lane + 64 * k;
+        const double x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, 512 * k, 0));
+        wr[k] = i >= lo ? x : 0.0;
+      }
     }
   };
   auto store_col = [&](double* w) {
-    const __amdgpu_buffer_rsrc_t rs = column_rsrc(w, m);
+    if constexpr (PAD) {
 #pragma unroll
-    for (int k = 0; k < KR; ++k)
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i64x1_t, wr[k]), rs, lane * 8, 512 * k, 0);
+      for (int k = 0; k < KR; ++k) w[lane + 64 * k] = wr[k];
+    } else {
+      const __amdgpu_buffer_rsrc_t rs = column_rsrc(w, m);
+#pragma unroll
+      for (int k = 0; k < KR; ++k)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i64x1_t, wr[k]), rs, lane * 8, 512 * k, 0);
+    }
   };
   // wr <- (I - tj v v^T) wr; v is zero outside the reflector's rows
   auto apply_reg = [&](const double* v, double tj) {
@@ -1913,7 +1938,7 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int l
 #pragma unroll
     for (int k = 0; k < KR; ++k) sv[buf][lane + 64 * k] = lane + 64 * k == j ? v0 : wr[k];
     if (lane == j % 64) {
-      W[(long)j * m + j] = v0;
+      W[(long)j * ld + j] = v0;
       tau[j] = tj;
       diag[j] = alpha;
       stau[buf] = tj;
@@ -1929,7 +1954,7 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int l
     const double tj = stau[j & 1];
     const int nxt = j + 1;
     if (nxt < n && wave == nxt % NW) {
-      double* w = W + (long)nxt * m;
+      double* w = W + (long)nxt * ld;
       load_col(w, 0);
       if (tj != 0.0) apply_reg(v, tj);
       store_col(w);
@@ -1942,7 +1967,7 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int l
     if (tj != 0.0) {
       for (int col = nxt + 1; col < n; ++col) {
         if (col % NW != wave) continue;
-        double* w = W + (long)col * m;
+        double* w = W + (long)col * ld;
         load_col(w, 0);
         apply_reg(v, tj);
         store_col(w);
@@ -1952,11 +1977,11 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int l
   }
   for (long idx = tid; idx < (long)c * n; idx += NT) {
     const int i = idx / n, jj = idx % n;
-    R[(long)i * ldr + jj] = jj < i ? 0.0 : (jj == i ? diag[i] : W[(long)jj * m + i]);
+    R[(long)i * ldr + jj] = jj < i ? 0.0 : (jj == i ? diag[i] : W[(long)jj * ld + i]);
   }
   // Q, backwards over the reflectors; v_j staged into sv[j & 1] one step ahead
   auto stage = [&](int j) {
-    load_col(W + (long)j * m, j);
+    load_col(W + (long)j * ld, j);
 #pragma unroll
     for (int k = 0; k < KR; ++k) sv[j & 1][lane + 64 * k] = wr[k];
   };
@@ -1967,7 +1992,7 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int l
     const double tj = tau[j];
     for (int col = j; col < c; ++col) {
       if (col % NW != wave) continue;
-      double* q = Qc + (long)col * m;
+      double* q = Qc + (long)col * ld;
       if (col == j) {
 #pragma unroll
         for (int k = 0; k < KR; ++k) wr[k] = lane + 64 * k == j ? 1.0 : 0.0;
@@ -1982,7 +2007,7 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int l
   }
   for (long idx = tid; idx < (long)m * c; idx += NT) {
     const int i = idx / c, jj = idx % c;
-    Q[(long)i * ldq + jj] = Qc[(long)jj * m + i];
+    Q[(long)i * ldq + jj] = Qc[(long)jj * ld + i];
   }
 }
 
@@ -1990,25 +2015,62 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int l
 template <int KR>
 constexpr int qr_reg_threads() { return KR >= 32 ? 512 : QR_NT; }
 
-template <int KR>
+template <int KR, bool PAD>
 __global__ __launch_bounds__(qr_reg_threads<KR>()) void qr_reg_kernel(int m, int n, const double* A, int lda,
                                                                      double* Q, int ldq, double* R, int ldr,
                                                                      double* ws) {
-  qr_reg_body<KR, qr_reg_threads<KR>()>(m, n, A, lda, Q, ldq, R, ldr, ws);
+  extern __shared__ double dyn[];
+  qr_reg_body<KR, qr_reg_threads<KR>(), PAD>(m, n, A, lda, Q, ldq, R, ldr, ws, dyn);
 }
 
-template <int KR>
+template <int KR, bool PAD>
 __global__ __launch_bounds__(qr_reg_threads<KR>()) void qr_reg_batch_kernel(QrBatch b) {
+  extern __shared__ double dyn[];
   const QrJob j = b.job[blockIdx.x];
-  qr_reg_body<KR, qr_reg_threads<KR>()>(j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R, j.ldr, j.ws);
+  qr_reg_body<KR, qr_reg_threads<KR>(), PAD>(j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R, j.ldr, j.ws, dyn);
+}
+
+static void hip_check_attr(hipError_t e) {
+  if (e != hipSuccess) throw Error(TNFEM_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
 }
 
 // rows per lane of the register variant for m rows (0: too tall, use the plain global variant)
 static int qr_reg_rows(int m) { return m <= 512 ? 8 : (m <= 1024 ? 16 : (m <= 2048 ? 32 : 0)); }
+// rows per lane of the padded LDS variant (0: not offered for this height)
+static int qr_pad_rows(int m) { return m <= 64 ? 1 : (m <= 128 ? 2 : (m <= 256 ? 4 : (m <= 512 ? 8 : 0))); }
 
 static size_t qr_lds_bytes(int m, int n) {
   const int c = m < n ? m : n;
   return ((size_t)m * n + (size_t)m * c + 2 * (size_t)c) * sizeof(double);
+}
+// dynamic LDS of the padded variant with kr rows per lane (its reflector buffers are static)
+static size_t qr_pad_bytes(int m, int n, int kr) {
+  const int c = m < n ? m : n;
+  const size_t ld = 64 * (size_t)kr;
+  return (ld * n + ld * c + 2 * (size_t)c) * sizeof(double);
+}
+static bool qr_pad_fits(int m, int n, int kr) {
+  return kr > 0 && qr_pad_bytes(m, n, kr) + 2 * 64 * (size_t)kr * sizeof(double) + 64 <= QR_LDS_BYTES;
+}
+
+// the kernels' static LDS (reflector buffers) counts against the same 160 KB, so the
+// dynamic limit is what qr_pad_fits allows
+template <int KR, bool PAD>
+static void qr_reg_attr() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int dyn = (int)(QR_LDS_BYTES - 2 * 64 * (size_t)KR * sizeof(double) - 64);
+    hip_check_attr(hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_reg_kernel<KR, PAD>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
+    hip_check_attr(hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_reg_batch_kernel<KR, PAD>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
+  });
+}
+
+template <int KR, bool PAD>
+static void launch_qr_reg_batch(const QrBatch& b, size_t lds, hipStream_t s) {
+  if (PAD) qr_reg_attr<KR, PAD>();
+  hipLaunchKernelGGL((qr_reg_batch_kernel<KR, PAD>), dim3(b.njob), dim3(qr_reg_threads<KR>()), lds, s, b);
 }
 
 void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s) {
@@ -2018,16 +2080,29 @@ void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_owner_batch_kernel<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_BYTES);
   });
-  QrBatch in_lds, in_ws;
-  size_t lds_max = 0;
+  // padded LDS variant for the jobs that fit with the batch's common row count per
+  // lane, then the unpadded LDS kernel, then the global-memory variants
+  int kp = 0;
+  for (const QrJob& j : jobs) kp = std::max(kp, qr_pad_rows(j.m) == 0 ? 1 << 20 : qr_pad_rows(j.m));
+  QrBatch in_pad, in_lds, in_ws;
+  size_t pad_max = 0, lds_max = 0;
   for (const QrJob& j : jobs) {
-    const size_t b = qr_lds_bytes(j.m, j.n);
-    if (b <= QR_LDS_BYTES) {
+    if (kp <= 8 && qr_pad_fits(j.m, j.n, kp)) {
+      in_pad.job[in_pad.njob++] = j;
+      pad_max = std::max(pad_max, qr_pad_bytes(j.m, j.n, kp));
+    } else if (qr_lds_bytes(j.m, j.n) <= QR_LDS_BYTES) {
       in_lds.job[in_lds.njob++] = j;
-      lds_max = std::max(lds_max, b);
+      lds_max = std::max(lds_max, qr_lds_bytes(j.m, j.n));
     } else {
       in_ws.job[in_ws.njob++] = j;
     }
+  }
+  if (in_pad.njob) {
+    if (kp == 1) launch_qr_reg_batch<1, true>(in_pad, pad_max, s);
+    else if (kp == 2) launch_qr_reg_batch<2, true>(in_pad, pad_max, s);
+    else if (kp == 4) launch_qr_reg_batch<4, true>(in_pad, pad_max, s);
+    else launch_qr_reg_batch<8, true>(in_pad, pad_max, s);
+    TN_CHECK_LAUNCH();
   }
   if (in_lds.njob) {
     hipLaunchKernelGGL(qr_owner_batch_kernel<true>, dim3(in_lds.njob), dim3(QR_NT), lds_max, s, in_lds);
@@ -2039,19 +2114,33 @@ void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s) {
       const int r = qr_reg_rows(in_ws.job[i].m);
       kr = r == 0 ? 0 : (kr == 0 ? 0 : std::max(kr, r));
     }
-    if (kr == 8) hipLaunchKernelGGL(qr_reg_batch_kernel<8>, dim3(in_ws.njob), dim3(QR_NT), 0, s, in_ws);
-    else if (kr == 16) hipLaunchKernelGGL(qr_reg_batch_kernel<16>, dim3(in_ws.njob), dim3(QR_NT), 0, s, in_ws);
-    else if (kr == 32) hipLaunchKernelGGL(qr_reg_batch_kernel<32>, dim3(in_ws.njob), dim3(qr_reg_threads<32>()), 0, s, in_ws);
+    if (kr == 8) launch_qr_reg_batch<8, false>(in_ws, 0, s);
+    else if (kr == 16) launch_qr_reg_batch<16, false>(in_ws, 0, s);
+    else if (kr == 32) launch_qr_reg_batch<32, false>(in_ws, 0, s);
     else hipLaunchKernelGGL(qr_owner_batch_kernel<false>, dim3(in_ws.njob), dim3(QR_NT), 0, s, in_ws);
     TN_CHECK_LAUNCH();
   }
 }
 
+template <int KR, bool PAD>
+static void launch_qr_reg(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr,
+                          double* ws, size_t lds, hipStream_t s) {
+  if (PAD) qr_reg_attr<KR, PAD>();
+  hipLaunchKernelGGL((qr_reg_kernel<KR, PAD>), dim3(1), dim3(qr_reg_threads<KR>()), lds, s, m, n, A, lda, Q, ldq,
+                     R, ldr, ws);
+}
+
 void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws,
                hipStream_t s) {
-  const int c = m < n ? m : n;
-  const size_t bytes = ((size_t)m * n + (size_t)m * c + 2 * (size_t)c) * sizeof(double);
-  if (bytes <= QR_LDS_BYTES) {
+  const size_t bytes = qr_lds_bytes(m, n);
+  const int kp = qr_pad_rows(m);
+  if (qr_pad_fits(m, n, kp)) {
+    const size_t pb = qr_pad_bytes(m, n, kp);
+    if (kp == 1) launch_qr_reg<1, true>(m, n, A, lda, Q, ldq, R, ldr, ws, pb, s);
+    else if (kp == 2) launch_qr_reg<2, true>(m, n, A, lda, Q, ldq, R, ldr, ws, pb, s);
+    else if (kp == 4) launch_qr_reg<4, true>(m, n, A, lda, Q, ldq, R, ldr, ws, pb, s);
+    else launch_qr_reg<8, true>(m, n, A, lda, Q, ldq, R, ldr, ws, pb, s);
+  } else if (bytes <= QR_LDS_BYTES) {
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_owner_kernel<true>),
@@ -2060,10 +2149,9 @@ void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, doubl
     hipLaunchKernelGGL(qr_owner_kernel<true>, dim3(1), dim3(QR_NT), bytes, s, m, n, A, lda, Q, ldq, R, ldr, ws);
   } else {
     const int kr = qr_reg_rows(m);
-    if (kr == 8) hipLaunchKernelGGL(qr_reg_kernel<8>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
-    else if (kr == 16) hipLaunchKernelGGL(qr_reg_kernel<16>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
-    else if (kr == 32)
-      hipLaunchKernelGGL(qr_reg_kernel<32>, dim3(1), dim3(qr_reg_threads<32>()), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+    if (kr == 8) launch_qr_reg<8, false>(m, n, A, lda, Q, ldq, R, ldr, ws, 0, s);
+    else if (kr == 16) launch_qr_reg<16, false>(m, n, A, lda, Q, ldq, R, ldr, ws, 0, s);
+    else if (kr == 32) launch_qr_reg<32, false>(m, n, A, lda, Q, ldq, R, ldr, ws, 0, s);
     else hipLaunchKernelGGL(qr_owner_kernel<false>, dim3(1), dim3(QR_NT), 0, s, m, n, A, lda, Q, ldq, R, ldr, ws);
   }
   TN_CHECK_LAUNCH();

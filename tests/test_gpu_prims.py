@@ -26,10 +26,11 @@ def ctx():
     c.close()
 
 
-# beyond LDS: 8 / 16 / 32 rows per lane in registers (m <= 512 / 1024 / 2048), wide (m < n),
-# and taller than 2048 rows (the plain global-memory variant)
+# padded LDS layout (1 / 2 / 4 / 8 rows per lane: (8, 8), (128, 64), (256, 36), (512, 16), wide (5, 37));
+# unpadded LDS ((200, 40)); beyond LDS: 8 / 16 / 32 rows per lane in registers (m <= 512 / 1024 /
+# 2048), wide (m < n); taller than 2048 rows (the plain global-memory variant)
 QR_SHAPES = [(1, 1), (8, 8), (64, 16), (256, 36), (1024, 132), (37, 5), (5, 37), (300, 256), (1600, 200),
-             (100, 250), (2100, 40), (513, 65)]
+             (100, 250), (2100, 40), (513, 65), (200, 40), (128, 64), (512, 16)]
 
 
 @pytest.mark.parametrize("m,n", QR_SHAPES)
