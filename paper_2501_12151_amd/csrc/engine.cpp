@@ -213,16 +213,6 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
     }
     P.sp_n_ap = flatten(sa, sbb, sv, &P.sp_ap_beg, &P.sp_ap_a, &P.sp_ap_b, &P.sp_ap_v, &P.sp_ap_max);
   }
-  // diagonal terms
-  std::vector<std::vector<int>> db(n), de(n);
-  std::vector<std::vector<double>> dv(n);
-  for (size_t t = 0; t < c.nnz(); ++t)
-    if (c.io[t] == c.ii[t]) {
-      db[c.ii[t]].push_back(c.b[t]);
-      de[c.ii[t]].push_back(c.e[t]);
-      dv[c.ii[t]].push_back(c.v[t]);
-    }
-  flatten(db, de, dv, &P.dg_beg, &P.dg_b, &P.dg_e, &P.dg_v, nullptr);
   // all terms grouped by (out, in) mode pair: entries of the diagonal mode blocks
   std::vector<std::vector<int>> kb(n * n), ke(n * n);
   std::vector<std::vector<double>> kv(n * n);
@@ -604,7 +594,6 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   W.p = A(core);
   W.q = A(core);
   W.w = A(core);
-  W.dinv = A(core);
   W.binv = A(rc * rc * maxn * maxn);
   W.Tb = A(rc * maxn * smax);
   W.gz = A(core);
@@ -879,7 +868,6 @@ struct Sweep {
     a.z = W.z;
     a.p = W.p;
     a.q = W.w;
-    a.dinv = W.dinv;
     a.scal = W.scal;
     a.flag = W.flag;
     a.parts = W.part;
@@ -1237,7 +1225,6 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     a.z = W.z;
     a.p = W.p;
     a.q = W.w;
-    a.dinv = W.dinv;
     a.scal = W.scal;
     a.flag = W.flag;
     a.parts = W.part;

@@ -45,8 +45,6 @@ struct Plan {
   int *en_beg = nullptr, *en_a = nullptr, *en_b = nullptr;
   double* en_v = nullptr;
   int n_en = 0, en_max = 1;
-  int *dg_beg = nullptr, *dg_b = nullptr, *dg_e = nullptr;
-  double* dg_v = nullptr;
   // all nonzero terms grouped by (out, in) mode pair (j n + i): (b, e, v)
   int *bk_beg = nullptr, *bk_b = nullptr, *bk_e = nullptr;
   double* bk_v = nullptr;
@@ -82,7 +80,7 @@ struct Workspace {
   double *Xspare = nullptr, *Zspare = nullptr;
   std::vector<double*> EA, Eb, EzA, Ezb;  // K + 1 bond buffers
   double *T1 = nullptr, *T2 = nullptr;
-  double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *dinv = nullptr;
+  double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr;
   double* binv = nullptr;  // inverses of the diagonal mode blocks of the local operator
   double *Tb = nullptr, *gz = nullptr, *yz = nullptr, *ge = nullptr, *ye = nullptr;
   double *Qx = nullptr, *Rx = nullptr, *UR = nullptr, *S = nullptr, *V = nullptr, *Ur = nullptr, *SVt = nullptr,

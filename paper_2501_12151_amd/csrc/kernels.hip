@@ -378,161 +378,7 @@ static void launch_gemm_impl(const GemmDesc& d, hipStream_t s) {
 
 // ----------------------------------------------------------------------------- CG
 
-constexpr int CG_NT = 256;
-constexpr int CG_NT1 = 1024;          // single-workgroup variant
 constexpr int CG_MAXB = 512;
-constexpr int CG_SINGLE_MAX = 32768;  // vectors up to this length use one workgroup
-
-static int cg_blocks(int n) {
-  int b = (n + CG_NT * 4 - 1) / (CG_NT * 4);
-  return b < 1 ? 1 : (b > CG_MAXB ? CG_MAXB : b);
-}
-
-// Reduction of NV partial sums over the grid.  With one workgroup the block sum
-// is final; otherwise per-block partials are written and the last block to
-// finish sums them in block order.  Returns true in the block holding the totals.
-template <int NT, int NV>
-__device__ bool last_block_reduce(const double (&mine)[NV], double* part, int* counter, double* out) {
-  __shared__ double red[NT / 64];
-  __shared__ bool am_last;
-  double tot[NV];
-  for (int v = 0; v < NV; ++v) tot[v] = block_sum<NT>(mine[v], red);
-  if (gridDim.x == 1) {
-    for (int v = 0; v < NV; ++v) out[v] = tot[v];
-    return true;
-  }
-  if (threadIdx.x == 0) {
-    for (int v = 0; v < NV; ++v) part[v * CG_MAXB + blockIdx.x] = tot[v];
-    __threadfence();
-    const int prev = atomicAdd(counter, 1);
-    am_last = (prev == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
-  for (int v = 0; v < NV; ++v) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += NT) s += part[v * CG_MAXB + b];
-    out[v] = block_sum<NT>(s, red);
-  }
-  return true;
-}
-
-template <int NT>
-__global__ __launch_bounds__(NT) void cg_init_kernel(int n, const double* g, const double* q, const double* dinv,
-                                                        double* r, double* z, double* p, double* qr, double* scal,
-                                                        int* flag, double* part, double tol, int maxit) {
-  double loc[3] = {0.0, 0.0, 0.0};  // rz, rr, gg
-  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-    const double gi = g[i];
-    const double ri = gi - q[i];
-    const double zi = ri * dinv[i];
-    r[i] = ri;
-    z[i] = zi;
-    p[i] = 0.0;
-    qr[i] = 0.0;
-    loc[0] += ri * zi;
-    loc[1] += ri * ri;
-    loc[2] += gi * gi;
-  }
-  double tot[3];
-  if (last_block_reduce<NT, 3>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
-    const double rr = tot[1], gg = tot[2];
-    const double gn = sqrt(gg);
-    const double res = gg > 0.0 ? sqrt(rr) / gn : (rr == 0.0 ? 0.0 : 1.0);
-    const double thr = fmax(0.1 * res, 0.5 * tol) * gn;
-    scal[CG_RZ] = tot[0];
-    scal[CG_RR] = rr;
-    scal[CG_GG] = gg;
-    scal[CG_RES] = res;
-    scal[CG_THR2] = thr * thr;
-    scal[CG_BETA] = 0.0;
-    flag[CG_ITERS] = 0;
-    flag[CG_MAXIT] = maxit;
-    flag[CG_DONE] = (res <= 0.5 * tol || maxit <= 0) ? 1 : 0;
-    flag[CG_COUNTER] = 0;
-  }
-}
-
-// p = z + beta p; q = w + beta q (q = B p by linearity); pq = p . q
-template <int NT>
-__global__ __launch_bounds__(NT) void cg_dir_kernel(int n, const double* z, const double* w, double* p, double* q,
-                                                       double* scal, int* flag, double* part) {
-  if (flag[CG_DONE]) return;
-  const double beta = scal[CG_BETA];
-  double loc[1] = {0.0};
-  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-    const double pi = z[i] + beta * p[i];
-    const double qi = w[i] + beta * q[i];
-    p[i] = pi;
-    q[i] = qi;
-    loc[0] += pi * qi;
-  }
-  double tot[1];
-  if (last_block_reduce<NT, 1>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
-    scal[CG_PQ] = tot[0];
-    if (!(tot[0] > 0.0)) flag[CG_DONE] = 2;  // breakdown: stop before updating
-    flag[CG_COUNTER] = 0;
-  }
-}
-
-// x += alpha p; r -= alpha q; z = dinv r; beta = (r.z)_new / (r.z)_old; convergence flag
-template <int NT>
-__global__ __launch_bounds__(NT) void cg_update_kernel(int n, double* x, const double* p, const double* q, double* r,
-                                                          double* z, const double* dinv, double* scal, int* flag,
-                                                          double* part) {
-  if (flag[CG_DONE]) return;
-  const double alpha = scal[CG_RZ] / scal[CG_PQ];
-  double loc[2] = {0.0, 0.0};  // rz, rr
-  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    const double zi = ri * dinv[i];
-    r[i] = ri;
-    z[i] = zi;
-    loc[0] += ri * zi;
-    loc[1] += ri * ri;
-  }
-  double tot[2];
-  if (last_block_reduce<NT, 2>(loc, part, &flag[CG_COUNTER], tot) && threadIdx.x == 0) {
-    scal[CG_BETA] = tot[0] / scal[CG_RZ];
-    scal[CG_RZ] = tot[0];
-    scal[CG_RR] = tot[1];
-    const int it = flag[CG_ITERS] + 1;
-    flag[CG_ITERS] = it;
-    if (tot[1] <= scal[CG_THR2] || it >= flag[CG_MAXIT]) flag[CG_DONE] = 1;
-    flag[CG_COUNTER] = 0;
-  }
-}
-
-void launch_cg_init(int n, const double* g, const double* q, const double* dinv, double* r, double* z, double* p,
-                    double* qr, double* scal, int* flag, double* part, double tol, int maxit, hipStream_t s) {
-  if (n <= CG_SINGLE_MAX)
-    hipLaunchKernelGGL(cg_init_kernel<CG_NT1>, dim3(1), dim3(CG_NT1), 0, s, n, g, q, dinv, r, z, p, qr, scal, flag,
-                       part, tol, maxit);
-  else
-    hipLaunchKernelGGL(cg_init_kernel<CG_NT>, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, g, q, dinv, r, z, p, qr, scal,
-                       flag, part, tol, maxit);
-  TN_CHECK_LAUNCH();
-}
-void launch_cg_dir(int n, const double* z, const double* w, double* p, double* q, double* scal, int* flag,
-                   double* part, hipStream_t s) {
-  if (n <= CG_SINGLE_MAX)
-    hipLaunchKernelGGL(cg_dir_kernel<CG_NT1>, dim3(1), dim3(CG_NT1), 0, s, n, z, w, p, q, scal, flag, part);
-  else
-    hipLaunchKernelGGL(cg_dir_kernel<CG_NT>, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, z, w, p, q, scal, flag, part);
-  TN_CHECK_LAUNCH();
-}
-void launch_cg_update(int n, double* x, const double* p, const double* q, double* r, double* z, const double* dinv,
-                      double* scal, int* flag, double* part, hipStream_t s) {
-  if (n <= CG_SINGLE_MAX)
-    hipLaunchKernelGGL(cg_update_kernel<CG_NT1>, dim3(1), dim3(CG_NT1), 0, s, n, x, p, q, r, z, dinv, scal, flag,
-                       part);
-  else
-    hipLaunchKernelGGL(cg_update_kernel<CG_NT>, dim3(cg_blocks(n)), dim3(CG_NT), 0, s, n, x, p, q, r, z, dinv, scal,
-                       flag, part);
-  TN_CHECK_LAUNCH();
-}
 
 // ----------------------------------------------------------------------------- fused local apply
 
@@ -1217,7 +1063,7 @@ __device__ __forceinline__ void cg_reduce_dir_body(const CgIterArgs& a, const in
 __global__ __launch_bounds__(256) void cg_reduce_dir_kernel(CgIterArgs a, int k) { cg_reduce_dir_body(a, k, blockIdx.x); }
 
 
-// x += alpha p; r -= alpha q; z = dinv r; block partials of r.z and r.r for iteration k + 1.
+// x += alpha p; r -= alpha q; z = M^-1 r; block partials of r.z and r.r for iteration k + 1.
 __device__ __forceinline__ void cg_update2_body(const CgIterArgs& a, const int k, const int bid) {
   __shared__ double red[4];
   if (a.flag[CG_DONE]) return;
@@ -1232,34 +1078,22 @@ __device__ __forceinline__ void cg_update2_body(const CgIterArgs& a, const int k
   }
   const double alpha = a.scal[CG_RZ0 + (k & 1)] / pq;
   double lrz = 0.0, lrr = 0.0;
-  if (a.bn > 0) {
-    const int bn = a.bn, bnp = a.bnp, t = a.bt;
-    const long total = (long)(a.N / bn) * bnp;
-    const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
-    for (long idx = bid * 256 + threadIdx.x; idx < total; idx += (long)nb * 256) {
-      const int j = (int)(idx % bnp);
-      const long blk = idx / bnp;
-      const bool act = j < bn;
-      const long e = ((blk / t) * bn + j) * t + blk % t;
-      double ri = 0.0;
-      if (act) {
-        a.x[e] += alpha * a.p[e];
-        ri = a.r[e] - alpha * a.q[e];
-        a.r[e] = ri;
-      }
-      const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
-      if (act) {
-        a.z[e] = zi;
-        lrz += ri * zi;
-        lrr += ri * ri;
-      }
-    }
-  } else {
-    for (int e = bid * 256 + threadIdx.x; e < a.N; e += nb * 256) {
+  const int bn = a.bn, bnp = a.bnp, t = a.bt;
+  const long total = (long)(a.N / bn) * bnp;
+  const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
+  for (long idx = bid * 256 + threadIdx.x; idx < total; idx += (long)nb * 256) {
+    const int j = (int)(idx % bnp);
+    const long blk = idx / bnp;
+    const bool act = j < bn;
+    const long e = ((blk / t) * bn + j) * t + blk % t;
+    double ri = 0.0;
+    if (act) {
       a.x[e] += alpha * a.p[e];
-      const double ri = a.r[e] - alpha * a.q[e];
-      const double zi = ri * a.dinv[e];
+      ri = a.r[e] - alpha * a.q[e];
       a.r[e] = ri;
+    }
+    const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
+    if (act) {
       a.z[e] = zi;
       lrz += ri * zi;
       lrr += ri * ri;
@@ -1359,42 +1193,26 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
     return w;
   };
   double lrz = 0.0, lrr = 0.0;
-  if (a.bn > 0) {
-    const int bn = a.bn, bnp = a.bnp, t = a.bt;
-    const long total = (long)(a.N / bn) * bnp;
-    const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
-    for (long idx = bid * 256 + threadIdx.x; idx < total; idx += (long)nb * 256) {
-      const int j = (int)(idx % bnp);
-      const long blk = idx / bnp;
-      const bool act = j < bn;
-      const long e = ((blk / t) * bn + j) * t + blk % t;
-      double ri = 0.0;
-      if (act) {
-        const double pi = a.z[e] + beta * a.p[e];
-        const double qi = bz(e) + beta * a.q[e];
-        a.p[e] = pi;
-        a.q[e] = qi;
-        a.x[e] += alpha * pi;
-        ri = a.r[e] - alpha * qi;
-        a.r[e] = ri;
-      }
-      const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
-      if (act) {
-        a.z[e] = zi;
-        lrz += ri * zi;
-        lrr += ri * ri;
-      }
-    }
-  } else {
-    for (long e = bid * 256 + threadIdx.x; e < a.N; e += (long)nb * 256) {
+  const int bn = a.bn, bnp = a.bnp, t = a.bt;
+  const long total = (long)(a.N / bn) * bnp;
+  const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
+  for (long idx = bid * 256 + threadIdx.x; idx < total; idx += (long)nb * 256) {
+    const int j = (int)(idx % bnp);
+    const long blk = idx / bnp;
+    const bool act = j < bn;
+    const long e = ((blk / t) * bn + j) * t + blk % t;
+    double ri = 0.0;
+    if (act) {
       const double pi = a.z[e] + beta * a.p[e];
       const double qi = bz(e) + beta * a.q[e];
       a.p[e] = pi;
       a.q[e] = qi;
       a.x[e] += alpha * pi;
-      const double ri = a.r[e] - alpha * qi;
-      const double zi = ri * a.dinv[e];
+      ri = a.r[e] - alpha * qi;
       a.r[e] = ri;
+    }
+    const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
+    if (act) {
       a.z[e] = zi;
       lrz += ri * zi;
       lrr += ri * ri;
@@ -1411,46 +1229,31 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
 
 __global__ __launch_bounds__(256) void cg_step_kernel(CgIterArgs a, int k) { cg_step_body(a, k, blockIdx.x); }
 
-// r = g - Bx; z = dinv r; p = q = 0; block partials of r.z, r.r (parity 0);
+// r = g - Bx; z = M^-1 r; p = q = 0; block partials of r.z, r.r (parity 0);
 // the last block also derives res, thr and the skip decision for the host.
 __global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const double* g, const double* bx, double tol) {
   __shared__ double red[4];
   __shared__ bool am_last;
   double lrz = 0.0, lrr = 0.0, lgg = 0.0;
-  if (a.bn > 0) {
-    const int bn = a.bn, bnp = a.bnp, t = a.bt;
-    const long total = (long)(a.N / bn) * bnp;
-    const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
-    for (long idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long)gridDim.x * 256) {
-      const int j = (int)(idx % bnp);
-      const long blk = idx / bnp;
-      const bool act = j < bn;
-      const long e = ((blk / t) * bn + j) * t + blk % t;
-      double gi = 0.0, ri = 0.0;
-      if (act) {
-        gi = g[e];
-        ri = gi - bx[e];
-        a.r[e] = ri;
-        a.p[e] = 0.0;
-        a.q[e] = 0.0;
-      }
-      const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
-      if (act) {
-        a.z[e] = zi;
-        lrz += ri * zi;
-        lrr += ri * ri;
-        lgg += gi * gi;
-      }
-    }
-  } else {
-    for (int e = blockIdx.x * 256 + threadIdx.x; e < a.N; e += gridDim.x * 256) {
-      const double gi = g[e];
-      const double ri = gi - bx[e];
-      const double zi = ri * a.dinv[e];
+  const int bn = a.bn, bnp = a.bnp, t = a.bt;
+  const long total = (long)(a.N / bn) * bnp;
+  const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
+  for (long idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long)gridDim.x * 256) {
+    const int j = (int)(idx % bnp);
+    const long blk = idx / bnp;
+    const bool act = j < bn;
+    const long e = ((blk / t) * bn + j) * t + blk % t;
+    double gi = 0.0, ri = 0.0;
+    if (act) {
+      gi = g[e];
+      ri = gi - bx[e];
       a.r[e] = ri;
-      a.z[e] = zi;
       a.p[e] = 0.0;
       a.q[e] = 0.0;
+    }
+    const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
+    if (act) {
+      a.z[e] = zi;
       lrz += ri * zi;
       lrr += ri * ri;
       lgg += gi * gi;
@@ -1486,17 +1289,13 @@ __global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const doubl
   a.flag[CG_COUNTER] = 0;
 }
 
-int cg_vec_blocks(int n) {
-  int b = (n + 256 * 8 - 1) / (256 * 8);
-  return b < 1 ? 1 : (b > CG_MAXB ? CG_MAXB : b);
-}
-
 int cg_dir_blocks(int n) {
   int b = (n + 255) / 256;
   return b < 1 ? 1 : (b > CG_MAXB ? CG_MAXB : b);
 }
 
 void launch_cg_init2(const CgIterArgs& a, const double* g, const double* bx, double tol, hipStream_t s) {
+  if (a.bn < 1 || a.bnp < a.bn || a.bnp > 64 || !a.binv) throw Error(TNFEM_EINVAL, "CG: block preconditioner not set");
   hipLaunchKernelGGL(cg_init2_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, g, bx, tol);
   TN_CHECK_LAUNCH();
 }
@@ -1558,36 +1357,6 @@ void launch_cg_step_batch(const CgBatch& b, int k, hipStream_t s) {
   if (b.nreq <= 0) return;
   if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "CG batch: too many requests");
   hipLaunchKernelGGL(cg_step_batch_kernel, dim3(b.boff[b.nreq]), dim3(256), 0, s, b, k);
-  TN_CHECK_LAUNCH();
-}
-
-// ----------------------------------------------------------------------------- local diagonal
-
-__global__ void local_diag_kernel(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt,
-                                  const int* dg_beg, const int* dg_b, const int* dg_e, const double* dg_v,
-                                  double* dinv) {
-  const long total = (long)p * n * t;
-  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-    const int c = idx % t;
-    const int i = (idx / t) % n;
-    const int a = idx / ((long)t * n);
-    double s = 0.0;
-    for (int k = dg_beg[i]; k < dg_beg[i + 1]; ++k) {
-      const double lv = L[((long)a * Rl + dg_b[k]) * p + a];
-      const double rv = Rt[((long)c * Rr + dg_e[k]) * t + c];
-      s += dg_v[k] * lv * rv;
-    }
-    dinv[idx] = s > 0.0 ? 1.0 / s : 1.0;
-  }
-}
-
-void launch_local_diag(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* dg_beg,
-                       const int* dg_b, const int* dg_e, const double* dg_v, double* dinv, hipStream_t s) {
-  const long total = (long)p * n * t;
-  int blocks = (int)((total + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(local_diag_kernel, dim3(blocks), dim3(256), 0, s, p, n, t, Rl, Rr, L, Rt, dg_beg, dg_b, dg_e,
-                     dg_v, dinv);
   TN_CHECK_LAUNCH();
 }
 

@@ -81,19 +81,15 @@ void set_gemm_splitk_buffer(double* p, size_t cap_doubles);
 enum CgScal { CG_RZ = 0, CG_PQ, CG_RR, CG_GG, CG_THR2, CG_RES, CG_BETA, CG_NSCAL };
 enum CgFlag { CG_DONE = 0, CG_ITERS, CG_MAXIT, CG_COUNTER, CG_NFLAG };
 
-// Local preconditioned CG, one iteration = (w = B z), cg_dir, cg_update:
-//   init:   r = g - q (q = B x), z = dinv r, p = q_rec = 0, beta = 0; scalars rz, rr, gg;
+// Local preconditioned CG (block Jacobi over the mode index), one iteration =
+// (w = B z), then cg_step (after a fused apply that also formed (z, B z)) or
+// cg_reduce_dir + cg_update2:
+//   init:   r = g - q (q = B x), z = M^-1 r, p = q_rec = 0; scalars rz, rr, gg;
 //           res = ||r|| / ||g||; thr = max(0.1 res, tol/2) ||g||; done = (res <= tol/2) or maxit == 0.
 //   dir:    p = z + beta p; q_rec = w + beta q_rec (= B p); pq = p . q_rec.
-//   update: x += a p; r -= a q_rec; z = dinv r (a = rz / pq); beta = rz_new / rz;
+//   update: x += a p; r -= a q_rec; z = M^-1 r (a = rz / pq); beta = rz_new / rz;
 //           done when ||r||^2 <= thr^2 or the iteration limit is reached.
 // Every kernel returns at once when done is set.
-void launch_cg_init(int n, const double* g, const double* q, const double* dinv, double* r, double* z, double* p,
-                    double* qr, double* scal, int* flag, double* part, double tol, int maxit, hipStream_t s);
-void launch_cg_dir(int n, const double* z, const double* w, double* p, double* q, double* scal, int* flag,
-                   double* part, hipStream_t s);
-void launch_cg_update(int n, double* x, const double* p, const double* q, double* r, double* z, const double* dinv,
-                      double* scal, int* flag, double* part, hipStream_t s);
 
 // Fused local apply for operator cores given as term lists: writes split partial
 // tiles part[z][i'][tile][32 x 32] of y = (L x A_k x Rt) x (see kernels.hip).
@@ -156,7 +152,6 @@ constexpr int CG_DOT_OFFSET = 4 * 512, CG_DOT_MAX = 1024;
 struct CgIterArgs {
   int N = 0;
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-  const double* dinv = nullptr;
   const double* w = nullptr;        // apply output when ksplit == 0
   const double* partial = nullptr;  // fused-apply partial tiles when ksplit > 0
   int ksplit = 0, n = 0, t = 0, tiles_n = 1, ntiles = 1;
@@ -167,14 +162,13 @@ struct CgIterArgs {
   int nb_upd = 1;  // blocks of init / update (partials of r.z, r.r)
   int nb_dir = 1;  // blocks of reduce_dir (partials of p.q)
   int keep_thr = 0;  // init: keep the stored threshold (refinement restart) instead of deriving it
-  // block-Jacobi preconditioner over the mode index (bn > 0): z[a, :, c] = binv[a, c] r[a, :, c],
+  // block-Jacobi preconditioner over the mode index: z[a, :, c] = binv[a, c] r[a, :, c],
   // binv [p][t][bn][bn]; bnp = bn rounded up to a power of two (lanes per block); bt = t
   int bn = 0, bnp = 1, bt = 1;
   const double* binv = nullptr;
   // > 0: the apply wrote ndots partials of (z, B z) at parts + CG_DOT_OFFSET (cg_step)
   int ndots = 0;
 };
-int cg_vec_blocks(int n);
 int cg_dir_blocks(int n);
 void launch_cg_init2(const CgIterArgs& a, const double* g, const double* bx, double tol, hipStream_t s);
 void launch_cg_reduce_dir(const CgIterArgs& a, int k, hipStream_t s);
@@ -190,11 +184,6 @@ struct CgBatch {
 void launch_cg_reduce_dir_batch(const CgBatch& b, int k, hipStream_t s);  // boff over nb_dir
 void launch_cg_update2_batch(const CgBatch& b, int k, hipStream_t s);     // boff over nb_upd
 void launch_cg_step_batch(const CgBatch& b, int k, hipStream_t s);        // boff over nb_upd
-
-// Jacobi preconditioner: d[a][i][c] = sum over diagonal terms (b, e, v) of group i of
-// v * L[a][b][a] * Rt[c][e][c]; dinv = 1/d where d > 0 else 1.
-void launch_local_diag(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* dg_beg,
-                       const int* dg_b, const int* dg_e, const double* dg_v, double* dinv, hipStream_t s);
 
 // Explicit local matrix of a dense operator core A2 (rows (b, in-index), columns (out-index, e)):
 //   Bm[(a n + j) t + c][(a' n + i) t + c'] = sum_{b,e} L[a][b][a'] A[b][j][i][e] Rt[c][e][c'],
