@@ -2152,8 +2152,14 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
 }
 
 // The same iteration for 64 < n <= 137 on 1024 threads: G in dynamic LDS with a
-// padded column stride (n + 1), V in LDS as well when both fit, else in ws; each
-// column pair of a step is owned by an aligned group of lanes (DPP sums).
+// padded column stride (n + 1); each column pair of a step is owned by an aligned
+// group of lanes (DPP sums).  V is rotated in LDS as well when both fit.  Otherwise
+// V lives in ws and the rotations of a sweep are recorded (cs, sn per step and pair)
+// and applied to V once per sweep: G is stashed in ws, V brought into the same LDS,
+// rotated step by step with the same schedule, written back, and G restored; every
+// rotation then costs LDS traffic instead of an L2 round trip per step.
+// ws (V_LDS = false): V and the G stash (n (n + 1) doubles each), then
+// 2 (n + 1) (n + 1) / 2 doubles of rotations.
 constexpr int SVB_NT = 1024;
 constexpr size_t SVB_LDS_BYTES = 156 * 1024;
 
@@ -2166,6 +2172,8 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
   const int ld = n + 1;
   double* Gc = dyn;
   double* Vc = V_LDS ? dyn + (long)n * ld : ws;
+  double* Gs = ws + (long)n * ld;        // G stash while V is in LDS (V_LDS = false)
+  double* Rot = ws + 2 * (long)n * ld;   // (cs, sn) per (step, pair) of the current sweep
   for (int idx = tid; idx < n * n; idx += SVB_NT) {
     const int i = idx % n, j = idx / n;
     Gc[j * ld + i] = trans ? G[(long)j * ldg + i] : G[(long)i * ldg + j];
@@ -2200,23 +2208,59 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
         a = group_sum(a, tpp);
         b = group_sum(b, tpp);
         cc = group_sum(cc, tpp);
+        double cs = 1.0, sn = 0.0;
         if (q < n && jacobi_rotate(a, b, cc, eps)) {
-          double cs, sn;
           jacobi_rotation(a, b, cc, cs, sn);
           for (int i = i0; i < i1; ++i) {
             const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
             Gc[p * ld + i] = cs * gp - sn * gq;
             Gc[q * ld + i] = sn * gp + cs * gq;
-            const double vp = Vc[p * ld + i], vq = Vc[q * ld + i];
-            Vc[p * ld + i] = cs * vp - sn * vq;
-            Vc[q * ld + i] = sn * vp + cs * vq;
+            if (V_LDS) {
+              const double vp = Vc[p * ld + i], vq = Vc[q * ld + i];
+              Vc[p * ld + i] = cs * vp - sn * vq;
+              Vc[q * ld + i] = sn * vp + cs * vq;
+            }
           }
           rot = 1;
+        }
+        if (!V_LDS && sub == 0) {
+          Rot[2 * ((long)step * npairs + pair)] = cs;
+          Rot[2 * ((long)step * npairs + pair) + 1] = sn;
         }
       }
       __syncthreads();
     }
-    if (!__syncthreads_or(rot)) break;
+    const bool any = __syncthreads_or(rot);
+    if (!V_LDS && any) {
+      // G out to ws, V into LDS, the sweep's rotations on V, V back, G back
+      for (int idx = tid; idx < n * ld; idx += SVB_NT) Gs[idx] = Gc[idx];
+      __syncthreads();
+      for (int idx = tid; idx < n * ld; idx += SVB_NT) Gc[idx] = Vc[idx];
+      __syncthreads();
+      for (int step = 0; step < npad - 1; ++step) {
+        if (pair < npairs) {
+          const int ia = pair, ib = npad - 1 - pair;
+          const int pa = ia == 0 ? 0 : 1 + (ia - 1 + step) % (npad - 1);
+          const int pb = ib == 0 ? 0 : 1 + (ib - 1 + step) % (npad - 1);
+          const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+          const double cs = Rot[2 * ((long)step * npairs + pair)];
+          const double sn = Rot[2 * ((long)step * npairs + pair) + 1];
+          if (q < n && sn != 0.0) {
+            for (int i = i0; i < i1; ++i) {
+              const double vp = Gc[p * ld + i], vq = Gc[q * ld + i];
+              Gc[p * ld + i] = cs * vp - sn * vq;
+              Gc[q * ld + i] = sn * vp + cs * vq;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      for (int idx = tid; idx < n * ld; idx += SVB_NT) Vc[idx] = Gc[idx];
+      __syncthreads();
+      for (int idx = tid; idx < n * ld; idx += SVB_NT) Gc[idx] = Gs[idx];
+      __syncthreads();
+    }
+    if (!any) break;
   }
   for (int j = tid; j < n; j += SVB_NT) {
     double s2 = 0.0;

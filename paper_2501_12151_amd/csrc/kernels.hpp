@@ -218,7 +218,7 @@ struct QrBatch {
 void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s);
 
 // One-sided Jacobi SVD of the square n x n matrix G (row-major, ldg): G = U diag(S) V^T,
-// S descending.  U, V: n x n row-major.  ws: 2 n^2 doubles (used when n > 64).
+// S descending.  U, V: n x n row-major.  ws: 3 n (n + 1) doubles (used when n > 64).
 // trans != 0: works on G^T (element (i, j) read from G[j * ldg + i]).  Jacobi on R^T
 // (R from a QR) converges in fewer sweeps than on R; the caller then passes the
 // destinations swapped: U receives R's right and V its left singular vectors.

@@ -69,7 +69,8 @@ def test_qr_rank_deficient(ctx, m, n):
 
 SVD_CASES = [(1, 1, "rand"), (16, 8, "rand"), (256, 32, "rand"), (512, 68, "rand"), (40, 40, "graded"),
              (128, 64, "lowrank"), (1024, 132, "rand"), (7, 30, "rand"), (64, 64, "zero"), (100, 63, "rand"),
-             (70, 17, "graded"), (300, 100, "graded"), (200, 140, "rand")]
+             (70, 17, "graded"), (300, 100, "graded"), (200, 140, "rand"), (400, 120, "lowrank"),
+             (137, 137, "graded")]
 
 
 @pytest.mark.parametrize("m,n,kind", SVD_CASES)
