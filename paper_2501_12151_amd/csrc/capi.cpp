@@ -450,7 +450,7 @@ int tnfem_prim_qr(tnfem_ctx* ctx, int m, int n, const double* A, double* Q, doub
     if (m < 1 || n < 1 || n > 256) fail(TNFEM_EINVAL, "need m >= 1, 1 <= n <= 256");
     tnfem::hip_check(hipSetDevice(ctx->c.device), "hipSetDevice");
     const int c = std::min(m, n);
-    double* ws = ctx->c.ensure_scratch((size_t)m * n + (size_t)m * c + 2 * c + 1);
+    double* ws = ctx->c.ensure_scratch(tnfem::qr_ws_doubles(m, n) + 1);
     tnfem::launch_qr(m, n, A, n, Q, c, R, n, ws, pick_stream(ctx, stream));
     return TNFEM_OK;
   });
@@ -464,7 +464,8 @@ int tnfem_prim_svd(tnfem_ctx* ctx, int m, int n, const double* A, double* U, dou
     hipStream_t st = pick_stream(ctx, stream);
     const bool tall = m >= n;
     const int mm = tall ? m : n, nn = tall ? n : m;  // work on the tall orientation
-    const size_t need = (size_t)mm * nn * 4 + (size_t)nn * nn * 6 + 4 * nn + 8;
+    const size_t need = (size_t)mm * nn * 2 + (size_t)nn * nn * 3 +
+                        std::max(tnfem::qr_ws_doubles(mm, nn), (size_t)nn * nn * 3 + 3 * nn) + 8;
     double* ws = ctx->c.ensure_scratch(need);
     double* At = ws;                       // mm x nn (transposed input when wide)
     double* Q = At + (size_t)mm * nn;      // mm x nn

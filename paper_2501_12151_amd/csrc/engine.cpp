@@ -614,7 +614,7 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   W.Qa = A(M * Nw);
   W.Ra = A(Nw * Nw);
   W.Wm = A(Nw * Nw);
-  W.qrws = A(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw);
+  W.qrws = A(std::max(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw, qr_ws_doubles((int)M, (int)Nw)));
   W.Rz = A((size_t)rho * maxn * rho + 1);
   W.qrwsz = A(2 * (size_t)rho * maxn * rho + 4 * (size_t)rho);
   W.scal = A(16);

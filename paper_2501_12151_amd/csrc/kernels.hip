@@ -1803,6 +1803,258 @@ static void hip_check_attr(hipError_t e) {
   if (e != hipSuccess) throw Error(TNFEM_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
 }
 
+// ----- blocked Householder QR for tall matrices (512 < m <= 2048, n >= 32)
+// Panels of nb columns: a panel is factored by one workgroup with the panel in LDS
+// (wavefront w owns panel column w in registers, one barrier per column) and its
+// compact-WY factor T (H_0 ... H_{nb-1} = I - V T V^T, T upper triangular from
+// T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] V[:, 0:j]^T v_j) is formed; the trailing
+// columns are then updated by many workgroups, A -= V T^T (V^T A), one wavefront per
+// column with the panel's V staged in LDS.  Q = H_0 ... H_{c-1} E is accumulated
+// backwards over the panels with Q -= V T (V^T Q) on columns j0.. of Q.  The storage
+// follows the unblocked variants: W (m x n, column-major) holds R above the diagonal
+// and the reflectors v (v_0 on the diagonal) below it; diag holds R's diagonal.
+constexpr int QRB_NBMAX = 16;
+
+__global__ void qr_to_colmajor_kernel(int m, int n, const double* A, int lda, double* W) {
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < (long)m * n; idx += (long)gridDim.x * blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    W[(long)j * m + i] = A[(long)i * lda + j];
+  }
+}
+
+__global__ void qr_identity_kernel(int m, int c, double* Qc) {
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < (long)m * c; idx += (long)gridDim.x * blockDim.x)
+    Qc[idx] = (idx % m == idx / m) ? 1.0 : 0.0;
+}
+
+__global__ void qr_outputs_kernel(int m, int n, const double* W, const double* Qc, const double* diag, double* Q, int ldq,
+                                  double* R, int ldr) {
+  const int c = m < n ? m : n;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < (long)c * n; idx += (long)gridDim.x * blockDim.x) {
+    const int i = idx / n, jj = idx % n;
+    R[(long)i * ldr + jj] = jj < i ? 0.0 : (jj == i ? diag[i] : W[(long)jj * m + i]);
+  }
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < (long)m * c; idx += (long)gridDim.x * blockDim.x) {
+    const int i = idx / c, jj = idx % c;
+    Q[(long)i * ldq + jj] = Qc[(long)jj * m + i];
+  }
+}
+
+// Panel columns j0 .. j0 + nbk - 1 (nbk <= 16), rows j0 .. m - 1 (at most 64 KR).
+template <int KR>
+__global__ __launch_bounds__(1024) void qr_panel_kernel(int m, int j0, int nbk, double* W, double* tau, double* diag,
+                                                       double* Tk) {
+  constexpr int LDV = 64 * KR;
+  extern __shared__ double sh[];
+  double* Vp = sh;                         // nbk x LDV: reflector a in Vp[a * LDV + (i - j0)]
+  __shared__ double G[QRB_NBMAX][QRB_NBMAX];
+  __shared__ double stau[QRB_NBMAX];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int mr = m - j0;
+  double wr[KR];
+  double* col = W + (long)(j0 + wave) * m + j0;  // rows j0.. of the wave's panel column
+  if (wave < nbk) {
+    const __amdgpu_buffer_rsrc_t rs = column_rsrc(col, mr);
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+      wr[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, 512 * k, 0));
+  }
+  for (int j = 0; j < nbk; ++j) {
+    if (wave == j) {
+      // reflector of local column j from rows j.. (rows above are R entries, kept in wr)
+      double loc = 0.0, xj = 0.0;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = lane + 64 * k;
+        const double x = i >= j ? wr[k] : 0.0;
+        loc += x * x;
+        xj = i == j ? wr[k] : xj;
+      }
+      const double s2 = wave_sum(loc);
+      const double x0 = __shfl(xj, j % 64, 64);
+      const double nrm = sqrt(s2);
+      double tj = 0.0, alpha = 0.0, v0 = x0;
+      if (nrm > 0.0) {
+        alpha = x0 >= 0.0 ? -nrm : nrm;
+        v0 = x0 - alpha;
+        tj = 2.0 / (s2 - x0 * x0 + v0 * v0);
+      }
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = lane + 64 * k;
+        wr[k] = i == j ? v0 : wr[k];
+        Vp[j * LDV + i] = i >= j ? wr[k] : 0.0;  // rows >= mr read as zero from the load
+      }
+      const __amdgpu_buffer_rsrc_t rs = column_rsrc(col, mr);
+#pragma unroll
+      for (int k = 0; k < KR; ++k)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i64x1_t, wr[k]), rs, lane * 8, 512 * k, 0);
+      if (lane == 0) {
+        tau[j0 + j] = tj;
+        diag[j0 + j] = alpha;
+        stau[j] = tj;
+      }
+    }
+    __syncthreads();
+    if (wave > j && wave < nbk && stau[j] != 0.0) {
+      const double* v = Vp + j * LDV;
+      double part = 0.0;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) part += v[lane + 64 * k] * wr[k];
+      const double f = stau[j] * wave_sum(part);
+      __asm__ volatile("" ::: "memory");
+#pragma unroll
+      for (int k = 0; k < KR; ++k) wr[k] -= f * v[lane + 64 * k];
+    }
+  }
+  // G = V^T V (row a by wavefront a), then T by rows: lane r of wavefront 0 holds row r
+  if (wave < nbk) {
+    for (int b = 0; b < nbk; ++b) {
+      double part = 0.0;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) part += Vp[wave * LDV + lane + 64 * k] * Vp[b * LDV + lane + 64 * k];
+      const double g = wave_sum(part);
+      if (lane == 0) G[wave][b] = g;
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int r = lane;
+    double trow[QRB_NBMAX];
+#pragma unroll
+    for (int s = 0; s < QRB_NBMAX; ++s) trow[s] = 0.0;
+#pragma unroll
+    for (int j = 0; j < QRB_NBMAX; ++j) {
+      if (j < nbk) {
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < QRB_NBMAX; ++s)
+          if (s >= r && s < j) acc += trow[s] * G[s][j];
+        trow[j] = r < j ? -stau[j] * acc : (r == j ? stau[j] : 0.0);
+      }
+    }
+    if (r < nbk)
+      for (int s = 0; s < nbk; ++s) Tk[r * QRB_NBMAX + s] = trow[s];
+  }
+}
+
+// A[j0.., cols] -= V M (V^T A[j0.., cols]) with M = T^T (trans = 1) or T (trans = 0);
+// A column-major with column stride m; columns col0 .. col0 + ncols - 1; one wavefront
+// per column, four per workgroup; V (rows j0.., nbk columns) staged in LDS from W.
+template <int KR>
+__global__ __launch_bounds__(256) void qr_wy_update_kernel(int m, int j0, int nbk, const double* W, double* A, int col0,
+                                                          int ncols, const double* Tk, int trans) {
+  constexpr int LDV = 64 * KR;
+  extern __shared__ double sh[];
+  double* Vp = sh;
+  __shared__ double T[QRB_NBMAX][QRB_NBMAX];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int mr = m - j0;
+  for (int idx = tid; idx < nbk * LDV; idx += 256) {
+    const int a = idx / LDV, i = idx % LDV;
+    // reflector a: zero above its diagonal row a, v_0 on it, v below; zero past the matrix
+    Vp[idx] = (i >= a && i < mr) ? W[(long)(j0 + a) * m + j0 + i] : 0.0;
+  }
+  for (int idx = tid; idx < QRB_NBMAX * QRB_NBMAX; idx += 256) {
+    const int r = idx / QRB_NBMAX, s2 = idx % QRB_NBMAX;
+    T[r][s2] = (r < nbk && s2 < nbk) ? Tk[r * QRB_NBMAX + s2] : 0.0;
+  }
+  __syncthreads();
+  const int cl = blockIdx.x * 4 + wave;
+  if (cl >= ncols) return;
+  double* a = A + (long)(col0 + cl) * m + j0;
+  const __amdgpu_buffer_rsrc_t rs = column_rsrc(a, mr);
+  double ar[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k)
+    ar[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, 512 * k, 0));
+  double y[QRB_NBMAX];
+#pragma unroll
+  for (int b = 0; b < QRB_NBMAX; ++b) {
+    double part = 0.0;
+    if (b < nbk) {
+#pragma unroll
+      for (int k = 0; k < KR; ++k) part += Vp[b * LDV + lane + 64 * k] * ar[k];
+    }
+    y[b] = wave_sum(part);
+  }
+  double z[QRB_NBMAX];
+#pragma unroll
+  for (int r = 0; r < QRB_NBMAX; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < QRB_NBMAX; ++b) acc += (trans ? T[b][r] : T[r][b]) * y[b];
+    z[r] = acc;
+  }
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < QRB_NBMAX; ++b) acc += Vp[b * LDV + lane + 64 * k] * z[b];
+    ar[k] -= acc;
+  }
+#pragma unroll
+  for (int k = 0; k < KR; ++k)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i64x1_t, ar[k]), rs, lane * 8, 512 * k, 0);
+}
+
+static int qrb_blocks(long n) { return (int)std::min<long>(std::max<long>((n + 255) / 256, 1), 2048); }
+
+template <int KR>
+static void qr_blocked_kr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws,
+                          hipStream_t s) {
+  constexpr int LDV = 64 * KR;
+  const int nb = KR >= 32 ? 8 : QRB_NBMAX;  // panel in LDS: nb x 64 KR doubles <= 128 KB
+  const int c = m < n ? m : n;
+  double* W = ws;
+  double* Qc = W + (long)m * n;
+  double* tau = Qc + (long)m * c;
+  double* diag = tau + c;
+  double* T = diag + c;  // one QRB_NBMAX x QRB_NBMAX block per panel
+  const size_t panel_lds = (size_t)nb * LDV * sizeof(double);
+  static std::once_flag once;
+  std::call_once(once, [] {
+    hip_check_attr(hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_panel_kernel<KR>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+    hip_check_attr(hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_wy_update_kernel<KR>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+  });
+  hipLaunchKernelGGL(qr_to_colmajor_kernel, dim3(qrb_blocks((long)m * n)), dim3(256), 0, s, m, n, A, lda, W);
+  const int npanel = (c + nb - 1) / nb;
+  for (int k = 0; k < npanel; ++k) {
+    const int j0 = k * nb, nbk = std::min(nb, c - j0);
+    hipLaunchKernelGGL(qr_panel_kernel<KR>, dim3(1), dim3(1024), panel_lds, s, m, j0, nbk, W, tau, diag,
+                       T + (long)k * QRB_NBMAX * QRB_NBMAX);
+    const int rest = n - (j0 + nbk);
+    if (rest > 0)
+      hipLaunchKernelGGL(qr_wy_update_kernel<KR>, dim3((rest + 3) / 4), dim3(256), panel_lds, s, m, j0, nbk, W, W,
+                         j0 + nbk, rest, T + (long)k * QRB_NBMAX * QRB_NBMAX, 1);
+  }
+  hipLaunchKernelGGL(qr_identity_kernel, dim3(qrb_blocks((long)m * c)), dim3(256), 0, s, m, c, Qc);
+  for (int k = npanel - 1; k >= 0; --k) {
+    const int j0 = k * nb, nbk = std::min(nb, c - j0);
+    const int cols = c - j0;
+    hipLaunchKernelGGL(qr_wy_update_kernel<KR>, dim3((cols + 3) / 4), dim3(256), panel_lds, s, m, j0, nbk, W, Qc, j0,
+                       cols, T + (long)k * QRB_NBMAX * QRB_NBMAX, 0);
+  }
+  hipLaunchKernelGGL(qr_outputs_kernel, dim3(qrb_blocks((long)m * std::max(n, c))), dim3(256), 0, s, m, n, W, Qc,
+                     diag, Q, ldq, R, ldr);
+}
+
+// whether the blocked QR takes this shape
+static bool qr_blocked_ok(int m, int n) { return m > 512 && m <= 2048 && std::min(m, n) >= 32; }
+
+size_t qr_ws_doubles(int m, int n) {
+  const size_t c = (size_t)std::min(m, n);
+  return (size_t)m * n + (size_t)m * c + 2 * c + (c / 8 + 1) * QRB_NBMAX * QRB_NBMAX;
+}
+
+static void launch_qr_blocked(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr,
+                              double* ws, hipStream_t s) {
+  if (m <= 1024) qr_blocked_kr<16>(m, n, A, lda, Q, ldq, R, ldr, ws, s);
+  else qr_blocked_kr<32>(m, n, A, lda, Q, ldq, R, ldr, ws, s);
+}
+
 // rows per lane of the register variant for m rows (0: too tall, use the plain global variant)
 static int qr_reg_rows(int m) { return m <= 512 ? 8 : (m <= 1024 ? 16 : (m <= 2048 ? 32 : 0)); }
 // rows per lane of the padded LDS variant (0: not offered for this height)
@@ -1878,6 +2130,16 @@ void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s) {
     TN_CHECK_LAUNCH();
   }
   if (in_ws.njob) {
+    // tall jobs take the blocked QR one after another; the rest share one launch
+    QrBatch rest;
+    for (int i = 0; i < in_ws.njob; ++i) {
+      const QrJob& j = in_ws.job[i];
+      if (qr_blocked_ok(j.m, j.n)) launch_qr_blocked(j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R, j.ldr, j.ws, s);
+      else rest.job[rest.njob++] = j;
+    }
+    in_ws = rest;
+  }
+  if (in_ws.njob) {
     int kr = 8;
     for (int i = 0; i < in_ws.njob; ++i) {
       const int r = qr_reg_rows(in_ws.job[i].m);
@@ -1916,6 +2178,8 @@ void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, doubl
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_BYTES);
     });
     hipLaunchKernelGGL(qr_owner_kernel<true>, dim3(1), dim3(QR_NT), bytes, s, m, n, A, lda, Q, ldq, R, ldr, ws);
+  } else if (qr_blocked_ok(m, n)) {
+    launch_qr_blocked(m, n, A, lda, Q, ldq, R, ldr, ws, s);
   } else {
     const int kr = qr_reg_rows(m);
     if (kr == 8) launch_qr_reg<8, false>(m, n, A, lda, Q, ldq, R, ldr, ws, 0, s);

@@ -216,6 +216,8 @@ struct QrBatch {
   QrJob job[QR_BATCH_MAX];
 };
 void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s);
+// doubles of ws a QR of an m x n matrix may use (every variant)
+size_t qr_ws_doubles(int m, int n);
 
 // One-sided Jacobi SVD of the square n x n matrix G (row-major, ldg): G = U diag(S) V^T,
 // S descending.  U, V: n x n row-major.  ws: 3 n (n + 1) doubles (used when n > 64).
