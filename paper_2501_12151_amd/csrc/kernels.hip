@@ -1803,7 +1803,7 @@ static void hip_check_attr(hipError_t e) {
   if (e != hipSuccess) throw Error(TNFEM_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
 }
 
-// ----- blocked Householder QR for tall matrices (512 < m <= 2048, n >= 32)
+// ----- blocked Householder QR for tall matrices (256 < m <= 2048, n >= 32) that do not fit in LDS
 // Panels of nb columns: a panel is factored by one workgroup with the panel in LDS
 // (wavefront w owns panel column w in registers, one barrier per column) and its
 // compact-WY factor T (H_0 ... H_{nb-1} = I - V T V^T, T upper triangular from
@@ -2041,8 +2041,8 @@ static void qr_blocked_kr(int m, int n, const double* A, int lda, double* Q, int
                      diag, Q, ldq, R, ldr);
 }
 
-// whether the blocked QR takes this shape
-static bool qr_blocked_ok(int m, int n) { return m > 512 && m <= 2048 && std::min(m, n) >= 32; }
+// whether the blocked QR takes this shape (when it does not fit in LDS)
+static bool qr_blocked_ok(int m, int n) { return m > 256 && m <= 2048 && std::min(m, n) >= 32; }
 
 size_t qr_ws_doubles(int m, int n) {
   const size_t c = (size_t)std::min(m, n);
@@ -2051,7 +2051,8 @@ size_t qr_ws_doubles(int m, int n) {
 
 static void launch_qr_blocked(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr,
                               double* ws, hipStream_t s) {
-  if (m <= 1024) qr_blocked_kr<16>(m, n, A, lda, Q, ldq, R, ldr, ws, s);
+  if (m <= 512) qr_blocked_kr<8>(m, n, A, lda, Q, ldq, R, ldr, ws, s);
+  else if (m <= 1024) qr_blocked_kr<16>(m, n, A, lda, Q, ldq, R, ldr, ws, s);
   else qr_blocked_kr<32>(m, n, A, lda, Q, ldq, R, ldr, ws, s);
 }
 

@@ -27,10 +27,11 @@ def ctx():
 
 
 # padded LDS layout (1 / 2 / 4 / 8 rows per lane: (8, 8), (128, 64), (256, 36), (512, 16), wide (5, 37));
-# unpadded LDS ((200, 40)); beyond LDS: 8 / 16 / 32 rows per lane in registers (m <= 512 / 1024 /
-# 2048), wide (m < n); taller than 2048 rows (the plain global-memory variant)
+# unpadded LDS ((200, 40)); beyond LDS: blocked for 256 < m <= 2048 and n >= 32 ((300, 256), (513, 65),
+# (1024, 132), (1600, 200)), else 8 / 16 / 32 rows per lane in registers ((100, 250), (700, 24),
+# (1500, 20)); taller than 2048 rows (the plain global-memory variant)
 QR_SHAPES = [(1, 1), (8, 8), (64, 16), (256, 36), (1024, 132), (37, 5), (5, 37), (300, 256), (1600, 200),
-             (100, 250), (2100, 40), (513, 65), (200, 40), (128, 64), (512, 16)]
+             (100, 250), (2100, 40), (513, 65), (200, 40), (128, 64), (512, 16), (700, 24), (1500, 20)]
 
 
 @pytest.mark.parametrize("m,n", QR_SHAPES)
