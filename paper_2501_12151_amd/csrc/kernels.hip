@@ -2351,8 +2351,7 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
   int tpp = 1;
   while (tpp * 2 * npairs <= SVW_NT && tpp < 64) tpp *= 2;
   const int pair = tid / tpp, sub = tid % tpp;
-  const int rpl = (n + tpp - 1) / tpp;  // rows per lane, contiguous
-  const int i0 = sub * rpl, i1 = min(n, i0 + rpl);
+  // rows sub, sub + tpp, ...: the lanes of a pair read consecutive rows
   // rotation threshold at the rounding level of an n-term dot product: smaller
   // off-diagonal values are rounding noise, and rotating them never terminates
   const double eps = (n > 4 ? n : 4) * 2.220446049250313e-16;
@@ -2366,7 +2365,7 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
         const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
         double a = 0.0, b = 0.0, cc = 0.0;
         if (q < n) {
-          for (int i = i0; i < i1; ++i) {
+          for (int i = sub; i < n; i += tpp) {
             const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
             a += gp * gp;
             b += gq * gq;
@@ -2379,7 +2378,7 @@ __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int
         if (q < n && jacobi_rotate(a, b, cc, eps)) {
           double cs, sn;
           jacobi_rotation(a, b, cc, cs, sn);
-          for (int i = i0; i < i1; ++i) {
+          for (int i = sub; i < n; i += tpp) {
             const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
             Gc[p * ld + i] = cs * gp - sn * gq;
             Gc[q * ld + i] = sn * gp + cs * gq;
@@ -2450,8 +2449,7 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
   int tpp = 1;
   while (tpp * 2 * npairs <= SVB_NT && tpp < 64) tpp *= 2;
   const int pair = tid / tpp, sub = tid % tpp;
-  const int rpl = (n + tpp - 1) / tpp;
-  const int i0 = sub * rpl, i1 = min(n, i0 + rpl);
+  // rows sub, sub + tpp, ...: the lanes of a pair read consecutive rows
   const double eps = n * 2.220446049250313e-16;
   for (int sweep = 0; sweep < 40; ++sweep) {
     int rot = 0;
@@ -2463,7 +2461,7 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
         const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
         double a = 0.0, b = 0.0, cc = 0.0;
         if (q < n) {
-          for (int i = i0; i < i1; ++i) {
+          for (int i = sub; i < n; i += tpp) {
             const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
             a += gp * gp;
             b += gq * gq;
@@ -2476,7 +2474,7 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
         double cs = 1.0, sn = 0.0;
         if (q < n && jacobi_rotate(a, b, cc, eps)) {
           jacobi_rotation(a, b, cc, cs, sn);
-          for (int i = i0; i < i1; ++i) {
+          for (int i = sub; i < n; i += tpp) {
             const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
             Gc[p * ld + i] = cs * gp - sn * gq;
             Gc[q * ld + i] = sn * gp + cs * gq;
@@ -2511,7 +2509,7 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
           const double cs = Rot[2 * ((long)step * npairs + pair)];
           const double sn = Rot[2 * ((long)step * npairs + pair) + 1];
           if (q < n && sn != 0.0) {
-            for (int i = i0; i < i1; ++i) {
+            for (int i = sub; i < n; i += tpp) {
               const double vp = Gc[p * ld + i], vq = Gc[q * ld + i];
               Gc[p * ld + i] = cs * vp - sn * vq;
               Gc[q * ld + i] = sn * vp + cs * vq;
