@@ -959,6 +959,23 @@ void launch_fused_apply_batch(const FusedBatch& b, int n, int kind, hipStream_t 
 
 static int blocks_for(long total);
 
+// Sum over the ksplit split partials src[z * stride], z = 0 .. ksplit - 1, in split order.
+// The first 16 loads are issued together (indices clamped, so every load is in bounds;
+// the clamped copies are not added), then summed in order.
+__device__ inline double sum_splits(const double* src, long stride, int ksplit) {
+  constexpr int U = 16;
+  if (ksplit <= 0) return 0.0;
+  double v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = src[(long)(u < ksplit ? u : ksplit - 1) * stride];
+  double w = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (u < ksplit) w += v[u];
+  for (int z = U; z < ksplit; ++z) w += src[(long)z * stride];
+  return w;
+}
+
 // y[row][grp][col] = sum over splits of the fused partial tiles (split order).
 __global__ void fused_sum_kernel(FusedArgs f, double* y) {
   if (f.skip && *f.skip) return;
@@ -968,9 +985,7 @@ __global__ void fused_sum_kernel(FusedArgs f, double* y) {
     const int col = e % f.t, grp = (e / f.t) % f.n, row = e / ((long)f.t * f.n);
     const int tile = (row / 32) * f.tiles_n + col / 32;
     const double* src = f.partial + ((long)grp * f.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
-    double w = 0.0;
-    for (int z = 0; z < f.ksplit; ++z) w += src[z * stride];
-    y[e] = w;
+    y[e] = sum_splits(src, stride, f.ksplit);
   }
 }
 
@@ -1036,17 +1051,7 @@ __device__ __forceinline__ void cg_reduce_dir_body(const CgIterArgs& a, const in
       const int tile = (row / 32) * a.tiles_n + col / 32;
       const long stride = (long)a.n * a.ntiles * 1024;
       const double* src = a.partial + ((long)grp * a.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
-      w = 0.0;
-      int zz = 0;
-      for (; zz + 4 <= a.ksplit; zz += 4) {
-        const double w0 = src[zz * stride], w1 = src[(zz + 1) * stride];
-        const double w2 = src[(zz + 2) * stride], w3 = src[(zz + 3) * stride];
-        w += w0;
-        w += w1;
-        w += w2;
-        w += w3;
-      }
-      for (; zz < a.ksplit; ++zz) w += src[zz * stride];
+      w = sum_splits(src, stride, a.ksplit);
     } else {
       w = a.w[e];
     }
@@ -1179,18 +1184,7 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
     const int col = (int)(e % a.t), grp = (int)((e / a.t) % a.n), row = (int)(e / ((long)a.t * a.n));
     const int tile = (row / 32) * a.tiles_n + col / 32;
     const double* src = a.partial + ((long)grp * a.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
-    double w = 0.0;
-    int zz = 0;
-    for (; zz + 4 <= a.ksplit; zz += 4) {
-      const double w0 = src[zz * stride], w1 = src[(zz + 1) * stride];
-      const double w2 = src[(zz + 2) * stride], w3 = src[(zz + 3) * stride];
-      w += w0;
-      w += w1;
-      w += w2;
-      w += w3;
-    }
-    for (; zz < a.ksplit; ++zz) w += src[zz * stride];
-    return w;
+    return sum_splits(src, stride, a.ksplit);
   };
   double lrz = 0.0, lrr = 0.0;
   const int bn = a.bn, bnp = a.bnp, t = a.bt;
