@@ -1113,16 +1113,29 @@ struct Sweep {
     const int mz = pz * nk;
     s.cz = std::min(mz, tz);
     s.zqr = QrJob{mz, tz, tz, s.cz, tz, W.gz, Z[k], W.Rz, W.qrwsz};
-    // enrichment: residual on (left X, right Z) interfaces
-    local_rhs(p, nk, sb(k), sb(k + 1), tz, Eb[k], B(k), Ezb[k + 1], W.Tb, W.ge, st, &fl);
-    apply(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ye, nullptr);
-    launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
+    // enrichment: residual on (left X, right Z) interfaces, as many columns as the cap
+    // leaves room for
     const int rho_eff = std::max(0, std::min(tz, std::min(o.rank_cap - rk, M - rk)));
     const int rnew = rk + rho_eff;
     s.rnew = rnew;
+    if (rho_eff == 0) {
+      // no room: U_rk (orthonormal columns) is the new core as it stands
+      launch_copy2d(M, rk, W.Ur, rk, X[k], rk, 1.0, 0.0, st);
+      s.aqr = QrJob{};
+      return;
+    }
+    local_rhs(p, nk, sb(k), sb(k + 1), tz, Eb[k], B(k), Ezb[k + 1], W.Tb, W.ge, st, &fl);
+    apply(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ye, nullptr);
+    launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
     launch_copy2d(M, rk, W.Ur, rk, W.aug, rnew, 1.0, 0.0, st);
-    if (rho_eff > 0) launch_copy2d(M, rho_eff, W.ge, tz, W.aug + rk, rnew, 1.0, 0.0, st);
+    launch_copy2d(M, rho_eff, W.ge, tz, W.aug + rk, rnew, 1.0, 0.0, st);
     s.aqr = QrJob{M, rnew, rnew, rnew, rnew, W.aug, X[k], W.Ra, W.qrws};
+  }
+
+  // the QR jobs of enrich_begin (the enrichment QR only when columns were added)
+  static void push_enrich_jobs(const TruncState& s, std::vector<QrJob>& jobs) {
+    jobs.push_back(s.zqr);
+    if (s.aqr.m > 0) jobs.push_back(s.aqr);
   }
 
   void enrich_end(int k, TruncState& s) {
@@ -1145,7 +1158,9 @@ struct Sweep {
     trunc_rank(k, s);
     sync();
     enrich_begin(k, s);
-    launch_qr_batch({s.zqr, s.aqr}, st);  // independent: one launch, two workgroups
+    std::vector<QrJob> jobs;
+    push_enrich_jobs(s, jobs);
+    launch_qr_batch(jobs, st);  // independent: one launch, one workgroup each
     enrich_end(k, s);
   }
 
@@ -1608,8 +1623,7 @@ int run_solve_batch(std::vector<Problem*>& Ps, const tnfem_solve_opts& o, std::v
           const int r = live[i];
           set_gemm_splitk_buffer(Ps[r]->ws->splitk, Ps[r]->ws->splitk_cap);
           sweeps[r]->enrich_begin(k, ts[i]);
-          qj2.push_back(ts[i].zqr);
-          qj2.push_back(ts[i].aqr);
+          Sweep::push_enrich_jobs(ts[i], qj2);
         }
         launch_qr_batch(qj2, ctx->stream);
         for (size_t i = 0; i < live.size(); ++i) {
