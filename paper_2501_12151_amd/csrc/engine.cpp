@@ -885,10 +885,18 @@ struct Sweep {
                 "res readback");
       sync();
     };
-    readback();
-    const double res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
-    if (!std::isfinite(res)) nan_seen = 1;
-    int done = hint()[0];
+    // FP64: no readback before the first chunk (its kernels return at once when the
+    // initial residual already meets the target); low precision needs the initial
+    // residual to steer the refinement
+    const bool early = o.precision == 0 || pl.dense;
+    double res = 0.0;
+    int done = 0;
+    if (!early) {
+      readback();
+      res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+      if (!std::isfinite(res)) nan_seen = 1;
+      done = hint()[0];
+    }
     FusedArgs f;
     // fused evaluation from the nonzero lists: always for sparse plans; for dense
     // plans when the per-apply work of the term lists stays small
@@ -991,11 +999,19 @@ struct Sweep {
         done = hint()[0];
       }
       set_profile_tag(-1);
+      bool entry_done = false;
+      if (early && refine == 0) {
+        // the initial residual, read back with the first chunk's status (the init
+        // kernel set the stop flag when it already met the target: nothing ran)
+        res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+        if (!std::isfinite(res)) nan_seen = 1;
+        entry_done = res <= 0.5 * o.tol || o.cg_maxit <= 0;
+      }
       // the apply of launch index k runs before iteration k's convergence test, so a
       // pass that stopped after `its` iterations ran its + 1 applies; later launches
       // of the last chunk returned at once and are not counted
       const int its = hint()[1];
-      const int ran = std::min(kit, its + 1);
+      const int ran = entry_done ? 0 : std::min(kit, its + 1);
       profile_drop_from(pmark, ran);
       if (kit > 0) {
         const double frac = (double)ran / kit;
