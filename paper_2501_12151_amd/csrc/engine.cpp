@@ -182,6 +182,21 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
   };
   P.n_ap = flatten(ap_a, ap_b, ap_v, &P.ap_beg, &P.ap_a, &P.ap_b, &P.ap_v, &P.ap_max);
   P.n_en = flatten(en_a, en_b, en_v, &P.en_beg, &P.en_a, &P.en_b, &P.en_v, &P.en_max);
+  // per apply term of the nonzero lists: code = b * 16 + i of its slot (b, i), and the
+  // list offsets per output mode on the host
+  auto term_codes = [&](const std::vector<std::vector<int>>& A, const std::vector<int>& b_of,
+                        const std::vector<int>& i_of) {
+    std::vector<int> code, bh{0};
+    for (const auto& g : A) {
+      for (int slot : g) {
+        if (i_of[slot] < 0 || i_of[slot] >= 16) fail(TNFEM_EINVAL, "operator core: mode index beyond 15");
+        code.push_back(b_of[slot] * 16 + i_of[slot]);
+      }
+      bh.push_back((int)code.size());
+    }
+    P.sp_ap_c = arena.upload(code, s);
+    P.sp_beg_h = bh;
+  };
   // nonzero term lists (identical to the main lists for sparse plans)
   if (!P.dense) {
     P.sp_nslot = P.nslot;
@@ -193,6 +208,7 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
     P.sp_ap_v = P.ap_v;
     P.sp_n_ap = P.n_ap;
     P.sp_ap_max = P.ap_max;
+    term_codes(ap_a, sb, si);
   } else {
     std::vector<int> ssb, ssi;
     int k2 = 0;
@@ -212,6 +228,7 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
       sv[c.io[t]].push_back(c.v[t]);
     }
     P.sp_n_ap = flatten(sa, sbb, sv, &P.sp_ap_beg, &P.sp_ap_a, &P.sp_ap_b, &P.sp_ap_v, &P.sp_ap_max);
+    term_codes(sa, ssb, ssi);
   }
   // all terms grouped by (out, in) mode pair: entries of the diagonal mode blocks
   std::vector<std::vector<int>> kb(n * n), ke(n * n);
@@ -224,6 +241,22 @@ static Plan build_plan(const MpoCore& c, DevArena& arena, hipStream_t s, size_t*
   }
   flatten(kb, ke, kv, &P.bk_beg, &P.bk_b, &P.bk_e, &P.bk_v, nullptr);
   return P;
+}
+
+// The fused kernels' view of the nonzero term lists: slot (b, i) resolved per term
+// into code = b * 16 + i, and the per-mode list offsets by value.
+static void set_terms(FusedArgs& f, const Plan& pl) {
+  if (pl.n > FUSED_MAX_MODES || (int)pl.sp_beg_h.size() != pl.n + 1 || !pl.sp_ap_c)
+    fail(TNFEM_EINVAL, "fused apply: term lists missing or more than 8 modes");
+  f.slot_b = pl.sp_slot_b;
+  f.slot_i = pl.sp_slot_i;
+  f.beg = pl.sp_ap_beg;
+  f.ta = pl.sp_ap_a;
+  f.tb = pl.sp_ap_b;
+  f.tv = pl.sp_ap_v;
+  f.tc = pl.sp_ap_c;
+  f.nslot = pl.sp_nslot;
+  for (int i = 0; i <= pl.n; ++i) f.begv[i] = pl.sp_beg_h[i];
 }
 
 std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& desc) {
@@ -422,13 +455,7 @@ void dev_local_apply_fused(Problem& P, const Plan& pl, int p, int q, int s, int 
   f.Rl = pl.Rl;
   f.Rr = pl.Rr;
   f.n = pl.n;
-  f.slot_b = pl.sp_slot_b;
-  f.slot_i = pl.sp_slot_i;
-  f.beg = pl.sp_ap_beg;
-  f.ta = pl.sp_ap_a;
-  f.tb = pl.sp_ap_b;
-  f.tv = pl.sp_ap_v;
-  f.nslot = pl.sp_nslot;
+  set_terms(f, pl);
   if (fused_kind(f) == FUSED_TILED) {
     const size_t elems = fused_stage_elems(f);
     f.stage = P.ctx->ensure_scratch(elems);
@@ -726,10 +753,12 @@ struct Sweep {
   double max_res = 0.0;
   int nan_seen = 0;
   int verbose = 0;  // 2: one line per local solve on stderr
+  std::vector<int> cg_last;  // CG iterations of the last local solve at each core (chain order)
 
   Sweep(Problem& p, const tnfem_solve_opts& opts) : P(p), W(*p.ws), o(opts), st(p.ctx->stream), K(p.K) {
     const char* v = std::getenv("TNFEM_VERBOSE");
     verbose = v ? std::atoi(v) : 0;
+    cg_last.assign(K, 0);
   }
 
   volatile int* hint() { return static_cast<volatile int*>(W.host_pinned); }
@@ -806,13 +835,7 @@ struct Sweep {
     f.Rl = pl.Rl;
     f.Rr = pl.Rr;
     f.n = pl.n;
-    f.slot_b = pl.sp_slot_b;
-    f.slot_i = pl.sp_slot_i;
-    f.beg = pl.sp_ap_beg;
-    f.ta = pl.sp_ap_a;
-    f.tb = pl.sp_ap_b;
-    f.tv = pl.sp_ap_v;
-    f.nslot = pl.sp_nslot;
+    set_terms(f, pl);
     f.stage = W.stage;
     f.stage_bytes = W.stage_bytes;
     f.skip = skip;
@@ -919,13 +942,7 @@ struct Sweep {
       f.Rl = R(k);
       f.Rr = R(k + 1);
       f.n = n[k];
-      f.slot_b = pl.sp_slot_b;
-      f.slot_i = pl.sp_slot_i;
-      f.beg = pl.sp_ap_beg;
-      f.ta = pl.sp_ap_a;
-      f.tb = pl.sp_ap_b;
-      f.tv = pl.sp_ap_v;
-      f.nslot = pl.sp_nslot;
+      set_terms(f, pl);
       f.stage = W.stage;
       f.stage_bytes = W.stage_bytes;
       f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
@@ -975,8 +992,13 @@ struct Sweep {
       a.maxit = budget;
       const size_t pmark = profile_mark();
       const double fl0 = fl.total, fll0 = fl_low;
+      // the first chunk covers as many iterations as this core's previous local solve
+      // took, so that one status readback usually suffices; later chunks are short
+      const int phys = orient ? K - 1 - k : k;
+      const int first = refine == 0 ? std::min(48, std::max(chunk, cg_last[phys] + 1)) : chunk;
       while (!done && kit <= budget) {
-        for (int c = 0; c < chunk && kit <= budget; ++c, ++kit) {
+        const int cn = kit == 0 ? first : chunk;
+        for (int c = 0; c < cn && kit <= budget; ++c, ++kit) {
           set_profile_tag(kit);
           if (fused) {
             launch_fused_apply(f, apply_flops, st, prec);
@@ -1020,6 +1042,7 @@ struct Sweep {
       }
       applies += ran;
       total_its += its;
+      if (refine == 0) cg_last[phys] = entry_done ? 0 : its;
       if (prec == 0 || converged_at_entry || total_its >= o.cg_maxit) break;
       const double res_now = fp64_restart();
       refinements++;
@@ -1301,13 +1324,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
       f.Rl = w.R(k);
       f.Rr = w.R(k + 1);
       f.n = w.n[k];
-      f.slot_b = pl.sp_slot_b;
-      f.slot_i = pl.sp_slot_i;
-      f.beg = pl.sp_ap_beg;
-      f.ta = pl.sp_ap_a;
-      f.tb = pl.sp_ap_b;
-      f.tv = pl.sp_ap_v;
-      f.nslot = pl.sp_nslot;
+      set_terms(f, pl);
       f.stage = W.stage;
       f.stage_bytes = W.stage_bytes;
       f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
@@ -1368,7 +1385,10 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     dir.args = upd.args = args.d_a + nstep;
     dir.nreq = upd.nreq = (int)cg.size() - nstep;
     for (int i = 0; i < (int)order.size(); ++i) args.h_a[i] = L[order[i]].a;
-    for (int i = 0; i < nstep; ++i) step.boff[i + 1] = step.boff[i] + L[order[i]].a.nb_upd;
+    for (int i = 0; i < nstep; ++i) {
+      cg_step_check(L[order[i]].a);
+      step.boff[i + 1] = step.boff[i] + L[order[i]].a.nb_upd;
+    }
     for (int i = 0; i < dir.nreq; ++i) {
       const CgIterArgs& a = L[order[nstep + i]].a;
       dir.boff[i + 1] = dir.boff[i] + a.nb_dir;

@@ -53,6 +53,8 @@ struct Plan {
   int sp_nslot = 0, sp_n_ap = 0, sp_ap_max = 1;
   int *sp_slot_b = nullptr, *sp_slot_i = nullptr, *sp_ap_beg = nullptr, *sp_ap_a = nullptr, *sp_ap_b = nullptr;
   double* sp_ap_v = nullptr;
+  int* sp_ap_c = nullptr;        // per term: b * 16 + i of its slot
+  std::vector<int> sp_beg_h;     // host copy of sp_ap_beg (n + 1 offsets)
   int n_t1() const { return nslot; }
   int n_t2() const { return dense ? n * Rr : 0; }
 };

@@ -159,7 +159,21 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
 
   const bool a_kfast = (g.a_sk == 1);
   const bool b_nfast = (g.b_sn == 1);
-  for (long it = it0; it < it1; ++it) {
+  // thread -> NA elements of the A tile and NB of the B tile, idx = tid + 256 u
+  constexpr int NA = TM * BK / 256, NB = TN * BK / 256;
+  auto a_pos = [&](int idx, int& mm, int& kk) {
+    mm = a_kfast ? idx / BK : idx % TM;
+    kk = a_kfast ? idx % BK : idx / TM;
+  };
+  auto b_pos = [&](int idx, int& nn, int& kk) {
+    nn = b_nfast ? idx % TN : idx / BK;
+    kk = b_nfast ? idx / TN : idx % BK;
+  };
+  // the operands of one (term, k-step) iteration into registers: every load issued
+  // before any is used (out-of-range elements read the slot's first element and are
+  // replaced by zero)
+  double ra[NA], rb[NB];
+  auto load = [&](long it) {
     const int t = tb + (int)(it / nks);
     const int k0 = (int)(it % nks) * BK;
     const int ai = g.grp_beg ? g.t_a[t] : t;
@@ -167,20 +181,41 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
     const double v = g.t_v ? g.t_v[t] : 1.0;
     const double* Ab = g.A + (long)ai * g.a_slot;
     const double* Bb = g.B + (long)bi * g.b_slot;
-    for (int idx = tid; idx < TM * BK; idx += 256) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
       int mm, kk;
-      if (a_kfast) { mm = idx / BK; kk = idx % BK; }
-      else { mm = idx % TM; kk = idx / TM; }
+      a_pos(tid + 256 * u, mm, kk);
       const int gm = m0 + mm, gk = k0 + kk;
-      sA[kk][mm] = (gm < g.M && gk < g.K) ? v * Ab[(long)gm * g.a_sm + (long)gk * g.a_sk] : 0.0;
+      const bool in = gm < g.M && gk < g.K;
+      const double a = Ab[in ? (long)gm * g.a_sm + (long)gk * g.a_sk : 0];
+      ra[u] = in ? v * a : 0.0;
     }
-    for (int idx = tid; idx < TN * BK; idx += 256) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
       int nn, kk;
-      if (b_nfast) { nn = idx % TN; kk = idx / TN; }
-      else { nn = idx / BK; kk = idx % BK; }
+      b_pos(tid + 256 * u, nn, kk);
       const int gn = n0 + nn, gk = k0 + kk;
-      sB[kk][nn] = (gn < g.N && gk < g.K) ? Bb[(long)gk * g.b_sk + (long)gn * g.b_sn] : 0.0;
+      const bool in = gn < g.N && gk < g.K;
+      const double b = Bb[in ? (long)gk * g.b_sk + (long)gn * g.b_sn : 0];
+      rb[u] = in ? b : 0.0;
     }
+  };
+  if (it0 < it1) load(it0);
+  for (long it = it0; it < it1; ++it) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      int mm, kk;
+      a_pos(tid + 256 * u, mm, kk);
+      sA[kk][mm] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      int nn, kk;
+      b_pos(tid + 256 * u, nn, kk);
+      sB[kk][nn] = rb[u];
+    }
+    // the next iteration's operands load while this one's products run
+    if (it + 1 < it1) load(it + 1);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
@@ -211,19 +246,39 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
   }
   const int ci = g.grp_c ? g.grp_c[grp] : grp;
   double* Cb = g.C + (long)ci * g.c_slot;
+  // v_mfma_f64_16x16x4f64 result: D[r][c] is in lane c + 16 (r % 4), register r / 4
+  auto c_off = [&](int i, int j, int q, bool& in) {
+    const int col = n0 + wn * 16 * WNB + j * 16 + lrow;
+    const int row = m0 + wm * 16 * WMB + i * 16 + 4 * q + lk;
+    in = row < g.M && col < g.N;
+    return in ? (long)row * g.c_sm + (long)col * g.c_sn : 0L;
+  };
+  // with beta != 0 the old C values are all read before any is written back
+  double cv[WMB][WNB][4];
+  if (g.beta != 0.0) {
+#pragma unroll
+    for (int i = 0; i < WMB; ++i)
+#pragma unroll
+      for (int j = 0; j < WNB; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          bool in;
+          cv[i][j][q] = Cb[c_off(i, j, q, in)];
+        }
+  }
+#pragma unroll
   for (int i = 0; i < WMB; ++i)
-    for (int j = 0; j < WNB; ++j) {
-      const int col = n0 + wn * 16 * WNB + j * 16 + lrow;
+#pragma unroll
+    for (int j = 0; j < WNB; ++j)
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
-        // v_mfma_f64_16x16x4f64 result: D[r][c] is in lane c + 16 (r % 4), register r / 4
-        const int row = m0 + wm * 16 * WMB + i * 16 + 4 * q + lk;
-        if (row < g.M && col < g.N) {
-          double* c = Cb + (long)row * g.c_sm + (long)col * g.c_sn;
+        bool in;
+        const long off = c_off(i, j, q, in);
+        if (in) {
           const double val = g.alpha * acc[i][j][q];
-          *c = (g.beta == 0.0) ? val : val + g.beta * *c;
+          Cb[off] = (g.beta == 0.0) ? val : val + g.beta * cv[i][j][q];
         }
       }
-    }
 }
 
 // Sums the split partial tiles in split order and writes C (alpha, beta as above).
@@ -478,6 +533,33 @@ __device__ inline void mfma_k32o(const typename Prec<P>::T (*sA)[LD], const type
   }
 }
 
+// Term metadata of a workgroup's term range tb .. te - 1, read once into the lanes:
+// lane l of every wavefront holds term tb + l (l < 64); terms beyond are read directly.
+__device__ inline void term_prefetch(const FusedArgs& f, int tb, int te, int lane, int& mc, int& me, double& mv) {
+  const int t = tb + lane;
+  const bool ok = t < te;
+  mc = ok ? f.tc[t] : 0;
+  me = ok ? f.tb[t] : 0;
+  mv = ok ? f.tv[t] : 0.0;
+}
+
+__device__ inline void term_get(const FusedArgs& f, int t, int tb, int mc, int me, double mv, int& code, int& e,
+                                double& v) {
+  const int j = t - tb;
+  if (j < 64) {
+    code = __builtin_amdgcn_readlane(mc, j);
+    e = __builtin_amdgcn_readlane(me, j);
+    const long long bits = __double_as_longlong(mv);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), j);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), j);
+    v = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  } else {
+    code = f.tc[t];
+    e = f.tb[t];
+    v = f.tv[t];
+  }
+}
+
 // The fused apply for 32 < max(p, q, s, t) <= 64: one workgroup computes the whole
 // p x t output of its mode (each wave one 32 x 32 quadrant), so the stage-1 product
 // L_b x_i (p x s, K = q) is formed once per term; the next term's operands are
@@ -494,19 +576,24 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
   const int lrow = lane % 16, lk = lane / 16;
-  const int tb0 = f.beg[grp], te0 = f.beg[grp + 1];
+  const int tb0 = f.begv[grp], te0 = f.begv[grp + 1];
   const int cnt = te0 - tb0;
   const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
   const int tb = tb0 + z * chunk;
   const int te = tb + chunk < te0 ? tb + chunk : te0;
   const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
+  // the term metadata and the skip flag are read together, before any tile load
+  int mc, me;
+  double mv;
+  term_prefetch(f, tb, te, lane, mc, me, mv);
+  if (f.skip && *f.skip) return;
   // thread -> 16 elements of each 64 x 64 tile: r = idx / 64, c = idx % 64, idx = tid + 256 j
   double la[16], xb[16], rb[16], vcur = 0.0;
   auto load = [&](int t, double (&l)[16], double (&x)[16], double (&rr)[16], double& v) {
-    const int slot = f.ta[t], e = f.tb[t];
-    v = f.tv[t];
-    const double* Lb = f.L + (long)f.slot_b[slot] * f.q;
-    const double* Xi = f.x + (long)f.slot_i[slot] * f.s;
+    int code, e;
+    term_get(f, t, tb, mc, me, mv, code, e, v);
+    const double* Lb = f.L + (long)(code >> 4) * f.q;
+    const double* Xi = f.x + (long)(code & 15) * f.s;
     const double* Re = f.Rt + (long)e * f.s;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -567,6 +654,19 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
           Pt[(mi * 16 + acc_row<P>(qq, lk)) * 32 + ni * 16 + lrow] = (double)acc[mi][ni][qq];
   }
   if (f.dots) {
+    // x at the fragment positions: all loads issued together (out-of-range positions read
+    // element 0 and are not added), then summed in fragment order
+    double xv[2][2][4];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int row = wm * 32 + mi * 16 + acc_row<P>(qq, lk), col = wn * 32 + ni * 16 + lrow;
+          const bool in = row < f.p && col < f.t;
+          xv[mi][ni][qq] = f.x[in ? ((long)row * f.n + grp) * f.s + col : 0];
+        }
     double d = 0.0;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -575,7 +675,7 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
           const int row = wm * 32 + mi * 16 + acc_row<P>(qq, lk), col = wn * 32 + ni * 16 + lrow;
-          if (row < f.p && col < f.t) d += (double)acc[mi][ni][qq] * f.x[((long)row * f.n + grp) * f.s + col];
+          if (row < f.p && col < f.t) d += (double)acc[mi][ni][qq] * xv[mi][ni][qq];
         }
     store_block_dot(d, f.dots + (long)z * f.n + grp);
   }
@@ -583,7 +683,6 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
 
 template <int P>
 __global__ __launch_bounds__(256) void fused_apply64_kernel(FusedArgs f) {
-  if (f.skip && *f.skip) return;
   fused_apply64_body<P>(f, blockIdx.y, blockIdx.z);
 }
 
@@ -601,19 +700,35 @@ __device__ __forceinline__ void fused_apply32_body(const FusedArgs& f, const int
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
   const int lrow = lane % 16, lk = lane / 16;
-  const int tb0 = f.beg[grp], te0 = f.beg[grp + 1];
+  const int tb0 = f.begv[grp], te0 = f.begv[grp + 1];
   const int cnt = te0 - tb0;
   const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
   const int tb = tb0 + z * chunk;
   const int te = tb + chunk < te0 ? tb + chunk : te0;
   const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
+  // the term metadata and the skip flag are read together, before any tile load
+  int mc, me;
+  double mv;
+  term_prefetch(f, tb, te, lane, mc, me, mv);
+  if (f.skip && *f.skip) return;
+  // x at this thread's output positions for the dot epilogue, read with the first term
+  // (out-of-range positions read element 0 and are not added)
+  double xd[4] = {0.0, 0.0, 0.0, 0.0};
+  if (f.dots) {
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int row = wm * 16 + acc_row<P>(qq, lk), col = wn * 16 + lrow;
+      const bool in = row < f.p && col < f.t;
+      xd[qq] = f.x[in ? ((long)row * f.n + grp) * f.s + col : 0];
+    }
+  }
   // thread -> 4 elements of each 32 x 32 tile: r = idx / 32, c = idx % 32, idx = tid + 256 j
   double la[4], xb[4], rb[4], vcur = 0.0;
   auto load = [&](int t, double (&l)[4], double (&x)[4], double (&rr)[4], double& v) {
-    const int slot = f.ta[t], e = f.tb[t];
-    v = f.tv[t];
-    const double* Lb = f.L + (long)f.slot_b[slot] * f.q;
-    const double* Xi = f.x + (long)f.slot_i[slot] * f.s;
+    int code, e;
+    term_get(f, t, tb, mc, me, mv, code, e, v);
+    const double* Lb = f.L + (long)(code >> 4) * f.q;
+    const double* Xi = f.x + (long)(code & 15) * f.s;
     const double* Re = f.Rt + (long)e * f.s;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -652,7 +767,7 @@ __device__ __forceinline__ void fused_apply32_body(const FusedArgs& f, const int
 #pragma unroll
     for (int qq = 0; qq < 4; ++qq) {
       const int row = wm * 16 + acc_row<P>(qq, lk), col = wn * 16 + lrow;
-      if (row < f.p && col < f.t) d += (double)acc[qq] * f.x[((long)row * f.n + grp) * f.s + col];
+      if (row < f.p && col < f.t) d += (double)acc[qq] * xd[qq];
     }
     store_block_dot(d, f.dots + (long)z * f.n + grp);
   }
@@ -660,7 +775,6 @@ __device__ __forceinline__ void fused_apply32_body(const FusedArgs& f, const int
 
 template <int P>
 __global__ __launch_bounds__(256) void fused_apply32_kernel(FusedArgs f) {
-  if (f.skip && *f.skip) return;
   fused_apply32_body<P>(f, blockIdx.y, blockIdx.z);
 }
 
@@ -831,6 +945,18 @@ __global__ __launch_bounds__(256) void slot_apply_kernel(FusedArgs f) {
           Pt[(mi * 16 + acc_row<P>(qq, lk)) * 32 + ni * 16 + lrow] = acc[mi][ni][qq];
   }
   if (f.dots) {
+    // as in the one-pass kernels: the x loads issued together, then summed in order
+    double xv[2][2][4];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int row = m0 + wm * 32 + mi * 16 + acc_row<P>(qq, lk), col = n0 + wn * 32 + ni * 16 + lrow;
+          const bool in = row < f.p && col < f.t;
+          xv[mi][ni][qq] = f.x[in ? ((long)row * f.n + grp) * f.s + col : 0];
+        }
     double d = 0.0;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -839,7 +965,7 @@ __global__ __launch_bounds__(256) void slot_apply_kernel(FusedArgs f) {
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
           const int row = m0 + wm * 32 + mi * 16 + acc_row<P>(qq, lk), col = n0 + wn * 32 + ni * 16 + lrow;
-          if (row < f.p && col < f.t) d += acc[mi][ni][qq] * f.x[((long)row * f.n + grp) * f.s + col];
+          if (row < f.p && col < f.t) d += acc[mi][ni][qq] * xv[mi][ni][qq];
         }
     store_block_dot(d, f.dots + ((long)z * f.n + grp) * (((f.p + 63) / 64) * tn) + blockIdx.x);
   }
@@ -855,8 +981,7 @@ __global__ __launch_bounds__(256) void fused_apply32_batch_kernel(FusedBatch b) 
   const int z = blockIdx.z;
   int r = 0;
   while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
-  const FusedArgs f = b.args[r];
-  if (f.skip && *f.skip) return;
+  const FusedArgs& f = b.args[r];
   fused_apply32_body<P>(f, blockIdx.y, z - b.zoff[r]);
 }
 
@@ -865,8 +990,7 @@ __global__ __launch_bounds__(256) void fused_apply64_batch_kernel(FusedBatch b) 
   const int z = blockIdx.z;
   int r = 0;
   while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
-  const FusedArgs f = b.args[r];
-  if (f.skip && *f.skip) return;
+  const FusedArgs& f = b.args[r];
   fused_apply64_body<P>(f, blockIdx.y, z - b.zoff[r]);
 }
 
@@ -903,6 +1027,8 @@ static void prof_end(hipEvent_t* pair, double flops, hipStream_t s, int kind);
 template <int P>
 static void launch_fused_kind(const FusedArgs& f, int kind, hipEvent_t* ev, hipStream_t s) {
   const dim3 g1(1, f.n, f.ksplit);
+  if (kind != FUSED_TILED && (!f.tc || f.n > FUSED_MAX_MODES))
+    throw Error(TNFEM_EINVAL, "fused apply: per-term codes missing or more than 8 modes");
   if (kind == FUSED_32) {
     TN_LAUNCH(ev, fused_apply32_kernel<P>, g1, dim3(256), 0, s, f);
   } else if (kind == FUSED_64) {
@@ -1008,6 +1134,19 @@ static_assert(CG_DOT_OFFSET == PART_PQ && CG_DOT_MAX == 2 * CG_MAXB, "dot partia
 // every lane of the group takes part in the exchanges.
 __device__ inline double block_apply(const double* brow, double ri, int bn, int gbase, bool act) {
   double zi = 0.0;
+  if (bn <= 8) {
+    // rows of up to 8 entries: all loads issued before the first product
+    double b[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = (act && i < bn) ? brow[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i < bn) {
+        const double rv = __shfl(ri, gbase + i, 64);
+        if (act) zi += b[i] * rv;
+      }
+    return zi;
+  }
   for (int i = 0; i < bn; ++i) {
     const double rv = __shfl(ri, gbase + i, 64);
     if (act) zi += brow[i] * rv;
@@ -1124,46 +1263,97 @@ __global__ __launch_bounds__(256) void cg_update2_kernel(CgIterArgs a, int k) { 
 // Convergence of iteration k is tested first, from the previous step's partials.
 __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, const int bid) {
   __shared__ double red[4];
-  __shared__ double tot[3];
-  if (a.flag[CG_DONE]) return;
+  constexpr int U = 16;    // split partials read with the vectors (the rest after them)
+  constexpr int BPRE = 8;  // preconditioner rows of up to 8 entries are read with the vectors
   const int nb = a.nb_upd;
   const int par = k & 1;
-  // the three partial sums by the first wavefront (lane-strided, then a fixed-order
-  // wavefront sum), the same in every block
-  if (threadIdx.x < 64) {
-    const double* prr = a.parts + PART_RR + par * CG_MAXB;
-    const double* prz = a.parts + PART_RZ + par * CG_MAXB;
-    const double* pd = a.parts + CG_DOT_OFFSET;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 64) {
-      s0 += prr[i];
-      s1 += prz[i];
+  const int lane = threadIdx.x % 64;
+  // element layout [p][n][t]: the preconditioner block (a, c) holds the n entries of mode
+  // index j (n = bn, t = bt, checked on the host); 32-bit index arithmetic (N < 2^28)
+  const unsigned bn = a.bn, t = a.bt, bnp = a.bnp, lbnp = __builtin_ctz(a.bnp);
+  const int total = (a.N / a.bn) * a.bnp;
+  const int gbase = lane & ~(a.bnp - 1);
+  const long stride = (long)a.n * a.ntiles * 1024;
+  const int ks = a.ksplit;
+  const bool bpre = bn <= BPRE;
+  struct Elem {
+    unsigned e;
+    bool act;
+    double z, p, q, x, r;
+    double w[U];
+    double b[BPRE];
+    const double* brow;
+    const double* src;
+  };
+  auto load = [&](int idx, Elem& el) {
+    const unsigned j = (unsigned)idx & (bnp - 1), blk = (unsigned)idx >> lbnp;
+    const unsigned row = blk / t, col = blk - row * t;
+    el.act = idx < total && j < bn;
+    el.e = (row * bn + j) * t + col;
+    el.brow = a.binv + (long)blk * bn * bn + j * bn;
+    const int tile = (int)(row / 32) * a.tiles_n + (int)(col / 32);
+    el.src = a.partial + ((long)j * a.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
+    el.z = el.p = el.q = el.x = el.r = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) el.w[u] = 0.0;
+    if (el.act) {
+      const unsigned e = el.e;
+#pragma unroll
+      for (int u = 0; u < U; ++u) el.w[u] = el.src[(long)(u < ks ? u : ks - 1) * stride];
+      el.z = a.z[e];
+      el.p = a.p[e];
+      el.q = a.q[e];
+      el.x = a.x[e];
+      el.r = a.r[e];
     }
-    for (int i = threadIdx.x; i < a.ndots; i += 64) s2 += pd[i];
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    if (threadIdx.x == 0) {
-      tot[0] = s0;
-      tot[1] = s1;
-      tot[2] = s2;
-    }
+#pragma unroll
+    for (int i = 0; i < BPRE; ++i) el.b[i] = (bpre && el.act && i < (int)bn) ? el.brow[i] : 0.0;
+  };
+  // B z at the element: the ordered sum over the splits
+  auto bz = [&](const Elem& el) {
+    double w = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < ks) w += el.w[u];
+    for (int z = U; z < ks; ++z) w += el.src[(long)z * stride];
+    return w;
+  };
+  // everything the first element needs is read together with the done flag and the
+  // partial sums; the decisions below wait for all of it at once
+  const int idx0 = bid * 256 + threadIdx.x;
+  Elem cur;
+  load(idx0, cur);
+  const int done = a.flag[CG_DONE];
+  const double thr2 = a.scal[CG_THR2];
+  const double rz_prev = a.scal[CG_RZ0 + (par ^ 1)], alpha_prev = a.scal[CG_ALPHA0 + (par ^ 1)];
+  // the three partial sums, lane-strided and then a fixed-order wavefront sum: every
+  // wavefront forms the same values
+  const double* prr = a.parts + PART_RR + par * CG_MAXB;
+  const double* prz = a.parts + PART_RZ + par * CG_MAXB;
+  const double* pd = a.parts + CG_DOT_OFFSET;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+  for (int i = lane; i < nb; i += 64) {
+    s0 += prr[i];
+    s1 += prz[i];
   }
-  __syncthreads();
-  const double rr = tot[0];
-  if (rr <= a.scal[CG_THR2] || k >= a.maxit) {
+#pragma unroll 4
+  for (int i = lane; i < a.ndots; i += 64) s2 += pd[i];
+  if (done) return;
+  const double rr = wave_sum(s0);
+  if (rr <= thr2 || k >= a.maxit) {
     if (bid == 0 && threadIdx.x == 0) {
       a.flag[CG_DONE] = 1;
       a.flag[CG_ITERS] = k;
     }
     return;
   }
-  const double gamma = tot[1];
-  const double delta = tot[2];
+  const double gamma = wave_sum(s1);
+  const double delta = wave_sum(s2);
   double beta = 0.0, pq = delta;
   if (k > 0) {
-    beta = gamma / a.scal[CG_RZ0 + (par ^ 1)];
-    pq = delta - beta * gamma / a.scal[CG_ALPHA0 + (par ^ 1)];
+    beta = gamma / rz_prev;
+    pq = delta - beta * gamma / alpha_prev;
   }
   if (!(pq > 0.0)) {  // breakdown: stop without updating
     if (bid == 0 && threadIdx.x == 0) {
@@ -1178,36 +1368,30 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
     a.scal[CG_ALPHA0 + par] = alpha;
     a.flag[CG_ITERS] = k;
   }
-  const long stride = (long)a.n * a.ntiles * 1024;
-  // B z at element e: the ordered sum of the split partial tiles
-  auto bz = [&](long e) {
-    const int col = (int)(e % a.t), grp = (int)((e / a.t) % a.n), row = (int)(e / ((long)a.t * a.n));
-    const int tile = (row / 32) * a.tiles_n + col / 32;
-    const double* src = a.partial + ((long)grp * a.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
-    return sum_splits(src, stride, a.ksplit);
-  };
   double lrz = 0.0, lrr = 0.0;
-  const int bn = a.bn, bnp = a.bnp, t = a.bt;
-  const long total = (long)(a.N / bn) * bnp;
-  const int gbase = (threadIdx.x % 64) & ~(bnp - 1);
-  for (long idx = bid * 256 + threadIdx.x; idx < total; idx += (long)nb * 256) {
-    const int j = (int)(idx % bnp);
-    const long blk = idx / bnp;
-    const bool act = j < bn;
-    const long e = ((blk / t) * bn + j) * t + blk % t;
+  for (int idx = idx0; idx < total; idx += nb * 256) {
+    if (idx != idx0) load(idx, cur);
     double ri = 0.0;
-    if (act) {
-      const double pi = a.z[e] + beta * a.p[e];
-      const double qi = bz(e) + beta * a.q[e];
+    if (cur.act) {
+      const unsigned e = cur.e;
+      const double pi = cur.z + beta * cur.p;
+      const double qi = bz(cur) + beta * cur.q;
       a.p[e] = pi;
       a.q[e] = qi;
-      a.x[e] += alpha * pi;
-      ri = a.r[e] - alpha * qi;
+      a.x[e] = cur.x + alpha * pi;
+      ri = cur.r - alpha * qi;
       a.r[e] = ri;
     }
-    const double zi = block_apply(a.binv + blk * bn * bn + (long)j * bn, ri, bn, gbase, act);
-    if (act) {
-      a.z[e] = zi;
+    double zi = 0.0;
+    if (bpre) {
+#pragma unroll
+      for (int i = 0; i < BPRE; ++i)
+        if (i < (int)bn) zi += cur.b[i] * __shfl(ri, gbase + i, 64);
+    } else {
+      zi = block_apply(cur.brow, ri, bn, gbase, cur.act);
+    }
+    if (cur.act) {
+      a.z[cur.e] = zi;
       lrz += ri * zi;
       lrr += ri * ri;
     }
@@ -1301,8 +1485,15 @@ void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s) {
   hipLaunchKernelGGL(cg_update2_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, k);
   TN_CHECK_LAUNCH();
 }
-void launch_cg_step(const CgIterArgs& a, int k, hipStream_t s) {
+void cg_step_check(const CgIterArgs& a) {
   if (a.ndots <= 0 || a.ndots > CG_DOT_MAX || a.ksplit <= 0) throw Error(TNFEM_EINVAL, "cg_step: needs fused partials");
+  if (a.bn != a.n || a.bt != a.t || a.bn < 1 || a.bnp < a.bn || a.bnp > 64 || (a.bnp & (a.bnp - 1)) || !a.binv)
+    throw Error(TNFEM_EINVAL, "cg_step: preconditioner blocks must be the mode fibres of the apply output");
+  if (a.N < 0 || a.N >= (1 << 28) || a.N % a.bn) throw Error(TNFEM_EINVAL, "cg_step: vector length out of range");
+}
+
+void launch_cg_step(const CgIterArgs& a, int k, hipStream_t s) {
+  cg_step_check(a);
   hipLaunchKernelGGL(cg_step_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, k);
   TN_CHECK_LAUNCH();
 }

@@ -93,6 +93,7 @@ enum CgFlag { CG_DONE = 0, CG_ITERS, CG_MAXIT, CG_COUNTER, CG_NFLAG };
 
 // Fused local apply for operator cores given as term lists: writes split partial
 // tiles part[z][i'][tile][32 x 32] of y = (L x A_k x Rt) x (see kernels.hip).
+constexpr int FUSED_MAX_MODES = 8;
 struct FusedArgs {
   const double* L = nullptr;
   const double* x = nullptr;
@@ -105,6 +106,10 @@ struct FusedArgs {
   const int* ta = nullptr;
   const int* tb = nullptr;
   const double* tv = nullptr;
+  // the one-pass kernels (ranks <= 64) read per term code = b * 16 + i (the slot's L row
+  // index and x mode index) with tb and tv, and the n + 1 list offsets by value
+  const int* tc = nullptr;
+  int begv[FUSED_MAX_MODES + 1] = {};
   int ksplit = 1, tiles_n = 1, ntiles = 1;
   const int* skip = nullptr;
   // ranks above 64 (two-stage apply): the slot products S[slot] = L_b x_i, nslot slots,
@@ -176,6 +181,7 @@ void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s);
 // One kernel per iteration after a fused apply that wrote its (z, B z) partials
 // (Chronopoulos-Gear form of the same PCG): replaces reduce_dir + update2.
 void launch_cg_step(const CgIterArgs& a, int k, hipStream_t s);
+void cg_step_check(const CgIterArgs& a);  // throws unless the arguments fit cg_step
 struct CgBatch {
   const CgIterArgs* args = nullptr;  // device array
   int nreq = 0;
