@@ -27,7 +27,7 @@ METRIC = "solves/s + p50/p99 latency at 1e-6 rel. error; contraction TFLOP/s vs 
 # its launches in a solve: FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
 # counter reads for a 256 MiB copy (profiles/fused_apply_cube128_f64_cap32.md).  Valid
 # while that kernel and the set of applies it serves are unchanged.
-FUSED_APPLY_TRAFFIC_BYTES = 4481272.0
+FUSED_APPLY_TRAFFIC_BYTES = 4792751.0
 
 PEAKS = {0: 78.6, 1: 157.3, 2: 2500.0}  # dense MFMA TFLOP/s: FP64, FP32, BF16
 DTYPES = {0: "f64", 1: "f32 (FP32 MFMA local applies, FP64 refinement)",

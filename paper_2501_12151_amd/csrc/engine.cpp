@@ -956,6 +956,7 @@ struct Sweep {
       if (nd <= CG_DOT_MAX) {
         f.dots = W.part + CG_DOT_OFFSET;
         a.ndots = nd;
+        cg_step_shape(a);
       }
     } else {
       a.ksplit = 0;
@@ -1338,6 +1339,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
       if (nd <= CG_DOT_MAX) {
         f.dots = W.part + CG_DOT_OFFSET;
         c.a.ndots = nd;
+        cg_step_shape(c.a);
       }
     } else {
       c.a.ksplit = 0;
@@ -1373,21 +1375,32 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     for (int kd = 0; kd < 2; ++kd) fill(bykind[kd], fb[kd]);
     // requests whose apply forms (z, B z) take one step kernel per iteration, the others
     // the direction and update kernels; the argument array holds the step group first
+    // (step requests grouped by their block size: 64-thread blocks first)
     std::vector<int> order;
     for (int r : cg)
-      if (L[r].a.ndots > 0) order.push_back(r);
+      if (L[r].a.ndots > 0 && L[r].a.nt_step == 64) order.push_back(r);
+    const int nstep64 = (int)order.size();
+    for (int r : cg)
+      if (L[r].a.ndots > 0 && L[r].a.nt_step != 64) order.push_back(r);
     const int nstep = (int)order.size();
     for (int r : cg)
       if (L[r].a.ndots == 0) order.push_back(r);
-    CgBatch step, dir, upd;
-    step.args = args.d_a;
-    step.nreq = nstep;
+    CgBatch step[2], dir, upd;
+    step[0].args = args.d_a;
+    step[0].nreq = nstep64;
+    step[0].nt = 64;
+    step[1].args = args.d_a + nstep64;
+    step[1].nreq = nstep - nstep64;
+    step[1].nt = 256;
     dir.args = upd.args = args.d_a + nstep;
     dir.nreq = upd.nreq = (int)cg.size() - nstep;
     for (int i = 0; i < (int)order.size(); ++i) args.h_a[i] = L[order[i]].a;
     for (int i = 0; i < nstep; ++i) {
-      cg_step_check(L[order[i]].a);
-      step.boff[i + 1] = step.boff[i] + L[order[i]].a.nb_upd;
+      const CgIterArgs& a = L[order[i]].a;
+      cg_step_check(a);
+      CgBatch& sb = step[i < nstep64 ? 0 : 1];
+      const int j = i < nstep64 ? i : i - nstep64;
+      sb.boff[j + 1] = sb.boff[j] + a.nb_step;
     }
     for (int i = 0; i < dir.nreq; ++i) {
       const CgIterArgs& a = L[order[nstep + i]].a;
@@ -1419,7 +1432,8 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
             w.apply(k, L[r].p, L[r].p, L[r].t, L[r].t, w.EA[k], w.W.z, w.EA[k + 1], w.W.q, w.W.flag + CG_DONE);
           }
         }
-        launch_cg_step_batch(step, kit, st);
+        launch_cg_step_batch(step[0], kit, st);
+        launch_cg_step_batch(step[1], kit, st);
         launch_cg_reduce_dir_batch(dir, kit, st);
         launch_cg_update2_batch(upd, kit, st);
       }

@@ -1007,14 +1007,16 @@ int fused_dot_count(const FusedArgs& f) {
 int fused_apply_splits(const FusedArgs& f, int max_terms, size_t cap_doubles) {
   const int n = f.n;
   const int ntiles = ((f.p + 31) / 32) * ((f.t + 31) / 32);
-  // workgroups per split: the 32 / 64 kernels cover all output tiles of a mode in one;
-  // the two-stage kernel has 64 x 64 output tiles and far more work per term, so it is
-  // split further (about two workgroups per compute unit)
+  // workgroups per split: the 32 / 64 kernels cover all output tiles of a mode in one
+  // and are bound by the latency of their term loop, so they are split down to about one
+  // term per workgroup (one workgroup per compute unit); the two-stage kernel has 64 x 64
+  // output tiles and far more work per term, and keeps at least two terms per workgroup
+  // (about two workgroups per compute unit)
   const bool staged = fused_kind(f) == FUSED_TILED;
   const long per_split = staged ? (long)n * ((f.p + 63) / 64) * ((f.t + 63) / 64) : n;
-  const long target = staged ? 512 : 128;
+  const long target = staged ? 512 : 256;
   long ks = (target + per_split - 1) / per_split;
-  ks = std::min<long>(ks, std::max(1, max_terms / 2));
+  ks = std::min<long>(ks, std::max(1, staged ? max_terms / 2 : max_terms));
   const long fit = (long)(cap_doubles / ((size_t)n * ntiles * 1024));
   if (fit < 1) throw Error(TNFEM_EINVAL, "fused apply: partial buffer too small");
   ks = std::min<long>(ks, fit);
@@ -1086,10 +1088,10 @@ void launch_fused_apply_batch(const FusedBatch& b, int n, int kind, hipStream_t 
 static int blocks_for(long total);
 
 // Sum over the ksplit split partials src[z * stride], z = 0 .. ksplit - 1, in split order.
-// The first 16 loads are issued together (indices clamped, so every load is in bounds;
+// The first 32 loads are issued together (indices clamped, so every load is in bounds;
 // the clamped copies are not added), then summed in order.
 __device__ inline double sum_splits(const double* src, long stride, int ksplit) {
-  constexpr int U = 16;
+  constexpr int U = 32;
   if (ksplit <= 0) return 0.0;
   double v[U];
 #pragma unroll
@@ -1119,7 +1121,9 @@ void launch_fused_sum(FusedArgs f, double* y, hipStream_t s) {
   f.tiles_n = (f.t + 31) / 32;
   f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
   const long N = (long)f.p * f.n * f.t;
-  hipLaunchKernelGGL(fused_sum_kernel, dim3(blocks_for(N)), dim3(256), 0, s, f, y);
+  // 64-thread blocks: the split sums of a local vector spread over more compute units
+  const int nb = (int)std::min<long>(std::max<long>((N + 63) / 64, 1), 4096);
+  hipLaunchKernelGGL(fused_sum_kernel, dim3(nb), dim3(64), 0, s, f, y);
   TN_CHECK_LAUNCH();
 }
 
@@ -1261,11 +1265,13 @@ __global__ __launch_bounds__(256) void cg_update2_kernel(CgIterArgs a, int k) { 
 //   p = z + beta p; q = w + beta q (q = B p); x += alpha p; r -= alpha q; z = M^-1 r;
 //   block partials of (r, z), (r, r) for iteration k + 1.
 // Convergence of iteration k is tested first, from the previous step's partials.
+template <int NT>
 __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, const int bid) {
-  __shared__ double red[4];
-  constexpr int U = 16;    // split partials read with the vectors (the rest after them)
+  __shared__ double red[NT / 64];
+  constexpr int U = 32;    // split partials read with the vectors (the rest after them)
   constexpr int BPRE = 8;  // preconditioner rows of up to 8 entries are read with the vectors
-  const int nb = a.nb_upd;
+  const int nb_read = k == 0 ? a.nb_upd : a.nb_step;  // partials of the previous kernel
+  const int nb = a.nb_step;
   const int par = k & 1;
   const int lane = threadIdx.x % 64;
   // element layout [p][n][t]: the preconditioner block (a, c) holds the n entries of mode
@@ -1320,7 +1326,7 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
   };
   // everything the first element needs is read together with the done flag and the
   // partial sums; the decisions below wait for all of it at once
-  const int idx0 = bid * 256 + threadIdx.x;
+  const int idx0 = bid * NT + threadIdx.x;
   Elem cur;
   load(idx0, cur);
   const int done = a.flag[CG_DONE];
@@ -1333,7 +1339,7 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
   const double* pd = a.parts + CG_DOT_OFFSET;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll 4
-  for (int i = lane; i < nb; i += 64) {
+  for (int i = lane; i < nb_read; i += 64) {
     s0 += prr[i];
     s1 += prz[i];
   }
@@ -1369,7 +1375,7 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
     a.flag[CG_ITERS] = k;
   }
   double lrz = 0.0, lrr = 0.0;
-  for (int idx = idx0; idx < total; idx += nb * 256) {
+  for (int idx = idx0; idx < total; idx += nb * NT) {
     if (idx != idx0) load(idx, cur);
     double ri = 0.0;
     if (cur.act) {
@@ -1396,8 +1402,8 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
       lrr += ri * ri;
     }
   }
-  const double trz = block_sum<256>(lrz, red);
-  const double trr = block_sum<256>(lrr, red);
+  const double trz = block_sum<NT>(lrz, red);
+  const double trr = block_sum<NT>(lrr, red);
   const int npar = (k + 1) & 1;
   if (threadIdx.x == 0) {
     a.parts[PART_RZ + npar * CG_MAXB + bid] = trz;
@@ -1405,7 +1411,10 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
   }
 }
 
-__global__ __launch_bounds__(256) void cg_step_kernel(CgIterArgs a, int k) { cg_step_body(a, k, blockIdx.x); }
+template <int NT>
+__global__ __launch_bounds__(NT) void cg_step_kernel(CgIterArgs a, int k) {
+  cg_step_body<NT>(a, k, blockIdx.x);
+}
 
 // r = g - Bx; z = M^-1 r; p = q = 0; block partials of r.z, r.r (parity 0);
 // the last block also derives res, thr and the skip decision for the host.
@@ -1490,11 +1499,28 @@ void cg_step_check(const CgIterArgs& a) {
   if (a.bn != a.n || a.bt != a.t || a.bn < 1 || a.bnp < a.bn || a.bnp > 64 || (a.bnp & (a.bnp - 1)) || !a.binv)
     throw Error(TNFEM_EINVAL, "cg_step: preconditioner blocks must be the mode fibres of the apply output");
   if (a.N < 0 || a.N >= (1 << 28) || a.N % a.bn) throw Error(TNFEM_EINVAL, "cg_step: vector length out of range");
+  if ((a.nt_step != 64 && a.nt_step != 256) || a.nb_step < 1 || a.nb_step > CG_MAXB || a.nb_upd < 1 ||
+      a.nb_upd > CG_MAXB)
+    throw Error(TNFEM_EINVAL, "cg_step: launch shape not set (cg_step_shape)");
+}
+
+void cg_step_shape(CgIterArgs& a) {
+  if (a.bn < 1 || a.bnp < a.bn) throw Error(TNFEM_EINVAL, "cg_step: block preconditioner not set");
+  const long total = (long)(a.N / a.bn) * a.bnp;
+  const long b64 = (total + 63) / 64;
+  if (b64 <= CG_MAXB) {
+    a.nt_step = 64;
+    a.nb_step = (int)std::max<long>(b64, 1);
+  } else {
+    a.nt_step = 256;
+    a.nb_step = (int)std::min<long>((total + 255) / 256, CG_MAXB);
+  }
 }
 
 void launch_cg_step(const CgIterArgs& a, int k, hipStream_t s) {
   cg_step_check(a);
-  hipLaunchKernelGGL(cg_step_kernel, dim3(a.nb_upd), dim3(256), 0, s, a, k);
+  if (a.nt_step == 64) hipLaunchKernelGGL(cg_step_kernel<64>, dim3(a.nb_step), dim3(64), 0, s, a, k);
+  else hipLaunchKernelGGL(cg_step_kernel<256>, dim3(a.nb_step), dim3(256), 0, s, a, k);
   TN_CHECK_LAUNCH();
 }
 
@@ -1518,10 +1544,11 @@ __global__ __launch_bounds__(256) void cg_update2_batch_kernel(CgBatch b, int k)
   cg_update2_body(a, k, blockIdx.x - b.boff[r]);
 }
 
-__global__ __launch_bounds__(256) void cg_step_batch_kernel(CgBatch b, int k) {
+template <int NT>
+__global__ __launch_bounds__(NT) void cg_step_batch_kernel(CgBatch b, int k) {
   const int r = cg_batch_request(b, blockIdx.x);
   const CgIterArgs a = b.args[r];
-  cg_step_body(a, k, blockIdx.x - b.boff[r]);
+  cg_step_body<NT>(a, k, blockIdx.x - b.boff[r]);
 }
 
 void launch_cg_reduce_dir_batch(const CgBatch& b, int k, hipStream_t s) {
@@ -1541,7 +1568,9 @@ void launch_cg_update2_batch(const CgBatch& b, int k, hipStream_t s) {
 void launch_cg_step_batch(const CgBatch& b, int k, hipStream_t s) {
   if (b.nreq <= 0) return;
   if (b.nreq > FB_MAX) throw Error(TNFEM_EINVAL, "CG batch: too many requests");
-  hipLaunchKernelGGL(cg_step_batch_kernel, dim3(b.boff[b.nreq]), dim3(256), 0, s, b, k);
+  if (b.nt == 64) hipLaunchKernelGGL(cg_step_batch_kernel<64>, dim3(b.boff[b.nreq]), dim3(64), 0, s, b, k);
+  else if (b.nt == 256) hipLaunchKernelGGL(cg_step_batch_kernel<256>, dim3(b.boff[b.nreq]), dim3(256), 0, s, b, k);
+  else throw Error(TNFEM_EINVAL, "CG batch: step block size must be 64 or 256");
   TN_CHECK_LAUNCH();
 }
 

@@ -173,6 +173,9 @@ struct CgIterArgs {
   const double* binv = nullptr;
   // > 0: the apply wrote ndots partials of (z, B z) at parts + CG_DOT_OFFSET (cg_step)
   int ndots = 0;
+  // cg_step launch: nb_step blocks of nt_step (64 or 256) threads, set by cg_step_shape;
+  // iteration 0 reads the nb_upd partials of the init kernel, later ones nb_step
+  int nb_step = 1, nt_step = 256;
 };
 int cg_dir_blocks(int n);
 void launch_cg_init2(const CgIterArgs& a, const double* g, const double* bx, double tol, hipStream_t s);
@@ -182,9 +185,14 @@ void launch_cg_update2(const CgIterArgs& a, int k, hipStream_t s);
 // (Chronopoulos-Gear form of the same PCG): replaces reduce_dir + update2.
 void launch_cg_step(const CgIterArgs& a, int k, hipStream_t s);
 void cg_step_check(const CgIterArgs& a);  // throws unless the arguments fit cg_step
+// Sets nb_step / nt_step from N, bn, bnp: one element per thread, 64-thread blocks while
+// that needs at most CG_MAXB blocks (the vector work spread over more compute units),
+// else 256-thread blocks.
+void cg_step_shape(CgIterArgs& a);
 struct CgBatch {
   const CgIterArgs* args = nullptr;  // device array
   int nreq = 0;
+  int nt = 256;  // step batches: the common nt_step of the requests
   int boff[FB_MAX + 1] = {};
 };
 void launch_cg_reduce_dir_batch(const CgBatch& b, int k, hipStream_t s);  // boff over nb_dir
