@@ -535,16 +535,18 @@ __device__ inline void mfma_k32o(const typename Prec<P>::T (*sA)[LD], const type
 
 // Term metadata of a workgroup's term range tb .. te - 1, read once into the lanes:
 // lane l of every wavefront holds term tb + l (l < 64); terms beyond are read directly.
-__device__ inline void term_prefetch(const FusedArgs& f, int tb, int te, int lane, int& mc, int& me, double& mv) {
+// (code: f.tc for the one-pass kernels, f.ta (slot) for the two-stage apply)
+__device__ inline void term_prefetch(const FusedArgs& f, const int* code, int tb, int te, int lane, int& mc, int& me,
+                                     double& mv) {
   const int t = tb + lane;
   const bool ok = t < te;
-  mc = ok ? f.tc[t] : 0;
+  mc = ok ? code[t] : 0;
   me = ok ? f.tb[t] : 0;
   mv = ok ? f.tv[t] : 0.0;
 }
 
-__device__ inline void term_get(const FusedArgs& f, int t, int tb, int mc, int me, double mv, int& code, int& e,
-                                double& v) {
+__device__ inline void term_get(const FusedArgs& f, const int* codes, int t, int tb, int mc, int me, double mv,
+                                int& code, int& e, double& v) {
   const int j = t - tb;
   if (j < 64) {
     code = __builtin_amdgcn_readlane(mc, j);
@@ -554,7 +556,7 @@ __device__ inline void term_get(const FusedArgs& f, int t, int tb, int mc, int m
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), j);
     v = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
   } else {
-    code = f.tc[t];
+    code = codes[t];
     e = f.tb[t];
     v = f.tv[t];
   }
@@ -585,13 +587,13 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
   // the term metadata and the skip flag are read together, before any tile load
   int mc, me;
   double mv;
-  term_prefetch(f, tb, te, lane, mc, me, mv);
+  term_prefetch(f, f.tc, tb, te, lane, mc, me, mv);
   if (f.skip && *f.skip) return;
   // thread -> 16 elements of each 64 x 64 tile: r = idx / 64, c = idx % 64, idx = tid + 256 j
   double la[16], xb[16], rb[16], vcur = 0.0;
   auto load = [&](int t, double (&l)[16], double (&x)[16], double (&rr)[16], double& v) {
     int code, e;
-    term_get(f, t, tb, mc, me, mv, code, e, v);
+    term_get(f, f.tc, t, tb, mc, me, mv, code, e, v);
     const double* Lb = f.L + (long)(code >> 4) * f.q;
     const double* Xi = f.x + (long)(code & 15) * f.s;
     const double* Re = f.Rt + (long)e * f.s;
@@ -709,7 +711,7 @@ __device__ __forceinline__ void fused_apply32_body(const FusedArgs& f, const int
   // the term metadata and the skip flag are read together, before any tile load
   int mc, me;
   double mv;
-  term_prefetch(f, tb, te, lane, mc, me, mv);
+  term_prefetch(f, f.tc, tb, te, lane, mc, me, mv);
   if (f.skip && *f.skip) return;
   // x at this thread's output positions for the dot epilogue, read with the first term
   // (out-of-range positions read element 0 and are not added)
@@ -726,7 +728,7 @@ __device__ __forceinline__ void fused_apply32_body(const FusedArgs& f, const int
   double la[4], xb[4], rb[4], vcur = 0.0;
   auto load = [&](int t, double (&l)[4], double (&x)[4], double (&rr)[4], double& v) {
     int code, e;
-    term_get(f, t, tb, mc, me, mv, code, e, v);
+    term_get(f, f.tc, t, tb, mc, me, mv, code, e, v);
     const double* Lb = f.L + (long)(code >> 4) * f.q;
     const double* Xi = f.x + (long)(code & 15) * f.s;
     const double* Re = f.Rt + (long)e * f.s;
@@ -859,7 +861,6 @@ template <int P>
 __global__ __launch_bounds__(256) void slot_apply_kernel(FusedArgs f) {
   using T = typename Prec<P>::T;
   using Acc = typename Prec<P>::Acc;
-  if (f.skip && *f.skip) return;
   __shared__ T sA[32][65];
   __shared__ T sB[32][65];
   const int grp = blockIdx.y, z = blockIdx.z;
@@ -870,20 +871,28 @@ __global__ __launch_bounds__(256) void slot_apply_kernel(FusedArgs f) {
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
   const int lrow = lane % 16, lk = lane / 16;
-  const int tb0 = f.beg[grp], te0 = f.beg[grp + 1];
+  const int tb0 = f.begv[grp], te0 = f.begv[grp + 1];
   const int cnt = te0 - tb0;
   const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
   const int tb = tb0 + z * chunk;
   const int te = tb + chunk < te0 ? tb + chunk : te0;
   const long Rrow = (long)f.Rr * f.s;
   const T* S = static_cast<const T*>(f.stage);
+  // the term metadata (slot, e, v) and the skip flag are read together, before any tile
+  int ms, me;
+  double mv;
+  term_prefetch(f, f.ta, tb, te, lane, ms, me, mv);
+  if (f.skip && *f.skip) return;
   const int nks = (f.s + 31) / 32;
   // item = (term, k step); A = S[slot] rows m0.., k (in bounds: padded); B = Rt_e^T
   T ra[8];
   double rb[8];
   auto load = [&](int t, int k0) {
-    const T* Sa = S + ((long)f.ta[t] * p64 + m0) * s64 + k0;
-    const double* Re = f.Rt + (long)f.tb[t] * f.s + k0;
+    int slot, e;
+    double v;
+    term_get(f, f.ta, t, tb, ms, me, mv, slot, e, v);
+    const T* Sa = S + ((long)slot * p64 + m0) * s64 + k0;
+    const double* Re = f.Rt + (long)e * f.s + k0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int idx = tid + 256 * j;
@@ -921,7 +930,9 @@ __global__ __launch_bounds__(256) void slot_apply_kernel(FusedArgs f) {
         mfma_k32o<P, 65>(sA, sB, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, tacc[mi][ni]);
     __syncthreads();
     if (ks == nks - 1) {
-      const double v = f.tv[t];
+      int slot, e;
+      double v;
+      term_get(f, f.ta, t, tb, ms, me, mv, slot, e, v);
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -1029,8 +1040,8 @@ static void prof_end(hipEvent_t* pair, double flops, hipStream_t s, int kind);
 template <int P>
 static void launch_fused_kind(const FusedArgs& f, int kind, hipEvent_t* ev, hipStream_t s) {
   const dim3 g1(1, f.n, f.ksplit);
-  if (kind != FUSED_TILED && (!f.tc || f.n > FUSED_MAX_MODES))
-    throw Error(TNFEM_EINVAL, "fused apply: per-term codes missing or more than 8 modes");
+  if (f.n < 1 || f.n > FUSED_MAX_MODES || f.begv[f.n] <= 0 || (kind != FUSED_TILED && !f.tc))
+    throw Error(TNFEM_EINVAL, "fused apply: term lists not set or more than 8 modes");
   if (kind == FUSED_32) {
     TN_LAUNCH(ev, fused_apply32_kernel<P>, g1, dim3(256), 0, s, f);
   } else if (kind == FUSED_64) {
