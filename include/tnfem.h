@@ -193,9 +193,9 @@ int tnfem_solve_batch(tnfem_problem* const* problems, int n, const tnfem_solve_o
  * submission; each of `slots` worker slots (its own HIP stream) takes the oldest
  * queued request together with the other queued requests of its shape bucket
  * (same dimension, level and solve options, FP64; at most max_batch, default 8),
- * assembles and uploads their problems, and starts them as soon as their device
- * bytes (problems + workspaces) fit in the HBM budget next to the running
- * requests, so requests arriving while others run are admitted as slots and
+ * assembles their problems on the host, and uploads and starts them as soon as
+ * their device bytes (operator plans, load cores and workspaces, counted before
+ * any device allocation) fit in the HBM budget next to the running requests, so requests arriving while others run are admitted as slots and
  * memory free up, and the work of different slots overlaps on the device.  A
  * bucket of several requests runs as one lockstep batch (tnfem_solve_batch:
  * shared launches of the local CG iterations).  Requests share no arithmetic: a

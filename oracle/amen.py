@@ -29,8 +29,13 @@ the paper leaves open are listed in the design doc):
   * stop after a half-sweep with max_k res_k <= tol, or after max_sweeps.
 
 Parity: tests/test_oracle_amen.py pins it to the sparse direct solve of
-oracle.fem on small grids (unconstrained rank), to the load-scaling law
-u(sE) = u(E)/s and to superposition.
+oracle.fem on small grids (unconstrained rank), to the scaling law
+u(sE) = u(E)/s, to superposition of loads and to the mirror symmetry of a
+symmetric problem; with a binding rank cap to ranks <= cap on every bond after
+every step and to the energy J(x) = x^T A x / 2 - b^T x never rising across a
+local solve (computed from the dense reconstruction on tiny grids).  pcg is
+pinned to a dense solve, local_block to the blocks cut from the densely built
+local operator.
 """
 from __future__ import annotations
 
@@ -55,14 +60,6 @@ def local_apply(L, A, x, Rt):
 def local_rhs(Lb, B, Rb):
     """g[p, j, u] = sum Lb[p, s] B[s, j, t] Rb[u, t]."""
     return np.tensordot(np.tensordot(Lb, B, axes=([1], [0])), Rb, axes=([2], [1]))
-
-
-def local_diag(L, A, Rt):
-    """diag of the local operator: sum_{b,e} L[a, b, a] A[b, i, i, e] Rt[c, e, c]."""
-    Ld = np.einsum("aba->ab", L)
-    Ad = np.einsum("biie->bie", A)
-    Rd = np.einsum("cec->ce", Rt)
-    return np.tensordot(np.tensordot(Ld, Ad, axes=([1], [0])), Rd, axes=([2], [1]))
 
 
 def env_A(L, W, A, X):
@@ -97,22 +94,20 @@ def block_preconditioner(blk):
 def pcg(apply, g, x, precond, thr, maxit):
     """Preconditioned conjugate gradients from x until ||g - B x|| <= thr.
 
-    precond(r) returns the preconditioned residual z.  Each iteration applies B
-    to z and carries q = B p by the recurrence q = B z + beta q, which equals
-    B p for p = z + beta p by linearity (the textbook method, one product per
-    step).
+    The textbook method (Hestenes and Stiefel, with a preconditioner):
+    z = M^{-1} r, p = z + beta p, q = B p, alpha = (r, z) / (p, q),
+    x += alpha p, r -= alpha q, beta = (r_new, z_new) / (r, z); one product with
+    B per iteration.  precond(r) returns z.
     """
     r = g - apply(x)
     z = precond(r)
     p = np.zeros_like(r)
-    q = np.zeros_like(r)
     beta = 0.0
     rz = float(np.vdot(r, z))
     it = 0
     while it < maxit and np.linalg.norm(r) > thr:
-        w = apply(z)
         p = z + beta * p
-        q = w + beta * q
+        q = apply(p)
         pq = float(np.vdot(p, q))
         if pq <= 0.0:
             break
@@ -190,6 +185,12 @@ class _Chain:
         self.LzA, self.Lzb = self.LzA[::-1], self.Lzb[::-1]
         self.reversed = not self.reversed
 
+    def forward_cores(self):
+        """Cores of the current iterate in the forward (unreversed) chain order."""
+        if self.reversed:
+            return [C.transpose(2, 1, 0).copy() for C in self.X[::-1]]
+        return [C.copy() for C in self.X]
+
     def update_envs(self, k):
         A, B, X, Z = self.A[k], self.B[k], self.X[k], self.Z[k]
         self.LA[k + 1] = env_A(self.LA[k], X, A, X)
@@ -209,7 +210,7 @@ class _Chain:
             self.update_envs(k)
 
 
-def _half_sweep(ch: _Chain, opt: Options, st: Stats):
+def _half_sweep(ch: _Chain, opt: Options, st: Stats, observe=None):
     K = len(ch.A)
     tol = opt.tol
     tr_tol = tol / np.sqrt(max(K - 1, 1))
@@ -227,11 +228,16 @@ def _half_sweep(ch: _Chain, opt: Options, st: Stats):
         res0 = np.linalg.norm(g - apply(x))
         res = res0 / gn if gn > 0 else (0.0 if res0 == 0 else 1.0)
         max_res = max(max_res, res)
+        if observe is not None:
+            observe("before_solve", k, ch.forward_cores())
         if res > 0.5 * tol:
             precond = block_preconditioner(local_block(L, A, Rt))
             thr = max(0.1 * res, 0.5 * tol) * gn
             x, it = pcg(apply, g, x, precond, thr, opt.cg_maxit)
             st.cg_iters += it
+        if observe is not None:
+            ch.X[k] = x
+            observe("after_solve", k, ch.forward_cores())
         if k == K - 1:
             ch.X[k] = x
             break
@@ -257,11 +263,15 @@ def _half_sweep(ch: _Chain, opt: Options, st: Stats):
     return max_res
 
 
-def amen_solve(A, b, opt: Options | None = None, after_half_sweep=None):
+def amen_solve(A, b, opt: Options | None = None, after_half_sweep=None, observe=None):
     """Solve A u = b in TT format.  Returns (list of cores of u, Stats).
 
     after_half_sweep(stats), if given, is called after every half-sweep; a true
     return value ends the sweep loop there (used to time bounded samples).
+    observe(event, k, cores), if given, receives copies of the iterate's cores
+    (forward order) before and after every local solve ("before_solve",
+    "after_solve") and after every half-sweep ("half_sweep", k = -1); it only
+    reads (used by the pins of the rank cap and the energy).
     """
     opt = opt or Options()
     modes = [C.shape[1] for C in A]
@@ -273,9 +283,11 @@ def amen_solve(A, b, opt: Options | None = None, after_half_sweep=None):
     ch.qr_pass()
     ch.reverse()
     for _ in range(opt.max_sweeps):
-        mr = _half_sweep(ch, opt, st)
+        mr = _half_sweep(ch, opt, st, observe)
         st.sweeps += 1
         st.max_res.append(mr)
+        if observe is not None:
+            observe("half_sweep", -1, ch.forward_cores())
         ch.reverse()
         if mr <= opt.tol:
             break

@@ -450,8 +450,9 @@ int tnfem_prim_qr(tnfem_ctx* ctx, int m, int n, const double* A, double* Q, doub
     if (m < 1 || n < 1 || n > 256) fail(TNFEM_EINVAL, "need m >= 1, 1 <= n <= 256");
     tnfem::hip_check(hipSetDevice(ctx->c.device), "hipSetDevice");
     const int c = std::min(m, n);
-    double* ws = ctx->c.ensure_scratch(tnfem::qr_ws_doubles(m, n) + 1);
-    tnfem::launch_qr(m, n, A, n, Q, c, R, n, ws, pick_stream(ctx, stream));
+    const size_t cap = tnfem::qr_ws_doubles(m, n) + 1;
+    double* ws = ctx->c.ensure_scratch(cap);
+    tnfem::launch_qr(m, n, A, n, Q, c, R, n, ws, cap, pick_stream(ctx, stream));
     return TNFEM_OK;
   });
 }
@@ -478,7 +479,8 @@ int tnfem_prim_svd(tnfem_ctx* ctx, int m, int n, const double* A, double* U, dou
       tnfem::launch_core_transpose(m, 1, n, A, At, st);  // At = A^T (n x m)
       src = At;
     }
-    tnfem::launch_qr(mm, nn, src, nn, Q, nn, R, nn, qws, st);
+    const size_t qws_cap = need - (size_t)(qws - ws);
+    tnfem::launch_qr(mm, nn, src, nn, Q, nn, R, nn, qws, qws_cap, st);
     tnfem::launch_jacobi_svd(nn, R, nn, V, S, UR, qws, st, 1);  // on R^T: outputs swapped
     tnfem::GemmDesc g;
     if (tall) {

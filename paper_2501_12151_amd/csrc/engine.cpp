@@ -43,6 +43,10 @@ void DevArena::release_all() {
 void* DevArena::alloc(size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
+  if (dry_) {
+    bytes_ += bytes;
+    return nullptr;
+  }
   hip_check(hipMalloc(&p, bytes), "hipMalloc");
   ptrs_.push_back(p);
   bytes_ += bytes;
@@ -52,6 +56,7 @@ void* DevArena::alloc(size_t bytes) {
 template <class T>
 T* DevArena::upload(const std::vector<T>& v, hipStream_t s) {
   T* d = static_cast<T*>(alloc(std::max<size_t>(v.size(), 1) * sizeof(T)));
+  if (dry_) return d;
   // blocking copy: callers pass short-lived host vectors (setup only, never in the sweep)
   (void)s;
   if (!v.empty()) hip_check(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
@@ -259,30 +264,33 @@ static void set_terms(FusedArgs& f, const Plan& pl) {
   for (int i = 0; i <= pl.n; ++i) f.begv[i] = pl.sp_beg_h[i];
 }
 
-std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& desc) {
-  auto P = std::make_unique<Problem>();
-  P->ctx = ctx;
-  P->host = assemble(desc);
-  const auto& A = P->host.A;
-  const auto& b = P->host.b;
-  P->K = (int)A.size();
-  hipStream_t s = ctx->stream;
-  hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-  for (int k = 0; k < P->K; ++k) {
-    P->modes.push_back(A[k].n);
-    P->maxn = std::max(P->maxn, A[k].n);
+// Builds the plans and load cores of both chain orientations into `arena` (a dry
+// arena only counts their bytes).
+static void build_device_data(Problem& P, DevArena& arena, hipStream_t s) {
+  const auto& A = P.host.A;
+  const auto& b = P.host.b;
+  P.modes.clear();
+  P.maxn = 1;
+  P.Rmax = 1;
+  P.smax = 1;
+  P.t1max_slots = P.t2max_slots = P.sp_slots_max = 1;
+  for (int k = 0; k < P.K; ++k) {
+    P.modes.push_back(A[k].n);
+    P.maxn = std::max(P.maxn, A[k].n);
   }
   for (int o = 0; o < 2; ++o) {
-    P->mrank[o].assign(P->K + 1, 1);
-    P->brank[o].assign(P->K + 1, 1);
-    for (int j = 0; j < P->K; ++j) {
-      const int k = o ? P->K - 1 - j : j;
+    P.plans[o].clear();
+    P.bcore[o].clear();
+    P.mrank[o].assign(P.K + 1, 1);
+    P.brank[o].assign(P.K + 1, 1);
+    for (int j = 0; j < P.K; ++j) {
+      const int k = o ? P.K - 1 - j : j;
       MpoCore c = o ? reversed_core(A[k]) : A[k];
-      P->plans[o].push_back(build_plan(c, P->arena, s, &P->t1max_slots, &P->t2max_slots));
-      if (!P->plans[o].back().dense) P->sp_slots_max = std::max(P->sp_slots_max, (size_t)P->plans[o].back().sp_nslot);
-      P->mrank[o][j] = c.Rl;
-      P->mrank[o][j + 1] = c.Rr;
-      P->Rmax = std::max(P->Rmax, std::max(c.Rl, c.Rr));
+      P.plans[o].push_back(build_plan(c, arena, s, &P.t1max_slots, &P.t2max_slots));
+      if (!P.plans[o].back().dense) P.sp_slots_max = std::max(P.sp_slots_max, (size_t)P.plans[o].back().sp_nslot);
+      P.mrank[o][j] = c.Rl;
+      P.mrank[o][j + 1] = c.Rr;
+      P.Rmax = std::max(P.Rmax, std::max(c.Rl, c.Rr));
       const TTCore& bc = b[k];
       std::vector<double> data = bc.data;
       int rl = bc.rl, rr = bc.rr;
@@ -292,13 +300,36 @@ std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& de
             for (int y = 0; y < bc.rr; ++y) data[((size_t)y * bc.n + i) * bc.rl + x] = bc.data[((size_t)x * bc.n + i) * bc.rr + y];
         std::swap(rl, rr);
       }
-      P->bcore[o].push_back(P->arena.upload(data, s));
-      P->brank[o][j] = rl;
-      P->brank[o][j + 1] = rr;
-      P->smax = std::max(P->smax, std::max(rl, rr));
+      P.bcore[o].push_back(arena.upload(data, s));
+      P.brank[o][j] = rl;
+      P.brank[o][j + 1] = rr;
+      P.smax = std::max(P.smax, std::max(rl, rr));
     }
   }
-  hip_check(hipStreamSynchronize(s), "upload sync");
+}
+
+std::unique_ptr<Problem> make_problem_host(const tnfem_problem_desc& desc) {
+  auto P = std::make_unique<Problem>();
+  P->host = assemble(desc);
+  P->K = (int)P->host.A.size();
+  DevArena dry(true);
+  build_device_data(*P, dry, nullptr);
+  P->device_bytes = dry.bytes();
+  return P;
+}
+
+void upload_problem(Context* ctx, Problem& P) {
+  if (P.uploaded) fail(TNFEM_EINVAL, "problem already uploaded");
+  P.ctx = ctx;
+  hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+  build_device_data(P, P.arena, ctx->stream);
+  P.uploaded = true;
+  hip_check(hipStreamSynchronize(ctx->stream), "upload sync");
+}
+
+std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& desc) {
+  auto P = make_problem_host(desc);
+  upload_problem(ctx, *P);
   return P;
 }
 
@@ -641,9 +672,12 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   W.Qa = A(M * Nw);
   W.Ra = A(Nw * Nw);
   W.Wm = A(Nw * Nw);
-  W.qrws = A(std::max(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw, qr_ws_doubles((int)M, (int)Nw)));
+  W.qrws_cap = std::max(M * Nw * 2 + 4 * Nw + 2 * Nw * Nw, qr_ws_doubles((int)M, (int)Nw));
+  W.qrws = A(W.qrws_cap);
   W.Rz = A((size_t)rho * maxn * rho + 1);
-  W.qrwsz = A(2 * (size_t)rho * maxn * rho + 4 * (size_t)rho);
+  // residual-TT QR: (rho n) x rho at most, routed to any variant (the blocked one included)
+  W.qrwsz_cap = std::max(2 * (size_t)rho * maxn * rho + 4 * (size_t)rho, qr_ws_doubles((int)(rho * maxn), rho));
+  W.qrwsz = A(W.qrwsz_cap);
   W.scal = A(16);
   W.fpart_cap = (size_t)1 << 22;
   W.fpart = A(W.fpart_cap);
@@ -858,7 +892,7 @@ struct Sweep {
   void qr_step(std::vector<double*>& T, std::vector<int>& tr, int k, double* spare) {
     const int m = tr[k] * n[k], nc = tr[k + 1];
     const int c = std::min(m, nc);
-    launch_qr(m, nc, T[k], nc, W.Qa, c, W.Ra, nc, W.qrws, st);
+    launch_qr(m, nc, T[k], nc, W.Qa, c, W.Ra, nc, W.qrws, W.qrws_cap, st);
     launch_copy2d(m, c, W.Qa, c, T[k], c, 1.0, 0.0, st);
     const int cols = n[k + 1] * tr[k + 2];
     gemm_plain(c, cols, nc, W.Ra, nc, false, T[k + 1], cols, spare, cols, st, &fl);
@@ -1092,13 +1126,13 @@ struct Sweep {
     s.tall = s.M >= s.Nn;
     const int M = s.M, Nn = s.Nn;
     if (s.tall) {
-      s.qr = QrJob{M, Nn, Nn, Nn, Nn, X[k], W.Qx, W.Rx, W.qrws};
+      s.qr = QrJob{M, Nn, Nn, Nn, Nn, X[k], W.Qx, W.Rx, W.qrws, W.qrws_cap};
       // Jacobi on R^T: its normalised columns are R's right, its rotations R's left vectors
       s.svd = SvdJob{Nn, Nn, W.Rx, W.V, W.S, W.UR, W.qrws, 1};
     } else {
       // x^T = Q U_R S V^T  =>  x = V S (Q U_R)^T
       launch_core_transpose(M, 1, Nn, X[k], W.xT, st);
-      s.qr = QrJob{Nn, M, M, M, M, W.xT, W.Qx, W.Rx, W.qrws};
+      s.qr = QrJob{Nn, M, M, M, M, W.xT, W.Qx, W.Rx, W.qrws, W.qrws_cap};
       s.svd = SvdJob{M, M, W.Rx, W.V, W.S, W.UR, W.qrws, 1};
     }
   }
@@ -1152,7 +1186,7 @@ struct Sweep {
     launch_sub((long)pz * nk * tz, W.gz, W.yz, W.gz, st);
     const int mz = pz * nk;
     s.cz = std::min(mz, tz);
-    s.zqr = QrJob{mz, tz, tz, s.cz, tz, W.gz, Z[k], W.Rz, W.qrwsz};
+    s.zqr = QrJob{mz, tz, tz, s.cz, tz, W.gz, Z[k], W.Rz, W.qrwsz, W.qrwsz_cap};
     // enrichment: residual on (left X, right Z) interfaces, as many columns as the cap
     // leaves room for
     const int rho_eff = std::max(0, std::min(tz, std::min(o.rank_cap - rk, M - rk)));
@@ -1169,7 +1203,7 @@ struct Sweep {
     launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
     launch_copy2d(M, rk, W.Ur, rk, W.aug, rnew, 1.0, 0.0, st);
     launch_copy2d(M, rho_eff, W.ge, tz, W.aug + rk, rnew, 1.0, 0.0, st);
-    s.aqr = QrJob{M, rnew, rnew, rnew, rnew, W.aug, X[k], W.Ra, W.qrws};
+    s.aqr = QrJob{M, rnew, rnew, rnew, rnew, W.aug, X[k], W.Ra, W.qrws, W.qrws_cap};
   }
 
   // the QR jobs of enrich_begin (the enrichment QR only when columns were added)
@@ -1193,7 +1227,7 @@ struct Sweep {
   void truncate_enrich(int k) {
     TruncState s;
     trunc_begin(k, s);
-    launch_qr(s.qr.m, s.qr.n, s.qr.A, s.qr.lda, s.qr.Q, s.qr.ldq, s.qr.R, s.qr.ldr, s.qr.ws, st);
+    launch_qr(s.qr.m, s.qr.n, s.qr.A, s.qr.lda, s.qr.Q, s.qr.ldq, s.qr.R, s.qr.ldr, s.qr.ws, s.qr.ws_cap, st);
     launch_jacobi_svd(s.svd.n, s.svd.G, s.svd.ldg, s.svd.U, s.svd.S, s.svd.V, s.svd.ws, st, s.svd.trans);
     trunc_rank(k, s);
     sync();

@@ -16,6 +16,9 @@ void hip_check(hipError_t e, const char* what);
 // Owner of device allocations made for one object; freed on destruction.
 class DevArena {
  public:
+  // dry = true: allocations are only counted (null pointers, no copies), for
+  // sizing a problem's device memory before anything is allocated
+  explicit DevArena(bool dry = false) : dry_(dry) {}
   ~DevArena();
   void* alloc(size_t bytes);
   template <class T>
@@ -26,6 +29,7 @@ class DevArena {
  private:
   std::vector<void*> ptrs_;
   size_t bytes_ = 0;
+  bool dry_ = false;
 };
 
 // Contraction plan of one operator core in one chain orientation.
@@ -88,6 +92,7 @@ struct Workspace {
   double *Qx = nullptr, *Rx = nullptr, *UR = nullptr, *S = nullptr, *V = nullptr, *Ur = nullptr, *SVt = nullptr,
          *xt = nullptr, *aug = nullptr, *Vt = nullptr, *xT = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;
   double *Rz = nullptr, *qrwsz = nullptr;  // R and scratch of the residual-TT QR
+  size_t qrws_cap = 0, qrwsz_cap = 0;     // doubles at qrws and qrwsz
   double *scal = nullptr, *part = nullptr;
   double* splitk = nullptr;
   size_t splitk_cap = 0;
@@ -120,6 +125,8 @@ struct Problem {
   size_t t1max_slots = 1, t2max_slots = 1;
   size_t sp_slots_max = 1;  // most slots of a sparse plan (stage of the two-stage fused apply)
   DevArena arena;
+  size_t device_bytes = 0;  // bytes the operator plans and load cores take on the device
+  bool uploaded = false;
   std::unique_ptr<Workspace> ws;
   void ensure_workspace(int cap, int rho);
   size_t workspace_bytes(int cap, int rho) const;  // device bytes ensure_workspace would allocate
@@ -131,6 +138,11 @@ struct HostTT {
   std::vector<std::vector<double>> cores;
 };
 
+// Host assembly and contraction plans, sized but not uploaded (device_bytes set).
+std::unique_ptr<Problem> make_problem_host(const tnfem_problem_desc& desc);
+// Uploads the plans and load cores of a host-built problem to ctx's device.
+void upload_problem(Context* ctx, Problem& P);
+// Both steps.
 std::unique_ptr<Problem> make_problem(Context* ctx, const tnfem_problem_desc& desc);
 
 // Contractions on the problem's plans (device pointers, asynchronous on s).

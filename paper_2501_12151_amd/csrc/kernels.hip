@@ -2322,6 +2322,11 @@ static void launch_qr_reg_batch(const QrBatch& b, size_t lds, hipStream_t s) {
 
 void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s) {
   if (jobs.size() > (size_t)QR_BATCH_MAX) throw Error(TNFEM_EINVAL, "QR batch: too many jobs");
+  for (const QrJob& j : jobs)
+    if (j.ws_cap < qr_ws_doubles(j.m, j.n))
+      throw Error(TNFEM_EINVAL, "QR batch: workspace of " + std::to_string(j.ws_cap) + " doubles below the " +
+                                    std::to_string(qr_ws_doubles(j.m, j.n)) + " a " + std::to_string(j.m) + " x " +
+                                    std::to_string(j.n) + " QR may use");
   static std::once_flag attr_once;
   std::call_once(attr_once, [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_owner_batch_kernel<true>),
@@ -2388,7 +2393,11 @@ static void launch_qr_reg(int m, int n, const double* A, int lda, double* Q, int
 }
 
 void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws,
-               hipStream_t s) {
+               size_t ws_cap, hipStream_t s) {
+  if (ws_cap < qr_ws_doubles(m, n))
+    throw Error(TNFEM_EINVAL, "QR: workspace of " + std::to_string(ws_cap) + " doubles below the " +
+                                  std::to_string(qr_ws_doubles(m, n)) + " a " + std::to_string(m) + " x " +
+                                  std::to_string(n) + " QR may use");
   const size_t bytes = qr_lds_bytes(m, n);
   const int kp = qr_pad_rows(m);
   if (qr_pad_fits(m, n, kp)) {

@@ -214,21 +214,25 @@ void launch_dense_matvec(int N, const double* Bm, const double* z, double* y, co
 void launch_local_block_inv(int p, int n, int t, int Rl, int Rr, const double* L, const double* Rt, const int* beg,
                             const int* kb, const int* ke, const double* kv, double* binv, hipStream_t s);
 
-// Householder QR of A (m x n, row-major, lda), single workgroup: Q (m x c), R (c x n), c = min(m, n).
-// ws: workspace of m * n + m * c + 2 * c doubles.
-void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws, hipStream_t s);
+// Householder QR of A (m x n, row-major, lda): Q (m x c), R (c x n), c = min(m, n).
+// ws: workspace of ws_cap doubles; throws TNFEM_EINVAL on the host (nothing launched)
+// when ws_cap < qr_ws_doubles(m, n), the most any variant may use.
+void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, double* R, int ldr, double* ws,
+               size_t ws_cap, hipStream_t s);
 
 // Batched QR: one workgroup per job, each the same computation as launch_qr.
 struct QrJob {
   int m = 0, n = 0, lda = 0, ldq = 0, ldr = 0;
   const double* A = nullptr;
   double *Q = nullptr, *R = nullptr, *ws = nullptr;
+  size_t ws_cap = 0;  // doubles at ws; checked against qr_ws_doubles(m, n) before any launch
 };
 constexpr int QR_BATCH_MAX = 32;
 struct QrBatch {
   int njob = 0;
   QrJob job[QR_BATCH_MAX];
 };
+// Throws TNFEM_EINVAL (nothing launched) when a job's ws_cap is below qr_ws_doubles(m, n).
 void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s);
 // doubles of ws a QR of an m x n matrix may use (every variant)
 size_t qr_ws_doubles(int m, int n);

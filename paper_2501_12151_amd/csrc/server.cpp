@@ -4,10 +4,10 @@
 // A request is queued at submission.  Each worker slot owns a HIP stream (one
 // context); a free slot takes the oldest queued request together with the
 // queued requests of the same shape bucket (same dimension, level and solve
-// options, FP64; up to max_batch of them), assembles and uploads their problems,
-// computes the device bytes their solves will hold (problem + workspace) and is
-// admitted as soon as that fits in the HBM budget next to the requests already
-// running.  A bucket of several requests is solved in lockstep with shared
+// options, FP64; up to max_batch of them), assembles their problems on the host,
+// computes the device bytes their solves will hold (operator plans, load cores and
+// workspace) and uploads them once that fits in the HBM budget next to the
+// requests already running (nothing is allocated on the device before admission).  A bucket of several requests is solved in lockstep with shared
 // launches of the local CG iterations (run_solve_batch); different slots run
 // on different streams, so their work overlaps on the device.  A request's
 // arithmetic does not depend on what else runs (per-request kernels and
@@ -158,14 +158,19 @@ class Server {
     (void)hipStreamDestroy(ctx.stream);
   }
 
+  // Device bytes of a request: its operator plans and load cores plus the workspace of
+  // its rank cap, computed from the host assembly before anything is allocated.
+  static size_t request_bytes(const Problem& P, const Request* r) {
+    return P.device_bytes + P.workspace_bytes(r->opts.rank_cap, std::max(r->opts.rho, 1));
+  }
+
   void run(Context& ctx, Request* r) {
     std::unique_ptr<Problem> P;
     size_t bytes = 0;
     bool admitted = false;
     try {
-      P = make_problem(&ctx, r->desc);
-      const int rho = std::max(r->opts.rho, 1);
-      bytes = P->arena.bytes() + P->workspace_bytes(r->opts.rank_cap, rho);
+      P = make_problem_host(r->desc);
+      bytes = request_bytes(*P, r);
       if (bytes > budget_) fail(TNFEM_EBUDGET, "request needs %zu device bytes, budget is %zu", bytes, budget_);
       {
         std::unique_lock<std::mutex> lk(mu_);
@@ -178,6 +183,7 @@ class Server {
         admitted = true;
       }
       r->bytes = bytes;
+      upload_problem(&ctx, *P);  // device memory only after admission
       r->rc = run_solve(*P, r->opts, r->result, r->stats);
     } catch (const Error& e) {
       r->rc = e.code;
@@ -214,33 +220,39 @@ class Server {
     return true;
   }
 
+  // Runs a bucket as one lockstep batch.  On return `group` holds exactly the
+  // requests this worker finished (ran or failed); requests sent back to the queue
+  // are removed from it inside the same locked section that requeues them, so a
+  // worker that picks them up owns them alone.
   void run_group(Context& ctx, std::vector<Request*>& group) {
     std::vector<std::unique_ptr<Problem>> probs;
-    std::vector<Request*> members;
+    std::vector<Request*> members, mine;
     size_t bytes = 0;
     for (Request* r : group) {
       try {
-        auto P = make_problem(&ctx, r->desc);
-        const size_t b = P->arena.bytes() + P->workspace_bytes(r->opts.rank_cap, std::max(r->opts.rho, 1));
+        auto P = make_problem_host(r->desc);
+        const size_t b = request_bytes(*P, r);
         if (b > budget_) fail(TNFEM_EBUDGET, "request needs %zu device bytes, budget is %zu", b, budget_);
         if (bytes + b > budget_) {  // the rest waits for another slot
           std::lock_guard<std::mutex> lk(mu_);
           r->state = 0;
           queue_.push_front(r);
           cv_work_.notify_one();
-          continue;
+          continue;  // not in `mine`: another worker may own it from here on
         }
         bytes += b;
         r->bytes = b;
         probs.push_back(std::move(P));
         members.push_back(r);
+        mine.push_back(r);
       } catch (const Error& e) {
         r->rc = e.code;
         r->error = e.what();
         r->t_done = std::chrono::steady_clock::now();
+        mine.push_back(r);
       }
     }
-    group.erase(std::remove_if(group.begin(), group.end(), [](Request* r) { return r->state == 0; }), group.end());
+    group.swap(mine);
     if (members.empty()) return;
     if (!admit(bytes)) {
       for (Request* r : members) {
@@ -259,7 +271,10 @@ class Server {
     const auto t0 = std::chrono::steady_clock::now();
     try {
       std::vector<Problem*> ps;
-      for (auto& P : probs) ps.push_back(P.get());
+      for (auto& P : probs) {
+        upload_problem(&ctx, *P);  // device memory only after admission
+        ps.push_back(P.get());
+      }
       std::vector<HostTT> outs;
       std::vector<tnfem_solve_stats> st;
       std::vector<int> rcs;

@@ -71,9 +71,13 @@ def test_budget_rejects_and_serialises():
     print("small budget info", info, flush=True)
     assert info["peak_bytes"] <= budget
     assert info["peak_running"] == 1
+    assert info["completed"] == 4
     ref = _cores(outs[0])
-    for o in outs[1:]:
-        for a, b in zip(_cores(o), ref):
+    assert len(ref) == MIX[0][0]["level"] + 1
+    for o in outs:
+        got = _cores(o)
+        assert len(got) == len(ref) > 0  # every request came back with its whole TT
+        for a, b in zip(got, ref):
             assert np.array_equal(a, b)
 
 

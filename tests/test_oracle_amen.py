@@ -112,3 +112,88 @@ def test_block_preconditioned_pcg_solves_spd_local_system():
                        amen.block_preconditioner(amen.local_block(L1, A1, R1)), 1e-10 * np.linalg.norm(g1), 50)
     assert it1 == 1
     assert np.allclose(x1.reshape(-1), np.linalg.solve(_dense_local(L1, A1, R1), g1.reshape(-1)), rtol=1e-10)
+
+
+def test_scaling_and_superposition():
+    """u(sE) = u(E)/s (A scales with E, the loads do not), and solutions of summed loads add."""
+    base = dict(dim=2, level=3, nu=0.3, clamp=[(0, 0)])
+    p1 = dict(base, E=1.0, tractions=[(0, 1, [1.0, 0.0])])
+    p2 = dict(base, E=4.0, tractions=[(0, 1, [1.0, 0.0])])
+    X1, *_ = _solve_both(p1, tol=1e-11, rank_cap=64)
+    X2, *_ = _solve_both(p2, tol=1e-11, rank_cap=64)
+    assert np.linalg.norm(tt.tt_full(X1) - 4.0 * tt.tt_full(X2)) <= 1e-8 * np.linalg.norm(tt.tt_full(X1))
+    p3 = dict(base, E=1.0, body_force=[0.0, -1.0])
+    p4 = dict(base, E=1.0, tractions=[(0, 1, [1.0, 0.0])], body_force=[0.0, -1.0])
+    X3, *_ = _solve_both(p3, tol=1e-11, rank_cap=64)
+    X4, *_ = _solve_both(p4, tol=1e-11, rank_cap=64)
+    lhs = tt.tt_full(X4)
+    assert np.linalg.norm(lhs - tt.tt_full(X1) - tt.tt_full(X3)) <= 1e-8 * np.linalg.norm(lhs)
+
+
+def test_mirror_symmetry_body_force_cube():
+    """Clamp x = 0, load along -z: u_x, u_z even and u_y odd under y -> 1 - y."""
+    prob = dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, 0.0, -1.0])
+    X, st, u, grid = _solve_both(prob, tol=1e-10, rank_cap=128)
+    n = grid.n
+    coords = np.array([[i, j, k] for i in range(n) for j in range(n) for k in range(n)])
+    mirror = coords.copy()
+    mirror[:, 1] = n - 1 - coords[:, 1]
+    for c, sign in ((0, 1), (1, -1), (2, 1)):
+        v = tt.tt_eval(X, qtt.qtt_dof_index(3, 3, c, coords))
+        w = tt.tt_eval(X, qtt.qtt_dof_index(3, 3, c, mirror))
+        assert np.abs(v - sign * w).max() <= 1e-8 * np.abs(u).max()
+
+
+def _ranks(cores):
+    return [C.shape[0] for C in cores] + [cores[-1].shape[2]]
+
+
+@pytest.mark.parametrize("prob,cap", [
+    (dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])]), 4),
+    (dict(dim=2, level=4, E=2.0, nu=0.35, clamp=[(0, 0)], body_force=[0.2, -1.0]), 6),
+    (dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, 0.0, -1.0]), 5),
+    (dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])]), 7),
+])
+def test_rank_capped_sweep_keeps_cap_and_lowers_energy(prob, cap):
+    """A binding rank cap: every bond stays <= cap after every step (truncation at the cap
+    and the clipped enrichment), the cap is reached, and no local solve raises the energy
+    J(x) = x^T A x / 2 - b^T x of the whole iterate (A, b: the sparse element assembly,
+    permuted to the QTT order; each local solve is a Galerkin step on a subspace that holds
+    the current iterate, and CG does not raise the energy)."""
+    A, b, grid, _ = fem.build_system(prob)
+    D, d = prob["dim"], prob["level"]
+    Ap = qtt.matrix_to_qtt_order(A, D, d).tocsr()
+    bp = qtt.to_qtt_order(b, D, d)
+
+    def energy(cores):
+        x = tt.tt_full(cores)
+        return 0.5 * x @ (Ap @ x) - bp @ x
+
+    seen = dict(max_rank=0, solves=0, sweeps=0)
+    last = {}
+
+    def observe(event, k, cores):
+        r = _ranks(cores)
+        assert max(r) <= cap, (event, k, r)
+        seen["max_rank"] = max(seen["max_rank"], max(r))
+        if event == "before_solve":
+            last["J"] = energy(cores)
+        elif event == "after_solve":
+            J = energy(cores)
+            assert J <= last["J"] + 1e-12 * abs(last["J"]), (k, J, last["J"])
+            seen["solves"] += 1
+        else:
+            seen["sweeps"] += 1
+
+    Aq = qtt.assemble_operator(prob)
+    bq = qtt.assemble_load(prob)
+    X, st = amen.amen_solve(Aq, bq, amen.Options(tol=1e-12, rank_cap=cap, max_sweeps=6), observe=observe)
+    assert seen["max_rank"] == cap  # the cap binds
+    assert seen["sweeps"] == st.sweeps == 6 and seen["solves"] == 6 * (d + 1)
+    assert max(_ranks(X)) <= cap
+    # the capped iterate is still a good approximation: its energy lies above the
+    # exact discrete minimum and within a few per cent of it
+    u = fem.direct_solve(A, b)
+    Jmin = 0.5 * u @ (A @ u) - b @ u
+    Jx = energy(X)
+    assert Jmin - 1e-12 * abs(Jmin) <= Jx <= Jmin + 0.05 * abs(Jmin)
