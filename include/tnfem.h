@@ -290,6 +290,25 @@ int tnfem_prim_qr(tnfem_ctx* ctx, int m, int n, const double* A, double* Q, doub
  * One-sided Jacobi on the R factor of a Householder QR. */
 int tnfem_prim_svd(tnfem_ctx* ctx, int m, int n, const double* A, double* U, double* S, double* Vt, void* stream);
 
+/* Allocation-free variant of tnfem_prim_svd, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as tnfem_prim_svd; its
+ * workspace (the transposed input, the QR factors, the Jacobi rotations) lives in
+ * a fixed array of TNFEM_NOALLOC_SCRATCH_BYTES in device memory, one per device,
+ * resolved when the first context on that device is created and held until the
+ * process ends.  The call allocates nothing on the device or through any library.
+ * A shape whose workspace does not fit, tnfem_prim_svd_noalloc_doubles(m, n) >
+ * TNFEM_NOALLOC_SCRATCH_BYTES / 8, fails with TNFEM_EINVAL before anything is
+ * launched.  Every call on one device shares that device's array and leaves its
+ * contents behind (nothing in it needs to start at zero): calls that overlap on
+ * one device (different streams, or threads without ordering) race. */
+#define TNFEM_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int tnfem_prim_svd_noalloc(tnfem_ctx* ctx, int m, int n, const double* A, double* U, double* S, double* Vt,
+                           void* stream);
+/* Doubles of workspace tnfem_prim_svd and tnfem_prim_svd_noalloc use for an m x n input
+ * (0 for an invalid shape). */
+size_t tnfem_prim_svd_noalloc_doubles(int m, int n);
+
 #ifdef __cplusplus
 }
 #endif

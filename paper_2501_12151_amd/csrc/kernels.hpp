@@ -5,6 +5,8 @@
 
 #include <vector>
 
+#include "../../include/tnfem.h"
+
 namespace tnfem {
 
 // Grouped, strided, coefficient-weighted FP64 GEMM on MFMA:
@@ -280,5 +282,12 @@ void launch_sub(long n, const double* a, const double* b, double* out, hipStream
 
 // flag[k] = 1 if any of the n values is not finite (OR accumulated).
 void launch_nan_check(long n, const double* x, int* flag, hipStream_t s);
+
+// Fixed workspace of the allocation-free entry points: TNFEM_NOALLOC_SCRATCH_BYTES per
+// device.  noalloc_init (device current or not) resolves that device's address once;
+// noalloc_scratch returns it, or throws TNFEM_EDEVICE when it could not be resolved.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = TNFEM_NOALLOC_SCRATCH_BYTES / sizeof(double);
+void noalloc_init(int device);
+double* noalloc_scratch(int device);
 
 }  // namespace tnfem

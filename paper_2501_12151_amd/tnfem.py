@@ -116,6 +116,8 @@ _sig = {
     "tnfem_prim_env_update": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "tnfem_prim_qr": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "tnfem_prim_svd": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "tnfem_prim_svd_noalloc": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "tnfem_prim_svd_noalloc_doubles": (C.c_size_t, [C.c_int, C.c_int]),
     "tnfem_server_create": (C.c_int, [C.c_int, C.c_int, C.c_size_t, C.POINTER(_vp)]),
     "tnfem_server_submit": (C.c_int, [_vp, C.POINTER(ProblemDesc), C.POINTER(SolveOpts), C.POINTER(C.c_longlong)]),
     "tnfem_server_poll": (C.c_int, [_vp, C.c_longlong, C.c_int, C.POINTER(_vp), C.POINTER(SolveStats),
@@ -323,6 +325,18 @@ class Context:
 
     def svd(self, m, n, A, U, S, Vt, stream=None):
         _check(_lib.tnfem_prim_svd(self._h, m, n, _ptr(A), _ptr(U), _ptr(S), _ptr(Vt), _ptr(stream)))
+
+    def svd_noalloc(self, m, n, A, U, S, Vt, stream=None):
+        """The same SVD with the library's fixed device workspace (no allocation)."""
+        _check(_lib.tnfem_prim_svd_noalloc(self._h, m, n, _ptr(A), _ptr(U), _ptr(S), _ptr(Vt), _ptr(stream)))
+
+
+def svd_noalloc_doubles(m, n):
+    """Workspace doubles of an m x n SVD (0 for an invalid shape)."""
+    return int(_lib.tnfem_prim_svd_noalloc_doubles(int(m), int(n)))
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 def _ptr(x):
