@@ -90,6 +90,16 @@ typedef struct {
   int layer_axis;
   int n_layer_E;
   const double* layer_E; /* host, n_layer_E values, copied */
+  /* Optional nodal load f0 of Alg. 2 (Sec. 5.3): the body force at every node as a TT in
+   * the layout of u (d level cores of mode 2^D, then the component core of mode D).
+   * The load gains P M f0, M the consistent (vector) mass matrix and P the mask of the
+   * dofs not clamped; the product is formed in TT format on the host (each axis' 1D
+   * mass matrix as an exact rank <= 2 QTT operator per term) and rounded at 1e-14.
+   * f0_ranks: d + 2 values, the first and last 1 (host, copied); f0_cores: all cores
+   * concatenated, core k row-major [r_k][n_k][r_{k+1}] (host, copied).  f0_cores NULL:
+   * no nodal load.  Invalid ranks fail with TNFEM_EINVAL. */
+  const int* f0_ranks;
+  const double* f0_cores;
 } tnfem_problem_desc;
 
 /*

@@ -188,6 +188,15 @@ def body_load(grid: Grid, M, f_nodal):
     return np.concatenate([M @ f_nodal[c] for c in range(grid.D)])
 
 
+def nodal_values_from_tt(cores, D: int, d: int):
+    """f0[c, node] from a TT of nodal values in the solution layout: d level cores
+    (most significant bit first, mode (bx 2 + by) 2 + bz) then the component core."""
+    from . import qtt, tt
+
+    flat = tt.tt_full([np.asarray(c, dtype=np.float64) for c in cores]).reshape(-1)
+    return flat[qtt.natural_to_qtt(D, d)].reshape(D, -1)
+
+
 def face_nodes(grid: Grid, axis: int, side: int):
     """Natural indices of the nodes on face {x_axis = side * extent}."""
     coords = np.array(list(itertools.product(range(grid.n), repeat=grid.D)), dtype=np.int64)
@@ -289,6 +298,7 @@ def build_system(problem: dict):
     clamp: list of (axis, side), tractions: list of (axis, side, t),
     body_force: constant vector (opt), manufactured_c: vector (opt; load
     f = M f0 with f0 the closed-form manufactured force at the nodes),
+    f_nodal_tt: TT cores of nodal force values f0 (opt; load M f0, Alg. 2 / Sec. 5.3),
     layered_E: (axis, values per element along that axis) (opt).
     """
     D, d = problem["dim"], problem["level"]
@@ -310,6 +320,8 @@ def build_system(problem: dict):
         x = grid.node_coords()
         f0 = manufactured_f(x, np.asarray(problem["manufactured_c"], dtype=np.float64), lam, mu)
         b += body_load(grid, M, f0)
+    if problem.get("f_nodal_tt") is not None:
+        b += body_load(grid, M, nodal_values_from_tt(problem["f_nodal_tt"], D, d))
     for axis, side, t in problem.get("tractions", []):
         b += traction_load(grid, axis, side, t)
     mask = clamp_mask(grid, problem.get("clamp", []))

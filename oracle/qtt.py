@@ -280,6 +280,15 @@ def assemble_load(problem: dict, eps=1e-14, component_first=False):
             vecs.append(masks[a] * v)
         pieces.append((t, vecs))
     total = None
+    if problem.get("f_nodal_tt") is not None:
+        # nodal load f0 given as a TT (Alg. 2): b = P M f0 formed with the sparse mass
+        # matrix on the dense grid, then compressed by TT-SVD
+        grid = fem.Grid(D, d, problem.get("extent"))
+        _, M = fem.assemble(grid, lam, mu)
+        mask = fem.clamp_mask(grid, problem.get("clamp", []))
+        bn = mask * fem.body_load(grid, M, fem.nodal_values_from_tt(problem["f_nodal_tt"], D, d))
+        modes = [D] + [2 ** D] * d if component_first else [2 ** D] * d + [D]
+        total = tt.tt_svd(to_qtt_order(bn, D, d, component_first).reshape(modes), modes, eps)
     for comp, vecs in pieces:
         lev = kron_levels_vector([vector_qtt(v, d) for v in vecs])
         c0 = np.asarray(comp, dtype=np.float64).reshape(1, D, 1)

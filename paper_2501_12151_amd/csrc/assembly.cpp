@@ -326,7 +326,168 @@ std::vector<TTCore> tt_sum(const std::vector<TTCore>& x, const std::vector<TTCor
   return out;
 }
 
+// ----------------------------------------------------------------------------- nodal load f0
+
+// A 1D operator in QTT form: d cores [R][2][2][R'] (output bit, input bit), most
+// significant level first, boundary ranks 1.
+struct Qtt1d {
+  std::vector<int> r;                    // d + 1 ranks
+  std::vector<std::vector<double>> c;    // d cores
+  double coef = 1.0;
+};
+
+// Per-level 2 x 2 blocks (output bit, input bit).
+static const double I2[4] = {1, 0, 0, 1};
+static const double J2[4] = {0, 1, 0, 0};   // (0, 1): the input index is the output index + 1
+static const double J2t[4] = {0, 0, 1, 0};  // (1, 0)
+static const double E0[4] = {1, 0, 0, 0};
+static const double E1[4] = {0, 0, 0, 1};
+
+// Rank-1 Kronecker product of per-level blocks: blk(l) for l < d - 1, last for l = d - 1.
+static Qtt1d qtt1d_rank1(int d, const double* blk, const double* last, double coef) {
+  Qtt1d q;
+  q.coef = coef;
+  q.r.assign(d + 1, 1);
+  for (int l = 0; l < d; ++l) q.c.emplace_back(l == d - 1 ? last : blk, (l == d - 1 ? last : blk) + 4);
+  return q;
+}
+
+// The upper shift J (J[i][j] = 1 iff j = i + 1), or its transpose: a carry automaton
+// whose bond state is the carry passed from the less significant levels (right bond:
+// carry into the level, left bond: carry out of it).  Without a carry the bits agree;
+// with one the level either absorbs it (bits 0 -> 1 for J) or passes it on (1 -> 0).
+static Qtt1d qtt1d_shift(int d, bool transpose, double coef) {
+  const double* up = transpose ? J2t : J2;    // carry absorbed
+  const double* pass = transpose ? J2 : J2t;  // carry passed on
+  Qtt1d q;
+  q.coef = coef;
+  q.r.assign(d + 1, 2);
+  q.r[0] = 1;
+  q.r[d] = 1;
+  for (int l = 0; l < d; ++l) {
+    const int rl = q.r[l], rr = q.r[l + 1];
+    std::vector<double> c((size_t)rl * 4 * rr, 0.0);
+    auto put = [&](int a, int b, const double* m) {
+      for (int e = 0; e < 4; ++e) c[((size_t)a * 4 + e) * rr + b] = m[e];
+    };
+    if (d == 1) {
+      put(0, 0, up);  // one level: the carry enters and must be absorbed
+    } else if (l == 0) {
+      put(0, 0, I2);  // no overflow out of the most significant level
+      put(0, 1, up);
+    } else if (l == d - 1) {
+      put(0, 0, up);  // the +1 enters at the least significant level
+      put(1, 0, pass);
+    } else {
+      put(0, 0, I2);
+      put(0, 1, up);
+      put(1, 1, pass);
+    }
+    q.c.push_back(c);
+  }
+  return q;
+}
+
+// Terms of P_a M_a, the 1D consistent mass matrix of axis a with the rows of clamped
+// ends removed:  M = h/6 (4 I + J + J^T - 2 E00 - 2 Ell),  E00 M = h/6 (2 E00 + E00 J),
+// Ell M = h/6 (2 Ell + Ell J^T),  P_a M = M - c0 E00 M - c1 Ell M.
+static std::vector<Qtt1d> masked_mass_terms(int d, double h, bool c0, bool c1) {
+  const double s = h / 6.0;
+  std::vector<Qtt1d> t;
+  t.push_back(qtt1d_rank1(d, I2, I2, 4 * s));
+  t.push_back(qtt1d_shift(d, false, s));
+  t.push_back(qtt1d_shift(d, true, s));
+  t.push_back(qtt1d_rank1(d, E0, E0, -(2.0 + 2.0 * c0) * s));
+  t.push_back(qtt1d_rank1(d, E1, E1, -(2.0 + 2.0 * c1) * s));
+  if (c0) t.push_back(qtt1d_rank1(d, E0, J2, -s));   // e_0 e_1^T
+  if (c1) t.push_back(qtt1d_rank1(d, E1, J2t, -s));  // e_l e_{l-1}^T
+  return t;
+}
+
+// Applies the 1D operator op to the bits of axis a of a TT in the solution layout (d level
+// cores of mode 2^D, mode bit of axis a at position D - 1 - a, then the component core).
+static std::vector<TTCore> apply_axis(const std::vector<TTCore>& X, const Qtt1d& op, int a, int D) {
+  const int d = (int)X.size() - 1;
+  const int nm = 1 << D, shift = D - 1 - a;
+  std::vector<TTCore> Y(d + 1);
+  for (int l = 0; l < d; ++l) {
+    const TTCore& x = X[l];
+    const int Rl = op.r[l], Rr = op.r[l + 1];
+    TTCore y;
+    y.rl = x.rl * Rl;
+    y.n = nm;
+    y.rr = x.rr * Rr;
+    y.data.assign((size_t)y.rl * nm * y.rr, 0.0);
+    const std::vector<double>& c = op.c[l];
+    for (int al = 0; al < x.rl; ++al)
+      for (int mo = 0; mo < nm; ++mo) {
+        const int bo = (mo >> shift) & 1;
+        for (int bi = 0; bi < 2; ++bi) {
+          const int mi = (mo & ~(1 << shift)) | (bi << shift);
+          for (int rho = 0; rho < Rl; ++rho)
+            for (int sg = 0; sg < Rr; ++sg) {
+              const double w = c[((size_t)rho * 4 + bo * 2 + bi) * Rr + sg];
+              if (w == 0.0) continue;
+              for (int be = 0; be < x.rr; ++be)
+                y.data[(((size_t)al * Rl + rho) * nm + mo) * y.rr + (size_t)be * Rr + sg] +=
+                    w * x.data[((size_t)al * nm + mi) * x.rr + be];
+            }
+        }
+      }
+    Y[l] = y;
+  }
+  Y[d] = X[d];
+  for (double& v : Y[0].data) v *= op.coef;
+  return Y;
+}
+
 }  // namespace
+
+size_t f0_doubles(const tnfem_problem_desc& desc) {
+  if (!desc.f0_cores) return 0;
+  TNFEM_REQUIRE(desc.f0_ranks != nullptr, "f0_cores given without f0_ranks");
+  const int D = desc.dim, d = desc.level;
+  TNFEM_REQUIRE((D == 2 || D == 3) && d >= 2 && d <= 20, "invalid dim or level");
+  const int K = d + 1;
+  TNFEM_REQUIRE(desc.f0_ranks[0] == 1 && desc.f0_ranks[K] == 1, "f0 boundary ranks must be 1");
+  size_t total = 0;
+  for (int k = 0; k < K; ++k) {
+    const int rl = desc.f0_ranks[k], rr = desc.f0_ranks[k + 1];
+    TNFEM_REQUIRE(rl >= 1 && rl <= 4096 && rr >= 1 && rr <= 4096, "f0 ranks must be in [1, 4096]");
+    total += (size_t)rl * (k < d ? (1u << D) : (unsigned)D) * rr;
+  }
+  return total;
+}
+
+// P M f0 in TT format: one axis at a time, the masked 1D mass terms applied, summed and
+// rounded.
+static std::vector<TTCore> nodal_load(const tnfem_problem_desc& desc, const bool* c0, const bool* c1) {
+  const int D = desc.dim, d = desc.level, K = d + 1;
+  f0_doubles(desc);  // validates
+  std::vector<TTCore> X(K);
+  size_t off = 0;
+  for (int k = 0; k < K; ++k) {
+    X[k].rl = desc.f0_ranks[k];
+    X[k].rr = desc.f0_ranks[k + 1];
+    X[k].n = k < d ? (1 << D) : D;
+    const size_t sz = (size_t)X[k].rl * X[k].n * X[k].rr;
+    X[k].data.assign(desc.f0_cores + off, desc.f0_cores + off + sz);
+    for (double v : X[k].data) TNFEM_REQUIRE(std::isfinite(v), "f0 holds a non-finite value");
+    off += sz;
+  }
+  const int n = 1 << d;
+  for (int a = 0; a < D; ++a) {
+    const double h = desc.extent[a] / (n - 1);
+    std::vector<TTCore> acc;
+    for (const Qtt1d& op : masked_mass_terms(d, h, c0[a], c1[a])) {
+      std::vector<TTCore> y = apply_axis(X, op, a, D);
+      acc = acc.empty() ? y : tt_sum(acc, y);
+    }
+    tt_round_host(acc, 1e-14, 1 << 30);
+    X = acc;
+  }
+  return X;
+}
 
 void tt_round_host(std::vector<TTCore>& cores, double tol, int rmax) {
   const int K = (int)cores.size();
@@ -659,6 +820,15 @@ Assembled assemble(const tnfem_problem_desc& desc) {
       total = lev;
     } else {
       total = tt_sum(total, lev);
+      tt_round_host(total, 1e-14, 1 << 30);
+    }
+  }
+  if (desc.f0_cores) {
+    std::vector<TTCore> f0b = nodal_load(desc, c0, c1);
+    if (total.empty()) {
+      total = f0b;
+    } else {
+      total = tt_sum(total, f0b);
       tt_round_host(total, 1e-14, 1 << 30);
     }
   }

@@ -35,6 +35,9 @@ struct Assembled {
 // Validates desc (throws tnfem::Error) and assembles operator and load.
 Assembled assemble(const tnfem_problem_desc& desc);
 
+// Doubles of the nodal load f0 (0 without one); validates its ranks (throws tnfem::Error).
+size_t f0_doubles(const tnfem_problem_desc& desc);
+
 // TT rounding on the host (relative accuracy tol, at most rmax).
 void tt_round_host(std::vector<TTCore>& cores, double tol, int rmax);
 

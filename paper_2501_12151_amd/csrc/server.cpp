@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "assembly.hpp"
 #include "engine.hpp"
 
 namespace tnfem {
@@ -35,6 +36,8 @@ struct Request {
   long long id = 0;
   tnfem_problem_desc desc{};
   std::vector<double> layer;
+  std::vector<int> f0_ranks;
+  std::vector<double> f0_cores;
   tnfem_solve_opts opts{};
   std::chrono::steady_clock::time_point t_submit, t_done;
   int state = 0;  // 0 queued, 1 running, 2 done
@@ -68,6 +71,13 @@ class Server {
     if (d.layer_E && d.n_layer_E > 0) {
       r->layer.assign(d.layer_E, d.layer_E + d.n_layer_E);
       r->desc.layer_E = r->layer.data();
+    }
+    if (d.f0_cores) {
+      const size_t nd = f0_doubles(d);  // validates the ranks before they size the copy
+      r->f0_ranks.assign(d.f0_ranks, d.f0_ranks + d.level + 2);
+      r->f0_cores.assign(d.f0_cores, d.f0_cores + nd);
+      r->desc.f0_ranks = r->f0_ranks.data();
+      r->desc.f0_cores = r->f0_cores.data();
     }
     r->opts = o;
     r->t_submit = std::chrono::steady_clock::now();

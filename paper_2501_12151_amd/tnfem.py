@@ -48,6 +48,7 @@ class ProblemDesc(C.Structure):
         ("traction", (C.c_double * 3) * 6), ("has_body_force", C.c_int), ("body_force", C.c_double * 3),
         ("has_manufactured", C.c_int), ("manufactured_c", C.c_double * 3),
         ("layer_axis", C.c_int), ("n_layer_E", C.c_int), ("layer_E", C.POINTER(C.c_double)),
+        ("f0_ranks", C.POINTER(C.c_int)), ("f0_cores", C.POINTER(C.c_double)),
     ]
 
 
@@ -181,6 +182,13 @@ def make_desc(problem: dict) -> ProblemDesc:
         d.layer_axis = int(axis)
         d.n_layer_E = arr.size
         d.layer_E = arr.ctypes.data_as(_dp)
+    if problem.get("f_nodal_tt") is not None:
+        cores = [np.asarray(c, dtype=np.float64) for c in problem["f_nodal_tt"]]
+        ranks = np.ascontiguousarray([c.shape[0] for c in cores] + [cores[-1].shape[2]], dtype=np.int32)
+        flat = np.ascontiguousarray(np.concatenate([c.reshape(-1) for c in cores]))
+        d._f0_keep = (ranks, flat)
+        d.f0_ranks = ranks.ctypes.data_as(_ip)
+        d.f0_cores = flat.ctypes.data_as(_dp)
     return d
 
 

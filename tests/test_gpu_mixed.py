@@ -9,6 +9,7 @@ torch = pytest.importorskip("torch")
 from oracle import amen as oamen, fem, qtt, tt  # noqa: E402
 from paper_2501_12151_amd import tnfem, workloads  # noqa: E402
 
+U64 = 2.0 ** -53
 U32 = 2.0 ** -24
 UBF = 2.0 ** -8
 
@@ -51,7 +52,8 @@ def test_fused_apply_precision_bound(ctx, dim, ranks, precision):
     nterms = max(int(np.count_nonzero(A[:, j, :, :])) for j in range(n))
     K = q + s * nterms
     if precision == 0:
-        assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+        # element by element: the standard bound of a K-deep FP64 dot-product chain
+        assert np.all(err <= (6 + K) * U64 * yabs + 1e-300)
     elif precision == 1:
         assert np.all(err <= (6 * U32 + K * U32) * yabs + 1e-300)
     else:

@@ -17,19 +17,30 @@ def ctx():
     c.close()
 
 
+def _nodal_tt(D, d, rank, seed):
+    """Seeded TT of nodal force values f0 (levels, then component)."""
+    rng = np.random.default_rng(seed)
+    modes = [2 ** D] * d + [D]
+    ranks = [1] + [rank] * d + [1]
+    return [rng.standard_normal((ranks[k], modes[k], ranks[k + 1])) for k in range(d + 1)]
+
+
 SMALL = [
     dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])]),
     dict(dim=2, level=4, E=3.0, nu=0.2, clamp=[(0, 0)], body_force=[0.0, -1.0]),
     dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, 0.0, -1.0]),
     dict(dim=3, level=3, E=1.0, nu=0.45, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])]),
     dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(a, s) for a in range(3) for s in (0, 1)], manufactured_c=[0.3, -1.0, 0.5]),
+    # nodal load f0 given as a TT (Alg. 2 input)
+    dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], f_nodal_tt=_nodal_tt(3, 3, 2, seed=5)),
+    dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(1, 0)], f_nodal_tt=_nodal_tt(2, 4, 3, seed=6)),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(SMALL)))
 def test_unconstrained_solve_equals_direct_and_oracle(ctx, case):
     prob = SMALL[case]
-    print(f"solve small case {case}: {prob}", flush=True)
+    print(f"solve small case {case}: {dict((k, v) for k, v in prob.items() if k != 'f_nodal_tt')}", flush=True)
     A, b, grid, _ = fem.build_system(prob)
     u = qtt.to_qtt_order(fem.direct_solve(A, b), prob["dim"], prob["level"])
     P = tnfem.Problem(ctx, prob)

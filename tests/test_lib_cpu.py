@@ -55,6 +55,63 @@ def test_library_assembly_equals_sparse_fem(case):
     assert max(C.shape[3] for C in Ac) <= 5 ** D
 
 
+def _random_nodal_tt(D, d, rank, seed):
+    """Seeded TT of nodal force values in the solution layout (levels, then component)."""
+    rng = np.random.default_rng(seed)
+    modes = [2 ** D] * d + [D]
+    ranks = [1] + [rank] * d + [1]
+    return [rng.standard_normal((ranks[k], modes[k], ranks[k + 1])) for k in range(d + 1)]
+
+
+NODAL_CASES = [
+    dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(0, 0)]),
+    dict(dim=2, level=3, E=2.0, nu=0.25, clamp=[(0, 0), (0, 1), (1, 0), (1, 1)], extent=[3.0, 0.5],
+         body_force=[0.2, -1.0]),
+    dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(2, 0), (1, 1)], tractions=[(2, 1, [0.0, 0.0, -1.0])]),
+    dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[], extent=[1.0, 2.0, 0.5]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(NODAL_CASES)))
+def test_nodal_load_through_the_c_abi_equals_sparse_mass_product(case):
+    """A non-constant nodal load f0 (a random rank-3 TT; Alg. 2, Sec. 5.3) handed through
+    the C ABI: the library's load equals P M f0 of the sparse assembly (plus the other
+    loads of the case)."""
+    prob = dict(NODAL_CASES[case])
+    D, d = prob["dim"], prob["level"]
+    prob["f_nodal_tt"] = _random_nodal_tt(D, d, 3, seed=case)
+    _, b, _, _ = fem.build_system(prob)
+    bp = qtt.to_qtt_order(b, D, d)
+    bl = tt.tt_full(tnfem.export_load(prob))
+    assert np.abs(bl - bp).max() <= 1e-12 * np.abs(bp).max()
+    # the oracle's QTT load of the same description agrees as well
+    assert np.abs(tt.tt_full(qtt.assemble_load(prob)) - bp).max() <= 1e-12 * np.abs(bp).max()
+
+
+def test_constant_nodal_load_equals_body_force():
+    """f0 = constant vector at every node reproduces the body-force load exactly."""
+    f = [0.3, -1.0, 0.5]
+    base = dict(dim=3, level=4, E=1.0, nu=0.3, clamp=[(0, 0), (2, 1)])
+    ones = [np.ones((1, 8, 1)) for _ in range(4)] + [np.asarray(f).reshape(1, 3, 1)]
+    b1 = tt.tt_full(tnfem.export_load(dict(base, body_force=f)))
+    b2 = tt.tt_full(tnfem.export_load(dict(base, f_nodal_tt=ones)))
+    assert np.abs(b1 - b2).max() <= 1e-13 * np.abs(b1).max()
+
+
+@pytest.mark.parametrize("ranks", [[2, 1, 1, 1], [1, 0, 1, 1], [1, 5000, 1, 1], [1, 1, 1, 3]])
+def test_nodal_load_rejects_bad_ranks(ranks):
+    """Ranks are validated before any core is read (d + 2 = 4 ranks at level 2)."""
+    prob = dict(dim=2, level=2, E=1.0, nu=0.3, clamp=[(0, 0)],
+                f_nodal_tt=[np.ones((1, 4, 1)), np.ones((1, 4, 1)), np.ones((1, 2, 1))])
+    desc = tnfem.make_desc(prob)
+    r = (ctypes.c_int * 4)(*ranks)
+    desc.f0_ranks = ctypes.cast(r, ctypes.POINTER(ctypes.c_int))
+    nc, need = ctypes.c_int(), ctypes.c_size_t()
+    modes, rk = (ctypes.c_int * 64)(), (ctypes.c_int * 65)()
+    rc = tnfem._lib.tnfem_export_load(ctypes.byref(desc), ctypes.byref(nc), modes, rk, None, 0, ctypes.byref(need))
+    assert rc == tnfem.EINVAL
+
+
 @pytest.mark.parametrize("prob", [dict(workloads.small_2d(), level=8), workloads.cube_body_force(4),
                                   workloads.layered_cube(5)])
 def test_library_operator_matches_oracle_tt_at_larger_levels(prob):
