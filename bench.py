@@ -2,10 +2,14 @@
 """Throughput of the QTT AMEn elasticity solve on one MI355X.
 
 One step = one complete solve (initial orthogonalisation, half-sweeps of local
-CG solves, SVD truncation, residual enrichment, QR, interface updates) of the
-3D unit-cube workload: 128^3 nodes (QTT level 7, 6.3 M dofs), E = 1, nu = 0.3,
-face x = 0 clamped, uniform body force (0, 0, -1), FP64, TT rank cap 32.  The
-operator and load are assembled and resident on the device before timing.
+CG solves, SVD truncation, residual enrichment, QR, interface updates).  The
+default workload is the 3D unit cube with 1024^3 nodes (QTT level 10, 3.2e9
+dofs), all faces clamped, load of the manufactured field u_i = c_i sin(pi x)
+sin(pi y) sin(pi z) with c ~ N(0, 1) (seed 0), E = 1, nu = 0.3, TT rank cap 64,
+solved with FP32 local applies on MFMA (FP32 accumulate) refined in FP64; the
+plain FP64 solve of the same problem is timed beside it.  The operator and load
+are assembled and resident on the device before timing.  The oracle solves the
+same problem on the host cores; its solution is the accuracy reference.
 
 Prints one JSON line (see the repository documentation for the fields).
 """
@@ -23,15 +27,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "solves/s + p50/p99 latency at 1e-6 rel. error; contraction TFLOP/s vs peak"
-# HBM bytes per launch of fused_apply32_kernel<0> on the cube128 workload, averaged over all
-# its launches in a solve: FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
-# counter reads for a 256 MiB copy (profiles/fused_apply_cube128_f64_cap32.md).  Valid
-# while that kernel and the set of applies it serves are unchanged.
-FUSED_APPLY_TRAFFIC_BYTES = 4792751.0
+# Counter summaries of the fused local apply: HBM bytes per launch (FETCH_SIZE + WRITE_SIZE
+# per dispatch, copy-calibrated, averaged over every fused-apply launch of one solve), keyed
+# by (workload, precision).  Each file states the command that produced it and holds one line
+# "traffic_bytes_per_launch: <bytes>"; a summary is valid while the kernels it covers are.
+TRAFFIC_SUMMARIES = {
+    ("cube1024", 1): "fused_apply_cube1024_f32_cap64.md",
+    ("cube1024", 0): "fused_apply_cube1024_f64_cap64.md",
+}
 
 PEAKS = {0: 78.6, 1: 157.3, 2: 2500.0}  # dense MFMA TFLOP/s: FP64, FP32, BF16
 DTYPES = {0: "f64", 1: "f32 (FP32 MFMA local applies, FP64 refinement)",
           2: "bf16 (BF16 MFMA local applies, FP32 accumulate, FP64 refinement)"}
+DTYPE_TAGS = {0: "f64", 1: "f32/f64", 2: "bf16/f64"}
 
 WORKLOADS = {
     # refs: solve options of the FP64 reference solves for the accuracy block (the last one is
@@ -42,7 +50,8 @@ WORKLOADS = {
                     refs=[dict(rank_cap=64, tol=1e-9, max_sweeps=30), dict(rank_cap=96, tol=1e-9, max_sweeps=30)],
                     desc="3D unit cube 128^3 nodes (QTT level 7), body force (0,0,-1), x=0 clamped, E=1, nu=0.3, "
                          "rank cap 32"),
-    "cube1024": dict(level=10, opts=dict(rank_cap=64, tol=1e-6, max_sweeps=24),
+    # the oracle runs this whole solve on the host (about a minute) as the accuracy reference
+    "cube1024": dict(level=10, opts=dict(rank_cap=64, tol=1e-6, max_sweeps=24), oracle_full=True,
                      refs=[dict(rank_cap=64, tol=1e-8, max_sweeps=40), dict(rank_cap=96, tol=1e-9, max_sweeps=40)],
                      desc="3D unit cube 1024^3 nodes (QTT level 10), all faces clamped, load of the manufactured field "
                           "u_i = c_i sin(pi x) sin(pi y) sin(pi z), c ~ N(0,1) (seed 0), E=1, nu=0.3, rank cap 64"),
@@ -106,37 +115,52 @@ def manufactured_field_cores(level, c):
     return cores
 
 
-def cpu_baseline(name, gpu_applies, budget_s=20.0):
-    """The oracle sweep timed on the host, on a bounded sample of the same solve.
+def cpu_baseline(name, opts, gpu_applies, full, budget_s=20.0):
+    """The oracle timed on the host cores; returns (baseline dict, oracle solution cores or None).
 
-    The oracle runs the same solve (same options) until about budget_s seconds
-    have passed (checked between half-sweeps); its time is scaled by the ratio of
-    the GPU solve's local operator applications to the oracle's.  The sampled
-    early half-sweeps run at lower ranks than the later ones, so the estimate
-    favours the oracle.
+    full: the oracle runs the whole solve with the timed solve's options (FP64) and its
+    solution becomes the accuracy reference.  Otherwise it runs until about budget_s
+    seconds have passed (checked between half-sweeps) and its time is scaled by the ratio
+    of the GPU solve's local operator applications to the oracle's; the sampled early
+    half-sweeps run at lower ranks than the later ones, so that estimate favours the oracle.
+    Assembly is not timed.
     """
     from threadpoolctl import threadpool_info
 
     from oracle import amen, qtt
 
     prob = problem_for(name)
-    o = WORKLOADS[name]["opts"]
     A = qtt.assemble_operator(prob)
     b = qtt.assemble_load(prob)
-    opt = amen.Options(tol=o["tol"], rank_cap=o["rank_cap"], max_sweeps=o["max_sweeps"], rho=o.get("rho", 4))
+    opt = amen.Options(tol=opts["tol"], rank_cap=opts["rank_cap"], max_sweeps=opts["max_sweeps"],
+                       rho=opts.get("rho", 4))
+    stop = None if full else (lambda s: time.perf_counter() - t0 > budget_s)
     t0 = time.perf_counter()
-    _, st = amen.amen_solve(A, b, opt, after_half_sweep=lambda s: time.perf_counter() - t0 > budget_s)
+    X, st = amen.amen_solve(A, b, opt, after_half_sweep=stop)
     t1 = time.perf_counter()
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    per_solve = (t1 - t0) * max(gpu_applies, 1) / max(st.applies, 1)
-    return {
+    whole = full or st.sweeps >= opts["max_sweeps"]
+    per_solve = (t1 - t0) if whole else (t1 - t0) * max(gpu_applies, 1) / max(st.applies, 1)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    sample = (f"the whole solve ({st.sweeps} half-sweeps, {st.applies} local operator applications) in "
+              f"{t1 - t0:.1f} s" if whole else
+              f"first {st.sweeps} of {opts['max_sweeps']} half-sweeps of the same solve in {t1 - t0:.1f} s "
+              f"({st.applies} local operator applications); scaled by the GPU solve's {gpu_applies} applications")
+    out = {
         "value": 1.0 / per_solve,
         "unit": "solves/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"first {st.sweeps} of {o['max_sweeps']} half-sweeps of the same solve in {t1 - t0:.1f} s "
-                  f"({st.applies} local operator applications); scaled by the GPU solve's {gpu_applies} applications",
+        "sample": sample + "; FP64 numpy/LAPACK, assembly not timed",
+        "cpu_model": cpu_model,
+        "nproc": os.cpu_count(),
     }
+    return out, (X if whole else None)
 
 
 def main():
@@ -144,12 +168,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube128", choices=sorted(WORKLOADS) + ["serving"])
-    ap.add_argument("--precision", type=int, default=0, choices=(0, 1, 2),
+    ap.add_argument("--workload", default="cube1024", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--precision", type=int, default=1, choices=(0, 1, 2),
                     help="0 FP64; 1 FP32 local applies; 2 BF16 local applies (both refined in FP64)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (and its accuracy reference)")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-accuracy", action="store_true", help="skip the high-rank reference solves")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the GPU's high-rank reference solves")
+    ap.add_argument("--no-fp64-solver", action="store_true", help="do not time the plain FP64 solve beside")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (to calibrate HBM byte counters)")
     ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
@@ -183,30 +208,42 @@ def main():
     ctx = tnfem.Context(0)
     P = tnfem.Problem(ctx, prob)
     info = P.info()
-    for i in range(args.warmup):
-        _, st, rc = P.solve(**opts)
-        print(f"warmup {i}: {st['seconds']:.3f} s sweeps={st['sweeps']} res={st['final_max_res']:.2e}",
-              file=sys.stderr, flush=True)
-    lat, stats = [], []
-    t_begin = time.perf_counter()
-    for i in range(args.steps):
-        t0 = time.perf_counter()
-        u, st, rc = P.solve(**opts)
-        lat.append(time.perf_counter() - t0)
-        stats.append(st)
-        print(f"step {i}: {lat[-1]:.3f} s sweeps={st['sweeps']} cg={st['cg_iters']} res={st['final_max_res']:.2e}",
-              file=sys.stderr, flush=True)
-    total = time.perf_counter() - t_begin
-    st = stats[-1]
+
+    def timed(o, label):
+        for i in range(args.warmup):
+            _, st, rc = P.solve(**o)
+            print(f"{label} warmup {i}: {st['seconds']:.3f} s sweeps={st['sweeps']} res={st['final_max_res']:.2e}",
+                  file=sys.stderr, flush=True)
+        lat, stats, u = [], [], None
+        t_begin = time.perf_counter()
+        for i in range(args.steps):
+            if u is not None:
+                u.close()
+            t0 = time.perf_counter()
+            u, st, rc = P.solve(**o)
+            lat.append(time.perf_counter() - t0)
+            stats.append(st)
+            print(f"{label} step {i}: {lat[-1]:.3f} s sweeps={st['sweeps']} cg={st['cg_iters']} "
+                  f"res={st['final_max_res']:.2e}", file=sys.stderr, flush=True)
+        return u, stats[-1], lat, time.perf_counter() - t_begin
+
+    u, st, lat, total = timed(opts, DTYPES[args.precision].split(" ")[0])
+    u64 = None
+    fp64 = None
+    if args.precision != 0 and not args.no_fp64_solver:
+        o64 = dict(opts, precision=0)
+        u64, st64, lat64, total64 = timed(o64, "f64")
+        fp64 = {"value": args.steps / total64, "unit": "solves/s", "ms_per_step": 1e3 * total64 / args.steps,
+                "latency_ms": {"p50": 1e3 * percentile(lat64, 0.5), "p99": 1e3 * percentile(lat64, 0.99)},
+                "cg_iters": st64["cg_iters"], "counted_flops": st64["flops"],
+                "speed_of_this_line_vs_fp64": (args.steps / total) / (args.steps / total64)}
     roof = None
     if not args.no_profile:
-        roof = roofline(P, opts)
-    accuracy = None
-    if not args.no_accuracy:
-        accuracy = accuracy_vs_reference(P, u, opts, args.workload, prob)
-    cpu = None
+        roof = roofline(P, opts, args.workload)
+    cpu, oracle_cores = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, st["local_applies"])
+        cpu, oracle_cores = cpu_baseline(args.workload, opts, st["local_applies"], full=wl.get("oracle_full", False))
+    accuracy = accuracy_block(P, u, u64, oracle_cores, opts, args.workload, prob, refs=not args.no_accuracy)
     value = args.steps / total
     out = {
         "metric": METRIC,
@@ -219,7 +256,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPES[args.precision],
+        "dtype": DTYPE_TAGS[args.precision],
         "data": "synthetic",
         "config": {
             "workload": wl["desc"] + ", " + DTYPES[args.precision],
@@ -228,13 +265,17 @@ def main():
             "rank_cap": opts["rank_cap"],
             "tol": opts["tol"],
             "max_sweeps": opts["max_sweeps"],
+            "rho": opts.get("rho", 4),
         },
         "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
         "solve": {
             "sweeps": st["sweeps"], "converged": bool(st["converged"]), "final_max_local_residual": st["final_max_res"],
             "cg_iters": st["cg_iters"], "max_rank": st["max_rank"], "counted_flops": st["flops"],
+            "low_precision_flops": st["low_precision_flops"], "refinements": st["refinements"],
+            "precision_fallbacks": st["precision_fallbacks"],
             "median_latency_s": statistics.median(lat),
         },
+        "fp64_solver": fp64,
         "accuracy": accuracy,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -242,7 +283,24 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def roofline(P, opts):
+def traffic_from_summary(workload, precision):
+    """HBM bytes per fused-apply launch from the committed counter summary of this workload
+    and precision (None when there is none)."""
+    name = TRAFFIC_SUMMARIES.get((workload, precision))
+    if not name:
+        return None, None
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as f:
+            for ln in f:
+                if ln.startswith("traffic_bytes_per_launch:"):
+                    return float(ln.split(":", 1)[1]), "profiles/" + name
+    except OSError:
+        pass
+    return None, None
+
+
+def roofline(P, opts, workload):
     """Live roofline of the dominant contraction kernel, the fused local apply (row a2):
     one more solve with start/stop events stamped by every contraction dispatch.
     achieved = algorithmic flops of the launches that did work (nonzero-term counts at the
@@ -259,7 +317,8 @@ def roofline(P, opts):
     kname = " / ".join(f"{k}<{prec}>" for k in kinds)
     if len(kinds) > 1:
         kname += " (by the ranks of each core step)"
-    what = {0: "FP64 MFMA", 1: "FP32 MFMA", 2: "BF16 MFMA, FP32 accumulate"}[prec]
+    what = {0: "FP64 MFMA", 1: "FP32 MFMA, FP32 accumulate", 2: "BF16 MFMA, FP32 accumulate"}[prec]
+    traffic, src = traffic_from_summary(workload, prec)
     return {
         "bound": "mfma",
         "kernel": f"{kname} (fused local operator apply, {what})",
@@ -267,8 +326,9 @@ def roofline(P, opts):
         "peak": PEAKS[prec],
         "unit": "TFLOP/s",
         "frac": achieved / PEAKS[prec],
-        "traffic": FUSED_APPLY_TRAFFIC_BYTES if (prec == 0 and cap <= 32 and P.info()["ncores"] == 8) else None,
-        "traffic_unit": "bytes per launch (PMC, copy-calibrated)",
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "traffic_source": src,
         "launches_per_solve": nl,
         "avg_launch_us": 1e3 * ms / max(nl, 1),
         "flops_per_launch": fl / max(nl, 1),
@@ -280,45 +340,59 @@ def roofline(P, opts):
     }
 
 
-def accuracy_vs_reference(P, u, opts, name, prob):
-    """Relative displacement error of the timed solve, computed by the library in TT format
-    (no densification), against FP64 reference solves of the same problem with larger rank
+def accuracy_block(P, u, u64, oracle_cores, opts, name, prob, refs=True):
+    """Relative displacement errors of the timed solve, computed by the library in TT format
+    (no densification): against the oracle's FP64 solve of the same problem with the same
+    options (when the oracle ran the whole solve), against FP64 GPU solves with larger rank
     caps / tighter tolerances (their mutual difference bounds how far the last one is from
-    converged); for low precision also against the FP64 solve with the same options; for
-    the manufactured load also against the closed-form field (which adds the O(h^2)
+    converged), against the FP64 GPU solve with the same options (low precision), and for
+    the manufactured load against the closed-form field (which adds the O(h^2)
     discretisation error)."""
     from paper_2501_12151_amd import tnfem
 
     def label(o):
         return f"cap {o['rank_cap']} tol {o['tol']:g}" + (f" rho {o['rho']}" if "rho" in o else "")
 
-    refs = []
-    for ro in WORKLOADS[name]["refs"]:
-        r, rst, _ = P.solve(**ro)
-        refs.append((r, rst, ro))
-        print(f"reference {label(ro)}: {rst['seconds']:.2f} s, max local residual {rst['final_max_res']:.2e}",
-              file=sys.stderr, flush=True)
-    top, tst, ro = refs[-1]
-    err = u.rel_diff(top)
-    out = {
-        "rel_error_vs_reference": err,
-        "reference": f"same problem, FP64, {label(ro)}, {ro['max_sweeps']} half-sweeps "
-                     f"(max local residual {tst['final_max_res']:.2e}, max rank {tst['max_rank']})",
-        "target": 1e-6,
-        "meets_target": bool(err <= 1e-6),
-        "rank_cap_of_timed_solve": opts["rank_cap"],
-    }
-    if len(refs) > 1:
-        out["reference_gap"] = {"between": [label(o) for _, _, o in refs],
-                                "rel_diff": refs[0][0].rel_diff(top)}
-    if opts.get("precision", 0):
-        o64 = dict(opts, precision=0)
-        u64, _, _ = P.solve(**o64)
+    out = {"target": 1e-6, "rank_cap_of_timed_solve": opts["rank_cap"]}
+    judged = None
+    if oracle_cores is not None:
+        ref = tnfem.TT.from_cores(oracle_cores)
+        err = u.rel_diff(ref)
+        out["rel_error_vs_oracle"] = err
+        out["oracle"] = (f"the oracle's FP64 AMEn solve of the same problem on the host, {label(opts)}, "
+                         f"{opts['max_sweeps']} half-sweeps")
+        if u64 is not None:
+            out["fp64_solver_rel_error_vs_oracle"] = u64.rel_diff(ref)
+        judged = ("oracle", err)
+    top = None
+    if refs:
+        rs = []
+        for ro in WORKLOADS[name]["refs"]:
+            r, rst, _ = P.solve(**ro)
+            rs.append((r, rst, ro))
+            print(f"reference {label(ro)}: {rst['seconds']:.2f} s, max local residual {rst['final_max_res']:.2e}",
+                  file=sys.stderr, flush=True)
+        top, tst, ro = rs[-1]
+        err = u.rel_diff(top)
+        out["rel_error_vs_fp64_reference"] = err
+        out["fp64_reference"] = (f"same problem, FP64 on the GPU, {label(ro)}, {ro['max_sweeps']} half-sweeps "
+                                 f"(max local residual {tst['final_max_res']:.2e}, max rank {tst['max_rank']})")
+        if len(rs) > 1:
+            out["fp64_reference_gap"] = {"between": [label(o) for _, _, o in rs], "rel_diff": rs[0][0].rel_diff(top)}
+        if oracle_cores is not None:
+            out["oracle_vs_fp64_reference"] = tnfem.TT.from_cores(oracle_cores).rel_diff(top)
+        if judged is None:
+            judged = ("fp64_reference", err)
+    if u64 is not None:
         out["rel_diff_vs_fp64_same_options"] = u.rel_diff(u64)
     if "manufactured_c" in prob:
         exact = tnfem.TT.from_cores(manufactured_field_cores(prob["level"], prob["manufactured_c"]))
         out["rel_error_vs_closed_form"] = u.rel_diff(exact)
-        out["reference_vs_closed_form"] = top.rel_diff(exact)
+        if top is not None:
+            out["fp64_reference_vs_closed_form"] = top.rel_diff(exact)
+    if judged is not None:
+        out["meets_target"] = bool(judged[1] <= 1e-6)
+        out["judged_against"] = judged[0]
     return out
 
 

@@ -155,6 +155,7 @@ typedef struct {
                              precision of the solve) */
   double apply_kernel_flops;
   long long apply_kernel_launches;
+  int peak_rank;          /* largest TT rank of the iterate at any bond during the solve */
 } tnfem_solve_stats;
 
 /* ---------------------------------------------------------------- context */

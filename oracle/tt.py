@@ -87,7 +87,7 @@ def tt_orthogonalize_right(cores):
         r, n, r2 = cores[k].shape
         Q, R = np.linalg.qr(cores[k].reshape(r, n * r2).T)
         cores[k] = Q.T.reshape(-1, n, r2)
-        cores[k - 1] = np.einsum("anb,cb->anc", cores[k - 1], R)
+        cores[k - 1] = np.tensordot(cores[k - 1], R, axes=([2], [1]))  # [a, n, c] = sum_b core[a, n, b] R[c, b]
     return cores
 
 
@@ -102,7 +102,7 @@ def tt_round(cores, eps=1e-14, rmax=None):
         U, s, Vt = np.linalg.svd(cores[k].reshape(r * n, r2), full_matrices=False)
         rk = _trunc_rank(s, delta, rmax)
         cores[k] = U[:, :rk].reshape(r, n, rk)
-        cores[k + 1] = np.einsum("ab,bnc->anc", s[:rk, None] * Vt[:rk], cores[k + 1])
+        cores[k + 1] = np.tensordot(s[:rk, None] * Vt[:rk], cores[k + 1], axes=([1], [0]))
     return cores
 
 

@@ -785,6 +785,7 @@ struct Sweep {
   double fl_low = 0.0;
   long long cg_iters = 0, applies = 0, refinements = 0, fallbacks = 0;
   double max_res = 0.0;
+  int peak_rank = 0;  // largest rank of u at any bond during the solve
   int nan_seen = 0;
   int verbose = 0;  // 2: one line per local solve on stderr
   std::vector<int> cg_last;  // CG iterations of the last local solve at each core (chain order)
@@ -906,6 +907,7 @@ struct Sweep {
       qr_step(Z, zr, k, zspare);
       update_envs(k);
     }
+    peak_rank = std::max(peak_rank, *std::max_element(xr.begin(), xr.end()));
   }
 
   // Returns the local residual res_k before the solve.
@@ -1220,6 +1222,7 @@ struct Sweep {
     gemm_plain(rnew, cols, Nn, W.Wm, Nn, false, X[k + 1], cols, xspare, cols, st, &fl);
     std::swap(X[k + 1], xspare);
     xr[k + 1] = rnew;
+    peak_rank = std::max(peak_rank, rnew);
     zr[k + 1] = s.cz;
     update_envs(k);
   }
@@ -1549,6 +1552,7 @@ static void fill_stats(const Sweep& sw, int sweeps, int converged, double last, 
   stats.flops = sw.fl.total;
   stats.seconds = seconds;
   stats.max_rank = *std::max_element(sw.xr.begin(), sw.xr.end());
+  stats.peak_rank = std::max(sw.peak_rank, stats.max_rank);
   stats.refinements = sw.refinements;
   stats.low_precision_flops = sw.fl_low;
   stats.precision_fallbacks = sw.fallbacks;

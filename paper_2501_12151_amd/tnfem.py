@@ -69,7 +69,7 @@ class SolveStats(C.Structure):
         ("contraction_ms", C.c_double),
         ("contraction_flops", C.c_double), ("contraction_launches", C.c_longlong),
         ("apply_kernel_ms", C.c_double), ("apply_kernel_flops", C.c_double),
-        ("apply_kernel_launches", C.c_longlong),
+        ("apply_kernel_launches", C.c_longlong), ("peak_rank", C.c_int),
     ]
 
     def as_dict(self):

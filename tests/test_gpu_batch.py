@@ -4,6 +4,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+from oracle import amen as oamen, fem, qtt, tt  # noqa: E402
 from paper_2501_12151_amd import tnfem  # noqa: E402
 
 
@@ -70,4 +71,37 @@ def test_batch_rejects_mixed_levels_and_low_precision():
         tnfem.solve_batch([a], rank_cap=8, max_sweeps=2, precision=1)
     a.close()
     b.close()
+    ctx.close()
+
+
+ORACLE_OPTS = dict(rank_cap=64, tol=1e-10, max_sweeps=30)
+
+
+def _oracle_and_direct(prob, opts):
+    A, b, _, _ = fem.build_system(prob)
+    u = qtt.to_qtt_order(fem.direct_solve(A, b), prob["dim"], prob["level"])
+    X, ost = oamen.amen_solve(qtt.assemble_operator(prob), qtt.assemble_load(prob),
+                              oamen.Options(tol=opts["tol"], rank_cap=opts["rank_cap"], max_sweeps=opts["max_sweeps"]))
+    return u, tt.tt_full(X).reshape(-1), ost
+
+
+@pytest.mark.parametrize("which,level", [("3d", 3), ("2d", 5)])
+def test_batch_matches_oracle_and_direct_solve(which, level):
+    """Every problem of a lockstep batch reaches the oracle sweep's and the direct solve's
+    solution (unbinding cap, tight tolerance), with the oracle's half-sweep count."""
+    descs = _problems_3d(level) if which == "3d" else _problems_2d(level)
+    ctx = tnfem.Context(0)
+    probs = [tnfem.Problem(ctx, d) for d in descs]
+    batch = tnfem.solve_batch(probs, **ORACLE_OPTS)
+    for i, (d, (ub, sb, rb)) in enumerate(zip(descs, batch)):
+        u, uo, ost = _oracle_and_direct(d, ORACLE_OPTS)
+        ug = tt.tt_full(ub.cores).reshape(-1)
+        e_d = np.linalg.norm(ug - u) / np.linalg.norm(u)
+        e_o = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+        print(f"  problem {i}: sweeps {sb['sweeps']} / oracle {ost.sweeps}, vs direct {e_d:.2e}, vs oracle {e_o:.2e}",
+              flush=True)
+        assert rb == tnfem.OK and sb["sweeps"] == ost.sweeps
+        assert e_d <= 1e-8 and e_o <= 1e-8
+    for p in probs:
+        p.close()
     ctx.close()

@@ -6,7 +6,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-from oracle import tt  # noqa: E402
+from oracle import amen as oamen, fem, qtt, tt  # noqa: E402
 from paper_2501_12151_amd import tnfem, workloads  # noqa: E402
 
 MIX = [
@@ -119,3 +119,37 @@ def test_server_batches_one_bucket_and_results_equal_alone():
             for x, y in zip(got, a):
                 assert np.array_equal(x, y)
             assert o[3] > 0
+
+
+def test_served_results_match_oracle_and_direct_solve():
+    """Requests of different dimensions, levels and materials served together (overlapping
+    slots, lockstep batches of a bucket) reach the oracle sweep's and the direct solve's
+    solution (unbinding cap, tight tolerance)."""
+    opts = dict(rank_cap=64, tol=1e-10, max_sweeps=30)
+    reqs = [
+        dict(dim=2, level=5, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])]),
+        dict(dim=2, level=5, E=4.0, nu=0.2, clamp=[(0, 0)], tractions=[(0, 1, [-0.3, 0.8])]),
+        dict(dim=3, level=3, E=2.0, nu=0.25, clamp=[(0, 0)], tractions=[(0, 1, [0.3, -1.0, 0.5])]),
+        dict(dim=3, level=3, E=0.5, nu=0.4, clamp=[(0, 0)], body_force=[0.0, 0.0, -1.0]),
+        dict(dim=2, level=4, E=1.0, nu=0.35, plane_stress=True, clamp=[(1, 0)], body_force=[0.0, -1.0]),
+    ]
+    srv = tnfem.Server(0, slots=3)
+    tickets = [srv.submit(p, **opts) for p in reqs]
+    results = [srv.poll(t) for t in tickets]
+    info = srv.info()
+    srv.close()
+    assert info["completed"] == len(reqs)
+    for i, (prob, res) in enumerate(zip(reqs, results)):
+        A, b, _, _ = fem.build_system(prob)
+        u = qtt.to_qtt_order(fem.direct_solve(A, b), prob["dim"], prob["level"])
+        X, ost = oamen.amen_solve(qtt.assemble_operator(prob), qtt.assemble_load(prob),
+                                  oamen.Options(tol=opts["tol"], rank_cap=opts["rank_cap"],
+                                                max_sweeps=opts["max_sweeps"]))
+        ug = tt.tt_full(res[0].cores).reshape(-1)
+        uo = tt.tt_full(X).reshape(-1)
+        e_d = np.linalg.norm(ug - u) / np.linalg.norm(u)
+        e_o = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+        print(f"  request {i}: sweeps {res[1]['sweeps']} / oracle {ost.sweeps}, vs direct {e_d:.2e}, "
+              f"vs oracle {e_o:.2e}", flush=True)
+        assert res[2] == tnfem.OK and res[1]["sweeps"] == ost.sweeps
+        assert e_d <= 1e-8 and e_o <= 1e-8
