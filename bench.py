@@ -168,13 +168,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube1024", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--workload", default="cube1024", choices=sorted(WORKLOADS) + ["serving", "cantilever"])
+    ap.add_argument("--levels", default="6,8,10,12,14,16,18,20", help="cantilever: grid levels")
     ap.add_argument("--precision", type=int, default=1, choices=(0, 1, 2),
                     help="0 FP64; 1 FP32 local applies; 2 BF16 local applies (both refined in FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (and its accuracy reference)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the GPU's high-rank reference solves")
     ap.add_argument("--no-fp64-solver", action="store_true", help="do not time the plain FP64 solve beside")
+    ap.add_argument("--mfma-calibration", type=int, default=0, metavar="N",
+                    help="only run 10 FP64 and 10 FP32 N x N matrix products (to calibrate MFMA counters)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (to calibrate HBM byte counters)")
     ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
@@ -184,6 +187,21 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is not sharded across GPUs.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.mfma_calibration:
+        import torch
+
+        n = args.mfma_calibration
+        for dt in (torch.float64, torch.float32):
+            a = torch.ones((n, n), dtype=dt, device="cuda")
+            b = torch.ones((n, n), dtype=dt, device="cuda")
+            for _ in range(10):
+                c = a @ b
+            torch.cuda.synchronize()
+            del c
+        print(json.dumps({"mfma_calibration_flops_per_matmul": 2 * n ** 3, "matmuls_per_dtype": 10,
+                          "dtypes": ["f64", "f32"]}))
+        return
 
     if args.copy_calibration:
         import torch
@@ -201,6 +219,9 @@ def main():
 
     if args.workload == "serving":
         serving(args)
+        return
+    if args.workload == "cantilever":
+        cantilever(args)
         return
     wl = WORKLOADS[args.workload]
     prob = problem_for(args.workload)
@@ -300,6 +321,22 @@ def traffic_from_summary(workload, precision):
     return None, None
 
 
+def mfma_busy_from_summary(workload, precision):
+    """MFMA busy % per contraction kernel from the committed counter summary (None if absent)."""
+    key = f"mfma_busy_pct[{workload},{precision}]:"
+    path = os.path.join(ROOT, "profiles", "mfma_utilisation_contractions.md")
+    try:
+        with open(path) as f:
+            for ln in f:
+                if ln.startswith(key):
+                    vals = dict(tok.split("=") for tok in ln[len(key):].split())
+                    return {"busy_pct": {k: float(v) for k, v in vals.items()},
+                            "source": "profiles/mfma_utilisation_contractions.md"}
+    except OSError:
+        pass
+    return None
+
+
 def roofline(P, opts, workload):
     """Live roofline of the dominant contraction kernel, the fused local apply (row a2):
     one more solve with start/stop events stamped by every contraction dispatch.
@@ -329,6 +366,7 @@ def roofline(P, opts, workload):
         "traffic": traffic,
         "traffic_unit": "bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "traffic_source": src,
+        "mfma_counters": mfma_busy_from_summary(workload, prec),
         "launches_per_solve": nl,
         "avg_launch_us": 1e3 * ms / max(nl, 1),
         "flops_per_launch": fl / max(nl, 1),
@@ -394,6 +432,91 @@ def accuracy_block(P, u, u64, oracle_cores, opts, name, prob, refs=True):
         out["meets_target"] = bool(judged[1] <= 1e-6)
         out["judged_against"] = judged[0]
     return out
+
+
+CANTILEVER_OPTS = dict(rank_cap=64, tol=1e-10, max_sweeps=40, rho=8)
+
+
+def cantilever_tip(u, level):
+    """Largest |u_y| over 257 nodes of the free end x = L_x (the tip carries the largest
+    deflection), read from the TT by point evaluation."""
+    import numpy as np
+
+    n = 2 ** level
+    iy = np.unique(np.linspace(0, n - 1, 257).astype(np.int64))
+    idx = np.zeros((iy.size, level + 1), dtype=np.int64)
+    for l in range(level):
+        idx[:, l] = (((n - 1) >> (level - 1 - l)) & 1) * 2 + ((iy >> (level - 1 - l)) & 1)
+    idx[:, level] = 1
+    return float(np.abs(u.eval(idx)).max())
+
+
+def cantilever(args):
+    """The experiment of Sec. 6: the aluminium cantilever at increasing grid levels; per level
+    the solve time, the tip deflection against the Euler-Bernoulli value 3 rho g L_x^4 /
+    (2 E L_y^2), the strain energy b.u / 2, and the storage of u, b and the operator in TT
+    format against the dense vector / sparse matrix they replace."""
+    from paper_2501_12151_amd import tnfem, workloads
+
+    rho, g = workloads.CANTILEVER_RHO, workloads.CANTILEVER_G
+    levels = [int(x) for x in args.levels.split(",")]
+    ctx = tnfem.Context(0)
+    rows = []
+    for d in levels:
+        prob = workloads.cantilever(d)
+        Lx, Ly = prob["extent"]
+        ymax = 3 * rho * g * Lx ** 4 / (2 * prob["E"] * Ly ** 2)
+        P = tnfem.Problem(ctx, prob)
+        b = tnfem.TT.from_cores(tnfem.export_load(prob))
+        Ac = tnfem.export_operator(prob)
+        for _ in range(args.warmup):
+            P.solve(**CANTILEVER_OPTS)[0].close()
+        lat, u, st = [], None, None
+        for _ in range(args.steps):
+            if u is not None:
+                u.close()
+            t0 = time.perf_counter()
+            u, st, rc = P.solve(**CANTILEVER_OPTS)
+            lat.append(time.perf_counter() - t0)
+        tip = cantilever_tip(u, d)
+        ndof = 2 * 4 ** d
+        row = {
+            "level": d, "dofs": ndof, "solve_ms_p50": 1e3 * percentile(lat, 0.5), "sweeps": st["sweeps"],
+            "converged": bool(st["converged"]), "max_rank": st["max_rank"],
+            "tip_deflection_m": tip, "euler_bernoulli_m": ymax, "tip_rel_error": abs(tip - ymax) / ymax,
+            "strain_energy_J_per_m": 0.5 * b.dot(u),
+            "tt_bytes": {"u": 8 * sum(c.size for c in u.cores), "b": 8 * sum(c.size for c in b.cores),
+                         "operator_cores": 8 * sum(c.size for c in Ac),
+                         "operator_nonzeros": int(sum(int((c != 0).sum()) for c in Ac))},
+            "dense_bytes": {"u": 8 * ndof, "b": 8 * ndof, "sparse_K_csr": 12 * 18 * ndof},
+        }
+        print(f"cantilever level {d}: {row['solve_ms_p50']:.1f} ms, tip {tip:.5e} m ({tip / ymax:.5f} of "
+              f"Euler-Bernoulli), energy {row['strain_energy_J_per_m']:.5e}", file=sys.stderr, flush=True)
+        rows.append(row)
+        u.close()
+        b.close()
+        P.close()
+    ctx.close()
+    top = rows[-1]
+    out = {
+        "metric": METRIC,
+        "value": 1e3 / top["solve_ms_p50"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": top["solve_ms_p50"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"aluminium cantilever 20 m x 1 m, plane stress, E = 68 GPa, nu = 0.33, self-weight "
+                               f"rho g = {rho * g:g} N/m^3, x = 0 clamped; levels {levels} (value: finest level)",
+                   "solve_options": CANTILEVER_OPTS},
+        "levels": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 SERVING_REF = dict(rank_cap=96, tol=1e-9, max_sweeps=30)

@@ -253,6 +253,10 @@ int tnfem_tt_eval(const tnfem_tt* t, const int64_t* idx, size_t n, double* out);
 int tnfem_tt_destroy(tnfem_tt* t);
 /* Frobenius norm of the TT (host FP64: QR of each unfolding, R carried forward). */
 int tnfem_tt_norm(const tnfem_tt* t, double* out);
+/* Euclidean inner product <a, b> of two TTs of equal mode sizes (host FP64, contracted core
+ * by core from the left).  With the load b of a problem and its solution u, the discrete
+ * strain energy is <b, u> / 2 (A u = b, u zero on clamped dofs). */
+int tnfem_tt_dot(const tnfem_tt* a, const tnfem_tt* b, double* out);
 /* ||a - b|| / ||b|| (||a - b|| if b = 0) for TTs of equal mode sizes, in TT format: the
  * difference is the block TT of ranks r_a + r_b, whose norm is taken as above, so nearly
  * equal TTs do not cancel.  Host FP64; cost O(sum_k n_k (r_a + r_b)^3). */

@@ -396,6 +396,38 @@ int tnfem_tt_rel_diff(const tnfem_tt* a, const tnfem_tt* b, double* out) {
   });
 }
 
+int tnfem_tt_dot(const tnfem_tt* a, const tnfem_tt* b, double* out) {
+  return guarded([&] {
+    if (!a || !b || !out) fail(TNFEM_EINVAL, "NULL argument");
+    const auto& A = a->t;
+    const auto& B = b->t;
+    const int K = (int)A.modes.size();
+    if (K < 1 || B.modes != A.modes) fail(TNFEM_EINVAL, "TTs have different mode sizes");
+    // left-to-right: E[x][y] = sum over the cores so far of A[.. x] B[.. y]
+    std::vector<double> E(1, 1.0);
+    for (int k = 0; k < K; ++k) {
+      const int n = A.modes[k], ral = A.ranks[k], rar = A.ranks[k + 1], rbl = B.ranks[k], rbr = B.ranks[k + 1];
+      // T[x][i][v] = sum_y E[x][y] B[y][i][v]
+      std::vector<double> T((size_t)ral * n * rbr, 0.0);
+      tnfem::hostla::gemm(ral, n * rbr, rbl, E.data(), B.cores[k].data(), T.data());
+      std::vector<double> En((size_t)rar * rbr, 0.0);
+      for (int x = 0; x < ral; ++x)
+        for (int i = 0; i < n; ++i) {
+          const double* arow = &A.cores[k][((size_t)x * n + i) * rar];
+          const double* trow = &T[((size_t)x * n + i) * rbr];
+          for (int u = 0; u < rar; ++u) {
+            const double av = arow[u];
+            if (av == 0.0) continue;
+            for (int v = 0; v < rbr; ++v) En[(size_t)u * rbr + v] += av * trow[v];
+          }
+        }
+      E.swap(En);
+    }
+    *out = E[0];
+    return TNFEM_OK;
+  });
+}
+
 int tnfem_tt_destroy(tnfem_tt* t) {
   delete t;
   return TNFEM_OK;

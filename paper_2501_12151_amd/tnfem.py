@@ -109,6 +109,7 @@ _sig = {
     "tnfem_tt_destroy": (C.c_int, [_vp]),
     "tnfem_tt_norm": (C.c_int, [_vp, _dp]),
     "tnfem_tt_rel_diff": (C.c_int, [_vp, _vp, _dp]),
+    "tnfem_tt_dot": (C.c_int, [_vp, _vp, _dp]),
     "tnfem_export_operator": (C.c_int, [C.POINTER(ProblemDesc), _ip, _ip, _ip, _dp, C.c_size_t, C.POINTER(C.c_size_t)]),
     "tnfem_export_load": (C.c_int, [C.POINTER(ProblemDesc), _ip, _ip, _ip, _dp, C.c_size_t, C.POINTER(C.c_size_t)]),
     "tnfem_prim_local_apply": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
@@ -291,6 +292,12 @@ class TT:
         """||self - ref|| / ||ref||, computed by the library in TT format."""
         out = C.c_double()
         _check(_lib.tnfem_tt_rel_diff(self._h, ref._h, C.byref(out)))
+        return out.value
+
+    def dot(self, other):
+        """<self, other>, computed by the library in TT format."""
+        out = C.c_double()
+        _check(_lib.tnfem_tt_dot(self._h, other._h, C.byref(out)))
         return out.value
 
     def eval(self, idx):

@@ -38,6 +38,18 @@ def layered_cube(level: int = 9):
                 layered_E=(2, E.tolist()))
 
 
+# aluminium cantilever of Sec. 6: density (kg/m^3), gravity (m/s^2)
+CANTILEVER_RHO = 2700.0
+CANTILEVER_G = 9.81
+
+
+def cantilever(level: int = 8):
+    """2D plane-stress cantilever of Sec. 6: 20 m x 1 m aluminium (E = 68 GPa, nu = 0.33),
+    edge x = 0 clamped, loaded by its own weight f = (0, -rho g), 2^level nodes per axis."""
+    return dict(dim=2, level=level, E=68e9, nu=0.33, plane_stress=True, extent=[20.0, 1.0], clamp=[(0, 0)],
+                body_force=[0.0, -CANTILEVER_RHO * CANTILEVER_G])
+
+
 def serving_stream(n: int = 256, seed: int = 0, rate: float = 1.0):
     """Requests: (arrival time, problem dict, rank cap).  2D/3D with p = 1/2, level
     uniform in 6..10, nu ~ U[0.2, 0.45], E log-uniform in [0.1, 10], face x = 0 clamped,
