@@ -100,6 +100,15 @@ typedef struct {
    * no nodal load.  Invalid ranks fail with TNFEM_EINVAL. */
   const int* f0_ranks;
   const double* f0_cores;
+  /* Optional anisotropic material (the non-isotropic materials of Sec. 7): the constant
+   * stiffness in Voigt notation, sigma_V = C eps_V with engineering shear strains, order
+   * (xx, yy, xy) in 2D (the leading 3 x 3 block is read) and (xx, yy, zz, yz, xz, xy) in
+   * 3D.  It replaces the isotropic law built from E and nu in the element integrals
+   * (layer_E / E still scales it per element layer); it must be symmetric positive
+   * definite, and plane_stress must be 0 (a 2D C already states the plane assumption).
+   * The clamped dofs get the diagonal max_i C_ii h^(D-2) (normal components i). */
+  int has_stiffness;
+  double stiffness[6][6];
 } tnfem_problem_desc;
 
 /*

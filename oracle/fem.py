@@ -43,6 +43,36 @@ def lame(E: float, nu: float, plane_stress: bool = False):
     return lam, mu
 
 
+def voigt_to_tensor(Cv, D: int) -> np.ndarray:
+    """Stiffness tensor C[i, j, k, l] (sigma_ij = sum_kl C_ijkl eps_kl) from a Voigt matrix
+    with engineering shear strains: order (xx, yy, xy) in 2D, (xx, yy, zz, yz, xz, xy) in 3D.
+    With the engineering shear, C_ijkl is the Voigt entry of the pairs (ij) and (kl)."""
+    Cv = np.asarray(Cv, dtype=np.float64)
+    pairs = {2: {(0, 0): 0, (1, 1): 1, (0, 1): 2},
+             3: {(0, 0): 0, (1, 1): 1, (2, 2): 2, (1, 2): 3, (0, 2): 4, (0, 1): 5}}[D]
+    idx = lambda i, j: pairs[(min(i, j), max(i, j))]  # noqa: E731
+    C = np.zeros((D, D, D, D))
+    for i, j, k, l in itertools.product(range(D), repeat=4):
+        C[i, j, k, l] = Cv[idx(i, j), idx(k, l)]
+    return C
+
+
+def isotropic_tensor(lam: float, mu: float, D: int) -> np.ndarray:
+    """C_ijkl = lambda d_ij d_kl + mu (d_ik d_jl + d_il d_jk) (Sec. 2)."""
+    e = np.eye(D)
+    return (lam * np.einsum("ij,kl->ijkl", e, e) + mu * (np.einsum("ik,jl->ijkl", e, e)
+                                                          + np.einsum("il,jk->ijkl", e, e)))
+
+
+def material_tensor(problem: dict) -> np.ndarray:
+    """The problem's stiffness tensor: its Voigt matrix if given, else the isotropic law."""
+    D = problem["dim"]
+    if problem.get("stiffness_voigt") is not None:
+        return voigt_to_tensor(problem["stiffness_voigt"], D)
+    lam, mu = lame(problem["E"], problem["nu"], problem.get("plane_stress", False))
+    return isotropic_tensor(lam, mu, D)
+
+
 def corner_bits(D: int) -> np.ndarray:
     """Corners of the reference element [-1, 1]^D as 0/1 bits, x most significant."""
     return np.array(list(itertools.product((0, 1), repeat=D)), dtype=np.int64)
@@ -72,7 +102,7 @@ def ref_shape(D: int, xi: np.ndarray):
     return phi, dphi
 
 
-def element_matrices(D: int, h, lam: float, mu: float):
+def element_matrices(D: int, h, lam: float, mu: float, C=None):
     """Element stiffness and (scalar) mass matrices of one rectangular Q1 element.
 
     The element map Phi(xi) = x0 + (xi + 1) h / 2 has constant Jacobian
@@ -80,7 +110,8 @@ def element_matrices(D: int, h, lam: float, mu: float):
     and the integrand is weighted by |det J| (eq. elassembly).  The stiffness
     entry for test function e_a phi_p and trial function e_b phi_q is the
     integral of sigma(e_b phi_q) : eps(e_a phi_p) with
-    sigma = lambda tr(eps) I + 2 mu eps (Sec. 2).
+    sigma = lambda tr(eps) I + 2 mu eps (Sec. 2), or sigma_ij = sum_kl C_ijkl eps_kl
+    when a stiffness tensor C is given (anisotropic material).
 
     Returns Ke[(a, p), (b, q)] of size (D 2^D)^2 with index a * 2^D + p, and the
     scalar mass Me[p, q] (the vector mass is block diagonal in components).
@@ -108,7 +139,7 @@ def element_matrices(D: int, h, lam: float, mu: float):
         for b in range(D):
             for q in range(nc):
                 e = eps[b, q]
-                sig = lam * np.trace(e) * eye + 2.0 * mu * e
+                sig = lam * np.trace(e) * eye + 2.0 * mu * e if C is None else np.einsum("ijkl,kl->ij", C, e)
                 for a in range(D):
                     for p in range(nc):
                         Ke[a * nc + p, b * nc + q] += w * detJ * np.sum(sig * eps[a, p])
@@ -147,7 +178,7 @@ class Grid:
         return self.node_index(elems[:, None, :] + bits[None, :, :]), elems
 
 
-def assemble(grid: Grid, lam: float, mu: float, elem_weight=None):
+def assemble(grid: Grid, lam: float, mu: float, elem_weight=None, C=None):
     """Global stiffness K and scalar mass M by element-by-element assembly (Sec. 3).
 
     elem_weight, if given, is an array over element index tuples (shape
@@ -156,7 +187,7 @@ def assemble(grid: Grid, lam: float, mu: float, elem_weight=None):
     natural order, M over the n^D nodes.
     """
     D = grid.D
-    Ke, Me = element_matrices(D, grid.h, lam, mu)
+    Ke, Me = element_matrices(D, grid.h, lam, mu, C)
     enodes, elems = grid.element_nodes()
     ne_tot = len(elems)
     if elem_weight is None:
@@ -254,9 +285,11 @@ def apply_dirichlet(K, b, mask, alpha: float):
     return (P @ K @ P + alpha * Q).tocsr(), b * mask
 
 
-def bc_alpha(grid: Grid, lam: float, mu: float) -> float:
-    """Diagonal value given to clamped dofs: (lambda + 2 mu) h^(D-2), h along x."""
-    return (lam + 2.0 * mu) * grid.h[0] ** (grid.D - 2)
+def bc_alpha(grid: Grid, lam: float, mu: float, C=None) -> float:
+    """Diagonal value given to clamped dofs: max_i C_iiii h^(D-2), h along x (lambda + 2 mu
+    for an isotropic material)."""
+    cmax = lam + 2.0 * mu if C is None else max(C[i, i, i, i] for i in range(grid.D))
+    return cmax * grid.h[0] ** (grid.D - 2)
 
 
 def manufactured_u(x, c):
@@ -299,7 +332,9 @@ def build_system(problem: dict):
     body_force: constant vector (opt), manufactured_c: vector (opt; load
     f = M f0 with f0 the closed-form manufactured force at the nodes),
     f_nodal_tt: TT cores of nodal force values f0 (opt; load M f0, Alg. 2 / Sec. 5.3),
-    layered_E: (axis, values per element along that axis) (opt).
+    layered_E: (axis, values per element along that axis) (opt),
+    stiffness_voigt: constant anisotropic stiffness, Voigt matrix (opt; replaces E, nu in
+    the element integrals, layered_E / E still scales it).
     """
     D, d = problem["dim"], problem["level"]
     grid = Grid(D, d, problem.get("extent"))
@@ -311,7 +346,8 @@ def build_system(problem: dict):
         shape = [1] * D
         shape[axis] = grid.n - 1
         weight = np.broadcast_to(vals.reshape(shape), (grid.n - 1,) * D)
-    K, M = assemble(grid, lam, mu, weight)
+    C = voigt_to_tensor(problem["stiffness_voigt"], D) if problem.get("stiffness_voigt") is not None else None
+    K, M = assemble(grid, lam, mu, weight, C)
     b = np.zeros(grid.n_dofs)
     if problem.get("body_force") is not None:
         f0 = np.repeat(np.asarray(problem["body_force"], dtype=np.float64)[:D, None], grid.n_nodes, axis=1)
@@ -325,7 +361,7 @@ def build_system(problem: dict):
     for axis, side, t in problem.get("tractions", []):
         b += traction_load(grid, axis, side, t)
     mask = clamp_mask(grid, problem.get("clamp", []))
-    alpha = bc_alpha(grid, lam, mu)
+    alpha = bc_alpha(grid, lam, mu, C)
     A, bb = apply_dirichlet(K, b, mask, alpha)
     return A, bb, grid, dict(K=K, M=M, b_raw=b, mask=mask, lam=lam, mu=mu, alpha=alpha)
 

@@ -184,8 +184,9 @@ def assemble_operator(problem: dict, eps=1e-14, component_first=False):
 
     A_bc = sum over atoms of C_atom (x) D_atom where, for each ordered axis pair
     (a, b), D_ab is the Kronecker atom described in the module docstring and
-    C_ab = lambda E_ab + mu E_ba + delta_ab mu I collects every place D_ab occurs
-    in K; the clamped dofs add alpha I (x) (I - P).  component_first=True gives
+    C_ab[i, j] = C_iajb (stiffness tensor; lambda E_ab + mu E_ba + delta_ab mu I for an
+    isotropic material) collects every place D_ab occurs in K; the clamped dofs add
+    alpha I (x) (I - P).  component_first=True gives
     the paper's index order (component, level 0, ..., level d-1); the default
     puts the component index last.
     """
@@ -215,14 +216,15 @@ def assemble_operator(problem: dict, eps=1e-14, component_first=False):
         return np.asarray(Cm, dtype=np.float64).reshape(1, D, D, 1)
 
     E = np.eye(D)
+    Ct = fem.material_tensor(problem)
     total = None
     for a in range(D):
         for b in range(D):
-            Cm = lam * np.outer(E[a], E[b]) + mu * np.outer(E[b], E[a]) + (mu * E if a == b else 0.0)
+            Cm = Ct[:, a, :, b]  # test component i, trial component j of d_a phi_p d_b phi_q
             term = _attach_component(comp(Cm), atom(a, b), component_first)
             total = term if total is None else tt.mpo_round(tt.mpo_add(total, term), eps)
     h = extent[0] / (n - 1)
-    alpha = (lam + 2 * mu) * h ** (D - 2)
+    alpha = max(Ct[i, i, i, i] for i in range(D)) * h ** (D - 2)
     Ilev = kron_levels_matrix([matrix_qtt(np.eye(n), d) for _ in range(D)])
     Plev = kron_levels_matrix([matrix_qtt(np.diag(masks[a]), d) for a in range(D)])
     total = tt.mpo_round(tt.mpo_add(total, _attach_component(comp(alpha * E), Ilev, component_first)), eps)

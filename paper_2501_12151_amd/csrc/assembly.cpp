@@ -18,7 +18,7 @@
 // combines atoms with the material constants.  The result is exact (no rounding)
 // and its middle cores are 0/1 matrices with one nonzero per (input state,
 // mode) pair -- the structure the device contraction kernels exploit.
-// Clamped faces: A_bc = P A P + alpha (I - P), alpha = (lambda + 2 mu) h_x^(D-2),
+// Clamped faces: A_bc = P A P + alpha (I - P), alpha = max_i C_iiii h_x^(D-2) (lambda + 2 mu when isotropic),
 // with P the Kronecker product of 1D masks (symmetric elimination).
 #include "assembly.hpp"
 
@@ -565,6 +565,59 @@ void tt_round_host(std::vector<TTCore>& cores, double tol, int rmax) {
   }
 }
 
+// Index of the Voigt component of the symmetric pair (i, j): 2D (xx, yy, xy), 3D (xx, yy, zz,
+// yz, xz, xy).
+static int voigt(int D, int i, int j) {
+  if (i == j) return i;
+  if (D == 2) return 2;
+  return i + j == 3 ? 3 : (i + j == 2 ? 4 : 5);  // yz, xz, xy
+}
+
+std::vector<double> stiffness_tensor(const tnfem_problem_desc& desc, int D, double lam, double mu) {
+  std::vector<double> C((size_t)D * D * D * D, 0.0);
+  auto at = [&](int i, int a, int j, int b) -> double& { return C[((i * D + a) * D + j) * D + b]; };
+  if (!desc.has_stiffness) {
+    for (int i = 0; i < D; ++i)
+      for (int a = 0; a < D; ++a)
+        for (int j = 0; j < D; ++j)
+          for (int b = 0; b < D; ++b)
+            at(i, a, j, b) = lam * (i == a) * (j == b) + mu * ((i == j) * (a == b) + (i == b) * (a == j));
+    return C;
+  }
+  const int nv = D == 2 ? 3 : 6;
+  std::vector<double> V((size_t)nv * nv);
+  for (int r = 0; r < nv; ++r)
+    for (int c = 0; c < nv; ++c) {
+      V[(size_t)r * nv + c] = desc.stiffness[r][c];
+      TNFEM_REQUIRE(std::isfinite(desc.stiffness[r][c]), "stiffness holds a non-finite value");
+    }
+  double scale = 0.0;
+  for (double v : V) scale = std::max(scale, std::fabs(v));
+  for (int r = 0; r < nv; ++r)
+    for (int c = 0; c < r; ++c)
+      TNFEM_REQUIRE(std::fabs(V[(size_t)r * nv + c] - V[(size_t)c * nv + r]) <= 1e-12 * scale,
+                    "stiffness must be symmetric");
+  // positive definite: Cholesky
+  std::vector<double> L = V;
+  for (int j = 0; j < nv; ++j) {
+    double dj = L[(size_t)j * nv + j];
+    for (int k = 0; k < j; ++k) dj -= L[(size_t)j * nv + k] * L[(size_t)j * nv + k];
+    TNFEM_REQUIRE(dj > 1e-14 * scale, "stiffness must be positive definite");
+    dj = std::sqrt(dj);
+    L[(size_t)j * nv + j] = dj;
+    for (int i = j + 1; i < nv; ++i) {
+      double v = L[(size_t)i * nv + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * nv + k] * L[(size_t)j * nv + k];
+      L[(size_t)i * nv + j] = v / dj;
+    }
+  }
+  for (int i = 0; i < D; ++i)
+    for (int a = 0; a < D; ++a)
+      for (int j = 0; j < D; ++j)
+        for (int b = 0; b < D; ++b) at(i, a, j, b) = V[(size_t)voigt(D, i, a) * nv + voigt(D, j, b)];
+  return C;
+}
+
 Assembled assemble(const tnfem_problem_desc& desc) {
   const int D = desc.dim, d = desc.level;
   TNFEM_REQUIRE(D == 2 || D == 3, "dim must be 2 or 3 (got %d)", D);
@@ -573,6 +626,9 @@ Assembled assemble(const tnfem_problem_desc& desc) {
   TNFEM_REQUIRE(desc.nu > -1.0 && desc.nu < 0.5, "nu must be in (-1, 0.5)");
   for (int a = 0; a < D; ++a) TNFEM_REQUIRE(desc.extent[a] > 0, "extent[%d] must be positive", a);
   TNFEM_REQUIRE(!(desc.plane_stress && D == 3), "plane_stress is a 2D option");
+  TNFEM_REQUIRE(!(desc.plane_stress && desc.has_stiffness), "plane_stress does not combine with a stiffness matrix");
+  TNFEM_REQUIRE(!(desc.has_manufactured && desc.has_stiffness),
+                "the manufactured load is the isotropic closed form; it does not combine with a stiffness matrix");
   TNFEM_REQUIRE((desc.clamp_mask >> (2 * D)) == 0, "clamp_mask names a face beyond dim");
   TNFEM_REQUIRE(desc.n_tractions >= 0 && desc.n_tractions <= 6, "n_tractions must be in [0, 6]");
   const int n = 1 << d;
@@ -614,8 +670,13 @@ Assembled assemble(const tnfem_problem_desc& desc) {
   double lam = desc.E * desc.nu / ((1 + desc.nu) * (1 - 2 * desc.nu));
   double mu = desc.E / (2 * (1 + desc.nu));
   if (desc.plane_stress) lam = 2 * lam * mu / (lam + 2 * mu);
+  // stiffness tensor C[i][a][j][b]: sigma_ia = sum_jb C_iajb du_j/dx_b
+  std::vector<double> Ct = stiffness_tensor(desc, D, lam, mu);
+  auto Cq = [&](int i, int a, int j, int b) { return Ct[((i * D + a) * D + j) * D + b]; };
+  double cmax = 0.0;
+  for (int i = 0; i < D; ++i) cmax = std::max(cmax, Cq(i, i, i, i));
   const double h0 = desc.extent[0] / (n - 1);
-  const double alpha = (lam + 2 * mu) * std::pow(h0, D - 2);
+  const double alpha = cmax * std::pow(h0, D - 2);
   out.lam = lam;
   out.mu = mu;
   out.alpha = alpha;
@@ -662,11 +723,10 @@ Assembled assemble(const tnfem_problem_desc& desc) {
         if (a == b) at.axis.push_back(c == a ? S[c] : M[c]);
         else at.axis.push_back(c == a ? G[c] : (c == b ? GT[c] : M[c]));
       }
+      // test component i, trial component j of the term d_a phi_p d_b phi_q
       at.comp.assign(D * D, 0.0);
-      at.comp[a * D + b] += lam;
-      at.comp[b * D + a] += mu;
-      if (a == b)
-        for (int c = 0; c < D; ++c) at.comp[c * D + c] += mu;
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) at.comp[i * D + j] = Cq(i, a, j, b);
       atoms.push_back(at);
     }
   if (any_clamp) {

@@ -35,6 +35,10 @@ struct Assembled {
 // Validates desc (throws tnfem::Error) and assembles operator and load.
 Assembled assemble(const tnfem_problem_desc& desc);
 
+// Stiffness tensor C[((i D + a) D + j) D + b] (sigma_ia = sum C_iajb du_j/dx_b): the desc's Voigt
+// matrix when has_stiffness (validated: symmetric positive definite), else the isotropic law.
+std::vector<double> stiffness_tensor(const tnfem_problem_desc& desc, int D, double lam, double mu);
+
 // Doubles of the nodal load f0 (0 without one); validates its ranks (throws tnfem::Error).
 size_t f0_doubles(const tnfem_problem_desc& desc);
 

@@ -49,6 +49,7 @@ class ProblemDesc(C.Structure):
         ("has_manufactured", C.c_int), ("manufactured_c", C.c_double * 3),
         ("layer_axis", C.c_int), ("n_layer_E", C.c_int), ("layer_E", C.POINTER(C.c_double)),
         ("f0_ranks", C.POINTER(C.c_int)), ("f0_cores", C.POINTER(C.c_double)),
+        ("has_stiffness", C.c_int), ("stiffness", (C.c_double * 6) * 6),
     ]
 
 
@@ -183,6 +184,12 @@ def make_desc(problem: dict) -> ProblemDesc:
         d.layer_axis = int(axis)
         d.n_layer_E = arr.size
         d.layer_E = arr.ctypes.data_as(_dp)
+    if problem.get("stiffness_voigt") is not None:
+        Cv = np.asarray(problem["stiffness_voigt"], dtype=np.float64)
+        d.has_stiffness = 1
+        for i in range(Cv.shape[0]):
+            for j in range(Cv.shape[1]):
+                d.stiffness[i][j] = float(Cv[i, j])
     if problem.get("f_nodal_tt") is not None:
         cores = [np.asarray(c, dtype=np.float64) for c in problem["f_nodal_tt"]]
         ranks = np.ascontiguousarray([c.shape[0] for c in cores] + [cores[-1].shape[2]], dtype=np.int32)

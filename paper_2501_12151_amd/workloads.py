@@ -38,6 +38,32 @@ def layered_cube(level: int = 9):
                 layered_E=(2, E.tolist()))
 
 
+def random_anisotropic_voigt(dim: int, seed: int = 0):
+    """A seeded symmetric positive definite stiffness in Voigt notation (3 x 3 in 2D, 6 x 6 in
+    3D): an isotropic part (E = 1, nu = 0.3 scale) plus a random symmetric perturbation that
+    couples normal and shear components, as a fully anisotropic crystal does."""
+    rng = np.random.default_rng(seed)
+    nv = 3 if dim == 2 else 6
+    Bm = rng.standard_normal((nv, nv))
+    C = 0.3 * Bm @ Bm.T / nv + np.eye(nv)
+    C[:dim, :dim] += 0.5
+    return C.tolist()
+
+
+def orthotropic_voigt(dim: int, E1: float, E2: float, E3: float = 1.0, nu: float = 0.25, G: float = 0.4):
+    """Orthotropic stiffness aligned with the axes (Voigt), from its compliance: diagonal
+    1/E_a, off-diagonal -nu/E_a, shear 1/G."""
+    E = [E1, E2, E3][:dim]
+    nv = 3 if dim == 2 else 6
+    S = np.zeros((nv, nv))
+    for a in range(dim):
+        for b in range(dim):
+            S[a, b] = 1.0 / E[a] if a == b else -nu / max(E[a], E[b])
+    for k in range(dim, nv):
+        S[k, k] = 1.0 / G
+    return np.linalg.inv(S).tolist()
+
+
 # aluminium cantilever of Sec. 6: density (kg/m^3), gravity (m/s^2)
 CANTILEVER_RHO = 2700.0
 CANTILEVER_G = 9.81

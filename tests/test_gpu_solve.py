@@ -31,6 +31,11 @@ SMALL = [
     dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, 0.0, -1.0]),
     dict(dim=3, level=3, E=1.0, nu=0.45, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])]),
     dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(a, s) for a in range(3) for s in (0, 1)], manufactured_c=[0.3, -1.0, 0.5]),
+    # anisotropic materials (constant Voigt stiffness; one also in slabs)
+    dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.3])],
+         stiffness_voigt=workloads.random_anisotropic_voigt(2, 1)),
+    dict(dim=3, level=3, E=2.0, nu=0.3, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])],
+         layered_E=(2, [2.0, 2.0, 20.0, 20.0, 2.0, 2.0, 20.0]), stiffness_voigt=workloads.orthotropic_voigt(3, 1.0, 3.0, 0.5)),
     # nodal load f0 given as a TT (Alg. 2 input)
     dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], f_nodal_tt=_nodal_tt(3, 3, 2, seed=5)),
     dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(1, 0)], f_nodal_tt=_nodal_tt(2, 4, 3, seed=6)),
@@ -96,3 +101,35 @@ def test_layered_material_solve_equals_direct(prob):
     assert rel <= 1e-8
     P.close()
     ctx.close()
+
+
+def test_anisotropic_material_reproduces_linear_field_at_level_6(ctx):
+    """Patch test at 3 x 2^18 dofs: a fully anisotropic material clamped at x = 0 and loaded by
+    the face tractions sigma . n of the constant stress of u_i = g_i x is solved exactly by
+    that linear field (Q1 reproduces it); checked at 4096 random nodes."""
+    D, d = 3, 6
+    Cv = np.asarray(workloads.random_anisotropic_voigt(3, 7))
+    grad = np.array([0.7, -0.4, 0.25])
+    C = fem.voigt_to_tensor(Cv, D)
+    Gm = np.zeros((D, D))
+    Gm[:, 0] = grad
+    sig = np.einsum("ijkl,kl->ij", C, 0.5 * (Gm + Gm.T))
+    tr = [(0, 1, list(sig[:, 0]))] + [(a, s, list((1 if s else -1) * sig[:, a])) for a in (1, 2) for s in (0, 1)]
+    prob = dict(dim=D, level=d, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=tr, stiffness_voigt=Cv.tolist())
+    P = tnfem.Problem(ctx, prob)
+    U, st, rc = P.solve(rank_cap=32, tol=1e-10, max_sweeps=30)
+    rng = np.random.default_rng(3)
+    nodes = rng.integers(0, 2 ** d, size=(4096, D))
+    comp = rng.integers(0, D, size=4096)
+    idx = np.zeros((4096, d + 1), dtype=np.int64)
+    for l in range(d):
+        idx[:, l] = sum(((nodes[:, a] >> (d - 1 - l)) & 1) << (D - 1 - a) for a in range(D))
+    idx[:, d] = comp
+    x = nodes[:, 0] / (2 ** d - 1)
+    exact = grad[comp] * x
+    got = U.eval(idx)
+    err = np.abs(got - exact).max() / np.abs(exact).max()
+    print(f"anisotropic linear field, level {d}: max rel error {err:.2e}, max rank {st['max_rank']}, "
+          f"sweeps {st['sweeps']}", flush=True)
+    assert err <= 1e-8
+    P.close()

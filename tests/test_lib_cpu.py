@@ -36,6 +36,13 @@ CASES = [
     dict(dim=3, level=3, E=0.5, nu=0.4, clamp=[(2, 0), (0, 1)], tractions=[(2, 1, [0, 0, -1.0]), (0, 1, [0.3, 0.2, 0.1])],
          body_force=[0.1, 0.2, 0.3], extent=[2.0, 1.0, 0.5]),
     dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(a, s) for a in range(3) for s in (0, 1)], manufactured_c=[0.5, 1.0, -0.3]),
+    # anisotropic materials: constant Voigt stiffness (one with slabs of it)
+    dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.3])], extent=[2.0, 1.0],
+         stiffness_voigt=workloads.random_anisotropic_voigt(2, 1)),
+    dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(0, 0), (1, 1)], body_force=[0.0, 0.5, -1.0],
+         stiffness_voigt=workloads.random_anisotropic_voigt(3, 2)),
+    dict(dim=3, level=3, E=2.0, nu=0.3, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])],
+         layered_E=(2, [2.0, 2.0, 20.0, 20.0, 2.0, 2.0, 20.0]), stiffness_voigt=workloads.orthotropic_voigt(3, 1.0, 3.0, 0.5)),
 ]
 
 
@@ -51,8 +58,8 @@ def test_library_assembly_equals_sparse_fem(case):
     assert np.abs(tt.mpo_full(Ac) - Ap).max() <= 1e-13 * np.abs(Ap).max()
     bp = qtt.to_qtt_order(b, D, d)
     assert np.abs(tt.tt_full(bc) - bp).max() <= 1e-13 * np.abs(bp).max()
-    # exact automaton ranks: 5^D joint carry states in the middle
-    assert max(C.shape[3] for C in Ac) <= 5 ** D
+    # exact automaton ranks: 5^D joint carry states in the middle (7 on a layered axis)
+    assert max(C.shape[3] for C in Ac) <= (7 * 5 ** (D - 1) if "layered_E" in prob else 5 ** D)
 
 
 def _random_nodal_tt(D, d, rank, seed):
@@ -138,6 +145,11 @@ def test_library_operator_matches_oracle_tt_at_larger_levels(prob):
     (dict(level=1), "level"),
     (dict(E=-1.0), "E"),
     (dict(extent=[1.0, 0.0]), "extent"),
+    (dict(stiffness_voigt=[[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, -1.0]]), "positive definite"),
+    (dict(stiffness_voigt=[[1.0, 0.5, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]), "symmetric"),
+    (dict(stiffness_voigt=[[2.0, 0.5, 0.0], [0.5, 2.0, 0.0], [0.0, 0.0, 1.0]], plane_stress=True), "plane_stress"),
+    (dict(stiffness_voigt=[[2.0, 0.5, 0.0], [0.5, 2.0, 0.0], [0.0, 0.0, 1.0]], manufactured_c=[1.0, 0.0]),
+     "manufactured"),
 ])
 def test_invalid_descriptor_rejected(bad, msg):
     prob = dict(workloads.small_2d(), **bad)

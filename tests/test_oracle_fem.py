@@ -244,3 +244,79 @@ def test_cantilever_tip_deflection_approaches_euler_bernoulli():
         assert e_k == pytest.approx(0.5 * b @ u, rel=1e-6)  # up to the direct solve's residual (kappa ~ 1e9)
     assert np.all(np.diff(ratios) > 0) and np.all(np.diff(energies) > 0)
     assert abs(ratios[-1] - 1.0) <= 5e-3, ratios
+
+
+# ----------------------------------------------------------------------------- anisotropic material
+
+def _random_spd_voigt(D, seed):
+    rng = np.random.default_rng(seed)
+    nv = 3 if D == 2 else 6
+    B = rng.standard_normal((nv, nv))
+    return B @ B.T / nv + np.eye(nv)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_isotropic_voigt_matrix_reproduces_isotropic_element(D):
+    """The tensor from the isotropic Voigt matrix (lambda + 2 mu, lambda, mu) gives the element
+    of sigma = lambda tr(eps) I + 2 mu eps exactly."""
+    lam, mu = fem.lame(1.7, 0.27)
+    nv = 3 if D == 2 else 6
+    Cv = np.zeros((nv, nv))
+    Cv[:D, :D] = lam
+    for i in range(D):
+        Cv[i, i] = lam + 2 * mu
+    for k in range(D, nv):
+        Cv[k, k] = mu
+    C = fem.voigt_to_tensor(Cv, D)
+    assert np.abs(C - fem.isotropic_tensor(lam, mu, D)).max() == 0.0
+    h = [0.3, 0.7, 0.2][:D]
+    K1, _ = fem.element_matrices(D, h, lam, mu)
+    K2, _ = fem.element_matrices(D, h, 0.0, 0.0, C)
+    assert np.abs(K1 - K2).max() <= 1e-14 * np.abs(K1).max()
+
+
+@pytest.mark.parametrize("D,d", [(2, 3), (3, 2)])
+def test_anisotropic_stiffness_symmetric_with_rigid_null_space(D, d):
+    C = fem.voigt_to_tensor(_random_spd_voigt(D, 3), D)
+    g = fem.Grid(D, d, [1.0, 2.0, 0.5][:D])
+    K, _ = fem.assemble(g, 0.0, 0.0, None, C)
+    assert abs(K - K.T).max() <= 1e-14 * abs(K).max()
+    x = g.node_coords()
+    modes = [np.concatenate([np.full(g.n_nodes, float(a == c)) for c in range(D)]) for a in range(D)]
+    rots = [(0, 1)] if D == 2 else [(0, 1), (0, 2), (1, 2)]
+    for i, j in rots:  # u_i = -x_j, u_j = x_i
+        u = np.zeros((D, g.n_nodes))
+        u[i], u[j] = -x[:, j], x[:, i]
+        modes.append(u.reshape(-1))
+    for m in modes:
+        assert np.abs(K @ m).max() <= 1e-13 * abs(K).max() * np.abs(m).max()
+    # positive definite once clamped
+    A, _ = fem.apply_dirichlet(K, np.zeros(g.n_dofs), fem.clamp_mask(g, [(0, 0)]), 1.0)
+    np.linalg.cholesky(A.toarray())
+
+
+def linear_field_problem(D, d, Cv, grad):
+    """Clamped at x = 0, with the face tractions sigma . n of the constant stress of
+    u_i = grad[i] x: the exact solution is that linear field (Q1 reproduces it exactly)."""
+    C = fem.voigt_to_tensor(Cv, D)
+    Gm = np.zeros((D, D))
+    Gm[:, 0] = grad
+    sig = np.einsum("ijkl,kl->ij", C, 0.5 * (Gm + Gm.T))
+    tr = [(0, 1, list(sig[:, 0]))]
+    for a in range(1, D):
+        tr.append((a, 0, list(-sig[:, a])))
+        tr.append((a, 1, list(sig[:, a])))
+    return dict(dim=D, level=d, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=tr,
+                stiffness_voigt=np.asarray(Cv).tolist())
+
+
+@pytest.mark.parametrize("D,d", [(2, 4), (3, 3)])
+def test_anisotropic_patch_problem_reproduces_linear_field(D, d):
+    """Patch test for an anisotropic material: the direct solve returns u = grad x exactly."""
+    grad = np.array([0.7, -0.4, 0.25])[:D]
+    prob = linear_field_problem(D, d, _random_spd_voigt(D, 5), grad)
+    A, b, grid, _ = fem.build_system(prob)
+    u = fem.direct_solve(A, b).reshape(D, -1)
+    x = grid.node_coords()
+    exact = grad[:, None] * x[None, :, 0]
+    assert np.abs(u - exact).max() <= 1e-11 * np.abs(exact).max()

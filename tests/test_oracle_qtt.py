@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from oracle import fem, qtt, tt
+from paper_2501_12151_amd import workloads
 
 CASES = [
     dict(dim=2, level=2, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])]),
@@ -14,6 +15,13 @@ CASES = [
     dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])],
          layered_E=(2, [1.0, 1.0, 10.0, 10.0, 1.0, 1.0, 10.0])),
     dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(a, s) for a in range(3) for s in (0, 1)], manufactured_c=[0.5, 1.0, -0.3]),
+    # anisotropic materials (constant Voigt stiffness), one also layered
+    dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.3])],
+         stiffness_voigt=workloads.random_anisotropic_voigt(2, 1), extent=[2.0, 1.0]),
+    dict(dim=3, level=2, E=1.0, nu=0.3, clamp=[(2, 0)], body_force=[0.1, 0.0, -1.0],
+         stiffness_voigt=workloads.random_anisotropic_voigt(3, 2)),
+    dict(dim=3, level=3, E=2.0, nu=0.3, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])],
+         layered_E=(2, [2.0, 2.0, 20.0, 20.0, 2.0, 2.0, 20.0]), stiffness_voigt=workloads.orthotropic_voigt(3, 1.0, 3.0, 0.5)),
 ]
 
 
