@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--levels", default="6,8,10,12,14,16,18,20", help="cantilever: grid levels")
     ap.add_argument("--precision", type=int, default=1, choices=(0, 1, 2),
                     help="0 FP64; 1 FP32 local applies; 2 BF16 local applies (both refined in FP64)")
+    ap.add_argument("--ir-max", type=int, default=0, help="outer FP64 refinement steps after the solve (0: none)")
+    ap.add_argument("--ir-sweeps", type=int, default=4, help="half-sweeps of each correction solve")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (and its accuracy reference)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the GPU's high-rank reference solves")
@@ -226,6 +228,8 @@ def main():
     wl = WORKLOADS[args.workload]
     prob = problem_for(args.workload)
     opts = dict(wl["opts"], precision=args.precision)
+    if args.ir_max > 0:
+        opts.update(ir_max=args.ir_max, ir_sweeps=args.ir_sweeps, ir_tol=0.1 * opts["tol"])
     ctx = tnfem.Context(0)
     P = tnfem.Problem(ctx, prob)
     info = P.info()
@@ -252,7 +256,7 @@ def main():
     u64 = None
     fp64 = None
     if args.precision != 0 and not args.no_fp64_solver:
-        o64 = dict(opts, precision=0)
+        o64 = dict({k: v for k, v in opts.items() if not k.startswith("ir_")}, precision=0)
         u64, st64, lat64, total64 = timed(o64, "f64")
         fp64 = {"value": args.steps / total64, "unit": "solves/s", "ms_per_step": 1e3 * total64 / args.steps,
                 "latency_ms": {"p50": 1e3 * percentile(lat64, 0.5), "p99": 1e3 * percentile(lat64, 0.99)},

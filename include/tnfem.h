@@ -135,6 +135,20 @@ typedef struct {
   int cg_maxit;      /* iteration limit of each local conjugate-gradient solve */
   int precision;
   int profile;       /* 1: time every contraction launch with HIP events (adds host work) */
+  /* Outer FP64 iterative refinement (ir_max > 0): the sweeps above give u; then up to ir_max
+   * times the same sweep (ir_sweeps half-sweeps, 0 = max_sweeps; a fresh random start of seeds
+   * seed_x + i, seed_z + i) solves the correction equation A d = b - A u, whose load b - A u
+   * is never formed: its local right-hand sides and residual projections take the FP64 term
+   * (left interface) A_k u_k (right interface) with interfaces between the iterate and u
+   * through A, built in FP64; then u <- round(u + d) in FP64 on the device (orthogonalisation
+   * and SVD truncation at 0.1 ir_tol, ranks at most rank_cap).  Stops once
+   * ||d|| <= ir_tol ||u|| (0 = tol).  With ir_max > 0 and precision > 0 a local solve keeps
+   * its low-precision pass when that pass lowered the FP64 local residual (one FP64 check, no
+   * further restarts: the outer loop carries the FP64 correction), and otherwise returns to
+   * its best iterate and finishes in FP64 as without refinement.  Needs rank_cap <= 128. */
+  int ir_max;
+  int ir_sweeps;
+  double ir_tol;
 } tnfem_solve_opts;
 
 /* Fills opts with the defaults: cap 32, tol 1e-8, 30 sweeps, rho 4, init rank 2,
@@ -165,6 +179,9 @@ typedef struct {
   double apply_kernel_flops;
   long long apply_kernel_launches;
   int peak_rank;          /* largest TT rank of the iterate at any bond during the solve */
+  int ir_iters;           /* outer refinement steps done */
+  double ir_last_update;  /* ||d|| / ||u|| of the last refinement step */
+  int sweeps_total;       /* half-sweeps of all solves (the first and the corrections) */
 } tnfem_solve_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -56,56 +56,6 @@ static void check_svd_args(tnfem_ctx* ctx, int m, int n, const double* A, double
   if (m < 1 || n < 1 || std::min(m, n) > 256) fail(TNFEM_EINVAL, "need m, n >= 1 and min(m, n) <= 256");
 }
 
-// Workspace of svd_with_ws: the input in tall orientation, Q, R, the Jacobi factors and
-// the larger of the QR's and the Jacobi kernel's own workspace.
-static size_t svd_ws_doubles(int m, int n) {
-  const int mm = std::max(m, n), nn = std::min(m, n);
-  return (size_t)mm * nn * 2 + (size_t)nn * nn * 3 +
-         std::max(tnfem::qr_ws_doubles(mm, nn), (size_t)nn * nn * 3 + 3 * nn) + 8;
-}
-
-// A = U diag(S) Vt (thin, c = min(m, n)): Householder QR of the tall orientation, then
-// one-sided Jacobi on R^T; ws holds ws_cap >= svd_ws_doubles(m, n) doubles and needs no
-// initial contents.
-static void svd_with_ws(int m, int n, const double* A, double* U, double* S, double* Vt, double* ws, size_t ws_cap,
-                        hipStream_t st) {
-  const bool tall = m >= n;
-  const int mm = tall ? m : n, nn = tall ? n : m;  // work on the tall orientation
-  if (ws_cap < svd_ws_doubles(m, n)) fail(TNFEM_EINVAL, "SVD workspace too small");
-  double* At = ws;                       // mm x nn (transposed input when wide)
-  double* Q = At + (size_t)mm * nn;      // mm x nn
-  double* R = Q + (size_t)mm * nn;       // nn x nn
-  double* UR = R + (size_t)nn * nn;      // nn x nn
-  double* V = UR + (size_t)nn * nn;      // nn x nn
-  double* qws = V + (size_t)nn * nn;     // QR workspace, then the Jacobi kernel's
-  const double* src = A;
-  if (!tall) {
-    tnfem::launch_core_transpose(m, 1, n, A, At, st);  // At = A^T (n x m)
-    src = At;
-  }
-  const size_t qws_cap = ws_cap - (size_t)(qws - ws);
-  tnfem::launch_qr(mm, nn, src, nn, Q, nn, R, nn, qws, qws_cap, st);
-  tnfem::launch_jacobi_svd(nn, R, nn, V, S, UR, qws, st, 1);  // on R^T: outputs swapped
-  tnfem::GemmDesc g;
-  if (tall) {
-    // U = Q UR (m x n); Vt = V^T
-    g.A = Q; g.a_sm = nn; g.a_sk = 1;
-    g.B = UR; g.b_sk = nn; g.b_sn = 1;
-    g.C = U; g.c_sm = nn; g.c_sn = 1;
-    g.M = mm; g.N = nn; g.K = nn;
-    tnfem::launch_gemm(g, st);
-    tnfem::launch_core_transpose(nn, 1, nn, V, Vt, st);
-  } else {
-    // A^T = (Q UR) S V^T  =>  A = V S (Q UR)^T: U = V (m x m), Vt = (Q UR)^T (m x n)
-    tnfem::launch_copy2d(nn, nn, V, nn, U, nn, 1.0, 0.0, st);
-    g.A = UR; g.a_sm = 1; g.a_sk = nn;   // UR^T
-    g.B = Q; g.b_sk = 1; g.b_sn = nn;    // Q^T
-    g.C = Vt; g.c_sm = mm; g.c_sn = 1;
-    g.M = nn; g.N = mm; g.K = nn;
-    tnfem::launch_gemm(g, st);
-  }
-}
-
 extern "C" {
 
 const char* tnfem_last_error(void) { return tnfem::g_last_error.c_str(); }
@@ -328,23 +278,6 @@ namespace {
 
 // Frobenius norm of a TT by left-orthogonalisation: QR of each unfolding, the R
 // factor carried into the next core; the norm is that of the last carried core.
-double tt_norm_host(std::vector<int> modes, std::vector<int> ranks, std::vector<std::vector<double>> cores) {
-  const int K = (int)modes.size();
-  for (int k = 0; k + 1 < K; ++k) {
-    const int m = ranks[k] * modes[k], nc = ranks[k + 1];
-    std::vector<double> Q, R;
-    tnfem::hostla::qr(m, nc, cores[k].data(), Q, R);
-    const int c = std::min(m, nc);
-    const int cols = modes[k + 1] * ranks[k + 2];
-    std::vector<double> next((size_t)c * cols);
-    tnfem::hostla::gemm(c, cols, nc, R.data(), cores[k + 1].data(), next.data());
-    cores[k + 1].swap(next);
-    ranks[k + 1] = c;
-  }
-  double s = 0.0;
-  for (double v : cores[K - 1]) s += v * v;
-  return std::sqrt(s);
-}
 
 }  // namespace
 
@@ -353,7 +286,7 @@ extern "C" {
 int tnfem_tt_norm(const tnfem_tt* t, double* out) {
   return guarded([&] {
     if (!t || !out) fail(TNFEM_EINVAL, "NULL argument");
-    *out = tt_norm_host(t->t.modes, t->t.ranks, t->t.cores);
+    *out = tnfem::hostla::tt_norm(t->t.modes, t->t.ranks, t->t.cores);
     return TNFEM_OK;
   });
 }
@@ -389,8 +322,8 @@ int tnfem_tt_rel_diff(const tnfem_tt* a, const tnfem_tt* b, double* out) {
             cores[k][((size_t)(x + bl_off) * n + i) * rr + y + br_off] +=
                 bsign * B.cores[k][((size_t)x * n + i) * rbr + y];
     }
-    const double nd = tt_norm_host(A.modes, ranks, std::move(cores));
-    const double nb = tt_norm_host(B.modes, B.ranks, B.cores);
+    const double nd = tnfem::hostla::tt_norm(A.modes, ranks, std::move(cores));
+    const double nb = tnfem::hostla::tt_norm(B.modes, B.ranks, B.cores);
     *out = nb > 0.0 ? nd / nb : nd;
     return TNFEM_OK;
   });
@@ -550,15 +483,15 @@ int tnfem_prim_qr(tnfem_ctx* ctx, int m, int n, const double* A, double* Q, doub
 
 size_t tnfem_prim_svd_noalloc_doubles(int m, int n) {
   if (m < 1 || n < 1 || std::min(m, n) > 256) return 0;
-  return svd_ws_doubles(m, n);
+  return tnfem::svd_ws_doubles(m, n);
 }
 
 int tnfem_prim_svd(tnfem_ctx* ctx, int m, int n, const double* A, double* U, double* S, double* Vt, void* stream) {
   return guarded([&] {
     check_svd_args(ctx, m, n, A, U, S, Vt);
     tnfem::hip_check(hipSetDevice(ctx->c.device), "hipSetDevice");
-    const size_t need = svd_ws_doubles(m, n);
-    svd_with_ws(m, n, A, U, S, Vt, ctx->c.ensure_scratch(need), need, pick_stream(ctx, stream));
+    const size_t need = tnfem::svd_ws_doubles(m, n);
+    tnfem::svd_device(m, n, A, U, S, Vt, ctx->c.ensure_scratch(need), need, pick_stream(ctx, stream));
     return TNFEM_OK;
   });
 }
@@ -567,13 +500,13 @@ int tnfem_prim_svd_noalloc(tnfem_ctx* ctx, int m, int n, const double* A, double
                            void* stream) {
   return guarded([&] {
     check_svd_args(ctx, m, n, A, U, S, Vt);
-    const size_t need = svd_ws_doubles(m, n);
+    const size_t need = tnfem::svd_ws_doubles(m, n);
     if (need > tnfem::NOALLOC_SCRATCH_DOUBLES)
       fail(TNFEM_EINVAL, "a %d x %d SVD needs %zu doubles of workspace, the fixed workspace holds %zu", m, n, need,
            tnfem::NOALLOC_SCRATCH_DOUBLES);
     tnfem::hip_check(hipSetDevice(ctx->c.device), "hipSetDevice");
     double* ws = tnfem::noalloc_scratch(ctx->c.device);
-    svd_with_ws(m, n, A, U, S, Vt, ws, need, pick_stream(ctx, stream));
+    tnfem::svd_device(m, n, A, U, S, Vt, ws, need, pick_stream(ctx, stream));
     return TNFEM_OK;
   });
 }

@@ -13,6 +13,7 @@
 // reversed chain: cores are transposed on the device, operator plans for both
 // orientations are built at problem creation.
 #include "engine.hpp"
+#include "hostla.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -723,6 +724,35 @@ void Problem::ensure_workspace(int cap, int rho) {
   ws = std::move(W);
 }
 
+void Problem::ensure_ir(int cap, int rho) {
+  if (ws->ir && ws->ir->cap >= cap && ws->ir->rho >= rho) return;
+  ws->ir.reset();
+  auto B = std::make_unique<IrBuffers>();
+  B->cap = cap;
+  B->rho = rho;
+  auto A = [&](size_t d) { return static_cast<double*>(B->arena.alloc(std::max<size_t>(d, 1) * 8)); };
+  const size_t rc = (size_t)std::max(cap, rho), mx = (size_t)maxn, R = (size_t)Rmax;
+  const size_t core = rc * mx * rc, r2 = 2 * rc;
+  B->sum_cap = r2 * mx * r2;
+  for (int k = 0; k < K; ++k) {
+    B->U.push_back(A(core));
+    B->Sum.push_back(A(B->sum_cap));
+  }
+  B->uspare = A(core);
+  for (int k = 0; k <= K; ++k) {
+    B->EuA.push_back(A(rc * R * rc));
+    B->EzuA.push_back(A((size_t)rho * R * rc));
+  }
+  B->t1 = A(B->sum_cap);
+  B->t2 = A(B->sum_cap);
+  B->su = A(B->sum_cap);
+  B->ss = A(r2);
+  B->svt = A(r2 * r2);
+  B->svdws_cap = svd_ws_doubles((int)(r2 * mx), (int)r2);
+  B->svdws = A(B->svdws_cap);
+  ws->ir = std::move(B);
+}
+
 // ----------------------------------------------------------------------------- SplitMix64
 
 static inline uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
@@ -789,6 +819,13 @@ struct Sweep {
   int nan_seen = 0;
   int verbose = 0;  // 2: one line per local solve on stderr
   std::vector<int> cg_last;  // CG iterations of the last local solve at each core (chain order)
+  // outer refinement: the load is b - A u for a fixed TT u (cores U, ranks ur); EuA / EzuA are
+  // the interfaces X-A-u and Z-A-u.  ir_inner: low-precision local solves end after their
+  // low-precision pass (the outer loop carries the FP64 correction).
+  bool with_u = false, ir_inner = false;
+  std::vector<double*> U, EuA, EzuA;
+  std::vector<int> ur;
+  double* uspare = nullptr;
 
   Sweep(Problem& p, const tnfem_solve_opts& opts) : P(p), W(*p.ws), o(opts), st(p.ctx->stream), K(p.K) {
     const char* v = std::getenv("TNFEM_VERBOSE");
@@ -800,10 +837,12 @@ struct Sweep {
 
   void sync() { hip_check(hipStreamSynchronize(st), "hipStreamSynchronize"); }
 
-  void upload_initial() {
+  void upload_initial() { upload_initial(o.seed_x, o.seed_z); }
+
+  void upload_initial(uint64_t seed_x, uint64_t seed_z) {
     std::vector<int> rx, rz;
-    auto cx = random_tt_host(P.modes, o.init_rank, o.seed_x, rx);
-    auto cz = random_tt_host(P.modes, o.rho, o.seed_z, rz);
+    auto cx = random_tt_host(P.modes, o.init_rank, seed_x, rx);
+    auto cz = random_tt_host(P.modes, o.rho, seed_z, rz);
     X = W.X;
     Z = W.Z;
     xspare = W.Xspare;
@@ -822,6 +861,9 @@ struct Sweep {
     const double one = 1.0;
     for (double* b : {EA[0], Eb[0], EzA[0], Ezb[0], EA[K], Eb[K], EzA[K], Ezb[K]})
       hip_check(hipMemcpyAsync(b, &one, 8, hipMemcpyHostToDevice, st), "boundary interface");
+    if (with_u)
+      for (double* b : {EuA[0], EzuA[0], EuA[K], EzuA[K]})
+        hip_check(hipMemcpyAsync(b, &one, 8, hipMemcpyHostToDevice, st), "boundary interface");
     sync();  // `one` is on the host stack
   }
 
@@ -831,6 +873,16 @@ struct Sweep {
       std::swap(X[k], xspare);
       launch_core_transpose(zr[k], n[k], zr[k + 1], Z[k], zspare, st);
       std::swap(Z[k], zspare);
+    }
+    if (with_u) {
+      for (int k = 0; k < K; ++k) {
+        launch_core_transpose(ur[k], n[k], ur[k + 1], U[k], uspare, st);
+        std::swap(U[k], uspare);
+      }
+      std::reverse(U.begin(), U.end());
+      std::reverse(ur.begin(), ur.end());
+      std::reverse(EuA.begin(), EuA.end());
+      std::reverse(EzuA.begin(), EzuA.end());
     }
     std::reverse(X.begin(), X.end());
     std::reverse(Z.begin(), Z.end());
@@ -887,6 +939,11 @@ struct Sweep {
     env_b(p, n[k], sb(k), sb(k + 1), s, X[k], Eb[k], B(k), W.Tb, Eb[k + 1], st, &fl);
     env_update_ws(P, plan(k), pz, p, s, tz, Z[k], EzA[k], X[k], EzA[k + 1], st, &fl, W.T1, W.T2);
     env_b(pz, n[k], sb(k), sb(k + 1), tz, Z[k], Ezb[k], B(k), W.Tb, Ezb[k + 1], st, &fl);
+    if (with_u) {
+      const int q = ur[k], s2 = ur[k + 1];
+      env_update_ws(P, plan(k), p, q, s2, s, X[k], EuA[k], U[k], EuA[k + 1], st, &fl, W.T1, W.T2);
+      env_update_ws(P, plan(k), pz, q, s2, tz, Z[k], EzuA[k], U[k], EzuA[k + 1], st, &fl, W.T1, W.T2);
+    }
   }
 
   // Left-orthogonalise core k of T (ranks tr) by QR and carry R into core k+1.
@@ -915,6 +972,10 @@ struct Sweep {
     const int p = xr[k], t = xr[k + 1];
     const int N = p * n[k] * t;
     local_rhs(p, n[k], sb(k), sb(k + 1), t, Eb[k], B(k), Eb[k + 1], W.Tb, W.g, st, &fl);
+    if (with_u) {  // g -= (projected) A u, in FP64
+      apply(k, p, ur[k], ur[k + 1], t, EuA[k], U[k], EuA[k + 1], W.ye, nullptr);
+      launch_sub((long)N, W.g, W.ye, W.g, st);
+    }
     const Plan& pl = plan(k);
     launch_local_block_inv(p, n[k], t, R(k), R(k + 1), EA[k], EA[k + 1], pl.bk_beg, pl.bk_b, pl.bk_e, pl.bk_v,
                            W.binv, st);
@@ -1084,6 +1145,10 @@ struct Sweep {
       const double res_now = fp64_restart();
       refinements++;
       if (done) break;
+      // under the outer refinement a low-precision pass that lowered the FP64 residual is
+      // kept as it stands (the outer loop carries the correction); one that did not falls
+      // back below
+      if (ir_inner && std::isfinite(res_now) && res_now < res_best) break;
       if (std::isfinite(res_now) && res_now < 0.9 * res_best && refine < 30) {
         res_best = res_now;
         launch_copy2d(1, N, X[k], N, xbest, N, 1.0, 0.0, st);
@@ -1186,6 +1251,10 @@ struct Sweep {
     local_rhs(pz, nk, sb(k), sb(k + 1), tz, Ezb[k], B(k), Ezb[k + 1], W.Tb, W.gz, st, &fl);
     apply(k, pz, p, t, tz, EzA[k], W.xt, EzA[k + 1], W.yz, nullptr);
     launch_sub((long)pz * nk * tz, W.gz, W.yz, W.gz, st);
+    if (with_u) {
+      apply(k, pz, ur[k], ur[k + 1], tz, EzuA[k], U[k], EzuA[k + 1], W.yz, nullptr);
+      launch_sub((long)pz * nk * tz, W.gz, W.yz, W.gz, st);
+    }
     const int mz = pz * nk;
     s.cz = std::min(mz, tz);
     s.zqr = QrJob{mz, tz, tz, s.cz, tz, W.gz, Z[k], W.Rz, W.qrwsz, W.qrwsz_cap};
@@ -1203,6 +1272,10 @@ struct Sweep {
     local_rhs(p, nk, sb(k), sb(k + 1), tz, Eb[k], B(k), Ezb[k + 1], W.Tb, W.ge, st, &fl);
     apply(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ye, nullptr);
     launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
+    if (with_u) {
+      apply(k, p, ur[k], ur[k + 1], tz, EuA[k], U[k], EzuA[k + 1], W.ye, nullptr);
+      launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
+    }
     launch_copy2d(M, rk, W.Ur, rk, W.aug, rnew, 1.0, 0.0, st);
     launch_copy2d(M, rho_eff, W.ge, tz, W.aug + rk, rnew, 1.0, 0.0, st);
     s.aqr = QrJob{M, rnew, rnew, rnew, rnew, W.aug, X[k], W.Ra, W.qrws, W.qrws_cap};
@@ -1239,6 +1312,110 @@ struct Sweep {
     push_enrich_jobs(s, jobs);
     launch_qr_batch(jobs, st);  // independent: one launch, one workgroup each
     enrich_end(k, s);
+  }
+
+  // ---- outer refinement (forward orientation throughout)
+
+  // The current iterate becomes u; the sweep restarts from random cores on the correction
+  // equation A d = b - A u (orthogonalisation and right interfaces rebuilt, those of u too).
+  void begin_correction(IrBuffers& B, uint64_t seed_x, uint64_t seed_z) {
+    if (!with_u) {
+      U = B.U;
+      uspare = B.uspare;
+      EuA = B.EuA;
+      EzuA = B.EzuA;
+      with_u = true;
+      ur = xr;
+      for (int k = 0; k < K; ++k)
+        hip_check(hipMemcpyAsync(U[k], X[k], (size_t)xr[k] * n[k] * xr[k + 1] * 8, hipMemcpyDeviceToDevice, st),
+                  "copy u");
+    }
+    upload_initial(seed_x, seed_z);
+    reverse();
+    qr_pass();
+    reverse();
+  }
+
+  // Reads back the truncation rank written to W.drank.
+  int read_rank() {
+    hip_check(hipMemcpyAsync(W.host_pinned, W.drank, sizeof(int), hipMemcpyDeviceToHost, st), "rank readback");
+    sync();
+    return hint()[0];
+  }
+
+  // u <- round(u + d) with d the current iterate X: the block sum of the two TTs,
+  // right-to-left orthogonalisation (QR of each transposed unfolding), then left-to-right
+  // SVD truncation at rtol (relative to the whole TT) with ranks at most cap.
+  // Returns ||d|| / ||u + d|| (FP64 norms: d's on the host, the sum's from its first core).
+  double add_correction(IrBuffers& B, double rtol, int cap) {
+    // ||d|| on the host (d's cores are a few hundred KB)
+    std::vector<std::vector<double>> dc(K);
+    for (int k = 0; k < K; ++k) {
+      dc[k].resize((size_t)xr[k] * n[k] * xr[k + 1]);
+      hip_check(hipMemcpyAsync(dc[k].data(), X[k], dc[k].size() * 8, hipMemcpyDeviceToHost, st), "download d");
+    }
+    sync();
+    const double dnorm = hostla::tt_norm(n, xr, dc);
+    std::vector<int> sr(K + 1);
+    sr[0] = 1;
+    sr[K] = 1;
+    for (int k = 1; k < K; ++k) sr[k] = ur[k] + xr[k];
+    for (int k = 0; k < K; ++k) {
+      const int rl = sr[k], rr = sr[k + 1];
+      hip_check(hipMemsetAsync(B.Sum[k], 0, (size_t)rl * n[k] * rr * 8, st), "clear sum core");
+      const int roff = k == 0 ? 0 : ur[k], coff = k == K - 1 ? 0 : ur[k + 1];
+      launch_copy2d(ur[k] * n[k], ur[k + 1], U[k], ur[k + 1], B.Sum[k], rr, 1.0, 0.0, st);
+      launch_copy2d(xr[k] * n[k], xr[k + 1], X[k], xr[k + 1], B.Sum[k] + (size_t)roff * n[k] * rr + coff, rr, 1.0,
+                    1.0, st);
+    }
+    // right-to-left: core k = R^T Q^T with Q^T row-orthonormal; R^T goes into core k - 1
+    for (int k = K - 1; k > 0; --k) {
+      const int rl = sr[k], rr = sr[k + 1], nk = n[k];
+      const int m = rr * nk, c = std::min(m, rl);
+      launch_core_transpose(rl, nk, rr, B.Sum[k], B.t1, st);  // [rr][n][rl]: (rr n) x rl
+      launch_qr(m, rl, B.t1, rl, B.t2, c, B.svt, rl, B.svdws, B.svdws_cap, st);
+      launch_core_transpose(rr, nk, c, B.t2, B.Sum[k], st);   // [c][n][rr]
+      launch_core_transpose(c, 1, rl, B.svt, B.t1, st);  // R^T: rl x c
+      const int pm = sr[k - 1] * n[k - 1];
+      gemm_plain(pm, c, rl, B.Sum[k - 1], rl, false, B.t1, c, B.t2, c, st, &fl);
+      launch_copy2d(pm, c, B.t2, c, B.Sum[k - 1], c, 1.0, 0.0, st);
+      sr[k] = c;
+    }
+    // ||u + d|| = ||core 0|| now
+    std::vector<double> c0((size_t)sr[0] * n[0] * sr[1]);
+    hip_check(hipMemcpyAsync(c0.data(), B.Sum[0], c0.size() * 8, hipMemcpyDeviceToHost, st), "download core 0");
+    sync();
+    double snorm = 0.0;
+    for (double v : c0) snorm += v * v;
+    snorm = std::sqrt(snorm);
+    // left-to-right SVD truncation
+    const double ktol = rtol / std::sqrt((double)std::max(K - 1, 1));
+    for (int k = 0; k < K - 1; ++k) {
+      const int M = sr[k] * n[k], Nn = sr[k + 1], c = std::min(M, Nn);
+      svd_device(M, Nn, B.Sum[k], B.su, B.ss, B.svt, B.svdws, B.svdws_cap, st);
+      launch_trunc_rank(c, B.ss, ktol, cap, W.drank, st);
+      const int rk = read_rank();
+      launch_copy2d(M, rk, B.su, c, B.Sum[k], rk, 1.0, 0.0, st);
+      launch_scale_rows(rk, Nn, B.ss, B.svt, Nn, B.t2, st);  // diag(S) V^T, rk x Nn
+      const int cols = n[k + 1] * sr[k + 2];
+      gemm_plain(rk, cols, Nn, B.t2, Nn, false, B.Sum[k + 1], cols, B.t1, cols, st, &fl);
+      launch_copy2d(rk, cols, B.t1, cols, B.Sum[k + 1], cols, 1.0, 0.0, st);
+      sr[k + 1] = rk;
+    }
+    for (int k = 0; k < K; ++k)
+      hip_check(hipMemcpyAsync(U[k], B.Sum[k], (size_t)sr[k] * n[k] * sr[k + 1] * 8, hipMemcpyDeviceToDevice, st),
+                "store u");
+    ur = sr;
+    peak_rank = std::max(peak_rank, *std::max_element(sr.begin(), sr.end()));
+    return snorm > 0.0 ? dnorm / snorm : dnorm;
+  }
+
+  // The refined u becomes the iterate (for the download of the result).
+  void take_u() {
+    for (int k = 0; k < K; ++k)
+      hip_check(hipMemcpyAsync(X[k], U[k], (size_t)ur[k] * n[k] * ur[k + 1] * 8, hipMemcpyDeviceToDevice, st),
+                "copy u");
+    xr = ur;
   }
 
   double half_sweep() {
@@ -1512,6 +1689,10 @@ static void check_opts(const tnfem_solve_opts& o) {
   TNFEM_REQUIRE(o.max_sweeps >= 1, "max_sweeps must be >= 1");
   TNFEM_REQUIRE(o.cg_maxit >= 0, "cg_maxit must be >= 0");
   TNFEM_REQUIRE(o.precision >= 0 && o.precision <= 2, "precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
+  TNFEM_REQUIRE(o.ir_max >= 0 && o.ir_sweeps >= 0 && o.ir_tol >= 0 && std::isfinite(o.ir_tol),
+                "ir_max, ir_sweeps and ir_tol must be >= 0");
+  TNFEM_REQUIRE(o.ir_max == 0 || std::max(o.rank_cap, o.rho) <= 128,
+                "outer refinement needs rank_cap <= 128 (the rounding of u + d takes SVDs of 2 rank_cap columns)");
 }
 
 static void prepare_workspace(Problem& P, const tnfem_solve_opts& o) {
@@ -1581,33 +1762,71 @@ int run_solve(Problem& P, const tnfem_solve_opts& o, HostTT& out, tnfem_solve_st
   } unset;
   set_gemm_splitk_buffer(P.ws->splitk, P.ws->splitk_cap);
   Sweep sw(P, oo);
+  sw.ir_inner = o.ir_max > 0;
   sw.upload_initial();
   sw.reverse();
   sw.qr_pass();
   sw.reverse();
-  int sweeps = 0;
+  int sweeps = 0, sweeps_total = 0;
   double last = INFINITY;
   int converged = 0;
-  for (; sweeps < o.max_sweeps;) {
-    last = sw.half_sweep();
-    ++sweeps;
-    if (verbose) {
-      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      std::string rk;
-      for (int r : sw.xr) rk += std::to_string(r) + " ";
-      fprintf(stderr, "[tnfem] half-sweep %d max_res %.3e cg %lld t %.3fs ranks %s\n", sweeps, last, sw.cg_iters, el,
-              rk.c_str());
+  // half-sweeps until the local residuals meet tol or the budget is spent
+  auto run_sweeps = [&](int budget, const char* what) {
+    int done = 0;
+    converged = 0;
+    for (; done < budget;) {
+      last = sw.half_sweep();
+      ++done;
+      ++sweeps_total;
+      if (verbose) {
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        std::string rk;
+        for (int r : sw.xr) rk += std::to_string(r) + " ";
+        fprintf(stderr, "[tnfem] %s half-sweep %d max_res %.3e cg %lld t %.3fs ranks %s\n", what, done, last,
+                sw.cg_iters, el, rk.c_str());
+      }
+      if (sw.nan_seen || !std::isfinite(last)) break;
+      sw.reverse();
+      if (last <= o.tol) {
+        converged = 1;
+        break;
+      }
     }
-    if (sw.nan_seen || !std::isfinite(last)) break;
-    sw.reverse();
-    if (last <= o.tol) {
-      converged = 1;
-      break;
+    return done;
+  };
+  sweeps = run_sweeps(o.max_sweeps, "solve");
+  int ir_iters = 0;
+  double ir_update = 0.0;
+  if (o.ir_max > 0 && !sw.nan_seen && std::isfinite(last)) {
+    // outer refinement: correction solves on b - A u, u <- round(u + d) in FP64
+    P.ensure_ir(o.rank_cap, rho);
+    const double ir_tol = o.ir_tol > 0 ? o.ir_tol : o.tol;
+    const int ir_sweeps = o.ir_sweeps > 0 ? o.ir_sweeps : o.max_sweeps;
+    for (int it = 1; it <= o.ir_max; ++it) {
+      if (sw.orient) sw.reverse();
+      sw.begin_correction(*P.ws->ir, o.seed_x + it, o.seed_z + it);
+      run_sweeps(ir_sweeps, "correction");
+      if (sw.nan_seen || !std::isfinite(last)) break;
+      if (sw.orient) sw.reverse();
+      ir_update = sw.add_correction(*P.ws->ir, 0.1 * ir_tol, o.rank_cap);
+      ir_iters = it;
+      if (verbose) fprintf(stderr, "[tnfem] refinement %d: ||d|| / ||u|| = %.3e\n", it, ir_update);
+      if (!std::isfinite(ir_update)) {
+        sw.nan_seen = 1;
+        break;
+      }
+      if (ir_update <= ir_tol) break;
     }
+    if (sw.orient) sw.reverse();
+    sw.take_u();
+    converged = ir_update <= ir_tol && !sw.nan_seen;
   }
   finish_sweep(P, sw, out);
   const auto t1 = std::chrono::steady_clock::now();
   fill_stats(sw, sweeps, converged, last, std::chrono::duration<double>(t1 - t0).count(), stats);
+  stats.ir_iters = ir_iters;
+  stats.ir_last_update = ir_update;
+  stats.sweeps_total = sweeps_total;
   if (o.profile && P.ws->profile) {
     double fl = 0.0;
     long cnt = 0;
@@ -1629,6 +1848,7 @@ int run_solve_batch(std::vector<Problem*>& Ps, const tnfem_solve_opts& o, std::v
   const int nb = (int)Ps.size();
   TNFEM_REQUIRE(nb >= 1 && nb <= FB_MAX, "a batch holds 1 .. %d problems", FB_MAX);
   TNFEM_REQUIRE(o.precision == 0, "batched solves run in FP64 (precision 0)");
+  TNFEM_REQUIRE(o.ir_max == 0, "batched solves do not run the outer refinement");
   TNFEM_REQUIRE(!o.profile, "batched solves do not record per-launch profiles");
   Context* ctx = Ps[0]->ctx;
   for (Problem* P : Ps) {

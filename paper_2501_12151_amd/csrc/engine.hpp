@@ -78,6 +78,18 @@ struct Context {
 
 struct Problem;
 
+// Buffers of the outer iterative refinement (allocated on first use): the refined solution
+// u (K cores), the interfaces between the iterate and u through A (X-A-u, Z-A-u; K + 1 bonds
+// each), the cores of u + d before rounding, and the thin-SVD scratch of the rounding.
+struct IrBuffers {
+  int cap = 0, rho = 0;
+  DevArena arena;
+  std::vector<double*> U, EuA, EzuA, Sum;
+  double *uspare = nullptr, *t1 = nullptr, *t2 = nullptr, *su = nullptr, *ss = nullptr, *svt = nullptr,
+         *svdws = nullptr;
+  size_t sum_cap = 0, svdws_cap = 0;
+};
+
 // Workspace of one problem for a given rank cap.
 struct Workspace {
   int cap = 0, rho = 0;
@@ -107,6 +119,7 @@ struct Workspace {
   void* host_pinned = nullptr;
   size_t bytes = 0;
   std::unique_ptr<GemmProfile> profile;
+  std::unique_ptr<IrBuffers> ir;  // outer refinement (allocated on first use)
   ~Workspace() {
     if (host_pinned) (void)hipHostFree(host_pinned);
   }
@@ -130,6 +143,7 @@ struct Problem {
   std::unique_ptr<Workspace> ws;
   void ensure_workspace(int cap, int rho);
   size_t workspace_bytes(int cap, int rho) const;  // device bytes ensure_workspace would allocate
+  void ensure_ir(int cap, int rho);                 // refinement buffers (after ensure_workspace)
 };
 
 // Host TT object.

@@ -182,5 +182,23 @@ int trunc_rank(const double* s, int len, double tol, int cap) {
   return std::max(1, std::min(r, cap));
 }
 
+double tt_norm(std::vector<int> modes, std::vector<int> ranks, std::vector<std::vector<double>> cores) {
+  const int K = (int)modes.size();
+  for (int k = 0; k + 1 < K; ++k) {
+    const int m = ranks[k] * modes[k], nc = ranks[k + 1];
+    std::vector<double> Q, R;
+    qr(m, nc, cores[k].data(), Q, R);
+    const int c = std::min(m, nc);
+    const int cols = modes[k + 1] * ranks[k + 2];
+    std::vector<double> next((size_t)c * cols);
+    gemm(c, cols, nc, R.data(), cores[k + 1].data(), next.data());
+    cores[k + 1].swap(next);
+    ranks[k + 1] = c;
+  }
+  double s = 0.0;
+  for (double v : cores[K - 1]) s += v * v;
+  return std::sqrt(s);
+}
+
 }  // namespace hostla
 }  // namespace tnfem

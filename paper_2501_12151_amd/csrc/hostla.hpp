@@ -21,5 +21,9 @@ void gemm(int m, int n, int k, const double* A, const double* B, double* C);
 // Rank kept by truncation: smallest r with sum_{j>=r} s_j^2 <= tol^2 sum s^2, in [1, cap].
 int trunc_rank(const double* s, int len, double tol, int cap);
 
+// Frobenius norm of a TT (cores row-major [r_k][n_k][r_{k+1}]): QR of each unfolding, R carried
+// into the next core.
+double tt_norm(std::vector<int> modes, std::vector<int> ranks, std::vector<std::vector<double>> cores);
+
 }  // namespace hostla
 }  // namespace tnfem

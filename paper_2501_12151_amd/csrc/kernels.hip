@@ -2992,3 +2992,56 @@ void launch_nan_check(long n, const double* x, int* flag, hipStream_t s) {
 }
 
 }  // namespace tnfem
+
+// ----------------------------------------------------------------------------- thin SVD
+
+namespace tnfem {
+
+// Workspace: the input in tall orientation, Q, R, the Jacobi factors and the larger of the
+// QR's and the Jacobi kernel's own workspace.
+size_t svd_ws_doubles(int m, int n) {
+  const int mm = std::max(m, n), nn = std::min(m, n);
+  return (size_t)mm * nn * 2 + (size_t)nn * nn * 3 +
+         std::max(qr_ws_doubles(mm, nn), (size_t)nn * nn * 3 + 3 * nn) + 8;
+}
+
+void svd_device(int m, int n, const double* A, double* U, double* S, double* Vt, double* ws, size_t ws_cap,
+                hipStream_t st) {
+  const bool tall = m >= n;
+  const int mm = tall ? m : n, nn = tall ? n : m;  // work on the tall orientation
+  if (ws_cap < svd_ws_doubles(m, n)) throw Error(TNFEM_EINVAL, "SVD workspace too small");
+  double* At = ws;                       // mm x nn (transposed input when wide)
+  double* Q = At + (size_t)mm * nn;      // mm x nn
+  double* R = Q + (size_t)mm * nn;       // nn x nn
+  double* UR = R + (size_t)nn * nn;      // nn x nn
+  double* V = UR + (size_t)nn * nn;      // nn x nn
+  double* qws = V + (size_t)nn * nn;     // QR workspace, then the Jacobi kernel's
+  const double* src = A;
+  if (!tall) {
+    launch_core_transpose(m, 1, n, A, At, st);  // At = A^T (n x m)
+    src = At;
+  }
+  const size_t qws_cap = ws_cap - (size_t)(qws - ws);
+  launch_qr(mm, nn, src, nn, Q, nn, R, nn, qws, qws_cap, st);
+  launch_jacobi_svd(nn, R, nn, V, S, UR, qws, st, 1);  // on R^T: outputs swapped
+  GemmDesc g;
+  if (tall) {
+    // U = Q UR (m x n); Vt = V^T
+    g.A = Q; g.a_sm = nn; g.a_sk = 1;
+    g.B = UR; g.b_sk = nn; g.b_sn = 1;
+    g.C = U; g.c_sm = nn; g.c_sn = 1;
+    g.M = mm; g.N = nn; g.K = nn;
+    launch_gemm(g, st);
+    launch_core_transpose(nn, 1, nn, V, Vt, st);
+  } else {
+    // A^T = (Q UR) S V^T  =>  A = V S (Q UR)^T: U = V (m x m), Vt = (Q UR)^T (m x n)
+    launch_copy2d(nn, nn, V, nn, U, nn, 1.0, 0.0, st);
+    g.A = UR; g.a_sm = 1; g.a_sk = nn;   // UR^T
+    g.B = Q; g.b_sk = 1; g.b_sn = nn;    // Q^T
+    g.C = Vt; g.c_sm = mm; g.c_sn = 1;
+    g.M = nn; g.N = mm; g.K = nn;
+    launch_gemm(g, st);
+  }
+}
+
+}  // namespace tnfem

@@ -283,6 +283,14 @@ void launch_sub(long n, const double* a, const double* b, double* out, hipStream
 // flag[k] = 1 if any of the n values is not finite (OR accumulated).
 void launch_nan_check(long n, const double* x, int* flag, hipStream_t s);
 
+// Thin SVD A = U diag(S) Vt of an m x n row-major matrix (c = min(m, n) <= 256): Householder
+// QR of the tall orientation, then one-sided Jacobi on R^T.  U: m x c, S: c (descending),
+// Vt: c x n, all row-major.  ws holds ws_cap >= svd_ws_doubles(m, n) doubles and needs no
+// initial contents (throws TNFEM_EINVAL otherwise, nothing launched).
+size_t svd_ws_doubles(int m, int n);
+void svd_device(int m, int n, const double* A, double* U, double* S, double* Vt, double* ws, size_t ws_cap,
+                hipStream_t st);
+
 // Fixed workspace of the allocation-free entry points: TNFEM_NOALLOC_SCRATCH_BYTES per
 // device.  noalloc_init (device current or not) resolves that device's address once;
 // noalloc_scratch returns it, or throws TNFEM_EDEVICE when it could not be resolved.

@@ -58,6 +58,7 @@ class SolveOpts(C.Structure):
         ("rank_cap", C.c_int), ("tol", C.c_double), ("max_sweeps", C.c_int), ("rho", C.c_int),
         ("init_rank", C.c_int), ("seed_x", C.c_uint64), ("seed_z", C.c_uint64), ("cg_maxit", C.c_int),
         ("precision", C.c_int), ("profile", C.c_int),
+        ("ir_max", C.c_int), ("ir_sweeps", C.c_int), ("ir_tol", C.c_double),
     ]
 
 
@@ -71,6 +72,7 @@ class SolveStats(C.Structure):
         ("contraction_flops", C.c_double), ("contraction_launches", C.c_longlong),
         ("apply_kernel_ms", C.c_double), ("apply_kernel_flops", C.c_double),
         ("apply_kernel_launches", C.c_longlong), ("peak_rank", C.c_int),
+        ("ir_iters", C.c_int), ("ir_last_update", C.c_double), ("sweeps_total", C.c_int),
     ]
 
     def as_dict(self):

@@ -58,6 +58,19 @@ def test_full_size_manufactured_cube_matches_oracle(c3, precision):
     assert pt <= 1e-6
 
 
+@pytest.mark.parametrize("precision", [1, 2])
+def test_full_size_cube_with_outer_refinement_matches_oracle(c3, precision):
+    """The same cube with the outer FP64 iterative refinement (24 half-sweeps, then one
+    correction solve of 4 half-sweeps and the FP64 rounding of u + d)."""
+    prob, P, X = c3
+    U, st, rc = P.solve(precision=precision, ir_max=1, ir_sweeps=4, ir_tol=1e-7, **C3_OPTS)
+    rel = tt.tt_rel_diff(U.cores, X)
+    print(f"  precision {precision} + refinement: {st['ir_iters']} step(s), ||d||/||u|| {st['ir_last_update']:.2e}, "
+          f"rel.diff vs oracle {rel:.2e}", flush=True)
+    assert st["ir_iters"] == 1
+    assert rel <= 1e-6
+
+
 def _layers(n):
     return np.where((np.arange(n - 1) >> 5) & 1, 10.0, 1.0).tolist()
 
