@@ -109,6 +109,20 @@ typedef struct {
    * The clamped dofs get the diagonal max_i C_ii h^(D-2) (normal components i). */
   int has_stiffness;
   double stiffness[6][6];
+  /* Optional quadrilateral domain (2D, Sec. 5: "any quadrilateral"): corners P00, P10, P01,
+   * P11 (x, y), the images of the unit-square corners (s, t) = (0,0), (1,0), (0,1), (1,1)
+   * under the bilinear map; node (i, j) sits at x(i / (2^d - 1), j / (2^d - 1)) and extent
+   * is ignored.  Alg. 1 in full: element Jacobians and determinants at the element centres,
+   * the coefficient fields over the element grid compressed to QTT, placed at node pairs by
+   * corner-pair shift automata; clamps and tractions name the four sides as faces
+   * (TNFEM_FACE(0, 0) is the side P00-P01, (0, 1) P10-P11, (1, 0) P00-P10, (1, 1) P01-P11;
+   * a traction is per unit length of the side).  The corners must make every element's
+   * det J positive (convex, counterclockwise); level <= 8; no layer_E, no manufactured
+   * load.  The host assembly samples the fields on (2^d)^2 elements and rounds the products
+   * of the fields with the automata by TT-SVD on the host: about 4 s at level 4 and 80 s at
+   * level 5 (the rounding cost grows with the third power of the product ranks). */
+  int has_quad;
+  double quad[4][2];
 } tnfem_problem_desc;
 
 /*

@@ -178,6 +178,100 @@ class Grid:
         return self.node_index(elems[:, None, :] + bits[None, :, :]), elems
 
 
+# ----------------------------------------------------------------------------- quadrilateral domains
+
+def quad_corners(corners):
+    """Corners of a quadrilateral domain as a [4, 2] array in the order P00, P10, P01, P11
+    (images of the unit-square corners (s, t) = (0,0), (1,0), (0,1), (1,1))."""
+    P = np.asarray(corners, dtype=np.float64).reshape(4, 2)
+    return P
+
+
+def quad_map(corners, s, t):
+    """Bilinear map of the unit square onto the quadrilateral: x(s, t) (arrays broadcast)."""
+    P = quad_corners(corners)
+    s = np.asarray(s, dtype=np.float64)[..., None]
+    t = np.asarray(t, dtype=np.float64)[..., None]
+    return P[0] * (1 - s) * (1 - t) + P[1] * s * (1 - t) + P[2] * (1 - s) * t + P[3] * s * t
+
+
+class QuadGrid(Grid):
+    """2^d x 2^d nodes on a quadrilateral (Sec. 5): node (i, j) at x(i / (2^d - 1), j / (2^d - 1))."""
+
+    def __init__(self, d: int, corners):
+        super().__init__(2, d)
+        self.corners = quad_corners(corners)
+
+    def node_coords(self):
+        ij = np.array(list(itertools.product(range(self.n), repeat=2)), dtype=np.float64) / (self.n - 1)
+        return quad_map(self.corners, ij[:, 0], ij[:, 1])
+
+
+def quad_element_matrices(xc, C, frozen: bool = True):
+    """Stiffness and scalar mass of one Q1 element with corner coordinates xc[c, 2] (corner c
+    in the order of corner_bits(2)).  The element map Phi(xi) = sum_c x_c phi_c(xi) has the
+    Jacobian J(xi) = sum_c x_c (x) grad phi_c(xi); gradients are J^{-T} times reference
+    gradients (eq. grads), the integrand is weighted by det J (eq. elassembly), and the
+    element stiffness is the integral of C grad(v) : grad(u) over the 2-point Gauss rule.
+    frozen=True takes J and det J at the element centre xi = (0, 0) for every quadrature
+    point (Alg. 1 evaluates them there), which is exact for parallelograms; frozen=False
+    is the isoparametric element (J at each Gauss point, exact for the bilinear element)."""
+    xc = np.asarray(xc, dtype=np.float64)
+    pts, wts = gauss_points(2)
+    nc = 4
+    Ke = np.zeros((2 * nc, 2 * nc))
+    Me = np.zeros((nc, nc))
+    _, d0 = ref_shape(2, np.zeros(2))
+    J0 = xc.T @ d0  # J[k, gamma] = sum_c x_c[k] dphi_c/dxi_gamma
+    for xi, w in zip(pts, wts):
+        phi, dphi = ref_shape(2, xi)
+        J = J0 if frozen else xc.T @ dphi
+        det = np.linalg.det(J)
+        grad = dphi @ np.linalg.inv(J)  # grad[c, alpha] = sum_gamma dphi[c, gamma] (J^-1)[gamma, alpha]
+        Me += w * det * np.outer(phi, phi)
+        for a in range(2):
+            for b in range(2):
+                # sum_{alpha beta} C[a, alpha, b, beta] grad_p[alpha] grad_q[beta]
+                Ke[a * nc:(a + 1) * nc, b * nc:(b + 1) * nc] += w * det * grad @ C[a, :, b, :] @ grad.T
+    return Ke, Me
+
+
+def assemble_quad(grid: QuadGrid, C, frozen: bool = True):
+    """Global stiffness (2 n^2 dofs, natural order) and scalar mass (n^2 nodes) on a
+    quadrilateral grid, element by element."""
+    x = grid.node_coords()
+    enodes, elems = grid.element_nodes()
+    nc = 4
+    rows, cols, vals, mr, mc, mv = [], [], [], [], [], []
+    for e in range(len(elems)):
+        nodes = enodes[e]
+        Ke, Me = quad_element_matrices(x[nodes], C, frozen)
+        dofs = np.concatenate([a * grid.n_nodes + nodes for a in range(2)])
+        rows.append(np.repeat(dofs, 2 * nc)); cols.append(np.tile(dofs, 2 * nc)); vals.append(Ke.reshape(-1))
+        mr.append(np.repeat(nodes, nc)); mc.append(np.tile(nodes, nc)); mv.append(Me.reshape(-1))
+    K = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(grid.n_dofs, grid.n_dofs)).tocsr()
+    M = sp.coo_matrix((np.concatenate(mv), (np.concatenate(mr), np.concatenate(mc))),
+                      shape=(grid.n_nodes, grid.n_nodes)).tocsr()
+    return K, M
+
+
+def quad_traction_load(grid: QuadGrid, axis: int, side: int, t):
+    """Load of a uniform traction t on one straight side of the quadrilateral: the 1D mass
+    row sums along the side (length L, node spacing L / (n - 1)) times t."""
+    P = grid.corners
+    ends = {(0, 0): (0, 2), (0, 1): (1, 3), (1, 0): (0, 1), (1, 1): (2, 3)}[(axis, side)]
+    L = np.linalg.norm(P[ends[1]] - P[ends[0]])
+    h = L / (grid.n - 1)
+    m = np.full(grid.n, h)
+    m[0] = m[-1] = 0.5 * h
+    b = np.zeros(grid.n_dofs)
+    nodes = face_nodes(grid, axis, side)
+    for c in range(2):
+        b[c * grid.n_nodes + nodes] += t[c] * m
+    return b
+
+
 def assemble(grid: Grid, lam: float, mu: float, elem_weight=None, C=None):
     """Global stiffness K and scalar mass M by element-by-element assembly (Sec. 3).
 
@@ -337,6 +431,8 @@ def build_system(problem: dict):
     the element integrals, layered_E / E still scales it).
     """
     D, d = problem["dim"], problem["level"]
+    if problem.get("quad") is not None:
+        return _build_quad_system(problem)
     grid = Grid(D, d, problem.get("extent"))
     lam, mu = lame(problem["E"], problem["nu"], problem.get("plane_stress", False))
     weight = None
@@ -362,6 +458,32 @@ def build_system(problem: dict):
         b += traction_load(grid, axis, side, t)
     mask = clamp_mask(grid, problem.get("clamp", []))
     alpha = bc_alpha(grid, lam, mu, C)
+    A, bb = apply_dirichlet(K, b, mask, alpha)
+    return A, bb, grid, dict(K=K, M=M, b_raw=b, mask=mask, lam=lam, mu=mu, alpha=alpha)
+
+
+def _build_quad_system(problem: dict):
+    """build_system on a quadrilateral domain (2D; key quad = corners P00, P10, P01, P11):
+    stiffness with the Jacobian frozen at element centres (problem key quad_rule =
+    "isoparametric" for the exact bilinear element), consistent mass, loads and clamps as on
+    the box (the sides are the parametric faces)."""
+    D, d = problem["dim"], problem["level"]
+    assert D == 2, "quadrilateral domains are 2D"
+    grid = QuadGrid(d, problem["quad"])
+    lam, mu = lame(problem["E"], problem["nu"], problem.get("plane_stress", False))
+    C = material_tensor(problem)
+    frozen = problem.get("quad_rule", "frozen") == "frozen"
+    K, M = assemble_quad(grid, C, frozen)
+    b = np.zeros(grid.n_dofs)
+    if problem.get("body_force") is not None:
+        f0 = np.repeat(np.asarray(problem["body_force"], dtype=np.float64)[:D, None], grid.n_nodes, axis=1)
+        b += body_load(grid, M, f0)
+    if problem.get("f_nodal_tt") is not None:
+        b += body_load(grid, M, nodal_values_from_tt(problem["f_nodal_tt"], D, d))
+    for axis, side, t in problem.get("tractions", []):
+        b += quad_traction_load(grid, axis, side, t)
+    mask = clamp_mask(grid, problem.get("clamp", []))
+    alpha = max(C[i, i, i, i] for i in range(D))
     A, bb = apply_dirichlet(K, b, mask, alpha)
     return A, bb, grid, dict(K=K, M=M, b_raw=b, mask=mask, lam=lam, mu=mu, alpha=alpha)
 

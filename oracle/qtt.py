@@ -179,6 +179,18 @@ def _attach_component(comp_core, levels, component_first):
     return [comp_core] + levels if component_first else levels + [comp_core]
 
 
+def _dense_operator_qtt(A_nat, D, d, eps, component_first):
+    """MPO of a dense (natural-order) operator by TT-SVD over the paired (out, in) indices of
+    each core (tiny grids only)."""
+    Aq = matrix_to_qtt_order(A_nat, D, d, component_first).toarray()
+    modes = [D] + [2 ** D] * d if component_first else [2 ** D] * d + [D]
+    K = len(modes)
+    T = Aq.reshape(modes + modes)
+    T = T.transpose([x for k in range(K) for x in (k, K + k)]).reshape([m * m for m in modes])
+    cores = tt.tt_svd(T, [m * m for m in modes], eps=eps)
+    return [C.reshape(C.shape[0], m, m, C.shape[2]) for C, m in zip(cores, modes)]
+
+
 def assemble_operator(problem: dict, eps=1e-14, component_first=False):
     """QTT operator A_bc: component core + d level cores, rounded at eps.
 
@@ -191,6 +203,10 @@ def assemble_operator(problem: dict, eps=1e-14, component_first=False):
     puts the component index last.
     """
     D, d = problem["dim"], problem["level"]
+    if problem.get("quad") is not None:
+        # quadrilateral domain: the sparse element-by-element operator, compressed by TT-SVD
+        A, _, _, _ = fem.build_system(problem)
+        return _dense_operator_qtt(A, D, d, eps, component_first)
     n = 2 ** d
     extent = np.ones(D) if problem.get("extent") is None else np.asarray(problem["extent"], float)[:D]
     lam, mu = fem.lame(problem["E"], problem["nu"], problem.get("plane_stress", False))
@@ -252,6 +268,10 @@ def manufactured_terms(D, lam, mu, c):
 def assemble_load(problem: dict, eps=1e-14, component_first=False):
     """QTT of b = P (M f0 + tractions): component core + d level cores (order as in assemble_operator)."""
     D, d = problem["dim"], problem["level"]
+    if problem.get("quad") is not None:
+        _, bq, _, _ = fem.build_system(problem)
+        modes = [D] + [2 ** D] * d if component_first else [2 ** D] * d + [D]
+        return tt.tt_svd(to_qtt_order(bq, D, d, component_first).reshape(modes), modes, eps)
     n = 2 ** d
     extent = np.ones(D) if problem.get("extent") is None else np.asarray(problem["extent"], float)[:D]
     lam, mu = fem.lame(problem["E"], problem["nu"], problem.get("plane_stress", False))

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtnfem.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "noalloc.hip", "engine.cpp", "assembly.cpp", "hostla.cpp", "capi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "engine.cpp", "assembly.cpp", "hostla.cpp", "capi.cpp", "server.cpp", "quad.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # no packed FP32 instructions anywhere in device code

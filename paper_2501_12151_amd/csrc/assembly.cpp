@@ -220,6 +220,9 @@ struct Atom {
 };
 
 // Dense TT-SVD of a vector of length 2^d into d QTT cores [r][2][r'].
+}  // namespace
+
+// QTT of a vector of 2^d entries by TT-SVD (relative accuracy 1e-15), levels most significant first.
 std::vector<TTCore> vector_qtt(const std::vector<double>& v, int d) {
   std::vector<TTCore> cores;
   std::vector<double> rest = v;  // r x cols, row-major
@@ -325,6 +328,8 @@ std::vector<TTCore> tt_sum(const std::vector<TTCore>& x, const std::vector<TTCor
   }
   return out;
 }
+
+namespace {
 
 // ----------------------------------------------------------------------------- nodal load f0
 
@@ -619,6 +624,7 @@ std::vector<double> stiffness_tensor(const tnfem_problem_desc& desc, int D, doub
 }
 
 Assembled assemble(const tnfem_problem_desc& desc) {
+  if (desc.has_quad) return assemble_quad(desc);
   const int D = desc.dim, d = desc.level;
   TNFEM_REQUIRE(D == 2 || D == 3, "dim must be 2 or 3 (got %d)", D);
   TNFEM_REQUIRE(d >= 2 && d <= 20, "level must be in [2, 20] (got %d)", d);

@@ -42,6 +42,17 @@ std::vector<double> stiffness_tensor(const tnfem_problem_desc& desc, int D, doub
 // Doubles of the nodal load f0 (0 without one); validates its ranks (throws tnfem::Error).
 size_t f0_doubles(const tnfem_problem_desc& desc);
 
+// QTT of a vector of 2^d entries (levels most significant first) by TT-SVD.
+std::vector<TTCore> vector_qtt(const std::vector<double>& v, int d);
+// Level cores of the Kronecker product of per-axis QTT vectors (axis 0 most significant bit).
+std::vector<TTCore> kron_vector_levels(const std::vector<std::vector<TTCore>>& axes);
+// Direct sum of two TTs with equal modes (ranks add).
+std::vector<TTCore> tt_sum(const std::vector<TTCore>& x, const std::vector<TTCore>& y);
+
+// Operator and load on a quadrilateral domain (desc.has_quad; 2D), Alg. 1 with the element
+// Jacobians frozen at the element centres.
+Assembled assemble_quad(const tnfem_problem_desc& desc);
+
 // TT rounding on the host (relative accuracy tol, at most rmax).
 void tt_round_host(std::vector<TTCore>& cores, double tol, int rmax);
 

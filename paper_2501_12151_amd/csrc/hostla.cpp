@@ -77,66 +77,67 @@ void qr(int m, int n, const double* A, std::vector<double>& Q, std::vector<doubl
     for (int j = 0; j < c; ++j) Q[(size_t)i * c + j] = Qc[(size_t)j * m + i];
 }
 
-// One-sided Jacobi SVD of a square n x n matrix G (row-major): G = U diag(S) V^T.
-static void jacobi_square(int n, std::vector<double> G, std::vector<double>& U, std::vector<double>& S,
+// One-sided Jacobi SVD of a square n x n matrix G (row-major): G = U diag(S) V^T.  The
+// columns are rotated in a column-major copy (each column contiguous in memory).
+static void jacobi_square(int n, const std::vector<double>& Grow, std::vector<double>& U, std::vector<double>& S,
                           std::vector<double>& V) {
-  V.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  std::vector<double> G((size_t)n * n), Vc((size_t)n * n, 0.0);  // column-major
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) G[(size_t)j * n + i] = Grow[(size_t)i * n + j];
+  for (int i = 0; i < n; ++i) Vc[(size_t)i * n + i] = 1.0;
   const double eps = 1e-15;
   for (int sweep = 0; sweep < 60; ++sweep) {
     bool rotated = false;
     for (int p = 0; p < n - 1; ++p) {
+      double* gp = &G[(size_t)p * n];
+      double* vp = &Vc[(size_t)p * n];
       for (int q = p + 1; q < n; ++q) {
+        double* gq = &G[(size_t)q * n];
         double a = 0, b = 0, c = 0;
         for (int i = 0; i < n; ++i) {
-          const double gp = G[(size_t)i * n + p], gq = G[(size_t)i * n + q];
-          a += gp * gp;
-          b += gq * gq;
-          c += gp * gq;
+          a += gp[i] * gp[i];
+          b += gq[i] * gq[i];
+          c += gp[i] * gq[i];
         }
         if (c == 0.0 || std::fabs(c) <= eps * std::sqrt(a * b)) continue;
         rotated = true;
         const double zeta = (b - a) / (2.0 * c);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        double* vq = &Vc[(size_t)q * n];
         for (int i = 0; i < n; ++i) {
-          double& gp = G[(size_t)i * n + p];
-          double& gq = G[(size_t)i * n + q];
-          const double x = gp, y = gq;
-          gp = cs * x - sn * y;
-          gq = sn * x + cs * y;
-          double& vp = V[(size_t)i * n + p];
-          double& vq = V[(size_t)i * n + q];
-          const double xv = vp, yv = vq;
-          vp = cs * xv - sn * yv;
-          vq = sn * xv + cs * yv;
+          const double x = gp[i], y = gq[i];
+          gp[i] = cs * x - sn * y;
+          gq[i] = sn * x + cs * y;
+          const double xv = vp[i], yv = vq[i];
+          vp[i] = cs * xv - sn * yv;
+          vq[i] = sn * xv + cs * yv;
         }
       }
     }
     if (!rotated) break;
   }
   S.assign(n, 0.0);
-  U.assign((size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
     double s = 0;
-    for (int i = 0; i < n; ++i) s += G[(size_t)i * n + j] * G[(size_t)i * n + j];
+    for (int i = 0; i < n; ++i) s += G[(size_t)j * n + i] * G[(size_t)j * n + i];
     S[j] = std::sqrt(s);
   }
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return S[x] > S[y]; });
-  std::vector<double> S2(n), U2((size_t)n * n, 0.0), V2((size_t)n * n);
+  std::vector<double> S2(n);
+  U.assign((size_t)n * n, 0.0);
+  V.assign((size_t)n * n, 0.0);
   for (int jj = 0; jj < n; ++jj) {
     const int j = order[jj];
     S2[jj] = S[j];
     for (int i = 0; i < n; ++i) {
-      U2[(size_t)i * n + jj] = S[j] > 0 ? G[(size_t)i * n + j] / S[j] : (i == jj ? 1.0 : 0.0);
-      V2[(size_t)i * n + jj] = V[(size_t)i * n + j];
+      U[(size_t)i * n + jj] = S[j] > 0 ? G[(size_t)j * n + i] / S[j] : (i == jj ? 1.0 : 0.0);
+      V[(size_t)i * n + jj] = Vc[(size_t)j * n + i];
     }
   }
   S = S2;
-  U = U2;
-  V = V2;
 }
 
 void svd(int m, int n, const double* A, std::vector<double>& U, std::vector<double>& S,

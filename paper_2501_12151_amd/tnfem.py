@@ -50,6 +50,7 @@ class ProblemDesc(C.Structure):
         ("layer_axis", C.c_int), ("n_layer_E", C.c_int), ("layer_E", C.POINTER(C.c_double)),
         ("f0_ranks", C.POINTER(C.c_int)), ("f0_cores", C.POINTER(C.c_double)),
         ("has_stiffness", C.c_int), ("stiffness", (C.c_double * 6) * 6),
+        ("has_quad", C.c_int), ("quad", (C.c_double * 2) * 4),
     ]
 
 
@@ -192,6 +193,12 @@ def make_desc(problem: dict) -> ProblemDesc:
         for i in range(Cv.shape[0]):
             for j in range(Cv.shape[1]):
                 d.stiffness[i][j] = float(Cv[i, j])
+    if problem.get("quad") is not None:
+        Q = np.asarray(problem["quad"], dtype=np.float64).reshape(4, 2)
+        d.has_quad = 1
+        for c in range(4):
+            for k in range(2):
+                d.quad[c][k] = float(Q[c, k])
     if problem.get("f_nodal_tt") is not None:
         cores = [np.asarray(c, dtype=np.float64) for c in problem["f_nodal_tt"]]
         ranks = np.ascontiguousarray([c.shape[0] for c in cores] + [cores[-1].shape[2]], dtype=np.int32)

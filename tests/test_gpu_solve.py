@@ -36,6 +36,9 @@ SMALL = [
          stiffness_voigt=workloads.random_anisotropic_voigt(2, 1)),
     dict(dim=3, level=3, E=2.0, nu=0.3, clamp=[(2, 0)], tractions=[(2, 1, [0.0, 0.0, -1.0])],
          layered_E=(2, [2.0, 2.0, 20.0, 20.0, 2.0, 2.0, 20.0]), stiffness_voigt=workloads.orthotropic_voigt(3, 1.0, 3.0, 0.5)),
+    # quadrilateral domain (Alg. 1 in full: a trapezoid, slanted side loaded)
+    dict(dim=2, level=4, E=1.0, nu=0.3, quad=[[0.0, 0.0], [2.0, 0.0], [0.0, 1.0], [1.4, 0.7]], clamp=[(0, 0)],
+         tractions=[(0, 1, [0.3, -1.0])], body_force=[0.0, -0.5]),
     # nodal load f0 given as a TT (Alg. 2 input)
     dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], f_nodal_tt=_nodal_tt(3, 3, 2, seed=5)),
     dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(1, 0)], f_nodal_tt=_nodal_tt(2, 4, 3, seed=6)),

@@ -119,6 +119,50 @@ def test_nodal_load_rejects_bad_ranks(ranks):
     assert rc == tnfem.EINVAL
 
 
+TRAPEZOID = [[0.0, 0.0], [2.0, 0.0], [0.0, 1.0], [1.4, 0.7]]
+QUAD_CASES = [
+    dict(dim=2, level=2, E=1.0, nu=0.3, quad=TRAPEZOID, clamp=[], body_force=[0.0, -1.0]),
+    dict(dim=2, level=3, E=1.0, nu=0.3, quad=TRAPEZOID, clamp=[(0, 0)], tractions=[(0, 1, [0.3, -1.0])],
+         body_force=[0.1, -1.0]),
+    dict(dim=2, level=3, E=68.0, nu=0.33, plane_stress=True, quad=[[0.0, 0.0], [4.0, 0.5], [0.2, 1.0], [3.6, 1.4]],
+         clamp=[(0, 0), (1, 0)], tractions=[(1, 1, [0.0, -2.0])]),
+    dict(dim=2, level=3, E=1.0, nu=0.3, quad=TRAPEZOID, clamp=[(0, 1)], stiffness_voigt=workloads.random_anisotropic_voigt(2, 4),
+         f_nodal_tt=[np.full((1, 4, 1), 0.5), np.full((1, 4, 1), 1.0), np.full((1, 4, 1), -1.0), np.array([[[0.2], [1.0]]])]),
+    dict(dim=2, level=4, E=2.0, nu=0.25, quad=TRAPEZOID, clamp=[(0, 0), (1, 1)], tractions=[(1, 0, [0.0, -1.0])]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(QUAD_CASES)))
+def test_quadrilateral_assembly_equals_sparse_fem(case):
+    """Alg. 1 in full on a quadrilateral (element Jacobians at the centres, fields in QTT,
+    corner-pair automata): the library's operator and load equal the oracle's
+    element-by-element sparse assembly with the same rule."""
+    prob = QUAD_CASES[case]
+    A, b, grid, info = fem.build_system(prob)
+    D, d = 2, prob["level"]
+    Ac = tnfem.export_operator(prob)
+    bc = tnfem.export_load(prob)
+    Ap = qtt.matrix_to_qtt_order(A, D, d).toarray()
+    assert np.abs(tt.mpo_full(Ac) - Ap).max() <= 1e-12 * np.abs(Ap).max()
+    bp = qtt.to_qtt_order(b, D, d)
+    assert np.abs(tt.tt_full(bc) - bp).max() <= 1e-12 * np.abs(bp).max()
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(quad=[[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]]), "det J"),  # P01 / P11 swapped: twisted
+    (dict(quad=TRAPEZOID, dim=3), "2D"),
+    (dict(quad=TRAPEZOID, layered_E=(0, [1.0] * 7)), "layer_E"),
+    (dict(quad=TRAPEZOID, level=9), "level"),
+])
+def test_invalid_quadrilateral_rejected(bad, msg):
+    prob = dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, -1.0])
+    prob.update(bad)
+    with pytest.raises(tnfem.TnfemError) as e:
+        tnfem.export_operator(prob)
+    assert e.value.code == tnfem.EINVAL
+    assert msg in str(e.value)
+
+
 @pytest.mark.parametrize("prob", [dict(workloads.small_2d(), level=8), workloads.cube_body_force(4),
                                   workloads.layered_cube(5)])
 def test_library_operator_matches_oracle_tt_at_larger_levels(prob):

@@ -320,3 +320,65 @@ def test_anisotropic_patch_problem_reproduces_linear_field(D, d):
     x = grid.node_coords()
     exact = grad[:, None] * x[None, :, 0]
     assert np.abs(u - exact).max() <= 1e-11 * np.abs(exact).max()
+
+
+# ----------------------------------------------------------------------------- quadrilateral domains
+
+TRAPEZOID = [[0.0, 0.0], [2.0, 0.0], [0.0, 1.0], [1.4, 0.7]]
+
+
+def test_quad_on_a_rectangle_equals_box_assembly():
+    C = fem.isotropic_tensor(*fem.lame(1.3, 0.28), 2)
+    g = fem.QuadGrid(3, [[0, 0], [2.0, 0], [0, 0.5], [2.0, 0.5]])
+    for frozen in (True, False):
+        K, M = fem.assemble_quad(g, C, frozen)
+        Kb, Mb = fem.assemble(fem.Grid(2, 3, [2.0, 0.5]), *fem.lame(1.3, 0.28))
+        assert abs(K - Kb).max() <= 1e-14 * abs(Kb).max()
+        assert abs(M - Mb).max() <= 1e-14 * abs(Mb).max()
+
+
+def test_quad_frozen_jacobian_is_exact_on_parallelograms():
+    """An affine map has one constant Jacobian per element: the centre-frozen rule equals the
+    isoparametric element exactly, which passes the rigid-body and patch tests."""
+    C = fem.voigt_to_tensor(_random_spd_voigt(2, 9), 2)
+    g = fem.QuadGrid(3, [[0, 0], [2.0, 0.3], [0.5, 1.0], [2.5, 1.3]])
+    Kf, Mf = fem.assemble_quad(g, C, True)
+    Ki, Mi = fem.assemble_quad(g, C, False)
+    assert abs(Kf - Ki).max() <= 1e-13 * abs(Ki).max() and abs(Mf - Mi).max() <= 1e-15
+    x = g.node_coords()
+    for u in (np.concatenate([np.ones(g.n_nodes), np.zeros(g.n_nodes)]),
+              np.concatenate([-x[:, 1], x[:, 0]])):
+        assert np.abs(Kf @ u).max() <= 1e-12 * abs(Kf).max()
+    assert abs(Mf.sum() - 2.0 * 1.0 + 0.3 * 0.5) <= 1e-13  # area = |det [[2, 0.3], [0.5, 1]]|
+
+
+def test_quad_trapezoid_properties_and_convergence_of_frozen_rule():
+    """On a trapezoid: the isoparametric element integrates the area exactly and reproduces
+    rigid motions; the centre-frozen rule keeps symmetry, translations, the area, and its
+    solutions approach the isoparametric ones as the elements approach parallelograms."""
+    C = fem.isotropic_tensor(*fem.lame(1.0, 0.3), 2)
+    P = np.array(TRAPEZOID)
+    u, v = P[3] - P[0], P[2] - P[1]
+    area = 0.5 * abs(u[0] * v[1] - u[1] * v[0])  # half the cross product of the diagonals
+    diffs = []
+    for d in (3, 4, 5, 6):
+        g = fem.QuadGrid(d, TRAPEZOID)
+        Kf, Mf = fem.assemble_quad(g, C, True)
+        Ki, Mi = fem.assemble_quad(g, C, False)
+        assert abs(Kf - Kf.T).max() <= 1e-14 * abs(Kf).max()
+        assert abs(Mi.sum() - area) <= 1e-12 and abs(Mf.sum() - area) <= 1e-12
+        x = g.node_coords()
+        tx = np.concatenate([np.ones(g.n_nodes), np.zeros(g.n_nodes)])
+        rot = np.concatenate([-x[:, 1], x[:, 0]])
+        assert np.abs(Kf @ tx).max() <= 1e-12 * abs(Kf).max()
+        assert np.abs(Ki @ rot).max() <= 1e-12 * abs(Ki).max()
+        probs = [dict(dim=2, level=d, E=1.0, nu=0.3, quad=TRAPEZOID, clamp=[(0, 0)], tractions=[(0, 1, [0.3, -1.0])],
+                      quad_rule=r) for r in ("frozen", "isoparametric")]
+        us = []
+        for pr in probs:
+            A, b, _, _ = fem.build_system(pr)
+            us.append(fem.direct_solve(A, b))
+        diffs.append(np.linalg.norm(us[0] - us[1]) / np.linalg.norm(us[1]))
+    # second order: the frozen Jacobian deviates by O(h) inside an element of size O(h)
+    ratios = np.array(diffs[:-1]) / np.array(diffs[1:])
+    assert np.all(ratios > 3.0), diffs
