@@ -123,6 +123,15 @@ typedef struct {
    * level 5 (the rounding cost grows with the third power of the product ranks). */
   int has_quad;
   double quad[4][2];
+  /* Optional heterogeneous material in 2D (Sec. 7, non-homogeneous materials): a weight per
+   * element, elem_weight[i * (2^d - 1) + j] for element (i, j) (i along x), positive, that
+   * scales the stiffness of that element (E(x) = w E at fixed nu, or w C).  Assembled by
+   * the quadrilateral path (a box is the rectangle with corners (0,0), (Lx,0), (0,Ly),
+   * (Lx,Ly)): the weighted coefficient fields are compressed to QTT like the Jacobian
+   * terms, so any field is accepted (its QTT rank sets the operator's).  2D only, level
+   * <= 8, not with layer_E.  Host, n_elem_weight = (2^d - 1)^2 values, copied. */
+  int n_elem_weight;
+  const double* elem_weight;
 } tnfem_problem_desc;
 
 /*
@@ -204,6 +213,19 @@ typedef struct {
  * library creates its own default-priority stream).  Fails with TNFEM_EDEVICE
  * if no device is present. */
 int tnfem_ctx_create(tnfem_ctx** out, int device, void* hip_stream);
+
+/* Device allocator hooks (Sec. 8 boundary: PyTorch supplies device memory and streams):
+ * alloc(bytes, stream, user) returns device memory on the context's device (NULL fails the
+ * call with TNFEM_ENOMEM); free(ptr, stream, user) returns it.  stream is the context's
+ * stream.  Every device allocation the context makes (problem plans and loads, solve
+ * workspaces, scratch of the primitives) goes through them; the allocation-free entry
+ * point's fixed array and the request server's own contexts do not. */
+typedef void* (*tnfem_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*tnfem_free_fn)(void* ptr, void* stream, void* user);
+/* tnfem_ctx_create with allocator hooks (both or neither; NULL = hipMalloc / hipFree).  The
+ * hooks and `user` must stay valid until the context and its problems are destroyed. */
+int tnfem_ctx_create_ex(tnfem_ctx** out, int device, void* hip_stream, tnfem_alloc_fn alloc, tnfem_free_fn free_fn,
+                        void* user);
 int tnfem_ctx_destroy(tnfem_ctx* ctx);
 
 /* Message of the last failing call in this thread (static storage). */
@@ -336,11 +358,13 @@ int tnfem_prim_local_apply_ex(tnfem_problem* prob, int k, int reversed, int p, i
 int tnfem_prim_env_update(tnfem_problem* prob, int k, int reversed, int p, int q, int s, int t,
                           const double* W, const double* L, const double* X, double* Lnew, void* stream);
 
-/* Thin Householder QR of the m x n row-major matrix A (device, m, n >= 1,
- * n <= 256): Q (m x c, c = min(m, n)) and R (c x n), device, row-major. */
+/* Reduced QR factorisation A = Q R of eq. qr (Sec. 4), the step that orthogonalises a core
+ * unfolding: Householder QR of the m x n row-major matrix A (device, m >= 1,
+ * 1 <= n <= 256); Q (m x c, c = min(m, n)) and R (c x n), device, row-major. */
 int tnfem_prim_qr(tnfem_ctx* ctx, int m, int n, const double* A, double* Q, double* R, void* stream);
 
-/* Thin SVD of the m x n row-major matrix A (device, n <= 256, m >= 1):
+/* Thin SVD of the m x n row-major matrix A (device, n <= 256, m >= 1; the factorisation
+ * behind the TT-SVD truncation of Sec. 4, built on the QR of eq. qr):
  * U (m x c), S (c), Vt (c x n), c = min(m, n), singular values descending.
  * One-sided Jacobi on the R factor of a Householder QR. */
 int tnfem_prim_svd(tnfem_ctx* ctx, int m, int n, const double* A, double* U, double* S, double* Vt, void* stream);

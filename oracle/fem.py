@@ -236,18 +236,20 @@ def quad_element_matrices(xc, C, frozen: bool = True):
     return Ke, Me
 
 
-def assemble_quad(grid: QuadGrid, C, frozen: bool = True):
+def assemble_quad(grid: QuadGrid, C, frozen: bool = True, elem_weight=None):
     """Global stiffness (2 n^2 dofs, natural order) and scalar mass (n^2 nodes) on a
-    quadrilateral grid, element by element."""
+    quadrilateral grid, element by element; elem_weight[i, j] scales element (i, j)'s
+    stiffness (a non-homogeneous material)."""
     x = grid.node_coords()
     enodes, elems = grid.element_nodes()
+    w = np.ones(len(elems)) if elem_weight is None else np.asarray(elem_weight, dtype=np.float64)[tuple(elems.T)]
     nc = 4
     rows, cols, vals, mr, mc, mv = [], [], [], [], [], []
     for e in range(len(elems)):
         nodes = enodes[e]
         Ke, Me = quad_element_matrices(x[nodes], C, frozen)
         dofs = np.concatenate([a * grid.n_nodes + nodes for a in range(2)])
-        rows.append(np.repeat(dofs, 2 * nc)); cols.append(np.tile(dofs, 2 * nc)); vals.append(Ke.reshape(-1))
+        rows.append(np.repeat(dofs, 2 * nc)); cols.append(np.tile(dofs, 2 * nc)); vals.append(w[e] * Ke.reshape(-1))
         mr.append(np.repeat(nodes, nc)); mc.append(np.tile(nodes, nc)); mv.append(Me.reshape(-1))
     K = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(grid.n_dofs, grid.n_dofs)).tocsr()
@@ -428,7 +430,8 @@ def build_system(problem: dict):
     f_nodal_tt: TT cores of nodal force values f0 (opt; load M f0, Alg. 2 / Sec. 5.3),
     layered_E: (axis, values per element along that axis) (opt),
     stiffness_voigt: constant anisotropic stiffness, Voigt matrix (opt; replaces E, nu in
-    the element integrals, layered_E / E still scales it).
+    the element integrals, layered_E / E still scales it), elem_weight: per-element stiffness
+    factors (opt; a non-homogeneous material).
     """
     D, d = problem["dim"], problem["level"]
     if problem.get("quad") is not None:
@@ -436,6 +439,8 @@ def build_system(problem: dict):
     grid = Grid(D, d, problem.get("extent"))
     lam, mu = lame(problem["E"], problem["nu"], problem.get("plane_stress", False))
     weight = None
+    if problem.get("elem_weight") is not None:  # per-element field (2D)
+        weight = np.asarray(problem["elem_weight"], dtype=np.float64).reshape((grid.n - 1,) * D)
     if problem.get("layered_E") is not None:
         axis, vals = problem["layered_E"]
         vals = np.asarray(vals, dtype=np.float64) / problem["E"]
@@ -473,7 +478,9 @@ def _build_quad_system(problem: dict):
     lam, mu = lame(problem["E"], problem["nu"], problem.get("plane_stress", False))
     C = material_tensor(problem)
     frozen = problem.get("quad_rule", "frozen") == "frozen"
-    K, M = assemble_quad(grid, C, frozen)
+    ew = problem.get("elem_weight")
+    ew = None if ew is None else np.asarray(ew, dtype=np.float64).reshape(grid.n - 1, grid.n - 1)
+    K, M = assemble_quad(grid, C, frozen, ew)
     b = np.zeros(grid.n_dofs)
     if problem.get("body_force") is not None:
         f0 = np.repeat(np.asarray(problem["body_force"], dtype=np.float64)[:D, None], grid.n_nodes, axis=1)

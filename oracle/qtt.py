@@ -203,8 +203,9 @@ def assemble_operator(problem: dict, eps=1e-14, component_first=False):
     puts the component index last.
     """
     D, d = problem["dim"], problem["level"]
-    if problem.get("quad") is not None:
-        # quadrilateral domain: the sparse element-by-element operator, compressed by TT-SVD
+    if problem.get("quad") is not None or problem.get("elem_weight") is not None:
+        # quadrilateral domain or a general element field: the sparse element-by-element
+        # operator, compressed by TT-SVD
         A, _, _, _ = fem.build_system(problem)
         return _dense_operator_qtt(A, D, d, eps, component_first)
     n = 2 ** d

@@ -625,6 +625,16 @@ std::vector<double> stiffness_tensor(const tnfem_problem_desc& desc, int D, doub
 
 Assembled assemble(const tnfem_problem_desc& desc) {
   if (desc.has_quad) return assemble_quad(desc);
+  if (desc.elem_weight) {
+    // a per-element field on a 2D box: the quadrilateral path on the rectangle
+    TNFEM_REQUIRE(desc.dim == 2, "elem_weight is a 2D option");
+    tnfem_problem_desc q = desc;
+    q.has_quad = 1;
+    const double c[4][2] = {{0.0, 0.0}, {desc.extent[0], 0.0}, {0.0, desc.extent[1]}, {desc.extent[0], desc.extent[1]}};
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 2; ++k) q.quad[i][k] = c[i][k];
+    return assemble_quad(q);
+  }
   const int D = desc.dim, d = desc.level;
   TNFEM_REQUIRE(D == 2 || D == 3, "dim must be 2 or 3 (got %d)", D);
   TNFEM_REQUIRE(d >= 2 && d <= 20, "level must be in [2, 20] (got %d)", d);

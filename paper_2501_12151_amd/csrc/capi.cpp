@@ -75,7 +75,13 @@ void tnfem_default_opts(tnfem_solve_opts* o) {
 }
 
 int tnfem_ctx_create(tnfem_ctx** out, int device, void* hip_stream) {
+  return tnfem_ctx_create_ex(out, device, hip_stream, nullptr, nullptr, nullptr);
+}
+
+int tnfem_ctx_create_ex(tnfem_ctx** out, int device, void* hip_stream, tnfem_alloc_fn alloc, tnfem_free_fn free_fn,
+                        void* user) {
   return guarded([&] {
+    if ((alloc == nullptr) != (free_fn == nullptr)) fail(TNFEM_EINVAL, "give both allocator hooks or neither");
     if (!out) fail(TNFEM_EINVAL, "out is NULL");
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) fail(TNFEM_EDEVICE, "no HIP device");
@@ -90,6 +96,10 @@ int tnfem_ctx_create(tnfem_ctx** out, int device, void* hip_stream) {
       tnfem::hip_check(hipStreamCreateWithFlags(&c->c.stream, hipStreamNonBlocking), "hipStreamCreate");
       c->c.own_stream = true;
     }
+    c->c.allocator.alloc = alloc;
+    c->c.allocator.free = free_fn;
+    c->c.allocator.user = user;
+    c->c.allocator.stream = c->c.stream;
     *out = c.release();
     return TNFEM_OK;
   });
@@ -100,8 +110,8 @@ int tnfem_ctx_destroy(tnfem_ctx* ctx) {
     if (!ctx) return TNFEM_OK;
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
-    if (ctx->c.scratch) (void)hipFree(ctx->c.scratch);
-    if (ctx->c.splitk) (void)hipFree(ctx->c.splitk);
+    ctx->c.allocator.release(ctx->c.scratch);
+    ctx->c.allocator.release(ctx->c.splitk);
     if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
     delete ctx;
     return TNFEM_OK;

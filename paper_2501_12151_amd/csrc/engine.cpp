@@ -36,19 +36,42 @@ void hip_check(hipError_t e, const char* what) {
 DevArena::~DevArena() { release_all(); }
 
 void DevArena::release_all() {
-  for (void* p : ptrs_) (void)hipFree(p);
+  for (void* p : ptrs_) {
+    if (alloc_) alloc_->release(p);
+    else (void)hipFree(p);
+  }
   ptrs_.clear();
   bytes_ = 0;
 }
 
-void* DevArena::alloc(size_t bytes) {
+void* DeviceAllocator::allocate(size_t bytes) const {
+  if (alloc) {
+    void* p = alloc(bytes, static_cast<void*>(stream), user);
+    if (!p) throw Error(TNFEM_ENOMEM, "the caller's device allocator returned NULL");
+    return p;
+  }
   void* p = nullptr;
+  hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  return p;
+}
+
+void DeviceAllocator::release(void* p) const {
+  if (!p) return;
+  if (alloc) {
+    if (free) free(p, static_cast<void*>(stream), user);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+void* DevArena::alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (dry_) {
     bytes_ += bytes;
     return nullptr;
   }
-  hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  void* p = alloc_ ? alloc_->allocate(bytes) : nullptr;
+  if (!alloc_) hip_check(hipMalloc(&p, bytes), "hipMalloc");
   ptrs_.push_back(p);
   bytes_ += bytes;
   return p;
@@ -69,15 +92,15 @@ template double* DevArena::upload<double>(const std::vector<double>&, hipStream_
 void Context::ensure_splitk() {
   if (!splitk) {
     splitk_cap = (size_t)1 << 22;
-    hip_check(hipMalloc(&splitk, splitk_cap * sizeof(double)), "hipMalloc split-K buffer");
+    splitk = static_cast<double*>(allocator.allocate(splitk_cap * sizeof(double)));
   }
 }
 
 double* Context::ensure_scratch(size_t doubles) {
   if (doubles > scratch_doubles) {
-    if (scratch) (void)hipFree(scratch);
+    allocator.release(scratch);
     scratch = nullptr;
-    hip_check(hipMalloc(&scratch, doubles * sizeof(double)), "hipMalloc scratch");
+    scratch = static_cast<double*>(allocator.allocate(doubles * sizeof(double)));
     scratch_doubles = doubles;
   }
   return scratch;
@@ -323,6 +346,7 @@ void upload_problem(Context* ctx, Problem& P) {
   if (P.uploaded) fail(TNFEM_EINVAL, "problem already uploaded");
   P.ctx = ctx;
   hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+  P.arena.set_allocator(&ctx->allocator);
   build_device_data(P, P.arena, ctx->stream);
   P.uploaded = true;
   hip_check(hipStreamSynchronize(ctx->stream), "upload sync");
@@ -715,6 +739,7 @@ void Problem::ensure_workspace(int cap, int rho) {
   auto W = std::make_unique<Workspace>();
   W->cap = cap;
   W->rho = rho;
+  W->arena.set_allocator(&ctx->allocator);
   layout_workspace(*this, *W, cap, rho,
                    [&](size_t d) { return static_cast<double*>(W->arena.alloc(std::max<size_t>(d, 1) * 8)); });
   W->flag = static_cast<int*>(W->arena.alloc(sizeof(int) * 8));
@@ -730,6 +755,7 @@ void Problem::ensure_ir(int cap, int rho) {
   auto B = std::make_unique<IrBuffers>();
   B->cap = cap;
   B->rho = rho;
+  B->arena.set_allocator(&ctx->allocator);
   auto A = [&](size_t d) { return static_cast<double*>(B->arena.alloc(std::max<size_t>(d, 1) * 8)); };
   const size_t rc = (size_t)std::max(cap, rho), mx = (size_t)maxn, R = (size_t)Rmax;
   const size_t core = rc * mx * rc, r2 = 2 * rc;
@@ -1442,17 +1468,18 @@ struct BatchArgs {
   CgIterArgs* d_a = nullptr;
   FusedArgs* h_f = nullptr;
   CgIterArgs* h_a = nullptr;
-  explicit BatchArgs(int n) {
-    hip_check(hipMalloc(&d_f, sizeof(FusedArgs) * n), "hipMalloc batch args");
-    hip_check(hipMalloc(&d_a, sizeof(CgIterArgs) * n), "hipMalloc batch args");
+  const DeviceAllocator& alloc;
+  BatchArgs(int n, const DeviceAllocator& a) : alloc(a) {
+    d_f = static_cast<FusedArgs*>(alloc.allocate(sizeof(FusedArgs) * n));
+    d_a = static_cast<CgIterArgs*>(alloc.allocate(sizeof(CgIterArgs) * n));
     hip_check(hipHostMalloc(reinterpret_cast<void**>(&h_f), sizeof(FusedArgs) * n, hipHostMallocDefault),
               "hipHostMalloc batch args");
     hip_check(hipHostMalloc(reinterpret_cast<void**>(&h_a), sizeof(CgIterArgs) * n, hipHostMallocDefault),
               "hipHostMalloc batch args");
   }
   ~BatchArgs() {
-    if (d_f) (void)hipFree(d_f);
-    if (d_a) (void)hipFree(d_a);
+    alloc.release(d_f);
+    alloc.release(d_a);
     if (h_f) (void)hipHostFree(h_f);
     if (h_a) (void)hipHostFree(h_a);
   }
@@ -1874,7 +1901,7 @@ int run_solve_batch(std::vector<Problem*>& Ps, const tnfem_solve_opts& o, std::v
     sw->reverse();
     sweeps.push_back(std::move(sw));
   }
-  BatchArgs args(nb);
+  BatchArgs args(nb, ctx->allocator);
   outs.assign(nb, HostTT{});
   stats.assign(nb, tnfem_solve_stats{});
   rcs.assign(nb, TNFEM_ENOTCONV);

@@ -13,6 +13,17 @@ namespace tnfem {
 
 void hip_check(hipError_t e, const char* what);
 
+// Caller-supplied device allocator (e.g. bound to torch's caching allocator); alloc == NULL
+// means hipMalloc / hipFree.
+struct DeviceAllocator {
+  tnfem_alloc_fn alloc = nullptr;
+  tnfem_free_fn free = nullptr;
+  void* user = nullptr;
+  hipStream_t stream = nullptr;
+  void* allocate(size_t bytes) const;
+  void release(void* p) const;
+};
+
 // Owner of device allocations made for one object; freed on destruction.
 class DevArena {
  public:
@@ -20,6 +31,7 @@ class DevArena {
   // sizing a problem's device memory before anything is allocated
   explicit DevArena(bool dry = false) : dry_(dry) {}
   ~DevArena();
+  void set_allocator(const DeviceAllocator* a) { alloc_ = a; }
   void* alloc(size_t bytes);
   template <class T>
   T* upload(const std::vector<T>& v, hipStream_t s);
@@ -30,6 +42,7 @@ class DevArena {
   std::vector<void*> ptrs_;
   size_t bytes_ = 0;
   bool dry_ = false;
+  const DeviceAllocator* alloc_ = nullptr;
 };
 
 // Contraction plan of one operator core in one chain orientation.
@@ -67,6 +80,7 @@ struct Context {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  DeviceAllocator allocator;  // device memory of the context's problems and scratch
   DevArena arena;
   double* scratch = nullptr;  // for primitives
   size_t scratch_doubles = 0;

@@ -280,6 +280,12 @@ Assembled assemble_quad(const tnfem_problem_desc& desc) {
   TNFEM_REQUIRE(D == 2, "a quadrilateral domain is 2D");
   TNFEM_REQUIRE(d >= 2 && d <= 8, "level must be in [2, 8] on a quadrilateral domain (got %d)", d);
   TNFEM_REQUIRE(desc.layer_E == nullptr, "layer_E does not combine with a quadrilateral domain");
+  const int nel = (1 << d) - 1;
+  if (desc.elem_weight) {
+    TNFEM_REQUIRE(desc.n_elem_weight == nel * nel, "elem_weight must hold (2^d - 1)^2 = %d values", nel * nel);
+    for (int e = 0; e < nel * nel; ++e)
+      TNFEM_REQUIRE(desc.elem_weight[e] > 0 && std::isfinite(desc.elem_weight[e]), "elem_weight must be positive");
+  }
   TNFEM_REQUIRE(!desc.has_manufactured, "the manufactured load is defined on the unit box only");
   TNFEM_REQUIRE(desc.E > 0 && std::isfinite(desc.E), "E must be positive");
   TNFEM_REQUIRE(desc.nu > -1.0 && desc.nu < 0.5, "nu must be in (-1, 0.5)");
@@ -337,7 +343,7 @@ Assembled assemble_quad(const tnfem_problem_desc& desc) {
               double v = 0.0;
               for (int al = 0; al < 2; ++al)
                 for (int be = 0; be < 2; ++be) v += Cq(a, al, b, be) * inv[g][al] * inv[h][be];
-              Gf[g * 2 + h][q * 4 + a * 2 + b] = v * det;
+              Gf[g * 2 + h][q * 4 + a * 2 + b] = v * det * (desc.elem_weight ? desc.elem_weight[i * nel + j] : 1.0);
             }
     }
   std::vector<int> fmodes(d, 4);

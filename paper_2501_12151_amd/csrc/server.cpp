@@ -36,6 +36,7 @@ struct Request {
   long long id = 0;
   tnfem_problem_desc desc{};
   std::vector<double> layer;
+  std::vector<double> ew;
   std::vector<int> f0_ranks;
   std::vector<double> f0_cores;
   tnfem_solve_opts opts{};
@@ -71,6 +72,10 @@ class Server {
     if (d.layer_E && d.n_layer_E > 0) {
       r->layer.assign(d.layer_E, d.layer_E + d.n_layer_E);
       r->desc.layer_E = r->layer.data();
+    }
+    if (d.elem_weight && d.n_elem_weight > 0) {
+      r->ew.assign(d.elem_weight, d.elem_weight + d.n_elem_weight);
+      r->desc.elem_weight = r->ew.data();
     }
     if (d.f0_cores) {
       const size_t nd = f0_doubles(d);  // validates the ranks before they size the copy

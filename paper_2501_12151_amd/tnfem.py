@@ -51,6 +51,7 @@ class ProblemDesc(C.Structure):
         ("f0_ranks", C.POINTER(C.c_int)), ("f0_cores", C.POINTER(C.c_double)),
         ("has_stiffness", C.c_int), ("stiffness", (C.c_double * 6) * 6),
         ("has_quad", C.c_int), ("quad", (C.c_double * 2) * 4),
+        ("n_elem_weight", C.c_int), ("elem_weight", C.POINTER(C.c_double)),
     ]
 
 
@@ -94,6 +95,9 @@ class ServerInfo(C.Structure):
 _vp = C.c_void_p
 _ip = C.POINTER(C.c_int)
 _dp = C.POINTER(C.c_double)
+# device allocator hooks: alloc(bytes, stream, user) -> ptr, free(ptr, stream, user)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 _sig = {
     "tnfem_last_error": (C.c_char_p, []),
     "tnfem_default_opts": (None, [C.POINTER(SolveOpts)]),
@@ -120,6 +124,7 @@ _sig = {
     "tnfem_prim_local_apply_ex": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp,
                                              _vp, C.c_int, _vp]),
     "tnfem_prim_env_update": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "tnfem_ctx_create_ex": (C.c_int, [C.POINTER(_vp), C.c_int, _vp, ALLOC_FN, FREE_FN, _vp]),
     "tnfem_prim_qr": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "tnfem_prim_svd": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "tnfem_prim_svd_noalloc": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
@@ -193,6 +198,11 @@ def make_desc(problem: dict) -> ProblemDesc:
         for i in range(Cv.shape[0]):
             for j in range(Cv.shape[1]):
                 d.stiffness[i][j] = float(Cv[i, j])
+    if problem.get("elem_weight") is not None:
+        w = np.ascontiguousarray(problem["elem_weight"], dtype=np.float64).reshape(-1)
+        d._ew_keep = w
+        d.n_elem_weight = w.size
+        d.elem_weight = w.ctypes.data_as(_dp)
     if problem.get("quad") is not None:
         Q = np.asarray(problem["quad"], dtype=np.float64).reshape(4, 2)
         d.has_quad = 1
@@ -325,14 +335,35 @@ class TT:
 
 
 class Context:
-    """A device context; stream may be a torch.cuda.Stream or a raw hipStream_t int."""
+    """A device context; stream may be a torch.cuda.Stream or a raw hipStream_t int.
+    allocator="torch" hands the library's device allocations to torch's caching allocator."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, allocator=None):
         h = _vp()
         s = None
         if stream is not None:
             s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        _check(_lib.tnfem_ctx_create(C.byref(h), int(device), s))
+        self._hooks = None
+        if allocator == "torch":
+            import torch
+
+            dev = int(device)
+
+            def _alloc(nbytes, stream_ptr, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=int(stream_ptr or 0))
+                except Exception:  # noqa: BLE001 -- reported to the library as NULL (TNFEM_ENOMEM)
+                    return None
+
+            def _free(ptr, stream_ptr, user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+            _check(_lib.tnfem_ctx_create_ex(C.byref(h), dev, s, self._hooks[0], self._hooks[1], None))
+        elif allocator is None:
+            _check(_lib.tnfem_ctx_create(C.byref(h), int(device), s))
+        else:
+            raise ValueError("allocator must be None or 'torch'")
         self._h = h
         self._problems = weakref.WeakSet()
 

@@ -39,6 +39,10 @@ SMALL = [
     # quadrilateral domain (Alg. 1 in full: a trapezoid, slanted side loaded)
     dict(dim=2, level=4, E=1.0, nu=0.3, quad=[[0.0, 0.0], [2.0, 0.0], [0.0, 1.0], [1.4, 0.7]], clamp=[(0, 0)],
          tractions=[(0, 1, [0.3, -1.0])], body_force=[0.0, -0.5]),
+    # heterogeneous material: a stiff disk inclusion as a per-element field
+    dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(1, 0)], body_force=[0.0, -1.0],
+         elem_weight=np.where(np.add.outer(((np.arange(15) + 0.5) / 15 - 0.55) ** 2,
+                                           ((np.arange(15) + 0.5) / 15 - 0.45) ** 2) < 0.09, 10.0, 1.0)),
     # nodal load f0 given as a TT (Alg. 2 input)
     dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], f_nodal_tt=_nodal_tt(3, 3, 2, seed=5)),
     dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(1, 0)], f_nodal_tt=_nodal_tt(2, 4, 3, seed=6)),
@@ -48,7 +52,8 @@ SMALL = [
 @pytest.mark.parametrize("case", range(len(SMALL)))
 def test_unconstrained_solve_equals_direct_and_oracle(ctx, case):
     prob = SMALL[case]
-    print(f"solve small case {case}: {dict((k, v) for k, v in prob.items() if k != 'f_nodal_tt')}", flush=True)
+    print(f"solve small case {case}: {dict((k, v) for k, v in prob.items() if k not in ('f_nodal_tt', 'elem_weight'))}",
+          flush=True)
     A, b, grid, _ = fem.build_system(prob)
     u = qtt.to_qtt_order(fem.direct_solve(A, b), prob["dim"], prob["level"])
     P = tnfem.Problem(ctx, prob)
@@ -136,3 +141,31 @@ def test_anisotropic_material_reproduces_linear_field_at_level_6(ctx):
           f"sweeps {st['sweeps']}", flush=True)
     assert err <= 1e-8
     P.close()
+
+
+def test_torch_allocator_hooks_hold_the_device_memory():
+    """With allocator hooks bound to torch's caching allocator every device byte of the
+    problem and its solve comes from torch (and returns to it), and the result equals the
+    solve on the library's own allocations bit for bit."""
+    import torch
+
+    prob = SMALL[3]
+    ctx0 = tnfem.Context(0)
+    P0 = tnfem.Problem(ctx0, prob)
+    ref = P0.solve(rank_cap=32, tol=1e-9)[0].cores
+    P0.close()
+    ctx0.close()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    ctx = tnfem.Context(0, stream=torch.cuda.current_stream(), allocator="torch")
+    P = tnfem.Problem(ctx, prob)
+    U, st, rc = P.solve(rank_cap=32, tol=1e-9)
+    held = torch.cuda.memory_allocated() - base
+    print(f"torch allocator holds {held} bytes for the problem and its workspace", flush=True)
+    assert held > 1 << 20
+    for x, y in zip(U.cores, ref):
+        assert np.array_equal(x, y)
+    P.close()
+    ctx.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base

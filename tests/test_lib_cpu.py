@@ -148,11 +148,46 @@ def test_quadrilateral_assembly_equals_sparse_fem(case):
     assert np.abs(tt.tt_full(bc) - bp).max() <= 1e-12 * np.abs(bp).max()
 
 
+def _inclusion(level, value=10.0):
+    """Per-element weights: value inside a disk of radius 0.3 at (0.55, 0.45), 1 outside."""
+    ne = 2 ** level - 1
+    c = (np.arange(ne) + 0.5) / ne
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    return np.where((X - 0.55) ** 2 + (Y - 0.45) ** 2 < 0.09, value, 1.0)
+
+
+WEIGHT_CASES = [
+    dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], tractions=[(0, 1, [1.0, 0.0])],
+         elem_weight=np.random.default_rng(3).uniform(0.2, 5.0, (7, 7))),
+    dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(1, 0)], body_force=[0.0, -1.0], extent=[2.0, 1.0],
+         elem_weight=_inclusion(4)),
+    dict(dim=2, level=3, E=1.0, nu=0.3, quad=TRAPEZOID, clamp=[(0, 0)], tractions=[(0, 1, [0.3, -1.0])],
+         elem_weight=_inclusion(3, 4.0), stiffness_voigt=workloads.orthotropic_voigt(2, 1.0, 3.0)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(WEIGHT_CASES)))
+def test_element_field_assembly_equals_sparse_fem(case):
+    """A general per-element material field (random, or a stiff disk inclusion) in 2D: the
+    library's operator and load equal the oracle's element-by-element assembly."""
+    prob = WEIGHT_CASES[case]
+    A, b, grid, info = fem.build_system(prob)
+    d = prob["level"]
+    Ac = tnfem.export_operator(prob)
+    Ap = qtt.matrix_to_qtt_order(A, 2, d).toarray()
+    assert np.abs(tt.mpo_full(Ac) - Ap).max() <= 1e-12 * np.abs(Ap).max()
+    bp = qtt.to_qtt_order(b, 2, d)
+    assert np.abs(tt.tt_full(tnfem.export_load(prob)) - bp).max() <= 1e-12 * np.abs(bp).max()
+
+
 @pytest.mark.parametrize("bad,msg", [
     (dict(quad=[[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]]), "det J"),  # P01 / P11 swapped: twisted
     (dict(quad=TRAPEZOID, dim=3), "2D"),
     (dict(quad=TRAPEZOID, layered_E=(0, [1.0] * 7)), "layer_E"),
     (dict(quad=TRAPEZOID, level=9), "level"),
+    (dict(elem_weight=np.ones((6, 6))), "elem_weight"),
+    (dict(elem_weight=-np.ones((7, 7))), "elem_weight"),
+    (dict(elem_weight=np.ones(49), dim=3), "2D"),
 ])
 def test_invalid_quadrilateral_rejected(bad, msg):
     prob = dict(dim=2, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0.0, -1.0])
