@@ -19,6 +19,7 @@ library: the process then has one runtime, torch's, for both.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import weakref
@@ -334,6 +335,22 @@ class TT:
         return out
 
 
+# Device objects still open when the interpreter exits are closed by an exit handler, which
+# runs before module teardown and before the HIP runtime's own destructors at process exit;
+# left to garbage collection at shutdown, their hipFree calls could reach a runtime that is
+# already gone.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_objects():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:  # noqa: BLE001 -- best effort at exit
+            pass
+
+
 class Context:
     """A device context; stream may be a torch.cuda.Stream or a raw hipStream_t int.
     allocator="torch" hands the library's device allocations to torch's caching allocator."""
@@ -366,6 +383,7 @@ class Context:
             raise ValueError("allocator must be None or 'torch'")
         self._h = h
         self._problems = weakref.WeakSet()
+        _live.add(self)
 
     def close(self):
         """Destroys the context after every problem created on it."""
@@ -486,6 +504,7 @@ class Server:
         _check(_lib.tnfem_server_create(int(device), int(slots), int(hbm_budget_bytes), C.byref(h)))
         self._h = h
         self._descs = {}
+        _live.add(self)
 
     def submit(self, problem: dict, **opts) -> int:
         desc = make_desc(problem)

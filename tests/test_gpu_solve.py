@@ -169,3 +169,27 @@ def test_torch_allocator_hooks_hold_the_device_memory():
     ctx.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == base
+
+
+def test_interpreter_exit_with_open_device_objects():
+    """A process that leaves a context (with torch's allocator), a problem and a solution open
+    exits cleanly: the binding closes them in an exit handler, problems before their context,
+    while torch and the HIP runtime are still up."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import torch\n"
+            "from paper_2501_12151_amd import tnfem\n"
+            "ctx = tnfem.Context(0, stream=torch.cuda.current_stream(), allocator='torch')\n"
+            "ctx2 = tnfem.Context(0)\n"
+            "P = tnfem.Problem(ctx, dict(dim=3, level=3, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0, 0, -1.0]))\n"
+            "Q = tnfem.Problem(ctx2, dict(dim=2, level=4, E=1.0, nu=0.3, clamp=[(0, 0)], body_force=[0, -1.0]))\n"
+            "u = P.solve(rank_cap=16, max_sweeps=4)[0]\n"
+            "v = Q.solve(rank_cap=16, max_sweeps=4)[0]\n"
+            "print('left open', flush=True)\n") % root
+    r = subprocess.run([sys.executable, "-u", "-c", code], capture_output=True, text=True, timeout=300)
+    print(r.stdout[-400:], r.stderr[-400:], flush=True)
+    assert r.returncode == 0 and "left open" in r.stdout

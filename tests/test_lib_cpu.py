@@ -329,3 +329,19 @@ def test_tt_rel_diff_resolves_small_differences():
     fa, fb = tt.tt_full(a), tt.tt_full(b)
     ref = np.linalg.norm(fa - fb) / np.linalg.norm(fb)
     assert abs(A.rel_diff(B) - ref) <= 1e-6 * ref
+
+
+def test_interpreter_exit_with_open_library_objects():
+    """TT objects left open at interpreter exit are destroyed cleanly (the binding closes
+    live device objects from an exit handler, before the runtime's own teardown)."""
+    import subprocess
+    import sys
+
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import numpy as np\n"
+            "from paper_2501_12151_amd import tnfem\n"
+            "a = tnfem.TT.from_cores([np.ones((1, 4, 2)), np.ones((2, 4, 1))])\n"
+            "b = tnfem.TT.from_cores([np.ones((1, 4, 1)), np.ones((1, 4, 1))])\n"
+            "print(a.rel_diff(b))\n") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
