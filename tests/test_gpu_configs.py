@@ -1,6 +1,7 @@
 """GPU solves at the configurations' own shapes against the oracle.
 
-* The 1024^3 manufactured-load cube (3.2e9 dofs, rank cap 64, tol 1e-6, 24 half-sweeps),
+* The 1024^3 manufactured-load cube (3.2e9 dofs, rank cap 64, tol 1e-6, 16 half-sweeps with
+  enrichment rank 8, the bench's options),
   solved by the library in FP64, with FP32 and with BF16 local applies (FP64 refinement),
   against the oracle's FP64 AMEn solve of the same problem with the same options: relative
   error in TT format and entries at 10k seeded random multi-indices, both within the 1e-6
@@ -19,7 +20,7 @@ pytestmark = pytest.mark.gpu
 from oracle import amen as oamen, fem, qtt, tt  # noqa: E402
 from paper_2501_12151_amd import tnfem, workloads  # noqa: E402
 
-C3_OPTS = dict(rank_cap=64, tol=1e-6, max_sweeps=24)
+C3_OPTS = dict(rank_cap=64, tol=1e-6, max_sweeps=16, rho=8)
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +29,7 @@ def c3():
     print("oracle: assembling and solving the 1024^3 cube", flush=True)
     X, ost = oamen.amen_solve(qtt.assemble_operator(prob), qtt.assemble_load(prob),
                               oamen.Options(tol=C3_OPTS["tol"], rank_cap=C3_OPTS["rank_cap"],
-                                            max_sweeps=C3_OPTS["max_sweeps"]))
+                                            max_sweeps=C3_OPTS["max_sweeps"], rho=C3_OPTS["rho"]))
     print(f"oracle: {ost.sweeps} half-sweeps, ranks {[x.shape[2] for x in X]}", flush=True)
     ctx = tnfem.Context(0)
     P = tnfem.Problem(ctx, prob)
@@ -60,10 +61,11 @@ def test_full_size_manufactured_cube_matches_oracle(c3, precision):
 
 @pytest.mark.parametrize("precision", [1, 2])
 def test_full_size_cube_with_outer_refinement_matches_oracle(c3, precision):
-    """The same cube with the outer FP64 iterative refinement (24 half-sweeps, then one
-    correction solve of 4 half-sweeps and the FP64 rounding of u + d)."""
+    """The same cube with the outer FP64 iterative refinement (the sweeps above, then one
+    correction solve of 8 half-sweeps and the FP64 rounding of u + d; a correction solve of 4
+    half-sweeps from its random start is too coarse for BF16 here and moves u by ~1e-6)."""
     prob, P, X = c3
-    U, st, rc = P.solve(precision=precision, ir_max=1, ir_sweeps=4, ir_tol=1e-7, **C3_OPTS)
+    U, st, rc = P.solve(precision=precision, ir_max=1, ir_sweeps=8, ir_tol=1e-7, **C3_OPTS)
     rel = tt.tt_rel_diff(U.cores, X)
     print(f"  precision {precision} + refinement: {st['ir_iters']} step(s), ||d||/||u|| {st['ir_last_update']:.2e}, "
           f"rel.diff vs oracle {rel:.2e}", flush=True)
