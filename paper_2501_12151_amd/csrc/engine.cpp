@@ -690,7 +690,6 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   W.V = A(Nw * Nw);
   W.Ur = A(M * Nw);
   W.SVt = A(Nw * Nw);
-  W.Vt = A(Nw * Nw);
   W.xT = A(M * Nw);
   W.xt = A(M * Nw);
   W.aug = A(M * Nw);
@@ -1218,15 +1217,18 @@ struct Sweep {
     s.c = std::min(s.M, s.Nn);
     s.tall = s.M >= s.Nn;
     const int M = s.M, Nn = s.Nn;
+    // Only the left singular vectors of x and S are needed (the truncated x is the
+    // projection U_rk U_rk^T x), so the Jacobi SVD runs on the matrix whose normalised
+    // columns are those vectors and accumulates no rotations.
     if (s.tall) {
+      // x = Q R, R = U_R S V^T: Jacobi on R, U_R from its columns; U = Q U_R
       s.qr = QrJob{M, Nn, Nn, Nn, Nn, X[k], W.Qx, W.Rx, W.qrws, W.qrws_cap};
-      // Jacobi on R^T: its normalised columns are R's right, its rotations R's left vectors
-      s.svd = SvdJob{Nn, Nn, W.Rx, W.V, W.S, W.UR, W.qrws, 1};
+      s.svd = SvdJob{Nn, Nn, W.Rx, W.UR, W.S, W.V, W.qrws, 0, true};
     } else {
-      // x^T = Q U_R S V^T  =>  x = V S (Q U_R)^T
+      // x^T = Q R  =>  x = R^T Q^T: Jacobi on R^T, whose columns give U directly
       launch_core_transpose(M, 1, Nn, X[k], W.xT, st);
       s.qr = QrJob{Nn, M, M, M, M, W.xT, W.Qx, W.Rx, W.qrws, W.qrws_cap};
-      s.svd = SvdJob{M, M, W.Rx, W.V, W.S, W.UR, W.qrws, 1};
+      s.svd = SvdJob{M, M, W.Rx, W.UR, W.S, W.V, W.qrws, 1, true};
     }
   }
 
@@ -1235,26 +1237,8 @@ struct Sweep {
     const int M = s.M, Nn = s.Nn, c = s.c;
     if (s.tall) {
       gemm_plain(M, Nn, Nn, W.Qx, Nn, false, W.UR, Nn, W.Ur, c, st, &fl);
-      launch_core_transpose(Nn, 1, Nn, W.V, W.Vt, st);
     } else {
-      launch_copy2d(M, M, W.V, M, W.Ur, c, 1.0, 0.0, st);
-      // V^T = (Q U_R)^T = U_R^T Q^T, Q stored Nn x M row-major
-      GemmDesc g;
-      g.A = W.UR;
-      g.a_sm = 1;
-      g.a_sk = M;
-      g.B = W.Qx;
-      g.b_sk = 1;
-      g.b_sn = M;
-      g.C = W.Vt;
-      g.c_sm = Nn;
-      g.c_sn = 1;
-      g.M = M;
-      g.N = Nn;
-      g.K = M;
-      g.flops = flop_count(M, Nn, M, 1);
-      launch_gemm(g, st);
-      count(&fl, M, Nn, M, 1);
+      launch_copy2d(M, M, W.UR, M, W.Ur, c, 1.0, 0.0, st);
     }
     const double trtol = o.tol / std::sqrt((double)std::max(K - 1, 1));
     launch_trunc_rank(c, W.S, trtol, o.rank_cap, W.drank, st);
@@ -1265,12 +1249,13 @@ struct Sweep {
     const int p = s.p, nk = s.nk, t = s.t, M = s.M, Nn = s.Nn, c = s.c;
     const int rk = hint()[0];
     s.rk = rk;
-    // keep U[:, :rk] (in place, leading dimension rk) and xt = U_rk diag(S) V^T_rk
+    // keep U[:, :rk] (in place, leading dimension rk) and xt = U_rk (U_rk^T x), which
+    // equals U_rk diag(S_rk) V^T_rk
     if (rk < c) {
       launch_copy2d(M, rk, W.Ur, c, W.aug, rk, 1.0, 0.0, st);
       launch_copy2d(M, rk, W.aug, rk, W.Ur, rk, 1.0, 0.0, st);
     }
-    launch_scale_rows(rk, Nn, W.S, W.Vt, Nn, W.SVt, st);
+    gemm_plain(rk, Nn, M, W.Ur, rk, true, X[k], Nn, W.SVt, Nn, st, &fl);
     gemm_plain(M, Nn, rk, W.Ur, rk, false, W.SVt, Nn, W.xt, Nn, st, &fl);
     // residual projected on the Z interfaces -> new Z_k (QR job)
     const int pz = zr[k], tz = zr[k + 1];
@@ -1330,7 +1315,8 @@ struct Sweep {
     TruncState s;
     trunc_begin(k, s);
     launch_qr(s.qr.m, s.qr.n, s.qr.A, s.qr.lda, s.qr.Q, s.qr.ldq, s.qr.R, s.qr.ldr, s.qr.ws, s.qr.ws_cap, st);
-    launch_jacobi_svd(s.svd.n, s.svd.G, s.svd.ldg, s.svd.U, s.svd.S, s.svd.V, s.svd.ws, st, s.svd.trans);
+    launch_jacobi_svd(s.svd.n, s.svd.G, s.svd.ldg, s.svd.U, s.svd.S, s.svd.V, s.svd.ws, st, s.svd.trans,
+                      s.svd.left_only);
     trunc_rank(k, s);
     sync();
     enrich_begin(k, s);

@@ -116,7 +116,7 @@ struct Workspace {
   double* binv = nullptr;  // inverses of the diagonal mode blocks of the local operator
   double *Tb = nullptr, *gz = nullptr, *yz = nullptr, *ge = nullptr, *ye = nullptr;
   double *Qx = nullptr, *Rx = nullptr, *UR = nullptr, *S = nullptr, *V = nullptr, *Ur = nullptr, *SVt = nullptr,
-         *xt = nullptr, *aug = nullptr, *Vt = nullptr, *xT = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;
+         *xt = nullptr, *aug = nullptr, *xT = nullptr, *Qa = nullptr, *Ra = nullptr, *Wm = nullptr, *qrws = nullptr;
   double *Rz = nullptr, *qrwsz = nullptr;  // R and scratch of the residual-TT QR
   size_t qrws_cap = 0, qrwsz_cap = 0;     // doubles at qrws and qrwsz
   double *scal = nullptr, *part = nullptr;

@@ -2558,95 +2558,177 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
   for (int j = tid; j < n; j += SV_NT) S[pos[j]] = sv[j];
 }
 
-// The same one-sided Jacobi iteration for n <= 64 on four wavefronts: each column
-// pair of a step is owned by an aligned group of lanes (within one wavefront) that
-// reduce their dot products with DPP sums; a step ends with a workgroup barrier.
+// The same one-sided Jacobi iteration for n <= 64.  Each column pair of a step is
+// owned by an aligned group of SVW_TPP lanes of one wavefront; lane `sub` of a group
+// holds rows sub, sub + SVW_TPP, ... of both columns in registers from the dot
+// products to the rotation, and the group reduces with DPP sums.  Rows are
+// zero-padded to NR = SVW_TPP * RPL (no bounds tests in the step loop; zero rows
+// and the zero padding column of an odd n never rotate).  The column stride LD is
+// congruent to SVW_TPP mod 32 doubles: the groups of a half-wave read consecutive
+// columns of the round-robin schedule and so hit disjoint LDS banks.
+// WITH_V: a second set of wavefronts applies each step's rotations to V one step
+// behind the G wavefronts (rotation parameters through LDS), off the critical path
+// of the next step's dot products.  Without V the kernel returns the normalised
+// columns of G (its left singular vectors) and S only.
+// Dynamic LDS: svw_lds_bytes(n, RPL, WITH_V).
 constexpr int SVW_MAXN = 64;
-constexpr int SVW_NT = 256;
+constexpr int SVW_TPP = 8;
+constexpr int SVW_MAX_THREADS = 512;
 
+__host__ __device__ constexpr int svw_ld(int rpl) {
+  return SVW_TPP * rpl + ((SVW_TPP - SVW_TPP * rpl) % 32 + 32) % 32;
+}
+__host__ __device__ inline int svw_npairs(int n) {
+  const int npad = n + (n & 1);
+  return npad / 2 > 0 ? npad / 2 : 1;
+}
+// G wavefronts: whole waves covering npairs groups of SVW_TPP lanes
+__host__ __device__ inline int svw_gthreads(int n) { return (svw_npairs(n) * SVW_TPP + 63) / 64 * 64; }
+static int svw_rpl(int n) { return n <= SVW_TPP ? 1 : n <= 2 * SVW_TPP ? 2 : n <= 4 * SVW_TPP ? 4 : 8; }
+static size_t svw_lds_bytes(int n, int rpl, bool with_v) {
+  const size_t npad = n + (n & 1);
+  const size_t cols = (with_v ? 2 : 1) * npad * svw_ld(rpl);
+  return (cols + (with_v ? 4 * svw_npairs(n) : 0) + npad) * sizeof(double) + npad * sizeof(int);
+}
+static int svw_threads(int n, bool with_v) { return (with_v ? 2 : 1) * svw_gthreads(n); }
+
+template <int RPL, bool WITH_V>
 __device__ __forceinline__ void jacobi_svd_wave_body(int n, const double* G, int ldg, int trans, double* U, double* S,
-                                                     double* V) {
-  // column-major n x n with a padded column stride: the columns handled at one
-  // step start in different LDS banks
-  __shared__ double Gc[SVW_MAXN * (SVW_MAXN + 1)];
-  __shared__ double Vc[SVW_MAXN * (SVW_MAXN + 1)];
-  __shared__ double sv[SVW_MAXN];
-  __shared__ int pos[SVW_MAXN];
-  const int tid = threadIdx.x;
-  const int ld = n + 1;
-  for (int idx = tid; idx < n * n; idx += SVW_NT) {
-    const int i = idx % n, j = idx / n;
-    Gc[j * ld + i] = trans ? G[(long)j * ldg + i] : G[(long)i * ldg + j];
-    Vc[j * ld + i] = (i == j) ? 1.0 : 0.0;
+                                                     double* V, double* dyn) {
+  constexpr int TPP = SVW_TPP, NR = TPP * RPL, LD = svw_ld(RPL);
+  const int npad = n + (n & 1);
+  const int npairs = svw_npairs(n);
+  const int ngt = svw_gthreads(n);
+  double* Gc = dyn;                                    // npad columns of stride LD
+  double* Vc = Gc + (long)npad * LD;                   // WITH_V
+  double* rotb = Vc + (WITH_V ? (long)npad * LD : 0);  // WITH_V: (cs, sn) per pair, two steps
+  double* sv = rotb + (WITH_V ? 4 * npairs : 0);
+  int* pos = reinterpret_cast<int*>(sv + npad);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int idx = tid; idx < npad * NR; idx += nt) {
+    const int i = idx % NR, j = idx / NR;
+    Gc[j * LD + i] = (i < n && j < n) ? (trans ? G[(long)j * ldg + i] : G[(long)i * ldg + j]) : 0.0;
+    if (WITH_V) Vc[j * LD + i] = (i == j && j < n) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int npad = n + (n & 1);
-  const int npairs = npad / 2 > 0 ? npad / 2 : 1;
-  int tpp = 1;
-  while (tpp * 2 * npairs <= SVW_NT && tpp < 64) tpp *= 2;
-  const int pair = tid / tpp, sub = tid % tpp;
-  // rows sub, sub + tpp, ...: the lanes of a pair read consecutive rows
+  const int m1 = npad - 1;
   // rotation threshold at the rounding level of an n-term dot product: smaller
   // off-diagonal values are rounding noise, and rotating them never terminates
   const double eps = (n > 4 ? n : 4) * 2.220446049250313e-16;
+  const bool isg = !WITH_V || tid < ngt;
+  const int gt = isg ? tid : tid - ngt;
+  const int pair = gt / TPP, sub = gt % TPP;
+  const bool live = pair < npairs;
+  const int ia = pair, ib = npad - 1 - pair;
+  int buf = 0;
+  int vpa = -1, vpb = -1;  // V wavefronts: the columns of the step still to apply
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
     int rot = 0;
-    for (int step = 0; step < npad - 1; ++step) {
-      if (pair < npairs) {
-        const int ia = pair, ib = npad - 1 - pair;
-        const int pa = ia == 0 ? 0 : 1 + (ia - 1 + step) % (npad - 1);
-        const int pb = ib == 0 ? 0 : 1 + (ib - 1 + step) % (npad - 1);
-        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
-        double a = 0.0, b = 0.0, cc = 0.0;
-        if (q < n) {
-          for (int i = sub; i < n; i += tpp) {
-            const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
-            a += gp * gp;
-            b += gq * gq;
-            cc += gp * gq;
+    int pa = ia, pb = ib;  // round-robin positions; pair 0 keeps column 0
+    for (int step = 0; step < m1; ++step) {
+      if (isg) {
+        if (live) {
+          double gp[RPL], gq[RPL];
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            gp[r] = Gc[pa * LD + sub + r * TPP];
+            gq[r] = Gc[pb * LD + sub + r * TPP];
+          }
+          double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            a = fma(gp[r], gp[r], a);
+            b = fma(gq[r], gq[r], b);
+            c = fma(gp[r], gq[r], c);
+          }
+          a += dpp_get<DPP_XOR1>(a);
+          b += dpp_get<DPP_XOR1>(b);
+          c += dpp_get<DPP_XOR1>(c);
+          a += dpp_get<DPP_XOR2>(a);
+          b += dpp_get<DPP_XOR2>(b);
+          c += dpp_get<DPP_XOR2>(c);
+          a += dpp_get<DPP_HALF_MIRROR>(a);
+          b += dpp_get<DPP_HALF_MIRROR>(b);
+          c += dpp_get<DPP_HALF_MIRROR>(c);
+          double cs = 1.0, sn = 0.0;
+          if (jacobi_rotate(a, b, c, eps)) {
+            jacobi_rotation(a, b, c, cs, sn);
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+              Gc[pa * LD + sub + r * TPP] = cs * gp[r] - sn * gq[r];
+              Gc[pb * LD + sub + r * TPP] = sn * gp[r] + cs * gq[r];
+            }
+            rot = 1;
+          }
+          if (WITH_V && sub == 0) {
+            rotb[2 * (buf * npairs + pair)] = cs;
+            rotb[2 * (buf * npairs + pair) + 1] = sn;
           }
         }
-        a = group_sum(a, tpp);
-        b = group_sum(b, tpp);
-        cc = group_sum(cc, tpp);
-        if (q < n && jacobi_rotate(a, b, cc, eps)) {
-          double cs, sn;
-          jacobi_rotation(a, b, cc, cs, sn);
-          for (int i = sub; i < n; i += tpp) {
-            const double gp = Gc[p * ld + i], gq = Gc[q * ld + i];
-            Gc[p * ld + i] = cs * gp - sn * gq;
-            Gc[q * ld + i] = sn * gp + cs * gq;
-            const double vp = Vc[p * ld + i], vq = Vc[q * ld + i];
-            Vc[p * ld + i] = cs * vp - sn * vq;
-            Vc[q * ld + i] = sn * vp + cs * vq;
+      } else if (live && vpa >= 0) {
+        const double cs = rotb[2 * ((buf ^ 1) * npairs + pair)];
+        const double sn = rotb[2 * ((buf ^ 1) * npairs + pair) + 1];
+        if (sn != 0.0) {
+          double vp[RPL], vq[RPL];
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            vp[r] = Vc[vpa * LD + sub + r * TPP];
+            vq[r] = Vc[vpb * LD + sub + r * TPP];
           }
-          rot = 1;
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            Vc[vpa * LD + sub + r * TPP] = cs * vp[r] - sn * vq[r];
+            Vc[vpb * LD + sub + r * TPP] = sn * vp[r] + cs * vq[r];
+          }
         }
       }
+      if (!isg) {
+        vpa = pa;
+        vpb = pb;
+      }
+      buf ^= 1;
+      if (ia != 0) pa = pa == m1 ? 1 : pa + 1;
+      pb = pb == m1 ? 1 : pb + 1;
       __syncthreads();
     }
     if (!__syncthreads_or(rot)) break;
   }
-  for (int j = tid; j < n; j += SVW_NT) {
+  if (WITH_V) {
+    // the last step's rotations
+    if (!isg && live && vpa >= 0) {
+      const double cs = rotb[2 * ((buf ^ 1) * npairs + pair)];
+      const double sn = rotb[2 * ((buf ^ 1) * npairs + pair) + 1];
+      if (sn != 0.0) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const double vp = Vc[vpa * LD + sub + r * TPP], vq = Vc[vpb * LD + sub + r * TPP];
+          Vc[vpa * LD + sub + r * TPP] = cs * vp - sn * vq;
+          Vc[vpb * LD + sub + r * TPP] = sn * vp + cs * vq;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < n; j += nt) {
     double s2 = 0.0;
-    for (int i = 0; i < n; ++i) s2 += Gc[j * ld + i] * Gc[j * ld + i];
+    for (int i = 0; i < n; ++i) s2 += Gc[j * LD + i] * Gc[j * LD + i];
     sv[j] = sqrt(s2);
   }
   __syncthreads();
-  for (int j = tid; j < n; j += SVW_NT) {
+  for (int j = tid; j < n; j += nt) {
     int r = 0;
     for (int i = 0; i < n; ++i) r += (sv[i] > sv[j]) || (sv[i] == sv[j] && i < j);
     pos[j] = r;
   }
   __syncthreads();
-  for (int idx = tid; idx < n * n; idx += SVW_NT) {
+  for (int idx = tid; idx < n * n; idx += nt) {
     const int j = idx / n, i = idx % n;
     const int pj = pos[j];
     const double sj = sv[j];
-    U[(long)i * n + pj] = sj > 0.0 ? Gc[j * ld + i] / sj : (i == pj ? 1.0 : 0.0);
-    V[(long)i * n + pj] = Vc[j * ld + i];
+    U[(long)i * n + pj] = sj > 0.0 ? Gc[j * LD + i] / sj : (i == pj ? 1.0 : 0.0);
+    if (WITH_V) V[(long)i * n + pj] = Vc[j * LD + i];
   }
-  for (int j = tid; j < n; j += SVW_NT) S[pos[j]] = sv[j];
+  for (int j = tid; j < n; j += nt) S[pos[j]] = sv[j];
 }
 
 // The same iteration for 64 < n <= 137 on 1024 threads: G in dynamic LDS with a
@@ -2781,9 +2863,11 @@ __device__ __forceinline__ void jacobi_svd_big_body(int n, const double* G, int 
   for (int j = tid; j < n; j += SVB_NT) S[pos[j]] = sv[j];
 }
 
-__global__ __launch_bounds__(SVW_NT) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, int trans, double* U,
-                                                            double* S, double* V) {
-  jacobi_svd_wave_body(n, G, ldg, trans, U, S, V);
+template <int RPL, bool WITH_V>
+__global__ __launch_bounds__(SVW_MAX_THREADS) void jacobi_svd_wave_kernel(int n, const double* G, int ldg, int trans,
+                                                                          double* U, double* S, double* V) {
+  extern __shared__ double dyn[];
+  jacobi_svd_wave_body<RPL, WITH_V>(n, G, ldg, trans, U, S, V, dyn);
 }
 
 template <bool V_LDS>
@@ -2793,10 +2877,70 @@ __global__ __launch_bounds__(SVB_NT) void jacobi_svd_big_kernel(int n, const dou
   jacobi_svd_big_body<V_LDS>(n, G, ldg, trans, U, S, V, ws, dyn);
 }
 
-// One workgroup per job: the same one-sided Jacobi as the single launches.
-__global__ __launch_bounds__(SVW_NT) void jacobi_svd_wave_batch_kernel(SvdBatch b) {
+// One workgroup per job: the same one-sided Jacobi as the single launches (the jobs
+// of one launch share RPL and WITH_V; the block has the threads of the largest).
+template <int RPL, bool WITH_V>
+__global__ __launch_bounds__(SVW_MAX_THREADS) void jacobi_svd_wave_batch_kernel(SvdBatch b) {
+  extern __shared__ double dyn[];
   const SvdJob j = b.job[blockIdx.x];
-  jacobi_svd_wave_body(j.n, j.G, j.ldg, j.trans, j.U, j.S, j.V);
+  jacobi_svd_wave_body<RPL, WITH_V>(j.n, j.G, j.ldg, j.trans, j.U, j.S, j.V, dyn);
+}
+
+template <int RPL, bool WITH_V>
+static void svw_set_attr() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_wave_kernel<RPL, WITH_V>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)svw_lds_bytes(SVW_MAXN, 8, true));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_wave_batch_kernel<RPL, WITH_V>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)svw_lds_bytes(SVW_MAXN, 8, true));
+  });
+}
+
+template <int RPL, bool WITH_V>
+static void launch_svw(int n, const double* G, int ldg, int trans, double* U, double* S, double* V, hipStream_t s) {
+  svw_set_attr<RPL, WITH_V>();
+  hipLaunchKernelGGL((jacobi_svd_wave_kernel<RPL, WITH_V>), dim3(1), dim3(svw_threads(n, WITH_V)),
+                     svw_lds_bytes(n, RPL, WITH_V), s, n, G, ldg, trans, U, S, V);
+}
+
+template <int RPL, bool WITH_V>
+static void launch_svw_batch(const SvdBatch& b, hipStream_t s) {
+  svw_set_attr<RPL, WITH_V>();
+  int nt = 64;
+  size_t lds = 0;
+  for (int i = 0; i < b.njob; ++i) {
+    nt = std::max(nt, svw_threads(b.job[i].n, WITH_V));
+    lds = std::max(lds, svw_lds_bytes(b.job[i].n, RPL, WITH_V));
+  }
+  hipLaunchKernelGGL((jacobi_svd_wave_batch_kernel<RPL, WITH_V>), dim3(b.njob), dim3(nt), lds, s, b);
+}
+
+static void launch_svw_any(int n, const double* G, int ldg, int trans, double* U, double* S, double* V, bool with_v,
+                           hipStream_t s) {
+  switch (svw_rpl(n) * 2 + (with_v ? 1 : 0)) {
+    case 2: launch_svw<1, false>(n, G, ldg, trans, U, S, V, s); break;
+    case 3: launch_svw<1, true>(n, G, ldg, trans, U, S, V, s); break;
+    case 4: launch_svw<2, false>(n, G, ldg, trans, U, S, V, s); break;
+    case 5: launch_svw<2, true>(n, G, ldg, trans, U, S, V, s); break;
+    case 8: launch_svw<4, false>(n, G, ldg, trans, U, S, V, s); break;
+    case 9: launch_svw<4, true>(n, G, ldg, trans, U, S, V, s); break;
+    case 16: launch_svw<8, false>(n, G, ldg, trans, U, S, V, s); break;
+    default: launch_svw<8, true>(n, G, ldg, trans, U, S, V, s); break;
+  }
+}
+
+static void launch_svw_batch_any(int rpl, bool with_v, const SvdBatch& b, hipStream_t s) {
+  switch (rpl * 2 + (with_v ? 1 : 0)) {
+    case 2: launch_svw_batch<1, false>(b, s); break;
+    case 3: launch_svw_batch<1, true>(b, s); break;
+    case 4: launch_svw_batch<2, false>(b, s); break;
+    case 5: launch_svw_batch<2, true>(b, s); break;
+    case 8: launch_svw_batch<4, false>(b, s); break;
+    case 9: launch_svw_batch<4, true>(b, s); break;
+    case 16: launch_svw_batch<8, false>(b, s); break;
+    default: launch_svw_batch<8, true>(b, s); break;
+  }
 }
 
 template <bool V_LDS>
@@ -2815,12 +2959,14 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_big_batch_kernel<false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)SVB_LDS_BYTES);
   });
-  SvdBatch wave, big2, big1;
+  SvdBatch wave[8], big2, big1;  // wave jobs by (rows per lane, with V)
   size_t m2 = 0, m1 = 0;
   for (const SvdJob& j : jobs) {
     const size_t g = (size_t)j.n * (j.n + 1) * sizeof(double);
     if (j.n <= SVW_MAXN) {
-      wave.job[wave.njob++] = j;
+      const int r = svw_rpl(j.n);
+      SvdBatch& w = wave[(r == 1 ? 0 : r == 2 ? 1 : r == 4 ? 2 : 3) * 2 + (j.left_only ? 0 : 1)];
+      w.job[w.njob++] = j;
     } else if (2 * g <= SVB_LDS_BYTES) {
       big2.job[big2.njob++] = j;
       m2 = std::max(m2, 2 * g);
@@ -2828,11 +2974,12 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
       big1.job[big1.njob++] = j;
       m1 = std::max(m1, g);
     } else {
-      launch_jacobi_svd(j.n, j.G, j.ldg, j.U, j.S, j.V, j.ws, s, j.trans);
+      launch_jacobi_svd(j.n, j.G, j.ldg, j.U, j.S, j.V, j.ws, s, j.trans, j.left_only);
     }
   }
-  if (wave.njob) {
-    hipLaunchKernelGGL(jacobi_svd_wave_batch_kernel, dim3(wave.njob), dim3(SVW_NT), 0, s, wave);
+  for (int c = 0; c < 8; ++c) {
+    if (!wave[c].njob) continue;
+    launch_svw_batch_any(1 << (c / 2), c % 2 == 1, wave[c], s);
     TN_CHECK_LAUNCH();
   }
   if (big2.njob) {
@@ -2846,10 +2993,10 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
 }
 
 void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s,
-                       int trans) {
+                       int trans, bool left_only) {
   if (n > SV_MAXN) throw Error(TNFEM_EINVAL, "Jacobi SVD limited to n <= 256");
   if (n <= SVW_MAXN) {
-    hipLaunchKernelGGL(jacobi_svd_wave_kernel, dim3(1), dim3(SVW_NT), 0, s, n, G, ldg, trans, U, S, V);
+    launch_svw_any(n, G, ldg, trans, U, S, V, !left_only, s);
     TN_CHECK_LAUNCH();
     return;
   }

@@ -241,11 +241,13 @@ size_t qr_ws_doubles(int m, int n);
 
 // One-sided Jacobi SVD of the square n x n matrix G (row-major, ldg): G = U diag(S) V^T,
 // S descending.  U, V: n x n row-major.  ws: 3 n (n + 1) doubles (used when n > 64).
-// trans != 0: works on G^T (element (i, j) read from G[j * ldg + i]).  Jacobi on R^T
-// (R from a QR) converges in fewer sweeps than on R; the caller then passes the
-// destinations swapped: U receives R's right and V its left singular vectors.
+// trans != 0: works on G^T (element (i, j) read from G[j * ldg + i]).  U is formed from
+// the normalised columns of the rotated matrix, V from the accumulated rotations; for
+// the SVD of R^T (trans = 1, R from a QR) the caller passes the destinations swapped:
+// U receives R's right and V its left singular vectors.  left_only: only U and S are
+// needed; for n <= 64 the rotations are then not accumulated and V is not written.
 void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s,
-                       int trans = 0);
+                       int trans = 0, bool left_only = false);
 
 // Batched Jacobi SVD: one workgroup per job, each the same computation as launch_jacobi_svd.
 struct SvdJob {
@@ -253,6 +255,7 @@ struct SvdJob {
   const double* G = nullptr;
   double *U = nullptr, *S = nullptr, *V = nullptr, *ws = nullptr;
   int trans = 0;
+  bool left_only = false;
 };
 constexpr int SVD_BATCH_MAX = 16;
 struct SvdBatch {

