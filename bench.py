@@ -6,8 +6,8 @@ CG solves, SVD truncation, residual enrichment, QR, interface updates).  The
 default workload is the 3D unit cube with 1024^3 nodes (QTT level 10, 3.2e9
 dofs), all faces clamped, load of the manufactured field u_i = c_i sin(pi x)
 sin(pi y) sin(pi z) with c ~ N(0, 1) (seed 0), E = 1, nu = 0.3, TT rank cap 64,
-solved with FP32 local applies on MFMA (FP32 accumulate) refined in FP64; the
-plain FP64 solve of the same problem is timed beside it.  The operator and load
+solved in FP64 (FP64 MFMA); the mixed-precision solve (FP32 local applies on MFMA
+refined in FP64) of the same problem is timed beside it.  The operator and load
 are assembled and resident on the device before timing.  The oracle solves the
 same problem on the host cores; its solution is the accuracy reference.
 
@@ -172,14 +172,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube1024", choices=sorted(WORKLOADS) + ["serving", "cantilever"])
     ap.add_argument("--levels", default="6,8,10,12,14,16,18,20", help="cantilever: grid levels")
-    ap.add_argument("--precision", type=int, default=1, choices=(0, 1, 2),
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1, 2),
                     help="0 FP64; 1 FP32 local applies; 2 BF16 local applies (both refined in FP64)")
     ap.add_argument("--ir-max", type=int, default=0, help="outer FP64 refinement steps after the solve (0: none)")
     ap.add_argument("--ir-sweeps", type=int, default=4, help="half-sweeps of each correction solve")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (and its accuracy reference)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the GPU's high-rank reference solves")
-    ap.add_argument("--no-fp64-solver", action="store_true", help="do not time the plain FP64 solve beside")
+    ap.add_argument("--no-side-solver", "--no-fp64-solver", dest="no_side_solver", action="store_true",
+                    help="do not time the other precision beside (FP32 applies beside FP64, FP64 beside the rest)")
     ap.add_argument("--mfma-calibration", type=int, default=0, metavar="N",
                     help="only run 10 FP64 and 10 FP32 N x N matrix products (to calibrate MFMA counters)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -255,22 +256,28 @@ def main():
         return u, stats[-1], lat, time.perf_counter() - t_begin
 
     u, st, lat, total = timed(opts, DTYPES[args.precision].split(" ")[0])
-    u64 = None
-    fp64 = None
-    if args.precision != 0 and not args.no_fp64_solver:
-        o64 = dict({k: v for k, v in opts.items() if not k.startswith("ir_")}, precision=0)
-        u64, st64, lat64, total64 = timed(o64, "f64")
-        fp64 = {"value": args.steps / total64, "unit": "solves/s", "ms_per_step": 1e3 * total64 / args.steps,
-                "latency_ms": {"p50": 1e3 * percentile(lat64, 0.5), "p99": 1e3 * percentile(lat64, 0.99)},
-                "cg_iters": st64["cg_iters"], "counted_flops": st64["flops"],
-                "speed_of_this_line_vs_fp64": (args.steps / total) / (args.steps / total64)}
+    # the other precision, timed the same way: FP32 local applies beside an FP64
+    # headline, plain FP64 beside a low-precision one
+    side_prec = 1 if args.precision == 0 else 0
+    side_key = "mixed_precision_solver" if side_prec else "fp64_solver"
+    u_side, side = None, None
+    if not args.no_side_solver:
+        o2 = dict({k: v for k, v in opts.items() if not k.startswith("ir_")}, precision=side_prec)
+        u_side, st2, lat2, total2 = timed(o2, DTYPES[side_prec].split(" ")[0])
+        side = {"dtype": DTYPE_TAGS[side_prec], "value": args.steps / total2, "unit": "solves/s",
+                "ms_per_step": 1e3 * total2 / args.steps,
+                "latency_ms": {"p50": 1e3 * percentile(lat2, 0.5), "p99": 1e3 * percentile(lat2, 0.99)},
+                "cg_iters": st2["cg_iters"], "counted_flops": st2["flops"],
+                "low_precision_flops": st2["low_precision_flops"], "refinements": st2["refinements"],
+                "speed_of_this_line_vs_headline": (args.steps / total2) / (args.steps / total)}
     roof = None
     if not args.no_profile:
         roof = roofline(P, opts, args.workload)
     cpu, oracle_cores = None, None
     if not args.no_cpu_baseline:
         cpu, oracle_cores = cpu_baseline(args.workload, opts, st["local_applies"], full=wl.get("oracle_full", False))
-    accuracy = accuracy_block(P, u, u64, oracle_cores, opts, args.workload, prob, refs=not args.no_accuracy)
+    accuracy = accuracy_block(P, u, u_side, side_key, oracle_cores, opts, args.workload, prob,
+                              refs=not args.no_accuracy)
     value = args.steps / total
     out = {
         "metric": METRIC,
@@ -302,7 +309,7 @@ def main():
             "precision_fallbacks": st["precision_fallbacks"],
             "median_latency_s": statistics.median(lat),
         },
-        "fp64_solver": fp64,
+        side_key: side,
         "accuracy": accuracy,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -355,7 +362,8 @@ def roofline(P, opts, workload):
     achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     cms, cfl, cnl = pst["contraction_ms"], pst["contraction_flops"], pst["contraction_launches"]
     cap = opts["rank_cap"]
-    kinds = ["fused_apply32_kernel"] + (["fused_apply64_kernel"] if cap > 32 else []) + \
+    kinds = ["fused_apply32_kernel"] + \
+        ((["fused_apply16_kernel"] if prec != 2 else []) + ["fused_apply64_kernel"] if cap > 32 else []) + \
         (["slot_product_kernel + slot_apply_kernel"] if cap > 64 else [])
     kname = " / ".join(f"{k}<{prec}>" for k in kinds)
     if len(kinds) > 1:
@@ -384,13 +392,13 @@ def roofline(P, opts, workload):
     }
 
 
-def accuracy_block(P, u, u64, oracle_cores, opts, name, prob, refs=True):
+def accuracy_block(P, u, u_side, side_key, oracle_cores, opts, name, prob, refs=True):
     """Relative displacement errors of the timed solve, computed by the library in TT format
     (no densification): against the oracle's FP64 solve of the same problem with the same
     options (when the oracle ran the whole solve), against FP64 GPU solves with larger rank
     caps / tighter tolerances (their mutual difference bounds how far the last one is from
-    converged), against the FP64 GPU solve with the same options (low precision), and for
-    the manufactured load against the closed-form field (which adds the O(h^2)
+    converged), against the solve of the other precision timed beside it (`side_key`), and
+    for the manufactured load against the closed-form field (which adds the O(h^2)
     discretisation error)."""
     from paper_2501_12151_amd import tnfem
 
@@ -405,8 +413,8 @@ def accuracy_block(P, u, u64, oracle_cores, opts, name, prob, refs=True):
         out["rel_error_vs_oracle"] = err
         out["oracle"] = (f"the oracle's FP64 AMEn solve of the same problem on the host, {label(opts)}, "
                          f"{opts['max_sweeps']} half-sweeps")
-        if u64 is not None:
-            out["fp64_solver_rel_error_vs_oracle"] = u64.rel_diff(ref)
+        if u_side is not None:
+            out[side_key + "_rel_error_vs_oracle"] = u_side.rel_diff(ref)
         judged = ("oracle", err)
     top = None
     if refs:
@@ -427,8 +435,8 @@ def accuracy_block(P, u, u64, oracle_cores, opts, name, prob, refs=True):
             out["oracle_vs_fp64_reference"] = tnfem.TT.from_cores(oracle_cores).rel_diff(top)
         if judged is None:
             judged = ("fp64_reference", err)
-    if u64 is not None:
-        out["rel_diff_vs_fp64_same_options"] = u.rel_diff(u64)
+    if u_side is not None:
+        out["rel_diff_vs_" + side_key] = u.rel_diff(u_side)
     if "manufactured_c" in prob:
         exact = tnfem.TT.from_cores(manufactured_field_cores(prob["level"], prob["manufactured_c"]))
         out["rel_error_vs_closed_form"] = u.rel_diff(exact)

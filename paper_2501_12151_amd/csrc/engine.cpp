@@ -1596,6 +1596,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
         const FusedArgs& f = L[ids[i]].f;
         args.h_f[nf + i] = f;
         fb.zoff[i + 1] = fb.zoff[i] + f.ksplit;
+        fb.bpw = std::max(fb.bpw, fused16_bpw(f));
       }
       nf += fb.nreq;
     };

@@ -688,6 +688,188 @@ __global__ __launch_bounds__(256) void fused_apply64_kernel(FusedArgs f) {
   fused_apply64_body<P>(f, blockIdx.y, blockIdx.z);
 }
 
+// acc[j] += A[r[j] + 0..15][0..K-1] * B[0..K-1][c[j] + 0..15] for the BPW blocks of a
+// wave (A stored sA[k][m], B stored sB[k][n]), K a multiple of 8, k ascending per block.
+// The fragments of the next two k steps are read from LDS while the current ones
+// are multiplied, so the MFMA pipe does not wait for LDS between steps.
+template <int P, int BPW>
+__device__ __forceinline__ void mfma_blocks(const typename Prec<P>::T (*sA)[65], const typename Prec<P>::T (*sB)[65],
+                                            int K, const int (&r)[BPW], const int (&c)[BPW], int lk, int lrow,
+                                            typename Prec<P>::Acc (&acc)[BPW]) {
+  using T = typename Prec<P>::T;
+  T a[2][BPW], b[2][BPW], an[2][BPW], bn[2][BPW];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < BPW; ++j) {
+      a[h][j] = sA[4 * h + lk][r[j] + lrow];
+      b[h][j] = sB[4 * h + lk][c[j] + lrow];
+    }
+  for (int kk = 0; kk < K; kk += 8) {
+    const bool more = kk + 8 < K;
+    if (more) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < BPW; ++j) {
+          an[h][j] = sA[kk + 8 + 4 * h + lk][r[j] + lrow];
+          bn[h][j] = sB[kk + 8 + 4 * h + lk][c[j] + lrow];
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < BPW; ++j) {
+        if constexpr (P == 0)
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][j], b[h][j], acc[j], 0, 0, 0);
+        else
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][j], b[h][j], acc[j], 0, 0, 0);
+      }
+    if (more) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < BPW; ++j) {
+          a[h][j] = an[h][j];
+          b[h][j] = bn[h][j];
+        }
+    }
+  }
+}
+
+// FP64 and FP32 operands, 32 < max(p, q, s, t) <= 64: the same one-pass product on
+// 16 x 16 MFMA blocks.  The stage-1 product (p x s) and the output (p x t) are covered
+// by ceil(rows / 16) x ceil(cols / 16) blocks and both contractions run over K rounded
+// up to 8 (two MFMA depths), so a rank between 33 and 63 costs in proportion to its
+// size rather than to 64 (the zero padding adds exact zeros: the results equal those
+// of the 64-padded product bit for bit).  Wave w owns blocks w, w + 4, ..., BPW of
+// them (slots beyond the block count repeat the last block and are not stored); the
+// BPW independent accumulation chains are interleaved per k step.  The sT rows from s
+// to the next multiple of 8 are read by stage 2: stage 1 writes them (zero columns of x).
+template <int P, int BPW>
+__device__ __forceinline__ void fused_apply16_body(const FusedArgs& f, const int grp, const int z) {
+  using T = typename Prec<P>::T;
+  using Acc = typename Prec<P>::Acc;
+  static_assert(P == 0 || P == 1, "16 x 16 x 4 MFMA operands");
+  __shared__ T sA[64][65];
+  __shared__ T sB[64][65];
+  __shared__ T sT[64][65];
+  __shared__ T sR[64][65];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int lrow = lane % 16, lk = lane / 16;
+  const int tb0 = f.begv[grp], te0 = f.begv[grp + 1];
+  const int cnt = te0 - tb0;
+  const int chunk = (cnt + f.ksplit - 1) / f.ksplit;
+  const int tb = tb0 + z * chunk;
+  const int te = tb + chunk < te0 ? tb + chunk : te0;
+  const long Lrow = (long)f.Rl * f.q, Xrow = (long)f.n * f.s, Rrow = (long)f.Rr * f.s;
+  int mc, me;
+  double mv;
+  term_prefetch(f, f.tc, tb, te, lane, mc, me, mv);
+  if (f.skip && *f.skip) return;
+  const int mb = (f.p + 15) / 16, sbk = (f.s + 15) / 16, tbk = (f.t + 15) / 16;
+  const int nb1 = mb * sbk, nb2 = mb * tbk;
+  const int k1 = (f.q + 7) & ~7, k2 = (f.s + 7) & ~7;
+  // block offsets: stage 1 (rows of p, columns of s), stage 2 (rows of p, columns of t)
+  int r1[BPW], c1[BPW], r2[BPW], c2[BPW];
+#pragma unroll
+  for (int j = 0; j < BPW; ++j) {
+    const int b1 = min(wave + 4 * j, nb1 - 1), b2 = min(wave + 4 * j, nb2 - 1);
+    r1[j] = (b1 / sbk) * 16;
+    c1[j] = (b1 % sbk) * 16;
+    r2[j] = (b2 / tbk) * 16;
+    c2[j] = (b2 % tbk) * 16;
+  }
+  double la[16], xb[16], rb[16], vcur = 0.0;
+  auto load = [&](int t, double (&l)[16], double (&x)[16], double (&rr)[16], double& v) {
+    int code, e;
+    term_get(f, f.tc, t, tb, mc, me, mv, code, e, v);
+    const double* Lb = f.L + (long)(code >> 4) * f.q;
+    const double* Xi = f.x + (long)(code & 15) * f.s;
+    const double* Re = f.Rt + (long)e * f.s;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
+      l[j] = (r < f.p && c < f.q) ? Lb[r * Lrow + c] : 0.0;
+      x[j] = (r < f.q && c < f.s) ? Xi[r * Xrow + c] : 0.0;
+      rr[j] = (r < f.t && c < f.s) ? Re[r * Rrow + c] : 0.0;
+    }
+  };
+  if (tb < te) load(tb, la, xb, rb, vcur);
+  Acc acc[BPW];
+#pragma unroll
+  for (int j = 0; j < BPW; ++j) acc[j] = Acc{0, 0, 0, 0};
+  for (int t = tb; t < te; ++t) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
+      sA[c][r] = (T)la[j];  // A = L rows (m = r) x q (k = c)
+      sB[r][c] = (T)xb[j];  // B = x (k = r) x s (n = c)
+      sR[c][r] = (T)rb[j];  // B' = Rt^T: k = s (c), n = t (r)
+    }
+    const double v = vcur;
+    if (t + 1 < te) load(t + 1, la, xb, rb, vcur);
+    __syncthreads();
+    Acc tacc[BPW];
+#pragma unroll
+    for (int j = 0; j < BPW; ++j) tacc[j] = Acc{0, 0, 0, 0};
+    mfma_blocks<P, BPW>(sA, sB, k1, r1, c1, lk, lrow, tacc);
+#pragma unroll
+    for (int j = 0; j < BPW; ++j) {
+      if (wave + 4 * j < nb1) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          sT[c1[j] + lrow][r1[j] + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[j][qq]);
+      }
+    }
+    __syncthreads();
+    mfma_blocks<P, BPW>(sT, sR, k2, r2, c2, lk, lrow, acc);
+    __syncthreads();
+  }
+  // block (r2, c2) lies in 32 x 32 tile (r2 / 32, c2 / 32) of the partial layout
+#pragma unroll
+  for (int j = 0; j < BPW; ++j) {
+    if (wave + 4 * j < nb2) {
+      double* Pt = f.partial + (((long)z * f.n + grp) * f.ntiles + (r2[j] / 32) * f.tiles_n + c2[j] / 32) * 1024;
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq)
+        Pt[(r2[j] % 32 + acc_row<P>(qq, lk)) * 32 + c2[j] % 32 + lrow] = (double)acc[j][qq];
+    }
+  }
+  if (f.dots) {
+    double xv[BPW][4];
+#pragma unroll
+    for (int j = 0; j < BPW; ++j)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int row = r2[j] + acc_row<P>(qq, lk), col = c2[j] + lrow;
+        const bool in = wave + 4 * j < nb2 && row < f.p && col < f.t;
+        xv[j][qq] = f.x[in ? ((long)row * f.n + grp) * f.s + col : 0];
+      }
+    double d = 0.0;
+#pragma unroll
+    for (int j = 0; j < BPW; ++j)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int row = r2[j] + acc_row<P>(qq, lk), col = c2[j] + lrow;
+        if (wave + 4 * j < nb2 && row < f.p && col < f.t) d += (double)acc[j][qq] * xv[j][qq];
+      }
+    store_block_dot(d, f.dots + (long)z * f.n + grp);
+  }
+}
+
+template <int P, int BPW>
+__global__ __launch_bounds__(256) void fused_apply16_kernel(FusedArgs f) {
+  fused_apply16_body<P, BPW>(f, blockIdx.y, blockIdx.z);
+}
+
+// 16 x 16 blocks per wave for the 16-granular apply (stage 1 and the output)
+int fused16_bpw(const FusedArgs& f) {
+  const int mb = (f.p + 15) / 16;
+  const int nb = std::max(mb * ((f.s + 15) / 16), mb * ((f.t + 15) / 16));
+  return (nb + 3) / 4;
+}
+
 // Fast path of the fused apply for p, q, s, t <= 32 (one tile, one chunk of each
 // contracted index): the next term's operand tiles are loaded into registers
 // while the current term's two MFMA products run.
@@ -1005,6 +1187,15 @@ __global__ __launch_bounds__(256) void fused_apply64_batch_kernel(FusedBatch b) 
   fused_apply64_body<P>(f, blockIdx.y, z - b.zoff[r]);
 }
 
+template <int P, int BPW>
+__global__ __launch_bounds__(256) void fused_apply16_batch_kernel(FusedBatch b) {
+  const int z = blockIdx.z;
+  int r = 0;
+  while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
+  const FusedArgs& f = b.args[r];
+  fused_apply16_body<P, BPW>(f, blockIdx.y, z - b.zoff[r]);
+}
+
 int fused_kind(const FusedArgs& f) {
   const int m = std::max(std::max(f.p, f.q), std::max(f.s, f.t));
   return m <= 32 ? FUSED_32 : (m <= 64 ? FUSED_64 : FUSED_TILED);
@@ -1045,7 +1236,10 @@ static void launch_fused_kind(const FusedArgs& f, int kind, hipEvent_t* ev, hipS
   if (kind == FUSED_32) {
     TN_LAUNCH(ev, fused_apply32_kernel<P>, g1, dim3(256), 0, s, f);
   } else if (kind == FUSED_64) {
-    TN_LAUNCH(ev, fused_apply64_kernel<P>, g1, dim3(256), 0, s, f);
+    const int bpw = P == 2 ? 4 : fused16_bpw(f);
+    if (bpw <= 1) TN_LAUNCH(ev, (fused_apply16_kernel<P == 2 ? 0 : P, 1>), g1, dim3(256), 0, s, f);
+    else if (bpw == 2) TN_LAUNCH(ev, (fused_apply16_kernel<P == 2 ? 0 : P, 2>), g1, dim3(256), 0, s, f);
+    else TN_LAUNCH(ev, fused_apply64_kernel<P>, g1, dim3(256), 0, s, f);
   } else {
     if (!f.stage || f.nslot <= 0 || fused_stage_elems(f) * sizeof(double) > f.stage_bytes)
       throw Error(TNFEM_EINVAL, "fused apply: stage buffer missing or too small for ranks above 64");
@@ -1082,9 +1276,18 @@ template <int P>
 static void launch_fused_batch_kind(const FusedBatch& b, int n, int kind, hipStream_t s) {
   const int zt = b.zoff[b.nreq];
   const dim3 g1(1, n, zt);
-  if (kind == FUSED_32) hipLaunchKernelGGL(fused_apply32_batch_kernel<P>, g1, dim3(256), 0, s, b);
-  else if (kind == FUSED_64) hipLaunchKernelGGL(fused_apply64_batch_kernel<P>, g1, dim3(256), 0, s, b);
-  else throw Error(TNFEM_EINVAL, "fused apply batch: ranks above 64 are launched per request");
+  if (kind == FUSED_32) {
+    hipLaunchKernelGGL(fused_apply32_batch_kernel<P>, g1, dim3(256), 0, s, b);
+  } else if (kind == FUSED_64) {
+    // the requests' block counts differ; the largest sets the slots per wave (a block's
+    // result does not depend on it)
+    const int bpw = P == 2 ? 4 : b.bpw;
+    if (bpw <= 1) hipLaunchKernelGGL((fused_apply16_batch_kernel<P == 2 ? 0 : P, 1>), g1, dim3(256), 0, s, b);
+    else if (bpw == 2) hipLaunchKernelGGL((fused_apply16_batch_kernel<P == 2 ? 0 : P, 2>), g1, dim3(256), 0, s, b);
+    else hipLaunchKernelGGL(fused_apply64_batch_kernel<P>, g1, dim3(256), 0, s, b);
+  } else {
+    throw Error(TNFEM_EINVAL, "fused apply batch: ranks above 64 are launched per request");
+  }
 }
 
 void launch_fused_apply_batch(const FusedBatch& b, int n, int kind, hipStream_t s, int precision) {

@@ -142,7 +142,10 @@ struct FusedBatch {
   const FusedArgs* args = nullptr;  // device array of nreq prepared FusedArgs
   int nreq = 0;
   int zoff[FB_MAX + 1] = {};
+  int bpw = 1;  // FUSED_64: the largest fused16_bpw of the requests
 };
+// 16 x 16 output blocks per wavefront of the rank-64 one-pass apply (FP64 / FP32)
+int fused16_bpw(const FusedArgs& f);
 // All requests must have the same mode count n and the same fused_kind, FUSED_32 or
 // FUSED_64 (the two-stage apply of higher ranks is launched per request).
 void launch_fused_apply_batch(const FusedBatch& b, int n, int kind, hipStream_t s, int precision = 0);
