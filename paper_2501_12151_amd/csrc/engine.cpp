@@ -1024,10 +1024,8 @@ struct Sweep {
     set_block_precond(a, n[k], t, W.binv);
     launch_cg_init2(a, W.g, W.q, o.tol, st);
     auto readback = [&]() {
-      hip_check(hipMemcpyAsync(W.host_pinned, W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flag readback");
-      hip_check(hipMemcpyAsync(static_cast<char*>(W.host_pinned) + 64, W.scal + CG_RES, sizeof(double),
-                               hipMemcpyDeviceToHost, st),
-                "res readback");
+      hip_check(hipMemcpyAsync(W.host_pinned, W.flag, (CG_RES_COPY + 2) * sizeof(int), hipMemcpyDeviceToHost, st),
+                "flag readback");
       sync();
     };
     // FP64: no readback before the first chunk (its kernels return at once when the
@@ -1038,7 +1036,7 @@ struct Sweep {
     int done = 0;
     if (!early) {
       readback();
-      res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+      res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + CG_RES_COPY * sizeof(int));
       if (!std::isfinite(res)) nan_seen = 1;
       done = hint()[0];
     }
@@ -1107,7 +1105,7 @@ struct Sweep {
       a.keep_thr = 0;
       readback();
       done = hint()[0];
-      return *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+      return *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + CG_RES_COPY * sizeof(int));
     };
     for (int refine = 0;; ++refine) {
       int kit = 0;
@@ -1148,7 +1146,7 @@ struct Sweep {
       if (early && refine == 0) {
         // the initial residual, read back with the first chunk's status (the init
         // kernel set the stop flag when it already met the target: nothing ran)
-        res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+        res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + CG_RES_COPY * sizeof(int));
         if (!std::isfinite(res)) nan_seen = 1;
         entry_done = res <= 0.5 * o.tol || o.cg_maxit <= 0;
       }
@@ -1517,10 +1515,8 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     a.nb_dir = cg_dir_blocks(c.N);
     set_block_precond(a, w.n[k], c.t, W.binv);
     launch_cg_init2(a, W.g, W.q, w.o.tol, st);
-    hip_check(hipMemcpyAsync(W.host_pinned, W.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flag readback");
-    hip_check(hipMemcpyAsync(static_cast<char*>(W.host_pinned) + 64, W.scal + CG_RES, sizeof(double),
-                             hipMemcpyDeviceToHost, st),
-              "res readback");
+    hip_check(hipMemcpyAsync(W.host_pinned, W.flag, (CG_RES_COPY + 2) * sizeof(int), hipMemcpyDeviceToHost, st),
+              "flag readback");
   }
   hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
   int max_n = 0;
@@ -1529,7 +1525,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     Workspace& W = w.W;
     Loc& c = L[r];
     const Plan& pl = *c.pl;
-    c.res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + 64);
+    c.res = *reinterpret_cast<volatile double*>(static_cast<char*>(W.host_pinned) + CG_RES_COPY * sizeof(int));
     if (!std::isfinite(c.res)) w.nan_seen = 1;
     c.done = w.hint()[0] != 0;
     c.fused = !pl.dense;

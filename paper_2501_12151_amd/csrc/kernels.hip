@@ -1679,6 +1679,8 @@ __global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const doubl
   const double res = gg > 0.0 ? sqrt(rr) / gn : (rr == 0.0 ? 0.0 : 1.0);
   a.scal[CG_GG] = gg;
   a.scal[CG_RES] = res;
+  // beside the flags, so that one copy brings both to the host
+  *reinterpret_cast<double*>(a.flag + CG_RES_COPY) = res;
   a.flag[CG_ITERS] = 0;
   if (a.keep_thr) {
     a.flag[CG_DONE] = (rr <= a.scal[CG_THR2] || a.maxit <= 0) ? 1 : 0;
@@ -2761,10 +2763,11 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
   for (int j = tid; j < n; j += SV_NT) S[pos[j]] = sv[j];
 }
 
-// The same one-sided Jacobi iteration for n <= 64.  Each column pair of a step is
-// owned by an aligned group of SVW_TPP lanes of one wavefront; lane `sub` of a group
-// holds rows sub, sub + SVW_TPP, ... of both columns in registers from the dot
-// products to the rotation, and the group reduces with DPP sums.  Rows are
+// The same one-sided Jacobi iteration for n <= 64 (n <= 128 without V).  Each
+// column pair of a step is owned by an aligned group of SVW_TPP lanes of one
+// wavefront; lane `sub` of a group holds rows sub, sub + SVW_TPP, ... of both
+// columns in registers from the dot products to the rotation, and the group
+// reduces with DPP sums.  Rows are
 // zero-padded to NR = SVW_TPP * RPL (no bounds tests in the step loop; zero rows
 // and the zero padding column of an odd n never rotate).  The column stride LD is
 // congruent to SVW_TPP mod 32 doubles: the groups of a half-wave read consecutive
@@ -2774,7 +2777,8 @@ __global__ __launch_bounds__(SV_NT) void jacobi_svd_kernel(int n, const double* 
 // of the next step's dot products.  Without V the kernel returns the normalised
 // columns of G (its left singular vectors) and S only.
 // Dynamic LDS: svw_lds_bytes(n, RPL, WITH_V).
-constexpr int SVW_MAXN = 64;
+constexpr int SVW_MAXN = 64;        // with V (G and V in LDS)
+constexpr int SVW_MAXN_LEFT = 128;  // without V (G alone in LDS)
 constexpr int SVW_TPP = 8;
 constexpr int SVW_MAX_THREADS = 512;
 
@@ -2787,7 +2791,9 @@ __host__ __device__ inline int svw_npairs(int n) {
 }
 // G wavefronts: whole waves covering npairs groups of SVW_TPP lanes
 __host__ __device__ inline int svw_gthreads(int n) { return (svw_npairs(n) * SVW_TPP + 63) / 64 * 64; }
-static int svw_rpl(int n) { return n <= SVW_TPP ? 1 : n <= 2 * SVW_TPP ? 2 : n <= 4 * SVW_TPP ? 4 : 8; }
+static int svw_rpl(int n) {
+  return n <= SVW_TPP ? 1 : n <= 2 * SVW_TPP ? 2 : n <= 4 * SVW_TPP ? 4 : n <= 8 * SVW_TPP ? 8 : 16;
+}
 static size_t svw_lds_bytes(int n, int rpl, bool with_v) {
   const size_t npad = n + (n & 1);
   const size_t cols = (with_v ? 2 : 1) * npad * svw_ld(rpl);
@@ -3093,10 +3099,11 @@ template <int RPL, bool WITH_V>
 static void svw_set_attr() {
   static std::once_flag once;
   std::call_once(once, [] {
+    const int bytes = (int)std::max(svw_lds_bytes(SVW_MAXN, 8, true), svw_lds_bytes(SVW_MAXN_LEFT, 16, false));
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_wave_kernel<RPL, WITH_V>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)svw_lds_bytes(SVW_MAXN, 8, true));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_wave_batch_kernel<RPL, WITH_V>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)svw_lds_bytes(SVW_MAXN, 8, true));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   });
 }
 
@@ -3129,7 +3136,9 @@ static void launch_svw_any(int n, const double* G, int ldg, int trans, double* U
     case 8: launch_svw<4, false>(n, G, ldg, trans, U, S, V, s); break;
     case 9: launch_svw<4, true>(n, G, ldg, trans, U, S, V, s); break;
     case 16: launch_svw<8, false>(n, G, ldg, trans, U, S, V, s); break;
-    default: launch_svw<8, true>(n, G, ldg, trans, U, S, V, s); break;
+    case 17: launch_svw<8, true>(n, G, ldg, trans, U, S, V, s); break;
+    case 32: launch_svw<16, false>(n, G, ldg, trans, U, S, V, s); break;
+    default: throw Error(TNFEM_EINVAL, "Jacobi SVD: n > 64 with V goes to the 1024-thread kernels");
   }
 }
 
@@ -3142,7 +3151,9 @@ static void launch_svw_batch_any(int rpl, bool with_v, const SvdBatch& b, hipStr
     case 8: launch_svw_batch<4, false>(b, s); break;
     case 9: launch_svw_batch<4, true>(b, s); break;
     case 16: launch_svw_batch<8, false>(b, s); break;
-    default: launch_svw_batch<8, true>(b, s); break;
+    case 17: launch_svw_batch<8, true>(b, s); break;
+    case 32: launch_svw_batch<16, false>(b, s); break;
+    default: throw Error(TNFEM_EINVAL, "Jacobi SVD batch: n > 64 with V goes to the 1024-thread kernels");
   }
 }
 
@@ -3162,13 +3173,13 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_big_batch_kernel<false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)SVB_LDS_BYTES);
   });
-  SvdBatch wave[8], big2, big1;  // wave jobs by (rows per lane, with V)
+  SvdBatch wave[10], big2, big1;  // wave jobs by (rows per lane, with V)
   size_t m2 = 0, m1 = 0;
   for (const SvdJob& j : jobs) {
     const size_t g = (size_t)j.n * (j.n + 1) * sizeof(double);
-    if (j.n <= SVW_MAXN) {
+    if (j.n <= SVW_MAXN || (j.left_only && j.n <= SVW_MAXN_LEFT)) {
       const int r = svw_rpl(j.n);
-      SvdBatch& w = wave[(r == 1 ? 0 : r == 2 ? 1 : r == 4 ? 2 : 3) * 2 + (j.left_only ? 0 : 1)];
+      SvdBatch& w = wave[(r == 1 ? 0 : r == 2 ? 1 : r == 4 ? 2 : r == 8 ? 3 : 4) * 2 + (j.left_only ? 0 : 1)];
       w.job[w.njob++] = j;
     } else if (2 * g <= SVB_LDS_BYTES) {
       big2.job[big2.njob++] = j;
@@ -3180,7 +3191,7 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
       launch_jacobi_svd(j.n, j.G, j.ldg, j.U, j.S, j.V, j.ws, s, j.trans, j.left_only);
     }
   }
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < 10; ++c) {
     if (!wave[c].njob) continue;
     launch_svw_batch_any(1 << (c / 2), c % 2 == 1, wave[c], s);
     TN_CHECK_LAUNCH();
@@ -3198,7 +3209,7 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s) {
 void launch_jacobi_svd(int n, const double* G, int ldg, double* U, double* S, double* V, double* ws, hipStream_t s,
                        int trans, bool left_only) {
   if (n > SV_MAXN) throw Error(TNFEM_EINVAL, "Jacobi SVD limited to n <= 256");
-  if (n <= SVW_MAXN) {
+  if (n <= SVW_MAXN || (left_only && n <= SVW_MAXN_LEFT)) {
     launch_svw_any(n, G, ldg, trans, U, S, V, !left_only, s);
     TN_CHECK_LAUNCH();
     return;

@@ -82,6 +82,9 @@ void set_gemm_splitk_buffer(double* p, size_t cap_doubles);
 // Device scalars of a local CG solve.
 enum CgScal { CG_RZ = 0, CG_PQ, CG_RR, CG_GG, CG_THR2, CG_RES, CG_BETA, CG_NSCAL };
 enum CgFlag { CG_DONE = 0, CG_ITERS, CG_MAXIT, CG_COUNTER, CG_NFLAG };
+// the flag buffer (8 ints) also holds the initial relative residual as a double at ints
+// CG_RES_COPY .. CG_RES_COPY + 1 (written with CG_RES by cg_init2)
+constexpr int CG_RES_COPY = 4;
 
 // Local preconditioned CG (block Jacobi over the mode index), one iteration =
 // (w = B z), then cg_step (after a fused apply that also formed (z, B z)) or
