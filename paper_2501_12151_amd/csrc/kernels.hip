@@ -2210,6 +2210,208 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, const double* A, int l
   }
 }
 
+// The same Householder QR with every column in registers for m <= 64 KR and
+// n <= 16 CPW: column col is owned by wavefront col % 16 (slot col / 16), a lane holds
+// rows lane, lane + 64, ... of each of its columns, so no column goes through memory
+// while it is factored.  Step j: every wavefront applies reflector j (read from an LDS
+// double buffer) to its columns right of j, the owner of column j + 1 first, which then
+// forms reflector j + 1, publishes it in the other buffer and keeps it in place of its
+// column below the diagonal (R above).  One barrier per column.  Reflectors also go to
+// ws (column-major, stride m) for the accumulation of Q = H_0 ... H_{c-1} E, which runs
+// backwards with the columns of Q in registers and each reflector staged into LDS two
+// steps ahead (three buffers), so the L2 latency of the staging overlaps two steps.
+// The arithmetic of a column does not depend on KR or CPW (padding rows are zero), so
+// the batched launch, sized for its largest job, gives every job the results of its
+// own launch.
+constexpr int QRC_NT = 1024, QRC_NW = 16;
+
+template <int KR, int CPW>
+__device__ __forceinline__ void qr_cols_body(int m, int n, const double* A, int lda, double* Q, int ldq, double* R,
+                                             int ldr, double* ws) {
+  __shared__ double sv[3][64 * KR];
+  __shared__ double stau[2];
+  __shared__ double tau_s[QRC_NW * CPW], diag_s[QRC_NW * CPW];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int c = m < n ? m : n;
+  double w[CPW][KR];
+#pragma unroll
+  for (int s = 0; s < CPW; ++s) {
+    const int col = wave + QRC_NW * s;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = lane + 64 * k;
+      w[s][k] = (col < n && i < m) ? A[(long)i * lda + col] : 0.0;
+    }
+  }
+  // w[s] <- (I - tj v v^T) w[s], v in LDS (zero outside the reflector's rows)
+  auto apply = [&](int s, const double* v, double tj) {
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) part += v[lane + 64 * k] * w[s][k];
+    const double f = tj * wave_sum(part);
+#pragma unroll
+    for (int k = 0; k < KR; ++k) w[s][k] -= f * v[lane + 64 * k];
+  };
+  // reflector of column j (slot s of this wavefront): rows >= j of w[s]
+  auto reflect = [&](int j, int s, int buf) {
+    double loc = 0.0, xj = 0.0;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = lane + 64 * k;
+      const double x = i >= j ? w[s][k] : 0.0;
+      loc += x * x;
+      xj = i == j ? w[s][k] : xj;
+    }
+    const double s2 = wave_sum(loc);
+    const double x0 = __shfl(xj, j % 64, 64);
+    const double nrm = sqrt(s2);
+    double tj = 0.0, alpha = 0.0, v0 = x0;
+    if (nrm > 0.0) {
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      v0 = x0 - alpha;
+      tj = 2.0 / (s2 - x0 * x0 + v0 * v0);
+    }
+    double* wsj = ws + (long)j * m;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = lane + 64 * k;
+      const double v = i == j ? v0 : (i > j ? w[s][k] : 0.0);
+      sv[buf][i] = v;
+      if (i < m) wsj[i] = v;
+      if (i == j) w[s][k] = v0;  // rows > j already hold v; rows < j keep R
+    }
+    if (lane == 0) {
+      stau[buf] = tj;
+      tau_s[j] = tj;
+      diag_s[j] = alpha;
+    }
+  };
+  if (c > 0 && wave == 0) reflect(0, 0, 0);
+  __syncthreads();
+  for (int j = 0; j < c; ++j) {
+    const double* v = sv[j & 1];
+    const double tj = stau[j & 1];
+    const int nxt = j + 1;
+    // the owner of column j + 1: that column first, then its reflector (slots are
+    // compile-time indices, so the columns stay in registers)
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) {
+      if (nxt < n && wave + QRC_NW * s == nxt) {
+        if (tj != 0.0) apply(s, v, tj);
+        if (nxt < c) reflect(nxt, s, nxt & 1);
+      }
+    }
+    if (tj != 0.0) {
+#pragma unroll
+      for (int s = 0; s < CPW; ++s) {
+        const int col = wave + QRC_NW * s;
+        if (col > nxt && col < n) apply(s, v, tj);
+      }
+    }
+    __syncthreads();
+  }
+  // R: rows < col of a column are final, its diagonal is diag_s, zeros below
+#pragma unroll
+  for (int s = 0; s < CPW; ++s) {
+    const int col = wave + QRC_NW * s;
+    if (col >= n) continue;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = lane + 64 * k;
+      if (i < c) R[(long)i * ldr + col] = i < col ? w[s][k] : (i == col ? diag_s[col] : 0.0);
+    }
+  }
+  // Q = H_0 ... H_{c-1} E backwards; reflector j staged into sv[j % 3] two steps ahead
+  auto stage = [&](int j) {
+    const double* wsj = ws + (long)j * m;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = lane + 64 * k;
+      sv[j % 3][i] = i < m ? wsj[i] : 0.0;
+    }
+  };
+  __syncthreads();  // the reflectors in ws are complete (every wavefront wrote its own)
+  if (wave == 0 && c >= 1) stage(c - 1);
+  if (wave == 1 && c >= 2) stage(c - 2);
+#pragma unroll
+  for (int s = 0; s < CPW; ++s) {
+    const int col = wave + QRC_NW * s;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) w[s][k] = (lane + 64 * k == col) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = c - 1; j >= 0; --j) {
+    if (j >= 2 && wave == j % QRC_NW) stage(j - 2);
+    const double* v = sv[j % 3];
+    const double tj = tau_s[j];
+    if (tj != 0.0) {
+#pragma unroll
+      for (int s = 0; s < CPW; ++s) {
+        const int col = wave + QRC_NW * s;
+        if (col >= j && col < c) apply(s, v, tj);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < CPW; ++s) {
+    const int col = wave + QRC_NW * s;
+    if (col >= c) continue;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = lane + 64 * k;
+      if (i < m) Q[(long)i * ldq + col] = w[s][k];
+    }
+  }
+}
+
+template <int KR, int CPW>
+__global__ __launch_bounds__(QRC_NT) void qr_cols_kernel(int m, int n, const double* A, int lda, double* Q, int ldq,
+                                                         double* R, int ldr, double* ws) {
+  qr_cols_body<KR, CPW>(m, n, A, lda, Q, ldq, R, ldr, ws);
+}
+
+template <int KR, int CPW>
+__global__ __launch_bounds__(QRC_NT) void qr_cols_batch_kernel(QrBatch b) {
+  const QrJob j = b.job[blockIdx.x];
+  qr_cols_body<KR, CPW>(j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R, j.ldr, j.ws);
+}
+
+// rows per lane and columns per wavefront of the register-column QR (0: does not apply)
+static int qrc_kr(int m) { return m <= 64 ? 1 : (m <= 128 ? 2 : (m <= 256 ? 4 : (m <= 512 ? 8 : 0))); }
+static int qrc_cpw(int n) { return n <= 16 ? 1 : (n <= 32 ? 2 : (n <= 48 ? 3 : (n <= 80 ? 5 : 0))); }
+
+template <int KR>
+static void launch_qrc_kr(int cpw, const QrJob& j, const QrBatch* b, hipStream_t s) {
+  if (b) {
+    if (cpw == 1) hipLaunchKernelGGL((qr_cols_batch_kernel<KR, 1>), dim3(b->njob), dim3(QRC_NT), 0, s, *b);
+    else if (cpw == 2) hipLaunchKernelGGL((qr_cols_batch_kernel<KR, 2>), dim3(b->njob), dim3(QRC_NT), 0, s, *b);
+    else if (cpw == 3) hipLaunchKernelGGL((qr_cols_batch_kernel<KR, 3>), dim3(b->njob), dim3(QRC_NT), 0, s, *b);
+    else hipLaunchKernelGGL((qr_cols_batch_kernel<KR, 5>), dim3(b->njob), dim3(QRC_NT), 0, s, *b);
+  } else {
+    if (cpw == 1)
+      hipLaunchKernelGGL((qr_cols_kernel<KR, 1>), dim3(1), dim3(QRC_NT), 0, s, j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R,
+                         j.ldr, j.ws);
+    else if (cpw == 2)
+      hipLaunchKernelGGL((qr_cols_kernel<KR, 2>), dim3(1), dim3(QRC_NT), 0, s, j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R,
+                         j.ldr, j.ws);
+    else if (cpw == 3)
+      hipLaunchKernelGGL((qr_cols_kernel<KR, 3>), dim3(1), dim3(QRC_NT), 0, s, j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R,
+                         j.ldr, j.ws);
+    else
+      hipLaunchKernelGGL((qr_cols_kernel<KR, 5>), dim3(1), dim3(QRC_NT), 0, s, j.m, j.n, j.A, j.lda, j.Q, j.ldq, j.R,
+                         j.ldr, j.ws);
+  }
+}
+
+// one QR (b == nullptr) or a batch sized for its largest job
+static void launch_qrc(int kr, int cpw, const QrJob& j, const QrBatch* b, hipStream_t s) {
+  if (kr == 1) launch_qrc_kr<1>(cpw, j, b, s);
+  else if (kr == 2) launch_qrc_kr<2>(cpw, j, b, s);
+  else if (kr == 4) launch_qrc_kr<4>(cpw, j, b, s);
+  else launch_qrc_kr<8>(cpw, j, b, s);
+}
+
 // threads of the register variant: 32 rows per lane need the register file of 2 waves per SIMD
 template <int KR>
 constexpr int qr_reg_threads() { return KR >= 32 ? 512 : QR_NT; }
@@ -2537,13 +2739,30 @@ void launch_qr_batch(const std::vector<QrJob>& jobs, hipStream_t s) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_owner_batch_kernel<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_BYTES);
   });
-  // padded LDS variant for the jobs that fit with the batch's common row count per
-  // lane, then the unpadded LDS kernel, then the global-memory variants
+  // the register-column kernel for the jobs it takes (one launch sized for the largest),
+  // then the padded LDS variant for the jobs that fit with the batch's common row count
+  // per lane, then the unpadded LDS kernel, then the global-memory variants
+  QrBatch in_cols;
+  int ckr = 0, ccpw = 0;
+  std::vector<QrJob> rest_jobs;
+  for (const QrJob& j : jobs) {
+    if (qrc_kr(j.m) > 0 && qrc_cpw(j.n) > 0) {
+      in_cols.job[in_cols.njob++] = j;
+      ckr = std::max(ckr, qrc_kr(j.m));
+      ccpw = std::max(ccpw, qrc_cpw(j.n));
+    } else {
+      rest_jobs.push_back(j);
+    }
+  }
+  if (in_cols.njob) {
+    launch_qrc(ckr, ccpw, in_cols.job[0], &in_cols, s);
+    TN_CHECK_LAUNCH();
+  }
   int kp = 0;
-  for (const QrJob& j : jobs) kp = std::max(kp, qr_pad_rows(j.m) == 0 ? 1 << 20 : qr_pad_rows(j.m));
+  for (const QrJob& j : rest_jobs) kp = std::max(kp, qr_pad_rows(j.m) == 0 ? 1 << 20 : qr_pad_rows(j.m));
   QrBatch in_pad, in_lds, in_ws;
   size_t pad_max = 0, lds_max = 0;
-  for (const QrJob& j : jobs) {
+  for (const QrJob& j : rest_jobs) {
     if (kp <= 8 && qr_pad_fits(j.m, j.n, kp)) {
       in_pad.job[in_pad.njob++] = j;
       pad_max = std::max(pad_max, qr_pad_bytes(j.m, j.n, kp));
@@ -2605,7 +2824,10 @@ void launch_qr(int m, int n, const double* A, int lda, double* Q, int ldq, doubl
                                   std::to_string(n) + " QR may use");
   const size_t bytes = qr_lds_bytes(m, n);
   const int kp = qr_pad_rows(m);
-  if (qr_pad_fits(m, n, kp)) {
+  if (qrc_kr(m) > 0 && qrc_cpw(n) > 0) {
+    QrJob j{m, n, lda, ldq, ldr, A, Q, R, ws, ws_cap};
+    launch_qrc(qrc_kr(m), qrc_cpw(n), j, nullptr, s);
+  } else if (qr_pad_fits(m, n, kp)) {
     const size_t pb = qr_pad_bytes(m, n, kp);
     if (kp == 1) launch_qr_reg<1, true>(m, n, A, lda, Q, ldq, R, ldr, ws, pb, s);
     else if (kp == 2) launch_qr_reg<2, true>(m, n, A, lda, Q, ldq, R, ldr, ws, pb, s);

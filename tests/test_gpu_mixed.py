@@ -26,7 +26,11 @@ def ctx():
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("ranks", [(32, 32, 32, 32), (5, 7, 33, 17), (70, 65, 100, 66), (129, 40, 33, 72)])
+# rank classes: all <= 32 (fused_apply32), 16 x 16 blocks with one / two blocks per wavefront
+# (fused_apply16 at FP64 / FP32, fused_apply64 at BF16), 64 x 64 tiles (fused_apply64), above 64
+# (the two-stage slot apply)
+@pytest.mark.parametrize("ranks", [(32, 32, 32, 32), (5, 7, 33, 17), (20, 45, 37, 40), (64, 64, 64, 64),
+                                   (70, 65, 100, 66), (129, 40, 33, 72)])
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_fused_apply_precision_bound(ctx, dim, ranks, precision):
     prob = workloads.small_2d() if dim == 2 else workloads.cube_body_force(4)

@@ -26,12 +26,15 @@ def ctx():
     c.close()
 
 
-# padded LDS layout (1 / 2 / 4 / 8 rows per lane: (8, 8), (128, 64), (256, 36), (512, 16), wide (5, 37));
-# unpadded LDS ((200, 40)); beyond LDS: blocked for 256 < m <= 2048 and n >= 32 ((300, 256), (513, 65),
-# (1024, 132), (1600, 200)), else 8 / 16 / 32 rows per lane in registers ((100, 250), (700, 24),
-# (1500, 20)); taller than 2048 rows (the plain global-memory variant)
+# every column in registers for m <= 512 and n <= 80 (1 / 2 / 4 / 8 rows per lane, 1 / 2 / 3 / 5
+# columns per wavefront: (1, 1), (8, 8), (64, 16), (37, 5), wide (5, 37) and (64, 80), (128, 64),
+# (200, 40), (256, 36), (300, 80), (480, 33), (512, 16), (512, 72)); wider: the padded LDS layout
+# ((100, 250)); beyond LDS: blocked for 256 < m <= 2048 and n >= 32 ((300, 256), (513, 65),
+# (1024, 132), (1600, 200)), else 8 / 16 / 32 rows per lane ((700, 24), (1500, 20)); taller than
+# 2048 rows (the plain global-memory variant)
 QR_SHAPES = [(1, 1), (8, 8), (64, 16), (256, 36), (1024, 132), (37, 5), (5, 37), (300, 256), (1600, 200),
-             (100, 250), (2100, 40), (513, 65), (200, 40), (128, 64), (512, 16), (700, 24), (1500, 20)]
+             (100, 250), (2100, 40), (513, 65), (200, 40), (128, 64), (512, 16), (700, 24), (1500, 20),
+             (512, 72), (300, 80), (64, 80), (480, 33)]
 
 
 @pytest.mark.parametrize("m,n", QR_SHAPES)
@@ -50,7 +53,7 @@ def test_qr_matches_definition(ctx, m, n):
     assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rl)), rtol=1e-10, atol=1e-12)
 
 
-@pytest.mark.parametrize("m,n", [(700, 60), (40, 12)])
+@pytest.mark.parametrize("m,n", [(700, 60), (40, 12), (500, 60)])
 def test_qr_rank_deficient(ctx, m, n):
     """Zero and repeated columns (zero reflectors): Q R = A and Q orthonormal still hold."""
     print(f"qr deficient m={m} n={n}", flush=True)
