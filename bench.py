@@ -570,16 +570,17 @@ def serving_accuracy(reqs, kept):
     }
 
 
-def serving(args):
-    """Serving stream: Poisson arrivals of mixed 2D/3D requests; throughput and p50/p99 latency."""
+def serving_run(args, precision):
+    """One serving measurement at the given local-apply precision: a closed loop (64
+    requests at once, saturation throughput), then the Poisson stream at 0.8 x that rate.
+    Returns the stream's figures and the solutions kept for the accuracy sample."""
     from paper_2501_12151_amd import tnfem, workloads
 
     # enrichment rank 8 and 20 half-sweeps: 3D requests end near their cap's error floor
     # (12 half-sweeps with rank 4 stop at 2e-2 .. 8e-2 from the reference)
     def opts_for(cap):
-        return dict(rank_cap=cap, tol=1e-8, max_sweeps=20, rho=8)
+        return dict(rank_cap=cap, tol=1e-8, max_sweeps=20, rho=8, precision=precision)
 
-    # closed loop: all requests at once -> saturation throughput
     sat_reqs = workloads.serving_stream(min(64, args.requests), seed=1, rate=1.0)
     srv = tnfem.Server(0, slots=args.slots)
     t0 = time.perf_counter()
@@ -588,7 +589,7 @@ def serving(args):
         srv.poll(t)
     sat = len(ts) / (time.perf_counter() - t0)
     srv.close()
-    print(f"closed loop: {len(ts)} requests, {sat:.2f} solves/s", file=sys.stderr, flush=True)
+    print(f"{DTYPE_TAGS[precision]} closed loop: {len(ts)} requests, {sat:.2f} solves/s", file=sys.stderr, flush=True)
     rate = 0.8 * sat
     reqs = workloads.serving_stream(args.requests, seed=0, rate=rate)
     srv = tnfem.Server(0, slots=args.slots)
@@ -612,26 +613,45 @@ def serving(args):
     elapsed = time.perf_counter() - t0
     info = srv.info()
     srv.close()
+    return dict(sat=sat, rate=rate, n=len(tickets), elapsed=elapsed, lat=lat, info=info), reqs, kept
+
+
+def serving(args):
+    """Serving stream: Poisson arrivals of mixed 2D/3D requests; throughput and p50/p99 latency.
+    With --precision 1 or 2 (low-precision local applies, FP64-refined local solves, lockstep
+    batches as in FP64) the plain FP64 stream is measured the same way beside it."""
+    r, reqs, kept = serving_run(args, args.precision)
     accuracy = serving_accuracy(reqs, kept)
+    fp64 = None
+    if args.precision != 0 and not args.no_side_solver:
+        r64, _, kept64 = serving_run(args, 0)
+        for u in kept64.values():
+            if u is not None:
+                u.close()
+        fp64 = {"value": r64["n"] / r64["elapsed"], "unit": "solves/s", "closed_loop_solves_per_s": r64["sat"],
+                "latency_ms": {"p50": 1e3 * percentile(r64["lat"], 0.5), "p99": 1e3 * percentile(r64["lat"], 0.99)},
+                "server": r64["info"]}
     out = {
         "metric": METRIC,
-        "value": len(tickets) / elapsed,
+        "value": r["n"] / r["elapsed"],
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": len(tickets),
+        "steps": r["n"],
         "warmup": 0,
-        "ms_per_step": 1e3 * elapsed / len(tickets),
+        "ms_per_step": 1e3 * r["elapsed"] / r["n"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPE_TAGS[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"serving stream: {len(tickets)} requests, Poisson arrivals at 0.8 x closed-loop "
-                               f"rate ({rate:.2f}/s), 2D/3D, levels 6..10, caps 32..64, {args.slots} slots",
-                   "closed_loop_solves_per_s": sat},
-        "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
-        "server": info,
+        "config": {"workload": f"serving stream: {r['n']} requests, Poisson arrivals at 0.8 x closed-loop "
+                               f"rate ({r['rate']:.2f}/s), 2D/3D, levels 6..10, caps 32..64, {args.slots} slots, "
+                               f"{DTYPES[args.precision]}",
+                   "closed_loop_solves_per_s": r["sat"]},
+        "latency_ms": {"p50": 1e3 * percentile(r["lat"], 0.5), "p99": 1e3 * percentile(r["lat"], 0.99)},
+        "server": r["info"],
         "accuracy": accuracy,
+        "fp64_serving": fp64,
     }
     print(json.dumps(out), flush=True)
 

@@ -249,11 +249,13 @@ int tnfem_problem_info(const tnfem_problem* p, int* ncores, int* modes, int* mpo
 int tnfem_solve(tnfem_problem* p, const tnfem_solve_opts* opts, tnfem_tt** u_out, tnfem_solve_stats* stats);
 
 /* Lockstep solve of n problems (1 <= n <= 16) of the same dimension and level,
- * created in the same context, FP64 (opts->precision 0, no profile): every problem
- * takes exactly the steps of tnfem_solve and gets the same result bit for bit,
- * while the local CG iterations of all problems still iterating are issued as
- * shared launches (one fused local apply, one direction update and one vector
- * update per iteration for the whole batch).  Serving batches of requests of one
+ * created in the same context, with one set of options (any opts->precision, no
+ * outer refinement (ir_max 0), no profile): every problem takes exactly the steps of
+ * tnfem_solve and gets the same result bit for bit, including the FP64 refinement of
+ * its low-precision local solves, while the local CG iterations of all problems still
+ * iterating are issued as shared launches (one fused local apply per rank class and
+ * operand precision, one direction update and one vector update per iteration for
+ * the whole batch).  Serving batches of requests of one
  * shape bucket (the request server groups queued requests this way).
  * problems[n] (caller-owned); u_out[n] receives a TT per problem whose status[n]
  * is TNFEM_OK or TNFEM_ENOTCONV (NULL otherwise); stats[n] may be NULL.  Returns
@@ -265,7 +267,8 @@ int tnfem_solve_batch(tnfem_problem* const* problems, int n, const tnfem_solve_o
  * A server runs many solves on one device at once.  Requests are queued at
  * submission; each of `slots` worker slots (its own HIP stream) takes the oldest
  * queued request together with the other queued requests of its shape bucket
- * (same dimension, level and solve options, FP64; at most max_batch, default 8),
+ * (same dimension, level and solve options, no outer refinement; at most
+ * max_batch, default 8),
  * assembles their problems on the host, and uploads and starts them as soon as
  * their device bytes (operator plans, load cores and workspaces, counted before
  * any device allocation) fit in the HBM budget next to the running requests, so requests arriving while others run are admitted as slots and

@@ -1469,10 +1469,11 @@ struct BatchArgs {
   }
 };
 
-// The local solves of core k of several sweeps (same chain, same orientation, FP64):
-// per request exactly the steps of Sweep::solve_core, with the CG iterations of all
-// requests issued as shared launches (one fused apply, one direction update, one
-// vector update per iteration).  Returns each request's local residual.
+// The local solves of core k of several sweeps (same chain, same orientation, same
+// options): per request exactly the steps of Sweep::solve_core, with the CG iterations
+// of all requests issued as shared launches (one fused apply per rank class and
+// operand precision, one direction update, one vector update per iteration).  Returns
+// each request's local residual.
 std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& args, hipStream_t st) {
   const int nb = (int)S.size();
   struct Loc {
@@ -1572,31 +1573,78 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     c.fl0 = w.fl.total;
     max_n = std::max(max_n, w.n[k]);
   }
-  // requests still iterating, split by apply kind; argument arrays to the device once
-  std::vector<int> cg, other, bykind[3];
+  // The local refinement of Sweep::solve_core, request by request: passes of CG
+  // iterations (low precision: at most 100 iterations each) issued in lockstep for all
+  // requests still iterating, then, for the requests whose low-precision pass ended, the
+  // FP64 restart and the same decisions as the single solve (continue in low precision,
+  // go back to the best FP64-checked iterate, finish in FP64).
+  const int maxit = S[0]->o.cg_maxit;
+  const int lp_pass_cap = 100;
+  struct Pass {
+    int prec = 0, refine = 0, total_its = 0, applies = 0;
+    bool conv_entry = false, finished = false;
+    double res_best = 0.0;
+  };
+  std::vector<Pass> ps(nb);
   for (int r = 0; r < nb; ++r) {
-    if (L[r].done) continue;
-    cg.push_back(r);
-    if (!L[r].fused) other.push_back(r);
-    else bykind[fused_kind(L[r].f)].push_back(r);
+    Sweep& w = *S[r];
+    Pass& q = ps[r];
+    q.prec = L[r].fused ? w.o.precision : 0;
+    q.conv_entry = q.finished = L[r].done;
+    q.res_best = L[r].res;
+    if (q.prec && !q.conv_entry) launch_copy2d(1, L[r].N, w.X[k], L[r].N, w.W.ye, L[r].N, 1.0, 0.0, st);
   }
-  int kit = 0;
-  if (!cg.empty()) {
-    FusedBatch fb[2];  // shared launches of the one-pass kernels; ranks above 64 per request
+  // FP64 restart of request r: the residual of its iterate recomputed in FP64, the CG
+  // restarted from it with the kept threshold (read back by the caller)
+  auto restart = [&](int r) {
+    Sweep& w = *S[r];
+    Loc& c = L[r];
+    set_gemm_splitk_buffer(w.W.splitk, w.W.splitk_cap);
+    w.apply(k, c.p, c.p, c.t, c.t, w.EA[k], w.X[k], w.EA[k + 1], w.W.q, nullptr);
+    w.applies++;
+    c.a.keep_thr = 1;
+    c.a.maxit = maxit - ps[r].total_its;
+    launch_cg_init2(c.a, w.W.g, w.W.q, w.o.tol, st);
+    c.a.keep_thr = 0;
+    hip_check(hipMemcpyAsync(w.W.host_pinned, w.W.flag, (CG_RES_COPY + 2) * sizeof(int), hipMemcpyDeviceToHost, st),
+              "flag readback");
+  };
+  for (;;) {
+    // requests in a pass, split by apply kind and operand precision
+    std::vector<int> cg, other, tiled, bykind[2][3];
+    for (int r = 0; r < nb; ++r) {
+      if (ps[r].finished) continue;
+      cg.push_back(r);
+      if (!L[r].fused) other.push_back(r);
+      else if (fused_kind(L[r].f) == FUSED_TILED) tiled.push_back(r);
+      else bykind[fused_kind(L[r].f)][ps[r].prec].push_back(r);
+      L[r].a.maxit = ps[r].prec ? std::min(maxit - ps[r].total_its, lp_pass_cap) : maxit - ps[r].total_its;
+    }
+    if (cg.empty()) break;
+    int kit = 0, bmax = 0;
+    for (int r : cg) bmax = std::max(bmax, L[r].a.maxit);
+    std::vector<double> fl0(nb), fll0(nb);
+    for (int r : cg) {
+      fl0[r] = S[r]->fl.total;
+      fll0[r] = S[r]->fl_low;
+    }
+    FusedBatch fb[2][3];  // shared launches of the one-pass kernels; ranks above 64 per request
     int nf = 0;
-    auto fill = [&](const std::vector<int>& ids, FusedBatch& fb) {
-      fb.args = args.d_f + nf;
-      fb.nreq = (int)ids.size();
-      fb.zoff[0] = 0;
-      for (int i = 0; i < fb.nreq; ++i) {
-        const FusedArgs& f = L[ids[i]].f;
-        args.h_f[nf + i] = f;
-        fb.zoff[i + 1] = fb.zoff[i] + f.ksplit;
-        fb.bpw = std::max(fb.bpw, fused16_bpw(f));
+    for (int kd = 0; kd < 2; ++kd)
+      for (int pr = 0; pr < 3; ++pr) {
+        FusedBatch& b = fb[kd][pr];
+        const std::vector<int>& ids = bykind[kd][pr];
+        b.args = args.d_f + nf;
+        b.nreq = (int)ids.size();
+        b.zoff[0] = 0;
+        for (int i = 0; i < b.nreq; ++i) {
+          const FusedArgs& f = L[ids[i]].f;
+          args.h_f[nf + i] = f;
+          b.zoff[i + 1] = b.zoff[i] + f.ksplit;
+          b.bpw = std::max(b.bpw, fused16_bpw(f));
+        }
+        nf += b.nreq;
       }
-      nf += fb.nreq;
-    };
-    for (int kd = 0; kd < 2; ++kd) fill(bykind[kd], fb[kd]);
     // requests whose apply forms (z, B z) take one step kernel per iteration, the others
     // the direction and update kernels; the argument array holds the step group first
     // (step requests grouped by their block size: 64-thread blocks first)
@@ -1636,16 +1684,19 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
                 "batch args upload");
     hip_check(hipMemcpyAsync(args.d_a, args.h_a, sizeof(CgIterArgs) * cg.size(), hipMemcpyHostToDevice, st),
               "batch args upload");
-    const int budget = S[0]->o.cg_maxit;
     const int chunk = 8;
     bool any = true;
-    while (any && kit <= budget) {
-      for (int c = 0; c < chunk && kit <= budget; ++c, ++kit) {
+    while (any && kit <= bmax) {
+      for (int c = 0; c < chunk && kit <= bmax; ++c, ++kit) {
         for (int kd = 0; kd < 2; ++kd)
-          if (fb[kd].nreq) launch_fused_apply_batch(fb[kd], max_n, kd, st, 0);
-        for (int r : bykind[FUSED_TILED]) launch_fused_apply(L[r].f, 0.0, st, 0);
-        for (int kd = 0; kd < 3; ++kd)
-          for (int r : bykind[kd]) S[r]->fl.total += L[r].apply_flops;
+          for (int pr = 0; pr < 3; ++pr)
+            if (fb[kd][pr].nreq) launch_fused_apply_batch(fb[kd][pr], max_n, kd, st, pr);
+        for (int r : tiled) launch_fused_apply(L[r].f, 0.0, st, ps[r].prec);
+        for (int r : cg) {
+          if (!L[r].fused) continue;
+          S[r]->fl.total += L[r].apply_flops;
+          if (ps[r].prec) S[r]->fl_low += L[r].apply_flops;
+        }
         for (int r : other) {
           Sweep& w = *S[r];
           if (L[r].explicit_mat) {
@@ -1668,22 +1719,81 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
       any = false;
       for (int r : cg) any = any || S[r]->hint()[0] == 0;
     }
+    // the apply of launch index i runs before iteration i's convergence test, so a pass
+    // that stopped after `its` iterations ran its + 1 applies
+    std::vector<int> rs;
+    for (int r : cg) {
+      Sweep& w = *S[r];
+      Pass& q = ps[r];
+      const int its = w.hint()[1];
+      const int ran = std::min(kit, its + 1);
+      if (kit > 0) {
+        const double frac = (double)ran / kit;
+        w.fl.total = fl0[r] + (w.fl.total - fl0[r]) * frac;
+        w.fl_low = fll0[r] + (w.fl_low - fll0[r]) * frac;
+      }
+      q.applies += ran;
+      q.total_its += its;
+      if (q.prec == 0 || q.conv_entry || q.total_its >= maxit) {
+        q.finished = true;
+        continue;
+      }
+      rs.push_back(r);
+    }
+    if (rs.empty()) continue;
+    for (int r : rs) restart(r);
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    std::vector<int> back;
+    for (int r : rs) {
+      Sweep& w = *S[r];
+      Pass& q = ps[r];
+      const double res_now =
+          *reinterpret_cast<volatile double*>(static_cast<char*>(w.W.host_pinned) + CG_RES_COPY * sizeof(int));
+      w.refinements++;
+      if (w.hint()[0]) {
+        q.finished = true;
+        continue;
+      }
+      if (std::isfinite(res_now) && res_now < 0.9 * q.res_best && q.refine < 30) {
+        q.res_best = res_now;
+        launch_copy2d(1, L[r].N, w.X[k], L[r].N, w.W.ye, L[r].N, 1.0, 0.0, st);
+        q.refine++;
+        continue;
+      }
+      if (!(std::isfinite(res_now) && res_now < q.res_best)) {
+        launch_copy2d(1, L[r].N, w.W.ye, L[r].N, w.X[k], L[r].N, 1.0, 0.0, st);
+        back.push_back(r);
+        continue;
+      }
+      q.prec = 0;
+      w.fallbacks++;
+      q.refine++;
+    }
+    if (!back.empty()) {
+      for (int r : back) restart(r);
+      hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+      for (int r : back) {
+        Sweep& w = *S[r];
+        Pass& q = ps[r];
+        if (w.hint()[0]) {
+          q.finished = true;
+          continue;
+        }
+        q.prec = 0;
+        w.fallbacks++;
+        q.refine++;
+      }
+    }
   }
   std::vector<double> res(nb);
   for (int r = 0; r < nb; ++r) {
     Sweep& w = *S[r];
     Loc& c = L[r];
-    int its = 0, ran = 0;
-    if (!c.done) {
-      its = w.hint()[1];
-      ran = std::min(kit, its + 1);
-      if (kit > 0) w.fl.total = c.fl0 + (w.fl.total - c.fl0) * ((double)ran / kit);
-    }
-    w.applies += ran;
-    w.cg_iters += its;
+    w.applies += ps[r].applies;
+    w.cg_iters += ps[r].total_its;
     if (w.verbose >= 2)
       fprintf(stderr, "[tnfem]   core %d (orient %d, batch of %d) p %d n %d t %d N %d %s res %.3e cg %d\n", k,
-              w.orient, nb, c.p, w.n[k], c.t, c.N, c.pl->dense ? "dense" : "sparse", c.res, its);
+              w.orient, nb, c.p, w.n[k], c.t, c.N, c.pl->dense ? "dense" : "sparse", c.res, ps[r].total_its);
     res[r] = c.res;
   }
   return res;
@@ -1857,7 +1967,6 @@ int run_solve_batch(std::vector<Problem*>& Ps, const tnfem_solve_opts& o, std::v
   check_opts(o);
   const int nb = (int)Ps.size();
   TNFEM_REQUIRE(nb >= 1 && nb <= FB_MAX, "a batch holds 1 .. %d problems", FB_MAX);
-  TNFEM_REQUIRE(o.precision == 0, "batched solves run in FP64 (precision 0)");
   TNFEM_REQUIRE(o.ir_max == 0, "batched solves do not run the outer refinement");
   TNFEM_REQUIRE(!o.profile, "batched solves do not record per-launch profiles");
   Context* ctx = Ps[0]->ctx;

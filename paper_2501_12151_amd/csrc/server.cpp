@@ -4,7 +4,7 @@
 // A request is queued at submission.  Each worker slot owns a HIP stream (one
 // context); a free slot takes the oldest queued request together with the
 // queued requests of the same shape bucket (same dimension, level and solve
-// options, FP64; up to max_batch of them), assembles their problems on the host,
+// options, no outer refinement; up to max_batch of them), assembles their problems on the host,
 // computes the device bytes their solves will hold (operator plans, load cores and
 // workspace) and uploads them once that fits in the HBM budget next to the
 // requests already running (nothing is allocated on the device before admission).  A bucket of several requests is solved in lockstep with shared
@@ -217,7 +217,7 @@ class Server {
   }
 
   static bool batchable(const Request* r) {
-    return r->opts.precision == 0 && r->opts.profile == 0 && r->layer.empty();
+    return r->opts.ir_max == 0 && r->opts.profile == 0 && r->layer.empty();
   }
 
   static bool same_bucket(const Request* a, const Request* b) {

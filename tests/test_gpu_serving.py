@@ -90,8 +90,11 @@ def _bucket_requests():
     return out
 
 
-def test_server_batches_one_bucket_and_results_equal_alone():
-    opts = dict(rank_cap=32, tol=1e-6, max_sweeps=6)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_server_batches_one_bucket_and_results_equal_alone(precision):
+    """A queued bucket runs as one lockstep batch and every result equals the request
+    alone, in FP64 and with FP32 local applies (FP64-refined local solves)."""
+    opts = dict(rank_cap=32, tol=1e-6, max_sweeps=6, precision=precision)
     reqs = _bucket_requests()
     ctx = tnfem.Context(0)
     alone = []
