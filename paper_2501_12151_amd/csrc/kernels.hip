@@ -1867,21 +1867,46 @@ constexpr int BLK_MAXN = 8;
 // (modes n < 8 padded with the identity).  The blocks are principal submatrices of
 // the SPD local operator, so Gauss-Jordan needs no pivoting; the pivot row and
 // column entries are exchanged between lanes at each step.
+// The entries of block (a, c) use only the diagonal elements L[a, alpha, a] and
+// Rt[c, beta, c] of the interfaces: each wavefront first gathers those (Rl + Rr
+// values, a few loads per lane) into LDS, so the term loop reads LDS instead of one
+// scattered global load per term and interface (the same sums in the same order).
+// The block loop runs the same number of times in every wavefront of a workgroup
+// (inactive blocks skip the work), so the LDS staging can use workgroup barriers.
+constexpr int BLK_RMAX = 256;  // interface ranks staged in LDS (more: read from memory)
+
 __global__ __launch_bounds__(256) void local_block_inv_kernel(int p, int n, int t, int Rl, int Rr, const double* L,
                                                              const double* Rt, const int* beg, const int* kb,
                                                              const int* ke, const double* kv, double* binv) {
-  const int lane = threadIdx.x % 64;
+  __shared__ double sL[4][BLK_RMAX], sR[4][BLK_RMAX];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const long nblk = (long)p * t;
   const int j = lane / BLK_MAXN, i = lane % BLK_MAXN;
   const bool act = j < n && i < n;
-  for (long blk = (long)blockIdx.x * 4 + threadIdx.x / 64; blk < nblk; blk += (long)gridDim.x * 4) {
-    const int a = (int)(blk / t), c = (int)(blk % t);
+  const bool staged = Rl <= BLK_RMAX && Rr <= BLK_RMAX;
+  for (long base = (long)blockIdx.x * 4; base < nblk; base += (long)gridDim.x * 4) {
+    const long blk = base + wave;
+    const bool live = blk < nblk;
+    const int a = live ? (int)(blk / t) : 0, c = live ? (int)(blk % t) : 0;
+    if (staged) {
+      __syncthreads();  // the previous block's reads of sL / sR are done
+      if (live) {
+        for (int q = lane; q < Rl; q += 64) sL[wave][q] = L[((long)a * Rl + q) * p + a];
+        for (int q = lane; q < Rr; q += 64) sR[wave][q] = Rt[((long)c * Rr + q) * t + c];
+      }
+      __syncthreads();
+    }
+    if (!live) continue;
     double m = (j == i) ? 1.0 : 0.0;
     if (act) {
       m = 0.0;
       const int pr = j * n + i;
-      for (int k = beg[pr]; k < beg[pr + 1]; ++k)
-        m += kv[k] * L[((long)a * Rl + kb[k]) * p + a] * Rt[((long)c * Rr + ke[k]) * t + c];
+      if (staged) {
+        for (int k = beg[pr]; k < beg[pr + 1]; ++k) m += kv[k] * sL[wave][kb[k]] * sR[wave][ke[k]];
+      } else {
+        for (int k = beg[pr]; k < beg[pr + 1]; ++k)
+          m += kv[k] * L[((long)a * Rl + kb[k]) * p + a] * Rt[((long)c * Rr + ke[k]) * t + c];
+      }
     }
     double v = (j == i) ? 1.0 : 0.0;
     for (int col = 0; col < n; ++col) {
