@@ -366,8 +366,11 @@ static void count(Flops* f, double m, double n, double k, double terms) {
   if (f) f->total += flop_count(m, n, k, terms);
 }
 
-static void stage12(Problem& P, const Plan& pl, int p, int q, int s, const double* L, const double* x, const int* skip,
-                    hipStream_t st, Flops* f, double* T1, double* T2, const double** src) {
+// ---- contraction descriptors (launched alone, or several independent ones at once)
+
+// stage 1 of an apply / interface update: T1[slot] = L_b x_i over the operator's slots
+static GemmDesc stage1_desc(const Plan& pl, int p, int q, int s, const double* L, const double* x, const int* skip,
+                            double* T1) {
   GemmDesc g1;
   g1.A = L;
   g1.a_slot = q;
@@ -390,28 +393,173 @@ static void stage12(Problem& P, const Plan& pl, int p, int q, int s, const doubl
   g1.t_b = pl.slot_i;
   g1.skip = skip;
   g1.flops = flop_count(p, s, q, pl.nslot);
-  launch_gemm(g1, st);
-  count(f, p, s, q, pl.nslot);
+  return g1;
+}
+
+// dense operator cores: T2 = A2 T1 (the operator core applied to every slot product)
+static GemmDesc stage2_dense_desc(const Plan& pl, int p, int s, const double* T1, double* T2, const int* skip) {
+  GemmDesc g2;
+  g2.A = pl.A2;
+  g2.a_sm = 1;
+  g2.a_sk = (long)pl.n * pl.Rr;
+  g2.B = T1;
+  g2.b_sk = (long)p * s;
+  g2.b_sn = 1;
+  g2.C = T2;
+  g2.c_sm = (long)p * s;
+  g2.c_sn = 1;
+  g2.M = pl.n * pl.Rr;
+  g2.N = p * s;
+  g2.K = pl.nslot;
+  g2.ngroups = 1;
+  g2.skip = skip;
+  g2.flops = flop_count(g2.M, g2.N, g2.K, 1);
+  return g2;
+}
+
+// stage 3 of an interface update: Lnew[e] = sum over the terms of e of v W_i^T src
+static GemmDesc env_g3_desc(const Plan& pl, int p, int s, int t, const double* W, const double* src, double* Lnew) {
+  GemmDesc g3;
+  g3.A = W;
+  g3.a_slot = t;
+  g3.a_sm = 1;
+  g3.a_sk = (long)pl.n * t;
+  g3.B = src;
+  g3.b_slot = (long)p * s;
+  g3.b_sk = s;
+  g3.b_sn = 1;
+  g3.C = Lnew;
+  g3.c_slot = s;
+  g3.c_sm = (long)pl.Rr * s;
+  g3.c_sn = 1;
+  g3.M = t;
+  g3.N = s;
+  g3.K = p;
+  g3.ngroups = pl.Rr;
+  g3.grp_beg = pl.en_beg;
+  g3.t_a = pl.en_a;
+  g3.t_b = pl.en_b;
+  g3.t_v = pl.en_v;
+  g3.max_terms = pl.en_max;
+  g3.flops = flop_count(t, s, p, pl.n_en);
+  return g3;
+}
+
+// Tb[p][n][sb'] = sum Lb[p][sb] B[sb][n][sb'] (first product of the local load and of
+// its interface update)
+static GemmDesc rhs1_desc(int p, int n, int sb, int sb2, const double* Lb, const double* B, double* Tb) {
+  GemmDesc a;
+  a.A = Lb;
+  a.a_sm = sb;
+  a.a_sk = 1;
+  a.B = B;
+  a.b_sk = (long)n * sb2;
+  a.b_sn = 1;
+  a.C = Tb;
+  a.c_sm = (long)n * sb2;
+  a.c_sn = 1;
+  a.M = p;
+  a.N = n * sb2;
+  a.K = sb;
+  a.flops = flop_count(p, n * sb2, sb, 1);
+  return a;
+}
+
+// g[p][n][u] = sum Tb[p][n][sb'] Rb[u][sb']
+static GemmDesc rhs2_desc(int p, int n, int sb2, int u, const double* Tb, const double* Rb, double* g) {
+  GemmDesc b;
+  b.A = Tb;
+  b.a_slot = sb2;
+  b.a_sm = (long)n * sb2;
+  b.a_sk = 1;
+  b.B = Rb;
+  b.b_slot = 0;
+  b.b_sk = 1;
+  b.b_sn = sb2;
+  b.C = g;
+  b.c_slot = u;
+  b.c_sm = (long)n * u;
+  b.c_sn = 1;
+  b.M = p;
+  b.N = u;
+  b.K = sb2;
+  b.ngroups = n;
+  b.flops = flop_count(p, u, sb2, n);
+  return b;
+}
+
+// Lnew[t][sb'] = sum W[p][j][t] Tb[p][j][sb']
+static GemmDesc envb2_desc(int p, int n, int sb2, int t, const double* W, const double* Tb, double* Lnew) {
+  GemmDesc b;
+  b.A = W;
+  b.a_sm = 1;
+  b.a_sk = t;
+  b.B = Tb;
+  b.b_sk = sb2;
+  b.b_sn = 1;
+  b.C = Lnew;
+  b.c_sm = sb2;
+  b.c_sn = 1;
+  b.M = t;
+  b.N = sb2;
+  b.K = p * n;
+  b.flops = flop_count(t, sb2, p * n, 1);
+  return b;
+}
+
+// C (m x n) = A (m x k) B (k x n), plain row-major (lda/ldb/ldc given); transA reads A^T stored k x m.
+static GemmDesc plain_desc(int m, int n, int k, const double* A, long lda, bool transA, const double* B, long ldb,
+                           double* C, long ldc) {
+  GemmDesc g;
+  g.A = A;
+  if (transA) {
+    g.a_sm = 1;
+    g.a_sk = lda;
+  } else {
+    g.a_sm = lda;
+    g.a_sk = 1;
+  }
+  g.B = B;
+  g.b_sk = ldb;
+  g.b_sn = 1;
+  g.C = C;
+  g.c_sm = ldc;
+  g.c_sn = 1;
+  g.M = m;
+  g.N = n;
+  g.K = k;
+  g.flops = flop_count(m, n, k, 1);
+  return g;
+}
+
+static void run(const GemmDesc& d, hipStream_t st, Flops* f) {
+  launch_gemm(d, st);
+  if (f) f->total += d.flops;
+}
+
+// Independent contractions issued together (launch_gemm_multi), their flops counted.
+struct GemmSet {
+  static constexpr int kMax = 8;
+  GemmDesc d[kMax];
+  int n = 0;
+  void add(const GemmDesc& g) {
+    if (n == kMax) fail(TNFEM_EINVAL, "contraction set full");
+    d[n++] = g;
+  }
+  void launch(hipStream_t st, Flops* f) {
+    launch_gemm_multi(d, n, st);
+    if (f)
+      for (int i = 0; i < n; ++i) f->total += d[i].flops;
+    n = 0;
+  }
+};
+
+static void stage12(Problem& P, const Plan& pl, int p, int q, int s, const double* L, const double* x, const int* skip,
+                    hipStream_t st, Flops* f, double* T1, double* T2, const double** src) {
+  run(stage1_desc(pl, p, q, s, L, x, skip, T1), st, f);
   *src = T1;
   if (pl.dense) {
-    GemmDesc g2;
-    g2.A = pl.A2;
-    g2.a_sm = 1;
-    g2.a_sk = (long)pl.n * pl.Rr;
-    g2.B = T1;
-    g2.b_sk = (long)p * s;
-    g2.b_sn = 1;
-    g2.C = T2;
-    g2.c_sm = (long)p * s;
-    g2.c_sn = 1;
-    g2.M = pl.n * pl.Rr;
-    g2.N = p * s;
-    g2.K = pl.nslot;
-    g2.ngroups = 1;
-    g2.skip = skip;
-    g2.flops = flop_count(g2.M, g2.N, g2.K, 1);
-    launch_gemm(g2, st);
-    count(f, g2.M, g2.N, g2.K, 1);
+    run(stage2_dense_desc(pl, p, s, T1, T2, skip), st, f);
     *src = T2;
   }
   (void)P;
@@ -446,39 +594,14 @@ static void local_apply_ws(Problem& P, const Plan& pl, int p, int q, int s, int 
   g3.max_terms = pl.ap_max;
   g3.skip = skip;
   g3.flops = flop_count(p, t, s, pl.n_ap);
-  launch_gemm(g3, st);
-  count(f, p, t, s, pl.n_ap);
+  run(g3, st, f);
 }
 
 static void env_update_ws(Problem& P, const Plan& pl, int p, int q, int s, int t, const double* W, const double* L,
                           const double* X, double* Lnew, hipStream_t st, Flops* f, double* T1, double* T2) {
   const double* src = nullptr;
   stage12(P, pl, p, q, s, L, X, nullptr, st, f, T1, T2, &src);
-  GemmDesc g3;
-  g3.A = W;
-  g3.a_slot = t;
-  g3.a_sm = 1;
-  g3.a_sk = (long)pl.n * t;
-  g3.B = src;
-  g3.b_slot = (long)p * s;
-  g3.b_sk = s;
-  g3.b_sn = 1;
-  g3.C = Lnew;
-  g3.c_slot = s;
-  g3.c_sm = (long)pl.Rr * s;
-  g3.c_sn = 1;
-  g3.M = t;
-  g3.N = s;
-  g3.K = p;
-  g3.ngroups = pl.Rr;
-  g3.grp_beg = pl.en_beg;
-  g3.t_a = pl.en_a;
-  g3.t_b = pl.en_b;
-  g3.t_v = pl.en_v;
-  g3.max_terms = pl.en_max;
-  g3.flops = flop_count(t, s, p, pl.n_en);
-  launch_gemm(g3, st);
-  count(f, t, s, p, pl.n_en);
+  run(env_g3_desc(pl, p, s, t, W, src, Lnew), st, f);
 }
 
 struct SplitkScope {
@@ -534,105 +657,13 @@ void dev_env_update(Problem& P, const Plan& pl, int p, int q, int s, int t, cons
 // g[p][n][u] = sum Lb[p][sb] B[sb][n][sb'] Rb[u][sb']
 static void local_rhs(int p, int n, int sb, int sb2, int u, const double* Lb, const double* B, const double* Rb,
                       double* Tb, double* g, hipStream_t st, Flops* f) {
-  GemmDesc a;
-  a.A = Lb;
-  a.a_sm = sb;
-  a.a_sk = 1;
-  a.B = B;
-  a.b_sk = (long)n * sb2;
-  a.b_sn = 1;
-  a.C = Tb;
-  a.c_sm = (long)n * sb2;
-  a.c_sn = 1;
-  a.M = p;
-  a.N = n * sb2;
-  a.K = sb;
-  a.flops = flop_count(p, n * sb2, sb, 1);
-  launch_gemm(a, st);
-  count(f, p, n * sb2, sb, 1);
-  GemmDesc b;
-  b.A = Tb;
-  b.a_slot = sb2;
-  b.a_sm = (long)n * sb2;
-  b.a_sk = 1;
-  b.B = Rb;
-  b.b_slot = 0;
-  b.b_sk = 1;
-  b.b_sn = sb2;
-  b.C = g;
-  b.c_slot = u;
-  b.c_sm = (long)n * u;
-  b.c_sn = 1;
-  b.M = p;
-  b.N = u;
-  b.K = sb2;
-  b.ngroups = n;
-  b.flops = flop_count(p, u, sb2, n);
-  launch_gemm(b, st);
-  count(f, p, u, sb2, n);
+  run(rhs1_desc(p, n, sb, sb2, Lb, B, Tb), st, f);
+  run(rhs2_desc(p, n, sb2, u, Tb, Rb, g), st, f);
 }
 
-// Lnew[t][sb'] = sum W[p][j][t] Lb[p][sb] B[sb][j][sb']
-static void env_b(int p, int n, int sb, int sb2, int t, const double* W, const double* Lb, const double* B, double* Tb,
-                  double* Lnew, hipStream_t st, Flops* f) {
-  GemmDesc a;
-  a.A = Lb;
-  a.a_sm = sb;
-  a.a_sk = 1;
-  a.B = B;
-  a.b_sk = (long)n * sb2;
-  a.b_sn = 1;
-  a.C = Tb;
-  a.c_sm = (long)n * sb2;
-  a.c_sn = 1;
-  a.M = p;
-  a.N = n * sb2;
-  a.K = sb;
-  a.flops = flop_count(p, n * sb2, sb, 1);
-  launch_gemm(a, st);
-  count(f, p, n * sb2, sb, 1);
-  GemmDesc b;
-  b.A = W;
-  b.a_sm = 1;
-  b.a_sk = t;
-  b.B = Tb;
-  b.b_sk = sb2;
-  b.b_sn = 1;
-  b.C = Lnew;
-  b.c_sm = sb2;
-  b.c_sn = 1;
-  b.M = t;
-  b.N = sb2;
-  b.K = p * n;
-  b.flops = flop_count(t, sb2, p * n, 1);
-  launch_gemm(b, st);
-  count(f, t, sb2, p * n, 1);
-}
-
-// C (m x n) = A (m x k) B (k x n), plain row-major (lda/ldb/ldc given); transA reads A^T stored k x m.
 static void gemm_plain(int m, int n, int k, const double* A, long lda, bool transA, const double* B, long ldb,
                        double* C, long ldc, hipStream_t st, Flops* f) {
-  GemmDesc g;
-  g.A = A;
-  if (transA) {
-    g.a_sm = 1;
-    g.a_sk = lda;
-  } else {
-    g.a_sm = lda;
-    g.a_sk = 1;
-  }
-  g.B = B;
-  g.b_sk = ldb;
-  g.b_sn = 1;
-  g.C = C;
-  g.c_sm = ldc;
-  g.c_sn = 1;
-  g.M = m;
-  g.N = n;
-  g.K = k;
-  g.flops = flop_count(m, n, k, 1);
-  launch_gemm(g, st);
-  count(f, m, n, k, 1);
+  run(plain_desc(m, n, k, A, lda, transA, B, ldb, C, ldc), st, f);
 }
 
 // ----------------------------------------------------------------------------- workspace
@@ -671,6 +702,9 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   }
   W.T1 = A(P.t1max_slots * rc * rc);
   W.T2 = A(P.t2max_slots * rc * rc);
+  W.T1z = A(P.t1max_slots * (size_t)rho * rc);
+  W.T2z = A(P.t2max_slots * (size_t)rho * rc);
+  W.Tbz = A((size_t)rho * maxn * smax);
   W.g = A(core);
   W.r = A(core);
   W.z = A(core);
@@ -848,6 +882,10 @@ struct Sweep {
   // the interfaces X-A-u and Z-A-u.  ir_inner: low-precision local solves end after their
   // low-precision pass (the outer loop carries the FP64 correction).
   bool with_u = false, ir_inner = false;
+  // W.Tb holds Eb[tb_k] B(tb_k), W.Tbz holds Ezb[tbz_k] B(tbz_k) (-1: neither is known);
+  // the first product of the local load is reused by the enrichment load and by the
+  // interface update of the same core
+  int tb_k = -1, tbz_k = -1;
   std::vector<double*> U, EuA, EzuA;
   std::vector<int> ur;
   double* uspare = nullptr;
@@ -893,6 +931,7 @@ struct Sweep {
   }
 
   void reverse() {
+    tb_k = tbz_k = -1;
     for (int k = 0; k < K; ++k) {
       launch_core_transpose(xr[k], n[k], xr[k + 1], X[k], xspare, st);
       std::swap(X[k], xspare);
@@ -928,10 +967,12 @@ struct Sweep {
 
   // y = local operator applied to x between interfaces L and Rt: the fused kernel plus
   // the ordered sum of its partial tiles for sparse plans, the GEMM chain for dense ones
+  // y = A x on the interfaces L, Rt; with minus_from (sparse plans), y = minus_from - A x
   void apply(int k, int p, int q, int s, int t, const double* L, const double* x, const double* Rt, double* y,
-             const int* skip) {
+             const int* skip, const double* minus_from = nullptr) {
     const Plan& pl = plan(k);
     if (pl.dense) {
+      if (minus_from) fail(TNFEM_EINVAL, "apply: subtraction needs a sparse plan");
       local_apply_ws(P, pl, p, q, s, t, L, x, Rt, y, skip, st, &fl, W.T1, W.T2);
       return;
     }
@@ -954,16 +995,49 @@ struct Sweep {
     f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
     const double flops = 2.0 * p * q * s * pl.sp_nslot + 2.0 * p * s * t * pl.sp_n_ap;
     launch_fused_apply(f, flops, st, 0);
-    launch_fused_sum(f, y, st);
+    launch_fused_sum(f, y, st, minus_from);
     fl.total += flops;
   }
 
-  void update_envs(int k) {
+  // g -= A x (tmp holds A x where the plan is dense)
+  void apply_sub(int k, int p, int q, int s, int t, const double* L, const double* x, const double* Rt, double* g,
+                 double* tmp) {
+    if (plan(k).dense) {
+      apply(k, p, q, s, t, L, x, Rt, tmp, nullptr);
+      launch_sub((long)p * n[k] * t, g, tmp, g, st);
+    } else {
+      apply(k, p, q, s, t, L, x, Rt, g, nullptr, g);
+    }
+  }
+
+  // Interfaces at bond k + 1 from core k: the X and Z interface updates (operator and
+  // load) are independent, so their stages run as shared launches; pre1 / pre2 are
+  // independent products of the caller issued with the first / last stage.
+  void update_envs(int k, const GemmDesc* pre1 = nullptr, const GemmDesc* pre2 = nullptr) {
     const int p = xr[k], s = xr[k + 1], pz = zr[k], tz = zr[k + 1];
-    env_update_ws(P, plan(k), p, p, s, s, X[k], EA[k], X[k], EA[k + 1], st, &fl, W.T1, W.T2);
-    env_b(p, n[k], sb(k), sb(k + 1), s, X[k], Eb[k], B(k), W.Tb, Eb[k + 1], st, &fl);
-    env_update_ws(P, plan(k), pz, p, s, tz, Z[k], EzA[k], X[k], EzA[k + 1], st, &fl, W.T1, W.T2);
-    env_b(pz, n[k], sb(k), sb(k + 1), tz, Z[k], Ezb[k], B(k), W.Tb, Ezb[k + 1], st, &fl);
+    const Plan& pl = plan(k);
+    GemmSet g;
+    if (pre1) g.add(*pre1);
+    g.add(stage1_desc(pl, p, p, s, EA[k], X[k], nullptr, W.T1));
+    g.add(stage1_desc(pl, pz, p, s, EzA[k], X[k], nullptr, W.T1z));
+    if (tb_k != k) g.add(rhs1_desc(p, n[k], sb(k), sb(k + 1), Eb[k], B(k), W.Tb));
+    if (tbz_k != k) g.add(rhs1_desc(pz, n[k], sb(k), sb(k + 1), Ezb[k], B(k), W.Tbz));
+    g.launch(st, &fl);
+    tb_k = tbz_k = k;
+    const double *src = W.T1, *srcz = W.T1z;
+    if (pl.dense) {
+      g.add(stage2_dense_desc(pl, p, s, W.T1, W.T2, nullptr));
+      g.add(stage2_dense_desc(pl, pz, s, W.T1z, W.T2z, nullptr));
+      g.launch(st, &fl);
+      src = W.T2;
+      srcz = W.T2z;
+    }
+    if (pre2) g.add(*pre2);
+    g.add(env_g3_desc(pl, p, s, s, X[k], src, EA[k + 1]));
+    g.add(envb2_desc(p, n[k], sb(k + 1), s, X[k], W.Tb, Eb[k + 1]));
+    g.add(env_g3_desc(pl, pz, s, tz, Z[k], srcz, EzA[k + 1]));
+    g.add(envb2_desc(pz, n[k], sb(k + 1), tz, Z[k], W.Tbz, Ezb[k + 1]));
+    g.launch(st, &fl);
     if (with_u) {
       const int q = ur[k], s2 = ur[k + 1];
       env_update_ws(P, plan(k), p, q, s2, s, X[k], EuA[k], U[k], EuA[k + 1], st, &fl, W.T1, W.T2);
@@ -997,10 +1071,9 @@ struct Sweep {
     const int p = xr[k], t = xr[k + 1];
     const int N = p * n[k] * t;
     local_rhs(p, n[k], sb(k), sb(k + 1), t, Eb[k], B(k), Eb[k + 1], W.Tb, W.g, st, &fl);
-    if (with_u) {  // g -= (projected) A u, in FP64
-      apply(k, p, ur[k], ur[k + 1], t, EuA[k], U[k], EuA[k + 1], W.ye, nullptr);
-      launch_sub((long)N, W.g, W.ye, W.g, st);
-    }
+    tb_k = k;
+    if (with_u)  // g -= (projected) A u, in FP64
+      apply_sub(k, p, ur[k], ur[k + 1], t, EuA[k], U[k], EuA[k + 1], W.g, W.ye);
     const Plan& pl = plan(k);
     launch_local_block_inv(p, n[k], t, R(k), R(k + 1), EA[k], EA[k + 1], pl.bk_beg, pl.bk_b, pl.bk_e, pl.bk_v,
                            W.binv, st);
@@ -1247,45 +1320,40 @@ struct Sweep {
     const int p = s.p, nk = s.nk, t = s.t, M = s.M, Nn = s.Nn, c = s.c;
     const int rk = hint()[0];
     s.rk = rk;
-    // keep U[:, :rk] (in place, leading dimension rk) and xt = U_rk (U_rk^T x), which
-    // equals U_rk diag(S_rk) V^T_rk
-    if (rk < c) {
-      launch_copy2d(M, rk, W.Ur, c, W.aug, rk, 1.0, 0.0, st);
-      launch_copy2d(M, rk, W.aug, rk, W.Ur, rk, 1.0, 0.0, st);
-    }
-    gemm_plain(rk, Nn, M, W.Ur, rk, true, X[k], Nn, W.SVt, Nn, st, &fl);
-    gemm_plain(M, Nn, rk, W.Ur, rk, false, W.SVt, Nn, W.xt, Nn, st, &fl);
-    // residual projected on the Z interfaces -> new Z_k (QR job)
     const int pz = zr[k], tz = zr[k + 1];
-    local_rhs(pz, nk, sb(k), sb(k + 1), tz, Ezb[k], B(k), Ezb[k + 1], W.Tb, W.gz, st, &fl);
-    apply(k, pz, p, t, tz, EzA[k], W.xt, EzA[k + 1], W.yz, nullptr);
-    launch_sub((long)pz * nk * tz, W.gz, W.yz, W.gz, st);
-    if (with_u) {
-      apply(k, pz, ur[k], ur[k + 1], tz, EzuA[k], U[k], EzuA[k + 1], W.yz, nullptr);
-      launch_sub((long)pz * nk * tz, W.gz, W.yz, W.gz, st);
-    }
-    const int mz = pz * nk;
-    s.cz = std::min(mz, tz);
-    s.zqr = QrJob{mz, tz, tz, s.cz, tz, W.gz, Z[k], W.Rz, W.qrwsz, W.qrwsz_cap};
     // enrichment: residual on (left X, right Z) interfaces, as many columns as the cap
     // leaves room for
     const int rho_eff = std::max(0, std::min(tz, std::min(o.rank_cap - rk, M - rk)));
     const int rnew = rk + rho_eff;
     s.rnew = rnew;
+    // xt = U_rk (U_rk^T x) (U_rk: the first rk columns of U, leading dimension c), which
+    // equals U_rk diag(S_rk) V^T_rk; beside it the first products of the two loads
+    GemmSet g;
+    g.add(plain_desc(rk, Nn, M, W.Ur, c, true, X[k], Nn, W.SVt, Nn));
+    g.add(rhs1_desc(pz, nk, sb(k), sb(k + 1), Ezb[k], B(k), W.Tbz));
+    if (rho_eff > 0 && tb_k != k) g.add(rhs1_desc(p, nk, sb(k), sb(k + 1), Eb[k], B(k), W.Tb));
+    g.launch(st, &fl);
+    tbz_k = k;
+    if (rho_eff > 0) tb_k = k;
+    g.add(plain_desc(M, Nn, rk, W.Ur, c, false, W.SVt, Nn, W.xt, Nn));
+    g.add(rhs2_desc(pz, nk, sb(k + 1), tz, W.Tbz, Ezb[k + 1], W.gz));
+    if (rho_eff > 0) g.add(rhs2_desc(p, nk, sb(k + 1), tz, W.Tb, Ezb[k + 1], W.ge));
+    g.launch(st, &fl);
+    // residual projected on the Z interfaces -> new Z_k (QR job)
+    apply_sub(k, pz, p, t, tz, EzA[k], W.xt, EzA[k + 1], W.gz, W.yz);
+    if (with_u) apply_sub(k, pz, ur[k], ur[k + 1], tz, EzuA[k], U[k], EzuA[k + 1], W.gz, W.yz);
+    const int mz = pz * nk;
+    s.cz = std::min(mz, tz);
+    s.zqr = QrJob{mz, tz, tz, s.cz, tz, W.gz, Z[k], W.Rz, W.qrwsz, W.qrwsz_cap};
     if (rho_eff == 0) {
       // no room: U_rk (orthonormal columns) is the new core as it stands
-      launch_copy2d(M, rk, W.Ur, rk, X[k], rk, 1.0, 0.0, st);
+      launch_copy2d(M, rk, W.Ur, c, X[k], rk, 1.0, 0.0, st);
       s.aqr = QrJob{};
       return;
     }
-    local_rhs(p, nk, sb(k), sb(k + 1), tz, Eb[k], B(k), Ezb[k + 1], W.Tb, W.ge, st, &fl);
-    apply(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ye, nullptr);
-    launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
-    if (with_u) {
-      apply(k, p, ur[k], ur[k + 1], tz, EuA[k], U[k], EzuA[k + 1], W.ye, nullptr);
-      launch_sub((long)p * nk * tz, W.ge, W.ye, W.ge, st);
-    }
-    launch_copy2d(M, rk, W.Ur, rk, W.aug, rnew, 1.0, 0.0, st);
+    apply_sub(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ge, W.ye);
+    if (with_u) apply_sub(k, p, ur[k], ur[k + 1], tz, EuA[k], U[k], EzuA[k + 1], W.ge, W.ye);
+    launch_copy2d(M, rk, W.Ur, c, W.aug, rnew, 1.0, 0.0, st);
     launch_copy2d(M, rho_eff, W.ge, tz, W.aug + rk, rnew, 1.0, 0.0, st);
     s.aqr = QrJob{M, rnew, rnew, rnew, rnew, W.aug, X[k], W.Ra, W.qrws, W.qrws_cap};
   }
@@ -1298,15 +1366,15 @@ struct Sweep {
 
   void enrich_end(int k, TruncState& s) {
     const int M = s.M, Nn = s.Nn, rnew = s.rnew;
-    // W = Q^T xt (rnew x Nn); X_{k+1} <- W X_{k+1}
-    gemm_plain(rnew, Nn, M, X[k], rnew, true, W.xt, Nn, W.Wm, Nn, st, &fl);
+    // W = Q^T xt (rnew x Nn); X_{k+1} <- W X_{k+1}, issued with the interface updates
     const int cols = n[k + 1] * xr[k + 2];
-    gemm_plain(rnew, cols, Nn, W.Wm, Nn, false, X[k + 1], cols, xspare, cols, st, &fl);
-    std::swap(X[k + 1], xspare);
+    const GemmDesc wm = plain_desc(rnew, Nn, M, X[k], rnew, true, W.xt, Nn, W.Wm, Nn);
+    const GemmDesc carry = plain_desc(rnew, cols, Nn, W.Wm, Nn, false, X[k + 1], cols, xspare, cols);
     xr[k + 1] = rnew;
     peak_rank = std::max(peak_rank, rnew);
     zr[k + 1] = s.cz;
-    update_envs(k);
+    update_envs(k, &wm, &carry);
+    std::swap(X[k + 1], xspare);
   }
 
   void truncate_enrich(int k) {
@@ -1329,6 +1397,7 @@ struct Sweep {
   // The current iterate becomes u; the sweep restarts from random cores on the correction
   // equation A d = b - A u (orthogonalisation and right interfaces rebuilt, those of u too).
   void begin_correction(IrBuffers& B, uint64_t seed_x, uint64_t seed_z) {
+    tb_k = tbz_k = -1;
     if (!with_u) {
       U = B.U;
       uspare = B.uspare;
@@ -1495,6 +1564,7 @@ std::vector<double> batch_solve_core(std::vector<Sweep*>& S, int k, BatchArgs& a
     c.N = c.p * w.n[k] * c.t;
     c.pl = &w.plan(k);
     local_rhs(c.p, w.n[k], w.sb(k), w.sb(k + 1), c.t, w.Eb[k], w.B(k), w.Eb[k + 1], W.Tb, W.g, st, &w.fl);
+    w.tb_k = k;
     launch_local_block_inv(c.p, w.n[k], c.t, w.R(k), w.R(k + 1), w.EA[k], w.EA[k + 1], c.pl->bk_beg, c.pl->bk_b,
                            c.pl->bk_e, c.pl->bk_v, W.binv, st);
     w.apply(k, c.p, c.p, c.t, c.t, w.EA[k], w.X[k], w.EA[k + 1], W.q, nullptr);

@@ -112,6 +112,8 @@ struct Workspace {
   double *Xspare = nullptr, *Zspare = nullptr;
   std::vector<double*> EA, Eb, EzA, Ezb;  // K + 1 bond buffers
   double *T1 = nullptr, *T2 = nullptr;
+  // the Z interface update's own stage products, so that it runs beside the X one
+  double *T1z = nullptr, *T2z = nullptr, *Tbz = nullptr;
   double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr;
   double* binv = nullptr;  // inverses of the diagonal mode blocks of the local operator
   double *Tb = nullptr, *gz = nullptr, *yz = nullptr, *ge = nullptr, *ye = nullptr;

@@ -126,14 +126,11 @@ constexpr int BK = 32;
 // blockIdx.x: output tile, blockIdx.y: group, blockIdx.z: split of the group's
 // (term, k-step) iterations.
 template <int WMB, int WNB>
-__global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_body(const GemmArgs& g, const int tile, const int grp, const int z) {
   constexpr int TM = 32 * WMB, TN = 32 * WNB;
   __shared__ double sA[BK][TM + 1];
   __shared__ double sB[BK][TN + 1];
   if (g.skip && *g.skip) return;
-  const int grp = blockIdx.y;
-  const int tile = blockIdx.x;
-  const int z = blockIdx.z;
   const int m0 = (tile / g.tiles_n) * TM, n0 = (tile % g.tiles_n) * TN;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
@@ -284,10 +281,9 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
 // Sums the split partial tiles in split order and writes C (alpha, beta as above).
 // One thread per tile element; blockIdx.z covers the tile's elements.
 template <int TM, int TN>
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
+__device__ __forceinline__ void splitk_reduce_body(const GemmArgs& g, const int tile, const int grp, const int ez) {
   if (g.skip && *g.skip) return;
-  const int grp = blockIdx.y, tile = blockIdx.x;
-  const int e = blockIdx.z * 256 + threadIdx.x;
+  const int e = ez * 256 + threadIdx.x;
   if (e >= TM * TN) return;
   const int m0 = (tile / g.tiles_n) * TM, n0 = (tile % g.tiles_n) * TN;
   const int row = m0 + e / TN, col = n0 + e % TN;
@@ -309,6 +305,55 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
   double* c = g.C + (long)ci * g.c_slot + (long)row * g.c_sm + (long)col * g.c_sn;
   const double val = g.alpha * s;
   *c = (g.beta == 0.0) ? val : val + g.beta * *c;
+}
+
+template <int WMB, int WNB>
+__global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmArgs g) {
+  gemm_body<WMB, WNB>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
+  splitk_reduce_body<TM, TN>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Several independent grouped GEMMs of one tile class in one launch: the flattened
+// grid is cut into consecutive ranges, one per descriptor, each walked in the
+// (tile, group, split) order of the single launch (and, for the split sums, the
+// (tile, group, element block) order).
+constexpr int GM_MAX = 6;
+struct GemmMulti {
+  GemmArgs g[GM_MAX];
+  int beg[GM_MAX + 1];
+  int n;
+};
+
+__device__ __forceinline__ int multi_find(const GemmMulti& m, int b) {
+  int d = 0;
+  while (d + 1 < m.n && b >= m.beg[d + 1]) ++d;
+  return d;
+}
+
+template <int WMB, int WNB>
+__global__ __launch_bounds__(256) void gemm_multi_kernel(GemmMulti m) {
+  const int d = multi_find(m, blockIdx.x);
+  const GemmArgs& g = m.g[d];
+  const int loc = blockIdx.x - m.beg[d];
+  const int per = g.ntiles * g.ngroups;
+  const int z = loc / per, rem = loc - z * per;
+  const int grp = rem / g.ntiles;
+  gemm_body<WMB, WNB>(g, rem - grp * g.ntiles, grp, z);
+}
+
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void splitk_reduce_multi_kernel(GemmMulti m) {
+  const int d = multi_find(m, blockIdx.x);
+  const GemmArgs& g = m.g[d];
+  const int loc = blockIdx.x - m.beg[d];
+  const int per = g.ntiles * g.ngroups;
+  const int ez = loc / per, rem = loc - ez * per;
+  const int grp = rem / g.ntiles;
+  splitk_reduce_body<TM, TN>(g, rem - grp * g.ntiles, grp, ez);
 }
 
 static thread_local GemmProfile* g_prof = nullptr;
@@ -392,17 +437,23 @@ static void prof_end(hipEvent_t* pair, double flops, hipStream_t s, int kind) {
 constexpr long SPLIT_TARGET_WG = 512;
 constexpr int SPLIT_MIN_ITERS = 2;  // (term, k-step) iterations per split at least
 
+static GemmArgs gemm_args(const GemmDesc& d) {
+  return GemmArgs{d.A, d.a_slot, d.a_sm, d.a_sk, d.B, d.b_slot, d.b_sk, d.b_sn, d.C, d.c_slot, d.c_sm, d.c_sn,
+                  d.M, d.N, d.K, d.grp_beg, d.grp_c, d.t_a, d.t_b, d.t_v, d.alpha, d.beta, d.skip, 0, 0, 0, 1, nullptr};
+}
+
+// Tile counts and the split of a descriptor's (term, k-step) iterations; the partial
+// tiles go to pbuf (pcap doubles free there).  Returns the doubles of partials used.
 template <int WMB, int WNB>
-static void launch_tiled(GemmArgs a, const GemmDesc& d, hipStream_t s) {
+static size_t plan_tiled(GemmArgs& a, const GemmDesc& d, double* pbuf, size_t pcap) {
   constexpr int TM = 32 * WMB, TN = 32 * WNB;
   a.tiles_n = (d.N + TN - 1) / TN;
   a.ntiles = ((d.M + TM - 1) / TM) * a.tiles_n;
   a.ngroups = d.ngroups;
   a.ksplit = 1;
+  a.partial = pbuf;
   const long natural = (long)a.ntiles * d.ngroups;
   const long iters = (long)std::max(d.max_terms, 1) * ((d.K + BK - 1) / BK);
-  double* pbuf = d.partial ? d.partial : g_splitk;
-  const size_t pcap = d.partial ? d.partial_cap : g_splitk_cap;
   if (pbuf && natural < SPLIT_TARGET_WG && iters >= 2 * SPLIT_MIN_ITERS) {
     long ks = (SPLIT_TARGET_WG + natural - 1) / natural;
     ks = std::min(ks, iters / SPLIT_MIN_ITERS);
@@ -411,7 +462,14 @@ static void launch_tiled(GemmArgs a, const GemmDesc& d, hipStream_t s) {
     ks = std::min(ks, 64L);
     if (ks >= 2) a.ksplit = (int)ks;
   }
-  a.partial = d.partial ? d.partial : g_splitk;
+  return a.ksplit > 1 ? (size_t)natural * a.ksplit * (TM * TN) : 0;
+}
+
+template <int WMB, int WNB>
+static void launch_tiled(GemmArgs a, const GemmDesc& d, hipStream_t s) {
+  constexpr int TM = 32 * WMB, TN = 32 * WNB;
+  if (d.partial) plan_tiled<WMB, WNB>(a, d, d.partial, d.partial_cap);
+  else plan_tiled<WMB, WNB>(a, d, g_splitk, g_splitk_cap);
   dim3 grid(a.ntiles, d.ngroups, a.ksplit);
   hipEvent_t* ev = prof_begin(s);
   TN_LAUNCH(ev, (gemm_grouped_kernel<WMB, WNB>), grid, dim3(256), 0, s, a);
@@ -424,11 +482,78 @@ static void launch_tiled(GemmArgs a, const GemmDesc& d, hipStream_t s) {
   }
 }
 
+static bool gemm_wide(const GemmDesc& d) { return d.M >= 64 && d.N >= 64; }
+
 static void launch_gemm_impl(const GemmDesc& d, hipStream_t s) {
-  GemmArgs a{d.A, d.a_slot, d.a_sm, d.a_sk, d.B, d.b_slot, d.b_sk, d.b_sn, d.C, d.c_slot, d.c_sm, d.c_sn,
-             d.M, d.N, d.K, d.grp_beg, d.grp_c, d.t_a, d.t_b, d.t_v, d.alpha, d.beta, d.skip, 0, 0, 0, 1, nullptr};
-  if (d.M >= 64 && d.N >= 64) launch_tiled<2, 2>(a, d, s);
+  const GemmArgs a = gemm_args(d);
+  if (gemm_wide(d)) launch_tiled<2, 2>(a, d, s);
   else launch_tiled<1, 1>(a, d, s);
+}
+
+// One launch for the descriptors of one tile class (at most GM_MAX), the split sums of
+// those that split in a second one.  Each descriptor splits as it would alone, its
+// partial tiles in its own part of the split-K buffer (fewer splits where the buffer
+// runs out), so every result equals the one of its own launch.
+template <int WMB, int WNB>
+static void launch_multi_class(const GemmDesc* ds, const int* idx, int n, hipStream_t s) {
+  constexpr int TM = 32 * WMB, TN = 32 * WNB;
+  GemmMulti m{};
+  GemmMulti r{};
+  m.n = r.n = n;
+  size_t used = 0;
+  long wg = 0, rwg = 0;
+  double flops = 0.0;
+  bool any_split = false;
+  for (int j = 0; j < n; ++j) {
+    const GemmDesc& d = ds[idx[j]];
+    GemmArgs a = gemm_args(d);
+    if (d.partial) {
+      plan_tiled<WMB, WNB>(a, d, d.partial, d.partial_cap);
+    } else {
+      double* pbuf = g_splitk ? g_splitk + used : nullptr;
+      used += plan_tiled<WMB, WNB>(a, d, pbuf, g_splitk ? g_splitk_cap - used : 0);
+    }
+    m.g[j] = r.g[j] = a;
+    m.beg[j] = (int)wg;
+    r.beg[j] = (int)rwg;
+    wg += (long)a.ntiles * a.ngroups * a.ksplit;
+    if (a.ksplit > 1) {
+      rwg += (long)a.ntiles * a.ngroups * ((TM * TN + 255) / 256);
+      any_split = true;
+    }
+    flops += d.flops;
+  }
+  m.beg[n] = (int)wg;
+  r.beg[n] = (int)rwg;
+  if (wg > INT32_MAX / 2) throw Error(TNFEM_EINVAL, "grouped GEMM launch too large");
+  hipEvent_t* ev = prof_begin(s);
+  TN_LAUNCH(ev, (gemm_multi_kernel<WMB, WNB>), dim3((unsigned)wg), dim3(256), 0, s, m);
+  prof_end(ev, flops, s, PROF_GEMM);
+  TN_CHECK_LAUNCH();
+  if (any_split) {
+    hipLaunchKernelGGL((splitk_reduce_multi_kernel<TM, TN>), dim3((unsigned)rwg), dim3(256), 0, s, r);
+    TN_CHECK_LAUNCH();
+  }
+}
+
+void launch_gemm_multi(const GemmDesc* ds, int n, hipStream_t s) {
+  int wide[GM_MAX], narrow[GM_MAX];
+  int nw = 0, nn = 0;
+  auto flush = [&]() {
+    if (nw == 1) launch_gemm_impl(ds[wide[0]], s);
+    else if (nw > 1) launch_multi_class<2, 2>(ds, wide, nw, s);
+    if (nn == 1) launch_gemm_impl(ds[narrow[0]], s);
+    else if (nn > 1) launch_multi_class<1, 1>(ds, narrow, nn, s);
+    nw = nn = 0;
+  };
+  for (int i = 0; i < n; ++i) {
+    const GemmDesc& d = ds[i];
+    if (d.M <= 0 || d.N <= 0 || d.ngroups <= 0) continue;
+    if (gemm_wide(d)) wide[nw++] = i;
+    else narrow[nn++] = i;
+    if (nw == GM_MAX || nn == GM_MAX) flush();
+  }
+  flush();
 }
 
 // ----------------------------------------------------------------------------- CG
@@ -1318,8 +1443,9 @@ __device__ inline double sum_splits(const double* src, long stride, int ksplit) 
   return w;
 }
 
-// y[row][grp][col] = sum over splits of the fused partial tiles (split order).
-__global__ void fused_sum_kernel(FusedArgs f, double* y) {
+// y[row][grp][col] = sum over splits of the fused partial tiles (split order), or
+// g[e] minus that sum when g is given (g may be y).
+__global__ void fused_sum_kernel(FusedArgs f, double* y, const double* g) {
   if (f.skip && *f.skip) return;
   const long N = (long)f.p * f.n * f.t;
   const long stride = (long)f.n * f.ntiles * 1024;
@@ -1327,17 +1453,18 @@ __global__ void fused_sum_kernel(FusedArgs f, double* y) {
     const int col = e % f.t, grp = (e / f.t) % f.n, row = e / ((long)f.t * f.n);
     const int tile = (row / 32) * f.tiles_n + col / 32;
     const double* src = f.partial + ((long)grp * f.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
-    y[e] = sum_splits(src, stride, f.ksplit);
+    const double v = sum_splits(src, stride, f.ksplit);
+    y[e] = g ? g[e] - v : v;
   }
 }
 
-void launch_fused_sum(FusedArgs f, double* y, hipStream_t s) {
+void launch_fused_sum(FusedArgs f, double* y, hipStream_t s, const double* minus_from) {
   f.tiles_n = (f.t + 31) / 32;
   f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
   const long N = (long)f.p * f.n * f.t;
   // 64-thread blocks: the split sums of a local vector spread over more compute units
   const int nb = (int)std::min<long>(std::max<long>((N + 63) / 64, 1), 4096);
-  hipLaunchKernelGGL(fused_sum_kernel, dim3(nb), dim3(64), 0, s, f, y);
+  hipLaunchKernelGGL(fused_sum_kernel, dim3(nb), dim3(64), 0, s, f, y, minus_from);
   TN_CHECK_LAUNCH();
 }
 

@@ -43,6 +43,10 @@ struct GemmDesc {
 };
 
 void launch_gemm(const GemmDesc& g, hipStream_t s);
+// Independent descriptors (no one writes what another reads) in as few launches as
+// their tile classes allow; each result equals that of launch_gemm on its own
+// descriptor unless the split-K buffer cannot hold every descriptor's splits.
+void launch_gemm_multi(const GemmDesc* ds, int n, hipStream_t s);
 
 // Optional per-launch timing of the contraction kernels (launch_gemm and
 // launch_fused_apply) on the calling thread: while a profile is installed, every
@@ -155,7 +159,9 @@ void launch_fused_apply_batch(const FusedBatch& b, int n, int kind, hipStream_t 
 // precision: 0 FP64, 1 FP32 operands (FP32 accumulate), 2 BF16 operands (FP32 accumulate)
 void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision = 0);
 // y = sum of the partial tiles written by launch_fused_apply with the same f.
-void launch_fused_sum(FusedArgs f, double* y, hipStream_t s);
+// y = sum of the split partials of a fused apply; with minus_from, y = minus_from - sum
+// (element by element, minus_from may equal y).
+void launch_fused_sum(FusedArgs f, double* y, hipStream_t s, const double* minus_from = nullptr);
 
 // Local PCG with per-block partial sums (no atomics inside the iteration):
 // iteration k = apply (w = B z) -> reduce_dir(k) -> update2(k).
