@@ -684,6 +684,8 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   const size_t M = rc * maxn, Nw = rc + rho;
   W.X.clear();
   W.Z.clear();
+  W.Xalt.clear();
+  W.Zalt.clear();
   W.EA.clear();
   W.Eb.clear();
   W.EzA.clear();
@@ -691,6 +693,8 @@ static void layout_workspace(const Problem& P, Workspace& W, int cap, int rho, A
   for (int k = 0; k < K; ++k) {
     W.X.push_back(A(core));
     W.Z.push_back(A(std::max(zcore, core)));
+    W.Xalt.push_back(A(core));
+    W.Zalt.push_back(A(std::max(zcore, core)));
   }
   W.Xspare = A(core);
   W.Zspare = A(std::max(zcore, core));
@@ -870,6 +874,7 @@ struct Sweep {
   std::vector<int> xr, zr;  // K + 1 ranks (current orientation)
   std::vector<int> n;       // modes (current orientation)
   double *xspare = nullptr, *zspare = nullptr;
+  std::vector<double*> Xalt, Zalt;
   Flops fl;
   double fl_low = 0.0;
   long long cg_iters = 0, applies = 0, refinements = 0, fallbacks = 0;
@@ -910,6 +915,8 @@ struct Sweep {
     Z = W.Z;
     xspare = W.Xspare;
     zspare = W.Zspare;
+    Xalt = W.Xalt;
+    Zalt = W.Zalt;
     EA = W.EA;
     Eb = W.Eb;
     EzA = W.EzA;
@@ -932,12 +939,14 @@ struct Sweep {
 
   void reverse() {
     tb_k = tbz_k = -1;
+    std::vector<TransposeJob> jobs;
     for (int k = 0; k < K; ++k) {
-      launch_core_transpose(xr[k], n[k], xr[k + 1], X[k], xspare, st);
-      std::swap(X[k], xspare);
-      launch_core_transpose(zr[k], n[k], zr[k + 1], Z[k], zspare, st);
-      std::swap(Z[k], zspare);
+      jobs.push_back(TransposeJob{xr[k], n[k], xr[k + 1], X[k], Xalt[k]});
+      jobs.push_back(TransposeJob{zr[k], n[k], zr[k + 1], Z[k], Zalt[k]});
     }
+    launch_core_transpose_multi(jobs.data(), (int)jobs.size(), st);
+    std::swap(X, Xalt);
+    std::swap(Z, Zalt);
     if (with_u) {
       for (int k = 0; k < K; ++k) {
         launch_core_transpose(ur[k], n[k], ur[k + 1], U[k], uspare, st);
@@ -1077,7 +1086,34 @@ struct Sweep {
     const Plan& pl = plan(k);
     launch_local_block_inv(p, n[k], t, R(k), R(k + 1), EA[k], EA[k + 1], pl.bk_beg, pl.bk_b, pl.bk_e, pl.bk_v,
                            W.binv, st);
-    apply(k, p, p, t, t, EA[k], X[k], EA[k + 1], W.q, nullptr);
+    // the CG's fused apply (x = z); for sparse plans the initial A x is the same apply on
+    // X[k], whose split partials the CG init sums itself
+    FusedArgs f;
+    const bool fused = !pl.dense;
+    if (fused) {
+      f.L = EA[k];
+      f.x = W.z;
+      f.Rt = EA[k + 1];
+      f.partial = W.fpart;
+      f.p = p;
+      f.q = p;
+      f.s = t;
+      f.t = t;
+      f.Rl = R(k);
+      f.Rr = R(k + 1);
+      f.n = n[k];
+      set_terms(f, pl);
+      f.stage = W.stage;
+      f.stage_bytes = W.stage_bytes;
+      f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
+      FusedArgs f0 = f;
+      f0.x = X[k];
+      const double flops0 = 2.0 * p * p * t * pl.sp_nslot + 2.0 * p * t * t * pl.sp_n_ap;
+      launch_fused_apply(f0, flops0, st, 0);
+      fl.total += flops0;
+    } else {
+      apply(k, p, p, t, t, EA[k], X[k], EA[k + 1], W.q, nullptr);
+    }
     applies++;
     CgIterArgs a;
     a.N = N;
@@ -1095,7 +1131,13 @@ struct Sweep {
     a.nb_upd = cg_dir_blocks(N);
     a.nb_dir = cg_dir_blocks(N);
     set_block_precond(a, n[k], t, W.binv);
-    launch_cg_init2(a, W.g, W.q, o.tol, st);
+    if (fused) {
+      a.ksplit = f.ksplit;
+      a.partial = W.fpart;
+      a.tiles_n = (t + 31) / 32;
+      a.ntiles = ((p + 31) / 32) * a.tiles_n;
+    }
+    launch_cg_init2(a, W.g, fused ? nullptr : W.q, o.tol, st);
     auto readback = [&]() {
       hip_check(hipMemcpyAsync(W.host_pinned, W.flag, (CG_RES_COPY + 2) * sizeof(int), hipMemcpyDeviceToHost, st),
                 "flag readback");
@@ -1113,10 +1155,7 @@ struct Sweep {
       if (!std::isfinite(res)) nan_seen = 1;
       done = hint()[0];
     }
-    FusedArgs f;
-    // fused evaluation from the nonzero lists: always for sparse plans; for dense
-    // plans when the per-apply work of the term lists stays small
-    const bool fused = !pl.dense;
+    // fused evaluation from the nonzero lists for sparse plans
     const size_t m_need = (size_t)pl.Rl * n[k] * n[k] * (size_t)t * t;
     const bool explicit_mat = pl.dense && !done && (size_t)N <= W.bloc_n && m_need <= W.mloc_cap;
     if (explicit_mat) {
@@ -1124,26 +1163,7 @@ struct Sweep {
       fl.total += 2.0 * m_need * pl.Rr + 2.0 * (double)N * N * pl.Rl;
     }
     if (fused) {
-      f.L = EA[k];
-      f.x = W.z;
-      f.Rt = EA[k + 1];
-      f.partial = W.fpart;
-      f.p = p;
-      f.q = p;
-      f.s = t;
-      f.t = t;
-      f.Rl = R(k);
-      f.Rr = R(k + 1);
-      f.n = n[k];
-      set_terms(f, pl);
-      f.stage = W.stage;
-      f.stage_bytes = W.stage_bytes;
-      f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
       f.skip = W.flag + CG_DONE;
-      a.ksplit = f.ksplit;
-      a.partial = W.fpart;
-      a.tiles_n = (t + 31) / 32;
-      a.ntiles = ((p + 31) / 32) * a.tiles_n;
       // the apply also forms the partials of (z, B z): one CG kernel per iteration
       const int nd = fused_dot_count(f);
       if (nd <= CG_DOT_MAX) {
@@ -1901,6 +1921,8 @@ static void finish_sweep(Problem& P, Sweep& sw, HostTT& out) {
   P.ws->Z = sw.Z;
   P.ws->Xspare = sw.xspare;
   P.ws->Zspare = sw.zspare;
+  P.ws->Xalt = sw.Xalt;
+  P.ws->Zalt = sw.Zalt;
   out.modes = sw.n;
   out.ranks = sw.xr;
   out.cores.assign(P.K, {});

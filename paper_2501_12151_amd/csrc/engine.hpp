@@ -110,6 +110,8 @@ struct Workspace {
   DevArena arena;
   std::vector<double*> X, Z;  // K core buffers each (+1 spare for swaps)
   double *Xspare = nullptr, *Zspare = nullptr;
+  // second core sets: a change of orientation transposes every core into them at once
+  std::vector<double*> Xalt, Zalt;
   std::vector<double*> EA, Eb, EzA, Ezb;  // K + 1 bond buffers
   double *T1 = nullptr, *T2 = nullptr;
   // the Z interface update's own stage products, so that it runs beside the X one

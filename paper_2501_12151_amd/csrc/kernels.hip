@@ -1757,7 +1757,8 @@ __global__ __launch_bounds__(NT) void cg_step_kernel(CgIterArgs a, int k) {
   cg_step_body<NT>(a, k, blockIdx.x);
 }
 
-// r = g - Bx; z = M^-1 r; p = q = 0; block partials of r.z, r.r (parity 0);
+// r = g - Bx (Bx given, or summed from a fused apply's split partials when bx is null);
+// z = M^-1 r; p = q = 0; block partials of r.z, r.r (parity 0);
 // the last block also derives res, thr and the skip decision for the host.
 __global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const double* g, const double* bx, double tol) {
   __shared__ double red[4];
@@ -1774,7 +1775,17 @@ __global__ __launch_bounds__(256) void cg_init2_kernel(CgIterArgs a, const doubl
     double gi = 0.0, ri = 0.0;
     if (act) {
       gi = g[e];
-      ri = gi - bx[e];
+      double bxe;
+      if (bx) {
+        bxe = bx[e];
+      } else {
+        // B x straight from the fused apply's split partial tiles (mode j, row, col)
+        const int row = (int)(blk / t), col = (int)(blk % t);
+        const int tile = (row / 32) * a.tiles_n + col / 32;
+        const double* src = a.partial + ((long)j * a.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
+        bxe = sum_splits(src, (long)a.n * a.ntiles * 1024, a.ksplit);
+      }
+      ri = gi - bxe;
       a.r[e] = ri;
       a.p[e] = 0.0;
       a.q[e] = 0.0;
@@ -3700,6 +3711,39 @@ __global__ void core_transpose_kernel(int ra, int n, int rb, const double* in, d
 void launch_core_transpose(int ra, int n, int rb, const double* in, double* out, hipStream_t s) {
   hipLaunchKernelGGL(core_transpose_kernel, dim3(blocks_for((long)ra * n * rb)), dim3(256), 0, s, ra, n, rb, in, out);
   TN_CHECK_LAUNCH();
+}
+
+// Several core transposes in one launch: job j covers flattened blocks beg[j] ..
+// beg[j + 1] - 1, 256 elements each.
+__global__ __launch_bounds__(256) void core_transpose_multi_kernel(TransposeJobs J) {
+  int j = 0;
+  while (j + 1 < J.n && (int)blockIdx.x >= J.beg[j + 1]) ++j;
+  const TransposeJob& t = J.job[j];
+  const long idx = (long)(blockIdx.x - J.beg[j]) * 256 + threadIdx.x;
+  const long total = (long)t.ra * t.n * t.rb;
+  if (idx >= total) return;
+  const int b = idx % t.rb;
+  const int i = (idx / t.rb) % t.n;
+  const int a = idx / ((long)t.rb * t.n);
+  t.out[((long)b * t.n + i) * t.ra + a] = t.in[idx];
+}
+
+void launch_core_transpose_multi(const TransposeJob* jobs, int n, hipStream_t s) {
+  for (int off = 0; off < n; off += TRANSPOSE_MULTI_MAX) {
+    TransposeJobs J{};
+    J.n = std::min(TRANSPOSE_MULTI_MAX, n - off);
+    long blocks = 0;
+    for (int j = 0; j < J.n; ++j) {
+      J.job[j] = jobs[off + j];
+      J.beg[j] = (int)blocks;
+      blocks += ((long)jobs[off + j].ra * jobs[off + j].n * jobs[off + j].rb + 255) / 256;
+    }
+    J.beg[J.n] = (int)blocks;
+    if (blocks == 0) continue;
+    if (blocks > INT32_MAX / 2) throw Error(TNFEM_EINVAL, "core transpose launch too large");
+    hipLaunchKernelGGL(core_transpose_multi_kernel, dim3((unsigned)blocks), dim3(256), 0, s, J);
+    TN_CHECK_LAUNCH();
+  }
 }
 
 __global__ void sub_kernel(long n, const double* a, const double* b, double* out) {

@@ -291,6 +291,19 @@ void launch_scale_rows(int r, int n, const double* S, const double* Vt, int ldv,
 
 // Core transpose for chain reversal: out[b][i][a] = in[a][i][b], in: [ra][n][rb].
 void launch_core_transpose(int ra, int n, int rb, const double* in, double* out, hipStream_t s);
+// the same for independent (ra, n, rb, in, out) jobs, TRANSPOSE_MULTI_MAX to a launch
+struct TransposeJob {
+  int ra = 0, n = 0, rb = 0;
+  const double* in = nullptr;
+  double* out = nullptr;
+};
+constexpr int TRANSPOSE_MULTI_MAX = 48;
+struct TransposeJobs {
+  TransposeJob job[TRANSPOSE_MULTI_MAX];
+  int beg[TRANSPOSE_MULTI_MAX + 1];
+  int n;
+};
+void launch_core_transpose_multi(const TransposeJob* jobs, int n, hipStream_t s);
 
 // out = a - b (n entries)
 void launch_sub(long n, const double* a, const double* b, double* out, hipStream_t s);
