@@ -658,6 +658,15 @@ __device__ inline void mfma_k32o(const typename Prec<P>::T (*sA)[LD], const type
   }
 }
 
+// Raw buffer over n doubles from base: loads beyond the range read zero, and one offset
+// register serves all the loads of a tile (the rest of each offset in the scalar field).
+__device__ inline __amdgpu_buffer_rsrc_t tile_rsrc(const double* base, long n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)(n * 8), 0x00020000);
+}
+__device__ inline double tile_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
 // Term metadata of a workgroup's term range tb .. te - 1, read once into the lanes:
 // lane l of every wavefront holds term tb + l (l < 64); terms beyond are read directly.
 // (code: f.tc for the one-pass kernels, f.ta (slot) for the two-stage apply)
@@ -692,14 +701,16 @@ __device__ inline void term_get(const FusedArgs& f, const int* codes, int t, int
 // L_b x_i (p x s, K = q) is formed once per term; the next term's operands are
 // loaded into registers while the current term's products run.  Partial tiles are
 // written in the 32 x 32 tile layout of the general kernel.
+// Two workgroups of the one-pass applies share a compute unit (two LDS tiles each, at
+// most 256 registers a lane), so one's loads and barriers overlap the other's products.
+#define FUSED2_OCC __attribute__((amdgpu_waves_per_eu(2)))
+
 template <int P>
 __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int grp, const int z) {
   using T = typename Prec<P>::T;
   using Acc = typename Prec<P>::Acc;
-  __shared__ T sA[64][65];
-  __shared__ T sB[64][65];
-  __shared__ T sT[64][65];
-  __shared__ T sR[64][65];
+  __shared__ T sA[64][65];  // stage 1: L rows (sA[k][m]); stage 2: Rt^T (sA[s][t])
+  __shared__ T sB[64][65];  // stage 1: x (sB[k][n]); stage 2: the stage-1 product (sB[s][p])
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = wave / 2, wn = wave % 2;
   const int lrow = lane % 16, lk = lane / 16;
@@ -714,23 +725,42 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
   double mv;
   term_prefetch(f, f.tc, tb, te, lane, mc, me, mv);
   if (f.skip && *f.skip) return;
-  // thread -> 16 elements of each 64 x 64 tile: r = idx / 64, c = idx % 64, idx = tid + 256 j
   double la[16], xb[16], rb[16], vcur = 0.0;
-  auto load = [&](int t, double (&l)[16], double (&x)[16], double (&rr)[16], double& v) {
+  // thread -> rows tid / 64 + 4 j, column tid % 64 of each tile: rows beyond the tile's
+  // row count lie beyond the buffer range (zero), columns beyond are masked
+  const int r0 = tid / 64, c0 = tid % 64;
+  const bool cq = c0 < f.q, cs = c0 < f.s;
+  const double* re_next = nullptr;
+  auto load_lx = [&](int t, double& v) {
     int code, e;
     term_get(f, f.tc, t, tb, mc, me, mv, code, e, v);
-    const double* Lb = f.L + (long)(code >> 4) * f.q;
-    const double* Xi = f.x + (long)(code & 15) * f.s;
-    const double* Re = f.Rt + (long)e * f.s;
+    const long lb = (long)(code >> 4) * f.q, xi = (long)(code & 15) * f.s;
+    re_next = f.Rt + (long)e * f.s;
+    const __amdgpu_buffer_rsrc_t rl = tile_rsrc(f.L + lb, (long)f.p * Lrow - lb);
+    const __amdgpu_buffer_rsrc_t rx = tile_rsrc(f.x + xi, (long)f.q * Xrow - xi);
+    const int vl = (int)((r0 * Lrow + c0) * 8), vx = (int)((r0 * Xrow + c0) * 8);
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
-      l[j] = (r < f.p && c < f.q) ? Lb[r * Lrow + c] : 0.0;
-      x[j] = (r < f.q && c < f.s) ? Xi[r * Xrow + c] : 0.0;
-      rr[j] = (r < f.t && c < f.s) ? Re[r * Rrow + c] : 0.0;
+      const double a = tile_load(rl, vl, (int)(4 * j * Lrow * 8));
+      const double b = tile_load(rx, vx, (int)(4 * j * Xrow * 8));
+      la[j] = cq ? a : 0.0;
+      xb[j] = cs ? b : 0.0;
     }
   };
-  if (tb < te) load(tb, la, xb, rb, vcur);
+  auto load_r = [&](const double* Re) {
+    const long re = Re - f.Rt;
+    const __amdgpu_buffer_rsrc_t rt = tile_rsrc(Re, (long)f.t * Rrow - re);
+    const int vr = (int)((r0 * Rrow + c0) * 8);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double d = tile_load(rt, vr, (int)(4 * j * Rrow * 8));
+      rb[j] = cs ? d : 0.0;
+    }
+  };
+  if (tb < te) {
+    load_lx(tb, vcur);
+    load_r(re_next);
+  }
   Acc acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -742,29 +772,42 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
       const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
       sA[c][r] = (T)la[j];  // A = L rows (m = r) x q (k = c)
       sB[r][c] = (T)xb[j];  // B = x (k = r) x s (n = c)
-      sR[c][r] = (T)rb[j];  // B' = Rt^T: k = s (c), n = t (r)
     }
     const double v = vcur;
-    if (t + 1 < te) load(t + 1, la, xb, rb, vcur);
+    const bool more = t + 1 < te;
+    if (more) load_lx(t + 1, vcur);
     __syncthreads();
+    Acc tacc[2][2];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni) {
-        Acc tacc = {0, 0, 0, 0};
-        mfma_k32o<P, 65>(sA, sB, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, tacc);
-        mfma_k32o<P, 65>(sA, sB, 32, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, tacc);
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq)
-          sT[wn * 32 + ni * 16 + lrow][wm * 32 + mi * 16 + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[qq]);
+        tacc[mi][ni] = Acc{0, 0, 0, 0};
+        mfma_k32o<P, 65>(sA, sB, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, tacc[mi][ni]);
+        mfma_k32o<P, 65>(sA, sB, 32, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, tacc[mi][ni]);
       }
     __syncthreads();
+    // stage 2 operands into the same tiles: the stage-1 product and Rt^T
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          sB[wn * 32 + ni * 16 + lrow][wm * 32 + mi * 16 + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[mi][ni][qq]);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
+      sA[c][r] = (T)rb[j];  // B' = Rt^T: k = s (c), n = t (r)
+    }
+    if (more) load_r(re_next);
+    __syncthreads();
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni) {
-        mfma_k32o<P, 65>(sT, sR, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, acc[mi][ni]);
-        mfma_k32o<P, 65>(sT, sR, 32, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, acc[mi][ni]);
+        mfma_k32o<P, 65>(sB, sA, 0, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, acc[mi][ni]);
+        mfma_k32o<P, 65>(sB, sA, 32, wm * 32 + mi * 16, wn * 32 + ni * 16, lk, lrow, acc[mi][ni]);
       }
     __syncthreads();
   }
@@ -809,7 +852,7 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void fused_apply64_kernel(FusedArgs f) {
+__global__ __launch_bounds__(256) FUSED2_OCC void fused_apply64_kernel(FusedArgs f) {
   fused_apply64_body<P>(f, blockIdx.y, blockIdx.z);
 }
 
@@ -869,17 +912,18 @@ __device__ __forceinline__ void mfma_blocks(const typename Prec<P>::T (*sA)[65],
 // size rather than to 64 (the zero padding adds exact zeros: the results equal those
 // of the 64-padded product bit for bit).  Wave w owns blocks w, w + 4, ..., BPW of
 // them (slots beyond the block count repeat the last block and are not stored); the
-// BPW independent accumulation chains are interleaved per k step.  The sT rows from s
-// to the next multiple of 8 are read by stage 2: stage 1 writes them (zero columns of x).
+// BPW independent accumulation chains are interleaved per k step.  The stage-1 product
+// rows from s to the next multiple of 8 are read by stage 2: stage 1 writes them (zero
+// columns of x).
 template <int P, int BPW>
 __device__ __forceinline__ void fused_apply16_body(const FusedArgs& f, const int grp, const int z) {
   using T = typename Prec<P>::T;
   using Acc = typename Prec<P>::Acc;
   static_assert(P == 0 || P == 1, "16 x 16 x 4 MFMA operands");
+  // two tiles for both stages, as in the rank-64 kernel: L and x, then Rt^T and the
+  // stage-1 product
   __shared__ T sA[64][65];
   __shared__ T sB[64][65];
-  __shared__ T sT[64][65];
-  __shared__ T sR[64][65];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int lrow = lane % 16, lk = lane / 16;
   const int tb0 = f.begv[grp], te0 = f.begv[grp + 1];
@@ -906,21 +950,41 @@ __device__ __forceinline__ void fused_apply16_body(const FusedArgs& f, const int
     c2[j] = (b2 % tbk) * 16;
   }
   double la[16], xb[16], rb[16], vcur = 0.0;
-  auto load = [&](int t, double (&l)[16], double (&x)[16], double (&rr)[16], double& v) {
+  // thread -> rows tid / 64 + 4 j, column tid % 64 of each tile: rows beyond the tile's
+  // row count lie beyond the buffer range (zero), columns beyond are masked
+  const int r0 = tid / 64, c0 = tid % 64;
+  const bool cq = c0 < f.q, cs = c0 < f.s;
+  const double* re_next = nullptr;
+  auto load_lx = [&](int t, double& v) {
     int code, e;
     term_get(f, f.tc, t, tb, mc, me, mv, code, e, v);
-    const double* Lb = f.L + (long)(code >> 4) * f.q;
-    const double* Xi = f.x + (long)(code & 15) * f.s;
-    const double* Re = f.Rt + (long)e * f.s;
+    const long lb = (long)(code >> 4) * f.q, xi = (long)(code & 15) * f.s;
+    re_next = f.Rt + (long)e * f.s;
+    const __amdgpu_buffer_rsrc_t rl = tile_rsrc(f.L + lb, (long)f.p * Lrow - lb);
+    const __amdgpu_buffer_rsrc_t rx = tile_rsrc(f.x + xi, (long)f.q * Xrow - xi);
+    const int vl = (int)((r0 * Lrow + c0) * 8), vx = (int)((r0 * Xrow + c0) * 8);
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
-      l[j] = (r < f.p && c < f.q) ? Lb[r * Lrow + c] : 0.0;
-      x[j] = (r < f.q && c < f.s) ? Xi[r * Xrow + c] : 0.0;
-      rr[j] = (r < f.t && c < f.s) ? Re[r * Rrow + c] : 0.0;
+      const double a = tile_load(rl, vl, (int)(4 * j * Lrow * 8));
+      const double b = tile_load(rx, vx, (int)(4 * j * Xrow * 8));
+      la[j] = cq ? a : 0.0;
+      xb[j] = cs ? b : 0.0;
     }
   };
-  if (tb < te) load(tb, la, xb, rb, vcur);
+  auto load_r = [&](const double* Re) {
+    const long re = Re - f.Rt;
+    const __amdgpu_buffer_rsrc_t rt = tile_rsrc(Re, (long)f.t * Rrow - re);
+    const int vr = (int)((r0 * Rrow + c0) * 8);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double d = tile_load(rt, vr, (int)(4 * j * Rrow * 8));
+      rb[j] = cs ? d : 0.0;
+    }
+  };
+  if (tb < te) {
+    load_lx(tb, vcur);
+    load_r(re_next);
+  }
   Acc acc[BPW];
 #pragma unroll
   for (int j = 0; j < BPW; ++j) acc[j] = Acc{0, 0, 0, 0};
@@ -930,25 +994,32 @@ __device__ __forceinline__ void fused_apply16_body(const FusedArgs& f, const int
       const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
       sA[c][r] = (T)la[j];  // A = L rows (m = r) x q (k = c)
       sB[r][c] = (T)xb[j];  // B = x (k = r) x s (n = c)
-      sR[c][r] = (T)rb[j];  // B' = Rt^T: k = s (c), n = t (r)
     }
     const double v = vcur;
-    if (t + 1 < te) load(t + 1, la, xb, rb, vcur);
+    const bool more = t + 1 < te;
+    if (more) load_lx(t + 1, vcur);
     __syncthreads();
     Acc tacc[BPW];
 #pragma unroll
     for (int j = 0; j < BPW; ++j) tacc[j] = Acc{0, 0, 0, 0};
     mfma_blocks<P, BPW>(sA, sB, k1, r1, c1, lk, lrow, tacc);
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
       if (wave + 4 * j < nb1) {
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq)
-          sT[c1[j] + lrow][r1[j] + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[j][qq]);
+          sB[c1[j] + lrow][r1[j] + acc_row<P>(qq, lk)] = (T)(v * (double)tacc[j][qq]);
       }
     }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int idx = tid + 256 * j, r = idx / 64, c = idx % 64;
+      sA[c][r] = (T)rb[j];  // B' = Rt^T: k = s (c), n = t (r)
+    }
+    if (more) load_r(re_next);
     __syncthreads();
-    mfma_blocks<P, BPW>(sT, sR, k2, r2, c2, lk, lrow, acc);
+    mfma_blocks<P, BPW>(sB, sA, k2, r2, c2, lk, lrow, acc);
     __syncthreads();
   }
   // block (r2, c2) lies in 32 x 32 tile (r2 / 32, c2 / 32) of the partial layout
@@ -984,7 +1055,7 @@ __device__ __forceinline__ void fused_apply16_body(const FusedArgs& f, const int
 }
 
 template <int P, int BPW>
-__global__ __launch_bounds__(256) void fused_apply16_kernel(FusedArgs f) {
+__global__ __launch_bounds__(256) FUSED2_OCC void fused_apply16_kernel(FusedArgs f) {
   fused_apply16_body<P, BPW>(f, blockIdx.y, blockIdx.z);
 }
 
@@ -1304,7 +1375,7 @@ __global__ __launch_bounds__(256) void fused_apply32_batch_kernel(FusedBatch b) 
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void fused_apply64_batch_kernel(FusedBatch b) {
+__global__ __launch_bounds__(256) FUSED2_OCC void fused_apply64_batch_kernel(FusedBatch b) {
   const int z = blockIdx.z;
   int r = 0;
   while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
@@ -1313,7 +1384,7 @@ __global__ __launch_bounds__(256) void fused_apply64_batch_kernel(FusedBatch b) 
 }
 
 template <int P, int BPW>
-__global__ __launch_bounds__(256) void fused_apply16_batch_kernel(FusedBatch b) {
+__global__ __launch_bounds__(256) FUSED2_OCC void fused_apply16_batch_kernel(FusedBatch b) {
   const int z = blockIdx.z;
   int r = 0;
   while (r + 1 < b.nreq && z >= b.zoff[r + 1]) ++r;
