@@ -727,9 +727,11 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
   if (f.skip && *f.skip) return;
   double la[16], xb[16], rb[16], vcur = 0.0;
   // thread -> rows tid / 64 + 4 j, column tid % 64 of each tile: rows beyond the tile's
-  // row count lie beyond the buffer range (zero), columns beyond are masked
+  // row count lie beyond the buffer range, and so does every offset of a column beyond
+  // it (both read zero without a memory access)
   const int r0 = tid / 64, c0 = tid % 64;
   const bool cq = c0 < f.q, cs = c0 < f.s;
+  constexpr int OUT = 0x40000000;
   const double* re_next = nullptr;
   auto load_lx = [&](int t, double& v) {
     int code, e;
@@ -738,24 +740,19 @@ __device__ __forceinline__ void fused_apply64_body(const FusedArgs& f, const int
     re_next = f.Rt + (long)e * f.s;
     const __amdgpu_buffer_rsrc_t rl = tile_rsrc(f.L + lb, (long)f.p * Lrow - lb);
     const __amdgpu_buffer_rsrc_t rx = tile_rsrc(f.x + xi, (long)f.q * Xrow - xi);
-    const int vl = (int)((r0 * Lrow + c0) * 8), vx = (int)((r0 * Xrow + c0) * 8);
+    const int vl = cq ? (int)((r0 * Lrow + c0) * 8) : OUT, vx = cs ? (int)((r0 * Xrow + c0) * 8) : OUT;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const double a = tile_load(rl, vl, (int)(4 * j * Lrow * 8));
-      const double b = tile_load(rx, vx, (int)(4 * j * Xrow * 8));
-      la[j] = cq ? a : 0.0;
-      xb[j] = cs ? b : 0.0;
+      la[j] = tile_load(rl, vl, (int)(4 * j * Lrow * 8));
+      xb[j] = tile_load(rx, vx, (int)(4 * j * Xrow * 8));
     }
   };
   auto load_r = [&](const double* Re) {
     const long re = Re - f.Rt;
     const __amdgpu_buffer_rsrc_t rt = tile_rsrc(Re, (long)f.t * Rrow - re);
-    const int vr = (int)((r0 * Rrow + c0) * 8);
+    const int vr = cs ? (int)((r0 * Rrow + c0) * 8) : OUT;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double d = tile_load(rt, vr, (int)(4 * j * Rrow * 8));
-      rb[j] = cs ? d : 0.0;
-    }
+    for (int j = 0; j < 16; ++j) rb[j] = tile_load(rt, vr, (int)(4 * j * Rrow * 8));
   };
   if (tb < te) {
     load_lx(tb, vcur);
@@ -951,9 +948,11 @@ __device__ __forceinline__ void fused_apply16_body(const FusedArgs& f, const int
   }
   double la[16], xb[16], rb[16], vcur = 0.0;
   // thread -> rows tid / 64 + 4 j, column tid % 64 of each tile: rows beyond the tile's
-  // row count lie beyond the buffer range (zero), columns beyond are masked
+  // row count lie beyond the buffer range, and so does every offset of a column beyond
+  // it (both read zero without a memory access)
   const int r0 = tid / 64, c0 = tid % 64;
   const bool cq = c0 < f.q, cs = c0 < f.s;
+  constexpr int OUT = 0x40000000;
   const double* re_next = nullptr;
   auto load_lx = [&](int t, double& v) {
     int code, e;
@@ -962,24 +961,19 @@ __device__ __forceinline__ void fused_apply16_body(const FusedArgs& f, const int
     re_next = f.Rt + (long)e * f.s;
     const __amdgpu_buffer_rsrc_t rl = tile_rsrc(f.L + lb, (long)f.p * Lrow - lb);
     const __amdgpu_buffer_rsrc_t rx = tile_rsrc(f.x + xi, (long)f.q * Xrow - xi);
-    const int vl = (int)((r0 * Lrow + c0) * 8), vx = (int)((r0 * Xrow + c0) * 8);
+    const int vl = cq ? (int)((r0 * Lrow + c0) * 8) : OUT, vx = cs ? (int)((r0 * Xrow + c0) * 8) : OUT;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const double a = tile_load(rl, vl, (int)(4 * j * Lrow * 8));
-      const double b = tile_load(rx, vx, (int)(4 * j * Xrow * 8));
-      la[j] = cq ? a : 0.0;
-      xb[j] = cs ? b : 0.0;
+      la[j] = tile_load(rl, vl, (int)(4 * j * Lrow * 8));
+      xb[j] = tile_load(rx, vx, (int)(4 * j * Xrow * 8));
     }
   };
   auto load_r = [&](const double* Re) {
     const long re = Re - f.Rt;
     const __amdgpu_buffer_rsrc_t rt = tile_rsrc(Re, (long)f.t * Rrow - re);
-    const int vr = (int)((r0 * Rrow + c0) * 8);
+    const int vr = cs ? (int)((r0 * Rrow + c0) * 8) : OUT;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double d = tile_load(rt, vr, (int)(4 * j * Rrow * 8));
-      rb[j] = cs ? d : 0.0;
-    }
+    for (int j = 0; j < 16; ++j) rb[j] = tile_load(rt, vr, (int)(4 * j * Rrow * 8));
   };
   if (tb < te) {
     load_lx(tb, vcur);
