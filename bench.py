@@ -385,7 +385,7 @@ def roofline(P, opts, workload):
         "avg_launch_us": 1e3 * ms / max(nl, 1),
         "flops_per_launch": fl / max(nl, 1),
         "all_contractions": {
-            "kernels": f"{kname} + gemm_grouped_kernel<*>",
+            "kernels": f"{kname} + gemm_grouped_kernel<*> / gemm_multi_kernel<*>",
             "launches_per_solve": cnl, "ms_per_solve": cms,
             "tflops": cfl / (cms * 1e-3) / 1e12 if cms > 0 else 0.0,
         },
