@@ -1697,6 +1697,9 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
     const double* brow;
     const double* src;
   };
+  const __amdgpu_buffer_rsrc_t rpart = tile_rsrc(a.partial, (long)(ks > 0 ? ks : 1) * stride);
+  const __amdgpu_buffer_rsrc_t rz = tile_rsrc(a.z, a.N), rpv = tile_rsrc(a.p, a.N), rq = tile_rsrc(a.q, a.N),
+                               rx = tile_rsrc(a.x, a.N), rrv = tile_rsrc(a.r, a.N);
   auto load = [&](int idx, Elem& el) {
     const unsigned j = (unsigned)idx & (bnp - 1), blk = (unsigned)idx >> lbnp;
     const unsigned row = blk / t, col = blk - row * t;
@@ -1709,14 +1712,16 @@ __device__ __forceinline__ void cg_step_body(const CgIterArgs& a, const int k, c
 #pragma unroll
     for (int u = 0; u < U; ++u) el.w[u] = 0.0;
     if (el.act) {
-      const unsigned e = el.e;
+      // buffer loads: one offset register for the split partials (the split step in the
+      // scalar offset) and one for the five vectors
+      const int vo = (int)(el.src - a.partial) * 8, ve = (int)el.e * 8;
 #pragma unroll
-      for (int u = 0; u < U; ++u) el.w[u] = el.src[(long)(u < ks ? u : ks - 1) * stride];
-      el.z = a.z[e];
-      el.p = a.p[e];
-      el.q = a.q[e];
-      el.x = a.x[e];
-      el.r = a.r[e];
+      for (int u = 0; u < U; ++u) el.w[u] = tile_load(rpart, vo, (int)((u < ks ? u : ks - 1) * stride * 8));
+      el.z = tile_load(rz, ve, 0);
+      el.p = tile_load(rpv, ve, 0);
+      el.q = tile_load(rq, ve, 0);
+      el.x = tile_load(rx, ve, 0);
+      el.r = tile_load(rrv, ve, 0);
     }
 #pragma unroll
     for (int i = 0; i < BPRE; ++i) el.b[i] = (bpre && el.act && i < (int)bn) ? el.brow[i] : 0.0;
