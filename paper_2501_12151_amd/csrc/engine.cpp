@@ -985,11 +985,24 @@ struct Sweep {
       local_apply_ws(P, pl, p, q, s, t, L, x, Rt, y, skip, st, &fl, W.T1, W.T2);
       return;
     }
+    FusedArgs f = fused_args(k, p, q, s, t, L, x, Rt, W.fpart, W.fpart_cap);
+    f.skip = skip;
+    const double flops = 2.0 * p * q * s * pl.sp_nslot + 2.0 * p * s * t * pl.sp_n_ap;
+    launch_fused_apply(f, flops, st, 0);
+    launch_fused_sum(f, y, st, minus_from);
+    fl.total += flops;
+  }
+
+  // The fused apply of core k's sparse plan on the given interfaces, its split partials in
+  // `partial` (cap doubles)
+  FusedArgs fused_args(int k, int p, int q, int s, int t, const double* L, const double* x, const double* Rt,
+                       double* partial, size_t cap) {
+    const Plan& pl = plan(k);
     FusedArgs f;
     f.L = L;
     f.x = x;
     f.Rt = Rt;
-    f.partial = W.fpart;
+    f.partial = partial;
     f.p = p;
     f.q = q;
     f.s = s;
@@ -1000,12 +1013,8 @@ struct Sweep {
     set_terms(f, pl);
     f.stage = W.stage;
     f.stage_bytes = W.stage_bytes;
-    f.skip = skip;
-    f.ksplit = fused_apply_splits(f, pl.sp_ap_max, W.fpart_cap);
-    const double flops = 2.0 * p * q * s * pl.sp_nslot + 2.0 * p * s * t * pl.sp_n_ap;
-    launch_fused_apply(f, flops, st, 0);
-    launch_fused_sum(f, y, st, minus_from);
-    fl.total += flops;
+    f.ksplit = fused_apply_splits(f, pl.sp_ap_max, cap);
+    return f;
   }
 
   // g -= A x (tmp holds A x where the plan is dense)
@@ -1359,22 +1368,40 @@ struct Sweep {
     g.add(rhs2_desc(pz, nk, sb(k + 1), tz, W.Tbz, Ezb[k + 1], W.gz));
     if (rho_eff > 0) g.add(rhs2_desc(p, nk, sb(k + 1), tz, W.Tb, Ezb[k + 1], W.ge));
     g.launch(st, &fl);
-    // residual projected on the Z interfaces -> new Z_k (QR job)
-    apply_sub(k, pz, p, t, tz, EzA[k], W.xt, EzA[k + 1], W.gz, W.yz);
-    if (with_u) apply_sub(k, pz, ur[k], ur[k + 1], tz, EzuA[k], U[k], EzuA[k + 1], W.gz, W.yz);
     const int mz = pz * nk;
     s.cz = std::min(mz, tz);
     s.zqr = QrJob{mz, tz, tz, s.cz, tz, W.gz, Z[k], W.Rz, W.qrwsz, W.qrwsz_cap};
+    if (rho_eff > 0 && !plan(k).dense && !with_u) {
+      // both residuals (on the Z interfaces -> new Z_k; on (left X, right Z) -> the
+      // enrichment) from their applies, partials in the two halves of the split buffer,
+      // subtracted in one launch
+      const Plan& pl = plan(k);
+      const size_t half = W.fpart_cap / 2;
+      const FusedArgs fz = fused_args(k, pz, p, t, tz, EzA[k], W.xt, EzA[k + 1], W.fpart, half);
+      const FusedArgs fe = fused_args(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.fpart + half, half);
+      const double flz = 2.0 * pz * p * t * pl.sp_nslot + 2.0 * pz * t * tz * pl.sp_n_ap;
+      const double fle = 2.0 * p * p * t * pl.sp_nslot + 2.0 * p * t * tz * pl.sp_n_ap;
+      launch_fused_apply(fz, flz, st, 0);
+      launch_fused_apply(fe, fle, st, 0);
+      launch_fused_sum2(fz, W.gz, W.gz, fe, W.ge, W.ge, st);
+      fl.total += flz + fle;
+    } else {
+      // residual projected on the Z interfaces -> new Z_k (QR job)
+      apply_sub(k, pz, p, t, tz, EzA[k], W.xt, EzA[k + 1], W.gz, W.yz);
+      if (with_u) apply_sub(k, pz, ur[k], ur[k + 1], tz, EzuA[k], U[k], EzuA[k + 1], W.gz, W.yz);
+      if (rho_eff > 0) {
+        apply_sub(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ge, W.ye);
+        if (with_u) apply_sub(k, p, ur[k], ur[k + 1], tz, EuA[k], U[k], EzuA[k + 1], W.ge, W.ye);
+      }
+    }
     if (rho_eff == 0) {
       // no room: U_rk (orthonormal columns) is the new core as it stands
       launch_copy2d(M, rk, W.Ur, c, X[k], rk, 1.0, 0.0, st);
       s.aqr = QrJob{};
       return;
     }
-    apply_sub(k, p, p, t, tz, EA[k], W.xt, EzA[k + 1], W.ge, W.ye);
-    if (with_u) apply_sub(k, p, ur[k], ur[k + 1], tz, EuA[k], U[k], EzuA[k + 1], W.ge, W.ye);
-    launch_copy2d(M, rk, W.Ur, c, W.aug, rnew, 1.0, 0.0, st);
-    launch_copy2d(M, rho_eff, W.ge, tz, W.aug + rk, rnew, 1.0, 0.0, st);
+    // the augmented basis [U_rk | residual columns]
+    launch_copy_concat(M, rk, W.Ur, c, rho_eff, W.ge, tz, W.aug, rnew, st);
     s.aqr = QrJob{M, rnew, rnew, rnew, rnew, W.aug, X[k], W.Ra, W.qrws, W.qrws_cap};
   }
 

@@ -1523,6 +1523,39 @@ __global__ void fused_sum_kernel(FusedArgs f, double* y, const double* g) {
   }
 }
 
+// The same for two applies at once (their partials in separate buffers): elements
+// 0 .. N1 - 1 of the grid belong to the first, the rest to the second.
+__global__ void fused_sum2_kernel(FusedArgs f1, double* y1, const double* g1, FusedArgs f2, double* y2,
+                                  const double* g2) {
+  const long N1 = (long)f1.p * f1.n * f1.t, N2 = (long)f2.p * f2.n * f2.t;
+  for (long e0 = blockIdx.x * (long)blockDim.x + threadIdx.x; e0 < N1 + N2; e0 += (long)gridDim.x * blockDim.x) {
+    const bool first = e0 < N1;
+    const FusedArgs& f = first ? f1 : f2;
+    const long e = first ? e0 : e0 - N1;
+    const long stride = (long)f.n * f.ntiles * 1024;
+    const int col = e % f.t, grp = (e / f.t) % f.n, row = e / ((long)f.t * f.n);
+    const int tile = (row / 32) * f.tiles_n + col / 32;
+    const double* src = f.partial + ((long)grp * f.ntiles + tile) * 1024 + (row % 32) * 32 + (col % 32);
+    const double v = sum_splits(src, stride, f.ksplit);
+    const double* g = first ? g1 : g2;
+    double* y = first ? y1 : y2;
+    y[e] = g ? g[e] - v : v;
+  }
+}
+
+void launch_fused_sum2(FusedArgs f1, double* y1, const double* g1, FusedArgs f2, double* y2, const double* g2,
+                       hipStream_t s) {
+  if (f1.skip || f2.skip) throw Error(TNFEM_EINVAL, "fused sum of two applies: no stop flag");
+  f1.tiles_n = (f1.t + 31) / 32;
+  f1.ntiles = ((f1.p + 31) / 32) * f1.tiles_n;
+  f2.tiles_n = (f2.t + 31) / 32;
+  f2.ntiles = ((f2.p + 31) / 32) * f2.tiles_n;
+  const long N = (long)f1.p * f1.n * f1.t + (long)f2.p * f2.n * f2.t;
+  const int nb = (int)std::min<long>(std::max<long>((N + 63) / 64, 1), 4096);
+  hipLaunchKernelGGL(fused_sum2_kernel, dim3(nb), dim3(64), 0, s, f1, y1, g1, f2, y2, g2);
+  TN_CHECK_LAUNCH();
+}
+
 void launch_fused_sum(FusedArgs f, double* y, hipStream_t s, const double* minus_from) {
   f.tiles_n = (f.t + 31) / 32;
   f.ntiles = ((f.p + 31) / 32) * f.tiles_n;
@@ -3727,11 +3760,32 @@ __global__ void copy2d_kernel(int rows, int cols, const double* src, long sld, d
   }
 }
 
+// dst[i][0 .. c1 + c2) = [src1[i][0 .. c1) | src2[i][0 .. c2)] for rows i (column blocks
+// side by side, as the enrichment's augmented basis [U | residual])
+__global__ void copy_concat_kernel(int rows, int c1, const double* src1, long ld1, int c2, const double* src2,
+                                   long ld2, double* dst, long ldd) {
+  const int cols = c1 + c2;
+  const long total = (long)rows * cols;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const long i = idx / cols;
+    const int j = (int)(idx % cols);
+    dst[i * ldd + j] = j < c1 ? src1[i * ld1 + j] : src2[i * ld2 + (j - c1)];
+  }
+}
+
 static int blocks_for(long total) {
   long b = (total + 255) / 256;
   if (b < 1) b = 1;
   if (b > 4096) b = 4096;
   return (int)b;
+}
+
+void launch_copy_concat(int rows, int c1, const double* src1, long ld1, int c2, const double* src2, long ld2,
+                        double* dst, long ldd, hipStream_t s) {
+  if (rows <= 0 || c1 + c2 <= 0 || c1 < 0 || c2 < 0) return;
+  hipLaunchKernelGGL(copy_concat_kernel, dim3(blocks_for((long)rows * (c1 + c2))), dim3(256), 0, s, rows, c1, src1,
+                     ld1, c2, src2, ld2, dst, ldd);
+  TN_CHECK_LAUNCH();
 }
 
 void launch_copy2d(int rows, int cols, const double* src, long sld, double* dst, long dld, double alpha, double beta,

@@ -162,6 +162,10 @@ void launch_fused_apply(FusedArgs f, double flops, hipStream_t s, int precision 
 // y = sum of the split partials of a fused apply; with minus_from, y = minus_from - sum
 // (element by element, minus_from may equal y).
 void launch_fused_sum(FusedArgs f, double* y, hipStream_t s, const double* minus_from = nullptr);
+// the split sums of two applies (partials in separate buffers, no stop flags) in one launch:
+// y1 = g1 - A1 x1 (or A1 x1 when g1 is null), y2 likewise
+void launch_fused_sum2(FusedArgs f1, double* y1, const double* g1, FusedArgs f2, double* y2, const double* g2,
+                       hipStream_t s);
 
 // Local PCG with per-block partial sums (no atomics inside the iteration):
 // iteration k = apply (w = B z) -> reduce_dir(k) -> update2(k).
@@ -280,6 +284,9 @@ void launch_jacobi_svd_batch(const std::vector<SvdJob>& jobs, hipStream_t s);
 void launch_trunc_rank(int c, const double* S, double tol, int cap, int* out, hipStream_t s);
 
 // dst[i][j] = alpha * src[i][j] (+ beta * dst) for i < rows, j < cols.
+// dst = [src1 | src2] column blocks, row by row (rows x (c1 + c2), leading dimensions given)
+void launch_copy_concat(int rows, int c1, const double* src1, long ld1, int c2, const double* src2, long ld2,
+                        double* dst, long ldd, hipStream_t s);
 void launch_copy2d(int rows, int cols, const double* src, long sld, double* dst, long dld, double alpha, double beta,
                    hipStream_t s);
 
